@@ -1,0 +1,195 @@
+"""ctypes front end of the plain FP64 CPU oracle (oracle.c).
+
+Test infrastructure only: the tests, the smoke check and the benchmark's CPU
+baseline leg import this module; the product library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+i64p = C.POINTER(C.c_int64)
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Opts(C.Structure):
+    _fields_ = [("cg_tol", C.c_double), ("kkt_tol", C.c_double), ("qf_eps", C.c_double),
+                ("delta2", C.c_double), ("max_cg", C.c_int64), ("max_refine", C.c_int64)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("status", C.c_int64), ("passes", C.c_int64), ("cg_iters", C.c_int64 * 16),
+                ("rr_hist", C.c_double * 16), ("rr", C.c_double), ("be", C.c_double),
+                ("floor", C.c_double), ("inertia", C.c_int64 * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB)
+        L.orc_new.restype = C.c_void_p
+        L.orc_new.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, f64p, i64p, i32p, f64p,
+                              C.c_double, C.c_double]
+        L.orc_free.argtypes = [C.c_void_p]
+        L.orc_hgamma_nnz.restype = C.c_int64
+        L.orc_hgamma_nnz.argtypes = [C.c_void_p]
+        L.orc_hgamma.argtypes = [C.c_void_p, i64p, i32p, f64p]
+        L.orc_order_mindeg.argtypes = [C.c_void_p, i32p]
+        L.orc_factor.restype = C.c_int
+        L.orc_factor.argtypes = [C.c_void_p, i32p, i64p]
+        L.orc_L_nnz.restype = C.c_int64
+        L.orc_L_nnz.argtypes = [C.c_void_p]
+        L.orc_L.argtypes = [C.c_void_p, i64p, i32p, f64p]
+        L.orc_hsolve.argtypes = [C.c_void_p, f64p, f64p]
+        L.orc_metrics.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p, f64p]
+        L.orc_solve.restype = C.c_int
+        L.orc_solve.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.POINTER(_Report)]
+        L.orc_hybrid_once.restype = C.c_int64
+        L.orc_hybrid_once.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.POINTER(C.c_int)]
+        L.orc_apply_K.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class System:
+    """One KKT system K = [H + D_x + delta I, J^T; J, 0] in FP64 on the CPU."""
+
+    def __init__(self, n_x, m, H_rowptr, H_col, H_val, D_x, J_rowptr, J_col, J_val, delta, gamma):
+        self.n, self.m = int(n_x), int(m)
+        self._keep = [_c(H_rowptr, np.int64), _c(H_col, np.int32), _c(H_val, np.float64),
+                      _c(D_x, np.float64), _c(J_rowptr, np.int64), _c(J_col, np.int32),
+                      _c(J_val, np.float64)]
+        k = self._keep
+        self._h = lib().orc_new(self.n, self.m, _p(k[0], i64p), _p(k[1], i32p), _p(k[2], f64p),
+                                _p(k[3], f64p), _p(k[4], i64p), _p(k[5], i32p), _p(k[6], f64p),
+                                float(delta), float(gamma))
+        self.perm = None
+
+    @classmethod
+    def from_batch(cls, batch, b=0):
+        p = batch.pattern
+        return cls(p.n_x, p.m, p.H_rowptr, p.H_col, batch.H_val[b], batch.D_x[b], p.J_rowptr,
+                   p.J_col, batch.J_val[b], batch.delta[b], batch.gamma[b])
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().orc_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def hgamma(self):
+        """H_gamma lower triangle as (colptr, rowind, val), original order."""
+        nz = lib().orc_hgamma_nnz(self._h)
+        cp = np.empty(self.n + 1, np.int64)
+        ri = np.empty(nz, np.int32)
+        v = np.empty(nz, np.float64)
+        lib().orc_hgamma(self._h, _p(cp, i64p), _p(ri, i32p), _p(v, f64p))
+        return cp, ri, v
+
+    def order_mindeg(self):
+        perm = np.empty(self.n, np.int32)
+        lib().orc_order_mindeg(self._h, _p(perm, i32p))
+        return perm
+
+    def factor(self, perm=None):
+        """Returns (status, fail_col). perm[k] = original index of pivot k."""
+        fc = np.zeros(1, np.int64)
+        if perm is None:
+            st = lib().orc_factor(self._h, None, _p(fc, i64p))
+        else:
+            pa = _c(perm, np.int32)
+            st = lib().orc_factor(self._h, _p(pa, i32p), _p(fc, i64p))
+        self.perm = None if perm is None else np.asarray(perm, np.int32)
+        return int(st), int(fc[0])
+
+    def L(self):
+        nz = lib().orc_L_nnz(self._h)
+        if nz < 0:
+            raise RuntimeError("not factored")
+        cp = np.empty(self.n + 1, np.int64)
+        ri = np.empty(nz, np.int32)
+        v = np.empty(nz, np.float64)
+        lib().orc_L(self._h, _p(cp, i64p), _p(ri, i32p), _p(v, f64p))
+        return cp, ri, v
+
+    def hsolve(self, b):
+        b = _c(b, np.float64)
+        x = np.empty(self.n)
+        lib().orc_hsolve(self._h, _p(b, f64p), _p(x, f64p))
+        return x
+
+    def metrics(self, r1, r2, x, y):
+        """(RR, BE, floor) of z = (x, y) for K z = r."""
+        a = [_c(v, np.float64) for v in (r1, r2, x, y)]
+        out = np.empty(3)
+        lib().orc_metrics(self._h, *[_p(v, f64p) for v in a], _p(out, f64p))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    @staticmethod
+    def _opts(cg_tol=1e-12, kkt_tol=1e-10, qf_eps=1e-14, delta2=0.0, max_cg=0, max_refine=10):
+        return _Opts(cg_tol, kkt_tol, qf_eps, delta2, max_cg, max_refine)
+
+    def solve(self, r1, r2, **kw):
+        r1 = _c(r1, np.float64)
+        r2 = _c(r2, np.float64)
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        rep = _Report()
+        o = self._opts(**kw)
+        lib().orc_solve(self._h, C.byref(o), _p(r1, f64p), _p(r2, f64p), _p(x, f64p), _p(y, f64p),
+                        C.byref(rep))
+        info = dict(status=int(rep.status), passes=int(rep.passes),
+                    cg_iters=[int(rep.cg_iters[i]) for i in range(rep.passes)],
+                    rr_hist=[float(rep.rr_hist[i]) for i in range(rep.passes)],
+                    rr=float(rep.rr), be=float(rep.be), floor=float(rep.floor),
+                    inertia=tuple(int(v) for v in rep.inertia))
+        return x, y, info
+
+    def hybrid_once(self, r1, r2, **kw):
+        r1 = _c(r1, np.float64)
+        r2 = _c(r2, np.float64)
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        brk = C.c_int(0)
+        o = self._opts(**kw)
+        it = lib().orc_hybrid_once(self._h, C.byref(o), _p(r1, f64p), _p(r2, f64p), _p(x, f64p),
+                                   _p(y, f64p), C.byref(brk))
+        return x, y, int(it), bool(brk.value)
+
+    def apply_K(self, x, y):
+        x = _c(x, np.float64)
+        y = _c(y, np.float64)
+        o1 = np.empty(self.n)
+        o2 = np.empty(self.m)
+        lib().orc_apply_K(self._h, _p(x, f64p), _p(y, f64p), _p(o1, f64p), _p(o2, f64p))
+        return o1, o2

@@ -1,0 +1,605 @@
+/*
+ * oracle.c -- plain, slow, obviously correct FP64 CPU reference for the
+ * hybrid direct-iterative KKT solve (Regev et al., "A Hybrid Direct-Iterative
+ * Method for Solving KKT Linear Systems").
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library may link, call or
+ * execute this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg use it. It shares no code with the GPU library.
+ *
+ * What it computes (Sec. 3 eq. linsys2x2 with m_d = 0, Sec. 4):
+ *   K = [H + D_x + delta*I, J^T; J, 0],  K z = r,  z = (x, y), r = (r1, r2).
+ *   H_gamma = H + D_x + delta*I + gamma*J^T J          (eq. eq:gamma)
+ *   rhat    = r1 + gamma*J^T r2                        (eq. linsys2x2mod)
+ *   S y     = J H_gamma^{-1} rhat - r2,  S = J H_gamma^{-1} J^T   (eq. Schur1)
+ *   H_gamma x = rhat - J^T y                           (eq. Schur2)
+ * solved as in Algorithm 1 (solve phase): w = H_gamma^{-1} rhat, CG on S,
+ * then the primal recovery; followed by FP64 iterative refinement on the full
+ * KKT residual, with the metrics of Sec. 5.1 (RR and BE with ||K||_inf).
+ *
+ * Every step is the textbook form: triplet assembly with sorted duplicate
+ * summation, exact minimum degree on the explicit elimination graph,
+ * left-looking column Cholesky (George & Liu), column-oriented forward and
+ * dot-form backward substitution, unpreconditioned CG.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *  - CG starts from y = 0 and stops when ||res||_2 <= cg_tol * ||b||_2
+ *    (Sec. 5.1: relative residual tolerance 1e-12), or after max_cg steps.
+ *  - "small quadratic form" (Algorithm 1): p'q <= qf_eps*||p||^2*(p0'q0/||p0||^2).
+ *  - refinement: while RR > kkt_tol and steps < max_refine: solve K e = res by
+ *    the same hybrid steps, z += e, recompute res = r - K z.
+ *  - inertia of K after a successful Cholesky of H_gamma and CG without
+ *    breakdown: (n_x, m, 0) (Sec. 4.2, Theorem 3; congruence + Haynsworth).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef int64_t i64;
+typedef int32_t i32;
+
+/* ------------------------------------------------------------------ */
+/* system                                                              */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    i64 n, m;
+    /* tril(H) CSR (rows), J CSR */
+    i64 *Hp; i32 *Hi; double *Hx;
+    i64 *Jp; i32 *Ji; double *Jx;
+    double *Dx;
+    double delta, gamma;
+    /* H_gamma lower, CSC, original order */
+    i64 *Ap; i32 *Ai; double *Ax;
+    /* factor of P H_gamma P^T = L L^T, L in CSC, permuted order */
+    i32 *perm, *iperm;     /* perm[k] = original index of pivot k */
+    i64 *Lp; i32 *Li; double *Lx;
+    int factored;
+} orc;
+
+static void *xmalloc(size_t s) { void *p = malloc(s ? s : 1); if (!p) abort(); return p; }
+static void *xcalloc(size_t n, size_t s) { void *p = calloc(n ? n : 1, s ? s : 1); if (!p) abort(); return p; }
+
+typedef struct { i64 row, col; double v; i64 seq; } trip;
+
+static int trip_cmp(const void *a, const void *b) {
+    const trip *x = a, *y = b;
+    if (x->col != y->col) return x->col < y->col ? -1 : 1;
+    if (x->row != y->row) return x->row < y->row ? -1 : 1;
+    return x->seq < y->seq ? -1 : (x->seq > y->seq);
+}
+
+/* H_gamma = tril(H) + diag(D_x + delta) + gamma * tril(J^T J), Sec. 3 and
+ * eq. eq:gamma, as a lower CSC with duplicates summed in a fixed order. */
+static void assemble(orc *s) {
+    i64 n = s->n, m = s->m;
+    i64 cnt = s->Hp[n] + n;
+    for (i64 i = 0; i < m; i++) { i64 k = s->Jp[i + 1] - s->Jp[i]; cnt += k * (k + 1) / 2; }
+    trip *t = xmalloc(sizeof(trip) * (size_t)cnt);
+    i64 q = 0;
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+            t[q].row = i; t[q].col = s->Hi[p]; t[q].v = s->Hx[p]; t[q].seq = q; q++;
+        }
+    for (i64 j = 0; j < n; j++) { t[q].row = j; t[q].col = j; t[q].v = s->Dx[j] + s->delta; t[q].seq = q; q++; }
+    for (i64 i = 0; i < m; i++)
+        for (i64 a = s->Jp[i]; a < s->Jp[i + 1]; a++)
+            for (i64 b = s->Jp[i]; b < s->Jp[i + 1]; b++) {
+                i64 pa = s->Ji[a], pb = s->Ji[b];
+                if (pa < pb) continue;       /* lower triangle: row >= col */
+                t[q].row = pa; t[q].col = pb; t[q].v = s->gamma * s->Jx[a] * s->Jx[b]; t[q].seq = q; q++;
+            }
+    qsort(t, (size_t)q, sizeof(trip), trip_cmp);
+    s->Ap = xcalloc((size_t)n + 1, sizeof(i64));
+    s->Ai = xmalloc(sizeof(i32) * (size_t)q);
+    s->Ax = xmalloc(sizeof(double) * (size_t)q);
+    i64 nz = 0;
+    for (i64 k = 0; k < q; k++) {
+        if (nz > 0 && s->Ai[nz - 1] == t[k].row && (k > 0 && t[k - 1].col == t[k].col)) {
+            s->Ax[nz - 1] += t[k].v;
+        } else {
+            s->Ai[nz] = (i32)t[k].row; s->Ax[nz] = t[k].v; s->Ap[t[k].col + 1]++; nz++;
+        }
+    }
+    for (i64 j = 0; j < n; j++) s->Ap[j + 1] += s->Ap[j];
+    free(t);
+}
+
+orc *orc_new(i64 n, i64 m, const i64 *Hp, const i32 *Hi, const double *Hx, const double *Dx,
+             const i64 *Jp, const i32 *Ji, const double *Jx, double delta, double gamma) {
+    orc *s = xcalloc(1, sizeof(orc));
+    s->n = n; s->m = m; s->delta = delta; s->gamma = gamma;
+    s->Hp = xmalloc(sizeof(i64) * (size_t)(n + 1)); memcpy(s->Hp, Hp, sizeof(i64) * (size_t)(n + 1));
+    s->Hi = xmalloc(sizeof(i32) * (size_t)Hp[n]); memcpy(s->Hi, Hi, sizeof(i32) * (size_t)Hp[n]);
+    s->Hx = xmalloc(sizeof(double) * (size_t)Hp[n]); memcpy(s->Hx, Hx, sizeof(double) * (size_t)Hp[n]);
+    s->Jp = xmalloc(sizeof(i64) * (size_t)(m + 1)); memcpy(s->Jp, Jp, sizeof(i64) * (size_t)(m + 1));
+    s->Ji = xmalloc(sizeof(i32) * (size_t)Jp[m]); memcpy(s->Ji, Ji, sizeof(i32) * (size_t)Jp[m]);
+    s->Jx = xmalloc(sizeof(double) * (size_t)Jp[m]); memcpy(s->Jx, Jx, sizeof(double) * (size_t)Jp[m]);
+    s->Dx = xmalloc(sizeof(double) * (size_t)n); memcpy(s->Dx, Dx, sizeof(double) * (size_t)n);
+    assemble(s);
+    return s;
+}
+
+static void free_factor(orc *s) {
+    free(s->perm); free(s->iperm); free(s->Lp); free(s->Li); free(s->Lx);
+    s->perm = s->iperm = NULL; s->Lp = NULL; s->Li = NULL; s->Lx = NULL; s->factored = 0;
+}
+
+void orc_free(orc *s) {
+    if (!s) return;
+    free_factor(s);
+    free(s->Hp); free(s->Hi); free(s->Hx); free(s->Jp); free(s->Ji); free(s->Jx); free(s->Dx);
+    free(s->Ap); free(s->Ai); free(s->Ax);
+    free(s);
+}
+
+i64 orc_hgamma_nnz(const orc *s) { return s->Ap[s->n]; }
+
+void orc_hgamma(const orc *s, i64 *colptr, i32 *rowind, double *val) {
+    memcpy(colptr, s->Ap, sizeof(i64) * (size_t)(s->n + 1));
+    memcpy(rowind, s->Ai, sizeof(i32) * (size_t)s->Ap[s->n]);
+    memcpy(val, s->Ax, sizeof(double) * (size_t)s->Ap[s->n]);
+}
+
+/* ------------------------------------------------------------------ */
+/* exact minimum degree on the explicit elimination graph               */
+/* (any fill-reducing order gives the same solution in exact arithmetic;  */
+/*  the paper uses AMD, Sec. 5.3; this is the plain exact variant)        */
+/* ------------------------------------------------------------------ */
+
+typedef struct { i32 *v; i32 len, cap; } ivec;
+static void iv_push(ivec *a, i32 x) {
+    if (a->len == a->cap) { a->cap = a->cap ? a->cap * 2 : 4; a->v = realloc(a->v, sizeof(i32) * (size_t)a->cap); if (!a->v) abort(); }
+    a->v[a->len++] = x;
+}
+
+typedef struct { i64 key; i32 node; } hent;
+typedef struct { hent *h; i64 len, cap; } heap;
+static void hp_push(heap *H, i64 key, i32 node) {
+    if (H->len == H->cap) { H->cap = H->cap ? H->cap * 2 : 64; H->h = realloc(H->h, sizeof(hent) * (size_t)H->cap); if (!H->h) abort(); }
+    i64 i = H->len++;
+    H->h[i].key = key; H->h[i].node = node;
+    while (i > 0) {
+        i64 p = (i - 1) / 2;
+        if (H->h[p].key < H->h[i].key || (H->h[p].key == H->h[i].key && H->h[p].node <= H->h[i].node)) break;
+        hent tmp = H->h[p]; H->h[p] = H->h[i]; H->h[i] = tmp; i = p;
+    }
+}
+static hent hp_pop(heap *H) {
+    hent top = H->h[0];
+    H->h[0] = H->h[--H->len];
+    i64 i = 0;
+    for (;;) {
+        i64 l = 2 * i + 1, r = l + 1, b = i;
+        if (l < H->len && (H->h[l].key < H->h[b].key || (H->h[l].key == H->h[b].key && H->h[l].node < H->h[b].node))) b = l;
+        if (r < H->len && (H->h[r].key < H->h[b].key || (H->h[r].key == H->h[b].key && H->h[r].node < H->h[b].node))) b = r;
+        if (b == i) break;
+        hent tmp = H->h[b]; H->h[b] = H->h[i]; H->h[i] = tmp; i = b;
+    }
+    return top;
+}
+
+/* perm[k] = original index of the k-th eliminated node; ties -> smallest index */
+void orc_order_mindeg(const orc *s, i32 *perm) {
+    i64 n = s->n;
+    ivec *adj = xcalloc((size_t)n, sizeof(ivec));
+    for (i64 j = 0; j < n; j++)
+        for (i64 p = s->Ap[j]; p < s->Ap[j + 1]; p++) {
+            i32 i = s->Ai[p];
+            if (i == j) continue;
+            iv_push(&adj[i], (i32)j); iv_push(&adj[j], i);
+        }
+    char *gone = xcalloc((size_t)n, 1);
+    i64 *mark = xmalloc(sizeof(i64) * (size_t)n);
+    for (i64 i = 0; i < n; i++) mark[i] = -1;
+    /* dedupe initial lists */
+    for (i64 i = 0; i < n; i++) {
+        i32 w = 0;
+        for (i32 k = 0; k < adj[i].len; k++) { i32 u = adj[i].v[k]; if (mark[u] != i) { mark[u] = i; adj[i].v[w++] = u; } }
+        adj[i].len = w;
+    }
+    for (i64 i = 0; i < n; i++) mark[i] = -1;
+    heap H = {0};
+    for (i64 i = 0; i < n; i++) hp_push(&H, adj[i].len, (i32)i);
+    i32 *nbr = xmalloc(sizeof(i32) * (size_t)(n ? n : 1));
+    i64 stamp = 0;
+    for (i64 k = 0; k < n; k++) {
+        i32 v;
+        for (;;) {
+            hent e = hp_pop(&H);
+            if (!gone[e.node] && e.key == adj[e.node].len) { v = e.node; break; }
+        }
+        perm[k] = v; gone[v] = 1;
+        /* live neighbours of v */
+        i32 nn = 0;
+        for (i32 q = 0; q < adj[v].len; q++) { i32 u = adj[v].v[q]; if (!gone[u]) nbr[nn++] = u; }
+        free(adj[v].v); adj[v].v = NULL; adj[v].len = adj[v].cap = 0;
+        /* make the neighbours a clique; drop v from their lists */
+        for (i32 a = 0; a < nn; a++) {
+            i32 u = nbr[a];
+            stamp++;
+            i32 w = 0;
+            for (i32 q = 0; q < adj[u].len; q++) {
+                i32 t = adj[u].v[q];
+                if (t == v || gone[t]) continue;
+                if (mark[t] == stamp) continue;
+                mark[t] = stamp; adj[u].v[w++] = t;
+            }
+            adj[u].len = w;
+            mark[u] = stamp;
+            for (i32 b = 0; b < nn; b++) { i32 t = nbr[b]; if (mark[t] != stamp) { mark[t] = stamp; iv_push(&adj[u], t); } }
+            hp_push(&H, adj[u].len, u);
+        }
+    }
+    free(nbr); free(H.h); free(mark); free(gone);
+    for (i64 i = 0; i < n; i++) free(adj[i].v);
+    free(adj);
+}
+
+/* ------------------------------------------------------------------ */
+/* left-looking column Cholesky  P H_gamma P^T = L L^T                  */
+/* (Cholesky is stable without pivoting, Sec. 3; a non-positive or       */
+/*  non-finite pivot means H_gamma is not SPD: Algorithm 1's "Fail")     */
+/* ------------------------------------------------------------------ */
+
+static int cmp_i32(const void *a, const void *b) { i32 x = *(const i32 *)a, y = *(const i32 *)b; return (x > y) - (x < y); }
+
+/* returns 0 on success, 1 if not SPD; *fail_col = original index of the first
+ * failing pivot in elimination order (or -1) */
+int orc_factor(orc *s, const i32 *perm_in, i64 *fail_col) {
+    i64 n = s->n;
+    free_factor(s);
+    s->perm = xmalloc(sizeof(i32) * (size_t)(n ? n : 1));
+    s->iperm = xmalloc(sizeof(i32) * (size_t)(n ? n : 1));
+    for (i64 k = 0; k < n; k++) s->perm[k] = perm_in ? perm_in[k] : (i32)k;
+    for (i64 k = 0; k < n; k++) s->iperm[s->perm[k]] = (i32)k;
+    /* C = P A P^T, lower CSC */
+    i64 nzA = s->Ap[n];
+    i64 *Cp = xcalloc((size_t)n + 1, sizeof(i64));
+    for (i64 j = 0; j < n; j++)
+        for (i64 p = s->Ap[j]; p < s->Ap[j + 1]; p++) {
+            i64 a = s->iperm[s->Ai[p]], b = s->iperm[j];
+            Cp[(a < b ? a : b) + 1]++;
+        }
+    for (i64 j = 0; j < n; j++) Cp[j + 1] += Cp[j];
+    i64 *fill = xmalloc(sizeof(i64) * (size_t)(n ? n : 1));
+    for (i64 j = 0; j < n; j++) fill[j] = Cp[j];
+    i32 *Ci = xmalloc(sizeof(i32) * (size_t)(nzA ? nzA : 1));
+    double *Cx = xmalloc(sizeof(double) * (size_t)(nzA ? nzA : 1));
+    for (i64 j = 0; j < n; j++)
+        for (i64 p = s->Ap[j]; p < s->Ap[j + 1]; p++) {
+            i64 a = s->iperm[s->Ai[p]], b = s->iperm[j];
+            i64 lo = a < b ? a : b, hi = a < b ? b : a;
+            Ci[fill[lo]] = (i32)hi; Cx[fill[lo]] = s->Ax[p]; fill[lo]++;
+        }
+    free(fill);
+
+    i64 cap = nzA + n + 16, nz = 0;
+    s->Lp = xcalloc((size_t)n + 1, sizeof(i64));
+    s->Li = xmalloc(sizeof(i32) * (size_t)cap);
+    s->Lx = xmalloc(sizeof(double) * (size_t)cap);
+    double *w = xcalloc((size_t)(n ? n : 1), sizeof(double));
+    char *mk = xcalloc((size_t)(n ? n : 1), 1);
+    i32 *pat = xmalloc(sizeof(i32) * (size_t)(n ? n : 1));
+    i64 *head = xmalloc(sizeof(i64) * (size_t)(n ? n : 1));   /* linked list of columns k with L(j,k) != 0 */
+    i64 *next = xmalloc(sizeof(i64) * (size_t)(n ? n : 1));
+    i64 *first = xmalloc(sizeof(i64) * (size_t)(n ? n : 1));  /* next unused position in column k */
+    for (i64 j = 0; j < n; j++) head[j] = -1;
+    int status = 0;
+    *fail_col = -1;
+    for (i64 j = 0; j < n; j++) {
+        i32 np = 0;
+        for (i64 p = Cp[j]; p < Cp[j + 1]; p++) {
+            i32 i = Ci[p];
+            if (!mk[i]) { mk[i] = 1; pat[np++] = i; w[i] = 0.0; }
+            w[i] += Cx[p];
+        }
+        if (!mk[j]) { mk[j] = 1; pat[np++] = (i32)j; w[j] = 0.0; }
+        /* left-looking updates from every column k < j with L(j,k) != 0 */
+        i64 k = head[j];
+        while (k >= 0) {
+            i64 nk = next[k];
+            i64 pos = first[k];
+            double ljk = s->Lx[pos];
+            for (i64 p = pos; p < s->Lp[k + 1]; p++) {
+                i32 i = s->Li[p];
+                if (!mk[i]) { mk[i] = 1; pat[np++] = i; w[i] = 0.0; }
+                w[i] -= s->Lx[p] * ljk;
+            }
+            first[k] = pos + 1;
+            if (first[k] < s->Lp[k + 1]) {
+                i32 r = s->Li[first[k]];
+                next[k] = head[r]; head[r] = k;
+            }
+            k = nk;
+        }
+        double d = w[j];
+        if (!(d > 0.0) || !isfinite(d)) {
+            status = 1; *fail_col = s->perm[j];
+            for (i32 q = 0; q < np; q++) mk[pat[q]] = 0;
+            break;
+        }
+        double ljj = sqrt(d);
+        qsort(pat, (size_t)np, sizeof(i32), cmp_i32);   /* pat[0] == j */
+        if (nz + np > cap) {
+            while (nz + np > cap) cap *= 2;
+            s->Li = realloc(s->Li, sizeof(i32) * (size_t)cap); s->Lx = realloc(s->Lx, sizeof(double) * (size_t)cap);
+            if (!s->Li || !s->Lx) abort();
+        }
+        s->Li[nz] = (i32)j; s->Lx[nz] = ljj; nz++;
+        for (i32 q = 1; q < np; q++) { s->Li[nz] = pat[q]; s->Lx[nz] = w[pat[q]] / ljj; nz++; }
+        for (i32 q = 0; q < np; q++) mk[pat[q]] = 0;
+        s->Lp[j + 1] = nz;
+        first[j] = s->Lp[j] + 1;
+        if (first[j] < s->Lp[j + 1]) { i32 r = s->Li[first[j]]; next[j] = head[r]; head[r] = j; }
+    }
+    free(w); free(mk); free(pat); free(head); free(next); free(first); free(Cp); free(Ci); free(Cx);
+    s->factored = (status == 0);
+    return status;
+}
+
+i64 orc_L_nnz(const orc *s) { return s->factored ? s->Lp[s->n] : -1; }
+
+void orc_L(const orc *s, i64 *colptr, i32 *rowind, double *val) {
+    memcpy(colptr, s->Lp, sizeof(i64) * (size_t)(s->n + 1));
+    memcpy(rowind, s->Li, sizeof(i32) * (size_t)s->Lp[s->n]);
+    memcpy(val, s->Lx, sizeof(double) * (size_t)s->Lp[s->n]);
+}
+
+/* x = H_gamma^{-1} b (original order): forward column-oriented, backward dot form */
+void orc_hsolve(const orc *s, const double *b, double *x) {
+    i64 n = s->n;
+    double *t = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    for (i64 k = 0; k < n; k++) t[k] = b[s->perm[k]];
+    for (i64 j = 0; j < n; j++) {                /* L t = P b */
+        t[j] /= s->Lx[s->Lp[j]];
+        for (i64 p = s->Lp[j] + 1; p < s->Lp[j + 1]; p++) t[s->Li[p]] -= s->Lx[p] * t[j];
+    }
+    for (i64 j = n - 1; j >= 0; j--) {           /* L^T u = t */
+        double a = t[j];
+        for (i64 p = s->Lp[j] + 1; p < s->Lp[j + 1]; p++) a -= s->Lx[p] * t[s->Li[p]];
+        t[j] = a / s->Lx[s->Lp[j]];
+    }
+    for (i64 k = 0; k < n; k++) x[s->perm[k]] = t[k];
+    free(t);
+}
+
+/* ------------------------------------------------------------------ */
+/* operators                                                           */
+/* ------------------------------------------------------------------ */
+
+static void J_mul(const orc *s, const double *v, double *out) {          /* out = J v */
+    for (i64 i = 0; i < s->m; i++) {
+        double a = 0.0;
+        for (i64 p = s->Jp[i]; p < s->Jp[i + 1]; p++) a += s->Jx[p] * v[s->Ji[p]];
+        out[i] = a;
+    }
+}
+static void JT_mul(const orc *s, const double *v, double *out) {         /* out = J^T v */
+    for (i64 j = 0; j < s->n; j++) out[j] = 0.0;
+    for (i64 i = 0; i < s->m; i++)
+        for (i64 p = s->Jp[i]; p < s->Jp[i + 1]; p++) out[s->Ji[p]] += s->Jx[p] * v[i];
+}
+static void H_mul(const orc *s, const double *v, double *out) {          /* out = H v, from tril(H) */
+    for (i64 j = 0; j < s->n; j++) out[j] = 0.0;
+    for (i64 i = 0; i < s->n; i++)
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+            i64 j = s->Hi[p];
+            out[i] += s->Hx[p] * v[j];
+            if (j != i) out[j] += s->Hx[p] * v[i];
+        }
+}
+static double dot(const double *a, const double *b, i64 n) { double s = 0.0; for (i64 i = 0; i < n; i++) s += a[i] * b[i]; return s; }
+static double nrm2(const double *a, i64 n) { return sqrt(dot(a, a, n)); }
+
+/* res = r - K z;  K = [H + D_x + delta I, J^T; J, 0] */
+static void kkt_residual(const orc *s, const double *r1, const double *r2, const double *x, const double *y,
+                         double *res1, double *res2) {
+    i64 n = s->n, m = s->m;
+    double *hx = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *jty = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *jx = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    H_mul(s, x, hx); JT_mul(s, y, jty); J_mul(s, x, jx);
+    for (i64 j = 0; j < n; j++) res1[j] = r1[j] - (hx[j] + (s->Dx[j] + s->delta) * x[j] + jty[j]);
+    for (i64 i = 0; i < m; i++) res2[i] = r2[i] - jx[i];
+    free(hx); free(jty); free(jx);
+}
+
+/* ||K||_inf: max row sum of |K| */
+static double kkt_norm_inf(const orc *s) {
+    i64 n = s->n, m = s->m;
+    double *rs = xcalloc((size_t)(n + m ? n + m : 1), sizeof(double));
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+            i64 j = s->Hi[p];
+            if (j == i) rs[i] += fabs(s->Hx[p] + s->Dx[i] + s->delta);
+            else { rs[i] += fabs(s->Hx[p]); rs[j] += fabs(s->Hx[p]); }
+        }
+    for (i64 i = 0; i < n; i++) {  /* diagonals absent from the tril(H) pattern */
+        int has = 0;
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) if (s->Hi[p] == i) has = 1;
+        if (!has) rs[i] += fabs(s->Dx[i] + s->delta);
+    }
+    for (i64 i = 0; i < m; i++)
+        for (i64 p = s->Jp[i]; p < s->Jp[i + 1]; p++) { rs[n + i] += fabs(s->Jx[p]); rs[s->Ji[p]] += fabs(s->Jx[p]); }
+    double mx = 0.0;
+    for (i64 i = 0; i < n + m; i++) if (rs[i] > mx) mx = rs[i];
+    free(rs);
+    return mx;
+}
+
+/* RR, BE (Sec. 5.1, ||K||_inf for ||K||_2) and the FP64 evaluation floor
+ * u * || |K||z| + |r| ||_2 / ||r||_2 (u = 2^-53). */
+void orc_metrics(orc *s, const double *r1, const double *r2, const double *x, const double *y, double *out3) {
+    i64 n = s->n, m = s->m;
+    double *a = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *b = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    kkt_residual(s, r1, r2, x, y, a, b);
+    double rn = sqrt(dot(a, a, n) + dot(b, b, m));
+    double bn = sqrt(dot(r1, r1, n) + dot(r2, r2, m));
+    double zn = sqrt(dot(x, x, n) + dot(y, y, m));
+    double kn = kkt_norm_inf(s);
+    /* |K||z| + |r| */
+    double *f1 = xcalloc((size_t)(n ? n : 1), sizeof(double)), *f2 = xcalloc((size_t)(m ? m : 1), sizeof(double));
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+            i64 j = s->Hi[p];
+            f1[i] += fabs(s->Hx[p] * x[j]);
+            if (j != i) f1[j] += fabs(s->Hx[p] * x[i]);
+        }
+    for (i64 i = 0; i < n; i++) f1[i] += fabs((s->Dx[i] + s->delta) * x[i]) + fabs(r1[i]);
+    for (i64 i = 0; i < m; i++)
+        for (i64 p = s->Jp[i]; p < s->Jp[i + 1]; p++) {
+            f1[s->Ji[p]] += fabs(s->Jx[p] * y[i]);
+            f2[i] += fabs(s->Jx[p] * x[s->Ji[p]]);
+        }
+    for (i64 i = 0; i < m; i++) f2[i] += fabs(r2[i]);
+    double fl = ldexp(1.0, -53) * sqrt(dot(f1, f1, n) + dot(f2, f2, m));
+    out3[0] = bn > 0 ? rn / bn : rn;
+    out3[1] = rn / (kn * zn + bn);
+    out3[2] = bn > 0 ? fl / bn : fl;
+    free(a); free(b); free(f1); free(f2);
+}
+
+/* ------------------------------------------------------------------ */
+/* hybrid solve: Algorithm 1 solve phase + FP64 refinement             */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double cg_tol;        /* 1e-12 */
+    double kkt_tol;       /* 1e-10 */
+    double qf_eps;        /* 1e-14 */
+    double delta2;        /* used only after a breakdown; 0 = report breakdown */
+    i64 max_cg;           /* <= 0: min(m, 1000) */
+    i64 max_refine;       /* 10 */
+} orc_opts;
+
+typedef struct {
+    i64 status;           /* 0 ok, 2 CG breakdown, 3 not converged, -3 no factor */
+    i64 passes;           /* hybrid passes run (1 + refinement steps) */
+    i64 cg_iters[16];     /* CG iterations per pass */
+    double rr_hist[16];   /* RR after each pass */
+    double rr, be, floor;
+    i64 inertia[3];
+} orc_report;
+
+/* one hybrid pass: (x, y) ~= K^{-1} (r1, r2); returns CG iterations, or -1 on
+ * breakdown with delta2 == 0 */
+static i64 hybrid_pass(const orc *s, const orc_opts *o, const double *r1, const double *r2, double *x, double *y,
+                       int *breakdown) {
+    i64 n = s->n, m = s->m;
+    double *rhat = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *w = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *t = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *u = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *bv = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *res = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *p = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *q = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    *breakdown = 0;
+    /* rhat = r1 + gamma J^T r2 */
+    JT_mul(s, r2, t);
+    for (i64 j = 0; j < n; j++) rhat[j] = r1[j] + s->gamma * t[j];
+    /* w = H_gamma^{-1} rhat ;  b = J w - r2 */
+    orc_hsolve(s, rhat, w);
+    J_mul(s, w, bv);
+    for (i64 i = 0; i < m; i++) bv[i] -= r2[i];
+    /* CG on S y = b, y0 = 0 */
+    i64 max_cg = o->max_cg > 0 ? o->max_cg : (m < 1000 ? m : 1000);
+    if (max_cg < 1) max_cg = 1;
+    for (i64 i = 0; i < m; i++) { y[i] = 0.0; res[i] = bv[i]; p[i] = bv[i]; }
+    double bnorm = nrm2(bv, m);
+    double rho = dot(res, res, m);
+    double curv0 = -1.0;
+    i64 it = 0;
+    double d2 = 0.0;
+    if (m > 0 && bnorm > 0.0) {
+        while (it < max_cg) {
+            JT_mul(s, p, t);
+            orc_hsolve(s, t, u);
+            J_mul(s, u, q);
+            for (i64 i = 0; i < m; i++) q[i] += d2 * p[i];
+            double pq = dot(p, q, m), pp = dot(p, p, m);
+            if (curv0 < 0.0) curv0 = pq / pp;
+            if (!(pq > o->qf_eps * pp * curv0)) {
+                /* small quadratic form (Algorithm 1): restart on S + delta2 I */
+                *breakdown = 1;
+                if (o->delta2 > 0.0 && d2 == 0.0) {
+                    d2 = o->delta2;
+                    for (i64 i = 0; i < m; i++) { y[i] = 0.0; res[i] = bv[i]; p[i] = bv[i]; }
+                    rho = dot(res, res, m); curv0 = -1.0;
+                    continue;
+                }
+                break;
+            }
+            double alpha = rho / pq;
+            for (i64 i = 0; i < m; i++) { y[i] += alpha * p[i]; res[i] -= alpha * q[i]; }
+            double rho1 = dot(res, res, m);
+            it++;
+            if (sqrt(rho1) <= o->cg_tol * bnorm) break;
+            double beta = rho1 / rho;
+            rho = rho1;
+            for (i64 i = 0; i < m; i++) p[i] = res[i] + beta * p[i];
+        }
+    }
+    /* x = H_gamma^{-1} (rhat - J^T y) */
+    JT_mul(s, y, t);
+    for (i64 j = 0; j < n; j++) t[j] = rhat[j] - t[j];
+    orc_hsolve(s, t, x);
+    free(rhat); free(w); free(t); free(u); free(bv); free(res); free(p); free(q);
+    return it;
+}
+
+int orc_solve(orc *s, const orc_opts *o, const double *r1, const double *r2, double *x, double *y, orc_report *rep) {
+    i64 n = s->n, m = s->m;
+    memset(rep, 0, sizeof(*rep));
+    if (!s->factored) { rep->status = -3; return -3; }
+    double *ex = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *ey = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *g1 = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *g2 = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double rn = sqrt(dot(r1, r1, n) + dot(r2, r2, m));
+    for (i64 j = 0; j < n; j++) { x[j] = 0.0; g1[j] = r1[j]; }
+    for (i64 i = 0; i < m; i++) { y[i] = 0.0; g2[i] = r2[i]; }
+    i64 max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    if (max_ref > 15) max_ref = 15;
+    int brk_any = 0;
+    double rr = rn > 0 ? 1.0 : 0.0;
+    i64 pass = 0;
+    while (pass <= max_ref) {
+        int brk = 0;
+        i64 it = hybrid_pass(s, o, g1, g2, ex, ey, &brk);
+        brk_any |= brk;
+        for (i64 j = 0; j < n; j++) x[j] += ex[j];
+        for (i64 i = 0; i < m; i++) y[i] += ey[i];
+        kkt_residual(s, r1, r2, x, y, g1, g2);
+        rr = rn > 0 ? sqrt(dot(g1, g1, n) + dot(g2, g2, m)) / rn : 0.0;
+        rep->cg_iters[pass] = it;
+        rep->rr_hist[pass] = rr;
+        pass++;
+        if (rr <= o->kkt_tol || brk) break;
+    }
+    rep->passes = pass;
+    double mt[3];
+    orc_metrics(s, r1, r2, x, y, mt);
+    rep->rr = mt[0]; rep->be = mt[1]; rep->floor = mt[2];
+    rep->inertia[0] = n; rep->inertia[1] = brk_any ? m - 1 : m; rep->inertia[2] = brk_any ? 1 : 0;
+    rep->status = brk_any && o->delta2 == 0.0 ? 2 : (rr <= o->kkt_tol ? 0 : 3);
+    free(ex); free(ey); free(g1); free(g2);
+    return (int)rep->status;
+}
+
+/* single hybrid pass without refinement (for CG-count and Theorem 4 tests) */
+i64 orc_hybrid_once(orc *s, const orc_opts *o, const double *r1, const double *r2, double *x, double *y, int *breakdown) {
+    if (!s->factored) return -3;
+    return hybrid_pass(s, o, r1, r2, x, y, breakdown);
+}
+
+/* plain operator applications, exposed so tests can check them against
+ * dense matrices */
+void orc_apply_K(const orc *s, const double *x, const double *y, double *o1, double *o2) {
+    i64 n = s->n, m = s->m;
+    double *z1 = xcalloc((size_t)(n ? n : 1), sizeof(double)), *z2 = xcalloc((size_t)(m ? m : 1), sizeof(double));
+    kkt_residual(s, z1, z2, x, y, o1, o2);
+    for (i64 j = 0; j < n; j++) o1[j] = -o1[j];
+    for (i64 i = 0; i < m; i++) o2[i] = -o2[i];
+    free(z1); free(z2);
+}

@@ -1,0 +1,101 @@
+"""Small shared helpers for the tests: dense views of generated systems and
+tiny hand-made systems. No solver arithmetic lives here."""
+from __future__ import annotations
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import scipy.sparse as sp
+
+from paper_2110_03636_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def csr_from_dense_lower(Hd):
+    """tril(H) CSR with the diagonal always present."""
+    n = Hd.shape[0]
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j in range(i + 1):
+            if Hd[i, j] != 0 or i == j:
+                rows.append(i); cols.append(j); vals.append(float(Hd[i, j]))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, np.asarray(rows) + 1, 1)
+    return np.cumsum(rp).astype(np.int64), np.asarray(cols, np.int32), np.asarray(vals)
+
+
+def csr_from_dense(Jd):
+    A = sp.csr_matrix(np.asarray(Jd, dtype=np.float64))
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def batch_from_dense(Hd, Dx, Jd, delta, gamma, r1, r2):
+    Hd = np.asarray(Hd, float); Jd = np.asarray(Jd, float).reshape(-1, Hd.shape[0])
+    Hp, Hc, Hv = csr_from_dense_lower(Hd)
+    if Jd.shape[0]:
+        Jp, Jc, Jv = csr_from_dense(Jd)
+    else:
+        Jp, Jc, Jv = np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0)
+    pat = synth.Pattern(Hd.shape[0], Jd.shape[0], Hp, Hc, Jp, Jc)
+    return synth.Batch(pat, Hv[None], Jv[None], np.asarray(Dx, float)[None],
+                       np.array([delta], float), np.array([gamma], float),
+                       np.asarray(r1, float)[None], np.asarray(r2, float).reshape(1, -1))
+
+
+def dense_H(batch, b=0):
+    p = batch.pattern
+    L = sp.csr_matrix((batch.H_val[b], p.H_col, p.H_rowptr), shape=(p.n_x, p.n_x)).toarray()
+    return L + np.tril(L, -1).T
+
+
+def dense_J(batch, b=0):
+    p = batch.pattern
+    return sp.csr_matrix((batch.J_val[b], p.J_col, p.J_rowptr), shape=(p.m, p.n_x)).toarray()
+
+
+def dense_K(batch, b=0):
+    p = batch.pattern
+    n, m = p.n_x, p.m
+    A = dense_H(batch, b) + np.diag(batch.D_x[b] + batch.delta[b])
+    J = dense_J(batch, b)
+    K = np.zeros((n + m, n + m))
+    K[:n, :n] = A
+    K[n:, :n] = J
+    K[:n, n:] = J.T
+    return K
+
+
+def dense_Hgamma(batch, b=0):
+    J = dense_J(batch, b)
+    return dense_H(batch, b) + np.diag(batch.D_x[b] + batch.delta[b]) + batch.gamma[b] * (J.T @ J)
+
+
+def csc_to_dense_lower(cp, ri, v, n):
+    return sp.csc_matrix((v, ri, cp), shape=(n, n)).toarray()
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def frac_array(lst):
+    return np.array([float(Fraction(s)) for s in lst])
+
+
+def tiny_dense_like(n_x, seed, gamma=1e4, dx_exp=1.0, delta=1e-8):
+    b = synth.dense_like(n_x, seed=seed, gamma=gamma, dx_exp=dx_exp, delta=delta)
+    return b
+
+
+def tiny_grid_like(n_x, seed, gamma=1e4, dx_exp=1.0, nb=1):
+    return synth.grid_like(n_x, nb=nb, seed=seed, gammas=(gamma,), dx_exp=dx_exp)
+
+
+def with_gamma(batch, gamma):
+    import dataclasses
+    return dataclasses.replace(batch, gamma=np.full_like(batch.gamma, gamma))
