@@ -435,3 +435,22 @@ def test_refinement_contracts():
     h = info["rr_hist"]
     assert info["passes"] >= 2 and info["rr"] <= 1e-10
     assert all(c < a for a, c in zip(h, h[1:])), h
+
+
+@pytest.mark.parametrize("gen,seed", [("dense", 91), ("grid", 92)])
+def test_single_pass_is_exact(gen, seed):
+    # eqs. Schur1/Schur2 are an exact transform: one pass with an accurate CG
+    # already gives z (refinement must not be what makes the answer right)
+    b = H.tiny_dense_like(40, seed) if gen == "dense" else H.tiny_grid_like(60, seed)
+    s = _sys(b)
+    s.factor(s.order_mindeg())
+    x, y, it, brk = s.hybrid_once(b.r1[0], b.r2[0])
+    K = H.dense_K(b)
+    r = np.concatenate([b.r1[0], b.r2[0]])
+    z_np = np.linalg.solve(K, r)
+    z = np.concatenate([x, y])
+    assert not brk
+    assert np.linalg.norm(z - z_np) / np.linalg.norm(z_np) < max(1e-10, np.linalg.cond(K) * 1e-15)
+    assert np.linalg.norm(K @ z - r) / np.linalg.norm(r) < 1e-9
+    xs, ys, info = s.solve(b.r1[0], b.r2[0])
+    assert info["passes"] <= 2
