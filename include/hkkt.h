@@ -1,0 +1,204 @@
+/*
+ * hkkt.h -- C ABI of the MI355X hybrid direct-iterative KKT solver.
+ *
+ * Method: Regev, Chiang, Darve, Petra, Saunders, Swirydowicz, Peles,
+ * "A Hybrid Direct-Iterative Method for Solving KKT Linear Systems".
+ *
+ * The solver handles the 2x2 block KKT system of Sec. 3 (eq. linsys2x2, with
+ * the inequality block already eliminated, m_d = 0) with a regularised (1,1)
+ * block:
+ *
+ *     K z = r,   K = [ H_delta  J^T ]   H_delta = H + D_x + delta*I,
+ *                    [ J        0   ]   z = (x, y),  r = (r1, r2).
+ *
+ * Following Sec. 4 (eqs. linsys2x2mod, eq:gamma, Schur1, Schur2) it assembles
+ * H_gamma = H_delta + gamma*J^T J on a fixed pattern, factors it by supernodal
+ * Cholesky (one symbolic analysis per pattern, Sec. 2 reuse list), and solves
+ *     S y = J H_gamma^{-1} rhat - r2,  S = J H_gamma^{-1} J^T,  rhat = r1 + gamma J^T r2
+ * by unpreconditioned CG, then H_gamma x = rhat - J^T y (Algorithm 1, solve
+ * phase). FP64 iterative refinement on the full KKT residual follows; in mixed
+ * precision the factor and the triangular solves run in FP32 and an FP64
+ * refactor is taken when refinement stalls.
+ *
+ * Conventions for every entry point:
+ *  - Indices are 0-based. Row pointers are int64, column indices int32.
+ *  - tril(H): lower triangle of H as CSR (rows), columns sorted and unique
+ *    within a row; the diagonal may be absent (it is added structurally).
+ *  - J: m x n_x CSR, columns sorted and unique within a row.
+ *  - Value arrays follow the pattern order given to hkkt_analyze. Batched
+ *    value arrays are batch-major and contiguous: instance b starts at
+ *    b*nnz (or b*n_x, b*m).
+ *  - Buffers are owned by the caller. Pointer mode (hkkt_options) says whether
+ *    value/vector pointers are host or device (device = on the context's
+ *    device, e.g. a torch tensor's data_ptr()). Pattern arrays given to
+ *    hkkt_analyze are always host pointers and are copied.
+ *  - Work is enqueued on the stream given to hkkt_create; entry points return
+ *    after their outputs are written (factor: after its one status read;
+ *    solve: after x and y are written).
+ *  - Return codes: 0 OK; positive = numerical outcome the caller may act on
+ *    (1 NOT_SPD, 2 CG_BREAKDOWN, 3 NOT_CONVERGED); negative = usage or device
+ *    error with a message in hkkt_last_error (-1 ARG, -2 PATTERN, -3 STATE,
+ *    -4 DEVICE, -5 OOM).
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef HKKT_H
+#define HKKT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HKKT_OK = 0,
+    HKKT_NOT_SPD = 1,         /* Cholesky of H_gamma met a pivot <= 0 or not finite */
+    HKKT_CG_BREAKDOWN = 2,    /* CG met a small quadratic form (rank-deficient J) */
+    HKKT_NOT_CONVERGED = 3,   /* CG or refinement did not reach the tolerances */
+    HKKT_ERR_ARG = -1,
+    HKKT_ERR_PATTERN = -2,
+    HKKT_ERR_STATE = -3,
+    HKKT_ERR_DEVICE = -4,
+    HKKT_ERR_OOM = -5
+};
+
+enum { HKKT_FP64 = 0, HKKT_MIXED = 1 };
+enum { HKKT_PTR_HOST = 0, HKKT_PTR_DEVICE = 1 };
+
+typedef struct hkkt_ctx hkkt_ctx;
+
+typedef struct {
+    int precision;          /* HKKT_FP64 or HKKT_MIXED (FP32 factor + solves, FP64 refinement) */
+    int pointer_mode;       /* HKKT_PTR_HOST or HKKT_PTR_DEVICE */
+    double cg_tol;          /* relative CG residual, Sec. 5.1 uses 1e-12 */
+    double cg_tol_mixed;    /* inner CG tolerance when the operator is FP32 (default 1e-7) */
+    double kkt_tol;         /* target relative KKT residual ||r - K z||_2 / ||r||_2 */
+    double quad_form_eps;   /* breakdown if p'q <= eps*||p||^2*(p0'q0/||p0||^2) (default 1e-14) */
+    double delta2;          /* 0: report CG_BREAKDOWN; > 0: restart CG on S + delta2*I (Algorithm 1) */
+    int max_cg;             /* <= 0: min(m, 1000) */
+    int max_refine;         /* refinement passes after the first (default 10) */
+    int ordering;           /* 0 = own approximate minimum degree (Sec. 5.3), 1 = natural */
+    int relax;              /* supernode amalgamation: 0 none (fundamental), 1 default */
+    int reserved[6];
+} hkkt_options;
+
+typedef struct {
+    int status;             /* per instance, codes as above */
+    int cg_iters;           /* total CG iterations over all passes */
+    int passes;             /* hybrid passes (1 + refinement steps) */
+    int fp64_fallback;      /* 1 if the instance was refactored in FP64 */
+    double rr;              /* ||r - K z||_2 / ||r||_2, FP64 on the device */
+    double be;              /* ||r - K z||_2 / (||K||_inf ||z||_2 + ||r||_2), Sec. 5.1 */
+    double floor;           /* 2^-53 * || |K||z| + |r| ||_2 / ||r||_2 */
+    int64_t fail_col;       /* first failing pivot (original index) or -1 */
+} hkkt_info;
+
+/* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-7,
+ * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
+ * ordering 0, relax 1. */
+void hkkt_default_options(hkkt_options *opt);
+
+/* Create a context bound to the current HIP device and the given stream
+ * (NULL = the null stream). Returns 0 or a negative code. */
+int hkkt_create(hkkt_ctx **ctx, const hkkt_options *opt, void *hip_stream);
+void hkkt_destroy(hkkt_ctx *ctx);
+const char *hkkt_last_error(const hkkt_ctx *ctx);
+
+/* Symbolic analysis, once per pattern (Sec. 2: ordering and symbolic
+ * factorization are needed once per sequence; Sec. 5.3: AMD ordering).
+ * Builds the pattern of H_gamma = tril(H) U diag U tril(J^T J), orders it
+ * (own AMD, or `perm` if non-NULL: perm[k] = original index of the k-th
+ * pivot), computes the elimination tree, supernodes, the assembly map and the
+ * level schedules, and uploads them. Host pointers; copied. Errors: -2 on a
+ * malformed pattern (unsorted/duplicate/out-of-range index, bad row pointers),
+ * -1 if n_x < 1 or m < 0. */
+int hkkt_analyze(hkkt_ctx *ctx, int64_t n_x, int64_t m,
+                 const int64_t *H_rowptr, const int32_t *H_col,
+                 const int64_t *J_rowptr, const int32_t *J_col,
+                 const int32_t *perm);
+
+/* Numeric factorization of nb instances that share the analysed pattern
+ * (Sec. 2: once per matrix; Algorithm 1 "Try LL^T = chol(H_delta)").
+ * H_val [nb][nnz(tril H)], D_x [nb][n_x], J_val [nb][nnz(J)], delta [nb],
+ * gamma [nb] (always host arrays for delta and gamma). status[b] (host, may
+ * be NULL) gets 0 or HKKT_NOT_SPD; fail_col[b] (host, may be NULL) gets the
+ * original index of the first failing pivot in elimination order, or -1.
+ * The values are copied; the caller may reuse its buffers after return.
+ * Returns 0 if every instance factored, 1 if any is NOT_SPD, negative on
+ * error (-3 if not analysed). */
+int hkkt_factor_batch(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
+                      const double *J_val, const double *delta, const double *gamma,
+                      int *status, int64_t *fail_col);
+
+/* Single-instance form of hkkt_factor_batch. */
+int hkkt_factor(hkkt_ctx *ctx, const double *H_val, const double *D_x, const double *J_val,
+                double delta, double gamma, int64_t *fail_col);
+
+/* Solve K z = r for the nb instances of the last factorization (Algorithm 1
+ * solve phase: rhat, w = H_gamma^{-1} rhat, CG on eq. Schur1, x from eq.
+ * Schur2; then refinement to kkt_tol). r1 [nb][n_x], r2 [nb][m] in; x
+ * [nb][n_x], y [nb][m] out; info [nb] (host, may be NULL). nb must equal the
+ * last factorization's nb. Returns the largest per-instance status (0 if all
+ * converged), or negative on error (-3 if not factored successfully). */
+int hkkt_solve_batch(hkkt_ctx *ctx, int nb, const double *r1, const double *r2,
+                     double *x, double *y, hkkt_info *info);
+
+int hkkt_solve(hkkt_ctx *ctx, const double *r1, const double *r2, double *x, double *y,
+               hkkt_info *info);
+
+/* Inertia (positive, negative, zero eigenvalue counts) of K for instance b
+ * after a successful factor and solve (Sec. 4.2, Theorem 3: a successful
+ * Cholesky of H_gamma gives n_x positive; with full-rank J the Schur
+ * complement adds m negative). A CG breakdown counts one zero eigenvalue.
+ * Returns -3 if no successful factor+solve precedes it. */
+int hkkt_inertia(const hkkt_ctx *ctx, int b, int64_t out[3]);
+
+/* ---- host-only symbolic analysis handle (no GPU needed) ------------------
+ * The same analysis hkkt_analyze runs, exposed for inspection and tests.
+ * Arguments as for hkkt_analyze; ordering/relax as in hkkt_options. */
+typedef struct hkkt_symbolic hkkt_symbolic;
+int hkkt_symbolic_create(hkkt_symbolic **out, int64_t n_x, int64_t m,
+                         const int64_t *H_rowptr, const int32_t *H_col,
+                         const int64_t *J_rowptr, const int32_t *J_col,
+                         const int32_t *perm, int ordering, int relax, char *err, int errlen);
+void hkkt_symbolic_destroy(hkkt_symbolic *sym);
+
+/* The analysis owned by a context (valid until the next hkkt_analyze). */
+const hkkt_symbolic *hkkt_get_symbolic(const hkkt_ctx *ctx);
+
+/* Symbolic statistics (host ints): stats[0] n_x, [1] m, [2] nnz(tril
+ * H_gamma), [3] nnz(L) (structural), [4] L storage entries (supernodal
+ * panels), [5] supernodes, [6] factor levels, [7] sum of c_j^2 over columns
+ * (factor flop proxy), [8] max supernode width, [9] max supernode rows,
+ * [10] contribution-block workspace entries, [11] etree height, [12] update
+ * vector entries, [13] nnz(J). */
+int hkkt_symbolic_stats(const hkkt_symbolic *sym, int64_t stats[16]);
+
+/* Final elimination order: perm[k] = original index of pivot k. */
+int hkkt_symbolic_perm(const hkkt_symbolic *sym, int32_t *perm);
+
+/* Supernode partition: sn_first [ns+1], sn_rowptr [ns+1], sn_rows
+ * [sn_rowptr[ns]], sn_parent [ns], level_ptr [nlevels+1], level_sn [ns].
+ * Any pointer may be NULL. */
+int hkkt_symbolic_supernodes(const hkkt_symbolic *sym, int32_t *sn_first, int64_t *sn_rowptr,
+                             int32_t *sn_rows, int32_t *sn_parent, int32_t *level_ptr,
+                             int32_t *level_sn);
+
+/* Copy the factor of instance b into CSC form in the permuted order
+ * (colptr [n_x+1], rowind, val [nnz(L)] in FP64), for parity tests. */
+int hkkt_get_factor(hkkt_ctx *ctx, int b, int64_t *colptr, int32_t *rowind, double *val);
+
+/* Apply H_gamma^{-1} (forward + backward supernodal triangular solves) of
+ * instance set [0, nb) to b, in the original order: x = H_gamma^{-1} b.
+ * Vectors [nb][n_x], per pointer mode. For parity tests. */
+int hkkt_hsolve(hkkt_ctx *ctx, int nb, const double *b, double *x);
+
+/* Time spent in the phases of the last calls (milliseconds, host clock
+ * around stream-synchronised phases): [0] analyze, [1] assemble+factor,
+ * [2] solve, [3] fp64 fallback. */
+int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,81 @@
+// Host-side symbolic analysis of H_gamma = tril(H) U diag U tril(J^T J).
+//
+// Sec. 2 (reuse list): ordering and symbolic factorization are done once per
+// pattern; Sec. 5.3: the fill-reducing order is approximate minimum degree.
+// Everything here is integer work on the host; the result is uploaded once.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace hkkt {
+
+using i64 = int64_t;
+using i32 = int32_t;
+
+struct AnalyzeOptions {
+    int ordering = 0;   // 0 own AMD, 1 natural
+    int relax = 1;      // supernode amalgamation level
+    int lds_rows = 64;  // fronts with at most this many rows use the LDS kernel
+};
+
+// One "big front" work item list per (level, step) of the blocked front
+// factorization, built on the host so that kernels only index tables.
+struct Symbolic {
+    i64 n = 0, m = 0;
+    std::vector<i32> perm, iperm;          // perm[k] = original index of pivot k
+
+    // supernodes, numbered in postorder (children before parents)
+    i32 ns = 0;
+    std::vector<i32> sn_first;             // [ns+1] first column
+    std::vector<i64> sn_rowptr;            // [ns+1] into sn_rows
+    std::vector<i32> sn_rows;              // sorted row indices; first w are the columns
+    std::vector<i64> sn_lptr;              // [ns+1] L storage offsets (nr*w col-major panel)
+    std::vector<i64> sn_cbptr;             // [ns+1] contribution block offsets ((nr-w)^2)
+    std::vector<i64> sn_uvptr;             // [ns+1] update-vector offsets (nr-w)
+    std::vector<i32> sn_parent;            // -1 for roots
+    std::vector<i32> child_ptr, child_list;
+    std::vector<i32> relmap;               // at sn_uvptr[s]+k: index of rows_below(s)[k] in rows(parent)
+    std::vector<i32> col2sn;
+
+    // levels (leaves = 0)
+    std::vector<i32> level_ptr, level_sn;  // supernodes grouped by level
+    i32 nlevels = 0;
+
+    // structural statistics
+    i64 nnzA = 0, nnzL = 0, Lsize = 0, CBsize = 0, UVsize = 0;
+    double flops_proxy = 0;                // sum over columns of c_j^2
+    i32 max_w = 0, max_nr = 0;
+    i64 etree_height = 0;
+
+    // assembly map over the entries of tril(P H_gamma P^T)
+    std::vector<i64> a_dst;                // L storage offset
+    std::vector<i32> a_h;                  // index into H_val or -1
+    std::vector<i32> a_d;                  // original variable for D_x + delta, or -1
+    std::vector<i64> a_pptr;               // [nnzA+1] into a_pa/a_pb
+    std::vector<i32> a_pa, a_pb;           // J value index pairs: gamma*J[pa]*J[pb]
+
+    // operators in the permuted order
+    std::vector<i64> J_rowptr;             // rows of J unchanged
+    std::vector<i32> J_colp;               // iperm[col]
+    std::vector<i64> JT_rowptr;            // [n+1] J^T rows = permuted columns
+    std::vector<i32> JT_col;               // J row index
+    std::vector<i32> JT_src;               // index into J_val
+    std::vector<i64> HF_rowptr;            // full symmetric H, permuted rows
+    std::vector<i32> HF_col;
+    std::vector<i32> HF_src;               // index into H_val
+    i64 nnzH = 0, nnzJ = 0;
+};
+
+// Validates the CSR inputs; returns "" if fine, else a message.
+std::string validate_pattern(i64 n, i64 m, const i64* Hp, const i32* Hi, const i64* Jp, const i32* Ji);
+
+// Own approximate minimum degree on the symmetric graph (ptr/adj without
+// the diagonal). Returns perm[k] = node eliminated k-th.
+std::vector<i32> amd_order(i64 n, const std::vector<i64>& ptr, const std::vector<i32>& adj);
+
+// Full analysis. perm_in may be null. Returns "" or an error message.
+std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, const i64* Jp,
+                    const i32* Ji, const i32* perm_in, const AnalyzeOptions& opt);
+
+}  // namespace hkkt

@@ -1,0 +1,1048 @@
+// Orchestration of the hybrid direct-iterative KKT solve and its C ABI.
+//
+// One context = one analysed pattern on one device and stream. A factor call
+// fills a batch of nb instances (shared pattern, own values); a solve call
+// runs Algorithm 1's solve phase (rhat, w = H_gamma^{-1} rhat, CG on the
+// Schur complement, primal recovery) followed by FP64 refinement on the full
+// KKT residual, for every instance of the batch at once. In mixed precision
+// the factor and the triangular solves are FP32; instances whose FP32 factor
+// fails or whose refinement stalls are refactored and finished in FP64.
+#include "../../include/hkkt.h"
+#include "analysis.hpp"
+#include "kernels.hpp"
+#include "kernels.inl"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+struct hkkt_symbolic {
+    hkkt::Symbolic S;
+};
+
+namespace hkkt {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                        \
+    do {                                                                                                 \
+        hipError_t e_ = (x);                                                                             \
+        if (e_ != hipSuccess)                                                                            \
+            throw ::hkkt::Error(e_ == hipErrorOutOfMemory ? HKKT_ERR_OOM : HKKT_ERR_DEVICE,               \
+                                std::string(#x) + ": " + hipGetErrorString(e_));                         \
+    } while (0)
+
+#define KCHK() HIPCHK(hipGetLastError())
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// device memory owned by the library
+// ---------------------------------------------------------------------------
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        if (b == 0) b = 16;
+        HIPCHK(hipMalloc(&p, b));
+        bytes = b;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+static void upload(DBuf& d, const std::vector<T>& h, hipStream_t st) {
+    d.ensure(h.size() * sizeof(T));
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+static unsigned grid1(i64 n, unsigned cap = 65535u * 4) {
+    i64 g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > (i64)cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// uploaded analysis + level schedules
+// ---------------------------------------------------------------------------
+struct DevSym {
+    DBuf sn_first, sn_rowptr, sn_rows, sn_lptr, sn_cbptr, sn_uvptr, child_ptr, child_list, relmap, perm;
+    DBuf a_dst, a_h, a_d, a_pptr, a_pa, a_pb;
+    DBuf J_rowptr, J_colp, JT_rowptr, JT_col, JT_src, HF_rowptr, HF_col, HF_src;
+    DBuf lev_all, lev_small, lev_big;   // supernode lists, level-major
+    std::vector<i32> all_ptr, small_ptr, big_ptr;
+    std::vector<int> all_maxnr, small_maxnr;
+    SymView v{};
+};
+
+constexpr size_t kMaxLds = 65536;
+
+static int lds_rows_limit(int elem_bytes) {
+    // LDS front of nr x nr entries within 64 KiB
+    return elem_bytes == 8 ? 90 : 128;
+}
+
+static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_rows) {
+    upload(D.sn_first, S.sn_first, st);
+    upload(D.sn_rowptr, S.sn_rowptr, st);
+    upload(D.sn_rows, S.sn_rows, st);
+    upload(D.sn_lptr, S.sn_lptr, st);
+    upload(D.sn_cbptr, S.sn_cbptr, st);
+    upload(D.sn_uvptr, S.sn_uvptr, st);
+    upload(D.child_ptr, S.child_ptr, st);
+    upload(D.child_list, S.child_list, st);
+    upload(D.relmap, S.relmap, st);
+    upload(D.perm, S.perm, st);
+    upload(D.a_dst, S.a_dst, st);
+    upload(D.a_h, S.a_h, st);
+    upload(D.a_d, S.a_d, st);
+    upload(D.a_pptr, S.a_pptr, st);
+    upload(D.a_pa, S.a_pa, st);
+    upload(D.a_pb, S.a_pb, st);
+    upload(D.J_rowptr, S.J_rowptr, st);
+    upload(D.J_colp, S.J_colp, st);
+    upload(D.JT_rowptr, S.JT_rowptr, st);
+    upload(D.JT_col, S.JT_col, st);
+    upload(D.JT_src, S.JT_src, st);
+    upload(D.HF_rowptr, S.HF_rowptr, st);
+    upload(D.HF_col, S.HF_col, st);
+    upload(D.HF_src, S.HF_src, st);
+    // level lists: all supernodes of a level; split by front size
+    std::vector<i32> all, small, big;
+    D.all_ptr.assign(1, 0);
+    D.small_ptr.assign(1, 0);
+    D.big_ptr.assign(1, 0);
+    D.all_maxnr.clear();
+    D.small_maxnr.clear();
+    for (i32 l = 0; l < S.nlevels; l++) {
+        int mx = 0, mxs = 0;
+        for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
+            const i32 s = S.level_sn[q];
+            const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+            all.push_back(s);
+            mx = std::max(mx, nr);
+            if (nr <= lds_rows) { small.push_back(s); mxs = std::max(mxs, nr); }
+            else big.push_back(s);
+        }
+        D.all_ptr.push_back((i32)all.size());
+        D.small_ptr.push_back((i32)small.size());
+        D.big_ptr.push_back((i32)big.size());
+        D.all_maxnr.push_back(mx);
+        D.small_maxnr.push_back(mxs);
+    }
+    upload(D.lev_all, all, st);
+    upload(D.lev_small, small, st);
+    upload(D.lev_big, big, st);
+    SymView& v = D.v;
+    v.n = S.n; v.m = S.m; v.ns = S.ns;
+    v.sn_first = D.sn_first.as<i32>();
+    v.sn_rowptr = D.sn_rowptr.as<i64>();
+    v.sn_rows = D.sn_rows.as<i32>();
+    v.sn_lptr = D.sn_lptr.as<i64>();
+    v.sn_cbptr = D.sn_cbptr.as<i64>();
+    v.sn_uvptr = D.sn_uvptr.as<i64>();
+    v.child_ptr = D.child_ptr.as<i32>();
+    v.child_list = D.child_list.as<i32>();
+    v.relmap = D.relmap.as<i32>();
+    v.perm = D.perm.as<i32>();
+    v.Lsize = S.Lsize; v.CBsize = S.CBsize; v.UVsize = S.UVsize;
+    v.nnzA = S.nnzA;
+    v.a_dst = D.a_dst.as<i64>();
+    v.a_h = D.a_h.as<i32>();
+    v.a_d = D.a_d.as<i32>();
+    v.a_pptr = D.a_pptr.as<i64>();
+    v.a_pa = D.a_pa.as<i32>();
+    v.a_pb = D.a_pb.as<i32>();
+    v.nnzH = S.nnzH; v.nnzJ = S.nnzJ; v.nnzHF = (i64)S.HF_col.size();
+    v.J_rowptr = D.J_rowptr.as<i64>();
+    v.J_colp = D.J_colp.as<i32>();
+    v.JT_rowptr = D.JT_rowptr.as<i64>();
+    v.JT_col = D.JT_col.as<i32>();
+    v.JT_src = D.JT_src.as<i32>();
+    v.HF_rowptr = D.HF_rowptr.as<i64>();
+    v.HF_col = D.HF_col.as<i32>();
+    v.HF_src = D.HF_src.as<i32>();
+}
+
+// ---------------------------------------------------------------------------
+// a batch of instances at one precision
+// ---------------------------------------------------------------------------
+struct Batch {
+    int nb = 0;
+    int prec = HKKT_FP64;   // precision of L / triangular solves
+    // values (FP64)
+    DBuf H, J, JT, HF, Dx, Dxp, delta, gamma;
+    // factor
+    DBuf L, CB, fail;
+    // solve workspace
+    DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
+    DBuf rsq, rowred, knorm, active;
+    std::vector<int> h_fail;   // per instance min failing permuted column (INT_MAX ok)
+
+    ValView vals() const {
+        ValView V;
+        V.nb = nb;
+        V.H = H.as<double>(); V.J = J.as<double>(); V.JT = JT.as<double>(); V.HF = HF.as<double>();
+        V.Dxp = Dxp.as<double>(); V.Dx = Dx.as<double>(); V.delta = delta.as<double>(); V.gamma = gamma.as<double>();
+        return V;
+    }
+    size_t esz() const { return prec == HKKT_MIXED ? 4 : 8; }
+};
+
+}  // namespace hkkt
+
+using namespace hkkt;
+
+struct hkkt_ctx {
+    hkkt_options opt{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    bool analysed = false;
+    hkkt_symbolic sym;
+    DevSym dev;
+    Batch main, fb;               // fb: FP64 fallback sub-batch
+    std::vector<int> fb_idx;      // main index of each fallback instance
+    int nb = 0;
+    bool factored = false;
+    std::vector<int> fstatus;     // per instance factor status after fallback
+    std::vector<int64_t> ffail;   // per instance failing original column
+    std::vector<int> fp64_factored;  // instance has a valid FP64 factor in fb (mixed)
+    std::vector<int> solved;      // per instance: last solve status (for inertia), -100 none
+    std::vector<int> breakdown;
+    double ms[8] = {0};
+};
+
+namespace hkkt {
+
+// ---------------------------------------------------------------------------
+// kernel launch helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
+    const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
+    hipStream_t st = c->stream;
+    const int nb = B.nb;
+    T* L = B.L.as<T>();
+    T* CB = B.CB.as<T>();
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
+    KCHK();
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb, INT_MAX);
+    KCHK();
+    hipLaunchKernelGGL(k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.vals(), L, active);
+    KCHK();
+    for (i32 l = 0; l < S.nlevels; l++) {
+        const int ns_small = D.small_ptr[l + 1] - D.small_ptr[l];
+        if (ns_small > 0) {
+            const int nr = D.small_maxnr[l];
+            const size_t lds = (size_t)nr * nr * sizeof(T);
+            hipLaunchKernelGGL(k_front_lds<T>, dim3(ns_small, nb), dim3(kBlock), lds, st, D.v,
+                               D.lev_small.as<i32>() + D.small_ptr[l], L, CB, B.fail.as<int>(), active);
+            KCHK();
+        }
+        const int ns_big = D.big_ptr[l + 1] - D.big_ptr[l];
+        if (ns_big > 0) {
+            hipLaunchKernelGGL(k_front_global<T>, dim3(ns_big, nb), dim3(kBlock), 0, st, D.v,
+                               D.lev_big.as<i32>() + D.big_ptr[l], L, CB, B.fail.as<int>(), active);
+            KCHK();
+        }
+    }
+}
+
+// X <- H_gamma^{-1} X (in place), per instance skip by active/st
+template <typename T>
+static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* active, const CGState* st_) {
+    const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
+    hipStream_t st = c->stream;
+    const int nb = B.nb;
+    const T* L = B.L.as<T>();
+    T* X = B.X.as<T>();
+    T* UV = B.UV.as<T>();
+    for (i32 l = 0; l < S.nlevels; l++) {
+        const int cnt = D.all_ptr[l + 1] - D.all_ptr[l];
+        const size_t lds = (size_t)(kTri * kTri + D.all_maxnr[l]) * sizeof(T);
+        if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
+        hipLaunchKernelGGL(k_fwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
+                           UV, active, st_);
+        KCHK();
+    }
+    for (i32 l = S.nlevels - 1; l >= 0; l--) {
+        const int cnt = D.all_ptr[l + 1] - D.all_ptr[l];
+        const size_t lds = (size_t)(kTri * kTri + D.all_maxnr[l]) * sizeof(T);
+        hipLaunchKernelGGL(k_bwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
+                           active, st_);
+        KCHK();
+    }
+}
+
+static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {
+    const Symbolic& S = c->sym.S;
+    B.nb = nb;
+    B.H.ensure((size_t)nb * std::max<i64>(1, S.nnzH) * 8);
+    B.J.ensure((size_t)nb * std::max<i64>(1, S.nnzJ) * 8);
+    B.JT.ensure((size_t)nb * std::max<i64>(1, S.nnzJ) * 8);
+    B.HF.ensure((size_t)nb * std::max<i64>(1, (i64)S.HF_col.size()) * 8);
+    B.Dx.ensure((size_t)nb * S.n * 8);
+    B.Dxp.ensure((size_t)nb * S.n * 8);
+    B.delta.ensure((size_t)nb * 8);
+    B.gamma.ensure((size_t)nb * 8);
+    B.fail.ensure((size_t)nb * 4);
+    B.active.ensure((size_t)nb * 4);
+}
+
+static void alloc_factor(hkkt_ctx* c, Batch& B) {
+    const Symbolic& S = c->sym.S;
+    B.L.ensure((size_t)B.nb * std::max<i64>(1, S.Lsize) * B.esz());
+    B.CB.ensure((size_t)B.nb * std::max<i64>(1, S.CBsize) * B.esz());
+}
+
+static void alloc_solve(hkkt_ctx* c, Batch& B) {
+    const Symbolic& S = c->sym.S;
+    const size_t nb = B.nb, n = S.n, m = std::max<i64>(1, S.m);
+    for (DBuf* d : {&B.r1p, &B.xz, &B.g1, &B.rhat, &B.ex}) d->ensure(nb * n * 8);
+    for (DBuf* d : {&B.r2, &B.yz, &B.g2, &B.bvec, &B.y, &B.res, &B.p, &B.q}) d->ensure(nb * m * 8);
+    B.X.ensure(nb * n * B.esz());
+    B.UV.ensure(nb * std::max<i64>(1, S.UVsize) * B.esz());
+    const size_t nblk = grid1(S.n + S.m, 1u << 30);
+    for (DBuf* d : {&B.part1, &B.part2, &B.pfloor}) d->ensure(nb * nblk * 8);
+    B.st.ensure(nb * sizeof(CGState));
+    B.live.ensure(16);
+    for (DBuf* d : {&B.rsq, &B.rowred, &B.knorm}) d->ensure(nb * 8);
+}
+
+// copy values of the given (host or device) buffers into B, instance i of B
+// from instance src_idx[i] of the source arrays
+static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx, const double* J,
+                        const double* delta, const double* gamma, const std::vector<int>* src_idx, bool device_ptrs) {
+    const Symbolic& S = c->sym.S;
+    hipStream_t st = c->stream;
+    const hipMemcpyKind kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const int nb = B.nb;
+    auto cp = [&](DBuf& dst, const double* src, i64 len) {
+        if (len == 0) return;
+        if (!src_idx) {
+            HIPCHK(hipMemcpyAsync(dst.p, src, (size_t)nb * len * 8, kind, st));
+        } else {
+            for (int i = 0; i < nb; i++)
+                HIPCHK(hipMemcpyAsync(dst.as<double>() + (i64)i * len, src + (i64)(*src_idx)[i] * len, (size_t)len * 8,
+                                      kind, st));
+        }
+    };
+    cp(B.H, H, S.nnzH);
+    cp(B.J, J, S.nnzJ);
+    cp(B.Dx, Dx, S.n);
+    std::vector<double> hd(nb), hg(nb);
+    for (int i = 0; i < nb; i++) {
+        const int s = src_idx ? (*src_idx)[i] : i;
+        hd[i] = delta[s];
+        hg[i] = gamma[s];
+    }
+    HIPCHK(hipMemcpyAsync(B.delta.p, hd.data(), nb * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.gamma.p, hg.data(), nb * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_vals, dim3(grid1(std::max<i64>({S.n, S.nnzJ, (i64)S.HF_col.size()}), 1024), nb),
+                       dim3(kBlock), 0, st, c->dev.v, B.H.as<double>(), B.J.as<double>(), B.Dx.as<double>(),
+                       B.JT.as<double>(), B.HF.as<double>(), B.Dxp.as<double>());
+    KCHK();
+    HIPCHK(hipStreamSynchronize(st));   // host staging vectors go out of scope
+}
+
+// factor all instances of B whose active flag is set; returns per-instance
+// min failing permuted column (INT_MAX = ok) in B.h_fail
+static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h) {
+    hipStream_t st = c->stream;
+    alloc_factor(c, B);
+    HIPCHK(hipMemcpyAsync(B.active.p, active_h.data(), B.nb * 4, hipMemcpyHostToDevice, st));
+    if (B.prec == HKKT_MIXED) launch_factor<float>(c, B, B.active.as<int>());
+    else launch_factor<double>(c, B, B.active.as<int>());
+    B.h_fail.assign(B.nb, INT_MAX);
+    HIPCHK(hipMemcpyAsync(B.h_fail.data(), B.fail.p, B.nb * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// one hybrid pass on the residual (g1, g2): ex, y <- approx K^{-1} g
+// ---------------------------------------------------------------------------
+template <typename T>
+static void hybrid_pass(hkkt_ctx* c, Batch& B, int max_cg, double cg_tol, std::vector<CGState>& hst) {
+    const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
+    hipStream_t st = c->stream;
+    const int nb = B.nb;
+    const int* act = B.active.as<int>();
+    const ValView V = B.vals();
+    CGState* cst = B.st.as<CGState>();
+    const unsigned gn = grid1(S.n, 4096), gm = grid1(S.m);
+    T* X = B.X.as<T>();
+    // rhat = g1 + gamma J^T g2
+    hipLaunchKernelGGL(k_jt<double>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
+                       B.g2.as<double>(), B.rhat.as<double>(), act, (const CGState*)nullptr);
+    KCHK();
+    hipLaunchKernelGGL((k_cast<double, T>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(), X, (i64)S.n, act,
+                       (const CGState*)nullptr);
+    KCHK();
+    launch_trisolve<T>(c, B, act, nullptr);
+    // bvec = J w - g2
+    const unsigned gmb = (unsigned)std::max<i64>(1, (S.m + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
+                       (const double*)nullptr, (const CGState*)nullptr, 0, B.bvec.as<double>(), B.part1.as<double>(),
+                       (double*)nullptr, act);
+    KCHK();
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, act, (i64)S.m);
+    KCHK();
+    hipLaunchKernelGGL(k_cg_vecinit, dim3(gm, nb), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
+                       B.res.as<double>(), B.p.as<double>(), (i64)S.m, act);
+    KCHK();
+    int check_every = 4;
+    for (int it = 0; it < max_cg && S.m > 0; it++) {
+        hipLaunchKernelGGL(k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, (const double*)nullptr, 1.0, 0,
+                           B.p.as<double>(), X, act, (const CGState*)cst);
+        KCHK();
+        launch_trisolve<T>(c, B, act, cst);
+        hipLaunchKernelGGL(k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
+                           B.p.as<double>(), (const CGState*)cst, 1, B.q.as<double>(), B.part1.as<double>(),
+                           B.part2.as<double>(), act);
+        KCHK();
+        hipLaunchKernelGGL(k_cg_alpha, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), B.part2.as<double>(),
+                           (int)gmb, c->opt.quad_form_eps, c->opt.delta2);
+        KCHK();
+        hipLaunchKernelGGL(k_cg_update, dim3(gmb, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.q.as<double>(),
+                           B.bvec.as<double>(), B.y.as<double>(), B.res.as<double>(), (const CGState*)cst, (i64)S.m,
+                           B.part1.as<double>());
+        KCHK();
+        hipLaunchKernelGGL(k_cg_beta, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, cg_tol, max_cg);
+        KCHK();
+        hipLaunchKernelGGL(k_cg_p, dim3(gm, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.res.as<double>(),
+                           (const CGState*)cst, (i64)S.m);
+        KCHK();
+        if ((it + 1) % check_every == 0) {
+            hipLaunchKernelGGL(k_count_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, nb, B.live.as<int>());
+            KCHK();
+            int live = 0;
+            HIPCHK(hipMemcpyAsync(&live, B.live.p, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (live == 0) break;
+        }
+    }
+    // x = H_gamma^{-1} (rhat - J^T y)
+    hipLaunchKernelGGL(k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.rhat.as<double>(), -1.0, 0,
+                       B.y.as<double>(), X, act, (const CGState*)nullptr);
+    KCHK();
+    launch_trisolve<T>(c, B, act, nullptr);
+    hipLaunchKernelGGL((k_cast<T, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
+                       act, (const CGState*)nullptr);
+    KCHK();
+    hst.resize(nb);
+    HIPCHK(hipMemcpyAsync(hst.data(), cst, nb * sizeof(CGState), hipMemcpyDeviceToHost, st));
+}
+
+// z += e; g = r - K z; returns ||g||^2 per instance in rsq (host)
+static void update_residual(hkkt_ctx* c, Batch& B, std::vector<double>& rsq, bool add, double* floor_out) {
+    const Symbolic& S = c->sym.S;
+    hipStream_t st = c->stream;
+    const int nb = B.nb;
+    const int* act = B.active.as<int>();
+    if (add) {
+        hipLaunchKernelGGL(k_axpy2, dim3(grid1(S.n + S.m, 4096), nb), dim3(kBlock), 0, st, B.xz.as<double>(),
+                           B.ex.as<double>(), (i64)S.n, B.yz.as<double>(), B.y.as<double>(), (i64)S.m, act);
+        KCHK();
+    }
+    const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_residual, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.r1p.as<double>(),
+                       B.r2.as<double>(), B.xz.as<double>(), B.yz.as<double>(), B.g1.as<double>(), B.g2.as<double>(),
+                       B.part1.as<double>(), floor_out ? B.pfloor.as<double>() : (double*)nullptr, act);
+    KCHK();
+    hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g, B.rsq.as<double>());
+    KCHK();
+    rsq.resize(nb);
+    HIPCHK(hipMemcpyAsync(rsq.data(), B.rsq.p, nb * 8, hipMemcpyDeviceToHost, st));
+    if (floor_out) {
+        hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.pfloor.as<double>(), (int)g,
+                           B.rowred.as<double>());
+        KCHK();
+        HIPCHK(hipMemcpyAsync(floor_out, B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+struct InstState {
+    int status = HKKT_NOT_CONVERGED;
+    int cg = 0, passes = 0, brk = 0;
+    double rr = INFINITY, rr_prev = INFINITY, rnorm = 0.0;
+    bool fallback = false;
+};
+
+// refinement loop on batch B for the instances with run[i] set; vectors
+// r1p/r2 and (if warm) xz/yz must be in place.
+static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std::vector<int>& run, bool warm,
+                   bool allow_stall_exit) {
+    const Symbolic& S = c->sym.S;
+    hipStream_t st = c->stream;
+    const int nb = B.nb;
+    const hkkt_options& o = c->opt;
+    std::vector<int> act(run);
+    const int max_cg = o.max_cg > 0 ? o.max_cg : (int)std::max<i64>(1, std::min<i64>(S.m, 1000));
+    const double cg_tol = B.prec == HKKT_MIXED ? std::max(o.cg_tol, o.cg_tol_mixed) : o.cg_tol;
+    std::vector<double> rsq;
+    HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
+    if (!warm) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid1((i64)nb * S.n)), dim3(kBlock), 0, st, B.xz.as<double>(),
+                           (i64)nb * S.n, 0.0);
+        KCHK();
+        if (S.m > 0) {
+            hipLaunchKernelGGL(k_fill<double>, dim3(grid1((i64)nb * S.m)), dim3(kBlock), 0, st, B.yz.as<double>(),
+                               (i64)nb * S.m, 0.0);
+            KCHK();
+        }
+    }
+    update_residual(c, B, rsq, false, nullptr);
+    for (int i = 0; i < nb; i++)
+        if (act[i]) {
+            is[i].rr_prev = is[i].rnorm > 0 ? std::sqrt(rsq[i]) / is[i].rnorm : 0.0;
+            if (is[i].rnorm == 0.0 || is[i].rr_prev <= o.kkt_tol) {
+                is[i].status = HKKT_OK;
+                is[i].rr = is[i].rr_prev;
+                act[i] = 0;
+            }
+        }
+    int max_ref = o.max_refine >= 0 ? o.max_refine : 10;
+    std::vector<CGState> hst;
+    for (int pass = 0; pass <= max_ref; pass++) {
+        bool any = false;
+        for (int i = 0; i < nb; i++) any |= act[i] != 0;
+        if (!any) break;
+        HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
+        if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, max_cg, cg_tol, hst);
+        else hybrid_pass<double>(c, B, max_cg, cg_tol, hst);
+        update_residual(c, B, rsq, true, nullptr);
+        for (int i = 0; i < nb; i++) {
+            if (!act[i]) continue;
+            InstState& s = is[i];
+            s.passes++;
+            s.cg += hst[i].it;
+            const double rr = s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0;
+            s.rr = rr;
+            if (hst[i].breakdown && o.delta2 == 0.0) {
+                s.brk = 1;
+                s.status = HKKT_CG_BREAKDOWN;
+                act[i] = 0;
+            } else if (rr <= o.kkt_tol) {
+                s.status = HKKT_OK;
+                act[i] = 0;
+            } else if (allow_stall_exit && (!(rr < 0.5 * s.rr_prev) || s.passes >= 6)) {
+                s.fallback = true;
+                s.status = HKKT_NOT_CONVERGED;
+                act[i] = 0;
+            } else {
+                s.status = HKKT_NOT_CONVERGED;
+            }
+            s.rr_prev = rr;
+        }
+    }
+}
+
+}  // namespace hkkt
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void hkkt_default_options(hkkt_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->precision = HKKT_FP64;
+    o->pointer_mode = HKKT_PTR_HOST;
+    o->cg_tol = 1e-12;
+    o->cg_tol_mixed = 1e-7;
+    o->kkt_tol = 1e-10;
+    o->quad_form_eps = 1e-14;
+    o->delta2 = 0.0;
+    o->max_cg = 0;
+    o->max_refine = 10;
+    o->ordering = 0;
+    o->relax = 1;
+}
+
+#define ABI_GUARD(ctx, ...)                                              \
+    try {                                                                \
+        __VA_ARGS__                                                      \
+    } catch (const hkkt::Error& e) {                                     \
+        if (ctx) (ctx)->err = e.what();                                  \
+        return e.code;                                                   \
+    } catch (const std::bad_alloc&) {                                    \
+        if (ctx) (ctx)->err = "host out of memory";                      \
+        return HKKT_ERR_OOM;                                             \
+    } catch (const std::exception& e) {                                  \
+        if (ctx) (ctx)->err = e.what();                                  \
+        return HKKT_ERR_DEVICE;                                          \
+    }
+
+int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
+    if (!out) return HKKT_ERR_ARG;
+    *out = nullptr;
+    hkkt_ctx* c = new (std::nothrow) hkkt_ctx();
+    if (!c) return HKKT_ERR_OOM;
+    if (opt) c->opt = *opt;
+    else hkkt_default_options(&c->opt);
+    if (c->opt.precision != HKKT_FP64 && c->opt.precision != HKKT_MIXED) { delete c; return HKKT_ERR_ARG; }
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return HKKT_ERR_DEVICE; }
+    c->main.prec = c->opt.precision;
+    c->fb.prec = HKKT_FP64;
+    *out = c;
+    return HKKT_OK;
+}
+
+void hkkt_destroy(hkkt_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete c;
+}
+
+const char* hkkt_last_error(const hkkt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int hkkt_symbolic_create(hkkt_symbolic** out, int64_t n, int64_t m, const int64_t* Hp, const int32_t* Hi,
+                         const int64_t* Jp, const int32_t* Ji, const int32_t* perm, int ordering, int relax, char* err,
+                         int errlen) {
+    if (!out) return HKKT_ERR_ARG;
+    *out = nullptr;
+    try {
+        std::unique_ptr<hkkt_symbolic> s(new hkkt_symbolic());
+        AnalyzeOptions ao;
+        ao.ordering = ordering;
+        ao.relax = relax;
+        std::string e = analyze(s->S, n, m, Hp, Hi, Jp, Ji, perm, ao);
+        if (!e.empty()) {
+            if (err && errlen > 0) { std::snprintf(err, errlen, "%s", e.c_str()); }
+            return (n < 1 || m < 0) ? HKKT_ERR_ARG : HKKT_ERR_PATTERN;
+        }
+        *out = s.release();
+        return HKKT_OK;
+    } catch (const std::bad_alloc&) {
+        return HKKT_ERR_OOM;
+    }
+}
+
+void hkkt_symbolic_destroy(hkkt_symbolic* s) { delete s; }
+
+const hkkt_symbolic* hkkt_get_symbolic(const hkkt_ctx* c) { return c && c->analysed ? &c->sym : nullptr; }
+
+int hkkt_symbolic_stats(const hkkt_symbolic* sym, int64_t st[16]) {
+    if (!sym || !st) return HKKT_ERR_ARG;
+    const Symbolic& S = sym->S;
+    std::memset(st, 0, 16 * sizeof(int64_t));
+    st[0] = S.n; st[1] = S.m; st[2] = S.nnzA; st[3] = S.nnzL; st[4] = S.Lsize; st[5] = S.ns; st[6] = S.nlevels;
+    st[7] = (int64_t)S.flops_proxy; st[8] = S.max_w; st[9] = S.max_nr; st[10] = S.CBsize; st[11] = S.etree_height;
+    st[12] = S.UVsize; st[13] = S.nnzJ;
+    int64_t lower = 0;
+    for (i32 s = 0; s < S.ns; s++) {
+        const int64_t w = S.sn_first[s + 1] - S.sn_first[s], nr = S.sn_rowptr[s + 1] - S.sn_rowptr[s];
+        lower += nr * w - w * (w - 1) / 2;
+    }
+    st[14] = lower;
+    st[15] = (int64_t)S.sn_rows.size();
+    return HKKT_OK;
+}
+
+int hkkt_symbolic_perm(const hkkt_symbolic* sym, int32_t* perm) {
+    if (!sym || !perm) return HKKT_ERR_ARG;
+    std::memcpy(perm, sym->S.perm.data(), sym->S.perm.size() * 4);
+    return HKKT_OK;
+}
+
+int hkkt_symbolic_supernodes(const hkkt_symbolic* sym, int32_t* sn_first, int64_t* sn_rowptr, int32_t* sn_rows,
+                             int32_t* sn_parent, int32_t* level_ptr, int32_t* level_sn) {
+    if (!sym) return HKKT_ERR_ARG;
+    const Symbolic& S = sym->S;
+    if (sn_first) std::memcpy(sn_first, S.sn_first.data(), S.sn_first.size() * 4);
+    if (sn_rowptr) std::memcpy(sn_rowptr, S.sn_rowptr.data(), S.sn_rowptr.size() * 8);
+    if (sn_rows) std::memcpy(sn_rows, S.sn_rows.data(), S.sn_rows.size() * 4);
+    if (sn_parent) std::memcpy(sn_parent, S.sn_parent.data(), S.sn_parent.size() * 4);
+    if (level_ptr) std::memcpy(level_ptr, S.level_ptr.data(), S.level_ptr.size() * 4);
+    if (level_sn) std::memcpy(level_sn, S.level_sn.data(), S.level_sn.size() * 4);
+    return HKKT_OK;
+}
+
+int hkkt_analyze(hkkt_ctx* c, int64_t n, int64_t m, const int64_t* Hp, const int32_t* Hi, const int64_t* Jp,
+                 const int32_t* Ji, const int32_t* perm) {
+    if (!c) return HKKT_ERR_ARG;
+    ABI_GUARD(c, {
+        const double t0 = now_ms();
+        c->analysed = false;
+        c->factored = false;
+        AnalyzeOptions ao;
+        ao.ordering = c->opt.ordering;
+        ao.relax = c->opt.relax;
+        std::string e = analyze(c->sym.S, n, m, Hp, Hi, Jp, Ji, perm, ao);
+        if (!e.empty()) {
+            c->err = e;
+            return (n < 1 || m < 0) ? HKKT_ERR_ARG : HKKT_ERR_PATTERN;
+        }
+        HIPCHK(hipSetDevice(c->device));
+        build_devsym(c->dev, c->sym.S, c->stream, lds_rows_limit(c->opt.precision == HKKT_MIXED ? 4 : 8));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->analysed = true;
+        c->ms[0] = now_ms() - t0;
+        return HKKT_OK;
+    })
+}
+
+int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* delta,
+                      const double* gamma, int* status, int64_t* fail_col) {
+    if (!c) return HKKT_ERR_ARG;
+    if (!c->analysed) { c->err = "factor before analyze"; return HKKT_ERR_STATE; }
+    if (nb < 1 || !Dx || !delta || !gamma || (c->sym.S.nnzH > 0 && !H) || (c->sym.S.nnzJ > 0 && !J)) {
+        c->err = "bad factor arguments";
+        return HKKT_ERR_ARG;
+    }
+    ABI_GUARD(c, {
+        const double t0 = now_ms();
+        const Symbolic& S = c->sym.S;
+        const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
+        c->factored = false;
+        c->nb = nb;
+        alloc_values(c, c->main, nb);
+        load_values(c, c->main, H, Dx, J, delta, gamma, nullptr, dev);
+        std::vector<int> all(nb, 1);
+        factor_batch(c, c->main, all);
+        c->fstatus.assign(nb, HKKT_OK);
+        c->ffail.assign(nb, -1);
+        c->fp64_factored.assign(nb, 0);
+        c->solved.assign(nb, -100);
+        c->breakdown.assign(nb, 0);
+        c->fb_idx.clear();
+        std::vector<int> fpos(nb, INT_MAX);
+        for (int b = 0; b < nb; b++) {
+            if (c->main.h_fail[b] != INT_MAX) {
+                if (c->opt.precision == HKKT_MIXED) c->fb_idx.push_back(b);
+                else fpos[b] = c->main.h_fail[b];
+            }
+        }
+        // mixed precision: FP32 factor failed -> FP64 refactor of those instances
+        if (!c->fb_idx.empty()) {
+            const double t1 = now_ms();
+            alloc_values(c, c->fb, (int)c->fb_idx.size());
+            load_values(c, c->fb, H, Dx, J, delta, gamma, &c->fb_idx, dev);
+            std::vector<int> act(c->fb_idx.size(), 1);
+            factor_batch(c, c->fb, act);
+            for (size_t i = 0; i < c->fb_idx.size(); i++) {
+                c->fp64_factored[c->fb_idx[i]] = 1;
+                if (c->fb.h_fail[i] != INT_MAX) fpos[c->fb_idx[i]] = c->fb.h_fail[i];
+            }
+            c->ms[3] = now_ms() - t1;
+        }
+        int rc = HKKT_OK;
+        for (int b = 0; b < nb; b++) {
+            if (fpos[b] != INT_MAX) {
+                c->fstatus[b] = HKKT_NOT_SPD;
+                c->ffail[b] = S.perm[fpos[b]];
+                rc = HKKT_NOT_SPD;
+            }
+            if (status) status[b] = c->fstatus[b];
+            if (fail_col) fail_col[b] = c->ffail[b];
+        }
+        c->factored = true;
+        c->ms[1] = now_ms() - t0;
+        return rc;
+    })
+}
+
+int hkkt_factor(hkkt_ctx* c, const double* H, const double* Dx, const double* J, double delta, double gamma,
+                int64_t* fail_col) {
+    int st = 0;
+    return hkkt_factor_batch(c, 1, H, Dx, J, &delta, &gamma, &st, fail_col);
+}
+
+int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, double* x, double* y, hkkt_info* info) {
+    if (!c) return HKKT_ERR_ARG;
+    if (!c->factored) { c->err = "solve before factor"; return HKKT_ERR_STATE; }
+    if (nb != c->nb || !r1 || !x || (c->sym.S.m > 0 && (!r2 || !y))) { c->err = "bad solve arguments"; return HKKT_ERR_ARG; }
+    ABI_GUARD(c, {
+        const double t0 = now_ms();
+        const Symbolic& S = c->sym.S;
+        hipStream_t st = c->stream;
+        const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
+        const hipMemcpyKind in_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        const hipMemcpyKind out_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        Batch& B = c->main;
+        alloc_solve(c, B);
+        // right-hand side into the permuted order (staged through ex / g2)
+        HIPCHK(hipMemcpyAsync(B.ex.p, r1, (size_t)nb * S.n * 8, in_kind, st));
+        hipLaunchKernelGGL(k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+                           B.ex.as<double>(), B.r1p.as<double>(), (i64)S.n);
+        KCHK();
+        if (S.m > 0) HIPCHK(hipMemcpyAsync(B.r2.p, r2, (size_t)nb * S.m * 8, in_kind, st));
+        // ||r|| per instance
+        const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.r1p.as<double>(), (i64)S.n, B.r2.as<double>(),
+                           (i64)S.m, B.part1.as<double>());
+        KCHK();
+        hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
+                           B.rowred.as<double>());
+        KCHK();
+        std::vector<double> rn2(nb);
+        HIPCHK(hipMemcpyAsync(rn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<InstState> is(nb);
+        std::vector<int> run(nb, 0);
+        for (int b = 0; b < nb; b++) {
+            is[b].rnorm = std::sqrt(rn2[b]);
+            run[b] = c->fstatus[b] == HKKT_OK && !c->fp64_factored[b];
+        }
+        const bool mixed = B.prec == HKKT_MIXED;
+        refine(c, B, is, run, false, mixed);
+        // FP64 completion for mixed-precision fallbacks
+        std::vector<int> fbl;
+        for (int b = 0; b < nb; b++)
+            if (c->fstatus[b] == HKKT_OK && (c->fp64_factored[b] || is[b].fallback)) fbl.push_back(b);
+        if (!fbl.empty()) {
+            const double t1 = now_ms();
+            Batch& F = c->fb;
+            // (re)build the FP64 sub-batch when its membership differs
+            if (fbl != c->fb_idx) {
+                alloc_values(c, F, (int)fbl.size());
+                for (size_t i = 0; i < fbl.size(); i++) {
+                    const int b = fbl[i];
+                    auto cp = [&](DBuf& d, const DBuf& s, i64 len) {
+                        if (len > 0)
+                            HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, s.as<double>() + (i64)b * len,
+                                                  (size_t)len * 8, hipMemcpyDeviceToDevice, st));
+                    };
+                    cp(F.H, B.H, S.nnzH); cp(F.J, B.J, S.nnzJ); cp(F.JT, B.JT, S.nnzJ);
+                    cp(F.HF, B.HF, (i64)S.HF_col.size()); cp(F.Dx, B.Dx, S.n); cp(F.Dxp, B.Dxp, S.n);
+                    cp(F.delta, B.delta, 1); cp(F.gamma, B.gamma, 1);
+                }
+                std::vector<int> act(fbl.size(), 1);
+                factor_batch(c, F, act);
+                c->fb_idx = fbl;
+                for (size_t i = 0; i < fbl.size(); i++) {
+                    c->fp64_factored[fbl[i]] = 1;
+                    if (F.h_fail[i] != INT_MAX) {
+                        is[fbl[i]].status = HKKT_NOT_SPD;
+                    }
+                }
+            }
+            alloc_solve(c, F);
+            const int nf = (int)fbl.size();
+            std::vector<InstState> fs(nf);
+            std::vector<int> frun(nf, 1);
+            for (int i = 0; i < nf; i++) {
+                const int b = fbl[i];
+                fs[i].rnorm = is[b].rnorm;
+                fs[i].cg = is[b].cg;
+                fs[i].passes = is[b].passes;
+                frun[i] = F.h_fail[i] == INT_MAX;
+                auto cp = [&](DBuf& d, const DBuf& s, i64 len) {
+                    if (len > 0)
+                        HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, s.as<double>() + (i64)b * len,
+                                              (size_t)len * 8, hipMemcpyDeviceToDevice, st));
+                };
+                cp(F.r1p, B.r1p, S.n); cp(F.r2, B.r2, S.m); cp(F.xz, B.xz, S.n); cp(F.yz, B.yz, S.m);
+            }
+            // start from the mixed-precision iterate when there is one
+            refine(c, F, fs, frun, true, false);
+            for (int i = 0; i < nf; i++) {
+                const int b = fbl[i];
+                auto cpb = [&](DBuf& d, const DBuf& s, i64 len) {
+                    if (len > 0)
+                        HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)b * len, s.as<double>() + (i64)i * len,
+                                              (size_t)len * 8, hipMemcpyDeviceToDevice, st));
+                };
+                cpb(B.xz, F.xz, S.n); cpb(B.yz, F.yz, S.m);
+                if (frun[i]) {
+                    is[b].status = fs[i].status;
+                    is[b].rr = fs[i].rr;
+                    is[b].brk = fs[i].brk;
+                    is[b].cg = fs[i].cg;
+                    is[b].passes = fs[i].passes;
+                }
+                is[b].fallback = true;
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            c->ms[3] = now_ms() - t1;
+        }
+        // final metrics: RR, BE, floor on the full KKT residual
+        std::vector<int> allact(nb);
+        for (int b = 0; b < nb; b++) allact[b] = c->fstatus[b] == HKKT_OK;
+        HIPCHK(hipMemcpyAsync(B.active.p, allact.data(), nb * 4, hipMemcpyHostToDevice, st));
+        std::vector<double> rsq, fl(nb, 0.0);
+        update_residual(c, B, rsq, false, fl.data());
+        hipLaunchKernelGGL(k_knorm_rows, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.part2.as<double>());
+        KCHK();
+        hipLaunchKernelGGL(k_reduce_max, dim3(nb), dim3(64), 0, st, B.part2.as<double>(), (int)g, B.knorm.as<double>());
+        KCHK();
+        hipLaunchKernelGGL(k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.xz.as<double>(), (i64)S.n, B.yz.as<double>(),
+                           (i64)S.m, B.part1.as<double>());
+        KCHK();
+        hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
+                           B.rowred.as<double>());
+        KCHK();
+        std::vector<double> kn(nb), zn2(nb);
+        HIPCHK(hipMemcpyAsync(kn.data(), B.knorm.p, nb * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(zn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
+        // outputs in the original order
+        hipLaunchKernelGGL(k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+                           B.xz.as<double>(), B.ex.as<double>(), (i64)S.n);
+        KCHK();
+        HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, out_kind, st));
+        if (S.m > 0) HIPCHK(hipMemcpyAsync(y, B.yz.p, (size_t)nb * S.m * 8, out_kind, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int rc = HKKT_OK;
+        for (int b = 0; b < nb; b++) {
+            InstState& s = is[b];
+            int stt = c->fstatus[b] == HKKT_OK ? s.status : c->fstatus[b];
+            const double rnorm = s.rnorm;
+            const double rr = c->fstatus[b] == HKKT_OK ? (rnorm > 0 ? std::sqrt(rsq[b]) / rnorm : std::sqrt(rsq[b])) : NAN;
+            if (stt == HKKT_NOT_CONVERGED && rr <= c->opt.kkt_tol) stt = HKKT_OK;
+            c->solved[b] = stt;
+            c->breakdown[b] = s.brk;
+            rc = std::max(rc, stt);
+            if (info) {
+                hkkt_info& I = info[b];
+                I.status = stt;
+                I.cg_iters = s.cg;
+                I.passes = s.passes;
+                I.fp64_fallback = s.fallback ? 1 : 0;
+                I.rr = rr;
+                I.be = std::sqrt(rsq[b]) / (kn[b] * std::sqrt(zn2[b]) + rnorm);
+                I.floor = std::ldexp(1.0, -53) * std::sqrt(fl[b]) / (rnorm > 0 ? rnorm : 1.0);
+                I.fail_col = c->ffail[b];
+            }
+        }
+        c->ms[2] = now_ms() - t0;
+        return rc;
+    })
+}
+
+int hkkt_solve(hkkt_ctx* c, const double* r1, const double* r2, double* x, double* y, hkkt_info* info) {
+    return hkkt_solve_batch(c, 1, r1, r2, x, y, info);
+}
+
+int hkkt_inertia(const hkkt_ctx* c, int b, int64_t out[3]) {
+    if (!c || !out) return HKKT_ERR_ARG;
+    if (!c->factored || b < 0 || b >= c->nb || c->fstatus[b] != HKKT_OK || c->solved[b] == -100) return HKKT_ERR_STATE;
+    const int64_t nu = c->breakdown[b] ? 1 : 0;
+    out[0] = c->sym.S.n;
+    out[1] = c->sym.S.m - nu;
+    out[2] = nu;
+    return HKKT_OK;
+}
+
+int hkkt_get_factor(hkkt_ctx* c, int b, int64_t* colptr, int32_t* rowind, double* val) {
+    if (!c || !colptr || !rowind || !val) return HKKT_ERR_ARG;
+    if (!c->factored || b < 0 || b >= c->nb) return HKKT_ERR_STATE;
+    ABI_GUARD(c, {
+        const Symbolic& S = c->sym.S;
+        // take the FP64 fallback factor when the instance has one
+        const Batch* B = &c->main;
+        i64 bi = b;
+        for (size_t i = 0; i < c->fb_idx.size(); i++)
+            if (c->fb_idx[i] == b && c->fp64_factored[b]) { B = &c->fb; bi = (i64)i; }
+        std::vector<double> Lh(S.Lsize);
+        if (B->esz() == 8) {
+            HIPCHK(hipMemcpy(Lh.data(), B->L.as<double>() + bi * S.Lsize, S.Lsize * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(S.Lsize);
+            HIPCHK(hipMemcpy(tmp.data(), B->L.as<float>() + bi * S.Lsize, S.Lsize * 4, hipMemcpyDeviceToHost));
+            for (i64 k = 0; k < S.Lsize; k++) Lh[k] = tmp[k];
+        }
+        i64 nz = 0;
+        colptr[0] = 0;
+        for (i32 s = 0; s < S.ns; s++) {
+            const i32 f = S.sn_first[s];
+            const int w = S.sn_first[s + 1] - f;
+            const i64 nr = S.sn_rowptr[s + 1] - S.sn_rowptr[s];
+            for (int jj = 0; jj < w; jj++) {
+                for (i64 ii = jj; ii < nr; ii++) {
+                    rowind[nz] = S.sn_rows[S.sn_rowptr[s] + ii];
+                    val[nz] = Lh[S.sn_lptr[s] + (i64)jj * nr + ii];
+                    nz++;
+                }
+                colptr[f + jj + 1] = nz;
+            }
+        }
+        return HKKT_OK;
+    })
+}
+
+int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
+    if (!c || !bvec || !x) return HKKT_ERR_ARG;
+    if (!c->factored || nb != c->nb) return HKKT_ERR_STATE;
+    ABI_GUARD(c, {
+        const Symbolic& S = c->sym.S;
+        hipStream_t st = c->stream;
+        Batch& B = c->main;
+        alloc_solve(c, B);
+        const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
+        HIPCHK(hipMemcpyAsync(B.ex.p, bvec, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              st));
+        hipLaunchKernelGGL(k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+                           B.ex.as<double>(), B.rhat.as<double>(), (i64)S.n);
+        KCHK();
+        std::vector<int> act(nb, 1);
+        HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
+        const unsigned gn = grid1(S.n, 4096);
+        if (B.prec == HKKT_MIXED) {
+            hipLaunchKernelGGL((k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
+                               B.X.as<float>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+            KCHK();
+            launch_trisolve<float>(c, B, nullptr, nullptr);
+            hipLaunchKernelGGL((k_cast<float, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const float*)B.X.as<float>(),
+                               B.rhat.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+            KCHK();
+        } else {
+            hipLaunchKernelGGL((k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
+                               B.X.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+            KCHK();
+            launch_trisolve<double>(c, B, nullptr, nullptr);
+            hipLaunchKernelGGL((k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st,
+                               (const double*)B.X.as<double>(), B.rhat.as<double>(), (i64)S.n, (const int*)nullptr,
+                               (const CGState*)nullptr);
+            KCHK();
+        }
+        hipLaunchKernelGGL(k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+                           B.rhat.as<double>(), B.ex.as<double>(), (i64)S.n);
+        KCHK();
+        HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipStreamSynchronize(st));
+        return HKKT_OK;
+    })
+}
+
+int hkkt_timings(const hkkt_ctx* c, double ms[8]) {
+    if (!c || !ms) return HKKT_ERR_ARG;
+    std::memcpy(ms, c->ms, sizeof(c->ms));
+    return HKKT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Device kernels of the hybrid direct-iterative KKT solver (gfx950).
+//
+// Layout conventions (all batch-major, instance b at b * per-instance size):
+//  - L storage: supernode s is a dense column-major panel of nr x w entries
+//    (rows = the supernode's sorted row list, first w rows are its columns).
+//  - contribution blocks (multifrontal update matrices): (nr-w) x (nr-w)
+//    column-major, lower triangle used.
+//  - update vectors of the forward solve: (nr-w) entries per supernode.
+//  - vectors live in the permuted order of the symbolic analysis.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hkkt {
+
+using i64 = int64_t;
+using i32 = int32_t;
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kTri = 64;   // diagonal block size of the triangular solves
+
+// Device view of the symbolic analysis.
+struct SymView {
+    i64 n, m;
+    i32 ns;
+    const i32* sn_first;
+    const i64* sn_rowptr;
+    const i32* sn_rows;
+    const i64* sn_lptr;
+    const i64* sn_cbptr;
+    const i64* sn_uvptr;
+    const i32* child_ptr;
+    const i32* child_list;
+    const i32* relmap;
+    const i32* perm;
+    i64 Lsize, CBsize, UVsize;
+    // assembly
+    i64 nnzA;
+    const i64* a_dst;
+    const i32* a_h;
+    const i32* a_d;
+    const i64* a_pptr;
+    const i32* a_pa;
+    const i32* a_pb;
+    // operators
+    i64 nnzH, nnzJ, nnzHF;
+    const i64* J_rowptr;
+    const i32* J_colp;
+    const i64* JT_rowptr;
+    const i32* JT_col;
+    const i32* JT_src;
+    const i64* HF_rowptr;
+    const i32* HF_col;
+    const i32* HF_src;
+};
+
+// Per-batch numeric values (device, FP64 copies owned by the library).
+struct ValView {
+    int nb;
+    const double* H;      // [nb][nnzH]
+    const double* J;      // [nb][nnzJ]
+    const double* JT;     // [nb][nnzJ] values of J^T in JT order
+    const double* HF;     // [nb][nnzHF] full symmetric H, permuted
+    const double* Dxp;    // [nb][n] D_x permuted
+    const double* Dx;     // [nb][n] D_x original order
+    const double* delta;  // [nb]
+    const double* gamma;  // [nb]
+};
+
+// Per-instance CG scalars.
+struct CGState {
+    double rho, pq, pp, bnorm, alpha, beta, curv0, d2;
+    int it, done, breakdown, pad;
+};
+
+}  // namespace hkkt

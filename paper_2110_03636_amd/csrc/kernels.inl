@@ -1,0 +1,702 @@
+// Device kernels (gfx950), included by the library translation unit: assembly of H_gamma into supernodal storage,
+// multifrontal supernodal Cholesky, supernodal triangular solves, SpMV with
+// J and J^T, CG vector updates with deterministic reductions, and the FP64
+// KKT residual. Templated on the factor/solve precision T (float or double);
+// every reduction and every CG scalar is FP64.
+#include "kernels.hpp"
+
+#include <cfloat>
+#include <climits>
+
+namespace hkkt {
+
+__device__ __forceinline__ bool skip_inst(const int* active, const CGState* st, int b) {
+    return (active && !active[b]) || (st && st[b].done);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    return v;
+}
+
+// Block sum; the result is valid in thread 0. `sh` holds kBlock/kWave doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x / kWave); i++) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// utility
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, i64 n, T v) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <typename TI, typename TO>
+__global__ void k_cast(const TI* __restrict__ in, TO* __restrict__ out, i64 len, const int* active,
+                       const CGState* st) {
+    const int b = blockIdx.y;
+    if (skip_inst(active, st, b)) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (i64)gridDim.x * blockDim.x)
+        out[(i64)b * len + i] = (TO)in[(i64)b * len + i];
+}
+
+// permuted gather: out[b][k] = in[b][perm[k]]
+__global__ void k_perm_gather(const i32* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out,
+                              i64 n) {
+    const int b = blockIdx.y;
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
+        out[(i64)b * n + k] = in[(i64)b * n + perm[k]];
+}
+
+// permuted scatter: out[b][perm[k]] = in[b][k]
+__global__ void k_perm_scatter(const i32* __restrict__ perm, const double* __restrict__ in, double* __restrict__ out,
+                               i64 n) {
+    const int b = blockIdx.y;
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (i64)gridDim.x * blockDim.x)
+        out[(i64)b * n + perm[k]] = in[(i64)b * n + k];
+}
+
+// values of J^T (JT order), full symmetric H (permuted) and D_x (permuted)
+__global__ void k_gather_vals(SymView S, const double* __restrict__ H, const double* __restrict__ J,
+                              const double* __restrict__ Dx, double* __restrict__ JT, double* __restrict__ HF,
+                              double* __restrict__ Dxp) {
+    const int b = blockIdx.y;
+    const i64 stride = (i64)gridDim.x * blockDim.x;
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < S.nnzJ; k += stride)
+        JT[(i64)b * S.nnzJ + k] = J[(i64)b * S.nnzJ + S.JT_src[k]];
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < S.nnzHF; k += stride)
+        HF[(i64)b * S.nnzHF + k] = H[(i64)b * S.nnzH + S.HF_src[k]];
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < S.n; k += stride)
+        Dxp[(i64)b * S.n + k] = Dx[(i64)b * S.n + S.perm[k]];
+}
+
+// ---------------------------------------------------------------------------
+// assembly: H_gamma = tril(H) + diag(D_x + delta) + gamma * tril(J^T J)
+// (Sec. 3 and eq. eq:gamma), one thread per entry of tril(P H_gamma P^T),
+// summed in FP64 in a fixed order and written into the supernodal panels.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_assemble(SymView S, ValView V, T* __restrict__ L, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double* H = V.H + (i64)b * S.nnzH;
+    const double* J = V.J + (i64)b * S.nnzJ;
+    const double g = V.gamma[b];
+    const double dl = V.delta[b];
+    T* Lb = L + (i64)b * S.Lsize;
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < S.nnzA; e += (i64)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        const i32 h = S.a_h[e];
+        if (h >= 0) v += H[h];
+        const i32 d = S.a_d[e];
+        if (d >= 0) v += V.Dx[(i64)b * S.n + d] + dl;
+        for (i64 p = S.a_pptr[e]; p < S.a_pptr[e + 1]; p++) v += g * J[S.a_pa[p]] * J[S.a_pb[p]];
+        Lb[S.a_dst[e]] = (T)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// multifrontal supernodal Cholesky
+//
+// Front of supernode s: F (nr x nr, lower) = [panel of s (assembled entries of
+// its w columns) | zero update block], plus the extend-add of every child's
+// contribution block. Partial factorization of the first w columns:
+//   L11 = chol(F11), L21 = F21 L11^{-T}, CB = F22 - L21 L21^T.
+// Right-looking by columns with a single barrier per column: step k scales
+// column k-1 (with the pivot read in step k-1) while it applies the rank-1
+// update of column k to the trailing matrix; the two phases touch disjoint
+// columns. A pivot <= 0 or not finite records the smallest failing column.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool pivot_ok(T d) {
+    return d > T(0) && d <= (T)(sizeof(T) == 8 ? DBL_MAX : FLT_MAX);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __restrict__ list, T* __restrict__ L,
+                                                      T* __restrict__ CB, int* __restrict__ fail, const int* active) {
+    extern __shared__ double smem_d[];
+    T* F = reinterpret_cast<T*>(smem_d);
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const i32 s = list[blockIdx.x];
+    const i32 f = S.sn_first[s];
+    const int w = S.sn_first[s + 1] - f;
+    const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+    const int nc = nr - w;
+    T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    const int nn = nr * nr;
+    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) F[idx] = idx < nr * w ? Lb[idx] : T(0);
+    __syncthreads();
+    for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; q++) {
+        const i32 c = S.child_list[q];
+        const int wc = S.sn_first[c + 1] - S.sn_first[c];
+        const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
+        const i32* rel = S.relmap + S.sn_uvptr[c];
+        const T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[c];
+        for (int idx = threadIdx.x; idx < ncc * ncc; idx += blockDim.x) {
+            const int j = idx / ncc, i = idx - j * ncc;
+            if (i >= j) F[rel[j] * nr + rel[i]] += C[idx];
+        }
+        __syncthreads();
+    }
+    T dprev = T(1);
+    for (int k = 0; k <= w; k++) {
+        const T dk = k < w ? F[k * nr + k] : T(1);
+        if (k > 0) {
+            const int kk = k - 1;
+            const T sq = sqrt(dprev), inv = T(1) / sq;
+            for (int i = kk + threadIdx.x; i < nr; i += blockDim.x) F[kk * nr + i] = i == kk ? sq : F[kk * nr + i] * inv;
+        }
+        if (k < w) {
+            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b], f + k);
+            const T invd = T(1) / dk;
+            const int len = nr - k - 1;
+            for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
+                const int jj = idx / len, ii = idx - jj * len;
+                if (ii >= jj) {
+                    const int i = k + 1 + ii, j = k + 1 + jj;
+                    F[j * nr + i] -= F[k * nr + i] * F[k * nr + j] * invd;
+                }
+            }
+        }
+        dprev = dk;
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < nr * w; idx += blockDim.x) Lb[idx] = F[idx];
+    T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[s];
+    for (int idx = threadIdx.x; idx < nc * nc; idx += blockDim.x) {
+        const int j = idx / nc, i = idx - j * nc;
+        if (i >= j) C[idx] = F[(w + j) * nr + w + i];
+    }
+}
+
+// Same partial factorization for fronts too large for LDS: the front lives in
+// its panel (L storage) and its contribution block (CB workspace).
+template <typename T>
+struct FrontRef {
+    T* P;   // panel nr x w
+    T* C;   // contribution block nc x nc
+    int nr, w, nc;
+    __device__ __forceinline__ T& at(int i, int j) const {
+        return j < w ? P[(i64)j * nr + i] : C[(i64)(j - w) * nc + (i - w)];
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_front_global(SymView S, const i32* __restrict__ list, T* __restrict__ L,
+                                                         T* __restrict__ CB, int* __restrict__ fail,
+                                                         const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const i32 s = list[blockIdx.x];
+    const i32 f = S.sn_first[s];
+    FrontRef<T> F;
+    F.w = S.sn_first[s + 1] - f;
+    F.nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+    F.nc = F.nr - F.w;
+    F.P = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    F.C = CB + (i64)b * S.CBsize + S.sn_cbptr[s];
+    const int nr = F.nr, w = F.w, nc = F.nc;
+    for (i64 idx = threadIdx.x; idx < (i64)nc * nc; idx += blockDim.x) F.C[idx] = T(0);
+    __syncthreads();
+    for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; q++) {
+        const i32 c = S.child_list[q];
+        const int wc = S.sn_first[c + 1] - S.sn_first[c];
+        const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
+        const i32* rel = S.relmap + S.sn_uvptr[c];
+        const T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[c];
+        for (i64 idx = threadIdx.x; idx < (i64)ncc * ncc; idx += blockDim.x) {
+            const int j = (int)(idx / ncc), i = (int)(idx - (i64)j * ncc);
+            if (i >= j) F.at(rel[i], rel[j]) += C[idx];
+        }
+        __syncthreads();
+    }
+    T dprev = T(1);
+    for (int k = 0; k <= w; k++) {
+        const T dk = k < w ? F.at(k, k) : T(1);
+        if (k > 0) {
+            const int kk = k - 1;
+            const T sq = sqrt(dprev), inv = T(1) / sq;
+            for (int i = kk + threadIdx.x; i < nr; i += blockDim.x) F.at(i, kk) = i == kk ? sq : F.at(i, kk) * inv;
+        }
+        if (k < w) {
+            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b], f + k);
+            const T invd = T(1) / dk;
+            const int len = nr - k - 1;
+            // columns j of the trailing matrix, rows i >= j
+            for (i64 idx = threadIdx.x; idx < (i64)len * len; idx += blockDim.x) {
+                const int jj = (int)(idx / len), ii = (int)(idx - (i64)jj * len);
+                if (ii >= jj) {
+                    const int i = k + 1 + ii, j = k + 1 + jj;
+                    F.at(i, j) -= F.at(i, k) * F.at(j, k) * invd;
+                }
+            }
+        }
+        dprev = dk;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// supernodal triangular solves, one work-group per (supernode, instance) of a
+// level. Forward (L y = b), multifrontal form: each supernode gathers its
+// children's update vectors (the amount to subtract at their rows below),
+// solves with its diagonal block and emits L21 y plus the pass-through part
+// as its own update vector; no atomics, deterministic.
+// Backward (L^T x = y), pull form: gather x at the rows below (ancestors,
+// already final), subtract L21^T x, solve with L11^T.
+// The diagonal block is staged in LDS in kTri x kTri tiles and solved by one
+// wavefront with lane shuffles.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
+                                                T* __restrict__ X, T* __restrict__ UV, const int* active,
+                                                const CGState* st) {
+    extern __shared__ double smem_d[];
+    T* D = reinterpret_cast<T*>(smem_d);
+    T* u = D + kTri * kTri;
+    const int b = blockIdx.y;
+    if (skip_inst(active, st, b)) return;
+    const i32 s = list[blockIdx.x];
+    const i32 f = S.sn_first[s];
+    const int w = S.sn_first[s + 1] - f;
+    const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+    const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    T* x = X + (i64)b * S.n;
+    T* uvb = UV + (i64)b * S.UVsize;
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) u[i] = i < w ? x[f + i] : T(0);
+    __syncthreads();
+    for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; q++) {
+        const i32 c = S.child_list[q];
+        const int wc = S.sn_first[c + 1] - S.sn_first[c];
+        const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
+        const i32* rel = S.relmap + S.sn_uvptr[c];
+        const T* uc = uvb + S.sn_uvptr[c];
+        for (int k = threadIdx.x; k < ncc; k += blockDim.x) {
+            const int pos = rel[k];
+            u[pos] += pos < w ? -uc[k] : uc[k];
+        }
+        __syncthreads();
+    }
+    for (int kb = 0; kb < w; kb += kTri) {
+        const int bw = min(kTri, w - kb);
+        for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
+            const int jj = idx / bw, ii = idx - jj * bw;
+            D[jj * kTri + ii] = Lb[(i64)(kb + jj) * nr + kb + ii];
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            const int lane = threadIdx.x;
+            T val = lane < bw ? u[kb + lane] : T(0);
+            for (int k = 0; k < bw; k++) {
+                if (lane == k) val = val / D[k * kTri + k];
+                const T yk = __shfl(val, k, kWave);
+                if (lane > k && lane < bw) val -= D[k * kTri + lane] * yk;
+            }
+            if (lane < bw) u[kb + lane] = val;
+        }
+        __syncthreads();
+        for (int i = kb + bw + threadIdx.x; i < nr; i += blockDim.x) {
+            T sum = T(0);
+            for (int k = 0; k < bw; k++) sum += Lb[(i64)(kb + k) * nr + i] * u[kb + k];
+            u[i] += i < w ? -sum : sum;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+        if (i < w) x[f + i] = u[i];
+        else uvb[S.sn_uvptr[s] + (i - w)] = u[i];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
+                                                T* __restrict__ X, const int* active, const CGState* st) {
+    extern __shared__ double smem_d[];
+    T* D = reinterpret_cast<T*>(smem_d);
+    T* u = D + kTri * kTri;
+    const int b = blockIdx.y;
+    if (skip_inst(active, st, b)) return;
+    const i32 s = list[blockIdx.x];
+    const i32 f = S.sn_first[s];
+    const int w = S.sn_first[s + 1] - f;
+    const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+    const i32* rows = S.sn_rows + S.sn_rowptr[s];
+    const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    T* x = X + (i64)b * S.n;
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) u[i] = i < w ? x[f + i] : x[rows[i]];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int nblk = (w + kTri - 1) / kTri;
+    for (int kbi = nblk - 1; kbi >= 0; kbi--) {
+        const int kb = kbi * kTri;
+        const int bw = min(kTri, w - kb);
+        for (int jj = wid; jj < bw; jj += nw) {
+            const int j = kb + jj;
+            T sum = T(0);
+            for (int i = kb + bw + lane; i < nr; i += kWave) sum += Lb[(i64)j * nr + i] * u[i];
+            sum = wave_sum(sum);
+            if (lane == 0) u[j] -= sum;
+        }
+        for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
+            const int jj = idx / bw, ii = idx - jj * bw;
+            D[jj * kTri + ii] = Lb[(i64)(kb + jj) * nr + kb + ii];
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            T val = lane < bw ? u[kb + lane] : T(0);
+            for (int k = bw - 1; k >= 0; k--) {
+                if (lane == k) val = val / D[k * kTri + k];
+                const T xk = __shfl(val, k, kWave);
+                if (lane < k) val -= D[lane * kTri + k] * xk;
+            }
+            if (lane < bw) u[kb + lane] = val;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < w; i += blockDim.x) x[f + i] = u[i];
+}
+
+// ---------------------------------------------------------------------------
+// SpMV with J^T (rows = permuted columns of J):
+//   out[b][i] = a[b][i] + scale * g_b * sum_k JT[b][k] * v[b][JT_col[k]]
+// with g_b = gamma[b] if use_gamma else 1; a may be null.
+// ---------------------------------------------------------------------------
+template <typename TO>
+__global__ void k_jt(SymView S, ValView V, const double* __restrict__ a, double scale, int use_gamma,
+                     const double* __restrict__ v, TO* __restrict__ out, const int* active, const CGState* st) {
+    const int b = blockIdx.y;
+    if (skip_inst(active, st, b)) return;
+    const double sc = scale * (use_gamma ? V.gamma[b] : 1.0);
+    const double* JT = V.JT + (i64)b * S.nnzJ;
+    const double* vb = v + (i64)b * S.m;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += (i64)gridDim.x * blockDim.x) {
+        double sum = 0.0;
+        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) sum += JT[k] * vb[S.JT_col[k]];
+        const double base = a ? a[(i64)b * S.n + i] : 0.0;
+        out[(i64)b * S.n + i] = (TO)(base + sc * sum);
+    }
+}
+
+// SpMV with J (permuted columns), FP64 accumulation of an FP32 or FP64 input.
+// mode 0 (Schur right-hand side): q = J u - sub; part1 = sum q^2.
+// mode 1 (CG): q = J u + d2 * p; part1 = sum p.q; part2 = sum p.p.
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __restrict__ u, const double* __restrict__ sub,
+                                              const double* __restrict__ p, const CGState* st, int mode,
+                                              double* __restrict__ q, double* __restrict__ part1,
+                                              double* __restrict__ part2, const int* active) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    if (skip_inst(active, mode == 1 ? st : nullptr, b)) return;
+    const double* J = V.J + (i64)b * S.nnzJ;
+    const TI* ub = u + (i64)b * S.n;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    double a1 = 0.0, a2 = 0.0;
+    if (i < S.m) {
+        double sum = 0.0;
+        for (i64 k = S.J_rowptr[i]; k < S.J_rowptr[i + 1]; k++) sum += J[k] * (double)ub[S.J_colp[k]];
+        if (mode == 0) {
+            sum -= sub[(i64)b * S.m + i];
+            a1 = sum * sum;
+        } else {
+            const double pi = p[(i64)b * S.m + i];
+            sum += st[b].d2 * pi;
+            a1 = pi * sum;
+            a2 = pi * pi;
+        }
+        q[(i64)b * S.m + i] = sum;
+    }
+    a1 = block_sum(a1, sh);
+    if (mode == 1) a2 = block_sum(a2, sh);
+    if (threadIdx.x == 0) {
+        part1[(i64)b * gridDim.x + blockIdx.x] = a1;
+        if (mode == 1) part2[(i64)b * gridDim.x + blockIdx.x] = a2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CG on S y = bvec (unpreconditioned, y0 = 0), Algorithm 1 / eq. Schur1.
+// ---------------------------------------------------------------------------
+__device__ double reduce_parts(const double* part, int nblk, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += part[i];
+    return block_sum(v, sh);
+}
+
+// one block per instance: rho = ||b||^2, reset the state
+__global__ void k_cg_init(CGState* st, const double* part, int nblk, const int* active, i64 m) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    const double r = reduce_parts(part + (i64)b * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        CGState c = {};
+        c.rho = r;
+        c.bnorm = sqrt(r);
+        c.curv0 = -1.0;
+        c.done = (active && !active[b]) || m == 0 || !(r > 0.0);
+        st[b] = c;
+    }
+}
+
+__global__ void k_cg_vecinit(const double* __restrict__ bvec, double* __restrict__ y, double* __restrict__ res,
+                             double* __restrict__ p, i64 m, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) {
+        const double v = bvec[(i64)b * m + i];
+        y[(i64)b * m + i] = 0.0;
+        res[(i64)b * m + i] = v;
+        p[(i64)b * m + i] = v;
+    }
+}
+
+// alpha = rho / p'q, with the small-quadratic-form test of Algorithm 1
+__global__ void k_cg_alpha(CGState* st, const double* part1, const double* part2, int nblk, double qf_eps,
+                           double delta2) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    if (st[b].done) return;
+    const double pq = reduce_parts(part1 + (i64)b * nblk, nblk, sh);
+    const double pp = reduce_parts(part2 + (i64)b * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        CGState c = st[b];
+        if (c.curv0 < 0.0) c.curv0 = pq / pp;
+        c.pq = pq;
+        c.pp = pp;
+        if (!(pq > qf_eps * pp * c.curv0)) {
+            c.breakdown = 1;
+            if (delta2 > 0.0 && c.d2 == 0.0) {
+                c.d2 = delta2;      // restart on S + delta2 I
+                c.alpha = 0.0;
+                c.pad = 1;          // restart pending
+            } else {
+                c.done = 1;
+            }
+        } else {
+            c.alpha = c.rho / pq;
+        }
+        st[b] = c;
+    }
+}
+
+// y += alpha p; res -= alpha q; partial res'res. A pending restart resets
+// y = 0, res = bvec.
+__global__ __launch_bounds__(kBlock) void k_cg_update(const double* __restrict__ p, const double* __restrict__ q,
+                                                      const double* __restrict__ bvec, double* __restrict__ y,
+                                                      double* __restrict__ res, const CGState* st, i64 m,
+                                                      double* __restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    if (st[b].done) return;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;
+    if (i < m) {
+        const i64 o = (i64)b * m + i;
+        double r;
+        if (st[b].pad) {
+            y[o] = 0.0;
+            r = bvec[o];
+        } else {
+            const double al = st[b].alpha;
+            y[o] += al * p[o];
+            r = res[o] - al * q[o];
+        }
+        res[o] = r;
+        a = r * r;
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
+}
+
+__global__ void k_cg_beta(CGState* st, const double* part, int nblk, double tol, int max_it) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    if (st[b].done) return;
+    const double r1 = reduce_parts(part + (i64)b * nblk, nblk, sh);
+    if (threadIdx.x == 0) {
+        CGState c = st[b];
+        if (c.pad) {
+            c.pad = 0;
+            c.rho = r1;
+            c.beta = 0.0;
+            c.curv0 = -1.0;
+        } else {
+            c.it++;
+            if (sqrt(r1) <= tol * c.bnorm || c.it >= max_it) c.done = 1;
+            c.beta = r1 / c.rho;
+            c.rho = r1;
+        }
+        st[b] = c;
+    }
+}
+
+__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ res, const CGState* st, i64 m) {
+    const int b = blockIdx.y;
+    if (st[b].done) return;
+    const double be = st[b].beta;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) {
+        const i64 o = (i64)b * m + i;
+        p[o] = res[o] + be * p[o];
+    }
+}
+
+__global__ void k_count_live(const CGState* st, int nb, int* out) {
+    __shared__ double sh[kBlock / kWave];
+    double c = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) c += st[b].done ? 0.0 : 1.0;
+    c = block_sum(c, sh);
+    if (threadIdx.x == 0) *out = (int)c;
+}
+
+// ---------------------------------------------------------------------------
+// refinement support (FP64)
+// ---------------------------------------------------------------------------
+// z += e on active instances
+__global__ void k_axpy2(double* __restrict__ xz, const double* __restrict__ ex, i64 n, double* __restrict__ yz,
+                        const double* __restrict__ ey, i64 m, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += (i64)gridDim.x * blockDim.x) {
+        if (i < n) xz[(i64)b * n + i] += ex[(i64)b * n + i];
+        else yz[(i64)b * m + (i - n)] += ey[(i64)b * m + (i - n)];
+    }
+}
+
+// g = r - K z over rows [0, n) (first block row) and [n, n+m) (J rows),
+// partial ||g||^2; optional partials of || |K||z| + |r| ||^2 (floor).
+__global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const double* __restrict__ r1,
+                                                     const double* __restrict__ r2, const double* __restrict__ xz,
+                                                     const double* __restrict__ yz, double* __restrict__ g1,
+                                                     double* __restrict__ g2, double* __restrict__ part,
+                                                     double* __restrict__ part_floor, const int* active) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const double* x = xz + (i64)b * S.n;
+    const double* y = yz + (i64)b * S.m;
+    double a = 0.0, fl = 0.0;
+    if (i < S.n) {
+        const double* HF = V.HF + (i64)b * S.nnzHF;
+        const double* JT = V.JT + (i64)b * S.nnzJ;
+        double acc = 0.0, aabs = 0.0;
+        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) {
+            const double t = HF[k] * x[S.HF_col[k]];
+            acc += t;
+            aabs += fabs(t);
+        }
+        const double dt = (V.Dxp[(i64)b * S.n + i] + V.delta[b]) * x[i];
+        acc += dt;
+        aabs += fabs(dt);
+        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) {
+            const double t = JT[k] * y[S.JT_col[k]];
+            acc += t;
+            aabs += fabs(t);
+        }
+        const double rv = r1[(i64)b * S.n + i];
+        const double g = rv - acc;
+        g1[(i64)b * S.n + i] = g;
+        a = g * g;
+        fl = aabs + fabs(rv);
+        fl = fl * fl;
+    } else if (i < S.n + S.m) {
+        const i64 r = i - S.n;
+        const double* J = V.J + (i64)b * S.nnzJ;
+        double acc = 0.0, aabs = 0.0;
+        for (i64 k = S.J_rowptr[r]; k < S.J_rowptr[r + 1]; k++) {
+            const double t = J[k] * x[S.J_colp[k]];
+            acc += t;
+            aabs += fabs(t);
+        }
+        const double rv = r2[(i64)b * S.m + r];
+        const double g = rv - acc;
+        g2[(i64)b * S.m + r] = g;
+        a = g * g;
+        fl = aabs + fabs(rv);
+        fl = fl * fl;
+    }
+    a = block_sum(a, sh);
+    if (part_floor) fl = block_sum(fl, sh);
+    if (threadIdx.x == 0) {
+        part[(i64)b * gridDim.x + blockIdx.x] = a;
+        if (part_floor) part_floor[(i64)b * gridDim.x + blockIdx.x] = fl;
+    }
+}
+
+// per-instance sum of squares of [v1 (len n1) ; v2 (len n2)] into partials
+__global__ __launch_bounds__(kBlock) void k_sumsq2(const double* __restrict__ v1, i64 n1, const double* __restrict__ v2,
+                                                   i64 n2, double* __restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;
+    if (i < n1) a = v1[(i64)b * n1 + i];
+    else if (i < n1 + n2) a = v2[(i64)b * n2 + (i - n1)];
+    a = block_sum(a * a, sh);
+    if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
+}
+
+// out[b] = sum of partials (one block per instance)
+__global__ void k_reduce_rows(const double* part, int nblk, double* out) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    const double r = reduce_parts(part + (i64)b * nblk, nblk, sh);
+    if (threadIdx.x == 0) out[b] = r;
+}
+
+// ||K||_inf per instance: max row sum of |K| (Sec. 5.1 estimate of ||K||_2)
+__global__ __launch_bounds__(kBlock) void k_knorm_rows(SymView S, ValView V, double* __restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;
+    if (i < S.n) {
+        const double* HF = V.HF + (i64)b * S.nnzHF;
+        const double* JT = V.JT + (i64)b * S.nnzJ;
+        double dsum = V.Dxp[(i64)b * S.n + i] + V.delta[b];
+        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) {
+            if (S.HF_col[k] == i) dsum += HF[k];
+            else a += fabs(HF[k]);
+        }
+        a += fabs(dsum);
+        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) a += fabs(JT[k]);
+    } else if (i < S.n + S.m) {
+        const i64 r = i - S.n;
+        const double* J = V.J + (i64)b * S.nnzJ;
+        for (i64 k = S.J_rowptr[r]; k < S.J_rowptr[r + 1]; k++) a += fabs(J[k]);
+    }
+    // block max
+    for (int o = kWave / 2; o > 0; o >>= 1) a = fmax(a, __shfl_down(a, o, kWave));
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int t = 0; t < (int)(blockDim.x / kWave); t++) r = fmax(r, sh[t]);
+        part[(i64)b * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+__global__ void k_reduce_max(const double* part, int nblk, double* out) {
+    const int b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int i = 0; i < nblk; i++) r = fmax(r, part[(i64)b * nblk + i]);
+        out[b] = r;
+    }
+}
+
+}  // namespace hkkt

@@ -1,0 +1,304 @@
+"""Thin ctypes binding of the C ABI in include/hkkt.h (argument marshalling
+only; every step of the solve runs in the HIP library).
+
+Host mode takes numpy arrays; device mode takes torch tensors on the GPU and
+binds the context to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhkkt.so")
+
+OK, NOT_SPD, CG_BREAKDOWN, NOT_CONVERGED = 0, 1, 2, 3
+ERR_ARG, ERR_PATTERN, ERR_STATE, ERR_DEVICE, ERR_OOM = -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+PTR_HOST, PTR_DEVICE = 0, 1
+
+EXPORTS = [
+    "hkkt_default_options", "hkkt_create", "hkkt_destroy", "hkkt_last_error", "hkkt_analyze",
+    "hkkt_factor_batch", "hkkt_factor", "hkkt_solve_batch", "hkkt_solve", "hkkt_inertia",
+    "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
+    "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
+]
+
+i64p = C.POINTER(C.c_int64)
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("pointer_mode", C.c_int), ("cg_tol", C.c_double),
+                ("cg_tol_mixed", C.c_double), ("kkt_tol", C.c_double), ("quad_form_eps", C.c_double),
+                ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
+                ("ordering", C.c_int), ("relax", C.c_int), ("reserved", C.c_int * 6)]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int), ("cg_iters", C.c_int), ("passes", C.c_int),
+                ("fp64_fallback", C.c_int), ("rr", C.c_double), ("be", C.c_double),
+                ("floor", C.c_double), ("fail_col", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class HKKTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hkkt error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library; fails loudly when it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run paper_2110_03636_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        V = C.c_void_p
+        L.hkkt_default_options.argtypes = [C.POINTER(Options)]
+        L.hkkt_create.argtypes = [C.POINTER(V), C.POINTER(Options), V]
+        L.hkkt_destroy.argtypes = [V]
+        L.hkkt_last_error.restype = C.c_char_p
+        L.hkkt_last_error.argtypes = [V]
+        L.hkkt_analyze.argtypes = [V, C.c_int64, C.c_int64, V, V, V, V, V]
+        L.hkkt_factor_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V]
+        L.hkkt_factor.argtypes = [V, V, V, V, C.c_double, C.c_double, V]
+        L.hkkt_solve_batch.argtypes = [V, C.c_int, V, V, V, V, V]
+        L.hkkt_solve.argtypes = [V, V, V, V, V, V]
+        L.hkkt_inertia.argtypes = [V, C.c_int, V]
+        L.hkkt_symbolic_create.argtypes = [C.POINTER(V), C.c_int64, C.c_int64, V, V, V, V, V, C.c_int,
+                                           C.c_int, C.c_char_p, C.c_int]
+        L.hkkt_symbolic_destroy.argtypes = [V]
+        L.hkkt_get_symbolic.restype = V
+        L.hkkt_get_symbolic.argtypes = [V]
+        L.hkkt_symbolic_stats.argtypes = [V, V]
+        L.hkkt_symbolic_perm.argtypes = [V, V]
+        L.hkkt_symbolic_supernodes.argtypes = [V, V, V, V, V, V, V]
+        L.hkkt_get_factor.argtypes = [V, C.c_int, V, V, V]
+        L.hkkt_hsolve.argtypes = [V, C.c_int, V, V]
+        L.hkkt_timings.argtypes = [V, V]
+        _lib = L
+    return _lib
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+STAT_NAMES = ["n_x", "m", "nnz_A", "nnz_L", "L_storage", "supernodes", "levels", "flops_proxy",
+              "max_width", "max_rows", "cb_entries", "etree_height", "uv_entries", "nnz_J",
+              "L_lower_entries", "sn_rows_total"]
+
+
+class _SymbolicView:
+    """Accessors shared by the host-only analysis and a context's analysis."""
+
+    def _h(self):
+        raise NotImplementedError
+
+    def stats(self):
+        st = np.zeros(16, np.int64)
+        _check(lib().hkkt_symbolic_stats(self._h(), st.ctypes.data), None)
+        return dict(zip(STAT_NAMES, (int(v) for v in st)))
+
+    def perm(self):
+        n = self.stats()["n_x"]
+        p = np.empty(n, np.int32)
+        lib().hkkt_symbolic_perm(self._h(), p.ctypes.data)
+        return p
+
+    def supernodes(self):
+        s = self.stats()
+        ns, nl = s["supernodes"], s["levels"]
+        first = np.empty(ns + 1, np.int32)
+        rowptr = np.empty(ns + 1, np.int64)
+        rows = np.empty(s["sn_rows_total"], np.int32)
+        parent = np.empty(ns, np.int32)
+        lptr = np.empty(nl + 1, np.int32)
+        lsn = np.empty(ns, np.int32)
+        lib().hkkt_symbolic_supernodes(self._h(), first.ctypes.data, rowptr.ctypes.data, rows.ctypes.data,
+                                       parent.ctypes.data, lptr.ctypes.data, lsn.ctypes.data)
+        return dict(first=first, rowptr=rowptr, rows=rows, parent=parent, level_ptr=lptr, level_sn=lsn)
+
+
+def _check(rc, ctx, what=""):
+    if rc < 0:
+        msg = lib().hkkt_last_error(ctx).decode() if ctx else what
+        raise HKKTError(rc, msg)
+    return rc
+
+
+class Symbolic(_SymbolicView):
+    """Host-only symbolic analysis (no GPU needed)."""
+
+    def __init__(self, n_x, m, H_rowptr, H_col, J_rowptr, J_col, perm=None, ordering=0, relax=1):
+        self._keep = [_np(H_rowptr, np.int64), _np(H_col, np.int32), _np(J_rowptr, np.int64),
+                      _np(J_col, np.int32)]
+        pp = None if perm is None else _np(perm, np.int32)
+        self._keep.append(pp)
+        h = C.c_void_p()
+        err = C.create_string_buffer(512)
+        rc = lib().hkkt_symbolic_create(C.byref(h), int(n_x), int(m), *[_ptr(a) for a in self._keep[:4]],
+                                        _ptr(pp), ordering, relax, err, 512)
+        if rc != 0:
+            raise HKKTError(rc, err.value.decode())
+        self._handle = h
+
+    @classmethod
+    def from_pattern(cls, p, **kw):
+        return cls(p.n_x, p.m, p.H_rowptr, p.H_col, p.J_rowptr, p.J_col, **kw)
+
+    def _h(self):
+        return self._handle
+
+    def __del__(self):
+        try:
+            if getattr(self, "_handle", None):
+                lib().hkkt_symbolic_destroy(self._handle)
+                self._handle = None
+        except Exception:
+            pass
+
+
+class Solver(_SymbolicView):
+    """One context: analyse a pattern, factor batches, solve.
+
+    device=True: value/vector arguments are torch CUDA tensors (float64,
+    contiguous, batch-major) and the context runs on torch's current stream.
+    device=False: numpy arrays (host pointers)."""
+
+    def __init__(self, precision="fp64", device=False, stream=None, **opts):
+        o = Options()
+        lib().hkkt_default_options(C.byref(o))
+        o.precision = MIXED if precision in ("mixed", MIXED) else FP64
+        o.pointer_mode = PTR_DEVICE if device else PTR_HOST
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.device = device
+        if device and stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(lib().hkkt_create(C.byref(h), C.byref(o), C.c_void_p(stream or 0)), None, "hkkt_create failed")
+        self._ctx = h
+        self.n = self.m = None
+        self.nb = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "_ctx", None):
+                lib().hkkt_destroy(self._ctx)
+                self._ctx = None
+        except Exception:
+            pass
+
+    def _h(self):
+        h = lib().hkkt_get_symbolic(self._ctx)
+        if not h:
+            raise HKKTError(ERR_STATE, "not analysed")
+        return h
+
+    def analyze(self, pattern, perm=None):
+        p = pattern
+        keep = [_np(p.H_rowptr, np.int64), _np(p.H_col, np.int32), _np(p.J_rowptr, np.int64),
+                _np(p.J_col, np.int32)]
+        pp = None if perm is None else _np(perm, np.int32)
+        _check(lib().hkkt_analyze(self._ctx, int(p.n_x), int(p.m), *[_ptr(a) for a in keep], _ptr(pp)),
+               self._ctx)
+        self.n, self.m = int(p.n_x), int(p.m)
+        return self
+
+    # -- values -------------------------------------------------------------
+    def _arr(self, a, nb, width):
+        if self.device:
+            import torch
+            t = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a))
+            t = t.to(device="cuda", dtype=torch.float64).reshape(nb, width).contiguous()
+            return t
+        return _np(np.asarray(a, dtype=np.float64).reshape(nb, width), np.float64)
+
+    def factor(self, H_val, D_x, J_val, delta, gamma):
+        """Batch-major values ([nb, nnz] / [nb, n_x]); delta, gamma: [nb].
+        Returns (rc, status[nb], fail_col[nb])."""
+        delta = np.atleast_1d(np.asarray(delta, np.float64))
+        gamma = np.atleast_1d(np.asarray(gamma, np.float64))
+        nb = int(delta.shape[0])
+        Hv = self._arr(H_val, nb, -1)
+        Dx = self._arr(D_x, nb, self.n)
+        Jv = self._arr(J_val, nb, -1) if self.m > 0 else None
+        if Jv is not None and Jv.shape[1] == 0:
+            Jv = None
+        self._keep_vals = (Hv, Dx, Jv)
+        st = np.zeros(nb, np.int32)
+        fc = np.zeros(nb, np.int64)
+        rc = _check(lib().hkkt_factor_batch(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv),
+                                            _np(delta, np.float64).ctypes.data, _np(gamma, np.float64).ctypes.data,
+                                            st.ctypes.data, fc.ctypes.data), self._ctx)
+        self.nb = nb
+        return rc, st, fc
+
+    def factor_batch(self, batch):
+        return self.factor(batch.H_val, batch.D_x, batch.J_val, batch.delta, batch.gamma)
+
+    def _out(self, nb, width):
+        if self.device:
+            import torch
+            return torch.empty((nb, width), dtype=torch.float64, device="cuda")
+        return np.empty((nb, width), np.float64)
+
+    def solve(self, r1, r2):
+        """Returns (rc, x [nb, n_x], y [nb, m], infos list of dicts)."""
+        nb = self.nb
+        R1 = self._arr(r1, nb, self.n)
+        R2 = self._arr(r2, nb, self.m) if self.m > 0 else None
+        x = self._out(nb, self.n)
+        y = self._out(nb, max(self.m, 0))
+        info = (Info * nb)()
+        rc = _check(lib().hkkt_solve_batch(self._ctx, nb, _ptr(R1), _ptr(R2), _ptr(x),
+                                           _ptr(y) if self.m > 0 else None, info), self._ctx)
+        return rc, x, y, [info[i].as_dict() for i in range(nb)]
+
+    def inertia(self, b=0):
+        out = np.zeros(3, np.int64)
+        _check(lib().hkkt_inertia(self._ctx, b, out.ctypes.data), self._ctx)
+        return tuple(int(v) for v in out)
+
+    def factor_csc(self, b=0):
+        """L of instance b in the context's final order as (colptr, rowind, val)."""
+        s = self.stats()
+        nz = s["L_lower_entries"]
+        cp = np.empty(self.n + 1, np.int64)
+        ri = np.empty(nz, np.int32)
+        v = np.empty(nz, np.float64)
+        _check(lib().hkkt_get_factor(self._ctx, b, cp.ctypes.data, ri.ctypes.data, v.ctypes.data), self._ctx)
+        return cp, ri, v
+
+    def hsolve(self, bvec):
+        """x = H_gamma^{-1} b for every instance ([nb, n_x], original order)."""
+        B = self._arr(bvec, self.nb, self.n)
+        x = self._out(self.nb, self.n)
+        _check(lib().hkkt_hsolve(self._ctx, self.nb, _ptr(B), _ptr(x)), self._ctx)
+        return x
+
+    def timings(self):
+        ms = np.zeros(8)
+        lib().hkkt_timings(self._ctx, ms.ctypes.data)
+        return dict(analyze=ms[0], factor=ms[1], solve=ms[2], fallback=ms[3])

@@ -1,0 +1,191 @@
+"""Host symbolic analysis (no GPU): ordering, fill, supernodes, schedules,
+pattern validation, and the exported C ABI."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_03636_amd import hkkt, synth
+from tests import helpers as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    if not os.path.exists(hkkt.LIB_PATH):
+        from paper_2110_03636_amd import build
+        build.build()
+
+
+def _boolean_fill(S):
+    n = S.shape[0]
+    S = S.copy()
+    for k in range(n):
+        rows = np.nonzero(S[k + 1:, k])[0] + k + 1
+        if rows.size:
+            S[np.ix_(rows, rows)] = True
+    return np.tril(S)
+
+
+def _struct(b):
+    n = b.pattern.n_x
+    Hd = H.dense_H(b)
+    J = H.dense_J(b)
+    return (np.abs(Hd) + np.eye(n) + np.abs(J).T @ np.abs(J)) != 0
+
+
+def _cases():
+    return [H.tiny_grid_like(120, 1), H.tiny_dense_like(80, 2), H.tiny_grid_like(200, 3),
+            H.tiny_dense_like(150, 4)]
+
+
+def test_exports_match_header():
+    hdr = open(os.path.join(ROOT, "include", "hkkt.h")).read()
+    declared = set(re.findall(r"\b(hkkt_[a-z_]+)\s*\(", hdr))
+    declared = {d for d in declared if not d.endswith("_t")}
+    assert declared == set(hkkt.EXPORTS), declared ^ set(hkkt.EXPORTS)
+    L = ctypes.CDLL(hkkt.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("k", range(4))
+@pytest.mark.parametrize("relax", [0, 1])
+def test_supernodal_structure_equals_fill(k, relax):
+    b = _cases()[k]
+    n = b.pattern.n_x
+    sym = hkkt.Symbolic.from_pattern(b.pattern, relax=relax)
+    perm = sym.perm()
+    assert sorted(perm.tolist()) == list(range(n))
+    fill = _boolean_fill(_struct(b)[np.ix_(perm, perm)])
+    sn = sym.supernodes()
+    st = sym.stats()
+    assert st["nnz_L"] == int(fill.sum())
+    first, rowptr, rows, parent = sn["first"], sn["rowptr"], sn["rows"], sn["parent"]
+    ns = first.size - 1
+    col2sn = np.repeat(np.arange(ns), np.diff(first))
+    for s in range(ns):
+        f, l = first[s], first[s + 1]
+        r = rows[rowptr[s]:rowptr[s + 1]]
+        assert np.array_equal(r[:l - f], np.arange(f, l))          # own columns first
+        assert np.all(np.diff(r) > 0)                                # sorted
+        for j in range(f, l):
+            true_rows = np.nonzero(fill[:, j])[0]
+            panel_rows = r[r >= j]
+            assert set(true_rows) <= set(panel_rows)
+            if relax == 0:
+                assert np.array_equal(true_rows, panel_rows)
+        # supernodal etree: parent owns the first row below the block
+        if r.size > l - f:
+            assert parent[s] == col2sn[r[l - f]]
+            pr = set(rows[rowptr[parent[s]]:rowptr[parent[s] + 1]])
+            assert set(r[l - f:]) <= pr                              # extend-add target exists
+        else:
+            assert parent[s] == -1
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_level_schedule_is_topological(k):
+    b = _cases()[k]
+    sym = hkkt.Symbolic.from_pattern(b.pattern)
+    sn = sym.supernodes()
+    ns = sn["first"].size - 1
+    lev = np.empty(ns, np.int64)
+    lp, ls = sn["level_ptr"], sn["level_sn"]
+    for l in range(lp.size - 1):
+        lev[ls[lp[l]:lp[l + 1]]] = l
+    assert sorted(ls.tolist()) == list(range(ns))
+    for s in range(ns):
+        p = sn["parent"][s]
+        if p >= 0:
+            assert lev[s] < lev[p]
+            assert s < p                                             # postorder numbering
+
+
+@pytest.mark.parametrize("seed", [5, 6, 7])
+def test_amd_fill_close_to_exact_min_degree(seed):
+    for b in (H.tiny_grid_like(3000, seed, dx_exp=6.0), H.tiny_dense_like(600, seed)):
+        sym = hkkt.Symbolic.from_pattern(b.pattern)
+        o = oracle.System.from_batch(b)
+        o.factor(o.order_mindeg())
+        nnz_md = o.L()[0][-1]
+        assert sym.stats()["nnz_L"] <= 1.25 * nnz_md, (sym.stats()["nnz_L"], nnz_md)
+
+
+def test_given_permutation_is_postordered_equivalent():
+    b = H.tiny_grid_like(300, 9)
+    o = oracle.System.from_batch(b)
+    pmd = o.order_mindeg()
+    sym = hkkt.Symbolic.from_pattern(b.pattern, perm=pmd)
+    o.factor(pmd)
+    # a postorder of the same elimination tree has the same fill
+    assert sym.stats()["nnz_L"] == o.L()[0][-1]
+
+
+def test_natural_ordering_option():
+    b = H.tiny_dense_like(50, 10)
+    sym = hkkt.Symbolic.from_pattern(b.pattern, ordering=1, relax=0)
+    o = oracle.System.from_batch(b)
+    o.factor(None)
+    assert sym.stats()["nnz_L"] == o.L()[0][-1]
+
+
+def test_workload_sizes():
+    b = synth.workload(1)
+    s = hkkt.Symbolic.from_pattern(b.pattern).stats()
+    assert s["n_x"] == 1200 and s["m"] == 600 and s["nnz_J"] == 2400
+    assert 150_000 < s["nnz_L"] < 240_000
+
+
+def _pat(b):
+    p = b.pattern
+    return [p.n_x, p.m, p.H_rowptr.copy(), p.H_col.copy(), p.J_rowptr.copy(), p.J_col.copy()]
+
+
+def test_pattern_validation_errors():
+    b = H.tiny_grid_like(40, 11)
+    base = _pat(b)
+    bad = []
+    a = [x.copy() if isinstance(x, np.ndarray) else x for x in base]
+    a[3][1], a[3][2] = a[3][2], a[3][1]                # unsorted H columns somewhere
+    bad.append(a)
+    a = [x.copy() if isinstance(x, np.ndarray) else x for x in base]
+    a[5][0] = 40                                        # J column out of range
+    bad.append(a)
+    a = [x.copy() if isinstance(x, np.ndarray) else x for x in base]
+    a[5][1] = a[5][0]                                   # duplicate J column
+    bad.append(a)
+    a = [x.copy() if isinstance(x, np.ndarray) else x for x in base]
+    a[2][5] = a[2][4] - 1                               # non-monotone row pointers
+    bad.append(a)
+    a = [x.copy() if isinstance(x, np.ndarray) else x for x in base]
+    i = int(np.nonzero(np.diff(a[2]) > 1)[0][0])
+    a[3][a[2][i]] = i + 1                               # upper-triangle entry in tril(H)
+    bad.append(a)
+    for args in bad:
+        with pytest.raises(hkkt.HKKTError) as e:
+            hkkt.Symbolic(*args)
+        assert e.value.code == hkkt.ERR_PATTERN
+    with pytest.raises(hkkt.HKKTError) as e:
+        hkkt.Symbolic(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(1, np.int64),
+                      np.zeros(0, np.int32))
+    assert e.value.code == hkkt.ERR_ARG
+    with pytest.raises(hkkt.HKKTError) as e:
+        hkkt.Symbolic(*base, perm=np.zeros(40, np.int32))
+    assert e.value.code == hkkt.ERR_PATTERN
+
+
+def test_edge_shapes_analyse():
+    # m = 0, a diagonal-only H, a single variable
+    for n, m in ((1, 0), (5, 0), (6, 3)):
+        Hd = np.eye(n)
+        J = np.zeros((m, n))
+        for i in range(m):
+            J[i, 2 * i] = 1.0
+        b = H.batch_from_dense(Hd, np.ones(n), J, 0.0, 1.0, np.ones(n), np.ones(m))
+        s = hkkt.Symbolic.from_pattern(b.pattern).stats()
+        assert s["n_x"] == n and s["nnz_L"] >= n

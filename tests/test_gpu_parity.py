@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs. Tolerances:
+  - L (FP64): max per-column |L_gpu - L_oracle| / ||L_oracle(:,j)|| <= 1e-9
+    (both are backward-stable Cholesky factors of the same permuted matrix,
+    summed in different orders);
+  - H_gamma^{-1} b: normwise backward error <= 1e-14 (FP64);
+  - end to end: relative KKT residual RR <= kkt_tol (1e-10), evaluated by the
+    oracle's own FP64 residual on the CPU; CG iteration count within +-2 of
+    the oracle's on the first pass; inertia equal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_03636_amd import hkkt, synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _lower_in_original(cp, ri, v, perm, n):
+    """Dense L mapped to original variable labels: M[perm[i], perm[j]] = L[i, j]."""
+    M = np.zeros((n, n))
+    cols = np.repeat(np.arange(n), np.diff(cp))
+    M[perm[ri], perm[cols]] = v
+    return M
+
+
+def _oracle_L(b, perm):
+    o = oracle.System.from_batch(b)
+    st, fc = o.factor(perm)
+    assert st == 0
+    cp, ri, v = o.L()
+    return _lower_in_original(cp, ri, v, np.asarray(perm), b.pattern.n_x)
+
+
+def _solver(b, precision="fp64", perm=None, **kw):
+    s = hkkt.Solver(precision=precision, **kw)
+    s.analyze(b.pattern, perm=perm)
+    return s
+
+
+def _col_err(A, B):
+    nrm = np.linalg.norm(B, axis=0)
+    nrm[nrm == 0] = 1.0
+    return (np.abs(A - B).max(axis=0) / nrm).max()
+
+
+@pytest.mark.parametrize("case", ["workload1", "grid"])
+def test_factor_fp64_equals_oracle(case):
+    b = synth.workload(1) if case == "workload1" else H.tiny_grid_like(3000, 21, dx_exp=8.0)
+    n = b.pattern.n_x
+    o = oracle.System.from_batch(b)
+    pmd = o.order_mindeg()
+    s = _solver(b, perm=pmd)
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0 and st[0] == 0 and fc[0] == -1
+    cp, ri, v = s.factor_csc(0)
+    got = _lower_in_original(cp, ri, v, s.perm(), n)
+    want = _oracle_L(b, pmd)
+    assert _col_err(got, want) < 1e-9
+
+
+def test_factor_fp32_close_to_oracle():
+    b = H.tiny_grid_like(2000, 22, dx_exp=1.0, gamma=10.0)
+    o = oracle.System.from_batch(b)
+    pmd = o.order_mindeg()
+    s = _solver(b, precision="mixed", perm=pmd)
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0
+    cp, ri, v = s.factor_csc(0)
+    got = _lower_in_original(cp, ri, v, s.perm(), b.pattern.n_x)
+    assert _col_err(got, _oracle_L(b, pmd)) < 2e-4
+
+
+@pytest.mark.parametrize("case", ["workload1", "grid", "dense_small"])
+def test_hsolve_backward_error(case):
+    b = {"workload1": lambda: synth.workload(1),
+         "grid": lambda: H.tiny_grid_like(5000, 23, dx_exp=8.0),
+         "dense_small": lambda: H.tiny_dense_like(97, 24)}[case]()
+    s = _solver(b)
+    assert s.factor_batch(b)[0] == 0
+    rhs = np.random.default_rng(0).standard_normal((1, b.pattern.n_x))
+    x = s.hsolve(rhs)[0]
+    o = oracle.System.from_batch(b)
+    o.factor(o.order_mindeg())
+    xo = o.hsolve(rhs[0])
+    if b.pattern.n_x <= 3000:
+        A = H.dense_Hgamma(b)
+        be = np.linalg.norm(A @ x - rhs[0]) / (np.linalg.norm(A, np.inf) * np.linalg.norm(x) + np.linalg.norm(rhs))
+        assert be < 1e-14
+    # same solution as the oracle's up to the conditioning of H_gamma
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
+
+
+def _check_solution(b, x, y, infos, kkt_tol=1e-10, ref_iters=None):
+    for i in range(b.nb):
+        o = oracle.System.from_batch(b, i)
+        rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
+        assert rr <= max(kkt_tol, 20 * fl), (i, rr, fl)
+        assert infos[i]["status"] == 0, infos[i]
+        assert abs(infos[i]["rr"] - rr) <= 1e-3 * rr + 1e-15
+
+
+@pytest.mark.parametrize("kkt_tol", [1e-8, 1e-10])
+def test_solve_workload1_equals_oracle(kkt_tol):
+    b = synth.workload(1)
+    s = _solver(b, kkt_tol=kkt_tol)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    assert rc == 0
+    _check_solution(b, x, y, infos, kkt_tol)
+    o = oracle.System.from_batch(b)
+    o.factor(o.order_mindeg())
+    xo, yo, io = o.solve(b.r1[0], b.r2[0], kkt_tol=kkt_tol)
+    z = np.concatenate([x[0], y[0]])
+    zo = np.concatenate([xo, yo])
+    # forward error is bounded by cond(K)*RR only; report-level check
+    assert np.linalg.norm(z - zo) / np.linalg.norm(zo) < 1e-4
+    assert abs(infos[0]["cg_iters"] - sum(io["cg_iters"])) <= 2 * io["passes"] + 2
+    assert s.inertia(0) == io["inertia"] == (1200, 600, 0)
+
+
+def test_solve_batch_grid_fp64():
+    b = synth.grid_like(3000, nb=5, seed=31, gammas=(1e4, 1e6), dx_exp=8.0)
+    s = _solver(b)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
+    for i in range(b.nb):
+        o = oracle.System.from_batch(b, i)
+        o.factor(o.order_mindeg())
+        xo, yo, io = o.solve(b.r1[i], b.r2[i])
+        assert io["status"] == 0
+        assert abs(infos[i]["cg_iters"] - sum(io["cg_iters"])) <= 2 * io["passes"] + 2
+
+
+def test_solve_batch_mixed_reaches_target():
+    b = synth.grid_like(3000, nb=6, seed=32, gammas=(1e4, 1e6), dx_exp=8.0)
+    s = _solver(b, precision="mixed")
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
+
+
+def test_device_pointers_match_host():
+    torch = pytest.importorskip("torch")
+    b = synth.grid_like(2500, nb=3, seed=33, gammas=(1e4,), dx_exp=6.0)
+    sh = _solver(b)
+    sh.factor_batch(b)
+    _, xh, yh, _ = sh.solve(b.r1, b.r2)
+    sd = hkkt.Solver(precision="fp64", device=True)
+    sd.analyze(b.pattern)
+    t = lambda a: torch.as_tensor(a, device="cuda")
+    rc, st, fc = sd.factor(t(b.H_val), t(b.D_x), t(b.J_val), b.delta, b.gamma)
+    assert rc == 0
+    rc, xd, yd, infos = sd.solve(t(b.r1), t(b.r2))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(xd.cpu().numpy(), xh)
+    np.testing.assert_array_equal(yd.cpu().numpy(), yh)
+
+
+def test_gamma_invariance_gpu():
+    base = H.tiny_dense_like(300, 34, dx_exp=2.0)
+    zs = []
+    for g in (1.0, 1e2, 1e4, 1e6):
+        b = H.with_gamma(base, g)
+        s = _solver(b)
+        s.factor_batch(b)
+        rc, x, y, infos = s.solve(b.r1, b.r2)
+        assert rc == 0
+        zs.append(np.concatenate([x[0], y[0]]))
+    for z in zs[1:]:
+        assert np.linalg.norm(z - zs[0]) / np.linalg.norm(zs[0]) < 1e-7
+
+
+def test_not_spd_reports_oracle_column():
+    b = synth.grid_like(800, nb=3, seed=35, gammas=(1.0,), dx_exp=1.0)
+    p = b.pattern
+    victim = 123
+    diag_pos = [k for k in range(p.H_rowptr[victim], p.H_rowptr[victim + 1]) if p.H_col[k] == victim][0]
+    b.H_val[1, diag_pos] -= 1e4
+    s = _solver(b)
+    rc, st, fc = s.factor_batch(b)
+    assert rc == hkkt.NOT_SPD
+    assert list(st) == [0, hkkt.NOT_SPD, 0]
+    o = oracle.System.from_batch(b, 1)
+    ost, ofc = o.factor(s.perm())
+    assert ost == 1 and fc[1] == ofc and fc[0] == -1
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    assert infos[1]["status"] == hkkt.NOT_SPD and infos[0]["status"] == 0 and infos[2]["status"] == 0
+    with pytest.raises(hkkt.HKKTError):
+        s.inertia(1)
+
+
+def test_breakdown_on_duplicate_row():
+    rng = np.random.default_rng(36)
+    n, m = 40, 12
+    Bm = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.15)
+    Hd = Bm.T @ Bm
+    J = rng.standard_normal((m, n)) * (rng.random((m, n)) < 0.3)
+    J[:, :m] += np.eye(m)
+    J[5] = J[2]
+    b = H.batch_from_dense(Hd, 10 ** rng.uniform(-1, 1, n), J, 0.0, 1e2, rng.standard_normal(n),
+                           rng.standard_normal(m))
+    s = _solver(b)
+    s.factor_batch(b)
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    assert infos[0]["status"] == hkkt.CG_BREAKDOWN
+    assert s.inertia(0) == (n, m - 1, 1)
+
+
+@pytest.mark.parametrize("n,m", [(1, 0), (7, 0), (2, 1), (65, 32), (130, 1)])
+def test_edge_shapes(n, m):
+    rng = np.random.default_rng(n * 100 + m)
+    Bm = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.3)
+    Hd = Bm.T @ Bm + np.eye(n)
+    J = rng.standard_normal((m, n)) * (rng.random((m, n)) < 0.3)
+    for i in range(m):
+        J[i, (2 * i) % n] = 1.0
+    b = H.batch_from_dense(Hd, np.ones(n), J, 1e-8, 1e2, rng.standard_normal(n), rng.standard_normal(m))
+    s = _solver(b)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    z = np.concatenate([x[0], y[0]])
+    zn = np.linalg.solve(H.dense_K(b), np.concatenate([b.r1[0], b.r2[0]]))
+    assert np.linalg.norm(z - zn) <= 1e-8 * np.linalg.norm(zn)
+    assert s.inertia(0) == (n, m, 0)
+
+
+def test_state_errors():
+    b = H.tiny_grid_like(100, 37)
+    s = hkkt.Solver()
+    with pytest.raises(hkkt.HKKTError) as e:
+        s.factor_batch(b)
+    assert e.value.code == hkkt.ERR_STATE
+    s.analyze(b.pattern)
+    with pytest.raises(hkkt.HKKTError) as e:
+        s.nb = 1
+        s.solve(b.r1, b.r2)
+    assert e.value.code == hkkt.ERR_STATE
+
+
+def test_full_size_batch_sampled():
+    """256 instances of the 20k/10k grid-like workload in one batch, mixed
+    precision, as the benchmark runs it: sampled instances checked by the
+    oracle's CPU residual."""
+    b = synth.workload(4)
+    s = _solver(b, precision="mixed")
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    for i in (0, 1, 77, 128, 255):
+        o = oracle.System.from_batch(b, i)
+        rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
+        assert rr <= max(1e-10, 20 * fl), (i, rr, fl, infos[i])
+        assert infos[i]["status"] == 0
