@@ -198,6 +198,18 @@ int hkkt_hsolve(hkkt_ctx *ctx, int nb, const double *b, double *x);
  * [2] solve, [3] fp64 fallback. */
 int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
 
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * each launch, between hkkt_profile_begin and hkkt_profile_end. The end call
+ * synchronises the stream and returns, per kernel class, the summed
+ * launch durations ms[k] (milliseconds) and launch counts launches[k]
+ * (arrays of HKKT_NPROF; either may be NULL). Classes: 0 assembly,
+ * 1 LDS fronts, 2 global fronts, 3 forward solve, 4 backward solve,
+ * 5 J^T SpMV, 6 J SpMV, 7 CG vector updates, 8 CG scalars, 9 KKT residual,
+ * 10 other. */
+#define HKKT_NPROF 12
+int hkkt_profile_begin(hkkt_ctx *ctx);
+int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

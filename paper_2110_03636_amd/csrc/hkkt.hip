@@ -50,6 +50,57 @@ static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+
+// ---------------------------------------------------------------------------
+// optional per-kernel timing with HIP events on the context's stream
+// ---------------------------------------------------------------------------
+constexpr int kNProf = 12;
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> recs;
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    ~Prof() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+struct ProfScope {
+    Prof& p;
+    hipStream_t st;
+    int kind;
+    size_t i0 = 0;
+    ProfScope(Prof& p_, hipStream_t s, int k) : p(p_), st(s), kind(k) {
+        if (p.on) {
+            i0 = p.used;
+            HIPCHK(hipEventRecord(p.next(), st));
+        }
+    }
+    ~ProfScope() {
+        if (p.on && p.used == i0 + 1) {
+            try {
+                (void)hipEventRecord(p.next(), st);
+                p.recs.push_back({kind, i0});
+            } catch (...) {
+            }
+        }
+    }
+};
+
+#define LAUNCH(kind, ...)                                   \
+    do {                                                    \
+        ::hkkt::ProfScope ps_(c->prof, c->stream, kind);    \
+        hipLaunchKernelGGL(__VA_ARGS__);                    \
+        KCHK();                                             \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // device memory owned by the library
 // ---------------------------------------------------------------------------
@@ -238,6 +289,7 @@ struct hkkt_ctx {
     std::vector<int> solved;      // per instance: last solve status (for inertia), -100 none
     std::vector<int> breakdown;
     double ms[8] = {0};
+    hkkt::Prof prof;
 };
 
 namespace hkkt {
@@ -253,26 +305,21 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     const int nb = B.nb;
     T* L = B.L.as<T>();
     T* CB = B.CB.as<T>();
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
-    KCHK();
-    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb, INT_MAX);
-    KCHK();
-    hipLaunchKernelGGL(k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.vals(), L, active);
-    KCHK();
+    LAUNCH(10, k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
+    LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb, INT_MAX);
+    LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.vals(), L, active);
     for (i32 l = 0; l < S.nlevels; l++) {
         const int ns_small = D.small_ptr[l + 1] - D.small_ptr[l];
         if (ns_small > 0) {
             const int nr = D.small_maxnr[l];
             const size_t lds = (size_t)nr * nr * sizeof(T);
-            hipLaunchKernelGGL(k_front_lds<T>, dim3(ns_small, nb), dim3(kBlock), lds, st, D.v,
+            LAUNCH(1, k_front_lds<T>, dim3(ns_small, nb), dim3(kBlock), lds, st, D.v,
                                D.lev_small.as<i32>() + D.small_ptr[l], L, CB, B.fail.as<int>(), active);
-            KCHK();
         }
         const int ns_big = D.big_ptr[l + 1] - D.big_ptr[l];
         if (ns_big > 0) {
-            hipLaunchKernelGGL(k_front_global<T>, dim3(ns_big, nb), dim3(kBlock), 0, st, D.v,
+            LAUNCH(2, k_front_global<T>, dim3(ns_big, nb), dim3(kBlock), 0, st, D.v,
                                D.lev_big.as<i32>() + D.big_ptr[l], L, CB, B.fail.as<int>(), active);
-            KCHK();
         }
     }
 }
@@ -291,16 +338,14 @@ static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* active, const CGSt
         const int cnt = D.all_ptr[l + 1] - D.all_ptr[l];
         const size_t lds = (size_t)(kTri * kTri + D.all_maxnr[l]) * sizeof(T);
         if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
-        hipLaunchKernelGGL(k_fwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
+        LAUNCH(3, k_fwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
                            UV, active, st_);
-        KCHK();
     }
     for (i32 l = S.nlevels - 1; l >= 0; l--) {
         const int cnt = D.all_ptr[l + 1] - D.all_ptr[l];
         const size_t lds = (size_t)(kTri * kTri + D.all_maxnr[l]) * sizeof(T);
-        hipLaunchKernelGGL(k_bwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
+        LAUNCH(4, k_bwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
                            active, st_);
-        KCHK();
     }
 }
 
@@ -368,10 +413,9 @@ static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx
     }
     HIPCHK(hipMemcpyAsync(B.delta.p, hd.data(), nb * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(B.gamma.p, hg.data(), nb * 8, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gather_vals, dim3(grid1(std::max<i64>({S.n, S.nnzJ, (i64)S.HF_col.size()}), 1024), nb),
+    LAUNCH(10, k_gather_vals, dim3(grid1(std::max<i64>({S.n, S.nnzJ, (i64)S.HF_col.size()}), 1024), nb),
                        dim3(kBlock), 0, st, c->dev.v, B.H.as<double>(), B.J.as<double>(), B.Dx.as<double>(),
                        B.JT.as<double>(), B.HF.as<double>(), B.Dxp.as<double>());
-    KCHK();
     HIPCHK(hipStreamSynchronize(st));   // host staging vectors go out of scope
 }
 
@@ -403,49 +447,37 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int max_cg, double cg_tol, std::v
     const unsigned gn = grid1(S.n, 4096), gm = grid1(S.m);
     T* X = B.X.as<T>();
     // rhat = g1 + gamma J^T g2
-    hipLaunchKernelGGL(k_jt<double>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
+    LAUNCH(5, k_jt<double>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
                        B.g2.as<double>(), B.rhat.as<double>(), act, (const CGState*)nullptr);
-    KCHK();
-    hipLaunchKernelGGL((k_cast<double, T>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(), X, (i64)S.n, act,
+    LAUNCH(10, (k_cast<double, T>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(), X, (i64)S.n, act,
                        (const CGState*)nullptr);
-    KCHK();
     launch_trisolve<T>(c, B, act, nullptr);
     // bvec = J w - g2
     const unsigned gmb = (unsigned)std::max<i64>(1, (S.m + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
+    LAUNCH(6, k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
                        (const double*)nullptr, (const CGState*)nullptr, 0, B.bvec.as<double>(), B.part1.as<double>(),
                        (double*)nullptr, act);
-    KCHK();
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, act, (i64)S.m);
-    KCHK();
-    hipLaunchKernelGGL(k_cg_vecinit, dim3(gm, nb), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
+    LAUNCH(8, k_cg_init, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, act, (i64)S.m);
+    LAUNCH(7, k_cg_vecinit, dim3(gm, nb), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
                        B.res.as<double>(), B.p.as<double>(), (i64)S.m, act);
-    KCHK();
     int check_every = 4;
     for (int it = 0; it < max_cg && S.m > 0; it++) {
-        hipLaunchKernelGGL(k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, (const double*)nullptr, 1.0, 0,
+        LAUNCH(5, k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, (const double*)nullptr, 1.0, 0,
                            B.p.as<double>(), X, act, (const CGState*)cst);
-        KCHK();
         launch_trisolve<T>(c, B, act, cst);
-        hipLaunchKernelGGL(k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
+        LAUNCH(6, k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
                            B.p.as<double>(), (const CGState*)cst, 1, B.q.as<double>(), B.part1.as<double>(),
                            B.part2.as<double>(), act);
-        KCHK();
-        hipLaunchKernelGGL(k_cg_alpha, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), B.part2.as<double>(),
+        LAUNCH(8, k_cg_alpha, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), B.part2.as<double>(),
                            (int)gmb, c->opt.quad_form_eps, c->opt.delta2);
-        KCHK();
-        hipLaunchKernelGGL(k_cg_update, dim3(gmb, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.q.as<double>(),
+        LAUNCH(7, k_cg_update, dim3(gmb, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.q.as<double>(),
                            B.bvec.as<double>(), B.y.as<double>(), B.res.as<double>(), (const CGState*)cst, (i64)S.m,
                            B.part1.as<double>());
-        KCHK();
-        hipLaunchKernelGGL(k_cg_beta, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, cg_tol, max_cg);
-        KCHK();
-        hipLaunchKernelGGL(k_cg_p, dim3(gm, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.res.as<double>(),
+        LAUNCH(8, k_cg_beta, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, cg_tol, max_cg);
+        LAUNCH(7, k_cg_p, dim3(gm, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.res.as<double>(),
                            (const CGState*)cst, (i64)S.m);
-        KCHK();
         if ((it + 1) % check_every == 0) {
-            hipLaunchKernelGGL(k_count_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, nb, B.live.as<int>());
-            KCHK();
+            LAUNCH(8, k_count_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, nb, B.live.as<int>());
             int live = 0;
             HIPCHK(hipMemcpyAsync(&live, B.live.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -453,13 +485,11 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int max_cg, double cg_tol, std::v
         }
     }
     // x = H_gamma^{-1} (rhat - J^T y)
-    hipLaunchKernelGGL(k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.rhat.as<double>(), -1.0, 0,
+    LAUNCH(5, k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.rhat.as<double>(), -1.0, 0,
                        B.y.as<double>(), X, act, (const CGState*)nullptr);
-    KCHK();
     launch_trisolve<T>(c, B, act, nullptr);
-    hipLaunchKernelGGL((k_cast<T, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
+    LAUNCH(10, (k_cast<T, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
                        act, (const CGState*)nullptr);
-    KCHK();
     hst.resize(nb);
     HIPCHK(hipMemcpyAsync(hst.data(), cst, nb * sizeof(CGState), hipMemcpyDeviceToHost, st));
 }
@@ -471,23 +501,19 @@ static void update_residual(hkkt_ctx* c, Batch& B, std::vector<double>& rsq, boo
     const int nb = B.nb;
     const int* act = B.active.as<int>();
     if (add) {
-        hipLaunchKernelGGL(k_axpy2, dim3(grid1(S.n + S.m, 4096), nb), dim3(kBlock), 0, st, B.xz.as<double>(),
+        LAUNCH(10, k_axpy2, dim3(grid1(S.n + S.m, 4096), nb), dim3(kBlock), 0, st, B.xz.as<double>(),
                            B.ex.as<double>(), (i64)S.n, B.yz.as<double>(), B.y.as<double>(), (i64)S.m, act);
-        KCHK();
     }
     const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_residual, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.r1p.as<double>(),
+    LAUNCH(9, k_residual, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.r1p.as<double>(),
                        B.r2.as<double>(), B.xz.as<double>(), B.yz.as<double>(), B.g1.as<double>(), B.g2.as<double>(),
                        B.part1.as<double>(), floor_out ? B.pfloor.as<double>() : (double*)nullptr, act);
-    KCHK();
-    hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g, B.rsq.as<double>());
-    KCHK();
+    LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g, B.rsq.as<double>());
     rsq.resize(nb);
     HIPCHK(hipMemcpyAsync(rsq.data(), B.rsq.p, nb * 8, hipMemcpyDeviceToHost, st));
     if (floor_out) {
-        hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.pfloor.as<double>(), (int)g,
+        LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.pfloor.as<double>(), (int)g,
                            B.rowred.as<double>());
-        KCHK();
         HIPCHK(hipMemcpyAsync(floor_out, B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
@@ -514,13 +540,11 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
     std::vector<double> rsq;
     HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
     if (!warm) {
-        hipLaunchKernelGGL(k_fill<double>, dim3(grid1((i64)nb * S.n)), dim3(kBlock), 0, st, B.xz.as<double>(),
+        LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.n)), dim3(kBlock), 0, st, B.xz.as<double>(),
                            (i64)nb * S.n, 0.0);
-        KCHK();
         if (S.m > 0) {
-            hipLaunchKernelGGL(k_fill<double>, dim3(grid1((i64)nb * S.m)), dim3(kBlock), 0, st, B.yz.as<double>(),
+            LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.m)), dim3(kBlock), 0, st, B.yz.as<double>(),
                                (i64)nb * S.m, 0.0);
-            KCHK();
         }
     }
     update_residual(c, B, rsq, false, nullptr);
@@ -797,18 +821,15 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         alloc_solve(c, B);
         // right-hand side into the permuted order (staged through ex / g2)
         HIPCHK(hipMemcpyAsync(B.ex.p, r1, (size_t)nb * S.n * 8, in_kind, st));
-        hipLaunchKernelGGL(k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+        LAUNCH(10, k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.ex.as<double>(), B.r1p.as<double>(), (i64)S.n);
-        KCHK();
         if (S.m > 0) HIPCHK(hipMemcpyAsync(B.r2.p, r2, (size_t)nb * S.m * 8, in_kind, st));
         // ||r|| per instance
         const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.r1p.as<double>(), (i64)S.n, B.r2.as<double>(),
+        LAUNCH(10, k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.r1p.as<double>(), (i64)S.n, B.r2.as<double>(),
                            (i64)S.m, B.part1.as<double>());
-        KCHK();
-        hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
+        LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
                            B.rowred.as<double>());
-        KCHK();
         std::vector<double> rn2(nb);
         HIPCHK(hipMemcpyAsync(rn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -896,23 +917,18 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         HIPCHK(hipMemcpyAsync(B.active.p, allact.data(), nb * 4, hipMemcpyHostToDevice, st));
         std::vector<double> rsq, fl(nb, 0.0);
         update_residual(c, B, rsq, false, fl.data());
-        hipLaunchKernelGGL(k_knorm_rows, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.part2.as<double>());
-        KCHK();
-        hipLaunchKernelGGL(k_reduce_max, dim3(nb), dim3(64), 0, st, B.part2.as<double>(), (int)g, B.knorm.as<double>());
-        KCHK();
-        hipLaunchKernelGGL(k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.xz.as<double>(), (i64)S.n, B.yz.as<double>(),
+        LAUNCH(10, k_knorm_rows, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.part2.as<double>());
+        LAUNCH(10, k_reduce_max, dim3(nb), dim3(64), 0, st, B.part2.as<double>(), (int)g, B.knorm.as<double>());
+        LAUNCH(10, k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.xz.as<double>(), (i64)S.n, B.yz.as<double>(),
                            (i64)S.m, B.part1.as<double>());
-        KCHK();
-        hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
+        LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
                            B.rowred.as<double>());
-        KCHK();
         std::vector<double> kn(nb), zn2(nb);
         HIPCHK(hipMemcpyAsync(kn.data(), B.knorm.p, nb * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(zn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
         // outputs in the original order
-        hipLaunchKernelGGL(k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+        LAUNCH(10, k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.xz.as<double>(), B.ex.as<double>(), (i64)S.n);
-        KCHK();
         HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, out_kind, st));
         if (S.m > 0) HIPCHK(hipMemcpyAsync(y, B.yz.p, (size_t)nb * S.m * 8, out_kind, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1005,33 +1021,27 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
         HIPCHK(hipMemcpyAsync(B.ex.p, bvec, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                               st));
-        hipLaunchKernelGGL(k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+        LAUNCH(10, k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.ex.as<double>(), B.rhat.as<double>(), (i64)S.n);
-        KCHK();
         std::vector<int> act(nb, 1);
         HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
         const unsigned gn = grid1(S.n, 4096);
         if (B.prec == HKKT_MIXED) {
-            hipLaunchKernelGGL((k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
+            LAUNCH(10, (k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
                                B.X.as<float>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
-            KCHK();
             launch_trisolve<float>(c, B, nullptr, nullptr);
-            hipLaunchKernelGGL((k_cast<float, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const float*)B.X.as<float>(),
+            LAUNCH(10, (k_cast<float, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const float*)B.X.as<float>(),
                                B.rhat.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
-            KCHK();
         } else {
-            hipLaunchKernelGGL((k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
+            LAUNCH(10, (k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
                                B.X.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
-            KCHK();
             launch_trisolve<double>(c, B, nullptr, nullptr);
-            hipLaunchKernelGGL((k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st,
+            LAUNCH(10, (k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st,
                                (const double*)B.X.as<double>(), B.rhat.as<double>(), (i64)S.n, (const int*)nullptr,
                                (const CGState*)nullptr);
-            KCHK();
         }
-        hipLaunchKernelGGL(k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+        LAUNCH(10, k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.rhat.as<double>(), B.ex.as<double>(), (i64)S.n);
-        KCHK();
         HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                               st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1043,6 +1053,35 @@ int hkkt_timings(const hkkt_ctx* c, double ms[8]) {
     if (!c || !ms) return HKKT_ERR_ARG;
     std::memcpy(ms, c->ms, sizeof(c->ms));
     return HKKT_OK;
+}
+
+int hkkt_profile_begin(hkkt_ctx* c) {
+    if (!c) return HKKT_ERR_ARG;
+    c->prof.on = true;
+    c->prof.used = 0;
+    c->prof.recs.clear();
+    return HKKT_OK;
+}
+
+int hkkt_profile_end(hkkt_ctx* c, double* ms, int64_t* launches) {
+    if (!c) return HKKT_ERR_ARG;
+    ABI_GUARD(c, {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double t[kNProf] = {0};
+        int64_t k[kNProf] = {0};
+        for (auto& r : c->prof.recs) {
+            float e = 0.f;
+            HIPCHK(hipEventElapsedTime(&e, c->prof.pool[r.second], c->prof.pool[r.second + 1]));
+            t[r.first] += e;
+            k[r.first]++;
+        }
+        c->prof.on = false;
+        c->prof.recs.clear();
+        c->prof.used = 0;
+        if (ms) std::memcpy(ms, t, sizeof(t));
+        if (launches) std::memcpy(launches, k, sizeof(k));
+        return HKKT_OK;
+    })
 }
 
 }  // extern "C"

@@ -24,7 +24,10 @@ EXPORTS = [
     "hkkt_factor_batch", "hkkt_factor", "hkkt_solve_batch", "hkkt_solve", "hkkt_inertia",
     "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
+    "hkkt_profile_begin", "hkkt_profile_end",
 ]
+PROF_NAMES = ["assemble", "front_lds", "front_global", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
+              "cg_scalar", "residual", "other", "unused"]
 
 i64p = C.POINTER(C.c_int64)
 i32p = C.POINTER(C.c_int32)
@@ -63,6 +66,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run paper_2110_03636_amd/build.py "
                                "(or __graft_entry__.build())")
+        # Load torch's HIP runtime first when torch is present: the library's
+        # libamdhip64.so.7 dependency then resolves to that same runtime, so a
+        # process never holds two HIP/HSA runtimes (torch requests its copy by
+        # an unversioned name and would otherwise load a second one).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         V = C.c_void_p
         L.hkkt_default_options.argtypes = [C.POINTER(Options)]
@@ -87,6 +98,8 @@ def lib():
         L.hkkt_get_factor.argtypes = [V, C.c_int, V, V, V]
         L.hkkt_hsolve.argtypes = [V, C.c_int, V, V]
         L.hkkt_timings.argtypes = [V, V]
+        L.hkkt_profile_begin.argtypes = [V]
+        L.hkkt_profile_end.argtypes = [V, V, V]
         _lib = L
     return _lib
 
@@ -241,6 +254,9 @@ class Solver(_SymbolicView):
         delta = np.atleast_1d(np.asarray(delta, np.float64))
         gamma = np.atleast_1d(np.asarray(gamma, np.float64))
         nb = int(delta.shape[0])
+        if self.n is None:  # not analysed: let the library report the state error
+            _check(lib().hkkt_factor_batch(self._ctx, nb, None, None, None, delta.ctypes.data,
+                                           gamma.ctypes.data, None, None), self._ctx)
         Hv = self._arr(H_val, nb, -1)
         Dx = self._arr(D_x, nb, self.n)
         Jv = self._arr(J_val, nb, -1) if self.m > 0 else None
@@ -302,3 +318,13 @@ class Solver(_SymbolicView):
         ms = np.zeros(8)
         lib().hkkt_timings(self._ctx, ms.ctypes.data)
         return dict(analyze=ms[0], factor=ms[1], solve=ms[2], fallback=ms[3])
+
+    def profile_begin(self):
+        _check(lib().hkkt_profile_begin(self._ctx), self._ctx)
+
+    def profile_end(self):
+        """{class: (total_ms, launches)} of the launches since profile_begin."""
+        ms = np.zeros(12)
+        k = np.zeros(12, np.int64)
+        _check(lib().hkkt_profile_end(self._ctx, ms.ctypes.data, k.ctypes.data), self._ctx)
+        return {PROF_NAMES[i]: (float(ms[i]), int(k[i])) for i in range(11)}

@@ -99,7 +99,9 @@ def _check_solution(b, x, y, infos, kkt_tol=1e-10, ref_iters=None):
         rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
         assert rr <= max(kkt_tol, 20 * fl), (i, rr, fl)
         assert infos[i]["status"] == 0, infos[i]
-        assert abs(infos[i]["rr"] - rr) <= 1e-3 * rr + 1e-15
+        # both residuals are FP64 sums in different orders: they agree to
+        # within the evaluation floor u*|| |K||z| + |r| ||/||r||
+        assert abs(infos[i]["rr"] - rr) <= 1e-3 * rr + 2 * fl
 
 
 @pytest.mark.parametrize("kkt_tol", [1e-8, 1e-10])
