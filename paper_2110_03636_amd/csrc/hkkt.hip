@@ -19,6 +19,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -150,10 +151,27 @@ struct DevSym {
     DBuf lev_all, lev_small, lev_big;   // supernode lists, level-major
     std::vector<i32> all_ptr, small_ptr, big_ptr;
     std::vector<int> all_maxnr, small_maxnr;
+    DBuf ga_ptr, ga_idx;
+    // triangular-solve lists per (level, size class): classes 0..4 are the
+    // wavefront kernels with R = 1,2,4,8,16 rows per lane, class 5 the
+    // work-group kernel for supernodes with more than 1024 rows
+    DBuf tri_list;
+    std::vector<std::pair<i32, i32>> tri_seg;   // [level * kTriClasses + class] = (offset, count)
+    std::vector<int> tri_wg_maxnr;              // per level, class 5
     SymView v{};
 };
 
 constexpr size_t kMaxLds = 65536;
+constexpr int kTriClasses = 6;
+
+static int tri_class(int nr) {
+    if (nr <= 64) return 0;
+    if (nr <= 128) return 1;
+    if (nr <= 256) return 2;
+    if (nr <= 512) return 3;
+    if (nr <= 1024) return 4;
+    return 5;
+}
 
 static int lds_rows_limit(int elem_bytes) {
     // LDS front of nr x nr entries within 64 KiB
@@ -211,6 +229,26 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     upload(D.lev_all, all, st);
     upload(D.lev_small, small, st);
     upload(D.lev_big, big, st);
+    upload(D.ga_ptr, S.ga_ptr, st);
+    upload(D.ga_idx, S.ga_idx, st);
+    {
+        std::vector<i32> tl;
+        D.tri_seg.assign((size_t)S.nlevels * kTriClasses, {0, 0});
+        D.tri_wg_maxnr.assign(S.nlevels, 0);
+        for (i32 l = 0; l < S.nlevels; l++)
+            for (int cls = 0; cls < kTriClasses; cls++) {
+                const i32 off = (i32)tl.size();
+                for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
+                    const i32 sn = S.level_sn[q];
+                    const int nr = (int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]);
+                    if (tri_class(nr) != cls) continue;
+                    tl.push_back(sn);
+                    if (cls == 5) D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
+                }
+                D.tri_seg[(size_t)l * kTriClasses + cls] = {off, (i32)tl.size() - off};
+            }
+        upload(D.tri_list, tl, st);
+    }
     SymView& v = D.v;
     v.n = S.n; v.m = S.m; v.ns = S.ns;
     v.sn_first = D.sn_first.as<i32>();
@@ -222,6 +260,8 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     v.child_ptr = D.child_ptr.as<i32>();
     v.child_list = D.child_list.as<i32>();
     v.relmap = D.relmap.as<i32>();
+    v.ga_ptr = D.ga_ptr.as<i64>();
+    v.ga_idx = D.ga_idx.as<i64>();
     v.perm = D.perm.as<i32>();
     v.Lsize = S.Lsize; v.CBsize = S.CBsize; v.UVsize = S.UVsize;
     v.nnzA = S.nnzA;
@@ -326,27 +366,44 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
 
 // X <- H_gamma^{-1} X (in place), per instance skip by active/st
 template <typename T>
-static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* active, const CGState* st_) {
-    const Symbolic& S = c->sym.S;
+static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* active, const CGState* st_) {
     const DevSym& D = c->dev;
-    hipStream_t st = c->stream;
     const int nb = B.nb;
     const T* L = B.L.as<T>();
     T* X = B.X.as<T>();
     T* UV = B.UV.as<T>();
-    for (i32 l = 0; l < S.nlevels; l++) {
-        const int cnt = D.all_ptr[l + 1] - D.all_ptr[l];
-        const size_t lds = (size_t)(kTri * kTri + D.all_maxnr[l]) * sizeof(T);
-        if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
-        LAUNCH(3, k_fwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
-                           UV, active, st_);
+    for (int cls = 0; cls < kTriClasses; cls++) {
+        const auto seg = D.tri_seg[(size_t)l * kTriClasses + cls];
+        if (seg.second == 0) continue;
+        const i32* lst = D.tri_list.as<i32>() + seg.first;
+        const int cnt = seg.second;
+        const unsigned nblk = (unsigned)(((i64)cnt * nb + (kBlock / kWave) - 1) / (kBlock / kWave));
+#define HKKT_TRI_W(RR)                                                                                       \
+    if (fwd) LAUNCH(3, (k_fwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, UV, active, \
+                    st_, nb);                                                                                \
+    else LAUNCH(4, (k_bwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, active, st_, nb);
+        switch (cls) {
+            case 0: HKKT_TRI_W(1) break;
+            case 1: HKKT_TRI_W(2) break;
+            case 2: HKKT_TRI_W(4) break;
+            case 3: HKKT_TRI_W(8) break;
+            case 4: HKKT_TRI_W(16) break;
+            default: {
+                const size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
+                if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
+                if (fwd) LAUNCH(3, k_fwd<T>, dim3(cnt, nb), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, active, st_);
+                else LAUNCH(4, k_bwd<T>, dim3(cnt, nb), dim3(kBlock), lds, c->stream, D.v, lst, L, X, active, st_);
+            }
+        }
+#undef HKKT_TRI_W
     }
-    for (i32 l = S.nlevels - 1; l >= 0; l--) {
-        const int cnt = D.all_ptr[l + 1] - D.all_ptr[l];
-        const size_t lds = (size_t)(kTri * kTri + D.all_maxnr[l]) * sizeof(T);
-        LAUNCH(4, k_bwd<T>, dim3(cnt, nb), dim3(kBlock), lds, st, D.v, D.lev_all.as<i32>() + D.all_ptr[l], L, X,
-                           active, st_);
-    }
+}
+
+template <typename T>
+static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* active, const CGState* st_) {
+    const Symbolic& S = c->sym.S;
+    for (i32 l = 0; l < S.nlevels; l++) launch_tri_level<T>(c, B, l, true, active, st_);
+    for (i32 l = S.nlevels - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, active, st_);
 }
 
 static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {
@@ -567,9 +624,13 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
         if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, max_cg, cg_tol, hst);
         else hybrid_pass<double>(c, B, max_cg, cg_tol, hst);
         update_residual(c, B, rsq, true, nullptr);
+        static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
         for (int i = 0; i < nb; i++) {
             if (!act[i]) continue;
             InstState& s = is[i];
+            if (trace)
+                std::fprintf(stderr, "hkkt: prec=%d pass=%d inst=%d cg=%d rr=%.3e brk=%d\n", B.prec, s.passes, i,
+                             hst[i].it, s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0, hst[i].breakdown);
             s.passes++;
             s.cg += hst[i].it;
             const double rr = s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0;

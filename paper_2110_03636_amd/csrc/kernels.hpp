@@ -18,7 +18,8 @@ using i32 = int32_t;
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
-constexpr int kTri = 64;   // diagonal block size of the triangular solves
+constexpr int kTri = 64;   // diagonal block size of the work-group triangular solves
+constexpr int kChunk = 8;  // panel columns prefetched per step by the wavefront solves
 
 // Device view of the symbolic analysis.
 struct SymView {
@@ -33,6 +34,8 @@ struct SymView {
     const i32* child_ptr;
     const i32* child_list;
     const i32* relmap;
+    const i64* ga_ptr;
+    const i64* ga_idx;
     const i32* perm;
     i64 Lsize, CBsize, UVsize;
     // assembly

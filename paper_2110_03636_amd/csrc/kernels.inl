@@ -284,10 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
         const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
         const i32* rel = S.relmap + S.sn_uvptr[c];
         const T* uc = uvb + S.sn_uvptr[c];
-        for (int k = threadIdx.x; k < ncc; k += blockDim.x) {
-            const int pos = rel[k];
-            u[pos] += pos < w ? -uc[k] : uc[k];
-        }
+        for (int k = threadIdx.x; k < ncc; k += blockDim.x) u[rel[k]] += uc[k];
         __syncthreads();
     }
     for (int kb = 0; kb < w; kb += kTri) {
@@ -311,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
         for (int i = kb + bw + threadIdx.x; i < nr; i += blockDim.x) {
             T sum = T(0);
             for (int k = 0; k < bw; k++) sum += Lb[(i64)(kb + k) * nr + i] * u[kb + k];
-            u[i] += i < w ? -sum : sum;
+            u[i] -= sum;
         }
         __syncthreads();
     }
@@ -367,6 +364,151 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
         __syncthreads();
     }
     for (int i = threadIdx.x; i < w; i += blockDim.x) x[f + i] = u[i];
+}
+
+// ---------------------------------------------------------------------------
+// wavefront triangular solves: one wavefront per (supernode, instance), rows
+// across lanes (R rows per lane, nr <= 64 R), panel columns prefetched kChunk
+// at a time into registers (coalesced column loads), the pivot value
+// broadcast by a lane shuffle. No LDS and no work-group barriers, so many
+// small supernodes of many instances keep the memory system busy.
+// Forward: v = [x(cols); 0] + children's update vectors (pulled through the
+// per-row gather list); for each column j: y_j = v_j / L_jj, v_i -= L_ij y_j.
+// Backward: v = [y(cols); x(rows below)]; for j = w-1..0:
+// x_j = (v_j - sum_{i>j} L_ij x_i) / L_jj with a butterfly wave sum.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_allsum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_fwd_w(SymView S, const i32* __restrict__ list, int count,
+                                                  const T* __restrict__ L, T* __restrict__ X, T* __restrict__ UV,
+                                                  const int* active, const CGState* st, int nb) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const i64 t = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+    if (t >= (i64)count * nb) return;
+    const int q = (int)(t / nb), b = (int)(t - (i64)q * nb);
+    if (skip_inst(active, st, b)) return;
+    const i32 s = list[q];
+    const i32 f = S.sn_first[s];
+    const int w = S.sn_first[s + 1] - f;
+    const i64 rp = S.sn_rowptr[s];
+    const int nr = (int)(S.sn_rowptr[s + 1] - rp);
+    const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    T* x = X + (i64)b * S.n;
+    T* uvb = UV + (i64)b * S.UVsize;
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = lane + kWave * r;
+        T a = T(0);
+        if (row < nr) {
+            if (row < w) a = x[f + row];
+            for (i64 g = S.ga_ptr[rp + row]; g < S.ga_ptr[rp + row + 1]; g++) a += uvb[S.ga_idx[g]];
+        }
+        v[r] = a;
+    }
+    for (int j0 = 0; j0 < w; j0 += kChunk) {
+        T lc[kChunk][R];
+#pragma unroll
+        for (int jj = 0; jj < kChunk; jj++)
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int row = lane + kWave * r;
+                lc[jj][r] = (j0 + jj < w && row < nr) ? Lb[(i64)(j0 + jj) * nr + row] : T(0);
+            }
+#pragma unroll
+        for (int jj = 0; jj < kChunk; jj++) {
+            const int j = j0 + jj;
+            if (j < w) {
+                const int jl = j & (kWave - 1), jr = j / kWave;
+                T vs = v[0], ds = lc[jj][0];
+#pragma unroll
+                for (int r = 1; r < R; r++)
+                    if (r == jr) { vs = v[r]; ds = lc[jj][r]; }
+                const T yj = __shfl(vs, jl, kWave) / __shfl(ds, jl, kWave);
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int row = lane + kWave * r;
+                    if (row == j) v[r] = yj;
+                    else if (row > j) v[r] -= lc[jj][r] * yj;
+                }
+            }
+        }
+    }
+    const i64 uo = S.sn_uvptr[s];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = lane + kWave * r;
+        if (row < w) x[f + row] = v[r];
+        else if (row < nr) uvb[uo + row - w] = v[r];
+    }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kBlock) void k_bwd_w(SymView S, const i32* __restrict__ list, int count,
+                                                  const T* __restrict__ L, T* __restrict__ X, const int* active,
+                                                  const CGState* st, int nb) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const i64 t = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+    if (t >= (i64)count * nb) return;
+    const int q = (int)(t / nb), b = (int)(t - (i64)q * nb);
+    if (skip_inst(active, st, b)) return;
+    const i32 s = list[q];
+    const i32 f = S.sn_first[s];
+    const int w = S.sn_first[s + 1] - f;
+    const i64 rp = S.sn_rowptr[s];
+    const int nr = (int)(S.sn_rowptr[s + 1] - rp);
+    const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    T* x = X + (i64)b * S.n;
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = lane + kWave * r;
+        v[r] = row < w ? x[f + row] : (row < nr ? x[S.sn_rows[rp + row]] : T(0));
+    }
+    for (int jhi = w; jhi > 0; jhi -= kChunk) {
+        const int j0 = jhi > kChunk ? jhi - kChunk : 0;
+        T lc[kChunk][R];
+#pragma unroll
+        for (int jj = 0; jj < kChunk; jj++)
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int row = lane + kWave * r;
+                lc[jj][r] = (j0 + jj < jhi && row < nr) ? Lb[(i64)(j0 + jj) * nr + row] : T(0);
+            }
+#pragma unroll
+        for (int jj = kChunk - 1; jj >= 0; jj--) {
+            const int j = j0 + jj;
+            if (j < jhi) {
+                T part = T(0);
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int row = lane + kWave * r;
+                    if (row > j) part += lc[jj][r] * v[r];
+                }
+                part = wave_allsum(part);
+                const int jl = j & (kWave - 1), jr = j / kWave;
+                T vs = v[0], ds = lc[jj][0];
+#pragma unroll
+                for (int r = 1; r < R; r++)
+                    if (r == jr) { vs = v[r]; ds = lc[jj][r]; }
+                const T xj = (__shfl(vs, jl, kWave) - part) / __shfl(ds, jl, kWave);
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if (lane + kWave * r == j) v[r] = xj;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = lane + kWave * r;
+        if (row < w) x[f + row] = v[r];
+    }
 }
 
 // ---------------------------------------------------------------------------
