@@ -129,6 +129,8 @@ def run_gpu(args):
         "fp64_plain_solves_per_s": round(fp64_plain, 2),
         "speedup_vs_plain_fp64": round(value / fp64_plain, 2) if fp64_plain > 0 else None,
         "converged": f"{ok}/{nb}",
+        "not_converged": [{"rr": i["rr"], "floor": i["floor"], "fallback": i["fp64_fallback"]}
+                          for i in infos if not (i["status"] == 0 and i["rr"] <= 1e-10)],
         "max_rr": max(i["rr"] for i in infos),
         "fp64_fallbacks": sum(i["fp64_fallback"] for i in infos),
         "cg_iters_mean": round(float(np.mean(cg)), 2),

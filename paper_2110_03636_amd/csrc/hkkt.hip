@@ -295,6 +295,7 @@ struct Batch {
     // solve workspace
     DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
+    DBuf ids_pass, ids_a, ids_b, ids_all;   // instance-id lists of the solve phase
     std::vector<int> h_fail;   // per instance min failing permuted column (INT_MAX ok)
 
     ValView vals() const {
@@ -364,11 +365,11 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     }
 }
 
-// X <- H_gamma^{-1} X (in place), per instance skip by active/st
+// X <- H_gamma^{-1} X (in place) for the nids instances listed in ids;
+// instances whose CG is done (st) are skipped
 template <typename T>
-static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* active, const CGState* st_) {
+static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* ids, int nids, const CGState* st_) {
     const DevSym& D = c->dev;
-    const int nb = B.nb;
     const T* L = B.L.as<T>();
     T* X = B.X.as<T>();
     T* UV = B.UV.as<T>();
@@ -377,11 +378,11 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         if (seg.second == 0) continue;
         const i32* lst = D.tri_list.as<i32>() + seg.first;
         const int cnt = seg.second;
-        const unsigned nblk = (unsigned)(((i64)cnt * nb + (kBlock / kWave) - 1) / (kBlock / kWave));
-#define HKKT_TRI_W(RR)                                                                                       \
-    if (fwd) LAUNCH(3, (k_fwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, UV, active, \
-                    st_, nb);                                                                                \
-    else LAUNCH(4, (k_bwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, active, st_, nb);
+        const unsigned nblk = (unsigned)(((i64)cnt * nids + (kBlock / kWave) - 1) / (kBlock / kWave));
+#define HKKT_TRI_W(RR)                                                                                           \
+    if (fwd) LAUNCH(3, (k_fwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, UV, ids, st_, \
+                    nids);                                                                                       \
+    else LAUNCH(4, (k_bwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, ids, st_, nids);
         switch (cls) {
             case 0: HKKT_TRI_W(1) break;
             case 1: HKKT_TRI_W(2) break;
@@ -391,8 +392,8 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
             default: {
                 const size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
                 if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
-                if (fwd) LAUNCH(3, k_fwd<T>, dim3(cnt, nb), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, active, st_);
-                else LAUNCH(4, k_bwd<T>, dim3(cnt, nb), dim3(kBlock), lds, c->stream, D.v, lst, L, X, active, st_);
+                if (fwd) LAUNCH(3, k_fwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                else LAUNCH(4, k_bwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
             }
         }
 #undef HKKT_TRI_W
@@ -400,10 +401,11 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
 }
 
 template <typename T>
-static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* active, const CGState* st_) {
+static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* ids, int nids, const CGState* st_) {
     const Symbolic& S = c->sym.S;
-    for (i32 l = 0; l < S.nlevels; l++) launch_tri_level<T>(c, B, l, true, active, st_);
-    for (i32 l = S.nlevels - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, active, st_);
+    if (nids <= 0) return;
+    for (i32 l = 0; l < S.nlevels; l++) launch_tri_level<T>(c, B, l, true, ids, nids, st_);
+    for (i32 l = S.nlevels - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, ids, nids, st_);
 }
 
 static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {
@@ -438,6 +440,7 @@ static void alloc_solve(hkkt_ctx* c, Batch& B) {
     for (DBuf* d : {&B.part1, &B.part2, &B.pfloor}) d->ensure(nb * nblk * 8);
     B.st.ensure(nb * sizeof(CGState));
     B.live.ensure(16);
+    for (DBuf* d : {&B.ids_pass, &B.ids_a, &B.ids_b, &B.ids_all}) d->ensure(nb * 4);
     for (DBuf* d : {&B.rsq, &B.rowred, &B.knorm}) d->ensure(nb * 8);
 }
 
@@ -490,90 +493,110 @@ static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h
 }
 
 // ---------------------------------------------------------------------------
-// one hybrid pass on the residual (g1, g2): ex, y <- approx K^{-1} g
+// one hybrid pass on the residual (g1, g2) of the nids instances listed in
+// B.ids_pass: ex, y <- approx K^{-1} g (Algorithm 1, solve phase)
 // ---------------------------------------------------------------------------
 template <typename T>
-static void hybrid_pass(hkkt_ctx* c, Batch& B, int max_cg, double cg_tol, std::vector<CGState>& hst) {
+static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_tol, std::vector<CGState>& hst) {
     const Symbolic& S = c->sym.S;
     const DevSym& D = c->dev;
     hipStream_t st = c->stream;
-    const int nb = B.nb;
-    const int* act = B.active.as<int>();
+    const int* ids = B.ids_pass.as<int>();
     const ValView V = B.vals();
     CGState* cst = B.st.as<CGState>();
     const unsigned gn = grid1(S.n, 4096), gm = grid1(S.m);
     T* X = B.X.as<T>();
-    // rhat = g1 + gamma J^T g2
-    LAUNCH(5, k_jt<double>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
-                       B.g2.as<double>(), B.rhat.as<double>(), act, (const CGState*)nullptr);
-    LAUNCH(10, (k_cast<double, T>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(), X, (i64)S.n, act,
-                       (const CGState*)nullptr);
-    launch_trisolve<T>(c, B, act, nullptr);
-    // bvec = J w - g2
+    // rhat = g1 + gamma J^T g2; w = H_gamma^{-1} rhat
+    LAUNCH(5, k_jt<double>, dim3(gn, nids), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
+           B.g2.as<double>(), B.rhat.as<double>(), ids, (const CGState*)nullptr);
+    LAUNCH(10, (k_cast<double, T>), dim3(gn, nids), dim3(kBlock), 0, st, B.rhat.as<double>(), X, (i64)S.n, ids,
+           (const CGState*)nullptr);
+    launch_trisolve<T>(c, B, ids, nids, nullptr);
+    // bvec = J w - g2 (eq. Schur1 right-hand side)
     const unsigned gmb = (unsigned)std::max<i64>(1, (S.m + kBlock - 1) / kBlock);
-    LAUNCH(6, k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
-                       (const double*)nullptr, (const CGState*)nullptr, 0, B.bvec.as<double>(), B.part1.as<double>(),
-                       (double*)nullptr, act);
-    LAUNCH(8, k_cg_init, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, act, (i64)S.m);
-    LAUNCH(7, k_cg_vecinit, dim3(gm, nb), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
-                       B.res.as<double>(), B.p.as<double>(), (i64)S.m, act);
-    int check_every = 4;
-    for (int it = 0; it < max_cg && S.m > 0; it++) {
-        LAUNCH(5, k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, (const double*)nullptr, 1.0, 0,
-                           B.p.as<double>(), X, act, (const CGState*)cst);
-        launch_trisolve<T>(c, B, act, cst);
-        LAUNCH(6, k_j<T>, dim3(gmb, nb), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
-                           B.p.as<double>(), (const CGState*)cst, 1, B.q.as<double>(), B.part1.as<double>(),
-                           B.part2.as<double>(), act);
-        LAUNCH(8, k_cg_alpha, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), B.part2.as<double>(),
-                           (int)gmb, c->opt.quad_form_eps, c->opt.delta2);
-        LAUNCH(7, k_cg_update, dim3(gmb, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.q.as<double>(),
-                           B.bvec.as<double>(), B.y.as<double>(), B.res.as<double>(), (const CGState*)cst, (i64)S.m,
-                           B.part1.as<double>());
-        LAUNCH(8, k_cg_beta, dim3(nb), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, cg_tol, max_cg);
-        LAUNCH(7, k_cg_p, dim3(gm, nb), dim3(kBlock), 0, st, B.p.as<double>(), B.res.as<double>(),
-                           (const CGState*)cst, (i64)S.m);
+    LAUNCH(6, k_j<T>, dim3(gmb, nids), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
+           (const double*)nullptr, (const CGState*)nullptr, 0, B.bvec.as<double>(), B.part1.as<double>(),
+           (double*)nullptr, ids);
+    LAUNCH(8, k_cg_init, dim3(nids), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, ids, (i64)S.m);
+    LAUNCH(7, k_cg_vecinit, dim3(gm, nids), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
+           B.res.as<double>(), B.p.as<double>(), (i64)S.m, ids);
+    // CG on S y = bvec over a shrinking list of live instances
+    int* cur = B.ids_a.as<int>();
+    int* nxt = B.ids_b.as<int>();
+    HIPCHK(hipMemcpyAsync(cur, ids, (size_t)nids * 4, hipMemcpyDeviceToDevice, st));
+    int ncur = nids;
+    const int check_every = 4;
+    for (int it = 0; it < max_cg && S.m > 0 && ncur > 0; it++) {
+        LAUNCH(5, k_jt<T>, dim3(gn, ncur), dim3(kBlock), 0, st, D.v, V, (const double*)nullptr, 1.0, 0,
+               B.p.as<double>(), X, (const int*)cur, (const CGState*)cst);
+        launch_trisolve<T>(c, B, cur, ncur, cst);
+        LAUNCH(6, k_j<T>, dim3(gmb, ncur), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
+               B.p.as<double>(), (const CGState*)cst, 1, B.q.as<double>(), B.part1.as<double>(), B.part2.as<double>(),
+               (const int*)cur);
+        LAUNCH(8, k_cg_alpha, dim3(ncur), dim3(kBlock), 0, st, cst, B.part1.as<double>(), B.part2.as<double>(),
+               (int)gmb, c->opt.quad_form_eps, c->opt.delta2, (const int*)cur);
+        LAUNCH(7, k_cg_update, dim3(gmb, ncur), dim3(kBlock), 0, st, B.p.as<double>(), B.q.as<double>(),
+               B.bvec.as<double>(), B.y.as<double>(), B.res.as<double>(), (const CGState*)cst, (i64)S.m,
+               B.part1.as<double>(), (const int*)cur);
+        LAUNCH(8, k_cg_beta, dim3(ncur), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, cg_tol, max_cg,
+               (const int*)cur);
+        LAUNCH(7, k_cg_p, dim3(gm, ncur), dim3(kBlock), 0, st, B.p.as<double>(), B.res.as<double>(),
+               (const CGState*)cst, (i64)S.m, (const int*)cur);
         if ((it + 1) % check_every == 0) {
-            LAUNCH(8, k_count_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, nb, B.live.as<int>());
+            LAUNCH(8, k_compact_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, (const int*)cur, ncur, nxt,
+                   B.live.as<int>());
             int live = 0;
             HIPCHK(hipMemcpyAsync(&live, B.live.p, 4, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            if (live == 0) break;
+            std::swap(cur, nxt);
+            ncur = live;
         }
     }
-    // x = H_gamma^{-1} (rhat - J^T y)
-    LAUNCH(5, k_jt<T>, dim3(gn, nb), dim3(kBlock), 0, st, D.v, V, B.rhat.as<double>(), -1.0, 0,
-                       B.y.as<double>(), X, act, (const CGState*)nullptr);
-    launch_trisolve<T>(c, B, act, nullptr);
-    LAUNCH(10, (k_cast<T, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
-                       act, (const CGState*)nullptr);
-    hst.resize(nb);
-    HIPCHK(hipMemcpyAsync(hst.data(), cst, nb * sizeof(CGState), hipMemcpyDeviceToHost, st));
+    // x = H_gamma^{-1} (rhat - J^T y) (eq. Schur2)
+    LAUNCH(5, k_jt<T>, dim3(gn, nids), dim3(kBlock), 0, st, D.v, V, B.rhat.as<double>(), -1.0, 0,
+           B.y.as<double>(), X, ids, (const CGState*)nullptr);
+    launch_trisolve<T>(c, B, ids, nids, nullptr);
+    LAUNCH(10, (k_cast<T, double>), dim3(gn, nids), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
+           ids, (const CGState*)nullptr);
+    hst.resize(B.nb);
+    HIPCHK(hipMemcpyAsync(hst.data(), cst, B.nb * sizeof(CGState), hipMemcpyDeviceToHost, st));
 }
 
-// z += e; g = r - K z; returns ||g||^2 per instance in rsq (host)
-static void update_residual(hkkt_ctx* c, Batch& B, std::vector<double>& rsq, bool add, double* floor_out) {
+// for the nids instances in ids: (if add) z += e; g = r - K z; ||g||^2 into
+// rsq (host, indexed by instance)
+static void update_residual(hkkt_ctx* c, Batch& B, const int* ids, int nids, std::vector<double>& rsq, bool add,
+                            double* floor_out) {
     const Symbolic& S = c->sym.S;
     hipStream_t st = c->stream;
-    const int nb = B.nb;
-    const int* act = B.active.as<int>();
+    rsq.assign(B.nb, 0.0);
+    if (nids <= 0) return;
     if (add) {
-        LAUNCH(10, k_axpy2, dim3(grid1(S.n + S.m, 4096), nb), dim3(kBlock), 0, st, B.xz.as<double>(),
-                           B.ex.as<double>(), (i64)S.n, B.yz.as<double>(), B.y.as<double>(), (i64)S.m, act);
+        LAUNCH(10, k_axpy2, dim3(grid1(S.n + S.m, 4096), nids), dim3(kBlock), 0, st, B.xz.as<double>(),
+               B.ex.as<double>(), (i64)S.n, B.yz.as<double>(), B.y.as<double>(), (i64)S.m, ids);
     }
     const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
-    LAUNCH(9, k_residual, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.r1p.as<double>(),
-                       B.r2.as<double>(), B.xz.as<double>(), B.yz.as<double>(), B.g1.as<double>(), B.g2.as<double>(),
-                       B.part1.as<double>(), floor_out ? B.pfloor.as<double>() : (double*)nullptr, act);
-    LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g, B.rsq.as<double>());
-    rsq.resize(nb);
-    HIPCHK(hipMemcpyAsync(rsq.data(), B.rsq.p, nb * 8, hipMemcpyDeviceToHost, st));
+    LAUNCH(9, k_residual, dim3(g, nids), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.r1p.as<double>(),
+           B.r2.as<double>(), B.xz.as<double>(), B.yz.as<double>(), B.g1.as<double>(), B.g2.as<double>(),
+           B.part1.as<double>(), floor_out ? B.pfloor.as<double>() : (double*)nullptr, ids);
+    LAUNCH(10, k_reduce_rows, dim3(nids), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g, B.rsq.as<double>(), ids);
+    HIPCHK(hipMemcpyAsync(rsq.data(), B.rsq.p, B.nb * 8, hipMemcpyDeviceToHost, st));
     if (floor_out) {
-        LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.pfloor.as<double>(), (int)g,
-                           B.rowred.as<double>());
-        HIPCHK(hipMemcpyAsync(floor_out, B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
+        LAUNCH(10, k_reduce_rows, dim3(nids), dim3(kBlock), 0, st, B.pfloor.as<double>(), (int)g,
+               B.rowred.as<double>(), ids);
+        HIPCHK(hipMemcpyAsync(floor_out, B.rowred.p, B.nb * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
+}
+
+static int upload_ids(hkkt_ctx* c, DBuf& dst, const std::vector<int>& flags) {
+    std::vector<int> ids;
+    for (int i = 0; i < (int)flags.size(); i++)
+        if (flags[i]) ids.push_back(i);
+    if (!ids.empty()) {
+        HIPCHK(hipMemcpyAsync(dst.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return (int)ids.size();
 }
 
 struct InstState {
@@ -584,7 +607,11 @@ struct InstState {
 };
 
 // refinement loop on batch B for the instances with run[i] set; vectors
-// r1p/r2 and (if warm) xz/yz must be in place.
+// r1p/r2 and (if warm) xz/yz must be in place. Mixed precision
+// (allow_stall_exit): a pass that does not halve RR, or six passes, hands the
+// instance to the FP64 fallback. FP64: a pass that does not halve RR ends
+// refinement (RR is then at the FP64 evaluation floor) and the status stays
+// NOT_CONVERGED unless RR <= kkt_tol.
 static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std::vector<int>& run, bool warm,
                    bool allow_stall_exit) {
     const Symbolic& S = c->sym.S;
@@ -595,16 +622,16 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
     const int max_cg = o.max_cg > 0 ? o.max_cg : (int)std::max<i64>(1, std::min<i64>(S.m, 1000));
     const double cg_tol = B.prec == HKKT_MIXED ? std::max(o.cg_tol, o.cg_tol_mixed) : o.cg_tol;
     std::vector<double> rsq;
-    HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
     if (!warm) {
         LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.n)), dim3(kBlock), 0, st, B.xz.as<double>(),
-                           (i64)nb * S.n, 0.0);
+               (i64)nb * S.n, 0.0);
         if (S.m > 0) {
             LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.m)), dim3(kBlock), 0, st, B.yz.as<double>(),
-                               (i64)nb * S.m, 0.0);
+                   (i64)nb * S.m, 0.0);
         }
     }
-    update_residual(c, B, rsq, false, nullptr);
+    int nids = upload_ids(c, B.ids_pass, act);
+    update_residual(c, B, B.ids_pass.as<int>(), nids, rsq, false, nullptr);
     for (int i = 0; i < nb; i++)
         if (act[i]) {
             is[i].rr_prev = is[i].rnorm > 0 ? std::sqrt(rsq[i]) / is[i].rnorm : 0.0;
@@ -614,26 +641,24 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
                 act[i] = 0;
             }
         }
-    int max_ref = o.max_refine >= 0 ? o.max_refine : 10;
+    const int max_ref = o.max_refine >= 0 ? o.max_refine : 10;
+    static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
     std::vector<CGState> hst;
     for (int pass = 0; pass <= max_ref; pass++) {
-        bool any = false;
-        for (int i = 0; i < nb; i++) any |= act[i] != 0;
-        if (!any) break;
-        HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
-        if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, max_cg, cg_tol, hst);
-        else hybrid_pass<double>(c, B, max_cg, cg_tol, hst);
-        update_residual(c, B, rsq, true, nullptr);
-        static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
+        nids = upload_ids(c, B.ids_pass, act);
+        if (nids == 0) break;
+        if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, nids, max_cg, cg_tol, hst);
+        else hybrid_pass<double>(c, B, nids, max_cg, cg_tol, hst);
+        update_residual(c, B, B.ids_pass.as<int>(), nids, rsq, true, nullptr);
         for (int i = 0; i < nb; i++) {
             if (!act[i]) continue;
             InstState& s = is[i];
+            const double rr = s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0;
             if (trace)
                 std::fprintf(stderr, "hkkt: prec=%d pass=%d inst=%d cg=%d rr=%.3e brk=%d\n", B.prec, s.passes, i,
-                             hst[i].it, s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0, hst[i].breakdown);
+                             hst[i].it, rr, hst[i].breakdown);
             s.passes++;
             s.cg += hst[i].it;
-            const double rr = s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0;
             s.rr = rr;
             if (hst[i].breakdown && o.delta2 == 0.0) {
                 s.brk = 1;
@@ -646,10 +671,13 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
                 s.fallback = true;
                 s.status = HKKT_NOT_CONVERGED;
                 act[i] = 0;
+            } else if (!allow_stall_exit && s.passes >= 2 && !(rr < 0.5 * s.rr_prev)) {
+                s.status = HKKT_NOT_CONVERGED;   // stagnated at the evaluation floor
+                act[i] = 0;
             } else {
                 s.status = HKKT_NOT_CONVERGED;
             }
-            s.rr_prev = rr;
+            s.rr_prev = std::min(s.rr_prev, rr);
         }
     }
 }
@@ -890,7 +918,7 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         LAUNCH(10, k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.r1p.as<double>(), (i64)S.n, B.r2.as<double>(),
                            (i64)S.m, B.part1.as<double>());
         LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
-                           B.rowred.as<double>());
+                           B.rowred.as<double>(), (const int*)nullptr);
         std::vector<double> rn2(nb);
         HIPCHK(hipMemcpyAsync(rn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -975,15 +1003,15 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         // final metrics: RR, BE, floor on the full KKT residual
         std::vector<int> allact(nb);
         for (int b = 0; b < nb; b++) allact[b] = c->fstatus[b] == HKKT_OK;
-        HIPCHK(hipMemcpyAsync(B.active.p, allact.data(), nb * 4, hipMemcpyHostToDevice, st));
+        const int nall = upload_ids(c, B.ids_all, allact);
         std::vector<double> rsq, fl(nb, 0.0);
-        update_residual(c, B, rsq, false, fl.data());
+        update_residual(c, B, B.ids_all.as<int>(), nall, rsq, false, fl.data());
         LAUNCH(10, k_knorm_rows, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.part2.as<double>());
         LAUNCH(10, k_reduce_max, dim3(nb), dim3(64), 0, st, B.part2.as<double>(), (int)g, B.knorm.as<double>());
         LAUNCH(10, k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.xz.as<double>(), (i64)S.n, B.yz.as<double>(),
                            (i64)S.m, B.part1.as<double>());
         LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
-                           B.rowred.as<double>());
+                           B.rowred.as<double>(), (const int*)nullptr);
         std::vector<double> kn(nb), zn2(nb);
         HIPCHK(hipMemcpyAsync(kn.data(), B.knorm.p, nb * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(zn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
@@ -1084,19 +1112,17 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
                               st));
         LAUNCH(10, k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.ex.as<double>(), B.rhat.as<double>(), (i64)S.n);
-        std::vector<int> act(nb, 1);
-        HIPCHK(hipMemcpyAsync(B.active.p, act.data(), nb * 4, hipMemcpyHostToDevice, st));
         const unsigned gn = grid1(S.n, 4096);
         if (B.prec == HKKT_MIXED) {
             LAUNCH(10, (k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
                                B.X.as<float>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
-            launch_trisolve<float>(c, B, nullptr, nullptr);
+            launch_trisolve<float>(c, B, nullptr, nb, nullptr);
             LAUNCH(10, (k_cast<float, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const float*)B.X.as<float>(),
                                B.rhat.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
         } else {
             LAUNCH(10, (k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
                                B.X.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
-            launch_trisolve<double>(c, B, nullptr, nullptr);
+            launch_trisolve<double>(c, B, nullptr, nb, nullptr);
             LAUNCH(10, (k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st,
                                (const double*)B.X.as<double>(), B.rhat.as<double>(), (i64)S.n, (const int*)nullptr,
                                (const CGState*)nullptr);

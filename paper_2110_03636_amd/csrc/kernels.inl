@@ -14,6 +14,10 @@ __device__ __forceinline__ bool skip_inst(const int* active, const CGState* st, 
     return (active && !active[b]) || (st && st[b].done);
 }
 
+// Solve-phase kernels run over a list of instance ids (the instances still
+// active); grid index k maps to instance ids[k] (ids null: k itself).
+__device__ __forceinline__ int inst_of(const int* ids, int k) { return ids ? ids[k] : k; }
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -43,10 +47,10 @@ __global__ void k_fill(T* __restrict__ p, i64 n, T v) {
 }
 
 template <typename TI, typename TO>
-__global__ void k_cast(const TI* __restrict__ in, TO* __restrict__ out, i64 len, const int* active,
+__global__ void k_cast(const TI* __restrict__ in, TO* __restrict__ out, i64 len, const int* ids,
                        const CGState* st) {
-    const int b = blockIdx.y;
-    if (skip_inst(active, st, b)) return;
+    const int b = inst_of(ids, blockIdx.y);
+    if (st && st[b].done) return;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (i64)gridDim.x * blockDim.x)
         out[(i64)b * len + i] = (TO)in[(i64)b * len + i];
 }
@@ -262,13 +266,13 @@ __global__ __launch_bounds__(kBlock) void k_front_global(SymView S, const i32* _
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
-                                                T* __restrict__ X, T* __restrict__ UV, const int* active,
+                                                T* __restrict__ X, T* __restrict__ UV, const int* ids,
                                                 const CGState* st) {
     extern __shared__ double smem_d[];
     T* D = reinterpret_cast<T*>(smem_d);
     T* u = D + kTri * kTri;
-    const int b = blockIdx.y;
-    if (skip_inst(active, st, b)) return;
+    const int b = inst_of(ids, blockIdx.y);
+    if (st && st[b].done) return;
     const i32 s = list[blockIdx.x];
     const i32 f = S.sn_first[s];
     const int w = S.sn_first[s + 1] - f;
@@ -320,12 +324,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
-                                                T* __restrict__ X, const int* active, const CGState* st) {
+                                                T* __restrict__ X, const int* ids, const CGState* st) {
     extern __shared__ double smem_d[];
     T* D = reinterpret_cast<T*>(smem_d);
     T* u = D + kTri * kTri;
-    const int b = blockIdx.y;
-    if (skip_inst(active, st, b)) return;
+    const int b = inst_of(ids, blockIdx.y);
+    if (st && st[b].done) return;
     const i32 s = list[blockIdx.x];
     const i32 f = S.sn_first[s];
     const int w = S.sn_first[s + 1] - f;
@@ -387,12 +391,13 @@ __device__ __forceinline__ T wave_allsum(T v) {
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_fwd_w(SymView S, const i32* __restrict__ list, int count,
                                                   const T* __restrict__ L, T* __restrict__ X, T* __restrict__ UV,
-                                                  const int* active, const CGState* st, int nb) {
+                                                  const int* ids, const CGState* st, int nids) {
     const int lane = threadIdx.x & (kWave - 1);
     const i64 t = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-    if (t >= (i64)count * nb) return;
-    const int q = (int)(t / nb), b = (int)(t - (i64)q * nb);
-    if (skip_inst(active, st, b)) return;
+    if (t >= (i64)count * nids) return;
+    const int q = (int)(t / nids);
+    const int b = inst_of(ids, (int)(t - (i64)q * nids));
+    if (st && st[b].done) return;
     const i32 s = list[q];
     const i32 f = S.sn_first[s];
     const int w = S.sn_first[s + 1] - f;
@@ -451,13 +456,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd_w(SymView S, const i32* __restri
 
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_bwd_w(SymView S, const i32* __restrict__ list, int count,
-                                                  const T* __restrict__ L, T* __restrict__ X, const int* active,
-                                                  const CGState* st, int nb) {
+                                                  const T* __restrict__ L, T* __restrict__ X, const int* ids,
+                                                  const CGState* st, int nids) {
     const int lane = threadIdx.x & (kWave - 1);
     const i64 t = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-    if (t >= (i64)count * nb) return;
-    const int q = (int)(t / nb), b = (int)(t - (i64)q * nb);
-    if (skip_inst(active, st, b)) return;
+    if (t >= (i64)count * nids) return;
+    const int q = (int)(t / nids);
+    const int b = inst_of(ids, (int)(t - (i64)q * nids));
+    if (st && st[b].done) return;
     const i32 s = list[q];
     const i32 f = S.sn_first[s];
     const int w = S.sn_first[s + 1] - f;
@@ -518,9 +524,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_w(SymView S, const i32* __restri
 // ---------------------------------------------------------------------------
 template <typename TO>
 __global__ void k_jt(SymView S, ValView V, const double* __restrict__ a, double scale, int use_gamma,
-                     const double* __restrict__ v, TO* __restrict__ out, const int* active, const CGState* st) {
-    const int b = blockIdx.y;
-    if (skip_inst(active, st, b)) return;
+                     const double* __restrict__ v, TO* __restrict__ out, const int* ids, const CGState* st) {
+    const int b = inst_of(ids, blockIdx.y);
+    if (st && st[b].done) return;
     const double sc = scale * (use_gamma ? V.gamma[b] : 1.0);
     const double* JT = V.JT + (i64)b * S.nnzJ;
     const double* vb = v + (i64)b * S.m;
@@ -539,10 +545,10 @@ template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __restrict__ u, const double* __restrict__ sub,
                                               const double* __restrict__ p, const CGState* st, int mode,
                                               double* __restrict__ q, double* __restrict__ part1,
-                                              double* __restrict__ part2, const int* active) {
+                                              double* __restrict__ part2, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.y;
-    if (skip_inst(active, mode == 1 ? st : nullptr, b)) return;
+    const int b = inst_of(ids, blockIdx.y);
+    if (mode == 1 && st[b].done) return;
     const double* J = V.J + (i64)b * S.nnzJ;
     const TI* ub = u + (i64)b * S.n;
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -579,24 +585,23 @@ __device__ double reduce_parts(const double* part, int nblk, double* sh) {
 }
 
 // one block per instance: rho = ||b||^2, reset the state
-__global__ void k_cg_init(CGState* st, const double* part, int nblk, const int* active, i64 m) {
+__global__ void k_cg_init(CGState* st, const double* part, int nblk, const int* ids, i64 m) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.x;
+    const int b = inst_of(ids, blockIdx.x);
     const double r = reduce_parts(part + (i64)b * nblk, nblk, sh);
     if (threadIdx.x == 0) {
         CGState c = {};
         c.rho = r;
         c.bnorm = sqrt(r);
         c.curv0 = -1.0;
-        c.done = (active && !active[b]) || m == 0 || !(r > 0.0);
+        c.done = m == 0 || !(r > 0.0);
         st[b] = c;
     }
 }
 
 __global__ void k_cg_vecinit(const double* __restrict__ bvec, double* __restrict__ y, double* __restrict__ res,
-                             double* __restrict__ p, i64 m, const int* active) {
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
+                             double* __restrict__ p, i64 m, const int* ids) {
+    const int b = inst_of(ids, blockIdx.y);
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) {
         const double v = bvec[(i64)b * m + i];
         y[(i64)b * m + i] = 0.0;
@@ -607,9 +612,9 @@ __global__ void k_cg_vecinit(const double* __restrict__ bvec, double* __restrict
 
 // alpha = rho / p'q, with the small-quadratic-form test of Algorithm 1
 __global__ void k_cg_alpha(CGState* st, const double* part1, const double* part2, int nblk, double qf_eps,
-                           double delta2) {
+                           double delta2, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.x;
+    const int b = inst_of(ids, blockIdx.x);
     if (st[b].done) return;
     const double pq = reduce_parts(part1 + (i64)b * nblk, nblk, sh);
     const double pp = reduce_parts(part2 + (i64)b * nblk, nblk, sh);
@@ -639,9 +644,9 @@ __global__ void k_cg_alpha(CGState* st, const double* part1, const double* part2
 __global__ __launch_bounds__(kBlock) void k_cg_update(const double* __restrict__ p, const double* __restrict__ q,
                                                       const double* __restrict__ bvec, double* __restrict__ y,
                                                       double* __restrict__ res, const CGState* st, i64 m,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.y;
+    const int b = inst_of(ids, blockIdx.y);
     if (st[b].done) return;
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     double a = 0.0;
@@ -663,9 +668,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const double* __restrict__
     if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
 }
 
-__global__ void k_cg_beta(CGState* st, const double* part, int nblk, double tol, int max_it) {
+__global__ void k_cg_beta(CGState* st, const double* part, int nblk, double tol, int max_it, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.x;
+    const int b = inst_of(ids, blockIdx.x);
     if (st[b].done) return;
     const double r1 = reduce_parts(part + (i64)b * nblk, nblk, sh);
     if (threadIdx.x == 0) {
@@ -685,8 +690,9 @@ __global__ void k_cg_beta(CGState* st, const double* part, int nblk, double tol,
     }
 }
 
-__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ res, const CGState* st, i64 m) {
-    const int b = blockIdx.y;
+__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ res, const CGState* st, i64 m,
+                       const int* ids) {
+    const int b = inst_of(ids, blockIdx.y);
     if (st[b].done) return;
     const double be = st[b].beta;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) {
@@ -695,12 +701,31 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ res, c
     }
 }
 
-__global__ void k_count_live(const CGState* st, int nb, int* out) {
-    __shared__ double sh[kBlock / kWave];
-    double c = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) c += st[b].done ? 0.0 : 1.0;
-    c = block_sum(c, sh);
-    if (threadIdx.x == 0) *out = (int)c;
+// Order-preserving compaction of the instances whose CG is still running
+// (one work-group): ids_out = [b in ids_in with !st[b].done], *n_out = count.
+__global__ void k_compact_live(const CGState* st, const int* ids_in, int n_in, int* ids_out, int* n_out) {
+    __shared__ int sc[kBlock];
+    __shared__ int base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n_in; c0 += blockDim.x) {
+        const int k = c0 + threadIdx.x;
+        const int b = k < n_in ? ids_in[k] : -1;
+        const int f = (b >= 0 && !st[b].done) ? 1 : 0;
+        sc[threadIdx.x] = f;
+        __syncthreads();
+        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+            const int v = threadIdx.x >= (unsigned)o ? sc[threadIdx.x - o] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (f) ids_out[base + sc[threadIdx.x] - 1] = b;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) base += sc[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_out = base;
 }
 
 // ---------------------------------------------------------------------------
@@ -708,9 +733,8 @@ __global__ void k_count_live(const CGState* st, int nb, int* out) {
 // ---------------------------------------------------------------------------
 // z += e on active instances
 __global__ void k_axpy2(double* __restrict__ xz, const double* __restrict__ ex, i64 n, double* __restrict__ yz,
-                        const double* __restrict__ ey, i64 m, const int* active) {
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
+                        const double* __restrict__ ey, i64 m, const int* ids) {
+    const int b = inst_of(ids, blockIdx.y);
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += (i64)gridDim.x * blockDim.x) {
         if (i < n) xz[(i64)b * n + i] += ex[(i64)b * n + i];
         else yz[(i64)b * m + (i - n)] += ey[(i64)b * m + (i - n)];
@@ -723,10 +747,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const
                                                      const double* __restrict__ r2, const double* __restrict__ xz,
                                                      const double* __restrict__ yz, double* __restrict__ g1,
                                                      double* __restrict__ g2, double* __restrict__ part,
-                                                     double* __restrict__ part_floor, const int* active) {
+                                                     double* __restrict__ part_floor, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
+    const int b = inst_of(ids, blockIdx.y);
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     const double* x = xz + (i64)b * S.n;
     const double* y = yz + (i64)b * S.m;
@@ -792,9 +815,9 @@ __global__ __launch_bounds__(kBlock) void k_sumsq2(const double* __restrict__ v1
 }
 
 // out[b] = sum of partials (one block per instance)
-__global__ void k_reduce_rows(const double* part, int nblk, double* out) {
+__global__ void k_reduce_rows(const double* part, int nblk, double* out, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = blockIdx.x;
+    const int b = inst_of(ids, blockIdx.x);
     const double r = reduce_parts(part + (i64)b * nblk, nblk, sh);
     if (threadIdx.x == 0) out[b] = r;
 }
