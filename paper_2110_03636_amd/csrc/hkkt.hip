@@ -235,18 +235,30 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
         std::vector<i32> tl;
         D.tri_seg.assign((size_t)S.nlevels * kTriClasses, {0, 0});
         D.tri_wg_maxnr.assign(S.nlevels, 0);
-        for (i32 l = 0; l < S.nlevels; l++)
+        // merge_classes: every supernode of a level up to 1024 rows goes to the
+        // level's largest wavefront class (one launch per level)
+        const bool merge_classes = std::getenv("HKKT_TRI_MERGE") != nullptr;
+        for (i32 l = 0; l < S.nlevels; l++) {
+            int lvmax = 0;
+            for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
+                const i32 sn = S.level_sn[q];
+                const int cl = tri_class((int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]));
+                if (cl < 5) lvmax = std::max(lvmax, cl);
+            }
             for (int cls = 0; cls < kTriClasses; cls++) {
                 const i32 off = (i32)tl.size();
                 for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
                     const i32 sn = S.level_sn[q];
                     const int nr = (int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]);
-                    if (tri_class(nr) != cls) continue;
+                    int mine = tri_class(nr);
+                    if (merge_classes && mine < 5) mine = lvmax;
+                    if (mine != cls) continue;
                     tl.push_back(sn);
                     if (cls == 5) D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
                 }
                 D.tri_seg[(size_t)l * kTriClasses + cls] = {off, (i32)tl.size() - off};
             }
+        }
         upload(D.tri_list, tl, st);
     }
     SymView& v = D.v;
@@ -379,10 +391,11 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const i32* lst = D.tri_list.as<i32>() + seg.first;
         const int cnt = seg.second;
         const unsigned nblk = (unsigned)(((i64)cnt * nids + (kBlock / kWave) - 1) / (kBlock / kWave));
+    const int kf = 3 + 16 * (l + 1), kb = 4 + 16 * (l + 1);
 #define HKKT_TRI_W(RR)                                                                                           \
-    if (fwd) LAUNCH(3, (k_fwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, UV, ids, st_, \
+    if (fwd) LAUNCH(kf, (k_fwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, UV, ids, st_, \
                     nids);                                                                                       \
-    else LAUNCH(4, (k_bwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, ids, st_, nids);
+    else LAUNCH(kb, (k_bwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, ids, st_, nids);
         switch (cls) {
             case 0: HKKT_TRI_W(1) break;
             case 1: HKKT_TRI_W(2) break;
@@ -392,8 +405,8 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
             default: {
                 const size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
                 if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
-                if (fwd) LAUNCH(3, k_fwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                else LAUNCH(4, k_bwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
+                if (fwd) LAUNCH(kf, k_fwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                else LAUNCH(kb, k_bwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
             }
         }
 #undef HKKT_TRI_W
@@ -1156,11 +1169,24 @@ int hkkt_profile_end(hkkt_ctx* c, double* ms, int64_t* launches) {
         HIPCHK(hipStreamSynchronize(c->stream));
         double t[kNProf] = {0};
         int64_t k[kNProf] = {0};
+        std::vector<double> dt(64 * 16, 0.0);
+        std::vector<int64_t> dk(64 * 16, 0);
         for (auto& r : c->prof.recs) {
             float e = 0.f;
             HIPCHK(hipEventElapsedTime(&e, c->prof.pool[r.second], c->prof.pool[r.second + 1]));
-            t[r.first] += e;
-            k[r.first]++;
+            t[r.first & 15] += e;
+            k[r.first & 15]++;
+            const int lv = std::min(r.first >> 4, 63);
+            dt[lv * 16 + (r.first & 15)] += e;
+            dk[lv * 16 + (r.first & 15)]++;
+        }
+        if (std::getenv("HKKT_PROF_DETAIL")) {
+            for (int lv = 1; lv < 64; lv++)
+                for (int kk = 0; kk < 16; kk++)
+                    if (dk[lv * 16 + kk])
+                        std::fprintf(stderr, "hkkt-prof: class=%d level=%d launches=%lld total_ms=%.3f avg_us=%.2f\n", kk,
+                                     lv - 1, (long long)dk[lv * 16 + kk], dt[lv * 16 + kk],
+                                     1e3 * dt[lv * 16 + kk] / dk[lv * 16 + kk]);
         }
         c->prof.on = false;
         c->prof.recs.clear();
