@@ -515,23 +515,26 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
     // ---- gather lists: for every row slot of a supernode, the update-vector
     // entries of its children that map onto that row (children in order)
     {
+        if (S.UVsize >= (i64)INT32_MAX) return "update-vector workspace exceeds 2^31 entries";
         const i64 nrows = (i64)S.sn_rows.size();
-        S.ga_ptr.assign(nrows + 1, 0);
+        std::vector<i64> cnt(nrows + 1, 0);
         for (i32 s = 0; s < ns; s++) {
             const i32 p = S.sn_parent[s];
             if (p < 0) continue;
             for (i64 k = 0; k < S.sn_uvptr[s + 1] - S.sn_uvptr[s]; k++)
-                S.ga_ptr[S.sn_rowptr[p] + S.relmap[S.sn_uvptr[s] + k] + 1]++;
+                cnt[S.sn_rowptr[p] + S.relmap[S.sn_uvptr[s] + k] + 1]++;
         }
-        for (i64 r = 0; r < nrows; r++) S.ga_ptr[r + 1] += S.ga_ptr[r];
-        S.ga_idx.assign(S.ga_ptr[nrows], 0);
-        std::vector<i64> pos(S.ga_ptr.begin(), S.ga_ptr.end() - 1);
+        for (i64 r = 0; r < nrows; r++) cnt[r + 1] += cnt[r];
+        S.ga_row.assign(2 * nrows, 0);
+        for (i64 r = 0; r < nrows; r++) { S.ga_row[2 * r] = (i32)cnt[r]; S.ga_row[2 * r + 1] = (i32)(cnt[r + 1] - cnt[r]); }
+        S.ga_idx.assign(cnt[nrows], 0);
+        std::vector<i64> pos(cnt.begin(), cnt.end() - 1);
         for (i32 p = 0; p < ns; p++)
             for (i32 q = S.child_ptr[p]; q < S.child_ptr[p + 1]; q++) {
                 const i32 c = S.child_list[q];
                 for (i64 k = 0; k < S.sn_uvptr[c + 1] - S.sn_uvptr[c]; k++) {
                     const i64 slot = S.sn_rowptr[p] + S.relmap[S.sn_uvptr[c] + k];
-                    S.ga_idx[pos[slot]++] = S.sn_uvptr[c] + k;
+                    S.ga_idx[pos[slot]++] = (i32)(S.sn_uvptr[c] + k);
                 }
             }
     }

@@ -36,8 +36,8 @@ struct Symbolic {
     std::vector<i32> sn_parent;            // -1 for roots
     std::vector<i32> child_ptr, child_list;
     std::vector<i32> relmap;               // at sn_uvptr[s]+k: index of rows_below(s)[k] in rows(parent)
-    std::vector<i64> ga_ptr;               // [rows+1] per row slot of a supernode: children's update-vector
-    std::vector<i64> ga_idx;               //   entries that land on that row (UV offsets, children in order)
+    std::vector<i32> ga_row;               // [2*rows] per row slot of a supernode: (start, count) into ga_idx
+    std::vector<i32> ga_idx;               //   of its children's update-vector entries (UV offsets, children in order)
     std::vector<i32> col2sn;
 
     // levels (leaves = 0)

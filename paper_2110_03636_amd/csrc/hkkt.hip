@@ -151,26 +151,30 @@ struct DevSym {
     DBuf lev_all, lev_small, lev_big;   // supernode lists, level-major
     std::vector<i32> all_ptr, small_ptr, big_ptr;
     std::vector<int> all_maxnr, small_maxnr;
-    DBuf ga_ptr, ga_idx;
-    // triangular-solve lists per (level, size class): classes 0..4 are the
-    // wavefront kernels with R = 1,2,4,8,16 rows per lane, class 5 the
-    // work-group kernel for supernodes with more than 1024 rows
-    DBuf tri_list;
+    DBuf ga_row, ga_idx;
+    // triangular-solve lists per (level, size class): classes 0..6 are the
+    // segmented wavefront kernels (SEG, R) = (16,1) (32,1) (64,1) (64,2)
+    // (64,4) (64,8) (64,16), class 7 the work-group kernel for supernodes with
+    // more than 1024 rows
+    DBuf tri_list, tri_desc;
     std::vector<std::pair<i32, i32>> tri_seg;   // [level * kTriClasses + class] = (offset, count)
-    std::vector<int> tri_wg_maxnr;              // per level, class 5
+    std::vector<int> tri_wg_maxnr;              // per level, class 7
     SymView v{};
 };
 
 constexpr size_t kMaxLds = 65536;
-constexpr int kTriClasses = 6;
+constexpr int kTriClasses = 8;
+constexpr int kTriWG = 7;
 
 static int tri_class(int nr) {
-    if (nr <= 64) return 0;
-    if (nr <= 128) return 1;
-    if (nr <= 256) return 2;
-    if (nr <= 512) return 3;
-    if (nr <= 1024) return 4;
-    return 5;
+    if (nr <= 16) return 0;
+    if (nr <= 32) return 1;
+    if (nr <= 64) return 2;
+    if (nr <= 128) return 3;
+    if (nr <= 256) return 4;
+    if (nr <= 512) return 5;
+    if (nr <= 1024) return 6;
+    return kTriWG;
 }
 
 static int lds_rows_limit(int elem_bytes) {
@@ -229,21 +233,22 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     upload(D.lev_all, all, st);
     upload(D.lev_small, small, st);
     upload(D.lev_big, big, st);
-    upload(D.ga_ptr, S.ga_ptr, st);
+    upload(D.ga_row, S.ga_row, st);
     upload(D.ga_idx, S.ga_idx, st);
     {
         std::vector<i32> tl;
         D.tri_seg.assign((size_t)S.nlevels * kTriClasses, {0, 0});
         D.tri_wg_maxnr.assign(S.nlevels, 0);
-        // merge_classes: every supernode of a level up to 1024 rows goes to the
-        // level's largest wavefront class (one launch per level)
-        const bool merge_classes = std::getenv("HKKT_TRI_MERGE") != nullptr;
+        // supernodes of 33..1024 rows of a level share the level's largest
+        // 64-lane class (one launch); HKKT_TRI_SPLIT keeps them apart
+        const bool merge_classes = std::getenv("HKKT_TRI_SPLIT") == nullptr;
+        std::vector<TriDesc> td;
         for (i32 l = 0; l < S.nlevels; l++) {
-            int lvmax = 0;
+            int lvmax = 2;
             for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
                 const i32 sn = S.level_sn[q];
                 const int cl = tri_class((int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]));
-                if (cl < 5) lvmax = std::max(lvmax, cl);
+                if (cl < kTriWG) lvmax = std::max(lvmax, cl);
             }
             for (int cls = 0; cls < kTriClasses; cls++) {
                 const i32 off = (i32)tl.size();
@@ -251,14 +256,24 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                     const i32 sn = S.level_sn[q];
                     const int nr = (int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]);
                     int mine = tri_class(nr);
-                    if (merge_classes && mine < 5) mine = lvmax;
+                    if (merge_classes && mine >= 2 && mine < kTriWG) mine = lvmax;
                     if (mine != cls) continue;
                     tl.push_back(sn);
-                    if (cls == 5) D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
+                    TriDesc dd;
+                    dd.lptr = S.sn_lptr[sn];
+                    dd.uvptr = S.sn_uvptr[sn];
+                    dd.rp = S.sn_rowptr[sn];
+                    dd.f = S.sn_first[sn];
+                    dd.w = S.sn_first[sn + 1] - S.sn_first[sn];
+                    dd.nr = nr;
+                    dd.nchild = S.child_ptr[sn + 1] - S.child_ptr[sn];
+                    td.push_back(dd);
+                    if (cls == kTriWG) D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
                 }
                 D.tri_seg[(size_t)l * kTriClasses + cls] = {off, (i32)tl.size() - off};
             }
         }
+        upload(D.tri_desc, td, st);
         upload(D.tri_list, tl, st);
     }
     SymView& v = D.v;
@@ -272,8 +287,8 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     v.child_ptr = D.child_ptr.as<i32>();
     v.child_list = D.child_list.as<i32>();
     v.relmap = D.relmap.as<i32>();
-    v.ga_ptr = D.ga_ptr.as<i64>();
-    v.ga_idx = D.ga_idx.as<i64>();
+    v.ga_row = D.ga_row.as<i32>();
+    v.ga_idx = D.ga_idx.as<i32>();
     v.perm = D.perm.as<i32>();
     v.Lsize = S.Lsize; v.CBsize = S.CBsize; v.UVsize = S.UVsize;
     v.nnzA = S.nnzA;
@@ -389,19 +404,28 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const auto seg = D.tri_seg[(size_t)l * kTriClasses + cls];
         if (seg.second == 0) continue;
         const i32* lst = D.tri_list.as<i32>() + seg.first;
+        const TriDesc* dsc = D.tri_desc.as<TriDesc>() + seg.first;
         const int cnt = seg.second;
-        const unsigned nblk = (unsigned)(((i64)cnt * nids + (kBlock / kWave) - 1) / (kBlock / kWave));
-    const int kf = 3 + 16 * (l + 1), kb = 4 + 16 * (l + 1);
-#define HKKT_TRI_W(RR)                                                                                           \
-    if (fwd) LAUNCH(kf, (k_fwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, UV, ids, st_, \
-                    nids);                                                                                       \
-    else LAUNCH(kb, (k_bwd_w<T, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lst, cnt, L, X, ids, st_, nids);
+        const int kf = 3 + 16 * (l + 1), kb = 4 + 16 * (l + 1);
+#define HKKT_TRI_S(SEGW, RR)                                                                                      \
+    {                                                                                                             \
+        constexpr int G = kWave / SEGW;                                                                           \
+        const int npad = (nids + G - 1) / G * G;                                                                  \
+        const i64 waves = (i64)cnt * npad / G;                                                                    \
+        const unsigned nblk = (unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave));                      \
+        if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, X, \
+                        UV, ids, nids, st_);                                                                      \
+        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, X,   \
+                    ids, nids, st_);                                                                              \
+    }
         switch (cls) {
-            case 0: HKKT_TRI_W(1) break;
-            case 1: HKKT_TRI_W(2) break;
-            case 2: HKKT_TRI_W(4) break;
-            case 3: HKKT_TRI_W(8) break;
-            case 4: HKKT_TRI_W(16) break;
+            case 0: HKKT_TRI_S(16, 1) break;
+            case 1: HKKT_TRI_S(32, 1) break;
+            case 2: HKKT_TRI_S(64, 1) break;
+            case 3: HKKT_TRI_S(64, 2) break;
+            case 4: HKKT_TRI_S(64, 4) break;
+            case 5: HKKT_TRI_S(64, 8) break;
+            case 6: HKKT_TRI_S(64, 16) break;
             default: {
                 const size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
                 if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
@@ -409,7 +433,7 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
                 else LAUNCH(kb, k_bwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
             }
         }
-#undef HKKT_TRI_W
+#undef HKKT_TRI_S
     }
 }
 

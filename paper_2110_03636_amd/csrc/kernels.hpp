@@ -34,8 +34,8 @@ struct SymView {
     const i32* child_ptr;
     const i32* child_list;
     const i32* relmap;
-    const i64* ga_ptr;
-    const i64* ga_idx;
+    const i32* ga_row;   // (start, count) pairs per supernode row slot
+    const i32* ga_idx;
     const i32* perm;
     i64 Lsize, CBsize, UVsize;
     // assembly
@@ -56,6 +56,18 @@ struct SymView {
     const i64* HF_rowptr;
     const i32* HF_col;
     const i32* HF_src;
+};
+
+// Packed per-supernode description used by the wavefront triangular solves
+// (one broadcast load instead of a chain of metadata loads).
+struct TriDesc {
+    i64 lptr;    // panel offset in L storage
+    i64 uvptr;   // update-vector offset
+    i64 rp;      // first row slot (into sn_rows / ga_row)
+    i32 f;       // first column
+    i32 w;       // width
+    i32 nr;      // rows
+    i32 nchild;  // number of children (0: leaf, no gather)
 };
 
 // Per-batch numeric values (device, FP64 copies owned by the library).

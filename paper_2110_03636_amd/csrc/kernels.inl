@@ -371,121 +371,130 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// wavefront triangular solves: one wavefront per (supernode, instance), rows
-// across lanes (R rows per lane, nr <= 64 R), panel columns prefetched kChunk
-// at a time into registers (coalesced column loads), the pivot value
-// broadcast by a lane shuffle. No LDS and no work-group barriers, so many
-// small supernodes of many instances keep the memory system busy.
+// wavefront triangular solves: a wavefront is split into 64/SEG segments of
+// SEG lanes; each segment solves one (supernode, instance) task, all
+// segments of a wavefront the same supernode for consecutive instances (the
+// task space of a supernode is padded to a multiple of 64/SEG, so control
+// flow is uniform). Rows across the lanes of a segment (R rows per lane,
+// nr <= SEG*R), panel columns prefetched kChunk at a time into registers
+// (coalesced column loads), the pivot broadcast by a segment shuffle. No LDS
+// and no work-group barriers.
 // Forward: v = [x(cols); 0] + children's update vectors (pulled through the
-// per-row gather list); for each column j: y_j = v_j / L_jj, v_i -= L_ij y_j.
+// per-row gather list); for each column j: y_j = v_j / L_jj, v_i -= L_ij y_j;
+// rows below the block leave as this supernode's update vector.
 // Backward: v = [y(cols); x(rows below)]; for j = w-1..0:
-// x_j = (v_j - sum_{i>j} L_ij x_i) / L_jj with a butterfly wave sum.
+// x_j = (v_j - sum_{i>j} L_ij x_i) / L_jj with a butterfly segment sum.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_allsum(T v) {
+template <typename T, int SEG>
+__device__ __forceinline__ T seg_allsum(T v) {
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    for (int o = SEG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SEG);
     return v;
 }
 
-template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_fwd_w(SymView S, const i32* __restrict__ list, int count,
+template <typename T, int SEG, int R>
+__global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
                                                   const T* __restrict__ L, T* __restrict__ X, T* __restrict__ UV,
-                                                  const int* ids, const CGState* st, int nids) {
+                                                  const int* ids, int nids, const CGState* st) {
+    constexpr int G = kWave / SEG;
     const int lane = threadIdx.x & (kWave - 1);
-    const i64 t = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-    if (t >= (i64)count * nids) return;
-    const int q = (int)(t / nids);
-    const int b = inst_of(ids, (int)(t - (i64)q * nids));
-    if (st && st[b].done) return;
-    const i32 s = list[q];
-    const i32 f = S.sn_first[s];
-    const int w = S.sn_first[s + 1] - f;
-    const i64 rp = S.sn_rowptr[s];
-    const int nr = (int)(S.sn_rowptr[s + 1] - rp);
-    const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    const int sl = lane & (SEG - 1), seg = lane / SEG;
+    const i64 t0 = ((i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave)) * G;
+    const int q = (int)(t0 / npad);
+    if (q >= count) return;
+    const int k = (int)(t0 - (i64)q * npad) + seg;
+    bool valid = k < nids;
+    const int b = valid ? inst_of(ids, k) : 0;
+    if (valid && st && st[b].done) valid = false;
+    const TriDesc d = desc[q];
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
     T* x = X + (i64)b * S.n;
     T* uvb = UV + (i64)b * S.UVsize;
     T v[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int row = lane + kWave * r;
+        const int row = sl + SEG * r;
         T a = T(0);
-        if (row < nr) {
-            if (row < w) a = x[f + row];
-            for (i64 g = S.ga_ptr[rp + row]; g < S.ga_ptr[rp + row + 1]; g++) a += uvb[S.ga_idx[g]];
+        if (valid && row < d.nr) {
+            if (row < d.w) a = x[d.f + row];
+            if (d.nchild) {
+                const int g0 = S.ga_row[2 * (d.rp + row)], gn = S.ga_row[2 * (d.rp + row) + 1];
+                for (int g = g0; g < g0 + gn; g++) a += uvb[S.ga_idx[g]];
+            }
         }
         v[r] = a;
     }
-    for (int j0 = 0; j0 < w; j0 += kChunk) {
+    for (int j0 = 0; j0 < d.w; j0 += kChunk) {
         T lc[kChunk][R];
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++)
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const int row = lane + kWave * r;
-                lc[jj][r] = (j0 + jj < w && row < nr) ? Lb[(i64)(j0 + jj) * nr + row] : T(0);
+                const int row = sl + SEG * r;
+                lc[jj][r] = (valid && j0 + jj < d.w && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
             }
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++) {
             const int j = j0 + jj;
-            if (j < w) {
-                const int jl = j & (kWave - 1), jr = j / kWave;
+            if (j < d.w) {
+                const int jl = j & (SEG - 1), jr = j / SEG;
                 T vs = v[0], ds = lc[jj][0];
 #pragma unroll
                 for (int r = 1; r < R; r++)
                     if (r == jr) { vs = v[r]; ds = lc[jj][r]; }
-                const T yj = __shfl(vs, jl, kWave) / __shfl(ds, jl, kWave);
+                const T yj = __shfl(vs, jl, SEG) / __shfl(ds, jl, SEG);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
-                    const int row = lane + kWave * r;
+                    const int row = sl + SEG * r;
                     if (row == j) v[r] = yj;
                     else if (row > j) v[r] -= lc[jj][r] * yj;
                 }
             }
         }
     }
-    const i64 uo = S.sn_uvptr[s];
+    if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int row = lane + kWave * r;
-        if (row < w) x[f + row] = v[r];
-        else if (row < nr) uvb[uo + row - w] = v[r];
+        const int row = sl + SEG * r;
+        if (row < d.w) x[d.f + row] = v[r];
+        else if (row < d.nr) uvb[d.uvptr + row - d.w] = v[r];
     }
 }
 
-template <typename T, int R>
-__global__ __launch_bounds__(kBlock) void k_bwd_w(SymView S, const i32* __restrict__ list, int count,
-                                                  const T* __restrict__ L, T* __restrict__ X, const int* ids,
-                                                  const CGState* st, int nids) {
+template <typename T, int SEG, int R>
+__global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
+                                                  const T* __restrict__ L, T* __restrict__ X, const int* ids, int nids,
+                                                  const CGState* st) {
+    constexpr int G = kWave / SEG;
     const int lane = threadIdx.x & (kWave - 1);
-    const i64 t = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-    if (t >= (i64)count * nids) return;
-    const int q = (int)(t / nids);
-    const int b = inst_of(ids, (int)(t - (i64)q * nids));
-    if (st && st[b].done) return;
-    const i32 s = list[q];
-    const i32 f = S.sn_first[s];
-    const int w = S.sn_first[s + 1] - f;
-    const i64 rp = S.sn_rowptr[s];
-    const int nr = (int)(S.sn_rowptr[s + 1] - rp);
-    const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    const int sl = lane & (SEG - 1), seg = lane / SEG;
+    const i64 t0 = ((i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave)) * G;
+    const int q = (int)(t0 / npad);
+    if (q >= count) return;
+    const int k = (int)(t0 - (i64)q * npad) + seg;
+    bool valid = k < nids;
+    const int b = valid ? inst_of(ids, k) : 0;
+    if (valid && st && st[b].done) valid = false;
+    const TriDesc d = desc[q];
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
     T* x = X + (i64)b * S.n;
     T v[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int row = lane + kWave * r;
-        v[r] = row < w ? x[f + row] : (row < nr ? x[S.sn_rows[rp + row]] : T(0));
+        const int row = sl + SEG * r;
+        T a = T(0);
+        if (valid && row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
+        v[r] = a;
     }
-    for (int jhi = w; jhi > 0; jhi -= kChunk) {
+    for (int jhi = d.w; jhi > 0; jhi -= kChunk) {
         const int j0 = jhi > kChunk ? jhi - kChunk : 0;
         T lc[kChunk][R];
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++)
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                const int row = lane + kWave * r;
-                lc[jj][r] = (j0 + jj < jhi && row < nr) ? Lb[(i64)(j0 + jj) * nr + row] : T(0);
+                const int row = sl + SEG * r;
+                lc[jj][r] = (valid && j0 + jj < jhi && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
             }
 #pragma unroll
         for (int jj = kChunk - 1; jj >= 0; jj--) {
@@ -494,26 +503,27 @@ __global__ __launch_bounds__(kBlock) void k_bwd_w(SymView S, const i32* __restri
                 T part = T(0);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
-                    const int row = lane + kWave * r;
+                    const int row = sl + SEG * r;
                     if (row > j) part += lc[jj][r] * v[r];
                 }
-                part = wave_allsum(part);
-                const int jl = j & (kWave - 1), jr = j / kWave;
+                part = seg_allsum<T, SEG>(part);
+                const int jl = j & (SEG - 1), jr = j / SEG;
                 T vs = v[0], ds = lc[jj][0];
 #pragma unroll
                 for (int r = 1; r < R; r++)
                     if (r == jr) { vs = v[r]; ds = lc[jj][r]; }
-                const T xj = (__shfl(vs, jl, kWave) - part) / __shfl(ds, jl, kWave);
+                const T xj = (__shfl(vs, jl, SEG) - part) / __shfl(ds, jl, SEG);
 #pragma unroll
                 for (int r = 0; r < R; r++)
-                    if (lane + kWave * r == j) v[r] = xj;
+                    if (sl + SEG * r == j) v[r] = xj;
             }
         }
     }
+    if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int row = lane + kWave * r;
-        if (row < w) x[f + row] = v[r];
+        const int row = sl + SEG * r;
+        if (row < d.w) x[d.f + row] = v[r];
     }
 }
 
