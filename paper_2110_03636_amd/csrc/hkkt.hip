@@ -166,7 +166,12 @@ constexpr size_t kMaxLds = 65536;
 constexpr int kTriClasses = 8;
 constexpr int kTriWG = 7;
 
-static int tri_class(int nr) {
+// size class of a supernode for the triangular solves: wide diagonal blocks
+// (w above kWideW, default 40) go to the work-group kernel, whose 64x64
+// LDS-staged diagonal solve has a shorter dependency chain than a wavefront
+static int tri_class(int nr, int w) {
+    static const int wide = std::getenv("HKKT_TRI_WIDE") ? std::atoi(std::getenv("HKKT_TRI_WIDE")) : 40;
+    if (w > wide) return 7;
     if (nr <= 16) return 0;
     if (nr <= 32) return 1;
     if (nr <= 64) return 2;
@@ -247,7 +252,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
             int lvmax = 2;
             for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
                 const i32 sn = S.level_sn[q];
-                const int cl = tri_class((int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]));
+                const int cl = tri_class((int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]), S.sn_first[sn + 1] - S.sn_first[sn]);
                 if (cl < kTriWG) lvmax = std::max(lvmax, cl);
             }
             for (int cls = 0; cls < kTriClasses; cls++) {
@@ -255,7 +260,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                 for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
                     const i32 sn = S.level_sn[q];
                     const int nr = (int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]);
-                    int mine = tri_class(nr);
+                    int mine = tri_class(nr, S.sn_first[sn + 1] - S.sn_first[sn]);
                     if (merge_classes && mine >= 2 && mine < kTriWG) mine = lvmax;
                     if (mine != cls) continue;
                     tl.push_back(sn);

@@ -424,8 +424,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
         }
         v[r] = a;
     }
-    for (int j0 = 0; j0 < d.w; j0 += kChunk) {
-        T lc[kChunk][R];
+    // columns in chunks of kChunk; the next chunk's loads are issued before
+    // the current chunk is eliminated (two register buffers)
+    T la[kChunk][R], lb[kChunk][R];
+    auto load = [&](T (&lc)[kChunk][R], int j0) {
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++)
 #pragma unroll
@@ -433,6 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
                 const int row = sl + SEG * r;
                 lc[jj][r] = (valid && j0 + jj < d.w && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
             }
+    };
+    auto elim = [&](const T (&lc)[kChunk][R], int j0) {
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++) {
             const int j = j0 + jj;
@@ -451,6 +455,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
                 }
             }
         }
+    };
+    if (d.w > 0) load(la, 0);
+    for (int j0 = 0; j0 < d.w; j0 += 2 * kChunk) {
+        if (j0 + kChunk < d.w) load(lb, j0 + kChunk);
+        elim(la, j0);
+        if (j0 + kChunk >= d.w) break;
+        if (j0 + 2 * kChunk < d.w) load(la, j0 + 2 * kChunk);
+        elim(lb, j0 + kChunk);
     }
     if (!valid) return;
 #pragma unroll
@@ -486,20 +498,25 @@ __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __re
         if (valid && row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
         v[r] = a;
     }
-    for (int jhi = d.w; jhi > 0; jhi -= kChunk) {
-        const int j0 = jhi > kChunk ? jhi - kChunk : 0;
-        T lc[kChunk][R];
+    // columns from the last one down, in chunks [jhi - kChunk, jhi) with the
+    // next chunk's loads issued before the current chunk is processed
+    T la[kChunk][R], lb[kChunk][R];
+    auto load = [&](T (&lc)[kChunk][R], int jhi) {
+        const int j0 = jhi - kChunk;
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++)
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const int row = sl + SEG * r;
-                lc[jj][r] = (valid && j0 + jj < jhi && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
+                lc[jj][r] = (valid && j0 + jj >= 0 && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
             }
+    };
+    auto back = [&](const T (&lc)[kChunk][R], int jhi) {
+        const int j0 = jhi - kChunk;
 #pragma unroll
         for (int jj = kChunk - 1; jj >= 0; jj--) {
             const int j = j0 + jj;
-            if (j < jhi) {
+            if (j >= 0) {
                 T part = T(0);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
@@ -518,6 +535,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __re
                     if (sl + SEG * r == j) v[r] = xj;
             }
         }
+    };
+    if (d.w > 0) load(la, d.w);
+    for (int jhi = d.w; jhi > 0; jhi -= 2 * kChunk) {
+        if (jhi - kChunk > 0) load(lb, jhi - kChunk);
+        back(la, jhi);
+        if (jhi - kChunk <= 0) break;
+        if (jhi - 2 * kChunk > 0) load(la, jhi - 2 * kChunk);
+        back(lb, jhi - kChunk);
     }
     if (!valid) return;
 #pragma unroll
