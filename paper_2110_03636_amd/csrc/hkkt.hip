@@ -152,6 +152,11 @@ struct DevSym {
     std::vector<i32> all_ptr, small_ptr, big_ptr;
     std::vector<int> all_maxnr, small_maxnr;
     DBuf ga_row, ga_idx;
+    // large fronts: per level sorted by width (descending) in lev_big, child
+    // rank pair lists (front, child) and per-front (nr, w) on the host
+    DBuf big_pairs;
+    std::vector<std::vector<std::pair<i32, i32>>> big_pair_seg;   // [level][rank] = (offset, count) in pairs
+    std::vector<std::pair<int, int>> big_nrw;                     // parallel to lev_big
     // triangular-solve lists per (level, size class): classes 0..6 are the
     // segmented wavefront kernels (SEG, R) = (16,1) (32,1) (64,1) (64,2)
     // (64,4) (64,8) (64,16), class 7 the work-group kernel for supernodes with
@@ -221,6 +226,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     D.small_maxnr.clear();
     for (i32 l = 0; l < S.nlevels; l++) {
         int mx = 0, mxs = 0;
+        const size_t big0 = big.size();
         for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
             const i32 s = S.level_sn[q];
             const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
@@ -229,6 +235,10 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
             if (nr <= lds_rows) { small.push_back(s); mxs = std::max(mxs, nr); }
             else big.push_back(s);
         }
+        std::sort(big.begin() + big0, big.end(), [&](i32 a, i32 b2) {
+            const int wa = S.sn_first[a + 1] - S.sn_first[a], wb = S.sn_first[b2 + 1] - S.sn_first[b2];
+            return wa != wb ? wa > wb : a < b2;
+        });
         D.all_ptr.push_back((i32)all.size());
         D.small_ptr.push_back((i32)small.size());
         D.big_ptr.push_back((i32)big.size());
@@ -238,6 +248,32 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     upload(D.lev_all, all, st);
     upload(D.lev_small, small, st);
     upload(D.lev_big, big, st);
+    {
+        std::vector<i32> pairs;
+        D.big_pair_seg.assign(S.nlevels, {});
+        D.big_nrw.clear();
+        for (i32 s2 : big)
+            D.big_nrw.push_back({(int)(S.sn_rowptr[s2 + 1] - S.sn_rowptr[s2]), S.sn_first[s2 + 1] - S.sn_first[s2]});
+        for (i32 l = 0; l < S.nlevels; l++) {
+            int maxc = 0;
+            for (i32 q = D.big_ptr[l]; q < D.big_ptr[l + 1]; q++) {
+                const i32 s2 = big[q];
+                maxc = std::max(maxc, S.child_ptr[s2 + 1] - S.child_ptr[s2]);
+            }
+            for (int r = 0; r < maxc; r++) {
+                const i32 off = (i32)(pairs.size() / 2);
+                for (i32 q = D.big_ptr[l]; q < D.big_ptr[l + 1]; q++) {
+                    const i32 s2 = big[q];
+                    if (S.child_ptr[s2 + 1] - S.child_ptr[s2] > r) {
+                        pairs.push_back(s2);
+                        pairs.push_back(S.child_list[S.child_ptr[s2] + r]);
+                    }
+                }
+                D.big_pair_seg[l].push_back({off, (i32)(pairs.size() / 2) - off});
+            }
+        }
+        upload(D.big_pairs, pairs, st);
+    }
     upload(D.ga_row, S.ga_row, st);
     upload(D.ga_idx, S.ga_idx, st);
     {
@@ -391,8 +427,35 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
         }
         const int ns_big = D.big_ptr[l + 1] - D.big_ptr[l];
         if (ns_big > 0) {
-            LAUNCH(2, k_front_global<T>, dim3(ns_big, nb), dim3(kBlock), 0, st, D.v,
-                               D.lev_big.as<i32>() + D.big_ptr[l], L, CB, B.fail.as<int>(), active);
+            const i32* fr = D.lev_big.as<i32>() + D.big_ptr[l];
+            const auto* nrw = D.big_nrw.data() + D.big_ptr[l];
+            i64 maxcb = 0;
+            int maxw = 0;
+            for (int q = 0; q < ns_big; q++) {
+                maxcb = std::max<i64>(maxcb, (i64)(nrw[q].first - nrw[q].second) * (nrw[q].first - nrw[q].second));
+                maxw = std::max(maxw, nrw[q].second);
+            }
+            LAUNCH(2, k_big_zero<T>, dim3(grid1(maxcb, 512), ns_big, nb), dim3(kBlock), 0, st, D.v, fr, CB, active);
+            for (const auto& seg : D.big_pair_seg[l]) {
+                // children of any size: bound the grid by the largest front's CB
+                LAUNCH(2, k_big_extend<T>, dim3(grid1(maxcb, 512), seg.second, nb), dim3(kBlock), 0, st, D.v,
+                       D.big_pairs.as<i32>() + 2 * seg.first, L, CB, active);
+            }
+            for (int kb = 0; kb < maxw; kb += kNB) {
+                int cnt = 0, maxrows = 0;
+                for (int q = 0; q < ns_big && nrw[q].second > kb; q++) {
+                    cnt++;
+                    maxrows = std::max(maxrows, nrw[q].first - kb - std::min(kNB, nrw[q].second - kb));
+                }
+                LAUNCH(2, k_big_potrf<T>, dim3(1, cnt, nb), dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(),
+                       active);
+                if (maxrows <= 0) continue;
+                LAUNCH(2, k_big_trsm<T>, dim3((maxrows + kBlock - 1) / kBlock, cnt, nb), dim3(kBlock), 0, st, D.v, fr,
+                       kb, L, CB, active);
+                const int nt = (maxrows + kTile - 1) / kTile;
+                LAUNCH(2, k_big_update<T>, dim3(nt * (nt + 1) / 2, cnt, nb), dim3(kBlock), 0, st, D.v, fr, kb, L, CB,
+                       active);
+            }
         }
     }
 }

@@ -254,6 +254,218 @@ __global__ __launch_bounds__(kBlock) void k_front_global(SymView S, const i32* _
 }
 
 // ---------------------------------------------------------------------------
+// Blocked partial factorization of large fronts (above the LDS limit), one
+// step per NB = 32 columns, all large fronts of a level and all instances in
+// the same launches (grid.y = front, grid.z = instance):
+//   k_big_zero    clear the fronts' contribution blocks
+//   k_big_extend  add the children's contribution blocks (one child rank per
+//                 launch, so two children never write one front at once)
+//   k_big_potrf   Cholesky of the NB x NB diagonal block in LDS
+//   k_big_trsm    L21 = A21 L11^{-T}, one thread per row
+//   k_big_update  trailing SYRK/GEMM C -= L21 L21^T on 64 x 64 lower tiles
+//                 with MFMA (v_mfma_*_16x16x4: A lane i+16k, B lane j+16k,
+//                 D lane j+16(i/4), register i%4)
+// ---------------------------------------------------------------------------
+constexpr int kNB = 32;
+constexpr int kTile = 64;
+
+template <typename T>
+__device__ __forceinline__ FrontRef<T> front_of(const SymView& S, i32 s, int b, T* L, T* CB) {
+    FrontRef<T> F;
+    const i32 f = S.sn_first[s];
+    F.w = S.sn_first[s + 1] - f;
+    F.nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+    F.nc = F.nr - F.w;
+    F.P = L + (i64)b * S.Lsize + S.sn_lptr[s];
+    F.C = CB + (i64)b * S.CBsize + S.sn_cbptr[s];
+    return F;
+}
+
+template <typename T>
+__global__ void k_big_zero(SymView S, const i32* __restrict__ fronts, T* __restrict__ CB, const int* active) {
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const i32 s = fronts[blockIdx.y];
+    const i64 nc = (S.sn_rowptr[s + 1] - S.sn_rowptr[s]) - (S.sn_first[s + 1] - S.sn_first[s]);
+    T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[s];
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nc * nc; i += (i64)gridDim.x * blockDim.x) C[i] = T(0);
+}
+
+// pairs[2q] = front, pairs[2q+1] = its child of the launch's rank
+template <typename T>
+__global__ void k_big_extend(SymView S, const i32* __restrict__ pairs, T* __restrict__ L, T* __restrict__ CB,
+                             const int* active) {
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const i32 s = pairs[2 * blockIdx.y], c = pairs[2 * blockIdx.y + 1];
+    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
+    const int wc = S.sn_first[c + 1] - S.sn_first[c];
+    const i64 ncc = (S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
+    const i32* rel = S.relmap + S.sn_uvptr[c];
+    const T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[c];
+    for (i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x; idx < ncc * ncc; idx += (i64)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / ncc), i = (int)(idx - (i64)j * ncc);
+        if (i >= j) F.at(rel[i], rel[j]) += C[idx];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_big_potrf(SymView S, const i32* __restrict__ fronts, int kb,
+                                                      T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
+                                                      const int* active) {
+    __shared__ T D[kNB][kNB + 1];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const i32 s = fronts[blockIdx.y];
+    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
+    const int bw = min(kNB, F.w - kb);
+    for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
+        const int j = idx / bw, i = idx - j * bw;
+        D[j][i] = i >= j ? F.P[(i64)(kb + j) * F.nr + kb + i] : T(0);
+    }
+    __syncthreads();
+    const i32 f = S.sn_first[s];
+    T dprev = T(1);
+    for (int k = 0; k <= bw; k++) {
+        const T dk = k < bw ? D[k][k] : T(1);
+        if (k > 0) {
+            const int kk = k - 1;
+            const T sq = sqrt(dprev), inv = T(1) / sq;
+            for (int i = kk + threadIdx.x; i < bw; i += blockDim.x) D[kk][i] = i == kk ? sq : D[kk][i] * inv;
+        }
+        if (k < bw) {
+            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b], f + kb + k);
+            const T invd = T(1) / dk;
+            const int len = bw - k - 1;
+            for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
+                const int jj = idx / len, ii = idx - jj * len;
+                if (ii >= jj) D[k + 1 + jj][k + 1 + ii] -= D[k][k + 1 + ii] * D[k][k + 1 + jj] * invd;
+            }
+        }
+        dprev = dk;
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
+        const int j = idx / bw, i = idx - j * bw;
+        if (i >= j) F.P[(i64)(kb + j) * F.nr + kb + i] = D[j][i];
+    }
+}
+
+// rows below the diagonal block: x L11^T = a  (one thread per row)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_big_trsm(SymView S, const i32* __restrict__ fronts, int kb,
+                                                     T* __restrict__ L, T* __restrict__ CB, const int* active) {
+    __shared__ T D[kNB][kNB + 1];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const i32 s = fronts[blockIdx.y];
+    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
+    const int bw = min(kNB, F.w - kb);
+    const int row = kb + bw + blockIdx.x * blockDim.x + threadIdx.x;
+    if (kb + bw + (int)(blockIdx.x * blockDim.x) >= F.nr) return;   // whole block past the front
+    for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
+        const int j = idx / bw, i = idx - j * bw;
+        D[j][i] = F.P[(i64)(kb + j) * F.nr + kb + i];
+    }
+    __syncthreads();
+    if (row >= F.nr) return;
+    T x[kNB];
+#pragma unroll
+    for (int k = 0; k < kNB; k++) x[k] = k < bw ? F.P[(i64)(kb + k) * F.nr + row] : T(0);
+#pragma unroll
+    for (int k = 0; k < kNB; k++) {
+        if (k < bw) {
+            T a = x[k];
+#pragma unroll
+            for (int m = 0; m < kNB; m++)
+                if (m < k) a -= x[m] * D[m][k];
+            x[k] = a / D[k][k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kNB; k++)
+        if (k < bw) F.P[(i64)(kb + k) * F.nr + row] = x[k];
+}
+
+template <typename T>
+struct MfmaT;
+template <>
+struct MfmaT<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MfmaT<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// trailing update of the rows/columns >= kb + NB: tile (ti, tj), ti >= tj,
+// of 64 x 64; four wavefronts, each a 32 x 32 quarter as 2 x 2 MFMA blocks
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __restrict__ fronts, int kb,
+                                                       T* __restrict__ L, T* __restrict__ CB, const int* active) {
+    __shared__ T Ai[kTile][kNB + 1];
+    __shared__ T Aj[kTile][kNB + 1];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const i32 s = fronts[blockIdx.y];
+    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
+    const int bw = min(kNB, F.w - kb);
+    const int r0 = kb + bw;
+    const int nt = (F.nr - r0 + kTile - 1) / kTile;
+    const int lin = blockIdx.x;
+    if (lin >= nt * (nt + 1) / 2) return;
+    int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= lin) ti++;
+    while (ti * (ti + 1) / 2 > lin) ti--;
+    const int tj = lin - ti * (ti + 1) / 2;
+    const int i0 = r0 + ti * kTile, j0 = r0 + tj * kTile;
+    for (int idx = threadIdx.x; idx < kTile * kNB; idx += blockDim.x) {
+        const int k = idx / kTile, r = idx - k * kTile;
+        const bool ok = k < bw;
+        Ai[r][k] = (ok && i0 + r < F.nr) ? F.P[(i64)(kb + k) * F.nr + i0 + r] : T(0);
+        Aj[r][k] = (ok && j0 + r < F.nr) ? F.P[(i64)(kb + k) * F.nr + j0 + r] : T(0);
+    }
+    __syncthreads();
+    typedef typename MfmaT<T>::v4 v4;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int qi = (wv >> 1) * 32, qj = (wv & 1) * 32;
+    v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 2; c++) acc[a][c] = v4{T(0), T(0), T(0), T(0)};
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int k4 = 0; k4 < kNB; k4 += 4) {
+        T av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++) av[a] = Ai[qi + 16 * a + li][k4 + lk];
+#pragma unroll
+        for (int c = 0; c < 2; c++) bv[c] = Aj[qj + 16 * c + li][k4 + lk];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) acc[a][c] = MfmaT<T>::mma(av[a], bv[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = i0 + qi + 16 * a + 4 * (lane >> 4) + r;
+                const int j = j0 + qj + 16 * c + (lane & 15);
+                if (i < F.nr && j < F.nr && i >= j) F.at(i, j) -= acc[a][c][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // supernodal triangular solves, one work-group per (supernode, instance) of a
 // level. Forward (L y = b), multifrontal form: each supernode gathers its
 // children's update vectors (the amount to subtract at their rows below),
