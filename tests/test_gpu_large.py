@@ -1,0 +1,51 @@
+"""Full-size runs (n_x = 500,000): residual-only parity. The oracle's own
+FP64 KKT residual (O(nnz) on the CPU) judges the GPU solution; the paper's
+qualitative result that CG iterations fall as gamma grows (Sec. 5.1,
+Theorem 4) is checked on the same systems."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_03636_amd import hkkt, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def grid500k_fp64():
+    return synth.workload(2)          # gamma in {1e4, 1e6, 1e8}, D_x = 10^U(-8,8)
+
+
+def _check(b, x, y, infos, tol):
+    out = []
+    for i in range(b.nb):
+        o = oracle.System.from_batch(b, i)
+        rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
+        out.append((rr, fl))
+        assert rr <= max(tol, 20 * fl), (i, rr, fl, infos[i])
+        assert abs(infos[i]["rr"] - rr) <= 1e-3 * rr + 2 * fl
+    return out
+
+
+def test_workload2_fp64_gamma_sweep(grid500k_fp64):
+    b = grid500k_fp64
+    s = hkkt.Solver(precision="fp64", kkt_tol=1e-10)
+    s.analyze(b.pattern)
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check(b, x, y, infos, 1e-10)
+    its = [i["cg_iters"] / i["passes"] for i in infos]
+    assert its[1] <= its[0] + 1 and its[2] <= its[1] + 1, its
+    for i in range(b.nb):
+        assert s.inertia(i) == (500_000, 250_000, 0)
+
+
+def test_workload3_mixed():
+    b = synth.workload(3)             # D_x = 10^U(-6,6), mixed precision
+    s = hkkt.Solver(precision="mixed", kkt_tol=1e-10)
+    s.analyze(b.pattern)
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check(b, x, y, infos, 1e-10)

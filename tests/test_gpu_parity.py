@@ -123,6 +123,30 @@ def test_solve_workload1_equals_oracle(kkt_tol):
     assert s.inertia(0) == io["inertia"] == (1200, 600, 0)
 
 
+def test_solve_workload1_mixed_large_fronts():
+    """FP32 blocked large-front factor (MFMA trailing updates) inside the
+    mixed path: the refined solution still meets 1e-10."""
+    b = synth.workload(1)
+    s = _solver(b, precision="mixed")
+    assert s.stats()["max_rows"] > 128          # fronts beyond the LDS kernel
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
+
+
+def test_factor_fp32_large_fronts_close_to_oracle():
+    b = H.tiny_dense_like(900, 25, dx_exp=1.0, gamma=10.0)
+    o = oracle.System.from_batch(b)
+    pmd = o.order_mindeg()
+    s = _solver(b, precision="mixed", perm=pmd)
+    assert s.stats()["max_rows"] > 128
+    rc, st, fc = s.factor_batch(b)
+    assert rc == 0
+    cp, ri, v = s.factor_csc(0)
+    got = _lower_in_original(cp, ri, v, s.perm(), b.pattern.n_x)
+    assert _col_err(got, _oracle_L(b, pmd)) < 1e-3
+
+
 def test_solve_batch_grid_fp64():
     b = synth.grid_like(3000, nb=5, seed=31, gammas=(1e4, 1e6), dx_exp=8.0)
     s = _solver(b)
