@@ -263,8 +263,9 @@ __global__ __launch_bounds__(kBlock) void k_front_global(SymView S, const i32* _
 //   k_big_potrf   Cholesky of the NB x NB diagonal block in LDS
 //   k_big_trsm    L21 = A21 L11^{-T}, one thread per row
 //   k_big_update  trailing SYRK/GEMM C -= L21 L21^T on 64 x 64 lower tiles
-//                 with MFMA (v_mfma_*_16x16x4: A lane i+16k, B lane j+16k,
-//                 D lane j+16(i/4), register i%4)
+//                 with MFMA (v_mfma_*_16x16x4: A[i][k] in lane i+16k,
+//                 B[k][j] in lane j+16k; D[i][j] in lane j+16q, register r
+//                 with i = 4q+r for f32 and i = q+4r for f64, as measured)
 // ---------------------------------------------------------------------------
 constexpr int kNB = 32;
 constexpr int kTile = 64;
@@ -395,6 +396,7 @@ struct MfmaT<double> {
     static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 template <>
 struct MfmaT<float> {
@@ -402,6 +404,7 @@ struct MfmaT<float> {
     static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 // trailing update of the rows/columns >= kb + NB: tile (ti, tj), ti >= tj,
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __r
         for (int c = 0; c < 2; c++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int i = i0 + qi + 16 * a + 4 * (lane >> 4) + r;
+                const int i = i0 + qi + 16 * a + MfmaT<T>::row(lane, r);
                 const int j = j0 + qj + 16 * c + (lane & 15);
                 if (i < F.nr && j < F.nr && i >= j) F.at(i, j) -= acc[a][c][r];
             }
