@@ -71,15 +71,17 @@ typedef struct {
     int precision;          /* HKKT_FP64 or HKKT_MIXED (FP32 factor + solves, FP64 refinement) */
     int pointer_mode;       /* HKKT_PTR_HOST or HKKT_PTR_DEVICE */
     double cg_tol;          /* relative CG residual, Sec. 5.1 uses 1e-12 */
-    double cg_tol_mixed;    /* inner CG tolerance when the operator is FP32 (default 1e-7) */
+    double cg_tol_mixed;    /* inner CG tolerance when the operator is FP32 (default 1e-5) */
     double kkt_tol;         /* target relative KKT residual ||r - K z||_2 / ||r||_2 */
     double quad_form_eps;   /* breakdown if p'q <= eps*||p||^2*(p0'q0/||p0||^2) (default 1e-14) */
     double delta2;          /* 0: report CG_BREAKDOWN; > 0: restart CG on S + delta2*I (Algorithm 1) */
     int max_cg;             /* <= 0: min(m, 1000) */
     int max_refine;         /* refinement passes after the first (default 10) */
     int ordering;           /* 0 = own approximate minimum degree (Sec. 5.3), 1 = natural */
-    int relax;              /* supernode amalgamation: 0 none (fundamental), 1 default */
-    int reserved[6];
+    int relax;              /* supernode amalgamation: 0 none (fundamental), 1 default, 2 more */
+    int deterministic;      /* 1: forward solves pull children's update vectors in a fixed order
+                               (bitwise reproducible); 0: right-looking FP atomics (faster) */
+    int reserved[5];
 } hkkt_options;
 
 typedef struct {
@@ -93,9 +95,9 @@ typedef struct {
     int64_t fail_col;       /* first failing pivot (original index) or -1 */
 } hkkt_info;
 
-/* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-7,
+/* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
- * ordering 0, relax 1. */
+ * ordering 0, relax 1, deterministic 0. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream

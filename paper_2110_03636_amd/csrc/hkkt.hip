@@ -468,6 +468,7 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
     const T* L = B.L.as<T>();
     T* X = B.X.as<T>();
     T* UV = B.UV.as<T>();
+    const bool push = c->opt.deterministic == 0;
     for (int cls = 0; cls < kTriClasses; cls++) {
         const auto seg = D.tri_seg[(size_t)l * kTriClasses + cls];
         if (seg.second == 0) continue;
@@ -481,8 +482,10 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const int npad = (nids + G - 1) / G * G;                                                                  \
         const i64 waves = (i64)cnt * npad / G;                                                                    \
         const unsigned nblk = (unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave));                      \
-        if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, X, \
-                        UV, ids, nids, st_);                                                                      \
+        if (fwd && push) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, true>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, \
+                                cnt, npad, L, X, UV, ids, nids, st_);                                             \
+        else if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, false>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, \
+                             npad, L, X, UV, ids, nids, st_);                                                     \
         else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, X,   \
                     ids, nids, st_);                                                                              \
     }
@@ -497,7 +500,8 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
             default: {
                 const size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
                 if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
-                if (fwd) LAUNCH(kf, k_fwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                if (fwd && push) LAUNCH(kf, (k_fwd<T, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                else if (fwd) LAUNCH(kf, (k_fwd<T, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
                 else LAUNCH(kb, k_bwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
             }
         }
@@ -799,7 +803,7 @@ void hkkt_default_options(hkkt_options* o) {
     o->precision = HKKT_FP64;
     o->pointer_mode = HKKT_PTR_HOST;
     o->cg_tol = 1e-12;
-    o->cg_tol_mixed = 1e-7;
+    o->cg_tol_mixed = 1e-5;
     o->kkt_tol = 1e-10;
     o->quad_form_eps = 1e-14;
     o->delta2 = 0.0;
@@ -807,6 +811,7 @@ void hkkt_default_options(hkkt_options* o) {
     o->max_refine = 10;
     o->ordering = 0;
     o->relax = 1;
+    o->deterministic = 0;
 }
 
 #define ABI_GUARD(ctx, ...)                                              \

@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __r
 // The diagonal block is staged in LDS in kTri x kTri tiles and solved by one
 // wavefront with lane shuffles.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool PUSH>
 __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
                                                 T* __restrict__ X, T* __restrict__ UV, const int* ids,
                                                 const CGState* st) {
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
     T* uvb = UV + (i64)b * S.UVsize;
     for (int i = threadIdx.x; i < nr; i += blockDim.x) u[i] = i < w ? x[f + i] : T(0);
     __syncthreads();
-    for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; q++) {
+    for (int q = S.child_ptr[s]; !PUSH && q < S.child_ptr[s + 1]; q++) {
         const i32 c = S.child_list[q];
         const int wc = S.sn_first[c + 1] - S.sn_first[c];
         const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
@@ -533,6 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
     }
     for (int i = threadIdx.x; i < nr; i += blockDim.x) {
         if (i < w) x[f + i] = u[i];
+        else if (PUSH) unsafeAtomicAdd(&x[S.sn_rows[S.sn_rowptr[s] + i]], u[i]);
         else uvb[S.sn_uvptr[s] + (i - w)] = u[i];
     }
 }
@@ -607,7 +608,11 @@ __device__ __forceinline__ T seg_allsum(T v) {
     return v;
 }
 
-template <typename T, int SEG, int R>
+// PUSH = false: children's update vectors are pulled through the gather list
+// (deterministic). PUSH = true: the rows below the diagonal block are added
+// straight into the ancestors' right-hand-side entries with FP atomics
+// (right-looking; order of the additions not fixed).
+template <typename T, int SEG, int R, bool PUSH>
 __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
                                                   const T* __restrict__ L, T* __restrict__ X, T* __restrict__ UV,
                                                   const int* ids, int nids, const CGState* st) {
@@ -630,19 +635,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
     for (int r = 0; r < R; r++) {
         const int row = sl + SEG * r;
         T a = T(0);
-        if (valid && row < d.nr) {
-            if (row < d.w) a = x[d.f + row];
-            if (d.nchild) {
-                const int g0 = S.ga_row[2 * (d.rp + row)], gn = S.ga_row[2 * (d.rp + row) + 1];
-                for (int g = g0; g < g0 + gn; g++) a += uvb[S.ga_idx[g]];
-            }
+        if (valid && row < d.w) a = x[d.f + row];
+        if (!PUSH && valid && row < d.nr && d.nchild) {
+            const int g0 = S.ga_row[2 * (d.rp + row)], gn = S.ga_row[2 * (d.rp + row) + 1];
+            for (int g = g0; g < g0 + gn; g++) a += uvb[S.ga_idx[g]];
         }
         v[r] = a;
     }
-    // columns in chunks of kChunk; the next chunk's loads are issued before
-    // the current chunk is eliminated (two register buffers)
-    T la[kChunk][R], lb[kChunk][R];
-    auto load = [&](T (&lc)[kChunk][R], int j0) {
+    for (int j0 = 0; j0 < d.w; j0 += kChunk) {
+        T lc[kChunk][R];
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++)
 #pragma unroll
@@ -650,8 +651,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
                 const int row = sl + SEG * r;
                 lc[jj][r] = (valid && j0 + jj < d.w && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
             }
-    };
-    auto elim = [&](const T (&lc)[kChunk][R], int j0) {
 #pragma unroll
         for (int jj = 0; jj < kChunk; jj++) {
             const int j = j0 + jj;
@@ -670,21 +669,16 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
                 }
             }
         }
-    };
-    if (d.w > 0) load(la, 0);
-    for (int j0 = 0; j0 < d.w; j0 += 2 * kChunk) {
-        if (j0 + kChunk < d.w) load(lb, j0 + kChunk);
-        elim(la, j0);
-        if (j0 + kChunk >= d.w) break;
-        if (j0 + 2 * kChunk < d.w) load(la, j0 + 2 * kChunk);
-        elim(lb, j0 + kChunk);
     }
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int row = sl + SEG * r;
         if (row < d.w) x[d.f + row] = v[r];
-        else if (row < d.nr) uvb[d.uvptr + row - d.w] = v[r];
+        else if (row < d.nr) {
+            if (PUSH) unsafeAtomicAdd(&x[S.sn_rows[d.rp + row]], v[r]);
+            else uvb[d.uvptr + row - d.w] = v[r];
+        }
     }
 }
 

@@ -38,7 +38,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("pointer_mode", C.c_int), ("cg_tol", C.c_double),
                 ("cg_tol_mixed", C.c_double), ("kkt_tol", C.c_double), ("quad_form_eps", C.c_double),
                 ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
-                ("ordering", C.c_int), ("relax", C.c_int), ("reserved", C.c_int * 6)]
+                ("ordering", C.c_int), ("relax", C.c_int), ("deterministic", C.c_int),
+                ("reserved", C.c_int * 5)]
 
 
 class Info(C.Structure):

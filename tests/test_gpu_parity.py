@@ -282,3 +282,21 @@ def test_full_size_batch_sampled():
         rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
         assert rr <= max(1e-10, 20 * fl), (i, rr, fl, infos[i])
         assert infos[i]["status"] == 0
+
+
+def test_deterministic_and_atomic_forward_agree():
+    """The pull (deterministic) and push (FP atomics) forward solves give the
+    same solution up to rounding; the pull mode is bitwise reproducible."""
+    b = synth.grid_like(3000, nb=3, seed=38, gammas=(1e4, 1e6), dx_exp=8.0)
+    out = {}
+    for det in (1, 0):
+        s = _solver(b, deterministic=det)
+        s.factor_batch(b)
+        rc, x, y, infos = s.solve(b.r1, b.r2)
+        _check_solution(b, x, y, infos)
+        out[det] = np.concatenate([x, y], axis=1)
+        if det:
+            rc, x2, y2, _ = s.solve(b.r1, b.r2)
+            assert np.array_equal(np.concatenate([x2, y2], axis=1), out[1])
+    d = np.linalg.norm(out[0] - out[1], axis=1) / np.linalg.norm(out[1], axis=1)
+    assert d.max() < 1e-6, d
