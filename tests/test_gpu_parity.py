@@ -172,11 +172,12 @@ def test_solve_batch_mixed_reaches_target():
 
 def test_device_pointers_match_host():
     torch = pytest.importorskip("torch")
+    # bitwise comparison: the deterministic (pull) forward solve
     b = synth.grid_like(2500, nb=3, seed=33, gammas=(1e4,), dx_exp=6.0)
-    sh = _solver(b)
+    sh = _solver(b, deterministic=1)
     sh.factor_batch(b)
     _, xh, yh, _ = sh.solve(b.r1, b.r2)
-    sd = hkkt.Solver(precision="fp64", device=True)
+    sd = hkkt.Solver(precision="fp64", device=True, deterministic=1)
     sd.analyze(b.pattern)
     t = lambda a: torch.as_tensor(a, device="cuda")
     rc, st, fc = sd.factor(t(b.H_val), t(b.D_x), t(b.J_val), b.delta, b.gamma)
