@@ -151,7 +151,7 @@ struct DevSym {
     DBuf lev_all, lev_small, lev_big;   // supernode lists, level-major
     std::vector<i32> all_ptr, small_ptr, big_ptr;
     std::vector<int> all_maxnr, small_maxnr;
-    DBuf ga_row, ga_idx;
+    DBuf ga_row, ga_idx, diag_off;
     // large fronts: per level sorted by width (descending) in lev_big, child
     // rank pair lists (front, child) and per-front (nr, w) on the host
     DBuf big_pairs;
@@ -277,6 +277,17 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     upload(D.ga_row, S.ga_row, st);
     upload(D.ga_idx, S.ga_idx, st);
     {
+        std::vector<i64> doff(S.n);
+        for (i32 s2 = 0; s2 < S.ns; s2++) {
+            const i64 nr = S.sn_rowptr[s2 + 1] - S.sn_rowptr[s2];
+            for (i32 j = S.sn_first[s2]; j < S.sn_first[s2 + 1]; j++) {
+                const i64 jj = j - S.sn_first[s2];
+                doff[j] = S.sn_lptr[s2] + jj * nr + jj;
+            }
+        }
+        upload(D.diag_off, doff, st);
+    }
+    {
         std::vector<i32> tl;
         D.tri_seg.assign((size_t)S.nlevels * kTriClasses, {0, 0});
         D.tri_wg_maxnr.assign(S.nlevels, 0);
@@ -358,8 +369,8 @@ struct Batch {
     int prec = HKKT_FP64;   // precision of L / triangular solves
     // values (FP64)
     DBuf H, J, JT, HF, Dx, Dxp, delta, gamma;
-    // factor
-    DBuf L, CB, fail;
+    // factor (Dinv: reciprocals of the diagonal of L, per column)
+    DBuf L, CB, fail, Dinv;
     // solve workspace
     DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
@@ -458,6 +469,8 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
             }
         }
     }
+    LAUNCH(10, k_inv_diag<T>, dim3(grid1(S.n, 1024), nb), dim3(kBlock), 0, st, D.diag_off.as<i64>(), (i64)S.n,
+           (i64)S.Lsize, (const T*)L, B.Dinv.as<T>(), active);
 }
 
 // X <- H_gamma^{-1} X (in place) for the nids instances listed in ids;
@@ -466,6 +479,7 @@ template <typename T>
 static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* ids, int nids, const CGState* st_) {
     const DevSym& D = c->dev;
     const T* L = B.L.as<T>();
+    const T* Dv = B.Dinv.as<T>();
     T* X = B.X.as<T>();
     T* UV = B.UV.as<T>();
     const bool push = c->opt.deterministic == 0;
@@ -483,11 +497,11 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const i64 waves = (i64)cnt * npad / G;                                                                    \
         const unsigned nblk = (unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave));                      \
         if (fwd && push) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, true>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, \
-                                cnt, npad, L, X, UV, ids, nids, st_);                                             \
+                                cnt, npad, L, Dv, X, UV, ids, nids, st_);                                         \
         else if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, false>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, \
-                             npad, L, X, UV, ids, nids, st_);                                                     \
-        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, X,   \
-                    ids, nids, st_);                                                                              \
+                             npad, L, Dv, X, UV, ids, nids, st_);                                                 \
+        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, Dv,  \
+                    X, ids, nids, st_);                                                                           \
     }
         switch (cls) {
             case 0: HKKT_TRI_S(16, 1) break;
@@ -535,6 +549,7 @@ static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {
 static void alloc_factor(hkkt_ctx* c, Batch& B) {
     const Symbolic& S = c->sym.S;
     B.L.ensure((size_t)B.nb * std::max<i64>(1, S.Lsize) * B.esz());
+    B.Dinv.ensure((size_t)B.nb * S.n * B.esz());
     B.CB.ensure((size_t)B.nb * std::max<i64>(1, S.CBsize) * B.esz());
 }
 

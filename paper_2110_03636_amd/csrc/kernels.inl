@@ -601,6 +601,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
 // Backward: v = [y(cols); x(rows below)]; for j = w-1..0:
 // x_j = (v_j - sum_{i>j} L_ij x_i) / L_jj with a butterfly segment sum.
 // ---------------------------------------------------------------------------
+// panel columns fetched per memory round trip: 32 FP32 / 16 FP64 columns
+// with one row per lane, fewer as rows per lane grow (register budget)
+template <typename T, int R>
+__host__ __device__ constexpr int chunk_cols() {
+    return R == 1 ? (sizeof(T) == 4 ? 32 : 16) : (R == 2 ? 16 : 8);
+}
+
 template <typename T, int SEG>
 __device__ __forceinline__ T seg_allsum(T v) {
 #pragma unroll
@@ -614,9 +621,11 @@ __device__ __forceinline__ T seg_allsum(T v) {
 // (right-looking; order of the additions not fixed).
 template <typename T, int SEG, int R, bool PUSH>
 __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
-                                                  const T* __restrict__ L, T* __restrict__ X, T* __restrict__ UV,
-                                                  const int* ids, int nids, const CGState* st) {
+                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
+                                                  const CGState* st) {
     constexpr int G = kWave / SEG;
+    constexpr int CH = chunk_cols<T, R>();
     const int lane = threadIdx.x & (kWave - 1);
     const int sl = lane & (SEG - 1), seg = lane / SEG;
     const i64 t0 = ((i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave)) * G;
@@ -628,44 +637,50 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
     if (valid && st && st[b].done) valid = false;
     const TriDesc d = desc[q];
     const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
     T* uvb = UV + (i64)b * S.UVsize;
-    T v[R];
+    T v[R], di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int row = sl + SEG * r;
-        T a = T(0);
-        if (valid && row < d.w) a = x[d.f + row];
+        T a = T(0), e = T(0);
+        if (valid && row < d.w) {
+            a = x[d.f + row];
+            e = dinv[row];
+        }
         if (!PUSH && valid && row < d.nr && d.nchild) {
             const int g0 = S.ga_row[2 * (d.rp + row)], gn = S.ga_row[2 * (d.rp + row) + 1];
             for (int g = g0; g < g0 + gn; g++) a += uvb[S.ga_idx[g]];
         }
         v[r] = a;
+        di[r] = e;
     }
-    for (int j0 = 0; j0 < d.w; j0 += kChunk) {
-        T lc[kChunk][R];
+    for (int j0 = 0; j0 < d.w; j0 += CH) {
+        T lc[CH][R];
 #pragma unroll
-        for (int jj = 0; jj < kChunk; jj++)
+        for (int jj = 0; jj < CH; jj++)
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const int row = sl + SEG * r;
-                lc[jj][r] = (valid && j0 + jj < d.w && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
+                lc[jj][r] = (valid && j0 + jj < d.w && row > j0 + jj && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row]
+                                                                                     : T(0);
             }
 #pragma unroll
-        for (int jj = 0; jj < kChunk; jj++) {
+        for (int jj = 0; jj < CH; jj++) {
             const int j = j0 + jj;
             if (j < d.w) {
                 const int jl = j & (SEG - 1), jr = j / SEG;
-                T vs = v[0], ds = lc[jj][0];
+                T vs = v[0], es = di[0];
 #pragma unroll
                 for (int r = 1; r < R; r++)
-                    if (r == jr) { vs = v[r]; ds = lc[jj][r]; }
-                const T yj = __shfl(vs, jl, SEG) / __shfl(ds, jl, SEG);
+                    if (r == jr) { vs = v[r]; es = di[r]; }
+                const T yj = __shfl(vs, jl, SEG) * __shfl(es, jl, SEG);
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const int row = sl + SEG * r;
                     if (row == j) v[r] = yj;
-                    else if (row > j) v[r] -= lc[jj][r] * yj;
+                    else v[r] -= lc[jj][r] * yj;      // zero below-diagonal mask for rows <= j
                 }
             }
         }
@@ -684,9 +699,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
 
 template <typename T, int SEG, int R>
 __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
-                                                  const T* __restrict__ L, T* __restrict__ X, const int* ids, int nids,
-                                                  const CGState* st) {
+                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  T* __restrict__ X, const int* ids, int nids, const CGState* st) {
     constexpr int G = kWave / SEG;
+    constexpr int CH = chunk_cols<T, R>();
     const int lane = threadIdx.x & (kWave - 1);
     const int sl = lane & (SEG - 1), seg = lane / SEG;
     const i64 t0 = ((i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave)) * G;
@@ -698,60 +714,49 @@ __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __re
     if (valid && st && st[b].done) valid = false;
     const TriDesc d = desc[q];
     const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
-    T v[R];
+    T v[R], di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int row = sl + SEG * r;
-        T a = T(0);
+        T a = T(0), e = T(0);
         if (valid && row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
+        if (valid && row < d.w) e = dinv[row];
         v[r] = a;
+        di[r] = e;
     }
-    // columns from the last one down, in chunks [jhi - kChunk, jhi) with the
-    // next chunk's loads issued before the current chunk is processed
-    T la[kChunk][R], lb[kChunk][R];
-    auto load = [&](T (&lc)[kChunk][R], int jhi) {
-        const int j0 = jhi - kChunk;
+    // columns from the last one down in chunks [jhi - CH, jhi)
+    for (int jhi = d.w; jhi > 0; jhi -= CH) {
+        const int j0 = jhi - CH;
+        T lc[CH][R];
 #pragma unroll
-        for (int jj = 0; jj < kChunk; jj++)
+        for (int jj = 0; jj < CH; jj++)
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const int row = sl + SEG * r;
-                lc[jj][r] = (valid && j0 + jj >= 0 && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row] : T(0);
+                lc[jj][r] = (valid && j0 + jj >= 0 && row > j0 + jj && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row]
+                                                                                   : T(0);
             }
-    };
-    auto back = [&](const T (&lc)[kChunk][R], int jhi) {
-        const int j0 = jhi - kChunk;
 #pragma unroll
-        for (int jj = kChunk - 1; jj >= 0; jj--) {
+        for (int jj = CH - 1; jj >= 0; jj--) {
             const int j = j0 + jj;
             if (j >= 0) {
                 T part = T(0);
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const int row = sl + SEG * r;
-                    if (row > j) part += lc[jj][r] * v[r];
-                }
+                for (int r = 0; r < R; r++) part += lc[jj][r] * v[r];   // rows <= j are masked to zero
                 part = seg_allsum<T, SEG>(part);
                 const int jl = j & (SEG - 1), jr = j / SEG;
-                T vs = v[0], ds = lc[jj][0];
+                T vs = v[0], es = di[0];
 #pragma unroll
                 for (int r = 1; r < R; r++)
-                    if (r == jr) { vs = v[r]; ds = lc[jj][r]; }
-                const T xj = (__shfl(vs, jl, SEG) - part) / __shfl(ds, jl, SEG);
+                    if (r == jr) { vs = v[r]; es = di[r]; }
+                const T xj = (__shfl(vs, jl, SEG) - part) * __shfl(es, jl, SEG);
 #pragma unroll
                 for (int r = 0; r < R; r++)
                     if (sl + SEG * r == j) v[r] = xj;
             }
         }
-    };
-    if (d.w > 0) load(la, d.w);
-    for (int jhi = d.w; jhi > 0; jhi -= 2 * kChunk) {
-        if (jhi - kChunk > 0) load(lb, jhi - kChunk);
-        back(la, jhi);
-        if (jhi - kChunk <= 0) break;
-        if (jhi - 2 * kChunk > 0) load(la, jhi - 2 * kChunk);
-        back(lb, jhi - kChunk);
     }
     if (!valid) return;
 #pragma unroll
@@ -759,6 +764,17 @@ __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __re
         const int row = sl + SEG * r;
         if (row < d.w) x[d.f + row] = v[r];
     }
+}
+
+// reciprocals of the factor's diagonal (one per column), used by the
+// wavefront triangular solves in place of divisions
+template <typename T>
+__global__ void k_inv_diag(const i64* __restrict__ diag_off, i64 n, i64 Lsize, const T* __restrict__ L,
+                           T* __restrict__ Dinv, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    for (i64 j = (i64)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (i64)gridDim.x * blockDim.x)
+        Dinv[(i64)b * n + j] = T(1) / L[(i64)b * Lsize + diag_off[j]];
 }
 
 // ---------------------------------------------------------------------------
