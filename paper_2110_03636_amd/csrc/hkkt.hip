@@ -308,7 +308,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                     const i32 sn = S.level_sn[q];
                     const int nr = (int)(S.sn_rowptr[sn + 1] - S.sn_rowptr[sn]);
                     int mine = tri_class(nr, S.sn_first[sn + 1] - S.sn_first[sn]);
-                    if (merge_classes && mine >= 2 && mine < kTriWG) mine = lvmax;
+                    if (merge_classes && mine >= 2 && mine <= 3 && lvmax <= 3) mine = lvmax;
                     if (mine != cls) continue;
                     tl.push_back(sn);
                     TriDesc dd;
@@ -483,13 +483,34 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
     T* X = B.X.as<T>();
     T* UV = B.UV.as<T>();
     const bool push = c->opt.deterministic == 0;
-    for (int cls = 0; cls < kTriClasses; cls++) {
+    const int kf = 3 + 16 * (l + 1), kb = 4 + 16 * (l + 1);
+    // narrow classes 0..3 of the level: one launch
+    {
+        LevelTasks lt{};
+        i64 wend = 0;
+        const int segw[4] = {16, 32, 64, 64};
+        for (int cls = 0; cls < 4; cls++) {
+            const auto seg = D.tri_seg[(size_t)l * kTriClasses + cls];
+            const int G = kWave / segw[cls];
+            lt.desc[cls] = D.tri_desc.as<TriDesc>() + seg.first;
+            lt.count[cls] = seg.second;
+            lt.npad[cls] = (nids + G - 1) / G * G;
+            wend += (i64)seg.second * lt.npad[cls] / G;
+            lt.wave_end[cls] = wend;
+        }
+        if (wend > 0) {
+            const unsigned nblk = (unsigned)((wend + (kBlock / kWave) - 1) / (kBlock / kWave));
+            if (fwd && push) LAUNCH(kf, (k_fwd_lvl<T, true>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
+            else if (fwd) LAUNCH(kf, (k_fwd_lvl<T, false>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
+            else LAUNCH(kb, (k_bwd_lvl<T>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lt, L, Dv, X, ids, nids, st_);
+        }
+    }
+    for (int cls = 4; cls < kTriClasses; cls++) {
         const auto seg = D.tri_seg[(size_t)l * kTriClasses + cls];
         if (seg.second == 0) continue;
         const i32* lst = D.tri_list.as<i32>() + seg.first;
         const TriDesc* dsc = D.tri_desc.as<TriDesc>() + seg.first;
         const int cnt = seg.second;
-        const int kf = 3 + 16 * (l + 1), kb = 4 + 16 * (l + 1);
 #define HKKT_TRI_S(SEGW, RR)                                                                                      \
     {                                                                                                             \
         constexpr int G = kWave / SEGW;                                                                           \
@@ -504,10 +525,6 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
                     X, ids, nids, st_);                                                                           \
     }
         switch (cls) {
-            case 0: HKKT_TRI_S(16, 1) break;
-            case 1: HKKT_TRI_S(32, 1) break;
-            case 2: HKKT_TRI_S(64, 1) break;
-            case 3: HKKT_TRI_S(64, 2) break;
             case 4: HKKT_TRI_S(64, 4) break;
             case 5: HKKT_TRI_S(64, 8) break;
             case 6: HKKT_TRI_S(64, 16) break;

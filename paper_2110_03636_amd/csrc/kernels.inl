@@ -601,11 +601,11 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
 // Backward: v = [y(cols); x(rows below)]; for j = w-1..0:
 // x_j = (v_j - sum_{i>j} L_ij x_i) / L_jj with a butterfly segment sum.
 // ---------------------------------------------------------------------------
-// panel columns fetched per memory round trip: 32 FP32 / 16 FP64 columns
-// with one row per lane, fewer as rows per lane grow (register budget)
-template <typename T, int R>
+// panel columns fetched per memory round trip: 16 for the 64-lane class with
+// one row per lane, 8 otherwise (register budget and occupancy)
+template <typename T, int SEG, int R>
 __host__ __device__ constexpr int chunk_cols() {
-    return R == 1 ? (sizeof(T) == 4 ? 32 : 16) : (R == 2 ? 16 : 8);
+    return (SEG == 64 && R == 1) ? 16 : 8;
 }
 
 template <typename T, int SEG>
@@ -620,15 +620,15 @@ __device__ __forceinline__ T seg_allsum(T v) {
 // straight into the ancestors' right-hand-side entries with FP atomics
 // (right-looking; order of the additions not fixed).
 template <typename T, int SEG, int R, bool PUSH>
-__global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
-                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
-                                                  T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
-                                                  const CGState* st) {
+__device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
+                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
+                                         const CGState* st) {
     constexpr int G = kWave / SEG;
-    constexpr int CH = chunk_cols<T, R>();
+    constexpr int CH = chunk_cols<T, SEG, R>();
     const int lane = threadIdx.x & (kWave - 1);
     const int sl = lane & (SEG - 1), seg = lane / SEG;
-    const i64 t0 = ((i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave)) * G;
+    const i64 t0 = wave * G;
     const int q = (int)(t0 / npad);
     if (q >= count) return;
     const int k = (int)(t0 - (i64)q * npad) + seg;
@@ -698,14 +698,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __re
 }
 
 template <typename T, int SEG, int R>
-__global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
-                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
-                                                  T* __restrict__ X, const int* ids, int nids, const CGState* st) {
+__device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
+                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         T* __restrict__ X, const int* ids, int nids, const CGState* st) {
     constexpr int G = kWave / SEG;
-    constexpr int CH = chunk_cols<T, R>();
+    constexpr int CH = chunk_cols<T, SEG, R>();
     const int lane = threadIdx.x & (kWave - 1);
     const int sl = lane & (SEG - 1), seg = lane / SEG;
-    const i64 t0 = ((i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave)) * G;
+    const i64 t0 = wave * G;
     const int q = (int)(t0 / npad);
     if (q >= count) return;
     const int k = (int)(t0 - (i64)q * npad) + seg;
@@ -764,6 +764,64 @@ __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __re
         const int row = sl + SEG * r;
         if (row < d.w) x[d.f + row] = v[r];
     }
+}
+
+
+// one class per launch (used for the wide classes R >= 4)
+template <typename T, int SEG, int R, bool PUSH>
+__global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
+                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
+                                                  const CGState* st) {
+    fwd_task<T, SEG, R, PUSH>(S, desc, count, npad, (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, L, Dinv,
+                              X, UV, ids, nids, st);
+}
+
+template <typename T, int SEG, int R>
+__global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
+                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  T* __restrict__ X, const int* ids, int nids, const CGState* st) {
+    bwd_task<T, SEG, R>(S, desc, count, npad, (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, L, Dinv, X,
+                        ids, nids, st);
+}
+
+// the four narrow classes of one level in one launch: each wavefront looks
+// up its class by the wavefront ranges and runs that class's task
+struct LevelTasks {
+    const TriDesc* desc[4];
+    int count[4];
+    int npad[4];
+    i64 wave_end[4];   // cumulative wavefront counts
+};
+
+template <typename T, bool PUSH>
+__global__ __launch_bounds__(kBlock) void k_fwd_lvl(SymView S, LevelTasks lt, const T* __restrict__ L,
+                                                    const T* __restrict__ Dinv, T* __restrict__ X, T* __restrict__ UV,
+                                                    const int* ids, int nids, const CGState* st) {
+    const i64 wv = (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (wv < lt.wave_end[0])
+        fwd_task<T, 16, 1, PUSH>(S, lt.desc[0], lt.count[0], lt.npad[0], wv, L, Dinv, X, UV, ids, nids, st);
+    else if (wv < lt.wave_end[1])
+        fwd_task<T, 32, 1, PUSH>(S, lt.desc[1], lt.count[1], lt.npad[1], wv - lt.wave_end[0], L, Dinv, X, UV, ids, nids, st);
+    else if (wv < lt.wave_end[2])
+        fwd_task<T, 64, 1, PUSH>(S, lt.desc[2], lt.count[2], lt.npad[2], wv - lt.wave_end[1], L, Dinv, X, UV, ids, nids, st);
+    else if (wv < lt.wave_end[3])
+        fwd_task<T, 64, 2, PUSH>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], L, Dinv, X, UV, ids, nids, st);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bwd_lvl(SymView S, LevelTasks lt, const T* __restrict__ L,
+                                                    const T* __restrict__ Dinv, T* __restrict__ X, const int* ids,
+                                                    int nids, const CGState* st) {
+    const i64 wv = (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (wv < lt.wave_end[0])
+        bwd_task<T, 16, 1>(S, lt.desc[0], lt.count[0], lt.npad[0], wv, L, Dinv, X, ids, nids, st);
+    else if (wv < lt.wave_end[1])
+        bwd_task<T, 32, 1>(S, lt.desc[1], lt.count[1], lt.npad[1], wv - lt.wave_end[0], L, Dinv, X, ids, nids, st);
+    else if (wv < lt.wave_end[2])
+        bwd_task<T, 64, 1>(S, lt.desc[2], lt.count[2], lt.npad[2], wv - lt.wave_end[1], L, Dinv, X, ids, nids, st);
+    else if (wv < lt.wave_end[3])
+        bwd_task<T, 64, 2>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], L, Dinv, X, ids, nids, st);
 }
 
 // reciprocals of the factor's diagonal (one per column), used by the
