@@ -97,7 +97,10 @@ def run_gpu(args):
     avg_ms = ms_tot / max(launches, 1)
     per_launch = total[best] / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": best, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    kname = {"fwd": "k_fwd_lvl<float,true> (forward supernodal triangular solve, one launch per level)",
+             "bwd": "k_bwd_lvl<float> (backward supernodal triangular solve, one launch per level)",
+             "jt_spmv": "k_jt<float>", "j_spmv": "k_j<float>"}[best]
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(per_launch),
                 "launches_per_step": launches}

@@ -205,9 +205,10 @@ int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
  * synchronises the stream and returns, per kernel class, the summed
  * launch durations ms[k] (milliseconds) and launch counts launches[k]
  * (arrays of HKKT_NPROF; either may be NULL). Classes: 0 assembly,
- * 1 LDS fronts, 2 global fronts, 3 forward solve, 4 backward solve,
- * 5 J^T SpMV, 6 J SpMV, 7 CG vector updates, 8 CG scalars, 9 KKT residual,
- * 10 other. */
+ * 1 LDS fronts, 2 large fronts (blocked), 3 forward solve (per-level
+ * wavefront kernel), 4 backward solve (per-level wavefront kernel), 5 J^T
+ * SpMV, 6 J SpMV, 7 CG vector updates, 8 CG scalars, 9 KKT residual,
+ * 10 other, 11 triangular solves of very wide/tall supernodes. */
 #define HKKT_NPROF 12
 int hkkt_profile_begin(hkkt_ctx *ctx);
 int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);

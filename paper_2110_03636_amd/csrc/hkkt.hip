@@ -171,11 +171,11 @@ constexpr size_t kMaxLds = 65536;
 constexpr int kTriClasses = 8;
 constexpr int kTriWG = 7;
 
-// size class of a supernode for the triangular solves: wide diagonal blocks
-// (w above kWideW, default 40) go to the work-group kernel, whose 64x64
-// LDS-staged diagonal solve has a shorter dependency chain than a wavefront
+// size class of a supernode for the triangular solves: rows decide the
+// wavefront class; supernodes wider than HKKT_TRI_WIDE columns (default
+// 1024) or taller than 1024 rows go to the work-group kernel
 static int tri_class(int nr, int w) {
-    static const int wide = std::getenv("HKKT_TRI_WIDE") ? std::atoi(std::getenv("HKKT_TRI_WIDE")) : 40;
+    static const int wide = std::getenv("HKKT_TRI_WIDE") ? std::atoi(std::getenv("HKKT_TRI_WIDE")) : 1024;
     if (w > wide) return 7;
     if (nr <= 16) return 0;
     if (nr <= 32) return 1;
@@ -511,6 +511,7 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const i32* lst = D.tri_list.as<i32>() + seg.first;
         const TriDesc* dsc = D.tri_desc.as<TriDesc>() + seg.first;
         const int cnt = seg.second;
+        const int kf = 11 + 16 * (l + 1), kb = 11 + 16 * (l + 1);   // wide classes: own profile class
 #define HKKT_TRI_S(SEGW, RR)                                                                                      \
     {                                                                                                             \
         constexpr int G = kWave / SEGW;                                                                           \

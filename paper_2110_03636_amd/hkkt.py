@@ -26,8 +26,8 @@ EXPORTS = [
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
     "hkkt_profile_begin", "hkkt_profile_end",
 ]
-PROF_NAMES = ["assemble", "front_lds", "front_global", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
-              "cg_scalar", "residual", "other", "unused"]
+PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
+              "cg_scalar", "residual", "other", "tri_wide"]
 
 i64p = C.POINTER(C.c_int64)
 i32p = C.POINTER(C.c_int32)
@@ -328,4 +328,4 @@ class Solver(_SymbolicView):
         ms = np.zeros(12)
         k = np.zeros(12, np.int64)
         _check(lib().hkkt_profile_end(self._ctx, ms.ctypes.data, k.ctypes.data), self._ctx)
-        return {PROF_NAMES[i]: (float(ms[i]), int(k[i])) for i in range(11)}
+        return {PROF_NAMES[i]: (float(ms[i]), int(k[i])) for i in range(12)}
