@@ -144,6 +144,46 @@ def run_gpu(args):
     return value, el, roofline, extra, b
 
 
+def profile_hsolve(args):
+    """Counter-collection driver: a 1 GiB device copy (calibration of the
+    byte counters) followed by args.profile_hsolve applications of
+    H_gamma^{-1} to all instances of the workload (mixed precision)."""
+    import numpy as np
+    import torch
+    from paper_2110_03636_amd import hkkt, synth
+    a = torch.empty(2**28, dtype=torch.float32, device="cuda").fill_(1.0)
+    torch.empty_like(a).copy_(a)
+    torch.cuda.synchronize()
+    b = synth.grid_like(args.n, nb=args.nb, seed=4000, gammas=(1e4, 1e6), dx_exp=8.0)
+    dev = lambda x: torch.as_tensor(x, device="cuda")
+    s = hkkt.Solver(precision="mixed", device=True)
+    s.analyze(b.pattern)
+    s.factor(dev(b.H_val), dev(b.D_x), dev(b.J_val), b.delta, b.gamma)
+    rhs = dev(np.random.default_rng(0).standard_normal((args.nb, args.n)))
+    for _ in range(args.profile_hsolve):
+        s.hsolve(rhs)
+    torch.cuda.synchronize()
+    st = s.stats()
+    per = per_instance_bytes(st, 4)
+    print(json.dumps({"levels": st["levels"], "alg_bytes_per_launch": {k: per[k] * args.nb / st["levels"]
+                                                                      for k in ("fwd", "bwd")}}))
+
+
+def load_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, valid only while the kernel source is unchanged."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            t = json.load(f)
+        src = open(os.path.join(ROOT, "paper_2110_03636_amd", "csrc", "kernels.inl"), "rb").read()
+        if hashlib.sha256(src).hexdigest() != t.get("kernels_sha256"):
+            return None
+        return t
+    except (OSError, ValueError):
+        return None
+
+
 def cpu_baseline(b, budget_s):
     import oracle
     o0 = oracle.System.from_batch(b, 0)
@@ -171,13 +211,24 @@ def main():
     ap.add_argument("--single", type=int, default=4, help="instances timed on the plain FP64 path")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-hsolve", type=int, default=0,
+                    help="counter-collection mode: calibration copy + this many H_gamma^{-1} applications")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
               "(batches shard by instance across GPUs without communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile_hsolve:
+        profile_hsolve(args)
+        return
     value, el, roofline, extra, b = run_gpu(args)
+    tr = load_traffic()
+    if tr and roofline["kernel"].startswith(tr["kernel"]):
+        # counter-measured HBM bytes per launch relative to the algorithmic
+        # bytes of the same launches, applied to this run's launches
+        roofline["traffic"] = int(tr["traffic_over_alg"] * roofline["bytes_per_launch"])
+        roofline["traffic_over_alg"] = tr["traffic_over_alg"]
     cpu = None if args.no_cpu else cpu_baseline(b, args.cpu_budget)
     out = {
         "metric": "KKT solves/sec at 1e-10 rel. KKT residual: mixed-prec batched vs plain FP64",
