@@ -119,6 +119,28 @@ int hkkt_analyze(hkkt_ctx *ctx, int64_t n_x, int64_t m,
                  const int64_t *J_rowptr, const int32_t *J_col,
                  const int32_t *perm);
 
+/* Uneven batch in one launch: G independent KKT systems of different sizes
+ * and patterns ("members") analysed together as one block-diagonal system,
+ * so that every factor and solve kernel covers all of them (the Sec. 2
+ * reuse list then holds per group). Member k owns the variables
+ * [x_off[k], x_off[k+1]) and the J rows [y_off[k], y_off[k+1]) of the
+ * combined pattern given as for hkkt_analyze (x_off[0] = y_off[0] = 0,
+ * x_off[G] = n_x, y_off[G] = m; every member has at least one variable and
+ * may have no J rows). Host arrays of G+1 entries; copied. Each member keeps
+ * its own elimination range (own AMD order restricted to the member).
+ * After it, hkkt_factor_batch / hkkt_solve_batch / hkkt_hsolve take the
+ * combined value and vector arrays per batch entry, while every per-system
+ * scalar and result is per (entry b, member k) at index b*G + k: delta,
+ * gamma, status, fail_col (combined original index), info, and the index of
+ * hkkt_inertia. Each member runs its own CG, refinement and FP64 fallback
+ * (Algorithm 1 per member). hkkt_factor / hkkt_solve need G = 1.
+ * Errors: -1 if G is not in [1, 65535], offsets missing or not increasing; -2 if an entry of
+ * tril(H) or J couples two members, or as for hkkt_analyze. */
+int hkkt_analyze_group(hkkt_ctx *ctx, int G, const int64_t *x_off, const int64_t *y_off,
+                       int64_t n_x, int64_t m,
+                       const int64_t *H_rowptr, const int32_t *H_col,
+                       const int64_t *J_rowptr, const int32_t *J_col);
+
 /* Numeric factorization of nb instances that share the analysed pattern
  * (Sec. 2: once per matrix; Algorithm 1 "Try LL^T = chol(H_delta)").
  * H_val [nb][nnz(tril H)], D_x [nb][n_x], J_val [nb][nnz(J)], delta [nb],
@@ -139,8 +161,9 @@ int hkkt_factor(hkkt_ctx *ctx, const double *H_val, const double *D_x, const dou
 /* Solve K z = r for the nb instances of the last factorization (Algorithm 1
  * solve phase: rhat, w = H_gamma^{-1} rhat, CG on eq. Schur1, x from eq.
  * Schur2; then refinement to kkt_tol). r1 [nb][n_x], r2 [nb][m] in; x
- * [nb][n_x], y [nb][m] out; info [nb] (host, may be NULL). nb must equal the
- * last factorization's nb. Returns the largest per-instance status (0 if all
+ * [nb][n_x], y [nb][m] out; info [nb] (host, may be NULL; nb*G entries for
+ * a group, see hkkt_analyze_group). nb must equal the last factorization's
+ * nb. Returns the largest per-instance status (0 if all
  * converged), or negative on error (-3 if not factored successfully). */
 int hkkt_solve_batch(hkkt_ctx *ctx, int nb, const double *r1, const double *r2,
                      double *x, double *y, hkkt_info *info);
@@ -157,12 +180,20 @@ int hkkt_inertia(const hkkt_ctx *ctx, int b, int64_t out[3]);
 
 /* ---- host-only symbolic analysis handle (no GPU needed) ------------------
  * The same analysis hkkt_analyze runs, exposed for inspection and tests.
- * Arguments as for hkkt_analyze; ordering/relax as in hkkt_options. */
+ * Arguments as for hkkt_analyze; ordering/relax as in hkkt_options. The
+ * error message (if err is non-NULL) is written into err[errlen]. */
 typedef struct hkkt_symbolic hkkt_symbolic;
 int hkkt_symbolic_create(hkkt_symbolic **out, int64_t n_x, int64_t m,
                          const int64_t *H_rowptr, const int32_t *H_col,
                          const int64_t *J_rowptr, const int32_t *J_col,
                          const int32_t *perm, int ordering, int relax, char *err, int errlen);
+/* Group form (members as for hkkt_analyze_group; perm may be NULL; a given
+ * perm is regrouped by member, keeping its order within each member). */
+int hkkt_symbolic_create_group(hkkt_symbolic **out, int G, const int64_t *x_off, const int64_t *y_off,
+                               int64_t n_x, int64_t m,
+                               const int64_t *H_rowptr, const int32_t *H_col,
+                               const int64_t *J_rowptr, const int32_t *J_col,
+                               const int32_t *perm, int ordering, int relax, char *err, int errlen);
 void hkkt_symbolic_destroy(hkkt_symbolic *sym);
 
 /* The analysis owned by a context (valid until the next hkkt_analyze). */
@@ -186,7 +217,8 @@ int hkkt_symbolic_supernodes(const hkkt_symbolic *sym, int32_t *sn_first, int64_
                              int32_t *sn_rows, int32_t *sn_parent, int32_t *level_ptr,
                              int32_t *level_sn);
 
-/* Copy the factor of instance b into CSC form in the permuted order
+/* Copy the factor of batch entry b (for a group: the block-diagonal factor
+ * of all members) into CSC form in the permuted order
  * (colptr [n_x+1], rowind, val [nnz(L)] in FP64), for parity tests. */
 int hkkt_get_factor(hkkt_ctx *ctx, int b, int64_t *colptr, int32_t *rowind, double *val);
 

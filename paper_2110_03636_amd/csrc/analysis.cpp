@@ -266,7 +266,8 @@ std::vector<i32> amd_order(i64 n, const std::vector<i64>& ptr, const std::vector
 // full analysis
 // ---------------------------------------------------------------------------
 std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, const i64* Jp,
-                    const i32* Ji, const i32* perm_in, const AnalyzeOptions& opt) {
+                    const i32* Ji, const i32* perm_in, const AnalyzeOptions& opt, int G, const i64* x_off,
+                    const i64* y_off) {
     std::string err = validate_pattern(n, m, Hp, Hi, Jp, Ji);
     if (!err.empty()) return err;
     static const i64 zero_ptr[1] = {0};
@@ -275,6 +276,34 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
     S.n = n; S.m = m;
     S.nnzH = Hp[n];
     S.nnzJ = Jp[m];
+    // ---- members (uneven group) and their block structure
+    if (G < 1) return "group size must be >= 1";
+    S.G = G;
+    if (G == 1 || !x_off || !y_off) {
+        if (G > 1) return "group offsets missing";
+        S.x_off = {0, n};
+        S.y_off = {0, m};
+    } else {
+        S.x_off.assign(x_off, x_off + G + 1);
+        S.y_off.assign(y_off, y_off + G + 1);
+        if (S.x_off[0] != 0 || S.x_off[G] != n || S.y_off[0] != 0 || S.y_off[G] != m) return "group offsets do not cover the system";
+        for (int k = 0; k < G; k++)
+            if (S.x_off[k + 1] <= S.x_off[k] || S.y_off[k + 1] < S.y_off[k]) return "group offsets not increasing (every member needs n_x >= 1)";
+    }
+    std::vector<i32> xmem(n);
+    for (int k = 0; k < G; k++)
+        for (i64 i = S.x_off[k]; i < S.x_off[k + 1]; i++) xmem[i] = k;
+    S.y_mem.resize(m);
+    for (int k = 0; k < G; k++)
+        for (i64 r = S.y_off[k]; r < S.y_off[k + 1]; r++) S.y_mem[r] = k;
+    if (G > 1) {
+        for (i64 i = 0; i < n; i++)
+            for (i64 p = Hp[i]; p < Hp[i + 1]; p++)
+                if (xmem[Hi[p]] != xmem[i]) return "tril(H) entry couples two group members at row " + std::to_string(i);
+        for (i64 r = 0; r < m; r++)
+            for (i64 p = Jp[r]; p < Jp[r + 1]; p++)
+                if (xmem[Ji[p]] != S.y_mem[r]) return "J row " + std::to_string(r) + " has a column outside its member";
+    }
 
     std::vector<i64> gptr;
     std::vector<i32> gadj;
@@ -295,6 +324,16 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
     } else {
         perm0 = amd_order(n, gptr, gadj);
         if ((i64)perm0.size() != n) return "internal: ordering incomplete";
+    }
+    if (G > 1) {
+        // the members are decoupled: keep each member's pivots in its own
+        // range, in the order the ordering chose (same fill per member)
+        std::vector<i32> part;
+        part.reserve(n);
+        for (int k = 0; k < G; k++)
+            for (i32 v : perm0)
+                if (xmem[v] == k) part.push_back(v);
+        perm0.swap(part);
     }
     std::vector<i32> ip0(n);
     for (i64 k = 0; k < n; k++) ip0[perm0[k]] = (i32)k;
@@ -638,6 +677,48 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
                 if (a != b) { S.HF_col[pos[b]] = (i32)a; S.HF_src[pos[b]] = (i32)p; pos[b]++; }
             }
     }
+    // ---- member maps and member-aligned reduction blocks
+    S.xp_mem.resize(n);
+    for (i64 k = 0; k < n; k++) {
+        S.xp_mem[k] = xmem[perm[k]];
+        if (S.xp_mem[k] != xmem[k]) return "internal: elimination order mixes group members";
+    }
+    S.a_mem.resize(S.nnzA);
+    S.sn_mem.resize(ns);
+    for (i32 s2 = 0; s2 < ns; s2++) S.sn_mem[s2] = S.xp_mem[S.sn_first[s2]];
+    for (i64 e = 0; e < S.nnzA; e++) {
+        // supernode whose panel holds the entry
+        const i32 s2 = (i32)(std::upper_bound(S.sn_lptr.begin(), S.sn_lptr.begin() + ns + 1, S.a_dst[e]) -
+                             S.sn_lptr.begin()) - 1;
+        S.a_mem[e] = S.sn_mem[s2];
+    }
+    S.mblk.clear();
+    S.mblk_off.assign(G + 1, 0);
+    for (int k = 0; k < G; k++) {
+        S.mblk_off[k] = (i32)(S.mblk.size() / 3);
+        for (i64 r = S.y_off[k]; r < S.y_off[k + 1]; r += kRedBlock) {
+            S.mblk.push_back((i32)r);
+            S.mblk.push_back((i32)std::min<i64>(r + kRedBlock, S.y_off[k + 1]));
+            S.mblk.push_back(k);
+        }
+    }
+    S.mblk_off[G] = (i32)(S.mblk.size() / 3);
+    S.rblk.clear();
+    S.rblk_off.assign(G + 1, 0);
+    for (int k = 0; k < G; k++) {
+        S.rblk_off[k] = (i32)(S.rblk.size() / 3);
+        for (i64 i = S.x_off[k]; i < S.x_off[k + 1]; i += kRedBlock) {
+            S.rblk.push_back((i32)i);
+            S.rblk.push_back((i32)std::min<i64>(i + kRedBlock, S.x_off[k + 1]));
+            S.rblk.push_back(k);
+        }
+        for (i64 r = S.y_off[k]; r < S.y_off[k + 1]; r += kRedBlock) {
+            S.rblk.push_back((i32)(n + r));
+            S.rblk.push_back((i32)(n + std::min<i64>(r + kRedBlock, S.y_off[k + 1])));
+            S.rblk.push_back(k);
+        }
+    }
+    S.rblk_off[G] = (i32)(S.rblk.size() / 3);
     return "";
 }
 

@@ -67,7 +67,25 @@ struct Symbolic {
     std::vector<i32> HF_col;
     std::vector<i32> HF_src;               // index into H_val
     i64 nnzH = 0, nnzJ = 0;
+
+    // members of an uneven group (block-diagonal super-system); G = 1 for a
+    // single pattern. Member k owns variables [x_off[k], x_off[k+1]) and J
+    // rows [y_off[k], y_off[k+1]); the elimination order keeps every member's
+    // variables in its own contiguous range, so the same ranges hold in the
+    // permuted order.
+    i32 G = 1;
+    std::vector<i64> x_off, y_off;
+    std::vector<i32> xp_mem;               // [n] member of permuted variable
+    std::vector<i32> y_mem;                // [m] member of J row
+    std::vector<i32> a_mem;                // [nnzA] member of assembly entry
+    std::vector<i32> sn_mem;               // [ns] member of supernode
+    // member-aligned reduction blocks (start, end, member) over the J rows
+    // and over the combined [x ; y] index space of the KKT residual
+    std::vector<i32> mblk, mblk_off;       // mblk_off[k]: first block of member k
+    std::vector<i32> rblk, rblk_off;
 };
+
+constexpr int kRedBlock = 256;             // rows per reduction block
 
 // Validates the CSR inputs; returns "" if fine, else a message.
 std::string validate_pattern(i64 n, i64 m, const i64* Hp, const i32* Hi, const i64* Jp, const i32* Ji);
@@ -76,8 +94,11 @@ std::string validate_pattern(i64 n, i64 m, const i64* Hp, const i32* Hi, const i
 // the diagonal). Returns perm[k] = node eliminated k-th.
 std::vector<i32> amd_order(i64 n, const std::vector<i64>& ptr, const std::vector<i32>& adj);
 
-// Full analysis. perm_in may be null. Returns "" or an error message.
+// Full analysis. perm_in may be null. For an uneven group, G > 1 members
+// with variable offsets x_off[G+1] and J-row offsets y_off[G+1] (entries of
+// H and J must stay inside their member's block). Returns "" or an error.
 std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, const i64* Jp,
-                    const i32* Ji, const i32* perm_in, const AnalyzeOptions& opt);
+                    const i32* Ji, const i32* perm_in, const AnalyzeOptions& opt, int G = 1,
+                    const i64* x_off = nullptr, const i64* y_off = nullptr);
 
 }  // namespace hkkt

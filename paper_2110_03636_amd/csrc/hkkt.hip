@@ -152,6 +152,7 @@ struct DevSym {
     std::vector<i32> all_ptr, small_ptr, big_ptr;
     std::vector<int> all_maxnr, small_maxnr;
     DBuf ga_row, ga_idx, diag_off;
+    DBuf xp_mem, a_mem, sn_mem, mblk, mblk_off, rblk, rblk_off;   // group members
     // large fronts: per level sorted by width (descending) in lev_big, child
     // rank pair lists (front, child) and per-front (nr, w) on the host
     DBuf big_pairs;
@@ -217,6 +218,13 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     upload(D.HF_rowptr, S.HF_rowptr, st);
     upload(D.HF_col, S.HF_col, st);
     upload(D.HF_src, S.HF_src, st);
+    upload(D.xp_mem, S.xp_mem, st);
+    upload(D.a_mem, S.a_mem, st);
+    upload(D.sn_mem, S.sn_mem, st);
+    upload(D.mblk, S.mblk, st);
+    upload(D.mblk_off, S.mblk_off, st);
+    upload(D.rblk, S.rblk, st);
+    upload(D.rblk_off, S.rblk_off, st);
     // level lists: all supernodes of a level; split by front size
     std::vector<i32> all, small, big;
     D.all_ptr.assign(1, 0);
@@ -319,6 +327,8 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                     dd.w = S.sn_first[sn + 1] - S.sn_first[sn];
                     dd.nr = nr;
                     dd.nchild = S.child_ptr[sn + 1] - S.child_ptr[sn];
+                    dd.mem = S.sn_mem[sn];
+                    dd.pad = 0;
                     td.push_back(dd);
                     if (cls == kTriWG) D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
                 }
@@ -359,6 +369,16 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     v.HF_rowptr = D.HF_rowptr.as<i64>();
     v.HF_col = D.HF_col.as<i32>();
     v.HF_src = D.HF_src.as<i32>();
+    v.G = S.G;
+    v.xp_mem = D.xp_mem.as<i32>();
+    v.a_mem = D.a_mem.as<i32>();
+    v.sn_mem = D.sn_mem.as<i32>();
+    v.nbm = S.mblk_off[S.G];
+    v.mblk = D.mblk.as<i32>();
+    v.mblk_off = D.mblk_off.as<i32>();
+    v.nbr = S.rblk_off[S.G];
+    v.rblk = D.rblk.as<i32>();
+    v.rblk_off = D.rblk_off.as<i32>();
 }
 
 // ---------------------------------------------------------------------------
@@ -374,8 +394,9 @@ struct Batch {
     // solve workspace
     DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
-    DBuf ids_pass, ids_a, ids_b, ids_all;   // instance-id lists of the solve phase
-    std::vector<int> h_fail;   // per instance min failing permuted column (INT_MAX ok)
+    DBuf ids_pass, ids_a, ids_b, ids_all;   // batch-entry lists of the solve phase
+    DBuf cact;                 // per (entry, member): member takes part in the current pass (groups)
+    std::vector<int> h_fail;   // per (entry, member) min failing permuted column (INT_MAX ok)
 
     ValView vals() const {
         ValView V;
@@ -426,7 +447,7 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     T* L = B.L.as<T>();
     T* CB = B.CB.as<T>();
     LAUNCH(10, k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
-    LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb, INT_MAX);
+    LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb * S.G, INT_MAX);
     LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.vals(), L, active);
     for (i32 l = 0; l < S.nlevels; l++) {
         const int ns_small = D.small_ptr[l + 1] - D.small_ptr[l];
@@ -558,9 +579,9 @@ static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {
     B.HF.ensure((size_t)nb * std::max<i64>(1, (i64)S.HF_col.size()) * 8);
     B.Dx.ensure((size_t)nb * S.n * 8);
     B.Dxp.ensure((size_t)nb * S.n * 8);
-    B.delta.ensure((size_t)nb * 8);
-    B.gamma.ensure((size_t)nb * 8);
-    B.fail.ensure((size_t)nb * 4);
+    B.delta.ensure((size_t)nb * S.G * 8);
+    B.gamma.ensure((size_t)nb * S.G * 8);
+    B.fail.ensure((size_t)nb * S.G * 4);
     B.active.ensure((size_t)nb * 4);
 }
 
@@ -578,16 +599,19 @@ static void alloc_solve(hkkt_ctx* c, Batch& B) {
     for (DBuf* d : {&B.r2, &B.yz, &B.g2, &B.bvec, &B.y, &B.res, &B.p, &B.q}) d->ensure(nb * m * 8);
     B.X.ensure(nb * n * B.esz());
     B.UV.ensure(nb * std::max<i64>(1, S.UVsize) * B.esz());
-    const size_t nblk = grid1(S.n + S.m, 1u << 30);
+    const size_t nblk = std::max<size_t>(1, std::max(S.mblk.size(), S.rblk.size()) / 3);
+    const size_t nc = nb * S.G;
     for (DBuf* d : {&B.part1, &B.part2, &B.pfloor}) d->ensure(nb * nblk * 8);
-    B.st.ensure(nb * sizeof(CGState));
+    B.st.ensure(nc * sizeof(CGState));
     B.live.ensure(16);
     for (DBuf* d : {&B.ids_pass, &B.ids_a, &B.ids_b, &B.ids_all}) d->ensure(nb * 4);
-    for (DBuf* d : {&B.rsq, &B.rowred, &B.knorm}) d->ensure(nb * 8);
+    for (DBuf* d : {&B.rsq, &B.rowred, &B.knorm}) d->ensure(nc * 8);
+    B.cact.ensure(nc * 4);
 }
 
-// copy values of the given (host or device) buffers into B, instance i of B
-// from instance src_idx[i] of the source arrays
+// copy values of the given (host or device) buffers into B, entry i of B
+// from entry src_idx[i] of the source arrays (delta and gamma: one per
+// (entry, member))
 static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx, const double* J,
                         const double* delta, const double* gamma, const std::vector<int>* src_idx, bool device_ptrs) {
     const Symbolic& S = c->sym.S;
@@ -607,36 +631,40 @@ static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx
     cp(B.H, H, S.nnzH);
     cp(B.J, J, S.nnzJ);
     cp(B.Dx, Dx, S.n);
-    std::vector<double> hd(nb), hg(nb);
+    const int G = S.G;
+    std::vector<double> hd((size_t)nb * G), hg((size_t)nb * G);
     for (int i = 0; i < nb; i++) {
         const int s = src_idx ? (*src_idx)[i] : i;
-        hd[i] = delta[s];
-        hg[i] = gamma[s];
+        for (int k = 0; k < G; k++) {
+            hd[(size_t)i * G + k] = delta[(size_t)s * G + k];
+            hg[(size_t)i * G + k] = gamma[(size_t)s * G + k];
+        }
     }
-    HIPCHK(hipMemcpyAsync(B.delta.p, hd.data(), nb * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(B.gamma.p, hg.data(), nb * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.delta.p, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(B.gamma.p, hg.data(), hg.size() * 8, hipMemcpyHostToDevice, st));
     LAUNCH(10, k_gather_vals, dim3(grid1(std::max<i64>({S.n, S.nnzJ, (i64)S.HF_col.size()}), 1024), nb),
                        dim3(kBlock), 0, st, c->dev.v, B.H.as<double>(), B.J.as<double>(), B.Dx.as<double>(),
                        B.JT.as<double>(), B.HF.as<double>(), B.Dxp.as<double>());
     HIPCHK(hipStreamSynchronize(st));   // host staging vectors go out of scope
 }
 
-// factor all instances of B whose active flag is set; returns per-instance
-// min failing permuted column (INT_MAX = ok) in B.h_fail
+// factor all entries of B whose active flag is set; returns per (entry,
+// member) the min failing permuted column (INT_MAX = ok) in B.h_fail
 static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h) {
     hipStream_t st = c->stream;
     alloc_factor(c, B);
     HIPCHK(hipMemcpyAsync(B.active.p, active_h.data(), B.nb * 4, hipMemcpyHostToDevice, st));
     if (B.prec == HKKT_MIXED) launch_factor<float>(c, B, B.active.as<int>());
     else launch_factor<double>(c, B, B.active.as<int>());
-    B.h_fail.assign(B.nb, INT_MAX);
-    HIPCHK(hipMemcpyAsync(B.h_fail.data(), B.fail.p, B.nb * 4, hipMemcpyDeviceToHost, st));
+    B.h_fail.assign((size_t)B.nb * c->sym.S.G, INT_MAX);
+    HIPCHK(hipMemcpyAsync(B.h_fail.data(), B.fail.p, B.h_fail.size() * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------------------
-// one hybrid pass on the residual (g1, g2) of the nids instances listed in
-// B.ids_pass: ex, y <- approx K^{-1} g (Algorithm 1, solve phase)
+// one hybrid pass on the residual (g1, g2) of the nids batch entries listed
+// in B.ids_pass (members flagged in B.cact for a group):
+// ex, y <- approx K^{-1} g (Algorithm 1, solve phase)
 // ---------------------------------------------------------------------------
 template <typename T>
 static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_tol, std::vector<CGState>& hst) {
@@ -644,9 +672,12 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
     const DevSym& D = c->dev;
     hipStream_t st = c->stream;
     const int* ids = B.ids_pass.as<int>();
+    const int G = S.G;
+    const int* cact = G > 1 ? B.cact.as<int>() : nullptr;
     const ValView V = B.vals();
     CGState* cst = B.st.as<CGState>();
     const unsigned gn = grid1(S.n, 4096), gm = grid1(S.m);
+    const unsigned nbm = (unsigned)D.v.nbm;
     T* X = B.X.as<T>();
     // rhat = g1 + gamma J^T g2; w = H_gamma^{-1} rhat
     LAUNCH(5, k_jt<double>, dim3(gn, nids), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
@@ -655,14 +686,17 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
            (const CGState*)nullptr);
     launch_trisolve<T>(c, B, ids, nids, nullptr);
     // bvec = J w - g2 (eq. Schur1 right-hand side)
-    const unsigned gmb = (unsigned)std::max<i64>(1, (S.m + kBlock - 1) / kBlock);
-    LAUNCH(6, k_j<T>, dim3(gmb, nids), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
-           (const double*)nullptr, (const CGState*)nullptr, 0, B.bvec.as<double>(), B.part1.as<double>(),
-           (double*)nullptr, ids);
-    LAUNCH(8, k_cg_init, dim3(nids), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, ids, (i64)S.m);
-    LAUNCH(7, k_cg_vecinit, dim3(gm, nids), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
-           B.res.as<double>(), B.p.as<double>(), (i64)S.m, ids);
-    // CG on S y = bvec over a shrinking list of live instances
+    if (nbm > 0) {
+        LAUNCH(6, k_j<T>, dim3(nbm, nids), dim3(kBlock), 0, st, D.v, V, (const T*)X, B.g2.as<double>(),
+               (const double*)nullptr, (const CGState*)nullptr, 0, B.bvec.as<double>(), B.part1.as<double>(),
+               (double*)nullptr, ids);
+    }
+    LAUNCH(8, k_cg_init, dim3(nids, G), dim3(kBlock), 0, st, D.v, cst, (const double*)B.part1.as<double>(), ids, cact);
+    if (S.m > 0) {
+        LAUNCH(7, k_cg_vecinit, dim3(gm, nids), dim3(kBlock), 0, st, B.bvec.as<double>(), B.y.as<double>(),
+               B.res.as<double>(), B.p.as<double>(), (i64)S.m, ids);
+    }
+    // CG on S y = bvec over a shrinking list of live batch entries
     int* cur = B.ids_a.as<int>();
     int* nxt = B.ids_b.as<int>();
     HIPCHK(hipMemcpyAsync(cur, ids, (size_t)nids * 4, hipMemcpyDeviceToDevice, st));
@@ -672,20 +706,20 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
         LAUNCH(5, k_jt<T>, dim3(gn, ncur), dim3(kBlock), 0, st, D.v, V, (const double*)nullptr, 1.0, 0,
                B.p.as<double>(), X, (const int*)cur, (const CGState*)cst);
         launch_trisolve<T>(c, B, cur, ncur, cst);
-        LAUNCH(6, k_j<T>, dim3(gmb, ncur), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
+        LAUNCH(6, k_j<T>, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
                B.p.as<double>(), (const CGState*)cst, 1, B.q.as<double>(), B.part1.as<double>(), B.part2.as<double>(),
                (const int*)cur);
-        LAUNCH(8, k_cg_alpha, dim3(ncur), dim3(kBlock), 0, st, cst, B.part1.as<double>(), B.part2.as<double>(),
-               (int)gmb, c->opt.quad_form_eps, c->opt.delta2, (const int*)cur);
-        LAUNCH(7, k_cg_update, dim3(gmb, ncur), dim3(kBlock), 0, st, B.p.as<double>(), B.q.as<double>(),
-               B.bvec.as<double>(), B.y.as<double>(), B.res.as<double>(), (const CGState*)cst, (i64)S.m,
-               B.part1.as<double>(), (const int*)cur);
-        LAUNCH(8, k_cg_beta, dim3(ncur), dim3(kBlock), 0, st, cst, B.part1.as<double>(), (int)gmb, cg_tol, max_cg,
-               (const int*)cur);
-        LAUNCH(7, k_cg_p, dim3(gm, ncur), dim3(kBlock), 0, st, B.p.as<double>(), B.res.as<double>(),
-               (const CGState*)cst, (i64)S.m, (const int*)cur);
+        LAUNCH(8, k_cg_alpha, dim3(ncur, G), dim3(kBlock), 0, st, D.v, cst, (const double*)B.part1.as<double>(),
+               (const double*)B.part2.as<double>(), c->opt.quad_form_eps, c->opt.delta2, (const int*)cur);
+        LAUNCH(7, k_cg_update, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, (const double*)B.p.as<double>(),
+               (const double*)B.q.as<double>(), (const double*)B.bvec.as<double>(), B.y.as<double>(),
+               B.res.as<double>(), (const CGState*)cst, B.part1.as<double>(), (const int*)cur);
+        LAUNCH(8, k_cg_beta, dim3(ncur, G), dim3(kBlock), 0, st, D.v, cst, (const double*)B.part1.as<double>(),
+               cg_tol, max_cg, (const int*)cur);
+        LAUNCH(7, k_cg_p, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, B.p.as<double>(),
+               (const double*)B.res.as<double>(), (const CGState*)cst, (const int*)cur);
         if ((it + 1) % check_every == 0) {
-            LAUNCH(8, k_compact_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, (const int*)cur, ncur, nxt,
+            LAUNCH(8, k_compact_live, dim3(1), dim3(kBlock), 0, st, (const CGState*)cst, G, (const int*)cur, ncur, nxt,
                    B.live.as<int>());
             int live = 0;
             HIPCHK(hipMemcpyAsync(&live, B.live.p, 4, hipMemcpyDeviceToHost, st));
@@ -700,47 +734,60 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
     launch_trisolve<T>(c, B, ids, nids, nullptr);
     LAUNCH(10, (k_cast<T, double>), dim3(gn, nids), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
            ids, (const CGState*)nullptr);
-    hst.resize(B.nb);
-    HIPCHK(hipMemcpyAsync(hst.data(), cst, B.nb * sizeof(CGState), hipMemcpyDeviceToHost, st));
+    hst.resize((size_t)B.nb * G);
+    HIPCHK(hipMemcpyAsync(hst.data(), cst, hst.size() * sizeof(CGState), hipMemcpyDeviceToHost, st));
 }
 
-// for the nids instances in ids: (if add) z += e; g = r - K z; ||g||^2 into
-// rsq (host, indexed by instance)
+// for the nids batch entries in ids: (if add) z += e on the members of the
+// pass; g = r - K z; ||g||^2 per (entry, member) into rsq (host)
 static void update_residual(hkkt_ctx* c, Batch& B, const int* ids, int nids, std::vector<double>& rsq, bool add,
                             double* floor_out) {
     const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
     hipStream_t st = c->stream;
-    rsq.assign(B.nb, 0.0);
+    const int G = S.G;
+    const size_t nc = (size_t)B.nb * G;
+    rsq.assign(nc, 0.0);
     if (nids <= 0) return;
+    const unsigned nbr = (unsigned)D.v.nbr;
     if (add) {
-        LAUNCH(10, k_axpy2, dim3(grid1(S.n + S.m, 4096), nids), dim3(kBlock), 0, st, B.xz.as<double>(),
-               B.ex.as<double>(), (i64)S.n, B.yz.as<double>(), B.y.as<double>(), (i64)S.m, ids);
+        LAUNCH(10, k_axpy2, dim3(nbr, nids), dim3(kBlock), 0, st, D.v, B.xz.as<double>(),
+               (const double*)B.ex.as<double>(), B.yz.as<double>(), (const double*)B.y.as<double>(), ids,
+               (const int*)(G > 1 ? B.cact.as<int>() : nullptr));
     }
-    const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
-    LAUNCH(9, k_residual, dim3(g, nids), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.r1p.as<double>(),
+    LAUNCH(9, k_residual, dim3(nbr, nids), dim3(kBlock), 0, st, D.v, B.vals(), B.r1p.as<double>(),
            B.r2.as<double>(), B.xz.as<double>(), B.yz.as<double>(), B.g1.as<double>(), B.g2.as<double>(),
            B.part1.as<double>(), floor_out ? B.pfloor.as<double>() : (double*)nullptr, ids);
-    LAUNCH(10, k_reduce_rows, dim3(nids), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g, B.rsq.as<double>(), ids);
-    HIPCHK(hipMemcpyAsync(rsq.data(), B.rsq.p, B.nb * 8, hipMemcpyDeviceToHost, st));
+    LAUNCH(10, k_reduce_rows, dim3(nids, G), dim3(kBlock), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
+           D.v.rblk_off, B.rsq.as<double>(), ids);
+    HIPCHK(hipMemcpyAsync(rsq.data(), B.rsq.p, nc * 8, hipMemcpyDeviceToHost, st));
     if (floor_out) {
-        LAUNCH(10, k_reduce_rows, dim3(nids), dim3(kBlock), 0, st, B.pfloor.as<double>(), (int)g,
-               B.rowred.as<double>(), ids);
-        HIPCHK(hipMemcpyAsync(floor_out, B.rowred.p, B.nb * 8, hipMemcpyDeviceToHost, st));
+        LAUNCH(10, k_reduce_rows, dim3(nids, G), dim3(kBlock), 0, st, (const double*)B.pfloor.as<double>(),
+               (int)nbr, D.v.rblk_off, B.rowred.as<double>(), ids);
+        HIPCHK(hipMemcpyAsync(floor_out, B.rowred.p, nc * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
 }
 
-static int upload_ids(hkkt_ctx* c, DBuf& dst, const std::vector<int>& flags) {
+// flags per (entry, member): the list of entries with any flagged member
+// goes to dst, the flags themselves to B.cact (groups). Returns the count.
+static int upload_ids(hkkt_ctx* c, Batch& B, DBuf& dst, const std::vector<int>& flags) {
+    const int G = c->sym.S.G;
     std::vector<int> ids;
-    for (int i = 0; i < (int)flags.size(); i++)
-        if (flags[i]) ids.push_back(i);
+    for (int b = 0; b < B.nb; b++) {
+        bool any = false;
+        for (int k = 0; k < G; k++) any = any || flags[(size_t)b * G + k];
+        if (any) ids.push_back(b);
+    }
     if (!ids.empty()) {
         HIPCHK(hipMemcpyAsync(dst.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, c->stream));
+        if (G > 1) HIPCHK(hipMemcpyAsync(B.cact.p, flags.data(), flags.size() * 4, hipMemcpyHostToDevice, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     }
     return (int)ids.size();
 }
 
+// per (entry, member) solve state of the refinement
 struct InstState {
     int status = HKKT_NOT_CONVERGED;
     int cg = 0, passes = 0, brk = 0;
@@ -748,10 +795,10 @@ struct InstState {
     bool fallback = false;
 };
 
-// refinement loop on batch B for the instances with run[i] set; vectors
-// r1p/r2 and (if warm) xz/yz must be in place. Mixed precision
+// refinement loop on batch B for the (entry, member) pairs with run[i] set;
+// vectors r1p/r2 and (if warm) xz/yz must be in place. Mixed precision
 // (allow_stall_exit): a pass that does not halve RR, or six passes, hands the
-// instance to the FP64 fallback. FP64: a pass that does not halve RR ends
+// member to the FP64 fallback. FP64: a pass that does not halve RR ends
 // refinement (RR is then at the FP64 evaluation floor) and the status stays
 // NOT_CONVERGED unless RR <= kkt_tol.
 static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std::vector<int>& run, bool warm,
@@ -759,6 +806,7 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
     const Symbolic& S = c->sym.S;
     hipStream_t st = c->stream;
     const int nb = B.nb;
+    const int nc = nb * S.G;
     const hkkt_options& o = c->opt;
     std::vector<int> act(run);
     const int max_cg = o.max_cg > 0 ? o.max_cg : (int)std::max<i64>(1, std::min<i64>(S.m, 1000));
@@ -772,9 +820,9 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
                    (i64)nb * S.m, 0.0);
         }
     }
-    int nids = upload_ids(c, B.ids_pass, act);
+    int nids = upload_ids(c, B, B.ids_pass, act);
     update_residual(c, B, B.ids_pass.as<int>(), nids, rsq, false, nullptr);
-    for (int i = 0; i < nb; i++)
+    for (int i = 0; i < nc; i++)
         if (act[i]) {
             is[i].rr_prev = is[i].rnorm > 0 ? std::sqrt(rsq[i]) / is[i].rnorm : 0.0;
             if (is[i].rnorm == 0.0 || is[i].rr_prev <= o.kkt_tol) {
@@ -787,12 +835,12 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
     static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
     std::vector<CGState> hst;
     for (int pass = 0; pass <= max_ref; pass++) {
-        nids = upload_ids(c, B.ids_pass, act);
+        nids = upload_ids(c, B, B.ids_pass, act);
         if (nids == 0) break;
         if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, nids, max_cg, cg_tol, hst);
         else hybrid_pass<double>(c, B, nids, max_cg, cg_tol, hst);
         update_residual(c, B, B.ids_pass.as<int>(), nids, rsq, true, nullptr);
-        for (int i = 0; i < nb; i++) {
+        for (int i = 0; i < nc; i++) {
             if (!act[i]) continue;
             InstState& s = is[i];
             const double rr = s.rnorm > 0 ? std::sqrt(rsq[i]) / s.rnorm : 0.0;
@@ -829,6 +877,58 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// argument check of a group's member offsets ("" if fine)
+static std::string group_args_error(int G, const int64_t* xo, const int64_t* yo, int64_t n, int64_t m) {
+    if (G < 1 || G > 65535) return "group size must be in [1, 65535]";
+    if (G == 1) return "";
+    if (!xo || !yo) return "group offsets missing";
+    if (xo[0] != 0 || yo[0] != 0 || xo[G] != n || yo[G] != m) return "group offsets do not cover the system";
+    for (int k = 0; k < G; k++)
+        if (xo[k + 1] <= xo[k] || yo[k + 1] < yo[k])
+            return "group offsets not increasing (every member needs at least one variable)";
+    return "";
+}
+
+#define ABI_GUARD(ctx, ...)                                              \
+    try {                                                                \
+        __VA_ARGS__                                                      \
+    } catch (const hkkt::Error& e) {                                     \
+        if (ctx) (ctx)->err = e.what();                                  \
+        return e.code;                                                   \
+    } catch (const std::bad_alloc&) {                                    \
+        if (ctx) (ctx)->err = "host out of memory";                      \
+        return HKKT_ERR_OOM;                                             \
+    } catch (const std::exception& e) {                                  \
+        if (ctx) (ctx)->err = e.what();                                  \
+        return HKKT_ERR_DEVICE;                                          \
+    }
+
+static int analyze_ctx(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* y_off, int64_t n, int64_t m,
+                       const int64_t* Hp, const int32_t* Hi, const int64_t* Jp, const int32_t* Ji, const int32_t* perm) {
+    if (!c) return HKKT_ERR_ARG;
+    const std::string ge = group_args_error(G, x_off, y_off, n, m);
+    if (!ge.empty()) { c->err = ge; return HKKT_ERR_ARG; }
+    ABI_GUARD(c, {
+        const double t0 = now_ms();
+        c->analysed = false;
+        c->factored = false;
+        AnalyzeOptions ao;
+        ao.ordering = c->opt.ordering;
+        ao.relax = c->opt.relax;
+        std::string e = analyze(c->sym.S, n, m, Hp, Hi, Jp, Ji, perm, ao, G, x_off, y_off);
+        if (!e.empty()) {
+            c->err = e;
+            return (n < 1 || m < 0) ? HKKT_ERR_ARG : HKKT_ERR_PATTERN;
+        }
+        HIPCHK(hipSetDevice(c->device));
+        build_devsym(c->dev, c->sym.S, c->stream, lds_rows_limit(c->opt.precision == HKKT_MIXED ? 4 : 8));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->analysed = true;
+        c->ms[0] = now_ms() - t0;
+        return HKKT_OK;
+    })
+}
+
 extern "C" {
 
 void hkkt_default_options(hkkt_options* o) {
@@ -846,20 +946,6 @@ void hkkt_default_options(hkkt_options* o) {
     o->relax = 1;
     o->deterministic = 0;
 }
-
-#define ABI_GUARD(ctx, ...)                                              \
-    try {                                                                \
-        __VA_ARGS__                                                      \
-    } catch (const hkkt::Error& e) {                                     \
-        if (ctx) (ctx)->err = e.what();                                  \
-        return e.code;                                                   \
-    } catch (const std::bad_alloc&) {                                    \
-        if (ctx) (ctx)->err = "host out of memory";                      \
-        return HKKT_ERR_OOM;                                             \
-    } catch (const std::exception& e) {                                  \
-        if (ctx) (ctx)->err = e.what();                                  \
-        return HKKT_ERR_DEVICE;                                          \
-    }
 
 int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
     if (!out) return HKKT_ERR_ARG;
@@ -886,17 +972,22 @@ void hkkt_destroy(hkkt_ctx* c) {
 
 const char* hkkt_last_error(const hkkt_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int hkkt_symbolic_create(hkkt_symbolic** out, int64_t n, int64_t m, const int64_t* Hp, const int32_t* Hi,
-                         const int64_t* Jp, const int32_t* Ji, const int32_t* perm, int ordering, int relax, char* err,
-                         int errlen) {
+int hkkt_symbolic_create_group(hkkt_symbolic** out, int G, const int64_t* x_off, const int64_t* y_off, int64_t n,
+                               int64_t m, const int64_t* Hp, const int32_t* Hi, const int64_t* Jp, const int32_t* Ji,
+                               const int32_t* perm, int ordering, int relax, char* err, int errlen) {
     if (!out) return HKKT_ERR_ARG;
     *out = nullptr;
+    const std::string ge = group_args_error(G, x_off, y_off, n, m);
+    if (!ge.empty()) {
+        if (err && errlen > 0) std::snprintf(err, errlen, "%s", ge.c_str());
+        return HKKT_ERR_ARG;
+    }
     try {
         std::unique_ptr<hkkt_symbolic> s(new hkkt_symbolic());
         AnalyzeOptions ao;
         ao.ordering = ordering;
         ao.relax = relax;
-        std::string e = analyze(s->S, n, m, Hp, Hi, Jp, Ji, perm, ao);
+        std::string e = analyze(s->S, n, m, Hp, Hi, Jp, Ji, perm, ao, G, x_off, y_off);
         if (!e.empty()) {
             if (err && errlen > 0) { std::snprintf(err, errlen, "%s", e.c_str()); }
             return (n < 1 || m < 0) ? HKKT_ERR_ARG : HKKT_ERR_PATTERN;
@@ -906,6 +997,13 @@ int hkkt_symbolic_create(hkkt_symbolic** out, int64_t n, int64_t m, const int64_
     } catch (const std::bad_alloc&) {
         return HKKT_ERR_OOM;
     }
+}
+
+int hkkt_symbolic_create(hkkt_symbolic** out, int64_t n, int64_t m, const int64_t* Hp, const int32_t* Hi,
+                         const int64_t* Jp, const int32_t* Ji, const int32_t* perm, int ordering, int relax, char* err,
+                         int errlen) {
+    return hkkt_symbolic_create_group(out, 1, nullptr, nullptr, n, m, Hp, Hi, Jp, Ji, perm, ordering, relax, err,
+                                      errlen);
 }
 
 void hkkt_symbolic_destroy(hkkt_symbolic* s) { delete s; }
@@ -950,26 +1048,12 @@ int hkkt_symbolic_supernodes(const hkkt_symbolic* sym, int32_t* sn_first, int64_
 
 int hkkt_analyze(hkkt_ctx* c, int64_t n, int64_t m, const int64_t* Hp, const int32_t* Hi, const int64_t* Jp,
                  const int32_t* Ji, const int32_t* perm) {
-    if (!c) return HKKT_ERR_ARG;
-    ABI_GUARD(c, {
-        const double t0 = now_ms();
-        c->analysed = false;
-        c->factored = false;
-        AnalyzeOptions ao;
-        ao.ordering = c->opt.ordering;
-        ao.relax = c->opt.relax;
-        std::string e = analyze(c->sym.S, n, m, Hp, Hi, Jp, Ji, perm, ao);
-        if (!e.empty()) {
-            c->err = e;
-            return (n < 1 || m < 0) ? HKKT_ERR_ARG : HKKT_ERR_PATTERN;
-        }
-        HIPCHK(hipSetDevice(c->device));
-        build_devsym(c->dev, c->sym.S, c->stream, lds_rows_limit(c->opt.precision == HKKT_MIXED ? 4 : 8));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        c->analysed = true;
-        c->ms[0] = now_ms() - t0;
-        return HKKT_OK;
-    })
+    return analyze_ctx(c, 1, nullptr, nullptr, n, m, Hp, Hi, Jp, Ji, perm);
+}
+
+int hkkt_analyze_group(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* y_off, int64_t n, int64_t m,
+                       const int64_t* Hp, const int32_t* Hi, const int64_t* Jp, const int32_t* Ji) {
+    return analyze_ctx(c, G, x_off, y_off, n, m, Hp, Hi, Jp, Ji, nullptr);
 }
 
 int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* delta,
@@ -983,6 +1067,8 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
     ABI_GUARD(c, {
         const double t0 = now_ms();
         const Symbolic& S = c->sym.S;
+        const int G = S.G;
+        const int nc = nb * G;
         const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
         c->factored = false;
         c->nb = nb;
@@ -990,41 +1076,45 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         load_values(c, c->main, H, Dx, J, delta, gamma, nullptr, dev);
         std::vector<int> all(nb, 1);
         factor_batch(c, c->main, all);
-        c->fstatus.assign(nb, HKKT_OK);
-        c->ffail.assign(nb, -1);
-        c->fp64_factored.assign(nb, 0);
-        c->solved.assign(nb, -100);
-        c->breakdown.assign(nb, 0);
+        c->fstatus.assign(nc, HKKT_OK);
+        c->ffail.assign(nc, -1);
+        c->fp64_factored.assign(nc, 0);
+        c->solved.assign(nc, -100);
+        c->breakdown.assign(nc, 0);
         c->fb_idx.clear();
-        std::vector<int> fpos(nb, INT_MAX);
+        std::vector<int> fpos(nc, INT_MAX);
         for (int b = 0; b < nb; b++) {
-            if (c->main.h_fail[b] != INT_MAX) {
-                if (c->opt.precision == HKKT_MIXED) c->fb_idx.push_back(b);
-                else fpos[b] = c->main.h_fail[b];
-            }
+            bool any = false;
+            for (int k = 0; k < G; k++) any = any || c->main.h_fail[(size_t)b * G + k] != INT_MAX;
+            if (!any) continue;
+            if (c->opt.precision == HKKT_MIXED) c->fb_idx.push_back(b);
+            else
+                for (int k = 0; k < G; k++) fpos[(size_t)b * G + k] = c->main.h_fail[(size_t)b * G + k];
         }
-        // mixed precision: FP32 factor failed -> FP64 refactor of those instances
+        // mixed precision: FP32 factor failed -> FP64 refactor of those entries
         if (!c->fb_idx.empty()) {
             const double t1 = now_ms();
             alloc_values(c, c->fb, (int)c->fb_idx.size());
             load_values(c, c->fb, H, Dx, J, delta, gamma, &c->fb_idx, dev);
             std::vector<int> act(c->fb_idx.size(), 1);
             factor_batch(c, c->fb, act);
-            for (size_t i = 0; i < c->fb_idx.size(); i++) {
-                c->fp64_factored[c->fb_idx[i]] = 1;
-                if (c->fb.h_fail[i] != INT_MAX) fpos[c->fb_idx[i]] = c->fb.h_fail[i];
-            }
+            for (size_t i = 0; i < c->fb_idx.size(); i++)
+                for (int k = 0; k < G; k++) {
+                    const size_t ci = (size_t)c->fb_idx[i] * G + k;
+                    c->fp64_factored[ci] = 1;
+                    fpos[ci] = c->fb.h_fail[i * G + k];
+                }
             c->ms[3] = now_ms() - t1;
         }
         int rc = HKKT_OK;
-        for (int b = 0; b < nb; b++) {
-            if (fpos[b] != INT_MAX) {
-                c->fstatus[b] = HKKT_NOT_SPD;
-                c->ffail[b] = S.perm[fpos[b]];
+        for (int i = 0; i < nc; i++) {
+            if (fpos[i] != INT_MAX) {
+                c->fstatus[i] = HKKT_NOT_SPD;
+                c->ffail[i] = S.perm[fpos[i]];
                 rc = HKKT_NOT_SPD;
             }
-            if (status) status[b] = c->fstatus[b];
-            if (fail_col) fail_col[b] = c->ffail[b];
+            if (status) status[i] = c->fstatus[i];
+            if (fail_col) fail_col[i] = c->ffail[i];
         }
         c->factored = true;
         c->ms[1] = now_ms() - t0;
@@ -1034,6 +1124,7 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
 
 int hkkt_factor(hkkt_ctx* c, const double* H, const double* Dx, const double* J, double delta, double gamma,
                 int64_t* fail_col) {
+    if (c && c->analysed && c->sym.S.G != 1) { c->err = "hkkt_factor takes a single pattern"; return HKKT_ERR_STATE; }
     int st = 0;
     return hkkt_factor_batch(c, 1, H, Dx, J, &delta, &gamma, &st, fail_col);
 }
@@ -1045,6 +1136,9 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
     ABI_GUARD(c, {
         const double t0 = now_ms();
         const Symbolic& S = c->sym.S;
+        const DevSym& D = c->dev;
+        const int G = S.G;
+        const int nc = nb * G;
         hipStream_t st = c->stream;
         const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
         const hipMemcpyKind in_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1053,30 +1147,35 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         alloc_solve(c, B);
         // right-hand side into the permuted order (staged through ex / g2)
         HIPCHK(hipMemcpyAsync(B.ex.p, r1, (size_t)nb * S.n * 8, in_kind, st));
-        LAUNCH(10, k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+        LAUNCH(10, k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, D.v.perm,
                            B.ex.as<double>(), B.r1p.as<double>(), (i64)S.n);
         if (S.m > 0) HIPCHK(hipMemcpyAsync(B.r2.p, r2, (size_t)nb * S.m * 8, in_kind, st));
-        // ||r|| per instance
-        const unsigned g = (unsigned)((S.n + S.m + kBlock - 1) / kBlock);
-        LAUNCH(10, k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.r1p.as<double>(), (i64)S.n, B.r2.as<double>(),
-                           (i64)S.m, B.part1.as<double>());
-        LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
-                           B.rowred.as<double>(), (const int*)nullptr);
-        std::vector<double> rn2(nb);
-        HIPCHK(hipMemcpyAsync(rn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
+        // ||r|| per (entry, member)
+        const unsigned nbr = (unsigned)D.v.nbr;
+        LAUNCH(10, k_sumsq2, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, (const double*)B.r1p.as<double>(),
+               (const double*)B.r2.as<double>(), B.part1.as<double>());
+        LAUNCH(10, k_reduce_rows, dim3(nb, G), dim3(kBlock), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
+               D.v.rblk_off, B.rowred.as<double>(), (const int*)nullptr);
+        std::vector<double> rn2(nc);
+        HIPCHK(hipMemcpyAsync(rn2.data(), B.rowred.p, nc * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        std::vector<InstState> is(nb);
-        std::vector<int> run(nb, 0);
-        for (int b = 0; b < nb; b++) {
-            is[b].rnorm = std::sqrt(rn2[b]);
-            run[b] = c->fstatus[b] == HKKT_OK && !c->fp64_factored[b];
+        std::vector<InstState> is(nc);
+        std::vector<int> run(nc, 0);
+        for (int i = 0; i < nc; i++) {
+            is[i].rnorm = std::sqrt(rn2[i]);
+            run[i] = c->fstatus[i] == HKKT_OK && !c->fp64_factored[i];
         }
         const bool mixed = B.prec == HKKT_MIXED;
         refine(c, B, is, run, false, mixed);
-        // FP64 completion for mixed-precision fallbacks
+        // FP64 completion for mixed-precision fallbacks: the batch entries
+        // with a member that needs it form the FP64 sub-batch
+        auto needs_fp64 = [&](int i) { return c->fstatus[i] == HKKT_OK && (c->fp64_factored[i] || is[i].fallback); };
         std::vector<int> fbl;
-        for (int b = 0; b < nb; b++)
-            if (c->fstatus[b] == HKKT_OK && (c->fp64_factored[b] || is[b].fallback)) fbl.push_back(b);
+        for (int b = 0; b < nb; b++) {
+            bool any = false;
+            for (int k = 0; k < G; k++) any = any || needs_fp64(b * G + k);
+            if (any) fbl.push_back(b);
+        }
         if (!fbl.empty()) {
             const double t1 = now_ms();
             Batch& F = c->fb;
@@ -1092,28 +1191,31 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                     };
                     cp(F.H, B.H, S.nnzH); cp(F.J, B.J, S.nnzJ); cp(F.JT, B.JT, S.nnzJ);
                     cp(F.HF, B.HF, (i64)S.HF_col.size()); cp(F.Dx, B.Dx, S.n); cp(F.Dxp, B.Dxp, S.n);
-                    cp(F.delta, B.delta, 1); cp(F.gamma, B.gamma, 1);
+                    cp(F.delta, B.delta, G); cp(F.gamma, B.gamma, G);
                 }
                 std::vector<int> act(fbl.size(), 1);
                 factor_batch(c, F, act);
                 c->fb_idx = fbl;
-                for (size_t i = 0; i < fbl.size(); i++) {
-                    c->fp64_factored[fbl[i]] = 1;
-                    if (F.h_fail[i] != INT_MAX) {
-                        is[fbl[i]].status = HKKT_NOT_SPD;
+                for (size_t i = 0; i < fbl.size(); i++)
+                    for (int k = 0; k < G; k++) {
+                        const int ci = fbl[i] * G + k;
+                        c->fp64_factored[ci] = 1;
+                        if (needs_fp64(ci) && F.h_fail[i * G + k] != INT_MAX) is[ci].status = HKKT_NOT_SPD;
                     }
-                }
             }
             alloc_solve(c, F);
             const int nf = (int)fbl.size();
-            std::vector<InstState> fs(nf);
-            std::vector<int> frun(nf, 1);
+            std::vector<InstState> fs((size_t)nf * G);
+            std::vector<int> frun((size_t)nf * G, 0);
             for (int i = 0; i < nf; i++) {
                 const int b = fbl[i];
-                fs[i].rnorm = is[b].rnorm;
-                fs[i].cg = is[b].cg;
-                fs[i].passes = is[b].passes;
-                frun[i] = F.h_fail[i] == INT_MAX;
+                for (int k = 0; k < G; k++) {
+                    const size_t fi = (size_t)i * G + k, ci = (size_t)b * G + k;
+                    fs[fi].rnorm = is[ci].rnorm;
+                    fs[fi].cg = is[ci].cg;
+                    fs[fi].passes = is[ci].passes;
+                    frun[fi] = needs_fp64((int)ci) && F.h_fail[fi] == INT_MAX;
+                }
                 auto cp = [&](DBuf& d, const DBuf& s, i64 len) {
                     if (len > 0)
                         HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, s.as<double>() + (i64)b * len,
@@ -1121,7 +1223,8 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                 };
                 cp(F.r1p, B.r1p, S.n); cp(F.r2, B.r2, S.m); cp(F.xz, B.xz, S.n); cp(F.yz, B.yz, S.m);
             }
-            // start from the mixed-precision iterate when there is one
+            // start from the mixed-precision iterate when there is one; the
+            // members that do not run keep their iterate unchanged
             refine(c, F, fs, frun, true, false);
             for (int i = 0; i < nf; i++) {
                 const int b = fbl[i];
@@ -1131,59 +1234,64 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                                               (size_t)len * 8, hipMemcpyDeviceToDevice, st));
                 };
                 cpb(B.xz, F.xz, S.n); cpb(B.yz, F.yz, S.m);
-                if (frun[i]) {
-                    is[b].status = fs[i].status;
-                    is[b].rr = fs[i].rr;
-                    is[b].brk = fs[i].brk;
-                    is[b].cg = fs[i].cg;
-                    is[b].passes = fs[i].passes;
+                for (int k = 0; k < G; k++) {
+                    const size_t fi = (size_t)i * G + k, ci = (size_t)b * G + k;
+                    if (!needs_fp64((int)ci)) continue;
+                    if (frun[fi]) {
+                        is[ci].status = fs[fi].status;
+                        is[ci].rr = fs[fi].rr;
+                        is[ci].brk = fs[fi].brk;
+                        is[ci].cg = fs[fi].cg;
+                        is[ci].passes = fs[fi].passes;
+                    }
+                    is[ci].fallback = true;
                 }
-                is[b].fallback = true;
             }
             HIPCHK(hipStreamSynchronize(st));
             c->ms[3] = now_ms() - t1;
         }
-        // final metrics: RR, BE, floor on the full KKT residual
-        std::vector<int> allact(nb);
-        for (int b = 0; b < nb; b++) allact[b] = c->fstatus[b] == HKKT_OK;
-        const int nall = upload_ids(c, B.ids_all, allact);
-        std::vector<double> rsq, fl(nb, 0.0);
+        // final metrics: RR, BE, floor on the full KKT residual, per member
+        std::vector<int> allact(nc);
+        for (int i = 0; i < nc; i++) allact[i] = c->fstatus[i] == HKKT_OK;
+        const int nall = upload_ids(c, B, B.ids_all, allact);
+        std::vector<double> rsq, fl(nc, 0.0);
         update_residual(c, B, B.ids_all.as<int>(), nall, rsq, false, fl.data());
-        LAUNCH(10, k_knorm_rows, dim3(g, nb), dim3(kBlock), 0, st, c->dev.v, B.vals(), B.part2.as<double>());
-        LAUNCH(10, k_reduce_max, dim3(nb), dim3(64), 0, st, B.part2.as<double>(), (int)g, B.knorm.as<double>());
-        LAUNCH(10, k_sumsq2, dim3(g, nb), dim3(kBlock), 0, st, B.xz.as<double>(), (i64)S.n, B.yz.as<double>(),
-                           (i64)S.m, B.part1.as<double>());
-        LAUNCH(10, k_reduce_rows, dim3(nb), dim3(kBlock), 0, st, B.part1.as<double>(), (int)g,
-                           B.rowred.as<double>(), (const int*)nullptr);
-        std::vector<double> kn(nb), zn2(nb);
-        HIPCHK(hipMemcpyAsync(kn.data(), B.knorm.p, nb * 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(zn2.data(), B.rowred.p, nb * 8, hipMemcpyDeviceToHost, st));
+        LAUNCH(10, k_knorm_rows, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(), B.part2.as<double>());
+        LAUNCH(10, k_reduce_max, dim3(nb, G), dim3(64), 0, st, (const double*)B.part2.as<double>(), (int)nbr,
+               D.v.rblk_off, B.knorm.as<double>());
+        LAUNCH(10, k_sumsq2, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, (const double*)B.xz.as<double>(),
+               (const double*)B.yz.as<double>(), B.part1.as<double>());
+        LAUNCH(10, k_reduce_rows, dim3(nb, G), dim3(kBlock), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
+               D.v.rblk_off, B.rowred.as<double>(), (const int*)nullptr);
+        std::vector<double> kn(nc), zn2(nc);
+        HIPCHK(hipMemcpyAsync(kn.data(), B.knorm.p, nc * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(zn2.data(), B.rowred.p, nc * 8, hipMemcpyDeviceToHost, st));
         // outputs in the original order
-        LAUNCH(10, k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
+        LAUNCH(10, k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, D.v.perm,
                            B.xz.as<double>(), B.ex.as<double>(), (i64)S.n);
         HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, out_kind, st));
         if (S.m > 0) HIPCHK(hipMemcpyAsync(y, B.yz.p, (size_t)nb * S.m * 8, out_kind, st));
         HIPCHK(hipStreamSynchronize(st));
         int rc = HKKT_OK;
-        for (int b = 0; b < nb; b++) {
-            InstState& s = is[b];
-            int stt = c->fstatus[b] == HKKT_OK ? s.status : c->fstatus[b];
+        for (int i = 0; i < nc; i++) {
+            InstState& s = is[i];
+            int stt = c->fstatus[i] == HKKT_OK ? s.status : c->fstatus[i];
             const double rnorm = s.rnorm;
-            const double rr = c->fstatus[b] == HKKT_OK ? (rnorm > 0 ? std::sqrt(rsq[b]) / rnorm : std::sqrt(rsq[b])) : NAN;
+            const double rr = c->fstatus[i] == HKKT_OK ? (rnorm > 0 ? std::sqrt(rsq[i]) / rnorm : std::sqrt(rsq[i])) : NAN;
             if (stt == HKKT_NOT_CONVERGED && rr <= c->opt.kkt_tol) stt = HKKT_OK;
-            c->solved[b] = stt;
-            c->breakdown[b] = s.brk;
+            c->solved[i] = stt;
+            c->breakdown[i] = s.brk;
             rc = std::max(rc, stt);
             if (info) {
-                hkkt_info& I = info[b];
+                hkkt_info& I = info[i];
                 I.status = stt;
                 I.cg_iters = s.cg;
                 I.passes = s.passes;
                 I.fp64_fallback = s.fallback ? 1 : 0;
                 I.rr = rr;
-                I.be = std::sqrt(rsq[b]) / (kn[b] * std::sqrt(zn2[b]) + rnorm);
-                I.floor = std::ldexp(1.0, -53) * std::sqrt(fl[b]) / (rnorm > 0 ? rnorm : 1.0);
-                I.fail_col = c->ffail[b];
+                I.be = std::sqrt(rsq[i]) / (kn[i] * std::sqrt(zn2[i]) + rnorm);
+                I.floor = std::ldexp(1.0, -53) * std::sqrt(fl[i]) / (rnorm > 0 ? rnorm : 1.0);
+                I.fail_col = c->ffail[i];
             }
         }
         c->ms[2] = now_ms() - t0;
@@ -1192,15 +1300,19 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
 }
 
 int hkkt_solve(hkkt_ctx* c, const double* r1, const double* r2, double* x, double* y, hkkt_info* info) {
+    if (c && c->analysed && c->sym.S.G != 1) { c->err = "hkkt_solve takes a single pattern"; return HKKT_ERR_STATE; }
     return hkkt_solve_batch(c, 1, r1, r2, x, y, info);
 }
 
-int hkkt_inertia(const hkkt_ctx* c, int b, int64_t out[3]) {
+int hkkt_inertia(const hkkt_ctx* c, int i, int64_t out[3]) {
     if (!c || !out) return HKKT_ERR_ARG;
-    if (!c->factored || b < 0 || b >= c->nb || c->fstatus[b] != HKKT_OK || c->solved[b] == -100) return HKKT_ERR_STATE;
-    const int64_t nu = c->breakdown[b] ? 1 : 0;
-    out[0] = c->sym.S.n;
-    out[1] = c->sym.S.m - nu;
+    if (!c->factored || i < 0 || i >= (int)c->fstatus.size() || c->fstatus[i] != HKKT_OK || c->solved[i] == -100)
+        return HKKT_ERR_STATE;
+    const Symbolic& S = c->sym.S;
+    const int k = i % S.G;
+    const int64_t nu = c->breakdown[i] ? 1 : 0;
+    out[0] = S.x_off[k + 1] - S.x_off[k];
+    out[1] = S.y_off[k + 1] - S.y_off[k] - nu;
     out[2] = nu;
     return HKKT_OK;
 }
@@ -1210,11 +1322,11 @@ int hkkt_get_factor(hkkt_ctx* c, int b, int64_t* colptr, int32_t* rowind, double
     if (!c->factored || b < 0 || b >= c->nb) return HKKT_ERR_STATE;
     ABI_GUARD(c, {
         const Symbolic& S = c->sym.S;
-        // take the FP64 fallback factor when the instance has one
+        // take the FP64 fallback factor when the entry has one
         const Batch* B = &c->main;
         i64 bi = b;
         for (size_t i = 0; i < c->fb_idx.size(); i++)
-            if (c->fb_idx[i] == b && c->fp64_factored[b]) { B = &c->fb; bi = (i64)i; }
+            if (c->fb_idx[i] == b && c->fp64_factored[(size_t)b * S.G]) { B = &c->fb; bi = (i64)i; }
         std::vector<double> Lh(S.Lsize);
         if (B->esz() == 8) {
             HIPCHK(hipMemcpy(Lh.data(), B->L.as<double>() + bi * S.Lsize, S.Lsize * 8, hipMemcpyDeviceToHost));

@@ -56,6 +56,18 @@ struct SymView {
     const i64* HF_rowptr;
     const i32* HF_col;
     const i32* HF_src;
+    // group members (G = 1 for a single pattern): a "CG instance" is
+    // c = b * G + k for batch entry b and member k
+    i32 G;
+    const i32* xp_mem;     // [n] member of permuted variable
+    const i32* a_mem;      // [nnzA]
+    const i32* sn_mem;     // [ns]
+    i32 nbm;               // member-aligned blocks over the J rows
+    const i32* mblk;       // (start, end, member) per block
+    const i32* mblk_off;   // [G+1]
+    i32 nbr;               // member-aligned blocks over [x ; y]
+    const i32* rblk;
+    const i32* rblk_off;
 };
 
 // Packed per-supernode description used by the wavefront triangular solves
@@ -68,6 +80,8 @@ struct TriDesc {
     i32 w;       // width
     i32 nr;      // rows
     i32 nchild;  // number of children (0: leaf, no gather)
+    i32 mem;     // group member
+    i32 pad;
 };
 
 // Per-batch numeric values (device, FP64 copies owned by the library).
@@ -79,8 +93,8 @@ struct ValView {
     const double* HF;     // [nb][nnzHF] full symmetric H, permuted
     const double* Dxp;    // [nb][n] D_x permuted
     const double* Dx;     // [nb][n] D_x original order
-    const double* delta;  // [nb]
-    const double* gamma;  // [nb]
+    const double* delta;  // [nb * G]
+    const double* gamma;  // [nb * G]
 };
 
 // Per-instance CG scalars.

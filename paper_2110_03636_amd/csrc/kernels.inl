@@ -10,13 +10,14 @@
 
 namespace hkkt {
 
-__device__ __forceinline__ bool skip_inst(const int* active, const CGState* st, int b) {
-    return (active && !active[b]) || (st && st[b].done);
-}
-
 // Solve-phase kernels run over a list of instance ids (the instances still
 // active); grid index k maps to instance ids[k] (ids null: k itself).
 __device__ __forceinline__ int inst_of(const int* ids, int k) { return ids ? ids[k] : k; }
+
+// Group member of permuted variable i (0 for a single pattern). Scalars of
+// member k of batch entry b (delta, gamma, CG state, failure column, norms)
+// sit at index b * G + k.
+__device__ __forceinline__ int mem_x(const SymView& S, i64 i) { return S.G > 1 ? S.xp_mem[i] : 0; }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -96,10 +97,12 @@ __global__ void k_assemble(SymView S, ValView V, T* __restrict__ L, const int* a
     if (active && !active[b]) return;
     const double* H = V.H + (i64)b * S.nnzH;
     const double* J = V.J + (i64)b * S.nnzJ;
-    const double g = V.gamma[b];
-    const double dl = V.delta[b];
+    const double* gam = V.gamma + (i64)b * S.G;
+    const double* del = V.delta + (i64)b * S.G;
     T* Lb = L + (i64)b * S.Lsize;
     for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < S.nnzA; e += (i64)gridDim.x * blockDim.x) {
+        const int k = S.G > 1 ? S.a_mem[e] : 0;
+        const double g = gam[k], dl = del[k];
         double v = 0.0;
         const i32 h = S.a_h[e];
         if (h >= 0) v += H[h];
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __re
             for (int i = kk + threadIdx.x; i < nr; i += blockDim.x) F[kk * nr + i] = i == kk ? sq : F[kk * nr + i] * inv;
         }
         if (k < w) {
-            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b], f + k);
+            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + k);
             const T invd = T(1) / dk;
             const int len = nr - k - 1;
             for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
@@ -198,60 +201,6 @@ struct FrontRef {
     }
 };
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_front_global(SymView S, const i32* __restrict__ list, T* __restrict__ L,
-                                                         T* __restrict__ CB, int* __restrict__ fail,
-                                                         const int* active) {
-    const int b = blockIdx.y;
-    if (active && !active[b]) return;
-    const i32 s = list[blockIdx.x];
-    const i32 f = S.sn_first[s];
-    FrontRef<T> F;
-    F.w = S.sn_first[s + 1] - f;
-    F.nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
-    F.nc = F.nr - F.w;
-    F.P = L + (i64)b * S.Lsize + S.sn_lptr[s];
-    F.C = CB + (i64)b * S.CBsize + S.sn_cbptr[s];
-    const int nr = F.nr, w = F.w, nc = F.nc;
-    for (i64 idx = threadIdx.x; idx < (i64)nc * nc; idx += blockDim.x) F.C[idx] = T(0);
-    __syncthreads();
-    for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; q++) {
-        const i32 c = S.child_list[q];
-        const int wc = S.sn_first[c + 1] - S.sn_first[c];
-        const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
-        const i32* rel = S.relmap + S.sn_uvptr[c];
-        const T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[c];
-        for (i64 idx = threadIdx.x; idx < (i64)ncc * ncc; idx += blockDim.x) {
-            const int j = (int)(idx / ncc), i = (int)(idx - (i64)j * ncc);
-            if (i >= j) F.at(rel[i], rel[j]) += C[idx];
-        }
-        __syncthreads();
-    }
-    T dprev = T(1);
-    for (int k = 0; k <= w; k++) {
-        const T dk = k < w ? F.at(k, k) : T(1);
-        if (k > 0) {
-            const int kk = k - 1;
-            const T sq = sqrt(dprev), inv = T(1) / sq;
-            for (int i = kk + threadIdx.x; i < nr; i += blockDim.x) F.at(i, kk) = i == kk ? sq : F.at(i, kk) * inv;
-        }
-        if (k < w) {
-            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b], f + k);
-            const T invd = T(1) / dk;
-            const int len = nr - k - 1;
-            // columns j of the trailing matrix, rows i >= j
-            for (i64 idx = threadIdx.x; idx < (i64)len * len; idx += blockDim.x) {
-                const int jj = (int)(idx / len), ii = (int)(idx - (i64)jj * len);
-                if (ii >= jj) {
-                    const int i = k + 1 + ii, j = k + 1 + jj;
-                    F.at(i, j) -= F.at(i, k) * F.at(j, k) * invd;
-                }
-            }
-        }
-        dprev = dk;
-        __syncthreads();
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Blocked partial factorization of large fronts (above the LDS limit), one
@@ -335,7 +284,8 @@ __global__ __launch_bounds__(kBlock) void k_big_potrf(SymView S, const i32* __re
             for (int i = kk + threadIdx.x; i < bw; i += blockDim.x) D[kk][i] = i == kk ? sq : D[kk][i] * inv;
         }
         if (k < bw) {
-            if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b], f + kb + k);
+            if (threadIdx.x == 0 && !pivot_ok(dk))
+                atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + kb + k);
             const T invd = T(1) / dk;
             const int len = bw - k - 1;
             for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
@@ -487,8 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
     T* D = reinterpret_cast<T*>(smem_d);
     T* u = D + kTri * kTri;
     const int b = inst_of(ids, blockIdx.y);
-    if (st && st[b].done) return;
     const i32 s = list[blockIdx.x];
+    if (st && st[(i64)b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)].done) return;
     const i32 f = S.sn_first[s];
     const int w = S.sn_first[s + 1] - f;
     const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
@@ -545,8 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
     T* D = reinterpret_cast<T*>(smem_d);
     T* u = D + kTri * kTri;
     const int b = inst_of(ids, blockIdx.y);
-    if (st && st[b].done) return;
     const i32 s = list[blockIdx.x];
+    if (st && st[(i64)b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)].done) return;
     const i32 f = S.sn_first[s];
     const int w = S.sn_first[s + 1] - f;
     const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
@@ -634,8 +584,8 @@ __device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __rest
     const int k = (int)(t0 - (i64)q * npad) + seg;
     bool valid = k < nids;
     const int b = valid ? inst_of(ids, k) : 0;
-    if (valid && st && st[b].done) valid = false;
     const TriDesc d = desc[q];
+    if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
     const T* Lb = L + (i64)b * S.Lsize + d.lptr;
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
@@ -711,8 +661,8 @@ __device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __rest
     const int k = (int)(t0 - (i64)q * npad) + seg;
     bool valid = k < nids;
     const int b = valid ? inst_of(ids, k) : 0;
-    if (valid && st && st[b].done) valid = false;
     const TriDesc d = desc[q];
+    if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
     const T* Lb = L + (i64)b * S.Lsize + d.lptr;
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
@@ -837,18 +787,21 @@ __global__ void k_inv_diag(const i64* __restrict__ diag_off, i64 n, i64 Lsize, c
 
 // ---------------------------------------------------------------------------
 // SpMV with J^T (rows = permuted columns of J):
-//   out[b][i] = a[b][i] + scale * g_b * sum_k JT[b][k] * v[b][JT_col[k]]
-// with g_b = gamma[b] if use_gamma else 1; a may be null.
+//   out[b][i] = a[b][i] + scale * g * sum_k JT[b][k] * v[b][JT_col[k]]
+// with g = gamma of the row's member if use_gamma else 1; a may be null.
+// Rows of members whose CG is done (st) are left alone.
 // ---------------------------------------------------------------------------
 template <typename TO>
 __global__ void k_jt(SymView S, ValView V, const double* __restrict__ a, double scale, int use_gamma,
                      const double* __restrict__ v, TO* __restrict__ out, const int* ids, const CGState* st) {
     const int b = inst_of(ids, blockIdx.y);
-    if (st && st[b].done) return;
-    const double sc = scale * (use_gamma ? V.gamma[b] : 1.0);
+    if (S.G == 1 && st && st[b].done) return;
     const double* JT = V.JT + (i64)b * S.nnzJ;
     const double* vb = v + (i64)b * S.m;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += (i64)gridDim.x * blockDim.x) {
+        const i64 c = (i64)b * S.G + mem_x(S, i);
+        if (S.G > 1 && st && st[c].done) continue;
+        const double sc = scale * (use_gamma ? V.gamma[c] : 1.0);
         double sum = 0.0;
         for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) sum += JT[k] * vb[S.JT_col[k]];
         const double base = a ? a[(i64)b * S.n + i] : 0.0;
@@ -856,7 +809,19 @@ __global__ void k_jt(SymView S, ValView V, const double* __restrict__ a, double 
     }
 }
 
-// SpMV with J (permuted columns), FP64 accumulation of an FP32 or FP64 input.
+// Member-aligned blocks: block j of a table covers indices [t[3j], t[3j+1])
+// of member t[3j+2]; every block holds at most kBlock indices, so one
+// work-group of kBlock threads takes one block. Partial sums of batch entry b
+// go to part[b * nblk + j] and are reduced per member over the member's
+// consecutive blocks.
+struct Blk {
+    i64 lo, hi;
+    int k;
+};
+__device__ __forceinline__ Blk blk_of(const i32* t, int j) { return {t[3 * j], t[3 * j + 1], t[3 * j + 2]}; }
+
+// SpMV with J (permuted columns), FP64 accumulation of an FP32 or FP64 input,
+// over the member-aligned blocks of the J rows (grid.x = S.nbm).
 // mode 0 (Schur right-hand side): q = J u - sub; part1 = sum q^2.
 // mode 1 (CG): q = J u + d2 * p; part1 = sum p.q; part2 = sum p.p.
 template <typename TI>
@@ -866,12 +831,14 @@ __global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __
                                               double* __restrict__ part2, const int* ids) {
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.y);
-    if (mode == 1 && st[b].done) return;
+    const Blk bk = blk_of(S.mblk, blockIdx.x);
+    const i64 c = (i64)b * S.G + bk.k;
+    if (mode == 1 && st[c].done) return;
     const double* J = V.J + (i64)b * S.nnzJ;
     const TI* ub = u + (i64)b * S.n;
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const i64 i = bk.lo + threadIdx.x;
     double a1 = 0.0, a2 = 0.0;
-    if (i < S.m) {
+    if (i < bk.hi) {
         double sum = 0.0;
         for (i64 k = S.J_rowptr[i]; k < S.J_rowptr[i + 1]; k++) sum += J[k] * (double)ub[S.J_colp[k]];
         if (mode == 0) {
@@ -879,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __
             a1 = sum * sum;
         } else {
             const double pi = p[(i64)b * S.m + i];
-            sum += st[b].d2 * pi;
+            sum += st[c].d2 * pi;
             a1 = pi * sum;
             a2 = pi * pi;
         }
@@ -894,7 +861,9 @@ __global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __
 }
 
 // ---------------------------------------------------------------------------
-// CG on S y = bvec (unpreconditioned, y0 = 0), Algorithm 1 / eq. Schur1.
+// CG on S y = bvec (unpreconditioned, y0 = 0), Algorithm 1 / eq. Schur1, one
+// independent CG per (batch entry, member). Scalar kernels: grid.x = list
+// index, grid.y = member.
 // ---------------------------------------------------------------------------
 __device__ double reduce_parts(const double* part, int nblk, double* sh) {
     double v = 0.0;
@@ -902,18 +871,25 @@ __device__ double reduce_parts(const double* part, int nblk, double* sh) {
     return block_sum(v, sh);
 }
 
-// one block per instance: rho = ||b||^2, reset the state
-__global__ void k_cg_init(CGState* st, const double* part, int nblk, const int* ids, i64 m) {
+// sum of the partials of member k of batch entry b
+__device__ __forceinline__ double reduce_member(const double* part, int nblk, const i32* off, int b, int k,
+                                                double* sh) {
+    return reduce_parts(part + (i64)b * nblk + off[k], off[k + 1] - off[k], sh);
+}
+
+// rho = ||b||^2, reset the state; members not in this pass (cact) start done
+__global__ void k_cg_init(SymView S, CGState* st, const double* part, const int* ids, const int* cact) {
     __shared__ double sh[kBlock / kWave];
-    const int b = inst_of(ids, blockIdx.x);
-    const double r = reduce_parts(part + (i64)b * nblk, nblk, sh);
+    const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
+    const i64 ci = (i64)b * S.G + k;
+    const double r = reduce_member(part, S.nbm, S.mblk_off, b, k, sh);
     if (threadIdx.x == 0) {
         CGState c = {};
         c.rho = r;
         c.bnorm = sqrt(r);
         c.curv0 = -1.0;
-        c.done = m == 0 || !(r > 0.0);
-        st[b] = c;
+        c.done = (cact && !cact[ci]) || !(r > 0.0);
+        st[ci] = c;
     }
 }
 
@@ -929,15 +905,16 @@ __global__ void k_cg_vecinit(const double* __restrict__ bvec, double* __restrict
 }
 
 // alpha = rho / p'q, with the small-quadratic-form test of Algorithm 1
-__global__ void k_cg_alpha(CGState* st, const double* part1, const double* part2, int nblk, double qf_eps,
+__global__ void k_cg_alpha(SymView S, CGState* st, const double* part1, const double* part2, double qf_eps,
                            double delta2, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = inst_of(ids, blockIdx.x);
-    if (st[b].done) return;
-    const double pq = reduce_parts(part1 + (i64)b * nblk, nblk, sh);
-    const double pp = reduce_parts(part2 + (i64)b * nblk, nblk, sh);
+    const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
+    const i64 ci = (i64)b * S.G + k;
+    if (st[ci].done) return;
+    const double pq = reduce_member(part1, S.nbm, S.mblk_off, b, k, sh);
+    const double pp = reduce_member(part2, S.nbm, S.mblk_off, b, k, sh);
     if (threadIdx.x == 0) {
-        CGState c = st[b];
+        CGState c = st[ci];
         if (c.curv0 < 0.0) c.curv0 = pq / pp;
         c.pq = pq;
         c.pp = pp;
@@ -953,29 +930,31 @@ __global__ void k_cg_alpha(CGState* st, const double* part1, const double* part2
         } else {
             c.alpha = c.rho / pq;
         }
-        st[b] = c;
+        st[ci] = c;
     }
 }
 
-// y += alpha p; res -= alpha q; partial res'res. A pending restart resets
-// y = 0, res = bvec.
-__global__ __launch_bounds__(kBlock) void k_cg_update(const double* __restrict__ p, const double* __restrict__ q,
-                                                      const double* __restrict__ bvec, double* __restrict__ y,
-                                                      double* __restrict__ res, const CGState* st, i64 m,
-                                                      double* __restrict__ part, const int* ids) {
+// y += alpha p; res -= alpha q; partial res'res (member-aligned blocks of the
+// J rows). A pending restart resets y = 0, res = bvec.
+__global__ __launch_bounds__(kBlock) void k_cg_update(SymView S, const double* __restrict__ p,
+                                                      const double* __restrict__ q, const double* __restrict__ bvec,
+                                                      double* __restrict__ y, double* __restrict__ res,
+                                                      const CGState* st, double* __restrict__ part, const int* ids) {
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.y);
-    if (st[b].done) return;
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const Blk bk = blk_of(S.mblk, blockIdx.x);
+    const CGState* cs = st + (i64)b * S.G + bk.k;
+    if (cs->done) return;
+    const i64 i = bk.lo + threadIdx.x;
     double a = 0.0;
-    if (i < m) {
-        const i64 o = (i64)b * m + i;
+    if (i < bk.hi) {
+        const i64 o = (i64)b * S.m + i;
         double r;
-        if (st[b].pad) {
+        if (cs->pad) {
             y[o] = 0.0;
             r = bvec[o];
         } else {
-            const double al = st[b].alpha;
+            const double al = cs->alpha;
             y[o] += al * p[o];
             r = res[o] - al * q[o];
         }
@@ -986,13 +965,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const double* __restrict__
     if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
 }
 
-__global__ void k_cg_beta(CGState* st, const double* part, int nblk, double tol, int max_it, const int* ids) {
+__global__ void k_cg_beta(SymView S, CGState* st, const double* part, double tol, int max_it, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = inst_of(ids, blockIdx.x);
-    if (st[b].done) return;
-    const double r1 = reduce_parts(part + (i64)b * nblk, nblk, sh);
+    const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
+    const i64 ci = (i64)b * S.G + k;
+    if (st[ci].done) return;
+    const double r1 = reduce_member(part, S.nbm, S.mblk_off, b, k, sh);
     if (threadIdx.x == 0) {
-        CGState c = st[b];
+        CGState c = st[ci];
         if (c.pad) {
             c.pad = 0;
             c.rho = r1;
@@ -1004,24 +984,27 @@ __global__ void k_cg_beta(CGState* st, const double* part, int nblk, double tol,
             c.beta = r1 / c.rho;
             c.rho = r1;
         }
-        st[b] = c;
+        st[ci] = c;
     }
 }
 
-__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ res, const CGState* st, i64 m,
+// p = res + beta p (member-aligned blocks of the J rows)
+__global__ void k_cg_p(SymView S, double* __restrict__ p, const double* __restrict__ res, const CGState* st,
                        const int* ids) {
     const int b = inst_of(ids, blockIdx.y);
-    if (st[b].done) return;
-    const double be = st[b].beta;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) {
-        const i64 o = (i64)b * m + i;
-        p[o] = res[o] + be * p[o];
+    const Blk bk = blk_of(S.mblk, blockIdx.x);
+    const CGState* cs = st + (i64)b * S.G + bk.k;
+    if (cs->done) return;
+    const i64 i = bk.lo + threadIdx.x;
+    if (i < bk.hi) {
+        const i64 o = (i64)b * S.m + i;
+        p[o] = res[o] + cs->beta * p[o];
     }
 }
 
-// Order-preserving compaction of the instances whose CG is still running
-// (one work-group): ids_out = [b in ids_in with !st[b].done], *n_out = count.
-__global__ void k_compact_live(const CGState* st, const int* ids_in, int n_in, int* ids_out, int* n_out) {
+// Order-preserving compaction of the batch entries with a member whose CG is
+// still running (one work-group): ids_out = [b in ids_in live], *n_out = count.
+__global__ void k_compact_live(const CGState* st, int G, const int* ids_in, int n_in, int* ids_out, int* n_out) {
     __shared__ int sc[kBlock];
     __shared__ int base;
     if (threadIdx.x == 0) base = 0;
@@ -1029,7 +1012,8 @@ __global__ void k_compact_live(const CGState* st, const int* ids_in, int n_in, i
     for (int c0 = 0; c0 < n_in; c0 += blockDim.x) {
         const int k = c0 + threadIdx.x;
         const int b = k < n_in ? ids_in[k] : -1;
-        const int f = (b >= 0 && !st[b].done) ? 1 : 0;
+        int f = 0;
+        for (int g = 0; b >= 0 && g < G && !f; g++) f = !st[(i64)b * G + g].done;
         sc[threadIdx.x] = f;
         __syncthreads();
         for (int o = 1; o < (int)blockDim.x; o <<= 1) {
@@ -1047,16 +1031,20 @@ __global__ void k_compact_live(const CGState* st, const int* ids_in, int n_in, i
 }
 
 // ---------------------------------------------------------------------------
-// refinement support (FP64)
+// refinement support (FP64), over the member-aligned blocks of the combined
+// index space [x (n) ; y (m)] (grid.x = S.nbr)
 // ---------------------------------------------------------------------------
-// z += e on active instances
-__global__ void k_axpy2(double* __restrict__ xz, const double* __restrict__ ex, i64 n, double* __restrict__ yz,
-                        const double* __restrict__ ey, i64 m, const int* ids) {
+// z += e for the members in this pass (cact; null: all)
+__global__ __launch_bounds__(kBlock) void k_axpy2(SymView S, double* __restrict__ xz, const double* __restrict__ ex,
+                                                  double* __restrict__ yz, const double* __restrict__ ey,
+                                                  const int* ids, const int* cact) {
     const int b = inst_of(ids, blockIdx.y);
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += (i64)gridDim.x * blockDim.x) {
-        if (i < n) xz[(i64)b * n + i] += ex[(i64)b * n + i];
-        else yz[(i64)b * m + (i - n)] += ey[(i64)b * m + (i - n)];
-    }
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    if (cact && !cact[(i64)b * S.G + bk.k]) return;
+    const i64 i = bk.lo + threadIdx.x;
+    if (i >= bk.hi) return;
+    if (i < S.n) xz[(i64)b * S.n + i] += ex[(i64)b * S.n + i];
+    else yz[(i64)b * S.m + (i - S.n)] += ey[(i64)b * S.m + (i - S.n)];
 }
 
 // g = r - K z over rows [0, n) (first block row) and [n, n+m) (J rows),
@@ -1068,11 +1056,12 @@ __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const
                                                      double* __restrict__ part_floor, const int* ids) {
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.y);
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    const i64 i = bk.lo + threadIdx.x;
     const double* x = xz + (i64)b * S.n;
     const double* y = yz + (i64)b * S.m;
     double a = 0.0, fl = 0.0;
-    if (i < S.n) {
+    if (i < bk.hi && i < S.n) {
         const double* HF = V.HF + (i64)b * S.nnzHF;
         const double* JT = V.JT + (i64)b * S.nnzJ;
         double acc = 0.0, aabs = 0.0;
@@ -1081,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const
             acc += t;
             aabs += fabs(t);
         }
-        const double dt = (V.Dxp[(i64)b * S.n + i] + V.delta[b]) * x[i];
+        const double dt = (V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + bk.k]) * x[i];
         acc += dt;
         aabs += fabs(dt);
         for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) {
@@ -1095,7 +1084,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const
         a = g * g;
         fl = aabs + fabs(rv);
         fl = fl * fl;
-    } else if (i < S.n + S.m) {
+    } else if (i < bk.hi) {
         const i64 r = i - S.n;
         const double* J = V.J + (i64)b * S.nnzJ;
         double acc = 0.0, aabs = 0.0;
@@ -1119,44 +1108,46 @@ __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const
     }
 }
 
-// per-instance sum of squares of [v1 (len n1) ; v2 (len n2)] into partials
-__global__ __launch_bounds__(kBlock) void k_sumsq2(const double* __restrict__ v1, i64 n1, const double* __restrict__ v2,
-                                                   i64 n2, double* __restrict__ part) {
+// partial sums of squares of [v1 (n) ; v2 (m)] per block, all batch entries
+__global__ __launch_bounds__(kBlock) void k_sumsq2(SymView S, const double* __restrict__ v1,
+                                                   const double* __restrict__ v2, double* __restrict__ part) {
     __shared__ double sh[kBlock / kWave];
     const int b = blockIdx.y;
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    const i64 i = bk.lo + threadIdx.x;
     double a = 0.0;
-    if (i < n1) a = v1[(i64)b * n1 + i];
-    else if (i < n1 + n2) a = v2[(i64)b * n2 + (i - n1)];
+    if (i < bk.hi) a = i < S.n ? v1[(i64)b * S.n + i] : v2[(i64)b * S.m + (i - S.n)];
     a = block_sum(a * a, sh);
     if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
 }
 
-// out[b] = sum of partials (one block per instance)
-__global__ void k_reduce_rows(const double* part, int nblk, double* out, const int* ids) {
+// out[b * G + k] = sum of the partials of member k (grid.x = list index,
+// grid.y = member; off = first block of each member)
+__global__ void k_reduce_rows(const double* part, int nblk, const i32* off, double* out, const int* ids) {
     __shared__ double sh[kBlock / kWave];
-    const int b = inst_of(ids, blockIdx.x);
-    const double r = reduce_parts(part + (i64)b * nblk, nblk, sh);
-    if (threadIdx.x == 0) out[b] = r;
+    const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
+    const double r = reduce_member(part, nblk, off, b, k, sh);
+    if (threadIdx.x == 0) out[(i64)b * gridDim.y + k] = r;
 }
 
-// ||K||_inf per instance: max row sum of |K| (Sec. 5.1 estimate of ||K||_2)
+// ||K||_inf per member: max row sum of |K| (Sec. 5.1 estimate of ||K||_2)
 __global__ __launch_bounds__(kBlock) void k_knorm_rows(SymView S, ValView V, double* __restrict__ part) {
     __shared__ double sh[kBlock / kWave];
     const int b = blockIdx.y;
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    const i64 i = bk.lo + threadIdx.x;
     double a = 0.0;
-    if (i < S.n) {
+    if (i < bk.hi && i < S.n) {
         const double* HF = V.HF + (i64)b * S.nnzHF;
         const double* JT = V.JT + (i64)b * S.nnzJ;
-        double dsum = V.Dxp[(i64)b * S.n + i] + V.delta[b];
+        double dsum = V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + bk.k];
         for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) {
             if (S.HF_col[k] == i) dsum += HF[k];
             else a += fabs(HF[k]);
         }
         a += fabs(dsum);
         for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) a += fabs(JT[k]);
-    } else if (i < S.n + S.m) {
+    } else if (i < bk.hi) {
         const i64 r = i - S.n;
         const double* J = V.J + (i64)b * S.nnzJ;
         for (i64 k = S.J_rowptr[r]; k < S.J_rowptr[r + 1]; k++) a += fabs(J[k]);
@@ -1173,12 +1164,13 @@ __global__ __launch_bounds__(kBlock) void k_knorm_rows(SymView S, ValView V, dou
     }
 }
 
-__global__ void k_reduce_max(const double* part, int nblk, double* out) {
-    const int b = blockIdx.x;
+// out[b * G + k] = max of the partials of member k (grid (nb, G))
+__global__ void k_reduce_max(const double* part, int nblk, const i32* off, double* out) {
+    const int b = blockIdx.x, k = blockIdx.y;
     if (threadIdx.x == 0) {
         double r = 0.0;
-        for (int i = 0; i < nblk; i++) r = fmax(r, part[(i64)b * nblk + i]);
-        out[b] = r;
+        for (int i = off[k]; i < off[k + 1]; i++) r = fmax(r, part[(i64)b * nblk + i]);
+        out[(i64)b * gridDim.y + k] = r;
     }
 }
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "hkkt_factor_batch", "hkkt_factor", "hkkt_solve_batch", "hkkt_solve", "hkkt_inertia",
     "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
-    "hkkt_profile_begin", "hkkt_profile_end",
+    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide"]
@@ -83,6 +83,7 @@ def lib():
         L.hkkt_last_error.restype = C.c_char_p
         L.hkkt_last_error.argtypes = [V]
         L.hkkt_analyze.argtypes = [V, C.c_int64, C.c_int64, V, V, V, V, V]
+        L.hkkt_analyze_group.argtypes = [V, C.c_int, V, V, C.c_int64, C.c_int64, V, V, V, V]
         L.hkkt_factor_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V]
         L.hkkt_factor.argtypes = [V, V, V, V, C.c_double, C.c_double, V]
         L.hkkt_solve_batch.argtypes = [V, C.c_int, V, V, V, V, V]
@@ -90,6 +91,8 @@ def lib():
         L.hkkt_inertia.argtypes = [V, C.c_int, V]
         L.hkkt_symbolic_create.argtypes = [C.POINTER(V), C.c_int64, C.c_int64, V, V, V, V, V, C.c_int,
                                            C.c_int, C.c_char_p, C.c_int]
+        L.hkkt_symbolic_create_group.argtypes = [C.POINTER(V), C.c_int, V, V, C.c_int64, C.c_int64, V, V, V,
+                                                 V, V, C.c_int, C.c_int, C.c_char_p, C.c_int]
         L.hkkt_symbolic_destroy.argtypes = [V]
         L.hkkt_get_symbolic.restype = V
         L.hkkt_get_symbolic.argtypes = [V]
@@ -107,6 +110,55 @@ def lib():
 
 def _np(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
+
+
+class GroupPattern:
+    """Combined block-diagonal pattern of G member patterns (objects with
+    n_x, m, H_rowptr, H_col, J_rowptr, J_col), in the layout
+    hkkt_analyze_group takes: member k's variables at [x_off[k], x_off[k+1])
+    and J rows at [y_off[k], y_off[k+1]). Index bookkeeping only."""
+
+    def __init__(self, patterns):
+        pats = list(patterns)
+        if not pats:
+            raise ValueError("empty group")
+        self.G = len(pats)
+        self.x_off = np.zeros(self.G + 1, np.int64)
+        self.y_off = np.zeros(self.G + 1, np.int64)
+        self.h_off = np.zeros(self.G + 1, np.int64)
+        self.j_off = np.zeros(self.G + 1, np.int64)
+        for k, p in enumerate(pats):
+            self.x_off[k + 1] = self.x_off[k] + int(p.n_x)
+            self.y_off[k + 1] = self.y_off[k] + int(p.m)
+            self.h_off[k + 1] = self.h_off[k] + int(np.asarray(p.H_rowptr)[-1])
+            self.j_off[k + 1] = self.j_off[k] + int(np.asarray(p.J_rowptr)[-1])
+        self.n_x, self.m = int(self.x_off[-1]), int(self.y_off[-1])
+        hp, hc, jp, jc = [np.zeros(1, np.int64)], [], [np.zeros(1, np.int64)], []
+        for k, p in enumerate(pats):
+            hp.append(np.asarray(p.H_rowptr, np.int64)[1:] + self.h_off[k])
+            hc.append(np.asarray(p.H_col, np.int64) + self.x_off[k])
+            jp.append(np.asarray(p.J_rowptr, np.int64)[1:] + self.j_off[k])
+            jc.append(np.asarray(p.J_col, np.int64) + self.x_off[k])
+        self.H_rowptr = np.concatenate(hp)
+        self.H_col = np.concatenate(hc).astype(np.int32)
+        self.J_rowptr = np.concatenate(jp)
+        self.J_col = np.concatenate(jc).astype(np.int32)
+
+    @staticmethod
+    def concat(arrays):
+        """[nb, len_k] per member -> [nb, sum len_k] (numpy or torch)."""
+        arrays = list(arrays)
+        if hasattr(arrays[0], "data_ptr"):
+            import torch
+            return torch.cat([a.reshape(a.shape[0], -1) for a in arrays], dim=1).contiguous()
+        return np.concatenate([np.asarray(a).reshape(np.asarray(a).shape[0], -1) for a in arrays], axis=1)
+
+    def split_x(self, x):
+        """[nb, n_x] -> list of [nb, n_x_k]."""
+        return [x[:, self.x_off[k]:self.x_off[k + 1]] for k in range(self.G)]
+
+    def split_y(self, y):
+        return [y[:, self.y_off[k]:self.y_off[k + 1]] for k in range(self.G)]
 
 
 def _ptr(a):
@@ -163,15 +215,23 @@ def _check(rc, ctx, what=""):
 class Symbolic(_SymbolicView):
     """Host-only symbolic analysis (no GPU needed)."""
 
-    def __init__(self, n_x, m, H_rowptr, H_col, J_rowptr, J_col, perm=None, ordering=0, relax=1):
+    def __init__(self, n_x, m, H_rowptr, H_col, J_rowptr, J_col, perm=None, ordering=0, relax=1, x_off=None,
+                 y_off=None):
         self._keep = [_np(H_rowptr, np.int64), _np(H_col, np.int32), _np(J_rowptr, np.int64),
                       _np(J_col, np.int32)]
         pp = None if perm is None else _np(perm, np.int32)
         self._keep.append(pp)
         h = C.c_void_p()
         err = C.create_string_buffer(512)
-        rc = lib().hkkt_symbolic_create(C.byref(h), int(n_x), int(m), *[_ptr(a) for a in self._keep[:4]],
-                                        _ptr(pp), ordering, relax, err, 512)
+        if x_off is None:
+            rc = lib().hkkt_symbolic_create(C.byref(h), int(n_x), int(m), *[_ptr(a) for a in self._keep[:4]],
+                                            _ptr(pp), ordering, relax, err, 512)
+        else:
+            xo, yo = _np(x_off, np.int64), _np(y_off, np.int64)
+            self._keep += [xo, yo]
+            rc = lib().hkkt_symbolic_create_group(C.byref(h), len(xo) - 1, _ptr(xo), _ptr(yo), int(n_x), int(m),
+                                                  *[_ptr(a) for a in self._keep[:4]], _ptr(pp), ordering, relax,
+                                                  err, 512)
         if rc != 0:
             raise HKKTError(rc, err.value.decode())
         self._handle = h
@@ -179,6 +239,10 @@ class Symbolic(_SymbolicView):
     @classmethod
     def from_pattern(cls, p, **kw):
         return cls(p.n_x, p.m, p.H_rowptr, p.H_col, p.J_rowptr, p.J_col, **kw)
+
+    @classmethod
+    def from_group(cls, g, **kw):
+        return cls(g.n_x, g.m, g.H_rowptr, g.H_col, g.J_rowptr, g.J_col, x_off=g.x_off, y_off=g.y_off, **kw)
 
     def _h(self):
         return self._handle
@@ -215,6 +279,7 @@ class Solver(_SymbolicView):
         self._ctx = h
         self.n = self.m = None
         self.nb = 0
+        self.G = 1
 
     def __del__(self):
         try:
@@ -238,6 +303,20 @@ class Solver(_SymbolicView):
         _check(lib().hkkt_analyze(self._ctx, int(p.n_x), int(p.m), *[_ptr(a) for a in keep], _ptr(pp)),
                self._ctx)
         self.n, self.m = int(p.n_x), int(p.m)
+        self.G = 1
+        return self
+
+    def analyze_group(self, group):
+        """Analyse a GroupPattern (uneven systems in one launch). Afterwards
+        factor() takes combined [nb, ...] values with delta, gamma of shape
+        [nb, G]; statuses and infos are per (entry, member), flat index
+        b * G + k."""
+        g = group
+        keep = [_np(g.x_off, np.int64), _np(g.y_off, np.int64), _np(g.H_rowptr, np.int64),
+                _np(g.H_col, np.int32), _np(g.J_rowptr, np.int64), _np(g.J_col, np.int32)]
+        _check(lib().hkkt_analyze_group(self._ctx, int(g.G), _ptr(keep[0]), _ptr(keep[1]), int(g.n_x), int(g.m),
+                                        *[_ptr(a) for a in keep[2:]]), self._ctx)
+        self.n, self.m, self.G = int(g.n_x), int(g.m), int(g.G)
         return self
 
     # -- values -------------------------------------------------------------
@@ -250,11 +329,14 @@ class Solver(_SymbolicView):
         return _np(np.asarray(a, dtype=np.float64).reshape(nb, width), np.float64)
 
     def factor(self, H_val, D_x, J_val, delta, gamma):
-        """Batch-major values ([nb, nnz] / [nb, n_x]); delta, gamma: [nb].
-        Returns (rc, status[nb], fail_col[nb])."""
-        delta = np.atleast_1d(np.asarray(delta, np.float64))
-        gamma = np.atleast_1d(np.asarray(gamma, np.float64))
-        nb = int(delta.shape[0])
+        """Batch-major values ([nb, nnz] / [nb, n_x]); delta, gamma: [nb]
+        ([nb, G] after analyze_group). Returns (rc, status[nb*G],
+        fail_col[nb*G])."""
+        delta = np.atleast_1d(np.asarray(delta, np.float64)).reshape(-1)
+        gamma = np.atleast_1d(np.asarray(gamma, np.float64)).reshape(-1)
+        if delta.shape != gamma.shape or delta.shape[0] % self.G:
+            raise ValueError("delta and gamma need nb * G entries")
+        nb = int(delta.shape[0]) // self.G
         if self.n is None:  # not analysed: let the library report the state error
             _check(lib().hkkt_factor_batch(self._ctx, nb, None, None, None, delta.ctypes.data,
                                            gamma.ctypes.data, None, None), self._ctx)
@@ -264,8 +346,8 @@ class Solver(_SymbolicView):
         if Jv is not None and Jv.shape[1] == 0:
             Jv = None
         self._keep_vals = (Hv, Dx, Jv)
-        st = np.zeros(nb, np.int32)
-        fc = np.zeros(nb, np.int64)
+        st = np.zeros(nb * self.G, np.int32)
+        fc = np.zeros(nb * self.G, np.int64)
         rc = _check(lib().hkkt_factor_batch(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv),
                                             _np(delta, np.float64).ctypes.data, _np(gamma, np.float64).ctypes.data,
                                             st.ctypes.data, fc.ctypes.data), self._ctx)
@@ -282,16 +364,17 @@ class Solver(_SymbolicView):
         return np.empty((nb, width), np.float64)
 
     def solve(self, r1, r2):
-        """Returns (rc, x [nb, n_x], y [nb, m], infos list of dicts)."""
+        """Returns (rc, x [nb, n_x], y [nb, m], infos: nb * G dicts, index
+        b * G + k)."""
         nb = self.nb
         R1 = self._arr(r1, nb, self.n)
         R2 = self._arr(r2, nb, self.m) if self.m > 0 else None
         x = self._out(nb, self.n)
         y = self._out(nb, max(self.m, 0))
-        info = (Info * nb)()
+        info = (Info * (nb * self.G))()
         rc = _check(lib().hkkt_solve_batch(self._ctx, nb, _ptr(R1), _ptr(R2), _ptr(x),
                                            _ptr(y) if self.m > 0 else None, info), self._ctx)
-        return rc, x, y, [info[i].as_dict() for i in range(nb)]
+        return rc, x, y, [info[i].as_dict() for i in range(nb * self.G)]
 
     def inertia(self, b=0):
         out = np.zeros(3, np.int64)

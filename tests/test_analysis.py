@@ -189,3 +189,94 @@ def test_edge_shapes_analyse():
         b = H.batch_from_dense(Hd, np.ones(n), J, 0.0, 1.0, np.ones(n), np.ones(m))
         s = hkkt.Symbolic.from_pattern(b.pattern).stats()
         assert s["n_x"] == n and s["nnz_L"] >= n
+
+
+# ---------------------------------------------------------------------------
+# uneven groups: G systems of different sizes analysed as one block-diagonal
+# system (one launch per kernel for all members)
+# ---------------------------------------------------------------------------
+def _group_members():
+    return [H.tiny_grid_like(150, 31), H.tiny_dense_like(40, 32), H.tiny_grid_like(90, 33),
+            H.tiny_dense_like(64, 34)]
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+def test_group_keeps_members_apart(relax):
+    mem = _group_members()
+    g = hkkt.GroupPattern([b.pattern for b in mem])
+    sym = hkkt.Symbolic.from_group(g, relax=relax)
+    perm = sym.perm()
+    xo = g.x_off
+    # every member's pivots stay in the member's own range
+    for k in range(g.G):
+        seg = perm[xo[k]:xo[k + 1]]
+        assert seg.min() >= xo[k] and seg.max() < xo[k + 1]
+    # no supernode spans two members; the combined fill is the members' fill
+    sn = sym.supernodes()
+    owner = np.searchsorted(xo, np.arange(g.n_x), side="right") - 1
+    for s in range(sn["first"].size - 1):
+        rows = sn["rows"][sn["rowptr"][s]:sn["rowptr"][s + 1]]
+        assert np.unique(owner[rows]).size == 1
+    Sg = np.zeros((g.n_x, g.n_x), bool)
+    for k, b in enumerate(mem):
+        Sg[xo[k]:xo[k + 1], xo[k]:xo[k + 1]] = _struct(b)
+    fill = _boolean_fill(Sg[np.ix_(perm, perm)])
+    assert sym.stats()["nnz_L"] == int(fill.sum())
+
+
+def test_group_natural_order_fill_is_sum_of_members():
+    mem = _group_members()
+    g = hkkt.GroupPattern([b.pattern for b in mem])
+    tot = hkkt.Symbolic.from_group(g, ordering=1).stats()["nnz_L"]
+    parts = sum(hkkt.Symbolic.from_pattern(b.pattern, ordering=1).stats()["nnz_L"] for b in mem)
+    assert tot == parts
+
+
+def test_group_single_member_equals_plain():
+    b = H.tiny_grid_like(200, 35)
+    g = hkkt.GroupPattern([b.pattern])
+    a = hkkt.Symbolic.from_group(g)
+    p = hkkt.Symbolic.from_pattern(b.pattern)
+    assert a.stats() == p.stats()
+    assert np.array_equal(a.perm(), p.perm())
+
+
+def test_group_pattern_concat_layout():
+    mem = _group_members()[:2]
+    g = hkkt.GroupPattern([b.pattern for b in mem])
+    assert g.n_x == sum(b.pattern.n_x for b in mem) and g.m == sum(b.pattern.m for b in mem)
+    Hd = np.zeros((g.n_x, g.n_x))
+    Hv = hkkt.GroupPattern.concat([b.H_val for b in mem])[0]
+    rows = np.repeat(np.arange(g.n_x), np.diff(g.H_rowptr))
+    Hd[rows, g.H_col] = Hv
+    for k, b in enumerate(mem):
+        sl = slice(g.x_off[k], g.x_off[k + 1])
+        assert np.array_equal(Hd[sl, sl], np.tril(H.dense_H(b)))
+    assert np.count_nonzero(Hd) == sum(np.count_nonzero(np.tril(H.dense_H(b))) for b in mem)
+
+
+def test_group_argument_errors():
+    mem = _group_members()[:2]
+    g = hkkt.GroupPattern([b.pattern for b in mem])
+    with pytest.raises(hkkt.HKKTError) as e:   # offsets do not cover n_x
+        hkkt.Symbolic(g.n_x, g.m, g.H_rowptr, g.H_col, g.J_rowptr, g.J_col, x_off=[0, 5, g.n_x - 1],
+                      y_off=g.y_off)
+    assert e.value.code == hkkt.ERR_ARG
+    with pytest.raises(hkkt.HKKTError) as e:   # empty member
+        hkkt.Symbolic(g.n_x, g.m, g.H_rowptr, g.H_col, g.J_rowptr, g.J_col, x_off=[0, 0, g.n_x],
+                      y_off=g.y_off)
+    assert e.value.code == hkkt.ERR_ARG
+    # a J row of member 0 reaching into member 1
+    Jc = g.J_col.copy()
+    r0 = g.J_rowptr[0]
+    Jc[r0] = g.x_off[1]
+    Jc[:g.J_rowptr[1]] = np.sort(Jc[:g.J_rowptr[1]])
+    with pytest.raises(hkkt.HKKTError) as e:
+        hkkt.Symbolic(g.n_x, g.m, g.H_rowptr, g.H_col, g.J_rowptr, Jc, x_off=g.x_off, y_off=g.y_off)
+    assert e.value.code == hkkt.ERR_PATTERN and "outside its member" in str(e.value)
+    # member boundaries that split a member's own coupling
+    xo = g.x_off.copy()
+    xo[1] -= 1
+    with pytest.raises(hkkt.HKKTError) as e:
+        hkkt.Symbolic(g.n_x, g.m, g.H_rowptr, g.H_col, g.J_rowptr, g.J_col, x_off=xo, y_off=g.y_off)
+    assert e.value.code == hkkt.ERR_PATTERN and "member" in str(e.value)
