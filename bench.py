@@ -29,6 +29,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def level_bytes(sym, s_elem):
+    """Algorithmic bytes one instance moves per level of the supernodal tree,
+    forward and backward solve: the structurally non-zero panel entries
+    (s_elem each), the reciprocal diagonal and the solution entries of the
+    supernode's columns (read and written), the entries of the rows below
+    (forward: read-modify-write of the ancestors' entries; backward: read)
+    and their 4-byte row indices."""
+    import numpy as np
+    sn = sym.supernodes()
+    first, rowptr, lp, lsn = sn["first"], sn["rowptr"], sn["level_ptr"], sn["level_sn"]
+    fwd, bwd = [], []
+    for l in range(len(lp) - 1):
+        ids = lsn[lp[l]:lp[l + 1]]
+        w = (first[ids + 1] - first[ids]).astype(np.int64)
+        nr = (rowptr[ids + 1] - rowptr[ids]).astype(np.int64)
+        nnz = nr * w - w * (w - 1) // 2
+        below = nr - w
+        fwd.append(int((s_elem * nnz + 3 * s_elem * w + 2 * s_elem * below + 4 * below).sum()))
+        bwd.append(int((s_elem * nnz + 3 * s_elem * w + s_elem * below + 4 * below).sum()))
+    return fwd, bwd
+
+
 def per_instance_bytes(stats, s_elem):
     """Bytes one instance must move per kernel class and per application,
     per the layouts of the library (value bytes s_elem for the factor and
@@ -85,12 +107,18 @@ def run_gpu(args):
     pinfos = s.last_infos
     stats = s.stats()
     per = per_instance_bytes(stats, 4)
+    lf, lb = level_bytes(s, 4)
+    # levels below `lo` run one launch per level; the levels above in the
+    # tree-traversal kernel (one launch per application of H_gamma^{-1})
+    nlev = len(lf)
+    lo = round(prof["bwd"][1] / prof["tri_tree"][1]) if prof["tri_tree"][1] else nlev
     # applications per instance over the profiled step: each pass applies
     # H_gamma^{-1} once per CG iteration plus twice (w and the primal
     # recovery); J^T and J are applied once per CG iteration plus twice / once
     apps = sum(i["cg_iters"] + 2 * i["passes"] for i in pinfos)
     spmv_apps = sum(2 * i["cg_iters"] + 3 * i["passes"] for i in pinfos)
-    total = {"fwd": per["fwd"] * apps, "bwd": per["bwd"] * apps,
+    total = {"fwd": sum(lf[:lo]) * apps, "bwd": sum(lb[:lo]) * apps,
+             "tri_tree": (sum(lf[lo:]) + sum(lb[lo:])) * apps,
              "jt_spmv": per["jt_spmv"] * spmv_apps / 2, "j_spmv": per["j_spmv"] * spmv_apps / 2}
     best = max(total, key=lambda k: prof[k][0])
     ms_tot, launches = prof[best]
@@ -99,11 +127,12 @@ def run_gpu(args):
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     kname = {"fwd": "k_fwd_lvl<float,true> (forward supernodal triangular solve, one launch per level)",
              "bwd": "k_bwd_lvl<float> (backward supernodal triangular solve, one launch per level)",
+             "tri_tree": "k_tri_tree<float,true,512> (both solves over the thin top levels)",
              "jt_spmv": "k_jt<float>", "j_spmv": "k_j<float>"}[best]
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(per_launch),
-                "launches_per_step": launches}
+                "launches_per_step": launches, "per_level_launch_levels": lo}
 
     # plain FP64 comparators: batched, and one instance at a time
     s64 = make("fp64")
@@ -160,13 +189,15 @@ def profile_hsolve(args):
     s.analyze(b.pattern)
     s.factor(dev(b.H_val), dev(b.D_x), dev(b.J_val), b.delta, b.gamma)
     rhs = dev(np.random.default_rng(0).standard_normal((args.nb, args.n)))
+    s.profile_begin()
     for _ in range(args.profile_hsolve):
         s.hsolve(rhs)
-    torch.cuda.synchronize()
-    st = s.stats()
-    per = per_instance_bytes(st, 4)
-    print(json.dumps({"levels": st["levels"], "alg_bytes_per_launch": {k: per[k] * args.nb / st["levels"]
-                                                                      for k in ("fwd", "bwd")}}))
+    prof = s.profile_end()
+    lf, lb = level_bytes(s, 4)
+    lo = round(prof["bwd"][1] / prof["tri_tree"][1]) if prof["tri_tree"][1] else len(lf)
+    print(json.dumps({"levels": len(lf), "per_level_launch_levels": lo,
+                      "alg_bytes_per_launch": {"fwd": sum(lf[:lo]) * args.nb / lo, "bwd": sum(lb[:lo]) * args.nb / lo,
+                                               "tri_tree": (sum(lf[lo:]) + sum(lb[lo:])) * args.nb}}))
 
 
 def load_traffic():

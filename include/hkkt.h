@@ -240,8 +240,10 @@ int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
  * 1 LDS fronts, 2 large fronts (blocked), 3 forward solve (per-level
  * wavefront kernel), 4 backward solve (per-level wavefront kernel), 5 J^T
  * SpMV, 6 J SpMV, 7 CG vector updates, 8 CG scalars, 9 KKT residual,
- * 10 other, 11 triangular solves of very wide/tall supernodes. */
-#define HKKT_NPROF 12
+ * 10 other, 11 triangular solves of very wide/tall supernodes, 12 both
+ * triangular solves over the thin top levels of the tree (one launch, one
+ * work-group per instance). */
+#define HKKT_NPROF 13
 int hkkt_profile_begin(hkkt_ctx *ctx);
 int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);
 

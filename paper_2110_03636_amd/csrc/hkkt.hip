@@ -55,7 +55,7 @@ static double now_ms() {
 // ---------------------------------------------------------------------------
 // optional per-kernel timing with HIP events on the context's stream
 // ---------------------------------------------------------------------------
-constexpr int kNProf = 12;
+constexpr int kNProf = 13;
 struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -165,11 +165,14 @@ struct DevSym {
     DBuf tri_list, tri_desc;
     std::vector<std::pair<i32, i32>> tri_seg;   // [level * kTriClasses + class] = (offset, count)
     std::vector<int> tri_wg_maxnr;              // per level, class 7
+    DBuf tri_seg_dev;                           // tri_seg on the device (int pairs)
+    std::vector<int> lev_count;                 // supernodes per level
+    std::vector<char> tree_fits;                // level fits the tree-traversal classes
+    int tree_width = 32;                        // widest level run by the tree kernels
     SymView v{};
 };
 
 constexpr size_t kMaxLds = 65536;
-constexpr int kTriClasses = 8;
 constexpr int kTriWG = 7;
 
 // size class of a supernode for the triangular solves: rows decide the
@@ -337,6 +340,19 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
         }
         upload(D.tri_desc, td, st);
         upload(D.tri_list, tl, st);
+        std::vector<i32> sg(2 * D.tri_seg.size());
+        for (size_t q = 0; q < D.tri_seg.size(); q++) {
+            sg[2 * q] = D.tri_seg[q].first;
+            sg[2 * q + 1] = D.tri_seg[q].second;
+        }
+        upload(D.tri_seg_dev, sg, st);
+        D.lev_count.assign(S.nlevels, 0);
+        D.tree_fits.assign(S.nlevels, 1);
+        for (i32 l = 0; l < S.nlevels; l++) {
+            D.lev_count[l] = S.level_ptr[l + 1] - S.level_ptr[l];
+            for (int cls = kTreeClasses; cls < kTriClasses; cls++)
+                if (D.tri_seg[(size_t)l * kTriClasses + cls].second) D.tree_fits[l] = 0;
+        }
     }
     SymView& v = D.v;
     v.n = S.n; v.m = S.m; v.ns = S.ns;
@@ -562,12 +578,43 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
     }
 }
 
+// Levels [tree_lo, nlevels) run in the tree-traversal kernels: the top
+// levels that hold at most tree_width supernodes each and fit the tree
+// classes. HKKT_TREE_WIDTH overrides the width (0 turns the tree kernels off).
+static int tree_lo(const DevSym& D, int nlevels) {
+    static const int width = std::getenv("HKKT_TREE_WIDTH") ? std::atoi(std::getenv("HKKT_TREE_WIDTH")) : -1;
+    const int wmax = width >= 0 ? width : D.tree_width;
+    int lo = nlevels;
+    while (wmax > 0 && lo > 0 && D.lev_count[lo - 1] <= wmax && D.tree_fits[lo - 1]) lo--;
+    return lo;
+}
+
+template <typename T>
+static void launch_tree(hkkt_ctx* c, Batch& B, int l0, int l1, const int* ids, int nids, const CGState* st_) {
+    const DevSym& D = c->dev;
+    constexpr int NT = 512;
+    const T* L = B.L.as<T>();
+    const T* Dv = B.Dinv.as<T>();
+    T* X = B.X.as<T>();
+    const TriDesc* desc = D.tri_desc.as<TriDesc>();
+    const i32* sg = D.tri_seg_dev.as<i32>();
+    const int kind = 12 + 16 * (l0 + 1);
+    if (c->opt.deterministic == 0)
+        LAUNCH(kind, (k_tri_tree<T, true, NT>), dim3(nids), dim3(NT), 0, c->stream, D.v, desc, sg, l0, l1, L, Dv, X,
+               B.UV.as<T>(), ids, st_);
+    else
+        LAUNCH(kind, (k_tri_tree<T, false, NT>), dim3(nids), dim3(NT), 0, c->stream, D.v, desc, sg, l0, l1, L, Dv,
+               X, B.UV.as<T>(), ids, st_);
+}
+
 template <typename T>
 static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* ids, int nids, const CGState* st_) {
     const Symbolic& S = c->sym.S;
     if (nids <= 0) return;
-    for (i32 l = 0; l < S.nlevels; l++) launch_tri_level<T>(c, B, l, true, ids, nids, st_);
-    for (i32 l = S.nlevels - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, ids, nids, st_);
+    const int lo = tree_lo(c->dev, S.nlevels);
+    for (i32 l = 0; l < lo; l++) launch_tri_level<T>(c, B, l, true, ids, nids, st_);
+    if (lo < S.nlevels) launch_tree<T>(c, B, lo, S.nlevels, ids, nids, st_);
+    for (i32 l = lo - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, ids, nids, st_);
 }
 
 static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {

@@ -20,6 +20,7 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kTri = 64;   // diagonal block size of the work-group triangular solves
 constexpr int kChunk = 8;  // panel columns prefetched per step by the wavefront solves
+constexpr int kTriClasses = 8;   // size classes of the triangular-solve schedule
 
 // Device view of the symbolic analysis.
 struct SymView {

@@ -569,37 +569,47 @@ __device__ __forceinline__ T seg_allsum(T v) {
 // (deterministic). PUSH = true: the rows below the diagonal block are added
 // straight into the ancestors' right-hand-side entries with FP atomics
 // (right-looking; order of the additions not fixed).
+// Load panel columns [j0, j0 + CH) of the rows this lane holds (strictly
+// below the diagonal, zero elsewhere).
+template <typename T, int SEG, int R, int CH>
+__device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ Lb, const TriDesc& d, int j0,
+                                          int sl) {
+#pragma unroll
+    for (int jj = 0; jj < CH; jj++)
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int row = sl + SEG * r, j = j0 + jj;
+            lc[jj][r] = (j >= 0 && j < d.w && row > j && row < d.nr) ? Lb[(i64)j * d.nr + row] : T(0);
+        }
+}
+
+// One (supernode d, instance b) task on the SEG lanes of this thread's
+// segment. Loads depend on the descriptor and b only (b is a valid instance
+// even for an invalid task), so they are issued without waiting for the
+// validity test, and the first chunk of panel columns goes out together
+// with the right-hand-side entries; valid only gates the stores.
 template <typename T, int SEG, int R, bool PUSH>
-__device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
-                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
-                                         T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
-                                         const CGState* st) {
-    constexpr int G = kWave / SEG;
+__device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
+                                         const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X,
+                                         T* __restrict__ UV) {
     constexpr int CH = chunk_cols<T, SEG, R>();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int sl = lane & (SEG - 1), seg = lane / SEG;
-    const i64 t0 = wave * G;
-    const int q = (int)(t0 / npad);
-    if (q >= count) return;
-    const int k = (int)(t0 - (i64)q * npad) + seg;
-    bool valid = k < nids;
-    const int b = valid ? inst_of(ids, k) : 0;
-    const TriDesc d = desc[q];
-    if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
+    const int sl = threadIdx.x & (SEG - 1);
     const T* Lb = L + (i64)b * S.Lsize + d.lptr;
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
     T* uvb = UV + (i64)b * S.UVsize;
+    T lc[CH][R];
+    load_cols<T, SEG, R, CH>(lc, Lb, d, 0, sl);
     T v[R], di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int row = sl + SEG * r;
         T a = T(0), e = T(0);
-        if (valid && row < d.w) {
+        if (row < d.w) {
             a = x[d.f + row];
             e = dinv[row];
         }
-        if (!PUSH && valid && row < d.nr && d.nchild) {
+        if (!PUSH && row < d.nr && d.nchild) {
             const int g0 = S.ga_row[2 * (d.rp + row)], gn = S.ga_row[2 * (d.rp + row) + 1];
             for (int g = g0; g < g0 + gn; g++) a += uvb[S.ga_idx[g]];
         }
@@ -607,15 +617,7 @@ __device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __rest
         di[r] = e;
     }
     for (int j0 = 0; j0 < d.w; j0 += CH) {
-        T lc[CH][R];
-#pragma unroll
-        for (int jj = 0; jj < CH; jj++)
-#pragma unroll
-            for (int r = 0; r < R; r++) {
-                const int row = sl + SEG * r;
-                lc[jj][r] = (valid && j0 + jj < d.w && row > j0 + jj && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row]
-                                                                                     : T(0);
-            }
+        if (j0 > 0) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
 #pragma unroll
         for (int jj = 0; jj < CH; jj++) {
             const int j = j0 + jj;
@@ -648,46 +650,30 @@ __device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __rest
 }
 
 template <typename T, int SEG, int R>
-__device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
-                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
-                                         T* __restrict__ X, const int* ids, int nids, const CGState* st) {
-    constexpr int G = kWave / SEG;
+__device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
+                                         const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X) {
     constexpr int CH = chunk_cols<T, SEG, R>();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int sl = lane & (SEG - 1), seg = lane / SEG;
-    const i64 t0 = wave * G;
-    const int q = (int)(t0 / npad);
-    if (q >= count) return;
-    const int k = (int)(t0 - (i64)q * npad) + seg;
-    bool valid = k < nids;
-    const int b = valid ? inst_of(ids, k) : 0;
-    const TriDesc d = desc[q];
-    if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
+    const int sl = threadIdx.x & (SEG - 1);
     const T* Lb = L + (i64)b * S.Lsize + d.lptr;
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
+    // columns from the last one down in chunks [jhi - CH, jhi); the first
+    // chunk goes out with the vector loads
+    T lc[CH][R];
+    load_cols<T, SEG, R, CH>(lc, Lb, d, d.w - CH, sl);
     T v[R], di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int row = sl + SEG * r;
         T a = T(0), e = T(0);
-        if (valid && row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
-        if (valid && row < d.w) e = dinv[row];
+        if (row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
+        if (row < d.w) e = dinv[row];
         v[r] = a;
         di[r] = e;
     }
-    // columns from the last one down in chunks [jhi - CH, jhi)
     for (int jhi = d.w; jhi > 0; jhi -= CH) {
         const int j0 = jhi - CH;
-        T lc[CH][R];
-#pragma unroll
-        for (int jj = 0; jj < CH; jj++)
-#pragma unroll
-            for (int r = 0; r < R; r++) {
-                const int row = sl + SEG * r;
-                lc[jj][r] = (valid && j0 + jj >= 0 && row > j0 + jj && row < d.nr) ? Lb[(i64)(j0 + jj) * d.nr + row]
-                                                                                   : T(0);
-            }
+        if (jhi < d.w) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
 #pragma unroll
         for (int jj = CH - 1; jj >= 0; jj--) {
             const int j = j0 + jj;
@@ -716,6 +702,121 @@ __device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __rest
     }
 }
 
+
+// Per-level mapping: all segments of a wavefront take the same supernode for
+// consecutive entries of the instance list (the task space of a supernode is
+// padded to a multiple of 64/SEG, so control flow is wave-uniform).
+template <typename T, int SEG, int R, bool PUSH>
+__device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
+                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
+                                         const CGState* st) {
+    constexpr int G = kWave / SEG;
+    const int seg = (threadIdx.x & (kWave - 1)) / SEG;
+    const i64 t0 = wave * G;
+    const int q = (int)(t0 / npad);
+    if (q >= count) return;
+    const int k = (int)(t0 - (i64)q * npad) + seg;
+    bool valid = k < nids;
+    const int b = valid ? inst_of(ids, k) : 0;
+    const TriDesc d = desc[q];
+    if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
+    fwd_body<T, SEG, R, PUSH>(S, d, b, valid, L, Dinv, X, UV);
+}
+
+template <typename T, int SEG, int R>
+__device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
+                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         T* __restrict__ X, const int* ids, int nids, const CGState* st) {
+    constexpr int G = kWave / SEG;
+    const int seg = (threadIdx.x & (kWave - 1)) / SEG;
+    const i64 t0 = wave * G;
+    const int q = (int)(t0 / npad);
+    if (q >= count) return;
+    const int k = (int)(t0 - (i64)q * npad) + seg;
+    bool valid = k < nids;
+    const int b = valid ? inst_of(ids, k) : 0;
+    const TriDesc d = desc[q];
+    if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
+    bwd_body<T, SEG, R>(S, d, b, valid, L, Dinv, X);
+}
+
+// ---------------------------------------------------------------------------
+// Tree traversal: one work-group per instance walks a range of levels of the
+// supernodal tree (forward: up; backward: down) with a work-group barrier
+// between levels instead of a kernel boundary, so the instances progress
+// independently and a level costs no launch. Meant for the thin upper
+// levels, where a per-level launch is latency-bound; the wide lower levels
+// need the whole chip per level. Within a
+// level every segment of SEG lanes takes its own supernode of the class
+// (segments of one wavefront may hold different supernodes; all shuffles
+// stay inside a segment). seg[2 * (l * kTriClasses + c)] = (offset, count)
+// of the supernodes of level l, class c in desc. Classes 0..kTreeClasses-1
+// only; the host routes other levels to the per-level kernels.
+// ---------------------------------------------------------------------------
+constexpr int kTreeClasses = 5;
+
+
+template <typename T, int SEG, int R, bool PUSH>
+__device__ __forceinline__ void fwd_tree_class(const SymView& S, const TriDesc* __restrict__ desc, int cnt, int b,
+                                               const T* __restrict__ L, const T* __restrict__ Dinv,
+                                               T* __restrict__ X, T* __restrict__ UV, const CGState* st) {
+    constexpr int G = kWave / SEG;
+    const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int seg = (threadIdx.x & (kWave - 1)) / SEG;
+    for (int base = wv * G; base < cnt; base += nw * G) {
+        const int q = base + seg;
+        bool valid = q < cnt;
+        const TriDesc d = desc[valid ? q : cnt - 1];
+        if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
+        fwd_body<T, SEG, R, PUSH>(S, d, b, valid, L, Dinv, X, UV);
+    }
+}
+
+template <typename T, int SEG, int R>
+__device__ __forceinline__ void bwd_tree_class(const SymView& S, const TriDesc* __restrict__ desc, int cnt, int b,
+                                               const T* __restrict__ L, const T* __restrict__ Dinv,
+                                               T* __restrict__ X, const CGState* st) {
+    constexpr int G = kWave / SEG;
+    const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int seg = (threadIdx.x & (kWave - 1)) / SEG;
+    for (int base = wv * G; base < cnt; base += nw * G) {
+        const int q = base + seg;
+        bool valid = q < cnt;
+        const TriDesc d = desc[valid ? q : cnt - 1];
+        if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
+        bwd_body<T, SEG, R>(S, d, b, valid, L, Dinv, X);
+    }
+}
+
+// forward over levels [l0, l1), then backward from l1-1 down to l0 (the
+// levels above l1 are empty: the range ends at the root), one work-group
+// per listed instance
+template <typename T, bool PUSH, int NT>
+__global__ __launch_bounds__(NT) void k_tri_tree(SymView S, const TriDesc* __restrict__ desc,
+                                                 const i32* __restrict__ seg, int l0, int l1, const T* __restrict__ L,
+                                                 const T* __restrict__ Dinv, T* __restrict__ X, T* __restrict__ UV,
+                                                 const int* ids, const CGState* st) {
+    const int b = inst_of(ids, blockIdx.x);
+    for (int l = l0; l < l1; l++) {
+        const i32* sg = seg + 2 * (l * kTriClasses);
+        if (sg[1]) fwd_tree_class<T, 16, 1, PUSH>(S, desc + sg[0], sg[1], b, L, Dinv, X, UV, st);
+        if (sg[3]) fwd_tree_class<T, 32, 1, PUSH>(S, desc + sg[2], sg[3], b, L, Dinv, X, UV, st);
+        if (sg[5]) fwd_tree_class<T, 64, 1, PUSH>(S, desc + sg[4], sg[5], b, L, Dinv, X, UV, st);
+        if (sg[7]) fwd_tree_class<T, 64, 2, PUSH>(S, desc + sg[6], sg[7], b, L, Dinv, X, UV, st);
+        if (sg[9]) fwd_tree_class<T, 64, 4, PUSH>(S, desc + sg[8], sg[9], b, L, Dinv, X, UV, st);
+        __syncthreads();
+    }
+    for (int l = l1 - 1; l >= l0; l--) {
+        const i32* sg = seg + 2 * (l * kTriClasses);
+        if (sg[1]) bwd_tree_class<T, 16, 1>(S, desc + sg[0], sg[1], b, L, Dinv, X, st);
+        if (sg[3]) bwd_tree_class<T, 32, 1>(S, desc + sg[2], sg[3], b, L, Dinv, X, st);
+        if (sg[5]) bwd_tree_class<T, 64, 1>(S, desc + sg[4], sg[5], b, L, Dinv, X, st);
+        if (sg[7]) bwd_tree_class<T, 64, 2>(S, desc + sg[6], sg[7], b, L, Dinv, X, st);
+        if (sg[9]) bwd_tree_class<T, 64, 4>(S, desc + sg[8], sg[9], b, L, Dinv, X, st);
+        __syncthreads();
+    }
+}
 
 // one class per launch (used for the wide classes R >= 4)
 template <typename T, int SEG, int R, bool PUSH>

@@ -27,7 +27,7 @@ EXPORTS = [
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
-              "cg_scalar", "residual", "other", "tri_wide"]
+              "cg_scalar", "residual", "other", "tri_wide", "tri_tree"]
 
 i64p = C.POINTER(C.c_int64)
 i32p = C.POINTER(C.c_int32)
@@ -408,7 +408,7 @@ class Solver(_SymbolicView):
 
     def profile_end(self):
         """{class: (total_ms, launches)} of the launches since profile_begin."""
-        ms = np.zeros(12)
-        k = np.zeros(12, np.int64)
+        ms = np.zeros(len(PROF_NAMES))
+        k = np.zeros(len(PROF_NAMES), np.int64)
         _check(lib().hkkt_profile_end(self._ctx, ms.ctypes.data, k.ctypes.data), self._ctx)
-        return {PROF_NAMES[i]: (float(ms[i]), int(k[i])) for i in range(12)}
+        return {PROF_NAMES[i]: (float(ms[i]), int(k[i])) for i in range(len(PROF_NAMES))}
