@@ -558,11 +558,54 @@ __host__ __device__ constexpr int chunk_cols() {
     return (SEG == 64 && R == 1) ? 16 : 8;
 }
 
+// Lane permutations within rows of 16 lanes through DPP (a VALU operand
+// modifier, no LDS round trip): quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror (lane i <-> 7-i within 8), row_mirror (i <-> 15-i).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the SEG lanes of a segment, the same value in every lane of it:
+// butterfly over lane pairs, the steps within 16 lanes by DPP, the 16- and
+// 32-lane steps by lane permutes. Each step adds equal partial sums, so all
+// lanes end with bitwise equal results.
 template <typename T, int SEG>
 __device__ __forceinline__ T seg_allsum(T v) {
-#pragma unroll
-    for (int o = SEG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SEG);
+    v += dpp_mov<0xB1>(v);                          // pairs
+    v += dpp_mov<0x4E>(v);                          // quads
+    if (SEG >= 8) v += dpp_mov<0x141>(v);           // 8 lanes
+    if (SEG >= 16) v += dpp_mov<0x140>(v);          // 16 lanes
+    if (SEG >= 32) v += __shfl_xor(v, 16, SEG);
+    if (SEG >= 64) v += __shfl_xor(v, 32, SEG);
     return v;
+}
+
+// Value of lane jl of the segment in every lane of it. A 64-lane segment is
+// the whole wavefront, whose column loop runs in lockstep, so jl is uniform
+// and v_readlane serves; narrower segments use a lane permute (segments of a
+// tree-kernel wavefront may sit at different columns).
+__device__ __forceinline__ float lane_read(float v, int jl) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), __builtin_amdgcn_readfirstlane(jl)));
+}
+__device__ __forceinline__ double lane_read(double v, int jl) {
+    const long long u = __double_as_longlong(v);
+    const int l = __builtin_amdgcn_readfirstlane(jl);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T, int SEG>
+__device__ __forceinline__ T seg_bcast(T v, int jl) {
+    if (SEG == kWave) return lane_read(v, jl);
+    return __shfl(v, jl, SEG);
 }
 
 // PUSH = false: children's update vectors are pulled through the gather list
@@ -627,7 +670,7 @@ __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int
 #pragma unroll
                 for (int r = 1; r < R; r++)
                     if (r == jr) { vs = v[r]; es = di[r]; }
-                const T yj = __shfl(vs, jl, SEG) * __shfl(es, jl, SEG);
+                const T yj = seg_bcast<T, SEG>(vs * es, jl);      // y_j = v_j / L_jj, formed in lane jl
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const int row = sl + SEG * r;
@@ -687,7 +730,7 @@ __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int
 #pragma unroll
                 for (int r = 1; r < R; r++)
                     if (r == jr) { vs = v[r]; es = di[r]; }
-                const T xj = (__shfl(vs, jl, SEG) - part) * __shfl(es, jl, SEG);
+                const T xj = seg_bcast<T, SEG>((vs - part) * es, jl);   // formed in lane jl
 #pragma unroll
                 for (int r = 0; r < R; r++)
                     if (sl + SEG * r == j) v[r] = xj;
