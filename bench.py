@@ -78,9 +78,14 @@ def run_gpu(args):
     dev = lambda a: torch.as_tensor(a, device="cuda")
     H, D, J, R1, R2 = dev(b.H_val), dev(b.D_x), dev(b.J_val), dev(b.r1), dev(b.r2)
 
-    def make(prec):
+    tuned = {}
+
+    def make(prec, tune=False):
         s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10)
         s.analyze(b.pattern)
+        if tune:   # once per pattern, outside the timed region (like the analysis)
+            r = s.autotune(H, D, J, b.delta, b.gamma, R1, R2)
+            tuned[prec] = {"relax": r["relax"], "tree_width": r["tree_width"]}
         return s
 
     def step(s, h=H, d=D, j=J, r1=R1, r2=R2, delta=b.delta, gamma=b.gamma):
@@ -89,7 +94,7 @@ def run_gpu(args):
         s.last_infos = infos
         return infos
 
-    s = make("mixed")
+    s = make("mixed", tune=not args.no_autotune)
     for _ in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
@@ -135,7 +140,7 @@ def run_gpu(args):
                 "launches_per_step": launches, "per_level_launch_levels": lo}
 
     # plain FP64 comparators: batched, and one instance at a time
-    s64 = make("fp64")
+    s64 = make("fp64", tune=not args.no_autotune)
     step(s64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -168,6 +173,7 @@ def run_gpu(args):
         "cg_iters_mean": round(float(np.mean(cg)), 2),
         "passes_max": max(i["passes"] for i in infos),
         "profile_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "autotuned": tuned or None,
         "symbolic": {k: stats[k] for k in ("nnz_L", "L_storage", "supernodes", "levels", "etree_height")},
     }
     return value, el, roofline, extra, b
@@ -242,6 +248,7 @@ def main():
     ap.add_argument("--single", type=int, default=4, help="instances timed on the plain FP64 path")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="library default schedule instead of the autotuner's")
     ap.add_argument("--profile-hsolve", type=int, default=0,
                     help="counter-collection mode: calibration copy + this many H_gamma^{-1} applications")
     args = ap.parse_args()

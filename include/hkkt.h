@@ -141,6 +141,29 @@ int hkkt_analyze_group(hkkt_ctx *ctx, int G, const int64_t *x_off, const int64_t
                        const int64_t *H_rowptr, const int32_t *H_col,
                        const int64_t *J_rowptr, const int32_t *J_col);
 
+/* Autotuner (run once per pattern, after hkkt_analyze or
+ * hkkt_analyze_group): times candidate schedules on the given values and
+ * keeps the fastest. Candidates: supernode amalgamation relax in {0, 1, 2}
+ * (supernode shapes: fewer, wider supernodes and fewer levels against more
+ * stored zeros) x the number of top tree levels whose triangular solves run
+ * in the single-launch tree kernel (levels of at most {0, 8, 32, 128}
+ * supernodes). Cost per candidate (milliseconds, host clock around
+ * synchronised work): with right-hand sides r1, r2 (as for hkkt_solve_batch;
+ * r2 may be NULL when m = 0), one hkkt_factor_batch plus one hkkt_solve_batch
+ * of the nb instances; with r1 = NULL a proxy: one factorization + one
+ * application of H_gamma^{-1} to all instances + four applications to a list
+ * of min(nb, 8) instances (the late CG iterations run on few instances). The
+ * chosen relax is written to the context's options and the pattern is
+ * re-analysed with it; choice[0] = relax, choice[1] = tree width. cost_ms
+ * (may be NULL) gets up to max_cost candidate costs in the order relax-major,
+ * width-minor. Values as for hkkt_factor_batch. The context is left analysed
+ * and not factored: call hkkt_factor_batch next. Returns 0 or a negative
+ * code (-3 if not analysed). */
+int hkkt_autotune(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
+                  const double *J_val, const double *delta, const double *gamma,
+                  const double *r1, const double *r2,
+                  int32_t choice[2], double *cost_ms, int max_cost);
+
 /* Numeric factorization of nb instances that share the analysed pattern
  * (Sec. 2: once per matrix; Algorithm 1 "Try LL^T = chol(H_delta)").
  * H_val [nb][nnz(tril H)], D_x [nb][n_x], J_val [nb][nnz(J)], delta [nb],

@@ -447,6 +447,14 @@ struct hkkt_ctx {
     std::vector<int> breakdown;
     double ms[8] = {0};
     hkkt::Prof prof;
+    // copy of the analysed pattern (the autotuner re-runs the analysis)
+    struct {
+        int G = 1;
+        int64_t n = 0, m = 0;
+        std::vector<int64_t> xo, yo, Hp, Jp;
+        std::vector<int32_t> Hi, Ji, perm;
+    } pat;
+    int tree_width = -1;          // autotuned tree-kernel width (-1: library default)
 };
 
 namespace hkkt {
@@ -970,10 +978,31 @@ static int analyze_ctx(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* 
         HIPCHK(hipSetDevice(c->device));
         build_devsym(c->dev, c->sym.S, c->stream, lds_rows_limit(c->opt.precision == HKKT_MIXED ? 4 : 8));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->pat.Hp.data() != Hp) {   // keep a copy for re-analysis (not when re-analysing from it)
+            c->tree_width = -1;         // a new pattern drops the tuned choice
+            c->pat.G = G;
+            c->pat.n = n;
+            c->pat.m = m;
+            c->pat.xo.assign(x_off ? x_off : nullptr, x_off ? x_off + G + 1 : nullptr);
+            c->pat.yo.assign(y_off ? y_off : nullptr, y_off ? y_off + G + 1 : nullptr);
+            c->pat.Hp.assign(Hp, Hp + n + 1);
+            c->pat.Hi.assign(Hi, Hi + Hp[n]);
+            c->pat.Jp.assign(Jp, Jp + m + 1);
+            c->pat.Ji.assign(Ji, Ji + Jp[m]);
+            c->pat.perm.assign(perm ? perm : nullptr, perm ? perm + n : nullptr);
+        }
+        if (c->tree_width >= 0) c->dev.tree_width = c->tree_width;
         c->analysed = true;
         c->ms[0] = now_ms() - t0;
         return HKKT_OK;
     })
+}
+
+// analysis of the stored pattern with the context's current options
+static int reanalyze(hkkt_ctx* c) {
+    auto& P = c->pat;
+    return analyze_ctx(c, P.G, P.xo.empty() ? nullptr : P.xo.data(), P.yo.empty() ? nullptr : P.yo.data(), P.n, P.m,
+                       P.Hp.data(), P.Hi.data(), P.Jp.data(), P.Ji.data(), P.perm.empty() ? nullptr : P.perm.data());
 }
 
 extern "C" {
@@ -1101,6 +1130,123 @@ int hkkt_analyze(hkkt_ctx* c, int64_t n, int64_t m, const int64_t* Hp, const int
 int hkkt_analyze_group(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* y_off, int64_t n, int64_t m,
                        const int64_t* Hp, const int32_t* Hi, const int64_t* Jp, const int32_t* Ji) {
     return analyze_ctx(c, G, x_off, y_off, n, m, Hp, Hi, Jp, Ji, nullptr);
+}
+
+int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* delta,
+                  const double* gamma, const double* r1, const double* r2, int32_t choice[2], double* cost_ms,
+                  int max_cost) {
+    if (!c || !choice) return HKKT_ERR_ARG;
+    if (!c->analysed) { c->err = "autotune before analyze"; return HKKT_ERR_STATE; }
+    if (nb < 1 || !Dx || !delta || !gamma || (c->sym.S.nnzH > 0 && !H) || (c->sym.S.nnzJ > 0 && !J)) {
+        c->err = "bad autotune arguments";
+        return HKKT_ERR_ARG;
+    }
+    ABI_GUARD(c, {
+        static const int relaxes[] = {0, 1, 2};
+        static const int widths[] = {0, 8, 32, 128};
+        const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
+        hipStream_t st = c->stream;
+        // outputs of the trial solves (same pointer mode as the inputs)
+        const i64 nxo = (i64)nb * c->pat.n, nyo = (i64)nb * std::max<int64_t>(c->pat.m, 1);
+        DBuf dx, dy;
+        std::vector<double> hx, hy;
+        double *xo = nullptr, *yo = nullptr;
+        if (r1) {
+            if (dev) {
+                dx.ensure(nxo * 8);
+                dy.ensure(nyo * 8);
+                xo = dx.as<double>();
+                yo = dy.as<double>();
+            } else {
+                hx.resize(nxo);
+                hy.resize(nyo);
+                xo = hx.data();
+                yo = hy.data();
+            }
+        }
+        const bool prof_on = c->prof.on;
+        c->prof.on = false;
+        double best = INFINITY;
+        int best_relax = c->opt.relax, best_width = 32, k = 0;
+        for (int relax : relaxes) {
+            c->opt.relax = relax;
+            int rc = reanalyze(c);
+            if (rc != HKKT_OK) return rc;
+            Batch& B = c->main;
+            alloc_values(c, B, nb);
+            load_values(c, B, H, Dx, J, delta, gamma, nullptr, dev);
+            std::vector<int> all(nb, 1);
+            factor_batch(c, B, all);   // warm-up (allocation)
+            double t0 = now_ms();
+            factor_batch(c, B, all);
+            const double fms = now_ms() - t0;
+            alloc_solve(c, B);
+            const Symbolic& S = c->sym.S;
+            if (B.prec == HKKT_MIXED) {
+                LAUNCH(10, k_fill<float>, dim3(grid1((i64)nb * S.n)), dim3(kBlock), 0, st, B.X.as<float>(),
+                       (i64)nb * S.n, 1.0f);
+            } else {
+                LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.n)), dim3(kBlock), 0, st, B.X.as<double>(),
+                       (i64)nb * S.n, 1.0);
+            }
+            // a small list (the late CG iterations run on few instances)
+            const int ksmall = std::min(nb, 8);
+            std::vector<int> small(ksmall);
+            for (int i = 0; i < ksmall; i++) small[i] = i;
+            HIPCHK(hipMemcpyAsync(B.ids_a.p, small.data(), ksmall * 4, hipMemcpyHostToDevice, st));
+            for (int w : widths) {
+                c->dev.tree_width = w;
+                if (r1) {
+                    // the quantity being tuned: factor + solve to the tolerance
+                    t0 = now_ms();
+                    int rc2 = hkkt_factor_batch(c, nb, H, Dx, J, delta, gamma, nullptr, nullptr);
+                    if (rc2 >= 0) rc2 = hkkt_solve_batch(c, nb, r1, r2, xo, yo, nullptr);
+                    if (rc2 < 0) return rc2;
+                    const double cost = now_ms() - t0;
+                    if (cost_ms && k < max_cost) cost_ms[k] = cost;
+                    k++;
+                    if (cost < best) {
+                        best = cost;
+                        best_relax = relax;
+                        best_width = w;
+                    }
+                    continue;
+                }
+                auto run = [&](const int* ids, int nids) {
+                    if (B.prec == HKKT_MIXED) launch_trisolve<float>(c, B, ids, nids, nullptr);
+                    else launch_trisolve<double>(c, B, ids, nids, nullptr);
+                };
+                run(nullptr, nb);
+                HIPCHK(hipStreamSynchronize(st));
+                t0 = now_ms();
+                for (int r = 0; r < 3; r++) run(nullptr, nb);
+                HIPCHK(hipStreamSynchronize(st));
+                const double full = (now_ms() - t0) / 3;
+                t0 = now_ms();
+                for (int r = 0; r < 3; r++) run(B.ids_a.as<int>(), ksmall);
+                HIPCHK(hipStreamSynchronize(st));
+                const double part = (now_ms() - t0) / 3;
+                // one factorization, one full-batch application and four on
+                // a few instances (the CG tail)
+                const double cost = fms + full + 4 * part;
+                if (cost_ms && k < max_cost) cost_ms[k] = cost;
+                k++;
+                if (cost < best) {
+                    best = cost;
+                    best_relax = relax;
+                    best_width = w;
+                }
+            }
+        }
+        c->opt.relax = best_relax;
+        c->tree_width = best_width;
+        const int rc = reanalyze(c);
+        c->prof.on = prof_on;
+        if (rc != HKKT_OK) return rc;
+        choice[0] = best_relax;
+        choice[1] = best_width;
+        return HKKT_OK;
+    })
 }
 
 int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* delta,

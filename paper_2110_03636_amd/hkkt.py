@@ -24,7 +24,7 @@ EXPORTS = [
     "hkkt_factor_batch", "hkkt_factor", "hkkt_solve_batch", "hkkt_solve", "hkkt_inertia",
     "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
-    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group",
+    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree"]
@@ -85,6 +85,7 @@ def lib():
         L.hkkt_analyze.argtypes = [V, C.c_int64, C.c_int64, V, V, V, V, V]
         L.hkkt_analyze_group.argtypes = [V, C.c_int, V, V, C.c_int64, C.c_int64, V, V, V, V]
         L.hkkt_factor_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V]
+        L.hkkt_autotune.argtypes = [V, C.c_int, V, V, V, V, V, V, V, V, V, C.c_int]
         L.hkkt_factor.argtypes = [V, V, V, V, C.c_double, C.c_double, V]
         L.hkkt_solve_batch.argtypes = [V, C.c_int, V, V, V, V, V]
         L.hkkt_solve.argtypes = [V, V, V, V, V, V]
@@ -354,6 +355,31 @@ class Solver(_SymbolicView):
         self.nb = nb
         return rc, st, fc
 
+    def autotune(self, H_val, D_x, J_val, delta, gamma, r1=None, r2=None):
+        """Pick relax and the tree-kernel width for the analysed pattern by
+        timing candidates on these values, with trial solves of r1, r2 when
+        given (see hkkt_autotune). Returns {"relax", "tree_width", "cost_ms":
+        [[relax, width, ms], ...]}; the context is re-analysed and must be
+        factored next."""
+        delta = np.atleast_1d(np.asarray(delta, np.float64)).reshape(-1)
+        gamma = np.atleast_1d(np.asarray(gamma, np.float64)).reshape(-1)
+        nb = int(delta.shape[0]) // self.G
+        Hv = self._arr(H_val, nb, -1)
+        Dx = self._arr(D_x, nb, self.n)
+        Jv = self._arr(J_val, nb, -1) if self.m > 0 else None
+        if Jv is not None and Jv.shape[1] == 0:
+            Jv = None
+        R1 = self._arr(r1, nb, self.n) if r1 is not None else None
+        R2 = self._arr(r2, nb, self.m) if (r1 is not None and self.m > 0) else None
+        choice = np.zeros(2, np.int32)
+        cost = np.full(12, np.nan)
+        _check(lib().hkkt_autotune(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv), delta.ctypes.data,
+                                   gamma.ctypes.data, _ptr(R1), _ptr(R2), choice.ctypes.data, cost.ctypes.data, 12),
+               self._ctx)
+        self.nb = 0   # re-analysed: factor next
+        table = [[r, w, float(cost[i * 4 + j])] for i, r in enumerate((0, 1, 2)) for j, w in enumerate((0, 8, 32, 128))]
+        return {"relax": int(choice[0]), "tree_width": int(choice[1]), "cost_ms": table}
+
     def factor_batch(self, batch):
         return self.factor(batch.H_val, batch.D_x, batch.J_val, batch.delta, batch.gamma)
 
@@ -367,6 +393,8 @@ class Solver(_SymbolicView):
         """Returns (rc, x [nb, n_x], y [nb, m], infos: nb * G dicts, index
         b * G + k)."""
         nb = self.nb
+        if not nb:   # nothing factored: let the library report the state error
+            _check(lib().hkkt_solve_batch(self._ctx, 1, None, None, None, None, None), self._ctx)
         R1 = self._arr(r1, nb, self.n)
         R2 = self._arr(r2, nb, self.m) if self.m > 0 else None
         x = self._out(nb, self.n)

@@ -301,3 +301,24 @@ def test_deterministic_and_atomic_forward_agree():
             assert np.array_equal(np.concatenate([x2, y2], axis=1), out[1])
     d = np.linalg.norm(out[0] - out[1], axis=1) / np.linalg.norm(out[1], axis=1)
     assert d.max() < 1e-6, d
+
+
+def test_autotune_picks_min_cost_and_solves():
+    """The autotuner times all twelve candidates, keeps the cheapest, leaves
+    the context analysed with that relax, and the solve that follows meets
+    the oracle's residual bar."""
+    b = synth.grid_like(3000, nb=4, seed=39, gammas=(1e4,), dx_exp=6.0)
+    s = _solver(b, precision="mixed")
+    r0 = s.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma)      # proxy objective
+    assert min(r0["cost_ms"], key=lambda c: c[2])[:2] == [r0["relax"], r0["tree_width"]]
+    r = s.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma, b.r1, b.r2)   # trial solves
+    assert len(r["cost_ms"]) == 12 and all(np.isfinite(c[2]) and c[2] > 0 for c in r["cost_ms"])
+    best = min(r["cost_ms"], key=lambda c: c[2])
+    assert (best[0], best[1]) == (r["relax"], r["tree_width"])
+    ref = hkkt.Symbolic.from_pattern(b.pattern, relax=r["relax"]).stats()
+    assert s.stats()["supernodes"] == ref["supernodes"]
+    with pytest.raises(hkkt.HKKTError):        # re-analysed: not factored
+        s.solve(b.r1, b.r2)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
