@@ -179,6 +179,70 @@ def run_gpu(args):
     return value, el, roofline, extra, b
 
 
+# dense matrix-core peaks of MI355X (TFLOP/s)
+MFMA_PEAK = {"mixed": 157.3, "fp64": 78.6}
+LDS_FRONT_ROWS = {"mixed": 128, "fp64": 90}   # fronts above these row counts take the blocked MFMA path
+FRONT_NB = 32                                 # columns per step of the blocked fronts
+
+
+def big_front_flops(sym, lds_rows):
+    """Flops of the trailing updates (C -= L21 L21^T over the lower triangle)
+    of the fronts that take the blocked MFMA path, and of the whole
+    factorization (sum over columns of c_j^2 multiply-adds, c_j = entries
+    below the diagonal of column j)."""
+    import numpy as np
+    sn = sym.supernodes()
+    first, rowptr = sn["first"], sn["rowptr"]
+    upd = 0
+    for q in range(first.size - 1):
+        w = int(first[q + 1] - first[q])
+        nr = int(rowptr[q + 1] - rowptr[q])
+        if nr <= lds_rows:
+            continue
+        for kb in range(0, w, FRONT_NB):
+            bw = min(FRONT_NB, w - kb)
+            mt = nr - kb - bw
+            upd += mt * (mt + 1) * bw          # lower triangle, 2 flops per multiply-add
+    return upd, float(sym.stats()["flops_proxy"]) * 2
+
+
+def factor_mfma(args):
+    """Numeric factorization of one dense-like system (the generator of the
+    1200-variable configuration at a larger size), whose top supernodes are
+    dense fronts of thousands of rows: achieved TFLOP/s of the blocked
+    trailing updates (k_big_update, MFMA) against the matrix-core peak."""
+    import torch
+    from paper_2110_03636_amd import hkkt, synth
+    b = synth.dense_like(args.factor_mfma, seed=1000 + args.factor_mfma)
+    dev = lambda x: torch.as_tensor(x, device="cuda")
+    H, D, J = dev(b.H_val), dev(b.D_x), dev(b.J_val)
+    out = {}
+    for prec in ("mixed", "fp64"):
+        s = hkkt.Solver(precision=prec, device=True)
+        s.analyze(b.pattern)
+        s.factor(H, D, J, b.delta, b.gamma)
+        torch.cuda.synchronize()
+        s.profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rc, st, fc = s.factor(H, D, J, b.delta, b.gamma)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        prof = s.profile_end()
+        upd, total = big_front_flops(s, LDS_FRONT_ROWS[prec])
+        big_ms = prof["front_big"][0] / args.steps
+        out[prec] = {"factor_ms": round(el * 1e3, 3), "status": int(st[0]),
+                     "big_front_ms": round(big_ms, 3), "big_front_update_gflop": round(upd / 1e9, 2),
+                     "factor_gflop": round(total / 1e9, 2),
+                     "big_front_tflops": round(upd / (big_ms * 1e-3) / 1e12, 2),
+                     "factor_tflops": round(total / el / 1e12, 2),
+                     "peak_tflops": MFMA_PEAK[prec],
+                     "big_front_frac": round(upd / (big_ms * 1e-3) / 1e12 / MFMA_PEAK[prec], 4)}
+    print(json.dumps({"workload": f"dense-like n_x={args.factor_mfma}, m={args.factor_mfma // 2}, one instance",
+                      "symbolic": {k: s.stats()[k] for k in ("nnz_L", "L_storage", "max_width", "supernodes")},
+                      **out}))
+
+
 def profile_hsolve(args):
     """Counter-collection driver: a 1 GiB device copy (calibration of the
     byte counters) followed by args.profile_hsolve applications of
@@ -249,6 +313,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule instead of the autotuner's")
+    ap.add_argument("--factor-mfma", type=int, default=0,
+                    help="factorization of one dense-like system of this n_x (MFMA large-front measurement)")
     ap.add_argument("--profile-hsolve", type=int, default=0,
                     help="counter-collection mode: calibration copy + this many H_gamma^{-1} applications")
     args = ap.parse_args()
@@ -259,6 +325,9 @@ def main():
         sys.exit(2)
     if args.profile_hsolve:
         profile_hsolve(args)
+        return
+    if args.factor_mfma:
+        factor_mfma(args)
         return
     value, el, roofline, extra, b = run_gpu(args)
     tr = load_traffic()

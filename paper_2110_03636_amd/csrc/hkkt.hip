@@ -157,6 +157,7 @@ struct DevSym {
     // rank pair lists (front, child) and per-front (nr, w) on the host
     DBuf big_pairs;
     std::vector<std::vector<std::pair<i32, i32>>> big_pair_seg;   // [level][rank] = (offset, count) in pairs
+    std::vector<std::vector<int>> big_pair_maxnc;                // [level][rank] = widest child CB (columns)
     std::vector<std::pair<int, int>> big_nrw;                     // parallel to lev_big
     // triangular-solve lists per (level, size class): classes 0..6 are the
     // segmented wavefront kernels (SEG, R) = (16,1) (32,1) (64,1) (64,2)
@@ -262,6 +263,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     {
         std::vector<i32> pairs;
         D.big_pair_seg.assign(S.nlevels, {});
+        D.big_pair_maxnc.assign(S.nlevels, {});
         D.big_nrw.clear();
         for (i32 s2 : big)
             D.big_nrw.push_back({(int)(S.sn_rowptr[s2 + 1] - S.sn_rowptr[s2]), S.sn_first[s2 + 1] - S.sn_first[s2]});
@@ -273,14 +275,19 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
             }
             for (int r = 0; r < maxc; r++) {
                 const i32 off = (i32)(pairs.size() / 2);
+                int maxnc = 0;
                 for (i32 q = D.big_ptr[l]; q < D.big_ptr[l + 1]; q++) {
                     const i32 s2 = big[q];
                     if (S.child_ptr[s2 + 1] - S.child_ptr[s2] > r) {
+                        const i32 ch = S.child_list[S.child_ptr[s2] + r];
                         pairs.push_back(s2);
-                        pairs.push_back(S.child_list[S.child_ptr[s2] + r]);
+                        pairs.push_back(ch);
+                        maxnc = std::max(maxnc, (int)(S.sn_rowptr[ch + 1] - S.sn_rowptr[ch]) -
+                                                    (S.sn_first[ch + 1] - S.sn_first[ch]));
                     }
                 }
                 D.big_pair_seg[l].push_back({off, (i32)(pairs.size() / 2) - off});
+                D.big_pair_maxnc[l].push_back(maxnc);
             }
         }
         upload(D.big_pairs, pairs, st);
@@ -491,11 +498,14 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                 maxcb = std::max<i64>(maxcb, (i64)(nrw[q].first - nrw[q].second) * (nrw[q].first - nrw[q].second));
                 maxw = std::max(maxw, nrw[q].second);
             }
-            LAUNCH(2, k_big_zero<T>, dim3(grid1(maxcb, 512), ns_big, nb), dim3(kBlock), 0, st, D.v, fr, CB, active);
-            for (const auto& seg : D.big_pair_seg[l]) {
-                // children of any size: bound the grid by the largest front's CB
-                LAUNCH(2, k_big_extend<T>, dim3(grid1(maxcb, 512), seg.second, nb), dim3(kBlock), 0, st, D.v,
-                       D.big_pairs.as<i32>() + 2 * seg.first, L, CB, active);
+            LAUNCH(2, k_big_zero<T>, dim3(grid1(maxcb, 8192), ns_big, nb), dim3(kBlock), 0, st, D.v, fr, CB, active);
+            for (size_t r = 0; r < D.big_pair_seg[l].size(); r++) {
+                const auto& seg = D.big_pair_seg[l][r];
+                // columns of the widest child contribution block of this rank
+                const int ncc = D.big_pair_maxnc[l][r];
+                if (ncc <= 0) continue;
+                LAUNCH(2, k_big_extend<T>, dim3((ncc + kExtCols - 1) / kExtCols, seg.second, nb), dim3(kBlock), 0, st,
+                       D.v, D.big_pairs.as<i32>() + 2 * seg.first, L, CB, active);
             }
             for (int kb = 0; kb < maxw; kb += kNB) {
                 int cnt = 0, maxrows = 0;

@@ -241,21 +241,30 @@ __global__ void k_big_zero(SymView S, const i32* __restrict__ fronts, T* __restr
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nc * nc; i += (i64)gridDim.x * blockDim.x) C[i] = T(0);
 }
 
-// pairs[2q] = front, pairs[2q+1] = its child of the launch's rank
+// pairs[2q] = front, pairs[2q+1] = its child of the launch's rank. Work-group
+// x takes kExtCols consecutive columns of the child's contribution block
+// (lower triangle); its threads walk the rows, so the block is read in
+// contiguous column segments and the front is written along the (sorted)
+// row map.
+constexpr int kExtCols = 4;
+
 template <typename T>
-__global__ void k_big_extend(SymView S, const i32* __restrict__ pairs, T* __restrict__ L, T* __restrict__ CB,
-                             const int* active) {
+__global__ __launch_bounds__(kBlock) void k_big_extend(SymView S, const i32* __restrict__ pairs, T* __restrict__ L,
+                                                       T* __restrict__ CB, const int* active) {
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     const i32 s = pairs[2 * blockIdx.y], c = pairs[2 * blockIdx.y + 1];
-    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
     const int wc = S.sn_first[c + 1] - S.sn_first[c];
-    const i64 ncc = (S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
+    const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
+    const int j0 = blockIdx.x * kExtCols;
+    if (j0 >= ncc) return;
+    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
     const i32* rel = S.relmap + S.sn_uvptr[c];
     const T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[c];
-    for (i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x; idx < ncc * ncc; idx += (i64)gridDim.x * blockDim.x) {
-        const int j = (int)(idx / ncc), i = (int)(idx - (i64)j * ncc);
-        if (i >= j) F.at(rel[i], rel[j]) += C[idx];
+    for (int j = j0; j < min(ncc, j0 + kExtCols); j++) {
+        const int rj = rel[j];
+        const T* cj = C + (i64)j * ncc;
+        for (int i = j + threadIdx.x; i < ncc; i += blockDim.x) F.at(rel[i], rj) += cj[i];
     }
 }
 
