@@ -585,11 +585,18 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
             case 5: HKKT_TRI_S(64, 8) break;
             case 6: HKKT_TRI_S(64, 16) break;
             default: {
-                const size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
-                if (lds > kMaxLds) throw Error(HKKT_ERR_DEVICE, "supernode rows exceed the LDS triangular-solve limit");
-                if (fwd && push) LAUNCH(kf, (k_fwd<T, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                else if (fwd) LAUNCH(kf, (k_fwd<T, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                else LAUNCH(kb, k_bwd<T>, dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
+                // the working vector in LDS when it fits, else in the solve and update vectors
+                size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
+                if (lds <= kMaxLds) {
+                    if (fwd && push) LAUNCH(kf, (k_fwd<T, true, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                    else if (fwd) LAUNCH(kf, (k_fwd<T, false, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                    else LAUNCH(kb, (k_bwd<T, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
+                } else {
+                    lds = (size_t)kTri * kTri * sizeof(T);
+                    if (fwd && push) LAUNCH(kf, (k_fwd<T, true, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                    else if (fwd) LAUNCH(kf, (k_fwd<T, false, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
+                    else LAUNCH(kb, (k_bwd<T, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
+                }
             }
         }
 #undef HKKT_TRI_S

@@ -438,7 +438,10 @@ __global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __r
 // The diagonal block is staged in LDS in kTri x kTri tiles and solved by one
 // wavefront with lane shuffles.
 // ---------------------------------------------------------------------------
-template <typename T, bool PUSH>
+// GU: the working vector does not fit the LDS budget and lives in the solve
+// vector (the supernode's columns) and in the supernode's update vector
+// (rows below; forward only), with only the diagonal tile in LDS.
+template <typename T, bool PUSH, bool GU>
 __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
                                                 T* __restrict__ X, T* __restrict__ UV, const int* ids,
                                                 const CGState* st) {
@@ -454,7 +457,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
     const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
     T* x = X + (i64)b * S.n;
     T* uvb = UV + (i64)b * S.UVsize;
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) u[i] = i < w ? x[f + i] : T(0);
+    T* ub = uvb + S.sn_uvptr[s];
+    auto U = [&](int i) -> T& { return GU ? (i < w ? x[f + i] : ub[i - w]) : u[i]; };
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+        if (!GU) u[i] = i < w ? x[f + i] : T(0);
+        else if (i >= w) ub[i - w] = T(0);
+    }
     __syncthreads();
     for (int q = S.child_ptr[s]; !PUSH && q < S.child_ptr[s + 1]; q++) {
         const i32 c = S.child_list[q];
@@ -462,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
         const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
         const i32* rel = S.relmap + S.sn_uvptr[c];
         const T* uc = uvb + S.sn_uvptr[c];
-        for (int k = threadIdx.x; k < ncc; k += blockDim.x) u[rel[k]] += uc[k];
+        for (int k = threadIdx.x; k < ncc; k += blockDim.x) U(rel[k]) += uc[k];
         __syncthreads();
     }
     for (int kb = 0; kb < w; kb += kTri) {
@@ -474,30 +482,34 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
         __syncthreads();
         if (threadIdx.x < kWave) {
             const int lane = threadIdx.x;
-            T val = lane < bw ? u[kb + lane] : T(0);
+            T val = lane < bw ? U(kb + lane) : T(0);
             for (int k = 0; k < bw; k++) {
                 if (lane == k) val = val / D[k * kTri + k];
                 const T yk = __shfl(val, k, kWave);
                 if (lane > k && lane < bw) val -= D[k * kTri + lane] * yk;
             }
-            if (lane < bw) u[kb + lane] = val;
+            if (lane < bw) U(kb + lane) = val;
         }
         __syncthreads();
         for (int i = kb + bw + threadIdx.x; i < nr; i += blockDim.x) {
             T sum = T(0);
-            for (int k = 0; k < bw; k++) sum += Lb[(i64)(kb + k) * nr + i] * u[kb + k];
-            u[i] -= sum;
+            for (int k = 0; k < bw; k++) sum += Lb[(i64)(kb + k) * nr + i] * U(kb + k);
+            U(i) -= sum;
         }
         __syncthreads();
     }
     for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-        if (i < w) x[f + i] = u[i];
-        else if (PUSH) unsafeAtomicAdd(&x[S.sn_rows[S.sn_rowptr[s] + i]], u[i]);
-        else uvb[S.sn_uvptr[s] + (i - w)] = u[i];
+        if (i < w) {
+            if (!GU) x[f + i] = u[i];
+        } else if (PUSH) {
+            unsafeAtomicAdd(&x[S.sn_rows[S.sn_rowptr[s] + i]], U(i));
+        } else if (!GU) {
+            ub[i - w] = u[i];
+        }
     }
 }
 
-template <typename T>
+template <typename T, bool GU>
 __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict__ list, const T* __restrict__ L,
                                                 T* __restrict__ X, const int* ids, const CGState* st) {
     extern __shared__ double smem_d[];
@@ -512,7 +524,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
     const i32* rows = S.sn_rows + S.sn_rowptr[s];
     const T* Lb = L + (i64)b * S.Lsize + S.sn_lptr[s];
     T* x = X + (i64)b * S.n;
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) u[i] = i < w ? x[f + i] : x[rows[i]];
+    // GU: columns in place in x, rows below read from x (ancestors, final)
+    auto U = [&](int i) -> T& { return GU ? (i < w ? x[f + i] : x[rows[i]]) : u[i]; };
+    if (!GU)
+        for (int i = threadIdx.x; i < nr; i += blockDim.x) u[i] = i < w ? x[f + i] : x[rows[i]];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int nblk = (w + kTri - 1) / kTri;
@@ -522,9 +537,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
         for (int jj = wid; jj < bw; jj += nw) {
             const int j = kb + jj;
             T sum = T(0);
-            for (int i = kb + bw + lane; i < nr; i += kWave) sum += Lb[(i64)j * nr + i] * u[i];
+            for (int i = kb + bw + lane; i < nr; i += kWave) sum += Lb[(i64)j * nr + i] * U(i);
             sum = wave_sum(sum);
-            if (lane == 0) u[j] -= sum;
+            if (lane == 0) U(j) -= sum;
         }
         for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
             const int jj = idx / bw, ii = idx - jj * bw;
@@ -532,17 +547,18 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
         }
         __syncthreads();
         if (threadIdx.x < kWave) {
-            T val = lane < bw ? u[kb + lane] : T(0);
+            T val = lane < bw ? U(kb + lane) : T(0);
             for (int k = bw - 1; k >= 0; k--) {
                 if (lane == k) val = val / D[k * kTri + k];
                 const T xk = __shfl(val, k, kWave);
                 if (lane < k) val -= D[lane * kTri + k] * xk;
             }
-            if (lane < bw) u[kb + lane] = val;
+            if (lane < bw) U(kb + lane) = val;
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < w; i += blockDim.x) x[f + i] = u[i];
+    if (!GU)
+        for (int i = threadIdx.x; i < w; i += blockDim.x) x[f + i] = u[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -322,3 +322,21 @@ def test_autotune_picks_min_cost_and_solves():
     assert s.factor_batch(b)[0] == 0
     rc, x, y, infos = s.solve(b.r1, b.r2)
     _check_solution(b, x, y, infos)
+
+
+def test_wide_supernodes_beyond_lds():
+    """FP64 supernodes of more than 4096 rows: the work-group triangular
+    solves keep the working vector in the solve and update vectors instead
+    of LDS. End-to-end residual checked by the oracle."""
+    b = synth.dense_like(10000, seed=1234)
+    s = _solver(b)
+    assert s.stats()["max_rows"] > 4096
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
+    # the same system in deterministic (pull) mode, which keeps the rows
+    # below in the update vectors
+    s2 = _solver(b, deterministic=1)
+    assert s2.factor_batch(b)[0] == 0
+    rc, x2, y2, infos2 = s2.solve(b.r1, b.r2)
+    _check_solution(b, x2, y2, infos2)
