@@ -243,6 +243,94 @@ def factor_mfma(args):
                       **out}))
 
 
+def uneven_group(args):
+    """Uneven sizes in one launch: args.uneven dense-like systems (n_x
+    log-uniform in [2000, 50000], m = n_x/2, each its own pattern) analysed as
+    one group and factored and solved together in mixed precision."""
+    import numpy as np
+    import torch
+    from paper_2110_03636_amd import hkkt, synth
+    mem = synth.uneven_dense_like(nb=args.uneven, lo=2000, hi=args.uneven_hi, seed=5000)
+    g = hkkt.GroupPattern([b.pattern for b in mem])
+    cat = hkkt.GroupPattern.concat
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+    H, D, J = dev(cat([b.H_val for b in mem])), dev(cat([b.D_x for b in mem])), dev(cat([b.J_val for b in mem]))
+    R1, R2 = dev(cat([b.r1 for b in mem])), dev(cat([b.r2 for b in mem]))
+    delta = np.stack([b.delta for b in mem], axis=1)
+    gamma = np.stack([b.gamma for b in mem], axis=1)
+    s = hkkt.Solver(precision="mixed", device=True, kkt_tol=1e-10)
+    t0 = time.perf_counter()
+    s.analyze_group(g)
+    t_an = time.perf_counter() - t0
+    print(f"uneven: analysed {g.G} members, n_x total {g.n_x} in {t_an:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st, fc = s.factor(H, D, J, delta, gamma)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    print(f"uneven: factor {t_f:.2f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    rc2, x, y, infos = s.solve(R1, R2)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    ok = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
+    st_ = s.stats()
+    print(json.dumps({"workload": f"{g.G} dense-like systems in one group, n_x log-uniform in [2000, {args.uneven_hi}] "
+                                  f"(min {min(b.pattern.n_x for b in mem)}, max {max(b.pattern.n_x for b in mem)}, "
+                                  f"total {g.n_x}), mixed precision, target RR<=1e-10",
+                      "analyze_s": round(t_an, 2), "factor_s": round(t_f, 3), "solve_s": round(t_s, 3),
+                      "solves_per_s": round(ok / (t_f + t_s), 3), "converged": f"{ok}/{g.G}",
+                      "max_rr": max(i["rr"] for i in infos), "fp64_fallbacks": sum(i["fp64_fallback"] for i in infos),
+                      "cg_iters_max": max(i["cg_iters"] for i in infos), "passes_max": max(i["passes"] for i in infos),
+                      "symbolic": {k: st_[k] for k in ("nnz_L", "L_storage", "cb_entries", "max_width", "levels")}}))
+
+
+def large_single(args):
+    """One large grid-like system (connected reading) in mixed precision,
+    gamma = 1e6: sustained factor + solve cycles on a fixed pattern, each with
+    a fresh D_x (the next interior iteration), after one autotuning."""
+    import numpy as np
+    import torch
+    from paper_2110_03636_amd import hkkt, synth
+    n = args.large
+    t0 = time.perf_counter()
+    b = synth.grid_like(n, nb=1, seed=5100, gammas=(1e6,), dx_exp=8.0)
+    print(f"large: generated n_x={n} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+    H, J, R1, R2 = dev(b.H_val), dev(b.J_val), dev(b.r1), dev(b.r2)
+    dxs = [dev(synth.fresh_dx(n, 5200 + k)[None]) for k in range(args.cycles)]
+    s = hkkt.Solver(precision="mixed", device=True, kkt_tol=1e-10)
+    t0 = time.perf_counter()
+    s.analyze(b.pattern)
+    t_an = time.perf_counter() - t0
+    print(f"large: analysed in {t_an:.1f} s", file=sys.stderr, flush=True)
+    tune = s.autotune(H, dxs[0], J, b.delta, b.gamma)
+    print(f"large: autotuned {tune['relax']}/{tune['tree_width']}", file=sys.stderr, flush=True)
+    s.factor(H, dxs[0], J, b.delta, b.gamma)
+    s.solve(R1, R2)
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for k in range(args.cycles):
+        s.factor(H, dxs[k], J, b.delta, b.gamma)
+        rc, x, y, infos = s.solve(R1, R2)
+        res.append(infos[0])
+        print(f"large: cycle {k} rr={infos[0]['rr']:.2e} cg={infos[0]['cg_iters']} fb={infos[0]['fp64_fallback']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ok = sum(1 for i in res if i["status"] == 0 and i["rr"] <= 1e-10)
+    st = s.stats()
+    print(json.dumps({"workload": f"grid-like n_x={n}, m={n // 2}, gamma=1e6, mixed precision, "
+                                  f"{args.cycles} factor+solve cycles with fresh D_x, target RR<=1e-10",
+                      "analyze_s": round(t_an, 2), "autotuned": {"relax": tune["relax"], "tree_width": tune["tree_width"]},
+                      "sustained_solves_per_s": round(ok / el, 3), "s_per_cycle": round(el / args.cycles, 3),
+                      "converged": f"{ok}/{args.cycles}", "max_rr": max(i["rr"] for i in res),
+                      "fp64_fallbacks": sum(i["fp64_fallback"] for i in res),
+                      "cg_iters_mean": round(float(np.mean([i["cg_iters"] for i in res])), 1),
+                      "symbolic": {k: st[k] for k in ("nnz_L", "L_storage", "levels", "max_width")}}))
+
+
 def profile_hsolve(args):
     """Counter-collection driver: a 1 GiB device copy (calibration of the
     byte counters) followed by args.profile_hsolve applications of
@@ -313,6 +401,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule instead of the autotuner's")
+    ap.add_argument("--uneven", type=int, default=0,
+                    help="this many dense-like systems of uneven sizes in one group (factor + solve once)")
+    ap.add_argument("--uneven-hi", type=int, default=50_000, help="largest n_x of --uneven")
+    ap.add_argument("--large", type=int, default=0, help="one grid-like system of this n_x: sustained cycles")
+    ap.add_argument("--cycles", type=int, default=20, help="factor + solve cycles of --large")
     ap.add_argument("--factor-mfma", type=int, default=0,
                     help="factorization of one dense-like system of this n_x (MFMA large-front measurement)")
     ap.add_argument("--profile-hsolve", type=int, default=0,
@@ -328,6 +421,12 @@ def main():
         return
     if args.factor_mfma:
         factor_mfma(args)
+        return
+    if args.uneven:
+        uneven_group(args)
+        return
+    if args.large:
+        large_single(args)
         return
     value, el, roofline, extra, b = run_gpu(args)
     tr = load_traffic()

@@ -226,9 +226,16 @@ const hkkt_symbolic *hkkt_get_symbolic(const hkkt_ctx *ctx);
  * H_gamma), [3] nnz(L) (structural), [4] L storage entries (supernodal
  * panels), [5] supernodes, [6] factor levels, [7] sum of c_j^2 over columns
  * (factor flop proxy), [8] max supernode width, [9] max supernode rows,
- * [10] contribution-block workspace entries, [11] etree height, [12] update
+ * [10] contribution-block workspace entries per instance (ranges reused
+ * across lifetimes), [11] etree height, [12] update
  * vector entries, [13] nnz(J). */
 int hkkt_symbolic_stats(const hkkt_symbolic *sym, int64_t stats[16]);
+
+/* Contribution-block workspace offsets (entries): cb_off[s] for supernode
+ * s, cb_off[ns] = workspace size per instance (stats[10]). Blocks share
+ * ranges when their lifetimes (from the supernode's level to its parent's)
+ * do not overlap. */
+int hkkt_symbolic_cb_offsets(const hkkt_symbolic *sym, int64_t *cb_off);
 
 /* Final elimination order: perm[k] = original index of pivot k. */
 int hkkt_symbolic_perm(const hkkt_symbolic *sym, int32_t *perm);

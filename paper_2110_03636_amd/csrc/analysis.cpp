@@ -5,6 +5,7 @@
 #include "analysis.hpp"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -594,6 +595,67 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
         S.level_sn.resize(ns);
         std::vector<i32> pos(S.level_ptr.begin(), S.level_ptr.end() - 1);
         for (i32 s = 0; s < ns; s++) S.level_sn[pos[lev[s]]++] = s;
+
+        // ---- contribution blocks by lifetime: the block of supernode s is
+        // written while its level is factored and read while its parent's
+        // level is; its range is free again from the level after the
+        // parent's. Best-fit reuse of freed ranges, blocks rounded to whole
+        // 256-byte lines of FP32.
+        std::map<i64, i64> by_off;                 // free range offset -> size
+        std::multimap<i64, i64> by_size;           // free range size -> offset
+        auto drop = [&](i64 off, i64 sz) {
+            auto r = by_size.equal_range(sz);
+            for (auto it = r.first; it != r.second; ++it)
+                if (it->second == off) { by_size.erase(it); break; }
+            by_off.erase(off);
+        };
+        auto release = [&](i64 off, i64 sz) {
+            auto nx = by_off.lower_bound(off);
+            if (nx != by_off.end() && off + sz == nx->first) {
+                const i64 o = nx->first, z = nx->second;
+                drop(o, z);
+                sz += z;
+            }
+            auto pv = by_off.lower_bound(off);
+            if (pv != by_off.begin()) {
+                --pv;
+                if (pv->first + pv->second == off) {
+                    const i64 o = pv->first, z = pv->second;
+                    drop(o, z);
+                    off = o;
+                    sz += z;
+                }
+            }
+            by_off[off] = sz;
+            by_size.emplace(sz, off);
+        };
+        std::vector<std::vector<std::pair<i64, i64>>> frees(S.nlevels + 1);
+        i64 top = 0;
+        for (i32 l = 0; l < S.nlevels; l++) {
+            for (const auto& f : frees[l]) release(f.first, f.second);
+            for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
+                const i32 s = S.level_sn[q];
+                const i64 nc = (S.sn_rowptr[s + 1] - S.sn_rowptr[s]) - (S.sn_first[s + 1] - S.sn_first[s]);
+                if (nc == 0) { S.sn_cbptr[s] = 0; continue; }
+                if (S.sn_parent[s] < 0) return "internal: root supernode with rows below its columns";
+                const i64 sz = (nc * nc + 63) / 64 * 64;
+                i64 off;
+                auto it = by_size.lower_bound(sz);
+                if (it != by_size.end()) {
+                    const i64 fo = it->second, fz = it->first;
+                    drop(fo, fz);
+                    off = fo;
+                    if (fz > sz) { by_off[fo + sz] = fz - sz; by_size.emplace(fz - sz, fo + sz); }
+                } else {
+                    off = top;
+                    top += sz;
+                }
+                S.sn_cbptr[s] = off;
+                frees[lev[S.sn_parent[s]] + 1].push_back({off, sz});
+            }
+        }
+        S.CBsize = top;
+        S.sn_cbptr[ns] = top;
     }
 
     // ---- assembly map: every entry of tril(P H_gamma P^T) with its sources,

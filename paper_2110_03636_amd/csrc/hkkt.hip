@@ -413,7 +413,7 @@ struct Batch {
     // values (FP64)
     DBuf H, J, JT, HF, Dx, Dxp, delta, gamma;
     // factor (Dinv: reciprocals of the diagonal of L, per column)
-    DBuf L, CB, fail, Dinv;
+    DBuf L, fail, Dinv;
     // solve workspace
     DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
@@ -444,6 +444,7 @@ struct hkkt_ctx {
     hkkt_symbolic sym;
     DevSym dev;
     Batch main, fb;               // fb: FP64 fallback sub-batch
+    DBuf cbws;                    // contribution-block workspace, shared: the batches factor one after the other
     std::vector<int> fb_idx;      // main index of each fallback instance
     int nb = 0;
     bool factored = false;
@@ -476,7 +477,7 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     hipStream_t st = c->stream;
     const int nb = B.nb;
     T* L = B.L.as<T>();
-    T* CB = B.CB.as<T>();
+    T* CB = c->cbws.as<T>();
     LAUNCH(10, k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
     LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb * S.G, INT_MAX);
     LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.vals(), L, active);
@@ -661,7 +662,7 @@ static void alloc_factor(hkkt_ctx* c, Batch& B) {
     const Symbolic& S = c->sym.S;
     B.L.ensure((size_t)B.nb * std::max<i64>(1, S.Lsize) * B.esz());
     B.Dinv.ensure((size_t)B.nb * S.n * B.esz());
-    B.CB.ensure((size_t)B.nb * std::max<i64>(1, S.CBsize) * B.esz());
+    c->cbws.ensure((size_t)B.nb * std::max<i64>(1, S.CBsize) * B.esz());
 }
 
 static void alloc_solve(hkkt_ctx* c, Batch& B) {
@@ -1117,6 +1118,12 @@ int hkkt_symbolic_stats(const hkkt_symbolic* sym, int64_t st[16]) {
     }
     st[14] = lower;
     st[15] = (int64_t)S.sn_rows.size();
+    return HKKT_OK;
+}
+
+int hkkt_symbolic_cb_offsets(const hkkt_symbolic* sym, int64_t* cb_off) {
+    if (!sym || !cb_off) return HKKT_ERR_ARG;
+    std::memcpy(cb_off, sym->S.sn_cbptr.data(), sym->S.sn_cbptr.size() * 8);
     return HKKT_OK;
 }
 

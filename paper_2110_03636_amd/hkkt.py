@@ -24,7 +24,7 @@ EXPORTS = [
     "hkkt_factor_batch", "hkkt_factor", "hkkt_solve_batch", "hkkt_solve", "hkkt_inertia",
     "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
-    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
+    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune", "hkkt_symbolic_cb_offsets",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree"]
@@ -99,6 +99,7 @@ def lib():
         L.hkkt_get_symbolic.argtypes = [V]
         L.hkkt_symbolic_stats.argtypes = [V, V]
         L.hkkt_symbolic_perm.argtypes = [V, V]
+        L.hkkt_symbolic_cb_offsets.argtypes = [V, V]
         L.hkkt_symbolic_supernodes.argtypes = [V, V, V, V, V, V, V]
         L.hkkt_get_factor.argtypes = [V, C.c_int, V, V, V]
         L.hkkt_hsolve.argtypes = [V, C.c_int, V, V]
@@ -191,6 +192,12 @@ class _SymbolicView:
         p = np.empty(n, np.int32)
         lib().hkkt_symbolic_perm(self._h(), p.ctypes.data)
         return p
+
+    def cb_offsets(self):
+        """Contribution-block offsets per supernode (+ workspace size)."""
+        o = np.empty(self.stats()["supernodes"] + 1, np.int64)
+        _check(lib().hkkt_symbolic_cb_offsets(self._h(), o.ctypes.data), None)
+        return o
 
     def supernodes(self):
         s = self.stats()

@@ -341,6 +341,12 @@ def workload(k: int, nb: int | None = None, n_x: int | None = None) -> Batch:
     raise ValueError(f"unknown workload {k}")
 
 
+def fresh_dx(n_x: int, seed: int, dx_exp: float = 8.0) -> np.ndarray:
+    """A new D_x = 10^U(-dx_exp, dx_exp) from PCG64(seed) (the next interior
+    iteration of a sequence on an unchanged pattern)."""
+    return _loguniform(_rng(seed), -dx_exp, dx_exp, n_x)
+
+
 def uneven_dense_like(nb: int = 64, lo: int = 2000, hi: int = 50_000, seed: int = 5000,
                       gamma: float = 1e4):
     """nb dense-like instances with n_x log-uniform in [lo, hi], m = n_x/2,

@@ -280,3 +280,41 @@ def test_group_argument_errors():
     with pytest.raises(hkkt.HKKTError) as e:
         hkkt.Symbolic(g.n_x, g.m, g.H_rowptr, g.H_col, g.J_rowptr, g.J_col, x_off=xo, y_off=g.y_off)
     assert e.value.code == hkkt.ERR_PATTERN and "member" in str(e.value)
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_contribution_blocks_never_overlap_while_live(k):
+    """The contribution block of supernode s is live from its level to its
+    parent's level (inclusive); two blocks live at the same level must not
+    share a workspace entry, and the workspace is at most the plain sum."""
+    b = _cases()[k]
+    sym = hkkt.Symbolic.from_pattern(b.pattern)
+    sn = sym.supernodes()
+    off = sym.cb_offsets()
+    first, rowptr, parent, lp, lsn = sn["first"], sn["rowptr"], sn["parent"], sn["level_ptr"], sn["level_sn"]
+    ns = first.size - 1
+    lev = np.empty(ns, int)
+    for l in range(lp.size - 1):
+        lev[lsn[lp[l]:lp[l + 1]]] = l
+    nc = (rowptr[1:] - rowptr[:-1]) - (first[1:] - first[:-1])
+    size = nc.astype(np.int64) ** 2
+    assert off[ns] == sym.stats()["cb_entries"] and off[ns] <= ((size + 63) // 64 * 64).sum()
+    has = np.nonzero(size)[0]
+    assert (off[has] + size[has] <= off[ns]).all() and (off[has] >= 0).all()
+    for l in range(lp.size - 1):
+        live = [q for q in has if lev[q] <= l <= lev[parent[q]]]
+        iv = sorted((off[q], off[q] + size[q]) for q in live)
+        for (a0, a1), (b0, b1) in zip(iv, iv[1:]):
+            assert a1 <= b0, (l, a0, a1, b0, b1)
+
+
+def test_group_contribution_workspace_below_sum():
+    """Reuse pays on the dense-like members: the workspace is well below the
+    sum of the blocks."""
+    mem = [H.tiny_dense_like(300, 36), H.tiny_dense_like(500, 37), H.tiny_grid_like(3000, 38)]
+    g = hkkt.GroupPattern([b.pattern for b in mem])
+    sym = hkkt.Symbolic.from_group(g)
+    sn = sym.supernodes()
+    nc = (sn["rowptr"][1:] - sn["rowptr"][:-1]) - (sn["first"][1:] - sn["first"][:-1])
+    rounded = ((nc.astype(np.int64) ** 2 + 63) // 64 * 64).sum()
+    assert sym.cb_offsets()[-1] < 0.9 * rounded
