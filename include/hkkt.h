@@ -81,7 +81,13 @@ typedef struct {
     int relax;              /* supernode amalgamation: 0 none (fundamental), 1 default, 2 more */
     int deterministic;      /* 1: forward solves pull children's update vectors in a fixed order
                                (bitwise reproducible); 0: right-looking FP atomics (faster) */
-    int reserved[5];
+    int mixed_check;        /* mixed precision: 1 applies each FP32 factor M once to a fixed probe
+                               vector v and refactors in FP64 at factor time when
+                               ||v - H_gamma M^{-1} v|| / ||v|| > mixed_check_tol; 0 (default):
+                               only the stall test of the solve decides (measured faster on the
+                               benchmark: the first FP32 pass still warms the FP64 start) */
+    double mixed_check_tol; /* default 0.5 */
+    int reserved[2];
 } hkkt_options;
 
 typedef struct {
@@ -97,7 +103,7 @@ typedef struct {
 
 /* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
- * ordering 0, relax 1, deterministic 0. */
+ * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream

@@ -24,6 +24,11 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <condition_variable>
+#include <mutex>
+#include <thread>
+#include <functional>
+#include <exception>
 #include <vector>
 
 struct hkkt_symbolic {
@@ -58,16 +63,27 @@ static double now_ms() {
 constexpr int kNProf = 13;
 struct Prof {
     bool on = false;
+    std::mutex mu;                                   // launches may come from two host threads
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    std::vector<std::pair<int, size_t>> recs;
-    hipEvent_t next() {
-        if (used == pool.size()) {
+    std::vector<std::pair<int, size_t>> recs;        // (kind, index of the start event; end = +1)
+    size_t take2() {
+        std::lock_guard<std::mutex> g(mu);
+        while (pool.size() < used + 2) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e));
             pool.push_back(e);
         }
-        return pool[used++];
+        used += 2;
+        return used - 2;
+    }
+    hipEvent_t ev(size_t i) {
+        std::lock_guard<std::mutex> g(mu);
+        return pool[i];
+    }
+    void add(int kind, size_t i0) {
+        std::lock_guard<std::mutex> g(mu);
+        recs.push_back({kind, i0});
     }
     ~Prof() {
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
@@ -78,28 +94,31 @@ struct ProfScope {
     hipStream_t st;
     int kind;
     size_t i0 = 0;
+    bool rec = false;
     ProfScope(Prof& p_, hipStream_t s, int k) : p(p_), st(s), kind(k) {
         if (p.on) {
-            i0 = p.used;
-            HIPCHK(hipEventRecord(p.next(), st));
+            i0 = p.take2();
+            HIPCHK(hipEventRecord(p.ev(i0), st));
+            rec = true;
         }
     }
     ~ProfScope() {
-        if (p.on && p.used == i0 + 1) {
+        if (rec) {
             try {
-                (void)hipEventRecord(p.next(), st);
-                p.recs.push_back({kind, i0});
+                (void)hipEventRecord(p.ev(i0 + 1), st);
+                p.add(kind, i0);
             } catch (...) {
             }
         }
     }
 };
 
-#define LAUNCH(kind, ...)                                   \
-    do {                                                    \
-        ::hkkt::ProfScope ps_(c->prof, c->stream, kind);    \
-        hipLaunchKernelGGL(__VA_ARGS__);                    \
-        KCHK();                                             \
+// launch on stream STRM with per-kernel events when profiling is on
+#define LAUNCH(kind, kern, grid, block, shmem, strm, ...)       \
+    do {                                                        \
+        ::hkkt::ProfScope ps_(c->prof, strm, kind);             \
+        hipLaunchKernelGGL(kern, grid, block, shmem, strm, __VA_ARGS__); \
+        KCHK();                                                 \
     } while (0)
 
 // ---------------------------------------------------------------------------
@@ -409,6 +428,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
 // ---------------------------------------------------------------------------
 struct Batch {
     int nb = 0;
+    hipStream_t stream = nullptr;   // all of this batch's work is ordered on it
     int prec = HKKT_FP64;   // precision of L / triangular solves
     // values (FP64)
     DBuf H, J, JT, HF, Dx, Dxp, delta, gamma;
@@ -445,6 +465,8 @@ struct hkkt_ctx {
     DevSym dev;
     Batch main, fb;               // fb: FP64 fallback sub-batch
     DBuf cbws;                    // contribution-block workspace, shared: the batches factor one after the other
+    hipStream_t fb_stream = nullptr;  // FP64 fallback work, concurrent with the FP32 refinement
+    std::vector<std::unique_ptr<Batch>> fbx;   // fallback batches of a solve's stall groups
     std::vector<int> fb_idx;      // main index of each fallback instance
     int nb = 0;
     bool factored = false;
@@ -474,7 +496,7 @@ template <typename T>
 static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     const Symbolic& S = c->sym.S;
     const DevSym& D = c->dev;
-    hipStream_t st = c->stream;
+    hipStream_t st = B.stream;
     const int nb = B.nb;
     T* L = B.L.as<T>();
     T* CB = c->cbws.as<T>();
@@ -556,9 +578,9 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         }
         if (wend > 0) {
             const unsigned nblk = (unsigned)((wend + (kBlock / kWave) - 1) / (kBlock / kWave));
-            if (fwd && push) LAUNCH(kf, (k_fwd_lvl<T, true>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
-            else if (fwd) LAUNCH(kf, (k_fwd_lvl<T, false>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
-            else LAUNCH(kb, (k_bwd_lvl<T>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, lt, L, Dv, X, ids, nids, st_);
+            if (fwd && push) LAUNCH(kf, (k_fwd_lvl<T, true>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
+            else if (fwd) LAUNCH(kf, (k_fwd_lvl<T, false>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
+            else LAUNCH(kb, (k_bwd_lvl<T>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, L, Dv, X, ids, nids, st_);
         }
     }
     for (int cls = 4; cls < kTriClasses; cls++) {
@@ -574,11 +596,11 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const int npad = (nids + G - 1) / G * G;                                                                  \
         const i64 waves = (i64)cnt * npad / G;                                                                    \
         const unsigned nblk = (unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave));                      \
-        if (fwd && push) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, true>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, \
+        if (fwd && push) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, true>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, \
                                 cnt, npad, L, Dv, X, UV, ids, nids, st_);                                         \
-        else if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, false>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, \
+        else if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, false>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, cnt, \
                              npad, L, Dv, X, UV, ids, nids, st_);                                                 \
-        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, c->stream, D.v, dsc, cnt, npad, L, Dv,  \
+        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, cnt, npad, L, Dv,  \
                     X, ids, nids, st_);                                                                           \
     }
         switch (cls) {
@@ -589,14 +611,14 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
                 // the working vector in LDS when it fits, else in the solve and update vectors
                 size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
                 if (lds <= kMaxLds) {
-                    if (fwd && push) LAUNCH(kf, (k_fwd<T, true, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                    else if (fwd) LAUNCH(kf, (k_fwd<T, false, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                    else LAUNCH(kb, (k_bwd<T, false>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
+                    if (fwd && push) LAUNCH(kf, (k_fwd<T, true, false>), dim3(cnt, nids), dim3(kBlock), lds, B.stream, D.v, lst, L, X, UV, ids, st_);
+                    else if (fwd) LAUNCH(kf, (k_fwd<T, false, false>), dim3(cnt, nids), dim3(kBlock), lds, B.stream, D.v, lst, L, X, UV, ids, st_);
+                    else LAUNCH(kb, (k_bwd<T, false>), dim3(cnt, nids), dim3(kBlock), lds, B.stream, D.v, lst, L, X, ids, st_);
                 } else {
                     lds = (size_t)kTri * kTri * sizeof(T);
-                    if (fwd && push) LAUNCH(kf, (k_fwd<T, true, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                    else if (fwd) LAUNCH(kf, (k_fwd<T, false, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, UV, ids, st_);
-                    else LAUNCH(kb, (k_bwd<T, true>), dim3(cnt, nids), dim3(kBlock), lds, c->stream, D.v, lst, L, X, ids, st_);
+                    if (fwd && push) LAUNCH(kf, (k_fwd<T, true, true>), dim3(cnt, nids), dim3(kBlock), lds, B.stream, D.v, lst, L, X, UV, ids, st_);
+                    else if (fwd) LAUNCH(kf, (k_fwd<T, false, true>), dim3(cnt, nids), dim3(kBlock), lds, B.stream, D.v, lst, L, X, UV, ids, st_);
+                    else LAUNCH(kb, (k_bwd<T, true>), dim3(cnt, nids), dim3(kBlock), lds, B.stream, D.v, lst, L, X, ids, st_);
                 }
             }
         }
@@ -626,10 +648,10 @@ static void launch_tree(hkkt_ctx* c, Batch& B, int l0, int l1, const int* ids, i
     const i32* sg = D.tri_seg_dev.as<i32>();
     const int kind = 12 + 16 * (l0 + 1);
     if (c->opt.deterministic == 0)
-        LAUNCH(kind, (k_tri_tree<T, true, NT>), dim3(nids), dim3(NT), 0, c->stream, D.v, desc, sg, l0, l1, L, Dv, X,
+        LAUNCH(kind, (k_tri_tree<T, true, NT>), dim3(nids), dim3(NT), 0, B.stream, D.v, desc, sg, l0, l1, L, Dv, X,
                B.UV.as<T>(), ids, st_);
     else
-        LAUNCH(kind, (k_tri_tree<T, false, NT>), dim3(nids), dim3(NT), 0, c->stream, D.v, desc, sg, l0, l1, L, Dv,
+        LAUNCH(kind, (k_tri_tree<T, false, NT>), dim3(nids), dim3(NT), 0, B.stream, D.v, desc, sg, l0, l1, L, Dv,
                X, B.UV.as<T>(), ids, st_);
 }
 
@@ -688,7 +710,7 @@ static void alloc_solve(hkkt_ctx* c, Batch& B) {
 static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx, const double* J,
                         const double* delta, const double* gamma, const std::vector<int>* src_idx, bool device_ptrs) {
     const Symbolic& S = c->sym.S;
-    hipStream_t st = c->stream;
+    hipStream_t st = B.stream;
     const hipMemcpyKind kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const int nb = B.nb;
     auto cp = [&](DBuf& dst, const double* src, i64 len) {
@@ -724,7 +746,7 @@ static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx
 // factor all entries of B whose active flag is set; returns per (entry,
 // member) the min failing permuted column (INT_MAX = ok) in B.h_fail
 static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h) {
-    hipStream_t st = c->stream;
+    hipStream_t st = B.stream;
     alloc_factor(c, B);
     HIPCHK(hipMemcpyAsync(B.active.p, active_h.data(), B.nb * 4, hipMemcpyHostToDevice, st));
     if (B.prec == HKKT_MIXED) launch_factor<float>(c, B, B.active.as<int>());
@@ -732,6 +754,48 @@ static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h
     B.h_fail.assign((size_t)B.nb * c->sym.S.G, INT_MAX);
     HIPCHK(hipMemcpyAsync(B.h_fail.data(), B.fail.p, B.h_fail.size() * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// relative residual ||v - H_gamma M^{-1} v|| / ||v|| of B's FP32 factor M per
+// (entry, member), for a fixed probe vector v: above about 1 the FP32 factor
+// cannot drive refinement down (an FP32 pass would stall)
+// ---------------------------------------------------------------------------
+static std::vector<double> fp32_factor_quality(hkkt_ctx* c, Batch& B) {
+    const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
+    hipStream_t st = B.stream;
+    const int nb = B.nb, G = S.G;
+    alloc_solve(c, B);
+    const unsigned gn = grid1(S.n, 4096);
+    LAUNCH(10, k_probe_vec, dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(), (i64)S.n);
+    LAUNCH(10, (k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, (const double*)B.rhat.as<double>(),
+           B.X.as<float>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+    launch_trisolve<float>(c, B, nullptr, nb, nullptr);
+    if (D.v.nbm > 0) {
+        LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.m)), dim3(kBlock), 0, st, B.g2.as<double>(), (i64)nb * S.m,
+               0.0);
+        LAUNCH(10, k_j<float>, dim3(D.v.nbm, nb), dim3(kBlock), 0, st, D.v, B.vals(), (const float*)B.X.as<float>(),
+               (const double*)B.g2.as<double>(), (const double*)nullptr, (const CGState*)nullptr, 0,
+               B.bvec.as<double>(), B.part2.as<double>(), (double*)nullptr, (const int*)nullptr);
+    } else if (S.m > 0) {
+        throw Error(HKKT_ERR_DEVICE, "internal: J rows without reduction blocks");
+    }
+    const unsigned nbr = (unsigned)D.v.nbr;
+    LAUNCH(10, k_hgamma_check<float>, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(),
+           (const double*)B.rhat.as<double>(), (const float*)B.X.as<float>(), (const double*)B.bvec.as<double>(),
+           B.part1.as<double>(), B.pfloor.as<double>());
+    LAUNCH(10, k_reduce_rows, dim3(nb, G), dim3(kBlock), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
+           D.v.rblk_off, B.rsq.as<double>(), (const int*)nullptr);
+    LAUNCH(10, k_reduce_rows, dim3(nb, G), dim3(kBlock), 0, st, (const double*)B.pfloor.as<double>(), (int)nbr,
+           D.v.rblk_off, B.rowred.as<double>(), (const int*)nullptr);
+    std::vector<double> r2((size_t)nb * G), v2((size_t)nb * G);
+    HIPCHK(hipMemcpyAsync(r2.data(), B.rsq.p, r2.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(v2.data(), B.rowred.p, v2.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> rho(r2.size());
+    for (size_t i = 0; i < rho.size(); i++) rho[i] = v2[i] > 0 ? std::sqrt(r2[i] / v2[i]) : 0.0;
+    return rho;
 }
 
 // ---------------------------------------------------------------------------
@@ -743,7 +807,7 @@ template <typename T>
 static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_tol, std::vector<CGState>& hst) {
     const Symbolic& S = c->sym.S;
     const DevSym& D = c->dev;
-    hipStream_t st = c->stream;
+    hipStream_t st = B.stream;
     const int* ids = B.ids_pass.as<int>();
     const int G = S.G;
     const int* cact = G > 1 ? B.cact.as<int>() : nullptr;
@@ -817,7 +881,7 @@ static void update_residual(hkkt_ctx* c, Batch& B, const int* ids, int nids, std
                             double* floor_out) {
     const Symbolic& S = c->sym.S;
     const DevSym& D = c->dev;
-    hipStream_t st = c->stream;
+    hipStream_t st = B.stream;
     const int G = S.G;
     const size_t nc = (size_t)B.nb * G;
     rsq.assign(nc, 0.0);
@@ -853,9 +917,9 @@ static int upload_ids(hkkt_ctx* c, Batch& B, DBuf& dst, const std::vector<int>& 
         if (any) ids.push_back(b);
     }
     if (!ids.empty()) {
-        HIPCHK(hipMemcpyAsync(dst.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, c->stream));
-        if (G > 1) HIPCHK(hipMemcpyAsync(B.cact.p, flags.data(), flags.size() * 4, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpyAsync(dst.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, B.stream));
+        if (G > 1) HIPCHK(hipMemcpyAsync(B.cact.p, flags.data(), flags.size() * 4, hipMemcpyHostToDevice, B.stream));
+        HIPCHK(hipStreamSynchronize(B.stream));
     }
     return (int)ids.size();
 }
@@ -874,10 +938,12 @@ struct InstState {
 // member to the FP64 fallback. FP64: a pass that does not halve RR ends
 // refinement (RR is then at the FP64 evaluation floor) and the status stays
 // NOT_CONVERGED unless RR <= kkt_tol.
+// on_stall (may be empty): called after a pass with the (entry, member)
+// indices that stalled in it (mixed precision), while refinement continues
 static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std::vector<int>& run, bool warm,
-                   bool allow_stall_exit) {
+                   bool allow_stall_exit, const std::function<void(const std::vector<int>&)>& on_stall = {}) {
     const Symbolic& S = c->sym.S;
-    hipStream_t st = c->stream;
+    hipStream_t st = B.stream;
     const int nb = B.nb;
     const int nc = nb * S.G;
     const hkkt_options& o = c->opt;
@@ -907,6 +973,7 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
     const int max_ref = o.max_refine >= 0 ? o.max_refine : 10;
     static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
     std::vector<CGState> hst;
+    std::vector<int> stalled;
     for (int pass = 0; pass <= max_ref; pass++) {
         nids = upload_ids(c, B, B.ids_pass, act);
         if (nids == 0) break;
@@ -934,6 +1001,7 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
                 s.fallback = true;
                 s.status = HKKT_NOT_CONVERGED;
                 act[i] = 0;
+                stalled.push_back(i);
             } else if (!allow_stall_exit && s.passes >= 2 && !(rr < 0.5 * s.rr_prev)) {
                 s.status = HKKT_NOT_CONVERGED;   // stagnated at the evaluation floor
                 act[i] = 0;
@@ -942,6 +1010,8 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
             }
             s.rr_prev = std::min(s.rr_prev, rr);
         }
+        if (on_stall && !stalled.empty()) on_stall(stalled);
+        stalled.clear();
     }
 }
 
@@ -1039,6 +1109,8 @@ void hkkt_default_options(hkkt_options* o) {
     o->ordering = 0;
     o->relax = 1;
     o->deterministic = 0;
+    o->mixed_check = 0;
+    o->mixed_check_tol = 0.5;
 }
 
 int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
@@ -1053,6 +1125,10 @@ int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return HKKT_ERR_DEVICE; }
     c->main.prec = c->opt.precision;
     c->fb.prec = HKKT_FP64;
+    // the fallback stream: default priority, no implicit ordering with the caller's stream
+    if (hipStreamCreateWithFlags(&c->fb_stream, hipStreamNonBlocking) != hipSuccess) { delete c; return HKKT_ERR_DEVICE; }
+    c->main.stream = c->stream;
+    c->fb.stream = c->fb_stream;
     *out = c;
     return HKKT_OK;
 }
@@ -1061,7 +1137,10 @@ void hkkt_destroy(hkkt_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    delete c;
+    hipStream_t fs = c->fb_stream;
+    if (fs) (void)hipStreamSynchronize(fs);
+    delete c;   // frees the device buffers
+    if (fs) (void)hipStreamDestroy(fs);
 }
 
 const char* hkkt_last_error(const hkkt_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -1300,10 +1379,22 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         c->breakdown.assign(nc, 0);
         c->fb_idx.clear();
         std::vector<int> fpos(nc, INT_MAX);
+        // mixed precision: entries whose FP32 factor cannot drive refinement
+        // (probe residual above mixed_check_tol) go to the FP64 refactor now
+        std::vector<double> rho;
+        if (c->opt.precision == HKKT_MIXED && c->opt.mixed_check) rho = fp32_factor_quality(c, c->main);
+        static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
         for (int b = 0; b < nb; b++) {
-            bool any = false;
-            for (int k = 0; k < G; k++) any = any || c->main.h_fail[(size_t)b * G + k] != INT_MAX;
-            if (!any) continue;
+            bool any = false, weak = false;
+            for (int k = 0; k < G; k++) {
+                const size_t i = (size_t)b * G + k;
+                any = any || c->main.h_fail[i] != INT_MAX;
+                if (!rho.empty()) {
+                    weak = weak || !(rho[i] <= c->opt.mixed_check_tol);
+                    if (trace) std::fprintf(stderr, "hkkt: fp32 factor check inst=%zu rho=%.3e\n", i, rho[i]);
+                }
+            }
+            if (!any && !weak) continue;
             if (c->opt.precision == HKKT_MIXED) c->fb_idx.push_back(b);
             else
                 for (int k = 0; k < G; k++) fpos[(size_t)b * G + k] = c->main.h_fail[(size_t)b * G + k];
@@ -1383,90 +1474,198 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
             run[i] = c->fstatus[i] == HKKT_OK && !c->fp64_factored[i];
         }
         const bool mixed = B.prec == HKKT_MIXED;
-        refine(c, B, is, run, false, mixed);
-        // FP64 completion for mixed-precision fallbacks: the batch entries
-        // with a member that needs it form the FP64 sub-batch
-        auto needs_fp64 = [&](int i) { return c->fstatus[i] == HKKT_OK && (c->fp64_factored[i] || is[i].fallback); };
-        std::vector<int> fbl;
-        for (int b = 0; b < nb; b++) {
-            bool any = false;
-            for (int k = 0; k < G; k++) any = any || needs_fp64(b * G + k);
-            if (any) fbl.push_back(b);
-        }
-        if (!fbl.empty()) {
+        // FP64 completion of the mixed-precision fallbacks, concurrent with the
+        // FP32 refinement: each group of (entry, member) pairs handed over
+        // (the factor-time fallbacks first, then every pass's stalls) runs on
+        // the fallback stream in a worker thread, in a batch of its own entries
+        // (FP64 refactor from the caller's values, refinement from the
+        // member's current iterate); results merge per member after the join.
+        struct Group {
+            Batch* F = nullptr;
+            std::vector<int> entries;   // main entry of each F entry
+            std::vector<int> run;       // per (F entry, member): runs in FP64
+            std::vector<InstState> fs;
+            std::vector<int> ffail;     // F's factor status per (F entry, member)
+            bool prefactored = false;   // c->fb, factored at factor time
+            double ms = 0.0;
+        };
+        std::vector<std::unique_ptr<Group>> groups;
+        std::mutex qm;
+        std::condition_variable qcv;
+        std::vector<Group*> queue;
+        bool closed = false;
+        std::exception_ptr werr;
+        std::thread worker;
+        auto run_group = [&](Group& g) {
             const double t1 = now_ms();
-            Batch& F = c->fb;
-            // (re)build the FP64 sub-batch when its membership differs
-            if (fbl != c->fb_idx) {
-                alloc_values(c, F, (int)fbl.size());
-                for (size_t i = 0; i < fbl.size(); i++) {
-                    const int b = fbl[i];
-                    auto cp = [&](DBuf& d, const DBuf& s, i64 len) {
-                        if (len > 0)
-                            HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, s.as<double>() + (i64)b * len,
-                                                  (size_t)len * 8, hipMemcpyDeviceToDevice, st));
-                    };
-                    cp(F.H, B.H, S.nnzH); cp(F.J, B.J, S.nnzJ); cp(F.JT, B.JT, S.nnzJ);
-                    cp(F.HF, B.HF, (i64)S.HF_col.size()); cp(F.Dx, B.Dx, S.n); cp(F.Dxp, B.Dxp, S.n);
-                    cp(F.delta, B.delta, G); cp(F.gamma, B.gamma, G);
+            Batch& F = *g.F;
+            const int ne = (int)g.entries.size();
+            hipStream_t fst = F.stream;
+            auto cp = [&](DBuf& d, const DBuf& src, i64 len, int i, int e) {
+                if (len > 0)
+                    HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, src.as<double>() + (i64)e * len,
+                                          (size_t)len * 8, hipMemcpyDeviceToDevice, fst));
+            };
+            if (!g.prefactored) {
+                alloc_values(c, F, ne);
+                for (int i = 0; i < ne; i++) {
+                    const int e = g.entries[i];
+                    cp(F.H, B.H, S.nnzH, i, e); cp(F.J, B.J, S.nnzJ, i, e); cp(F.JT, B.JT, S.nnzJ, i, e);
+                    cp(F.HF, B.HF, (i64)S.HF_col.size(), i, e); cp(F.Dx, B.Dx, S.n, i, e);
+                    cp(F.Dxp, B.Dxp, S.n, i, e); cp(F.delta, B.delta, G, i, e); cp(F.gamma, B.gamma, G, i, e);
                 }
-                std::vector<int> act(fbl.size(), 1);
+                std::vector<int> act(ne, 1);
                 factor_batch(c, F, act);
-                c->fb_idx = fbl;
-                for (size_t i = 0; i < fbl.size(); i++)
-                    for (int k = 0; k < G; k++) {
-                        const int ci = fbl[i] * G + k;
-                        c->fp64_factored[ci] = 1;
-                        if (needs_fp64(ci) && F.h_fail[i * G + k] != INT_MAX) is[ci].status = HKKT_NOT_SPD;
-                    }
             }
+            g.ffail = F.h_fail;
             alloc_solve(c, F);
-            const int nf = (int)fbl.size();
-            std::vector<InstState> fs((size_t)nf * G);
-            std::vector<int> frun((size_t)nf * G, 0);
-            for (int i = 0; i < nf; i++) {
-                const int b = fbl[i];
-                for (int k = 0; k < G; k++) {
-                    const size_t fi = (size_t)i * G + k, ci = (size_t)b * G + k;
-                    fs[fi].rnorm = is[ci].rnorm;
-                    fs[fi].cg = is[ci].cg;
-                    fs[fi].passes = is[ci].passes;
-                    frun[fi] = needs_fp64((int)ci) && F.h_fail[fi] == INT_MAX;
+            for (int i = 0; i < ne; i++) {
+                const int e = g.entries[i];
+                cp(F.r1p, B.r1p, S.n, i, e);
+                cp(F.r2, B.r2, S.m, i, e);
+                if (!g.prefactored) {   // start from the FP32 iterate (stable: its members no longer run there)
+                    cp(F.xz, B.xz, S.n, i, e);
+                    cp(F.yz, B.yz, S.m, i, e);
                 }
-                auto cp = [&](DBuf& d, const DBuf& s, i64 len) {
-                    if (len > 0)
-                        HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, s.as<double>() + (i64)b * len,
-                                              (size_t)len * 8, hipMemcpyDeviceToDevice, st));
-                };
-                cp(F.r1p, B.r1p, S.n); cp(F.r2, B.r2, S.m); cp(F.xz, B.xz, S.n); cp(F.yz, B.yz, S.m);
             }
-            // start from the mixed-precision iterate when there is one; the
-            // members that do not run keep their iterate unchanged
-            refine(c, F, fs, frun, true, false);
-            for (int i = 0; i < nf; i++) {
-                const int b = fbl[i];
-                auto cpb = [&](DBuf& d, const DBuf& s, i64 len) {
-                    if (len > 0)
-                        HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)b * len, s.as<double>() + (i64)i * len,
-                                              (size_t)len * 8, hipMemcpyDeviceToDevice, st));
-                };
-                cpb(B.xz, F.xz, S.n); cpb(B.yz, F.yz, S.m);
-                for (int k = 0; k < G; k++) {
-                    const size_t fi = (size_t)i * G + k, ci = (size_t)b * G + k;
-                    if (!needs_fp64((int)ci)) continue;
-                    if (frun[fi]) {
-                        is[ci].status = fs[fi].status;
-                        is[ci].rr = fs[fi].rr;
-                        is[ci].brk = fs[fi].brk;
-                        is[ci].cg = fs[fi].cg;
-                        is[ci].passes = fs[fi].passes;
+            std::vector<int> frun(g.run);
+            for (size_t q = 0; q < frun.size(); q++)
+                if (g.ffail[q] != INT_MAX) frun[q] = 0;
+            refine(c, F, g.fs, frun, !g.prefactored, false);
+            HIPCHK(hipStreamSynchronize(fst));
+            g.ms = now_ms() - t1;
+        };
+        auto submit = [&](std::unique_ptr<Group> g) {
+            Group* p = g.get();
+            groups.push_back(std::move(g));
+            {
+                std::lock_guard<std::mutex> lk(qm);
+                queue.push_back(p);
+            }
+            qcv.notify_one();
+            if (!worker.joinable()) {
+                worker = std::thread([&, dev_id = c->device] {
+                    try {
+                        HIPCHK(hipSetDevice(dev_id));
+                        for (;;) {
+                            Group* g;
+                            {
+                                std::unique_lock<std::mutex> lk(qm);
+                                qcv.wait(lk, [&] { return closed || !queue.empty(); });
+                                if (queue.empty()) return;
+                                g = queue.front();
+                                queue.erase(queue.begin());
+                            }
+                            run_group(*g);
+                        }
+                    } catch (...) {
+                        werr = std::current_exception();
                     }
-                    is[ci].fallback = true;
-                }
+                });
             }
-            HIPCHK(hipStreamSynchronize(st));
-            c->ms[3] = now_ms() - t1;
+        };
+        auto close_join = [&] {
+            {
+                std::lock_guard<std::mutex> lk(qm);
+                closed = true;
+            }
+            qcv.notify_all();
+            if (worker.joinable()) worker.join();
+        };
+        struct Joiner {
+            std::function<void()> f;
+            ~Joiner() { f(); }
+        } joiner{close_join};
+        auto make_group = [&](const std::vector<int>& cis, Batch* F, bool prefactored) {
+            auto g = std::make_unique<Group>();
+            g->F = F;
+            g->prefactored = prefactored;
+            for (int ci : cis) {
+                const int e = ci / G;
+                if (g->entries.empty() || g->entries.back() != e) g->entries.push_back(e);
+            }
+            const int ne = (int)g->entries.size();
+            g->run.assign((size_t)ne * G, 0);
+            g->fs.assign((size_t)ne * G, InstState{});
+            for (int i = 0, q = 0; i < ne; i++)
+                for (; q < (int)cis.size() && cis[q] / G == g->entries[i]; q++) {
+                    const int k = cis[q] % G;
+                    g->run[(size_t)i * G + k] = 1;
+                    InstState& f = g->fs[(size_t)i * G + k];
+                    f.rnorm = is[cis[q]].rnorm;
+                    f.cg = is[cis[q]].cg;
+                    f.passes = is[cis[q]].passes;
+                }
+            return g;
+        };
+        // factor-time fallbacks (FP32 factor failed): FP64 factors are in c->fb
+        if (!c->fb_idx.empty()) {
+            std::vector<int> cis;
+            for (int e : c->fb_idx)
+                for (int k = 0; k < G; k++)
+                    if (c->fstatus[(size_t)e * G + k] == HKKT_OK && c->fp64_factored[(size_t)e * G + k])
+                        cis.push_back(e * G + k);
+            if (!cis.empty()) {
+                auto g = make_group(cis, &c->fb, true);
+                // F's entries are c->fb_idx in order: index the run flags by F's own entries
+                g->entries = c->fb_idx;
+                g->run.assign(c->fb_idx.size() * G, 0);
+                g->fs.assign(c->fb_idx.size() * G, InstState{});
+                for (size_t i = 0; i < c->fb_idx.size(); i++)
+                    for (int k = 0; k < G; k++) {
+                        const size_t ci = (size_t)c->fb_idx[i] * G + k;
+                        if (c->fstatus[ci] != HKKT_OK || !c->fp64_factored[ci]) continue;
+                        g->run[i * G + k] = 1;
+                        g->fs[i * G + k].rnorm = is[ci].rnorm;
+                    }
+                submit(std::move(g));
+            }
         }
+        int npool = 0;
+        auto on_stall = [&](const std::vector<int>& cis) {
+            if ((int)c->fbx.size() <= npool) {
+                c->fbx.emplace_back(new Batch());
+                c->fbx.back()->prec = HKKT_FP64;
+                c->fbx.back()->stream = c->fb_stream;
+            }
+            submit(make_group(cis, c->fbx[npool++].get(), false));
+        };
+        refine(c, B, is, run, false, mixed, mixed ? std::function<void(const std::vector<int>&)>(on_stall)
+                                                   : std::function<void(const std::vector<int>&)>());
+        close_join();
+        if (werr) std::rethrow_exception(werr);
+        double fb_ms = 0.0;
+        for (auto& gp : groups) {
+            Group& g = *gp;
+            fb_ms += g.ms;
+            for (size_t i = 0; i < g.entries.size(); i++)
+                for (int k = 0; k < G; k++) {
+                    const size_t fi = i * G + k, ci = (size_t)g.entries[i] * G + k;
+                    if (!g.run[fi]) continue;
+                    is[ci].fallback = true;
+                    if (g.ffail[fi] != INT_MAX) {
+                        is[ci].status = HKKT_NOT_SPD;
+                        continue;
+                    }
+                    // the member's slices of the iterate back into the main batch
+                    const i64 x0 = S.x_off[k], nx = S.x_off[k + 1] - S.x_off[k];
+                    const i64 y0 = S.y_off[k], ny = S.y_off[k + 1] - S.y_off[k];
+                    HIPCHK(hipMemcpyAsync(B.xz.as<double>() + (i64)g.entries[i] * S.n + x0,
+                                          g.F->xz.as<double>() + (i64)i * S.n + x0, (size_t)nx * 8,
+                                          hipMemcpyDeviceToDevice, st));
+                    if (ny > 0)
+                        HIPCHK(hipMemcpyAsync(B.yz.as<double>() + (i64)g.entries[i] * S.m + y0,
+                                              g.F->yz.as<double>() + (i64)i * S.m + y0, (size_t)ny * 8,
+                                              hipMemcpyDeviceToDevice, st));
+                    const InstState& f = g.fs[fi];
+                    is[ci].status = f.status;
+                    is[ci].rr = f.rr;
+                    is[ci].brk = f.brk;
+                    is[ci].cg = f.cg;
+                    is[ci].passes = f.passes;
+                }
+        }
+        c->ms[3] = fb_ms;
         // final metrics: RR, BE, floor on the full KKT residual, per member
         std::vector<int> allact(nc);
         for (int i = 0; i < nc; i++) allact[i] = c->fstatus[i] == HKKT_OK;
@@ -1626,6 +1825,7 @@ int hkkt_profile_end(hkkt_ctx* c, double* ms, int64_t* launches) {
     if (!c) return HKKT_ERR_ARG;
     ABI_GUARD(c, {
         HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipStreamSynchronize(c->fb_stream));
         double t[kNProf] = {0};
         int64_t k[kNProf] = {0};
         std::vector<double> dt(64 * 16, 0.0);

@@ -1333,6 +1333,51 @@ __global__ __launch_bounds__(kBlock) void k_knorm_rows(SymView S, ValView V, dou
     }
 }
 
+// ---------------------------------------------------------------------------
+// quality check of a low-precision factor M: v is a fixed probe vector, w =
+// M^{-1} v (the factor's own solve), t = J w; partial sums of
+// (v - H_gamma w)^2 and v^2 over the x rows of the member-aligned blocks
+// (H_gamma w = H w + (D_x + delta) w + gamma J^T (J w)).
+// ---------------------------------------------------------------------------
+__global__ void k_probe_vec(double* __restrict__ v, i64 n) {
+    const int b = blockIdx.y;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const unsigned h = (unsigned)(i * 2654435761ull) ^ (unsigned)(b * 40503u);
+        v[(i64)b * n + i] = 0.5 + (double)(h >> 8) * (1.0 / 16777216.0);   // in [0.5, 1.5)
+    }
+}
+
+template <typename TW>
+__global__ __launch_bounds__(kBlock) void k_hgamma_check(SymView S, ValView V, const double* __restrict__ v,
+                                                         const TW* __restrict__ w, const double* __restrict__ t,
+                                                         double* __restrict__ part_r, double* __restrict__ part_v) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    const i64 i = bk.lo + threadIdx.x;
+    double a = 0.0, c = 0.0;
+    if (i < bk.hi && i < S.n) {
+        const double* HF = V.HF + (i64)b * S.nnzHF;
+        const double* JT = V.JT + (i64)b * S.nnzJ;
+        const TW* wb = w + (i64)b * S.n;
+        const double* tb = t + (i64)b * S.m;
+        double acc = 0.0, jt = 0.0;
+        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) acc += HF[k] * (double)wb[S.HF_col[k]];
+        acc += (V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + bk.k]) * (double)wb[i];
+        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) jt += JT[k] * tb[S.JT_col[k]];
+        acc += V.gamma[(i64)b * S.G + bk.k] * jt;
+        const double vi = v[(i64)b * S.n + i];
+        a = (vi - acc) * (vi - acc);
+        c = vi * vi;
+    }
+    a = block_sum(a, sh);
+    c = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        part_r[(i64)b * gridDim.x + blockIdx.x] = a;
+        part_v[(i64)b * gridDim.x + blockIdx.x] = c;
+    }
+}
+
 // out[b * G + k] = max of the partials of member k (grid (nb, G))
 __global__ void k_reduce_max(const double* part, int nblk, const i32* off, double* out) {
     const int b = blockIdx.x, k = blockIdx.y;

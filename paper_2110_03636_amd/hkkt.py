@@ -39,7 +39,7 @@ class Options(C.Structure):
                 ("cg_tol_mixed", C.c_double), ("kkt_tol", C.c_double), ("quad_form_eps", C.c_double),
                 ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
                 ("ordering", C.c_int), ("relax", C.c_int), ("deterministic", C.c_int),
-                ("reserved", C.c_int * 5)]
+                ("mixed_check", C.c_int), ("mixed_check_tol", C.c_double), ("reserved", C.c_int * 2)]
 
 
 class Info(C.Structure):

@@ -340,3 +340,14 @@ def test_wide_supernodes_beyond_lds():
     assert s2.factor_batch(b)[0] == 0
     rc, x2, y2, infos2 = s2.solve(b.r1, b.r2)
     _check_solution(b, x2, y2, infos2)
+
+
+def test_mixed_factor_check_routes_to_fp64():
+    """With a zero tolerance the FP32 factor check sends every instance to
+    the FP64 refactor at factor time; the solutions still meet the bar."""
+    b = synth.grid_like(2500, nb=3, seed=40, gammas=(1e4, 1e6), dx_exp=8.0)
+    s = _solver(b, precision="mixed", mixed_check=1, mixed_check_tol=0.0)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    assert all(i["fp64_fallback"] == 1 for i in infos)
+    _check_solution(b, x, y, infos)
