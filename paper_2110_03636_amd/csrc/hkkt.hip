@@ -193,6 +193,7 @@ struct DevSym {
 };
 
 constexpr size_t kMaxLds = 65536;
+constexpr int kUpdBlock = 128;   // columns per trailing update of a large front
 constexpr int kTriWG = 7;
 
 // size class of a supernode for the triangular solves: rows decide the
@@ -530,20 +531,45 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                 LAUNCH(2, k_big_extend<T>, dim3((ncc + kExtCols - 1) / kExtCols, seg.second, nb), dim3(kBlock), 0, st,
                        D.v, D.big_pairs.as<i32>() + 2 * seg.first, L, CB, active);
             }
-            for (int kb = 0; kb < maxw; kb += kNB) {
-                int cnt = 0, maxrows = 0;
-                for (int q = 0; q < ns_big && nrw[q].second > kb; q++) {
-                    cnt++;
-                    maxrows = std::max(maxrows, nrw[q].first - kb - std::min(kNB, nrw[q].second - kb));
+            // 128-column blocks: per 32-column panel a left-looking strip
+            // update from the block's earlier panels, POTRF, TRSM; then one
+            // rank-128 update of everything right of the block. Fronts are
+            // sorted by width, so the fronts still active at column kb are a
+            // prefix of the level's list.
+            auto active_prefix = [&](int col) {
+                int cnt = 0;
+                while (cnt < ns_big && nrw[cnt].second > col) cnt++;
+                return cnt;
+            };
+            auto update = [&](int ka, int R, int strip) {
+                const int cnt = active_prefix(ka);
+                if (cnt == 0) return;
+                int rows = 0, cols = 0;
+                for (int q = 0; q < cnt; q++) {
+                    const int rf = std::min(R, nrw[q].second - ka), c0 = ka + rf;
+                    const int c1 = strip ? std::min(c0 + kNB, nrw[q].second) : nrw[q].first;
+                    rows = std::max(rows, nrw[q].first - c0);
+                    cols = std::max(cols, c1 - c0);
                 }
-                LAUNCH(2, k_big_potrf<T>, dim3(1, cnt, nb), dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(),
-                       active);
-                if (maxrows <= 0) continue;
-                LAUNCH(2, k_big_trsm<T>, dim3((maxrows + kBlock - 1) / kBlock, cnt, nb), dim3(kBlock), 0, st, D.v, fr,
-                       kb, L, CB, active);
-                const int nt = (maxrows + kTile - 1) / kTile;
-                LAUNCH(2, k_big_update<T>, dim3(nt * (nt + 1) / 2, cnt, nb), dim3(kBlock), 0, st, D.v, fr, kb, L, CB,
-                       active);
+                if (rows <= 0 || cols <= 0) return;
+                const int nti = (rows + kTile - 1) / kTile, ntj = (cols + kTile - 1) / kTile;
+                LAUNCH(2, k_big_update<T>, dim3(nti * ntj, cnt, nb), dim3(kBlock), 0, st, D.v, fr, ka, R, strip, nti,
+                       L, CB, active);
+            };
+            for (int K = 0; K < maxw; K += kUpdBlock) {
+                for (int kb = K; kb < std::min(K + kUpdBlock, maxw); kb += kNB) {
+                    if (kb > K) update(K, kb - K, 1);
+                    const int cnt = active_prefix(kb);
+                    int maxrows = 0;
+                    for (int q = 0; q < cnt; q++)
+                        maxrows = std::max(maxrows, nrw[q].first - kb - std::min(kNB, nrw[q].second - kb));
+                    LAUNCH(2, k_big_potrf<T>, dim3(1, cnt, nb), dim3(kWave), 0, st, D.v, fr, kb, L, CB,
+                           B.fail.as<int>(), active);
+                    if (maxrows <= 0) continue;
+                    LAUNCH(2, k_big_trsm<T>, dim3((maxrows + kBlock - 1) / kBlock, cnt, nb), dim3(kBlock), 0, st, D.v,
+                           fr, kb, L, CB, active);
+                }
+                update(K, kUpdBlock, 0);
             }
         }
     }

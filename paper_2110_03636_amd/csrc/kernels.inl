@@ -26,6 +26,18 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Value of lane jl (the same in all active lanes) in every lane (v_readlane).
+__device__ __forceinline__ float lane_read(float v, int jl) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), __builtin_amdgcn_readfirstlane(jl)));
+}
+__device__ __forceinline__ double lane_read(double v, int jl) {
+    const long long u = __double_as_longlong(v);
+    const int l = __builtin_amdgcn_readfirstlane(jl);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Block sum; the result is valid in thread 0. `sh` holds kBlock/kWave doubles.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     v = wave_sum(v);
@@ -209,9 +221,12 @@ struct FrontRef {
 //   k_big_zero    clear the fronts' contribution blocks
 //   k_big_extend  add the children's contribution blocks (one child rank per
 //                 launch, so two children never write one front at once)
-//   k_big_potrf   Cholesky of the NB x NB diagonal block in LDS
+//   k_big_potrf   Cholesky of the NB x NB diagonal block (one wavefront)
 //   k_big_trsm    L21 = A21 L11^{-T}, one thread per row
-//   k_big_update  trailing SYRK/GEMM C -= L21 L21^T on 64 x 64 lower tiles
+//   k_big_update  SYRK/GEMM C -= L21 L21^T on 64 x 64 lower tiles, rank up to
+//                 128: inside a 128-column block each panel first takes the
+//                 block's earlier panels (left-looking strip), then one
+//                 trailing update per block (right-looking)
 //                 with MFMA (v_mfma_*_16x16x4: A[i][k] in lane i+16k,
 //                 B[k][j] in lane j+16k; D[i][j] in lane j+16q, register r
 //                 with i = 4q+r for f32 and i = q+4r for f64, as measured)
@@ -268,47 +283,42 @@ __global__ __launch_bounds__(kBlock) void k_big_extend(SymView S, const i32* __r
     }
 }
 
+// Cholesky of the NB x NB diagonal block by one wavefront: lane i holds row
+// i in registers; column k is scaled and its values broadcast with
+// v_readlane (uniform lane index), no LDS and no barriers.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_big_potrf(SymView S, const i32* __restrict__ fronts, int kb,
-                                                      T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
-                                                      const int* active) {
-    __shared__ T D[kNB][kNB + 1];
+__global__ __launch_bounds__(kWave) void k_big_potrf(SymView S, const i32* __restrict__ fronts, int kb,
+                                                     T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
+                                                     const int* active) {
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     const i32 s = fronts[blockIdx.y];
     const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
     const int bw = min(kNB, F.w - kb);
-    for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
-        const int j = idx / bw, i = idx - j * bw;
-        D[j][i] = i >= j ? F.P[(i64)(kb + j) * F.nr + kb + i] : T(0);
-    }
-    __syncthreads();
+    const int i = threadIdx.x;
+    T r[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; j++) r[j] = (i < bw && j <= i) ? F.P[(i64)(kb + j) * F.nr + kb + i] : T(0);
     const i32 f = S.sn_first[s];
-    T dprev = T(1);
-    for (int k = 0; k <= bw; k++) {
-        const T dk = k < bw ? D[k][k] : T(1);
-        if (k > 0) {
-            const int kk = k - 1;
-            const T sq = sqrt(dprev), inv = T(1) / sq;
-            for (int i = kk + threadIdx.x; i < bw; i += blockDim.x) D[kk][i] = i == kk ? sq : D[kk][i] * inv;
-        }
+#pragma unroll
+    for (int k = 0; k < kNB; k++) {
         if (k < bw) {
-            if (threadIdx.x == 0 && !pivot_ok(dk))
-                atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + kb + k);
-            const T invd = T(1) / dk;
-            const int len = bw - k - 1;
-            for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
-                const int jj = idx / len, ii = idx - jj * len;
-                if (ii >= jj) D[k + 1 + jj][k + 1 + ii] -= D[k][k + 1 + ii] * D[k][k + 1 + jj] * invd;
+            const T d = lane_read(r[k], k);
+            if (i == 0 && !pivot_ok(d)) atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + kb + k);
+            const T sq = sqrt(d), inv = T(1) / sq;
+            r[k] = i == k ? sq : (i > k ? r[k] * inv : r[k]);
+#pragma unroll
+            for (int j = k + 1; j < kNB; j++) {
+                if (j < bw) {
+                    const T ljk = lane_read(r[k], j);
+                    if (i >= j) r[j] -= r[k] * ljk;
+                }
             }
         }
-        dprev = dk;
-        __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
-        const int j = idx / bw, i = idx - j * bw;
-        if (i >= j) F.P[(i64)(kb + j) * F.nr + kb + i] = D[j][i];
-    }
+#pragma unroll
+    for (int j = 0; j < kNB; j++)
+        if (i < bw && j <= i) F.P[(i64)(kb + j) * F.nr + kb + i] = r[j];
 }
 
 // rows below the diagonal block: x L11^T = a  (one thread per row)
@@ -366,34 +376,33 @@ struct MfmaT<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// trailing update of the rows/columns >= kb + NB: tile (ti, tj), ti >= tj,
-// of 64 x 64; four wavefronts, each a 32 x 32 quarter as 2 x 2 MFMA blocks
+// Update of a large front with its factored columns [ka, ka + R) (R <= 128,
+// clipped to the front's width): C -= L21 L21^T over the target columns
+// [c0, c1) (rows c0..nr-1, lower part), with c0 = ka + R. strip = 1: c1 =
+// min(c0 + NB, w), the next panel only (left-looking inside a 128-column
+// block); strip = 0: c1 = nr, the whole trailing matrix (once per block).
+// Tile (ti, tj) of 64 x 64 from blockIdx.x = tj * nti + ti, ti >= tj; four
+// wavefronts, each a 32 x 32 quarter as 2 x 2 MFMA blocks; the R columns are
+// staged through LDS 32 at a time and accumulate in the MFMA registers.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __restrict__ fronts, int kb,
-                                                       T* __restrict__ L, T* __restrict__ CB, const int* active) {
+__global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __restrict__ fronts, int ka, int R,
+                                                       int strip, int nti, T* __restrict__ L, T* __restrict__ CB,
+                                                       const int* active) {
     __shared__ T Ai[kTile][kNB + 1];
     __shared__ T Aj[kTile][kNB + 1];
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     const i32 s = fronts[blockIdx.y];
     const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
-    const int bw = min(kNB, F.w - kb);
-    const int r0 = kb + bw;
-    const int nt = (F.nr - r0 + kTile - 1) / kTile;
-    const int lin = blockIdx.x;
-    if (lin >= nt * (nt + 1) / 2) return;
-    int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= lin) ti++;
-    while (ti * (ti + 1) / 2 > lin) ti--;
-    const int tj = lin - ti * (ti + 1) / 2;
-    const int i0 = r0 + ti * kTile, j0 = r0 + tj * kTile;
-    for (int idx = threadIdx.x; idx < kTile * kNB; idx += blockDim.x) {
-        const int k = idx / kTile, r = idx - k * kTile;
-        const bool ok = k < bw;
-        Ai[r][k] = (ok && i0 + r < F.nr) ? F.P[(i64)(kb + k) * F.nr + i0 + r] : T(0);
-        Aj[r][k] = (ok && j0 + r < F.nr) ? F.P[(i64)(kb + k) * F.nr + j0 + r] : T(0);
-    }
-    __syncthreads();
+    const int rf = min(R, F.w - ka);
+    if (rf <= 0) return;
+    const int c0 = ka + rf;
+    const int c1 = strip ? min(c0 + kNB, F.w) : F.nr;
+    if (c1 <= c0) return;
+    const int tj = blockIdx.x / nti, ti = blockIdx.x - tj * nti;
+    if (ti < tj) return;
+    const int i0 = c0 + ti * kTile, j0 = c0 + tj * kTile;
+    if (i0 >= F.nr || j0 >= c1) return;
     typedef typename MfmaT<T>::v4 v4;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int qi = (wv >> 1) * 32, qj = (wv & 1) * 32;
@@ -403,17 +412,29 @@ __global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __r
 #pragma unroll
         for (int c = 0; c < 2; c++) acc[a][c] = v4{T(0), T(0), T(0), T(0)};
     const int li = lane & 15, lk = lane >> 4;
+    for (int kc = 0; kc < rf; kc += kNB) {
+        const int bw = min(kNB, rf - kc);
+        __syncthreads();   // previous chunk consumed
+        for (int idx = threadIdx.x; idx < kTile * kNB; idx += blockDim.x) {
+            const int k = idx / kTile, r = idx - k * kTile;
+            const bool ok = k < bw;
+            const i64 col = (i64)(ka + kc + k) * F.nr;
+            Ai[r][k] = (ok && i0 + r < F.nr) ? F.P[col + i0 + r] : T(0);
+            Aj[r][k] = (ok && j0 + r < F.nr) ? F.P[col + j0 + r] : T(0);
+        }
+        __syncthreads();
 #pragma unroll
-    for (int k4 = 0; k4 < kNB; k4 += 4) {
-        T av[2], bv[2];
+        for (int k4 = 0; k4 < kNB; k4 += 4) {
+            T av[2], bv[2];
 #pragma unroll
-        for (int a = 0; a < 2; a++) av[a] = Ai[qi + 16 * a + li][k4 + lk];
+            for (int a = 0; a < 2; a++) av[a] = Ai[qi + 16 * a + li][k4 + lk];
 #pragma unroll
-        for (int c = 0; c < 2; c++) bv[c] = Aj[qj + 16 * c + li][k4 + lk];
+            for (int c = 0; c < 2; c++) bv[c] = Aj[qj + 16 * c + li][k4 + lk];
 #pragma unroll
-        for (int a = 0; a < 2; a++)
+            for (int a = 0; a < 2; a++)
 #pragma unroll
-            for (int c = 0; c < 2; c++) acc[a][c] = MfmaT<T>::mma(av[a], bv[c], acc[a][c]);
+                for (int c = 0; c < 2; c++) acc[a][c] = MfmaT<T>::mma(av[a], bv[c], acc[a][c]);
+        }
     }
 #pragma unroll
     for (int a = 0; a < 2; a++)
@@ -423,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __r
             for (int r = 0; r < 4; r++) {
                 const int i = i0 + qi + 16 * a + MfmaT<T>::row(lane, r);
                 const int j = j0 + qj + 16 * c + (lane & 15);
-                if (i < F.nr && j < F.nr && i >= j) F.at(i, j) -= acc[a][c][r];
+                if (i < F.nr && j < c1 && i >= j) F.at(i, j) -= acc[a][c][r];
             }
 }
 
@@ -617,16 +638,6 @@ __device__ __forceinline__ T seg_allsum(T v) {
 // the whole wavefront, whose column loop runs in lockstep, so jl is uniform
 // and v_readlane serves; narrower segments use a lane permute (segments of a
 // tree-kernel wavefront may sit at different columns).
-__device__ __forceinline__ float lane_read(float v, int jl) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), __builtin_amdgcn_readfirstlane(jl)));
-}
-__device__ __forceinline__ double lane_read(double v, int jl) {
-    const long long u = __double_as_longlong(v);
-    const int l = __builtin_amdgcn_readfirstlane(jl);
-    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
-    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 template <typename T, int SEG>
 __device__ __forceinline__ T seg_bcast(T v, int jl) {
     if (SEG == kWave) return lane_read(v, jl);
