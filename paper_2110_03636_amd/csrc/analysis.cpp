@@ -595,6 +595,16 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
         S.level_sn.resize(ns);
         std::vector<i32> pos(S.level_ptr.begin(), S.level_ptr.end() - 1);
         for (i32 s = 0; s < ns; s++) S.level_sn[pos[lev[s]]++] = s;
+        // panels stored level by level (the supernodes of a level in one
+        // contiguous range, in level_sn order): a level's solve or factor
+        // reads one range, and the top levels' panels can be staged as a block
+        i64 off = 0;
+        for (i32 q = 0; q < ns; q++) {
+            const i32 s = S.level_sn[q];
+            S.sn_lptr[s] = off;
+            off += (i64)(S.sn_first[s + 1] - S.sn_first[s]) * (S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+        }
+        S.sn_lptr[ns] = off;
 
         // ---- contribution blocks by lifetime: the block of supernode s is
         // written while its level is factored and read while its parent's
@@ -748,11 +758,16 @@ std::string analyze(Symbolic& S, i64 n, i64 m, const i64* Hp, const i32* Hi, con
     S.a_mem.resize(S.nnzA);
     S.sn_mem.resize(ns);
     for (i32 s2 = 0; s2 < ns; s2++) S.sn_mem[s2] = S.xp_mem[S.sn_first[s2]];
-    for (i64 e = 0; e < S.nnzA; e++) {
-        // supernode whose panel holds the entry
-        const i32 s2 = (i32)(std::upper_bound(S.sn_lptr.begin(), S.sn_lptr.begin() + ns + 1, S.a_dst[e]) -
-                             S.sn_lptr.begin()) - 1;
-        S.a_mem[e] = S.sn_mem[s2];
+    {
+        // supernode whose panel holds the entry (panels ordered by offset)
+        std::vector<std::pair<i64, i32>> po(ns);
+        for (i32 s2 = 0; s2 < ns; s2++) po[s2] = {S.sn_lptr[s2], s2};
+        std::sort(po.begin(), po.end());
+        for (i64 e = 0; e < S.nnzA; e++) {
+            const size_t k = (size_t)(std::upper_bound(po.begin(), po.end(), std::make_pair(S.a_dst[e], INT32_MAX)) -
+                                      po.begin()) - 1;
+            S.a_mem[e] = S.sn_mem[po[k].second];
+        }
     }
     S.mblk.clear();
     S.mblk_off.assign(G + 1, 0);

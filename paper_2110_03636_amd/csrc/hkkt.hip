@@ -189,6 +189,14 @@ struct DevSym {
     std::vector<int> lev_count;                 // supernodes per level
     std::vector<char> tree_fits;                // level fits the tree-traversal classes
     int tree_width = 32;                        // widest level run by the tree kernels
+    // tree solve with x in LDS: columns ordered by level from the root down,
+    // so that the columns of levels [l, nlevels) are the first tree_nt[l]
+    // slots for every l; per supernode (parallel to tri_desc) its slots
+    DBuf tree_desc, tree_cols, tree_rs;
+    std::vector<int> tree_nt;                   // [nlevels + 1]
+    std::vector<int> lev_desc0, lev_rs0;        // [nlevels + 1] first descriptor / row slot of a level
+    std::vector<i64> lev_lptr;                  // [nlevels + 1] L storage range of a level's panels
+    DBuf lev_desc0_dev, lev_lptr_dev;
     SymView v{};
 };
 
@@ -367,6 +375,62 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
         }
         upload(D.tri_desc, td, st);
         upload(D.tri_list, tl, st);
+        {
+            std::vector<i32> slot(S.n, -1), tcols;
+            tcols.reserve(S.n);
+            D.tree_nt.assign(S.nlevels + 1, 0);
+            for (i32 l = S.nlevels - 1; l >= 0; l--) {
+                for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
+                    const i32 sn = S.level_sn[q];
+                    for (i32 j = S.sn_first[sn]; j < S.sn_first[sn + 1]; j++) {
+                        slot[j] = (i32)tcols.size();
+                        tcols.push_back(j);
+                    }
+                }
+                D.tree_nt[l] = (int)tcols.size();
+            }
+            std::vector<TreeDesc> trd(td.size());
+            std::vector<i32> trs;
+            for (size_t q = 0; q < td.size(); q++) {
+                const TriDesc& a = td[q];
+                TreeDesc& e = trd[q];
+                e.lptr = a.lptr;
+                e.f = a.f;
+                e.w = a.w;
+                e.nr = a.nr;
+                e.mem = a.mem;
+                e.slot = slot[a.f];
+                e.rs = (i32)trs.size();
+                for (i32 r = a.w; r < a.nr; r++) {
+                    const i32 sr = slot[S.sn_rows[a.rp + r]];
+                    // rows below a supernode are columns of its ancestors,
+                    // which sit at higher levels: earlier slots
+                    if (sr < 0 || sr >= e.slot) throw std::runtime_error("tree slots: row outside the ancestors");
+                    trs.push_back(sr);
+                }
+            }
+            D.lev_desc0.assign(S.nlevels + 1, (int)td.size());
+            D.lev_rs0.assign(S.nlevels + 1, (int)trs.size());
+            for (i32 l = 0; l < S.nlevels; l++) {
+                const int q = D.tri_seg[(size_t)l * kTriClasses].first;
+                D.lev_desc0[l] = q;
+                D.lev_rs0[l] = q < (int)trd.size() ? trd[q].rs : (int)trs.size();
+            }
+            D.lev_lptr.assign(S.nlevels + 1, S.Lsize);
+            for (i32 l = 0; l < S.nlevels; l++) {
+                D.lev_lptr[l] = S.sn_lptr[S.level_sn[S.level_ptr[l]]];
+                for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {   // panels stored level by level
+                    const i32 sn = S.level_sn[q];
+                    if (S.sn_lptr[sn] < D.lev_lptr[l]) throw std::runtime_error("panels not stored by level");
+                }
+            }
+            upload(D.tree_desc, trd, st);
+            upload(D.tree_cols, tcols, st);
+            upload(D.tree_rs, trs, st);
+            upload(D.lev_desc0_dev, D.lev_desc0, st);
+            upload(D.lev_lptr_dev, D.lev_lptr, st);
+            HIPCHK(hipStreamSynchronize(st));
+        }
         std::vector<i32> sg(2 * D.tri_seg.size());
         for (size_t q = 0; q < D.tri_seg.size(); q++) {
             sg[2 * q] = D.tri_seg[q].first;
@@ -467,6 +531,7 @@ struct hkkt_ctx {
     Batch main, fb;               // fb: FP64 fallback sub-batch
     DBuf cbws;                    // contribution-block workspace, shared: the batches factor one after the other
     hipStream_t fb_stream = nullptr;  // FP64 fallback work, concurrent with the FP32 refinement
+    i64 lds_max = 65536;          // dynamic LDS per work-group the device allows
     std::vector<std::unique_ptr<Batch>> fbx;   // fallback batches of a solve's stall groups
     std::vector<int> fb_idx;      // main index of each fallback instance
     int nb = 0;
@@ -681,11 +746,69 @@ static void launch_tree(hkkt_ctx* c, Batch& B, int l0, int l1, const int* ids, i
                X, B.UV.as<T>(), ids, st_);
 }
 
+// Staged tree kernel: the lowest level l >= lo such that every level of
+// [l, nlevels) has at most NT * PR panel entries and the LDS layout of the
+// range fits the device's limit (nlevels if none); *pmax = the range's
+// largest level. HKKT_TREE_STAGE=0 turns the staged kernel off.
+constexpr int kTreeNT = 512;
+
+template <typename T>
+static int tree2_lo(const hkkt_ctx* c, int lo, int* pmax_out) {
+    static const bool off = std::getenv("HKKT_TREE_STAGE") && std::atoi(std::getenv("HKKT_TREE_STAGE")) == 0;
+    const DevSym& D = c->dev;
+    const Symbolic& S = c->sym.S;
+    *pmax_out = 0;
+    if (off || c->opt.deterministic != 0) return S.nlevels;
+    const i64 cap = (i64)kTreeNT * tree2_pr<T>();
+    int best = S.nlevels;
+    i64 pmax = 0;
+    for (int l = S.nlevels - 1; l >= lo; l--) {
+        const i64 ps = D.lev_lptr[l + 1] - D.lev_lptr[l];
+        if (ps > cap) break;
+        pmax = std::max(pmax, ps);
+        const int nd = D.lev_desc0[S.nlevels] - D.lev_desc0[l];
+        const int nrs = D.lev_rs0[S.nlevels] - D.lev_rs0[l];
+        const i64 lds = tree2_layout(D.tree_nt[l], (int)sizeof(T), nd, nrs, S.nlevels - l, S.G, (int)pmax).total;
+        if (lds > c->lds_max) break;
+        best = l;
+        *pmax_out = (int)pmax;
+    }
+    return best;
+}
+
+template <typename T>
+static void launch_tree2(hkkt_ctx* c, Batch& B, int l0, int pmax, const int* ids, int nids, const CGState* st_) {
+    const DevSym& D = c->dev;
+    const Symbolic& S = c->sym.S;
+    constexpr int PR = tree2_pr<T>();
+    const int l1 = S.nlevels;
+    const int nd = D.lev_desc0[l1] - D.lev_desc0[l0];
+    const int rs0 = D.lev_rs0[l0], nrs = D.lev_rs0[l1] - rs0;
+    const size_t lds = tree2_layout(D.tree_nt[l0], (int)sizeof(T), nd, nrs, l1 - l0, S.G, pmax).total;
+    static std::once_flag attr;   // allow dynamic LDS up to the device's limit, once per instantiation
+    std::call_once(attr, [&] {
+        HIPCHK(hipFuncSetAttribute((const void*)k_tri_tree2<T, kTreeNT, PR>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_max));
+    });
+    LAUNCH(12 + 16 * (l0 + 1), (k_tri_tree2<T, kTreeNT, PR>), dim3(nids), dim3(kTreeNT), lds, B.stream, D.v,
+           D.tree_desc.as<TreeDesc>(), D.lev_desc0_dev.as<i32>(), D.lev_lptr_dev.as<i64>(), l0, l1,
+           D.tree_cols.as<i32>(), D.tree_nt[l0], D.tree_rs.as<i32>(), rs0, nrs, pmax, B.L.as<T>(), B.Dinv.as<T>(),
+           B.X.as<T>(), ids, st_);
+}
+
 template <typename T>
 static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* ids, int nids, const CGState* st_) {
     const Symbolic& S = c->sym.S;
     if (nids <= 0) return;
     const int lo = tree_lo(c->dev, S.nlevels);
+    int pmax = 0;
+    const int lo2 = lo < S.nlevels ? tree2_lo<T>(c, lo, &pmax) : S.nlevels;
+    if (lo2 < S.nlevels) {
+        for (i32 l = 0; l < lo2; l++) launch_tri_level<T>(c, B, l, true, ids, nids, st_);
+        launch_tree2<T>(c, B, lo2, pmax, ids, nids, st_);
+        for (i32 l = lo2 - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, ids, nids, st_);
+        return;
+    }
     for (i32 l = 0; l < lo; l++) launch_tri_level<T>(c, B, l, true, ids, nids, st_);
     if (lo < S.nlevels) launch_tree<T>(c, B, lo, S.nlevels, ids, nids, st_);
     for (i32 l = lo - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, ids, nids, st_);
@@ -1149,6 +1272,11 @@ int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
     if (c->opt.precision != HKKT_FP64 && c->opt.precision != HKKT_MIXED) { delete c; return HKKT_ERR_ARG; }
     c->stream = (hipStream_t)stream;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return HKKT_ERR_DEVICE; }
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && v > 0)
+            c->lds_max = v;
+    }
     c->main.prec = c->opt.precision;
     c->fb.prec = HKKT_FP64;
     // the fallback stream: default priority, no implicit ordering with the caller's stream

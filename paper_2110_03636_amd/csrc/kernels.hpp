@@ -85,6 +85,19 @@ struct TriDesc {
     i32 pad;
 };
 
+// Supernode of the tree-traversal solve with the right-hand side of the
+// tree's columns held in LDS: slot = LDS index of the first column, rs =
+// offset of its below-diagonal rows' LDS indices in the row-slot table.
+struct TreeDesc {
+    i64 lptr;    // panel offset in L storage
+    i32 f;       // first column (for the reciprocal diagonal)
+    i32 w;       // width
+    i32 nr;      // rows
+    i32 mem;     // group member
+    i32 slot;    // LDS index of column f
+    i32 rs;      // row-slot table offset of row w
+};
+
 // Per-batch numeric values (device, FP64 copies owned by the library).
 struct ValView {
     int nb;

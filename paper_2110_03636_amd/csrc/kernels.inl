@@ -649,17 +649,21 @@ __device__ __forceinline__ T seg_bcast(T v, int jl) {
 // straight into the ancestors' right-hand-side entries with FP atomics
 // (right-looking; order of the additions not fixed).
 // Load panel columns [j0, j0 + CH) of the rows this lane holds (strictly
-// below the diagonal, zero elsewhere).
-template <typename T, int SEG, int R, int CH>
-__device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ Lb, const TriDesc& d, int j0,
-                                          int sl) {
+// below the diagonal, zero elsewhere). Every lane loads from an address
+// clamped into the panel and selects afterwards: no branch per element.
+template <typename T, int SEG, int R, int CH, typename DT>
+__device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ Lb, const DT& d, int j0, int sl) {
 #pragma unroll
-    for (int jj = 0; jj < CH; jj++)
+    for (int jj = 0; jj < CH; jj++) {
+        const int j = j0 + jj;
+        const int jc = min(max(j, 0), d.w - 1);
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            const int row = sl + SEG * r, j = j0 + jj;
-            lc[jj][r] = (j >= 0 && j < d.w && row > j && row < d.nr) ? Lb[(i64)j * d.nr + row] : T(0);
+            const int row = sl + SEG * r;
+            const T val = Lb[jc * d.nr + min(row, d.nr - 1)];
+            lc[jj][r] = (j >= 0 && j < d.w && row > j && row < d.nr) ? val : T(0);
         }
+    }
 }
 
 // One (supernode d, instance b) task on the SEG lanes of this thread's
@@ -667,6 +671,68 @@ __device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ 
 // even for an invalid task), so they are issued without waiting for the
 // validity test, and the first chunk of panel columns goes out together
 // with the right-hand-side entries; valid only gates the stores.
+// Forward substitution over the panel columns on the rows this lane holds:
+// v enters as the right-hand side (rows of the diagonal block) or zero
+// (rows below) and leaves as the solution or the update for the rows below.
+// lc holds the first chunk of columns on entry.
+template <typename T, int SEG, int R, int CH, typename DT>
+__device__ __forceinline__ void fwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di)[R], const T* __restrict__ Lb,
+                                         const DT& d, int sl) {
+    for (int j0 = 0; j0 < d.w; j0 += CH) {
+        if (j0 > 0) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
+#pragma unroll
+        for (int jj = 0; jj < CH; jj++) {
+            const int j = j0 + jj;
+            if (j < d.w) {
+                const int jl = j & (SEG - 1), jr = j / SEG;
+                T vs = v[0], es = di[0];
+#pragma unroll
+                for (int r = 1; r < R; r++)
+                    if (r == jr) { vs = v[r]; es = di[r]; }
+                const T yj = seg_bcast<T, SEG>(vs * es, jl);      // y_j = v_j / L_jj, formed in lane jl
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int row = sl + SEG * r;
+                    if (row == j) v[r] = yj;
+                    else v[r] -= lc[jj][r] * yj;      // zero below-diagonal mask for rows <= j
+                }
+            }
+        }
+    }
+}
+
+// Backward substitution, columns from the last one down: v enters as the
+// right-hand side on the diagonal rows and the known solution on the rows
+// below, and leaves with the solution on the diagonal rows. lc holds the
+// chunk [w - CH, w) on entry.
+template <typename T, int SEG, int R, int CH, typename DT>
+__device__ __forceinline__ void bwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di)[R], const T* __restrict__ Lb,
+                                         const DT& d, int sl) {
+    for (int jhi = d.w; jhi > 0; jhi -= CH) {
+        const int j0 = jhi - CH;
+        if (jhi < d.w) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
+#pragma unroll
+        for (int jj = CH - 1; jj >= 0; jj--) {
+            const int j = j0 + jj;
+            if (j >= 0) {
+                T part = T(0);
+#pragma unroll
+                for (int r = 0; r < R; r++) part += lc[jj][r] * v[r];   // rows <= j are masked to zero
+                part = seg_allsum<T, SEG>(part);
+                const int jl = j & (SEG - 1), jr = j / SEG;
+                T vs = v[0], es = di[0];
+#pragma unroll
+                for (int r = 1; r < R; r++)
+                    if (r == jr) { vs = v[r]; es = di[r]; }
+                const T xj = seg_bcast<T, SEG>((vs - part) * es, jl);   // formed in lane jl
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if (sl + SEG * r == j) v[r] = xj;
+            }
+        }
+    }
+}
+
 template <typename T, int SEG, int R, bool PUSH>
 __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
                                          const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X,
@@ -695,27 +761,7 @@ __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int
         v[r] = a;
         di[r] = e;
     }
-    for (int j0 = 0; j0 < d.w; j0 += CH) {
-        if (j0 > 0) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
-#pragma unroll
-        for (int jj = 0; jj < CH; jj++) {
-            const int j = j0 + jj;
-            if (j < d.w) {
-                const int jl = j & (SEG - 1), jr = j / SEG;
-                T vs = v[0], es = di[0];
-#pragma unroll
-                for (int r = 1; r < R; r++)
-                    if (r == jr) { vs = v[r]; es = di[r]; }
-                const T yj = seg_bcast<T, SEG>(vs * es, jl);      // y_j = v_j / L_jj, formed in lane jl
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const int row = sl + SEG * r;
-                    if (row == j) v[r] = yj;
-                    else v[r] -= lc[jj][r] * yj;      // zero below-diagonal mask for rows <= j
-                }
-            }
-        }
-    }
+    fwd_cols<T, SEG, R, CH>(lc, v, di, Lb, d, sl);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -750,29 +796,7 @@ __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int
         v[r] = a;
         di[r] = e;
     }
-    for (int jhi = d.w; jhi > 0; jhi -= CH) {
-        const int j0 = jhi - CH;
-        if (jhi < d.w) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
-#pragma unroll
-        for (int jj = CH - 1; jj >= 0; jj--) {
-            const int j = j0 + jj;
-            if (j >= 0) {
-                T part = T(0);
-#pragma unroll
-                for (int r = 0; r < R; r++) part += lc[jj][r] * v[r];   // rows <= j are masked to zero
-                part = seg_allsum<T, SEG>(part);
-                const int jl = j & (SEG - 1), jr = j / SEG;
-                T vs = v[0], es = di[0];
-#pragma unroll
-                for (int r = 1; r < R; r++)
-                    if (r == jr) { vs = v[r]; es = di[r]; }
-                const T xj = seg_bcast<T, SEG>((vs - part) * es, jl);   // formed in lane jl
-#pragma unroll
-                for (int r = 0; r < R; r++)
-                    if (sl + SEG * r == j) v[r] = xj;
-            }
-        }
-    }
+    bwd_cols<T, SEG, R, CH>(lc, v, di, Lb, d, sl);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -895,6 +919,331 @@ __global__ __launch_bounds__(NT) void k_tri_tree(SymView S, const TriDesc* __res
         if (sg[9]) bwd_tree_class<T, 64, 4>(S, desc + sg[8], sg[9], b, L, Dinv, X, st);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Tree traversal with the whole working set of the top levels in LDS.
+//
+// Every row of a supernode in the top levels is a column of the supernode or
+// of one of its ancestors, all of them in the top levels too, so the entries
+// of x (and of the reciprocal diagonal) those levels touch form a closed set:
+// they are read into LDS once, the forward updates go to LDS with LDS
+// atomics, the backward solve reads them there, and x is written back once.
+// The panels of a level are one contiguous range of L storage (panels are
+// stored level by level); the work-group stages the next level's range in
+// registers while it solves the current level from LDS, so a level costs no
+// dependent global round trip.
+//
+// One wavefront per supernode. Forward (lane = row): the columns are scaled
+// by the reciprocal diagonal when read, so that a column step is a lane
+// broadcast of the running right-hand side entry and one FMA per row held.
+// Backward (lane = column of the diagonal block): the rows below the
+// diagonal block (ancestors, already solved) are first folded in by per-lane
+// dot products, then the triangle is swept from the last column down with
+// the same broadcast-and-FMA step; no cross-lane reductions.
+// ---------------------------------------------------------------------------
+
+// byte offsets of the LDS areas of k_tri_tree2 (the staged panels keep the
+// layout of L storage)
+struct Tree2Lds {
+    int xs, dv, desc, rs, lvd, lvp, done, pan, total;
+};
+__host__ __device__ inline int al16(int v) { return (v + 15) & ~15; }
+__host__ __device__ inline Tree2Lds tree2_layout(int nt, int esz, int nd, int nrs, int nlev, int G, int pmax) {
+    Tree2Lds o;
+    o.xs = 0;
+    o.dv = al16(nt * esz);
+    o.desc = al16(o.dv + nt * esz);
+    o.rs = al16(o.desc + nd * (int)sizeof(TreeDesc));
+    o.lvd = al16(o.rs + nrs * 4);
+    o.lvp = al16(o.lvd + (nlev + 1) * 4);
+    o.done = al16(o.lvp + (nlev + 1) * 8);
+    o.pan = al16(o.done + G * 4);
+    o.total = al16(o.pan + pmax * esz);
+    return o;
+}
+
+// panel staging registers per thread (a level of at most NT * PR entries)
+template <typename T>
+__host__ __device__ constexpr int tree2_pr() {
+    return sizeof(T) == 4 ? 32 : 16;
+}
+
+// columns per chunk of the column loops (register budget of 64 words)
+template <typename T, int R>
+__host__ __device__ constexpr int tree2_chunk() {
+    return (64 / (R * (int)(sizeof(T) / 4))) < 32 ? 64 / (R * (int)(sizeof(T) / 4)) : 32;
+}
+
+template <typename T, int NT, int PR>
+__device__ __forceinline__ void tree2_load(T (&pr)[PR], const T* __restrict__ src, int ne) {
+#pragma unroll
+    for (int k = 0; k < PR; k++)
+        if (k * NT < ne) pr[k] = src[min(k * NT + (int)threadIdx.x, ne - 1)];
+}
+
+template <typename T, int NT, int PR>
+__device__ __forceinline__ void tree2_store(const T (&pr)[PR], T* P, int ne) {
+    T* p = P + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PR; k++) {
+        if ((k + 1) * NT <= ne) p[k * NT] = pr[k];
+        else if (k * NT < ne && k * NT + (int)threadIdx.x < ne) p[k * NT] = pr[k];
+    }
+}
+
+// forward solve of one supernode (w columns, nr rows, panel at staged offset
+// p0, first column at LDS slot `slot`, below-diagonal row slots at rsl[rs..]).
+// A column step: y_c = v_c / L_cc formed in lane c and broadcast, then one
+// FMA per row held; loads and masks of a chunk of columns come first.
+template <typename T, int R>
+__device__ __forceinline__ void fwd2(int w, int nr, int slot, int rs, int p0, const T* P, T* xs, const T* dv,
+                                     const i32* rsl) {
+    constexpr int CH = tree2_chunk<T, R>();
+    const int lane = threadIdx.x & (kWave - 1);
+    T v[R], di[R];
+    const T* Pr[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = lane + kWave * r, rc = min(row, w - 1);
+        const T a = xs[slot + rc], e = dv[slot + rc];
+        v[r] = row < w ? a : T(0);
+        di[r] = e;
+        Pr[r] = P + p0 + min(row, nr - 1);
+    }
+    // column step on prescaled entries L(row, c) / L(c, c): broadcast the
+    // final v_c from lane c, one FMA per row held; the next chunk's entries
+    // are read from LDS while the current one is applied
+#pragma unroll
+    for (int rb = 0; rb < R; rb++) {
+        const int cend = min(w, kWave * (rb + 1));
+        T cur[CH][R], nxt[CH][R];
+#pragma unroll
+        for (int r = 0; r < R; r++)
+#pragma unroll
+            for (int cc = 0; cc < CH; cc++)
+                if (r >= rb) cur[cc][r] = Pr[r][min(kWave * rb + cc, w - 1) * nr];
+        for (int c0 = kWave * rb; c0 < cend; c0 += CH) {
+            if (c0 + CH < cend) {
+#pragma unroll
+                for (int r = 0; r < R; r++)
+#pragma unroll
+                    for (int cc = 0; cc < CH; cc++)
+                        if (r >= rb) nxt[cc][r] = Pr[r][min(c0 + CH + cc, w - 1) * nr];
+            }
+#pragma unroll
+            for (int cc = 0; cc < CH; cc++) {
+                const T sc = lane_read(di[rb], (c0 + cc) & (kWave - 1));   // 1 / L(c, c)
+                const T vc = lane_read(v[rb], (c0 + cc) & (kWave - 1));    // final v_c
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (r < rb) continue;   // rows above column block rb take no update
+                    // entry (row, c) is used iff it is below the diagonal and
+                    // the column is in the block
+                    const int row = lane + kWave * r;
+                    const T l = (row > c0 + cc && c0 + cc < cend) ? cur[cc][r] * sc : T(0);
+                    v[r] -= l * vc;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int cc = 0; cc < CH; cc++)
+                    if (r >= rb) cur[cc][r] = nxt[cc][r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = lane + kWave * r;
+        if (row < w) xs[slot + row] = v[r] * di[r];
+        else if (row < nr) atomicAdd(&xs[rsl[rs + row - w]], v[r]);
+    }
+}
+
+// backward solve of one supernode; lane i holds diagonal-block column i
+// (and i + 64, ... for wider supernodes). The rows below (ancestors, solved)
+// are folded in by per-lane dot products, then the triangle is swept from
+// the last column down, x_j = acc_j / L_jj broadcast from lane j.
+template <typename T, int R>
+__device__ __forceinline__ void bwd2(int w, int nr, int slot, int rs, int p0, const T* P, T* xs, const T* dv,
+                                     const i32* rsl) {
+    constexpr int CH = tree2_chunk<T, R>();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nb = nr - w;
+    T acc[R], acc2[R], xb[R], di[R];
+    const T* Pc[R];   // column i of the panel (lanes past w: column w - 1, never read back)
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int i = lane + kWave * q, ic = min(i, w - 1);
+        const T a = xs[slot + ic], e = dv[slot + ic];
+        acc[q] = i < w ? a : T(0);
+        di[q] = e;
+        acc2[q] = T(0);
+        Pc[q] = P + p0 + ic * nr;
+        // solution on the rows below, one per lane
+        T xv = T(0);
+        if (nb > 0) xv = xs[rsl[rs + min(i, nb - 1)]];
+        xb[q] = i < nb ? xv : T(0);
+    }
+    // acc_i -= sum_k L(w + k, i) x(w + k), CH rows at a time
+#pragma unroll
+    for (int kb = 0; kb < R; kb++) {
+        const int kend = min(nb - kWave * kb, kWave);
+        for (int k0 = 0; k0 < kend; k0 += CH) {
+            T pa[CH][R];
+#pragma unroll
+            for (int kk = 0; kk < CH; kk++) {
+                const int row = w + kWave * kb + min(k0 + kk, kend - 1);
+#pragma unroll
+                for (int q = 0; q < R; q++) pa[kk][q] = Pc[q][row];
+            }
+#pragma unroll
+            for (int kk = 0; kk < CH; kk++) {
+                // lanes past the last row below hold zero
+                const T xr = lane_read(xb[kb], (k0 + kk) & (kWave - 1));
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    if (kk & 1) acc2[q] -= pa[kk][q] * xr;
+                    else acc[q] -= pa[kk][q] * xr;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; q++) acc[q] += acc2[q];
+    // the triangle, from the last column down
+#pragma unroll
+    for (int qb = R - 1; qb >= 0; qb--) {
+        if (kWave * qb >= w) continue;
+        const int jlo = kWave * qb, jtop = min(w, kWave * (qb + 1)) - 1;
+        T cur[CH][R], nxt[CH][R];
+#pragma unroll
+        for (int q = 0; q < R; q++)
+#pragma unroll
+            for (int jj = 0; jj < CH; jj++)
+                if (q <= qb) cur[jj][q] = Pc[q][max(jtop - jj, jlo)];
+        for (int j1 = jtop; j1 >= jlo; j1 -= CH) {
+            if (j1 - CH >= jlo) {
+#pragma unroll
+                for (int q = 0; q < R; q++)
+#pragma unroll
+                    for (int jj = 0; jj < CH; jj++)
+                        if (q <= qb) nxt[jj][q] = Pc[q][max(j1 - CH - jj, jlo)];
+            }
+#pragma unroll
+            for (int jj = 0; jj < CH; jj++) {
+                const int j = j1 - jj;
+                const T sc = lane_read(di[qb], j & (kWave - 1));    // 1 / L(j, j)
+                const T aj = lane_read(acc[qb], j & (kWave - 1));   // final acc_j
+#pragma unroll
+                for (int q = 0; q < R; q++) {
+                    if (q > qb) continue;   // columns right of block qb are final
+                    // entry (j, i) is used iff it is below the diagonal and the
+                    // row is in block qb
+                    const int i = lane + kWave * q;
+                    const T l = (i < j && j >= jlo) ? cur[jj][q] * sc : T(0);
+                    acc[q] -= l * aj;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < R; q++)
+#pragma unroll
+                for (int jj = 0; jj < CH; jj++)
+                    if (q <= qb) cur[jj][q] = nxt[jj][q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const int i = lane + kWave * q;
+        if (i < w) xs[slot + i] = acc[q] * di[q];
+    }
+}
+
+// forward over levels [l0, l1), then backward. tcols[0..nt) are the columns
+// of those levels (slot i holds x[tcols[i]]); desc[lev_desc0[l0] ..
+// lev_desc0[l1]) their supernodes, trs[rs0, rs0 + nrs) their row slots;
+// level l's panels are L storage [lev_lptr[l], lev_lptr[l + 1]) of at most
+// pmax <= NT * PR entries.
+template <typename T, int NT, int PR>
+__global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __restrict__ desc,
+                                                  const i32* __restrict__ lev_desc0, const i64* __restrict__ lev_lptr,
+                                                  int l0, int l1, const i32* __restrict__ tcols, int nt,
+                                                  const i32* __restrict__ trs, int rs0, int nrs, int pmax,
+                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  T* __restrict__ X, const int* ids, const CGState* st) {
+    extern __shared__ double smem_d[];
+    const int nlev = l1 - l0;
+    const int d0 = lev_desc0[l0], nd = lev_desc0[l1] - d0;
+    const Tree2Lds o = tree2_layout(nt, (int)sizeof(T), nd, nrs, nlev, S.G, pmax);
+    unsigned char* sm = reinterpret_cast<unsigned char*>(smem_d);
+    T* xs = reinterpret_cast<T*>(sm + o.xs);
+    T* dv = reinterpret_cast<T*>(sm + o.dv);
+    TreeDesc* dl = reinterpret_cast<TreeDesc*>(sm + o.desc);
+    i32* rsl = reinterpret_cast<i32*>(sm + o.rs);
+    i32* lvd = reinterpret_cast<i32*>(sm + o.lvd);
+    i64* lvp = reinterpret_cast<i64*>(sm + o.lvp);
+    int* done = reinterpret_cast<int*>(sm + o.done);
+    T* P = reinterpret_cast<T*>(sm + o.pan);
+    const int b = inst_of(ids, blockIdx.x);
+    T* x = X + (i64)b * S.n;
+    const T* Lb = L + (i64)b * S.Lsize;
+    const T* Db = Dinv + (i64)b * S.n;
+    for (int i = threadIdx.x; i < nt; i += NT) {
+        const int col = tcols[i];
+        xs[i] = x[col];
+        dv[i] = Db[col];
+    }
+    for (int i = threadIdx.x; i < nd; i += NT) {
+        TreeDesc e = desc[d0 + i];
+        e.rs -= rs0;
+        dl[i] = e;
+    }
+    for (int i = threadIdx.x; i < nrs; i += NT) rsl[i] = trs[rs0 + i];
+    for (int i = threadIdx.x; i <= nlev; i += NT) {
+        lvd[i] = lev_desc0[l0 + i] - d0;
+        lvp[i] = lev_lptr[l0 + i];
+    }
+    for (int k = threadIdx.x; k < S.G; k += NT) done[k] = st ? st[(i64)b * S.G + k].done : 0;
+    T pr[PR];
+    tree2_load<T, NT, PR>(pr, Lb + lev_lptr[l0], (int)(lev_lptr[l0 + 1] - lev_lptr[l0]));
+    const int wv = threadIdx.x / kWave, nw = NT / kWave;
+    // visits: levels l0 .. l1-1 forward, then l1-1 .. l0 backward; the top
+    // level's staged panels serve both of its visits
+    for (int v = 0; v < 2 * nlev; v++) {
+        const bool fwd = v < nlev;
+        const int li = fwd ? v : 2 * nlev - 1 - v;
+        __syncthreads();   // previous visit done with P and xs
+        if (v != nlev) {
+            tree2_store<T, NT, PR>(pr, P, (int)(lvp[li + 1] - lvp[li]));
+            __syncthreads();
+        }
+        const int vn = v + 1;
+        if (vn < 2 * nlev && vn != nlev) {
+            const int ln = vn < nlev ? vn : 2 * nlev - 1 - vn;
+            tree2_load<T, NT, PR>(pr, Lb + lvp[ln], (int)(lvp[ln + 1] - lvp[ln]));
+        }
+        const i64 pbase = lvp[li];
+        for (int q = lvd[li] + wv; q < lvd[li + 1]; q += nw) {
+            const TreeDesc& e = dl[q];
+            const int w = __builtin_amdgcn_readfirstlane(e.w);
+            const int nr = __builtin_amdgcn_readfirstlane(e.nr);
+            const int slot = __builtin_amdgcn_readfirstlane(e.slot);
+            const int rs = __builtin_amdgcn_readfirstlane(e.rs);
+            const int p0 = __builtin_amdgcn_readfirstlane((int)(e.lptr - pbase));
+            if (__builtin_amdgcn_readfirstlane(done[e.mem])) continue;
+            if (fwd) {
+                if (nr <= kWave) fwd2<T, 1>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+                else if (nr <= 2 * kWave) fwd2<T, 2>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+                else fwd2<T, 4>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+            } else {
+                if (nr <= kWave) bwd2<T, 1>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+                else if (nr <= 2 * kWave) bwd2<T, 2>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+                else bwd2<T, 4>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nt; i += NT) x[tcols[i]] = xs[i];
 }
 
 // one class per launch (used for the wide classes R >= 4)
