@@ -85,7 +85,7 @@ def run_gpu(args):
         s.analyze(b.pattern)
         if tune:   # once per pattern, outside the timed region (like the analysis)
             r = s.autotune(H, D, J, b.delta, b.gamma, R1, R2)
-            tuned[prec] = {"relax": r["relax"], "tree_width": r["tree_width"]}
+            tuned[prec] = {"relax": r["relax"], "tree_width": r["tree_width"], "tree_staged": r["tree_staged"]}
         return s
 
     def step(s, h=H, d=D, j=J, r1=R1, r2=R2, delta=b.delta, gamma=b.gamma):
@@ -116,14 +116,15 @@ def run_gpu(args):
     # levels below `lo` run one launch per level; the levels above in the
     # tree-traversal kernel (one launch per application of H_gamma^{-1})
     nlev = len(lf)
-    lo = round(prof["bwd"][1] / prof["tri_tree"][1]) if prof["tri_tree"][1] else nlev
+    tk = tree_key(prof)
+    lo = round(prof["bwd"][1] / prof[tk][1]) if prof[tk][1] else nlev
     # applications per instance over the profiled step: each pass applies
     # H_gamma^{-1} once per CG iteration plus twice (w and the primal
     # recovery); J^T and J are applied once per CG iteration plus twice / once
     apps = sum(i["cg_iters"] + 2 * i["passes"] for i in pinfos)
     spmv_apps = sum(2 * i["cg_iters"] + 3 * i["passes"] for i in pinfos)
     total = {"fwd": sum(lf[:lo]) * apps, "bwd": sum(lb[:lo]) * apps,
-             "tri_tree": (sum(lf[lo:]) + sum(lb[lo:])) * apps,
+             tk: (sum(lf[lo:]) + sum(lb[lo:])) * apps,
              "jt_spmv": per["jt_spmv"] * spmv_apps / 2, "j_spmv": per["j_spmv"] * spmv_apps / 2}
     best = max(total, key=lambda k: prof[k][0])
     ms_tot, launches = prof[best]
@@ -133,6 +134,8 @@ def run_gpu(args):
     kname = {"fwd": "k_fwd_lvl<float,true> (forward supernodal triangular solve, one launch per level)",
              "bwd": "k_bwd_lvl<float> (backward supernodal triangular solve, one launch per level)",
              "tri_tree": "k_tri_tree<float,true,512> (both solves over the thin top levels)",
+             "tri_tree_staged": "k_tri_tree2<float,512,32> (both solves over the thin top levels, "
+                                "working set staged in LDS)",
              "jt_spmv": "k_jt<float>", "j_spmv": "k_j<float>"}[best]
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -323,7 +326,7 @@ def large_single(args):
     st = s.stats()
     print(json.dumps({"workload": f"grid-like n_x={n}, m={n // 2}, gamma=1e6, mixed precision, "
                                   f"{args.cycles} factor+solve cycles with fresh D_x, target RR<=1e-10",
-                      "analyze_s": round(t_an, 2), "autotuned": {"relax": tune["relax"], "tree_width": tune["tree_width"]},
+                      "analyze_s": round(t_an, 2), "autotuned": {"relax": tune["relax"], "tree_width": tune["tree_width"], "tree_staged": tune["tree_staged"]},
                       "sustained_solves_per_s": round(ok / el, 3), "s_per_cycle": round(el / args.cycles, 3),
                       "converged": f"{ok}/{args.cycles}", "max_rr": max(i["rr"] for i in res),
                       "fp64_fallbacks": sum(i["fp64_fallback"] for i in res),
@@ -352,10 +355,18 @@ def profile_hsolve(args):
         s.hsolve(rhs)
     prof = s.profile_end()
     lf, lb = level_bytes(s, 4)
-    lo = round(prof["bwd"][1] / prof["tri_tree"][1]) if prof["tri_tree"][1] else len(lf)
-    print(json.dumps({"levels": len(lf), "per_level_launch_levels": lo,
-                      "alg_bytes_per_launch": {"fwd": sum(lf[:lo]) * args.nb / lo, "bwd": sum(lb[:lo]) * args.nb / lo,
-                                               "tri_tree": (sum(lf[lo:]) + sum(lb[lo:])) * args.nb}}))
+    tk = tree_key(prof)
+    lo = round(prof["bwd"][1] / prof[tk][1]) if prof[tk][1] else len(lf)
+    print(json.dumps({"levels": len(lf), "per_level_launch_levels": lo, "tree_kernel": tk,
+                      "alg_bytes_per_launch": {"fwd": sum(lf[:lo]) * args.nb / max(lo, 1),
+                                               "bwd": sum(lb[:lo]) * args.nb / max(lo, 1),
+                                               tk: (sum(lf[lo:]) + sum(lb[lo:])) * args.nb}}))
+
+
+def tree_key(prof):
+    """Profile class of the tree-traversal launches of a run (the staged
+    kernel where the top levels fit it, else the global-memory one)."""
+    return "tri_tree_staged" if prof.get("tri_tree_staged", (0, 0))[1] else "tri_tree"
 
 
 def load_traffic():
@@ -430,11 +441,15 @@ def main():
         return
     value, el, roofline, extra, b = run_gpu(args)
     tr = load_traffic()
-    if tr and roofline["kernel"].startswith(tr["kernel"]):
+    ratio = None
+    for k, r in (tr or {}).get("traffic_over_alg", {}).items():
+        if roofline["kernel"].startswith(k):
+            ratio = r
+    if ratio is not None:
         # counter-measured HBM bytes per launch relative to the algorithmic
         # bytes of the same launches, applied to this run's launches
-        roofline["traffic"] = int(tr["traffic_over_alg"] * roofline["bytes_per_launch"])
-        roofline["traffic_over_alg"] = tr["traffic_over_alg"]
+        roofline["traffic"] = int(ratio * roofline["bytes_per_launch"])
+        roofline["traffic_over_alg"] = ratio
     cpu = None if args.no_cpu else cpu_baseline(b, args.cpu_budget)
     out = {
         "metric": "KKT solves/sec at 1e-10 rel. KKT residual: mixed-prec batched vs plain FP64",

@@ -151,24 +151,27 @@ int hkkt_analyze_group(hkkt_ctx *ctx, int G, const int64_t *x_off, const int64_t
  * hkkt_analyze_group): times candidate schedules on the given values and
  * keeps the fastest. Candidates: supernode amalgamation relax in {0, 1, 2}
  * (supernode shapes: fewer, wider supernodes and fewer levels against more
- * stored zeros) x the number of top tree levels whose triangular solves run
- * in the single-launch tree kernel (levels of at most {0, 8, 32, 128}
- * supernodes). Cost per candidate (milliseconds, host clock around
- * synchronised work): with right-hand sides r1, r2 (as for hkkt_solve_batch;
- * r2 may be NULL when m = 0), one hkkt_factor_batch plus one hkkt_solve_batch
- * of the nb instances; with r1 = NULL a proxy: one factorization + one
- * application of H_gamma^{-1} to all instances + four applications to a list
- * of min(nb, 8) instances (the late CG iterations run on few instances). The
- * chosen relax is written to the context's options and the pattern is
- * re-analysed with it; choice[0] = relax, choice[1] = tree width. cost_ms
- * (may be NULL) gets up to max_cost candidate costs in the order relax-major,
- * width-minor. Values as for hkkt_factor_batch. The context is left analysed
- * and not factored: call hkkt_factor_batch next. Returns 0 or a negative
- * code (-3 if not analysed). */
+ * stored zeros) x seven triangular-solve schedules: no tree kernel, then for
+ * tree widths 8, 32, 128 (the top levels of at most that many supernodes
+ * run in one tree-traversal launch) the staged tree kernel (right-hand side,
+ * schedule and panels in LDS, where they fit) and the global-memory one.
+ * Cost per candidate (milliseconds, host clock around synchronised work):
+ * with right-hand sides r1, r2 (as for hkkt_solve_batch; r2 may be NULL when
+ * m = 0), one hkkt_factor_batch plus one hkkt_solve_batch of the nb
+ * instances; with r1 = NULL a proxy: one factorization + one application of
+ * H_gamma^{-1} to all instances + four applications to a list of min(nb, 8)
+ * instances (the late CG iterations run on few instances). The chosen relax
+ * is written to the context's options and the pattern is re-analysed with
+ * it; choice[0] = relax, choice[1] = tree width, choice[2] = 1 for the
+ * staged tree kernel. cost_ms (may be NULL) gets up to max_cost candidate
+ * costs, relax-major, in the schedule order above (21 in all). Values as for
+ * hkkt_factor_batch. The context is left analysed and not factored: call
+ * hkkt_factor_batch next. Returns 0 or a negative code (-3 if not
+ * analysed). */
 int hkkt_autotune(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
                   const double *J_val, const double *delta, const double *gamma,
                   const double *r1, const double *r2,
-                  int32_t choice[2], double *cost_ms, int max_cost);
+                  int32_t choice[3], double *cost_ms, int max_cost);
 
 /* Numeric factorization of nb instances that share the analysed pattern
  * (Sec. 2: once per matrix; Algorithm 1 "Try LL^T = chol(H_delta)").
@@ -278,8 +281,9 @@ int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
  * SpMV, 6 J SpMV, 7 CG vector updates, 8 CG scalars, 9 KKT residual,
  * 10 other, 11 triangular solves of very wide/tall supernodes, 12 both
  * triangular solves over the thin top levels of the tree (one launch, one
- * work-group per instance). */
-#define HKKT_NPROF 13
+ * work-group per instance), 13 the same with the top levels' working set
+ * staged in LDS. */
+#define HKKT_NPROF 14
 int hkkt_profile_begin(hkkt_ctx *ctx);
 int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);
 

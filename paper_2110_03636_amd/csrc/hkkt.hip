@@ -60,7 +60,7 @@ static double now_ms() {
 // ---------------------------------------------------------------------------
 // optional per-kernel timing with HIP events on the context's stream
 // ---------------------------------------------------------------------------
-constexpr int kNProf = 13;
+constexpr int kNProf = 14;
 struct Prof {
     bool on = false;
     std::mutex mu;                                   // launches may come from two host threads
@@ -189,6 +189,7 @@ struct DevSym {
     std::vector<int> lev_count;                 // supernodes per level
     std::vector<char> tree_fits;                // level fits the tree-traversal classes
     int tree_width = 32;                        // widest level run by the tree kernels
+    int tree_stage = 1;                         // staged (LDS) tree kernel where it fits
     // tree solve with x in LDS: columns ordered by level from the root down,
     // so that the columns of levels [l, nlevels) are the first tree_nt[l]
     // slots for every l; per supernode (parallel to tri_desc) its slots
@@ -551,6 +552,7 @@ struct hkkt_ctx {
         std::vector<int32_t> Hi, Ji, perm;
     } pat;
     int tree_width = -1;          // autotuned tree-kernel width (-1: library default)
+    int tree_stage = -1;          // autotuned staged-kernel choice (-1: library default)
 };
 
 namespace hkkt {
@@ -758,7 +760,7 @@ static int tree2_lo(const hkkt_ctx* c, int lo, int* pmax_out) {
     const DevSym& D = c->dev;
     const Symbolic& S = c->sym.S;
     *pmax_out = 0;
-    if (off || c->opt.deterministic != 0) return S.nlevels;
+    if (off || c->opt.deterministic != 0 || D.tree_stage == 0) return S.nlevels;
     const i64 cap = (i64)kTreeNT * tree2_pr<T>();
     int best = S.nlevels;
     i64 pmax = 0;
@@ -790,7 +792,7 @@ static void launch_tree2(hkkt_ctx* c, Batch& B, int l0, int pmax, const int* ids
         HIPCHK(hipFuncSetAttribute((const void*)k_tri_tree2<T, kTreeNT, PR>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_max));
     });
-    LAUNCH(12 + 16 * (l0 + 1), (k_tri_tree2<T, kTreeNT, PR>), dim3(nids), dim3(kTreeNT), lds, B.stream, D.v,
+    LAUNCH(13 + 16 * (l0 + 1), (k_tri_tree2<T, kTreeNT, PR>), dim3(nids), dim3(kTreeNT), lds, B.stream, D.v,
            D.tree_desc.as<TreeDesc>(), D.lev_desc0_dev.as<i32>(), D.lev_lptr_dev.as<i64>(), l0, l1,
            D.tree_cols.as<i32>(), D.tree_nt[l0], D.tree_rs.as<i32>(), rs0, nrs, pmax, B.L.as<T>(), B.Dinv.as<T>(),
            B.X.as<T>(), ids, st_);
@@ -1217,6 +1219,7 @@ static int analyze_ctx(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* 
         HIPCHK(hipStreamSynchronize(c->stream));
         if (c->pat.Hp.data() != Hp) {   // keep a copy for re-analysis (not when re-analysing from it)
             c->tree_width = -1;         // a new pattern drops the tuned choice
+            c->tree_stage = -1;
             c->pat.G = G;
             c->pat.n = n;
             c->pat.m = m;
@@ -1229,6 +1232,7 @@ static int analyze_ctx(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* 
             c->pat.perm.assign(perm ? perm : nullptr, perm ? perm + n : nullptr);
         }
         if (c->tree_width >= 0) c->dev.tree_width = c->tree_width;
+        if (c->tree_stage >= 0) c->dev.tree_stage = c->tree_stage;
         c->analysed = true;
         c->ms[0] = now_ms() - t0;
         return HKKT_OK;
@@ -1390,7 +1394,7 @@ int hkkt_analyze_group(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* 
 }
 
 int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* delta,
-                  const double* gamma, const double* r1, const double* r2, int32_t choice[2], double* cost_ms,
+                  const double* gamma, const double* r1, const double* r2, int32_t choice[3], double* cost_ms,
                   int max_cost) {
     if (!c || !choice) return HKKT_ERR_ARG;
     if (!c->analysed) { c->err = "autotune before analyze"; return HKKT_ERR_STATE; }
@@ -1424,7 +1428,7 @@ int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const 
         const bool prof_on = c->prof.on;
         c->prof.on = false;
         double best = INFINITY;
-        int best_relax = c->opt.relax, best_width = 32, k = 0;
+        int best_relax = c->opt.relax, best_width = 32, best_stage = 1, k = 0;
         for (int relax : relaxes) {
             c->opt.relax = relax;
             int rc = reanalyze(c);
@@ -1451,8 +1455,11 @@ int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const 
             std::vector<int> small(ksmall);
             for (int i = 0; i < ksmall; i++) small[i] = i;
             HIPCHK(hipMemcpyAsync(B.ids_a.p, small.data(), ksmall * 4, hipMemcpyHostToDevice, st));
-            for (int w : widths) {
+            for (int cand = 0; cand < 7; cand++) {
+                // (0), then (w, staged), (w, global) for w = 8, 32, 128
+                const int w = widths[(cand + 1) / 2], stage = cand == 0 ? 1 : (cand & 1);
                 c->dev.tree_width = w;
+                c->dev.tree_stage = stage;
                 if (r1) {
                     // the quantity being tuned: factor + solve to the tolerance
                     t0 = now_ms();
@@ -1466,6 +1473,7 @@ int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const 
                         best = cost;
                         best_relax = relax;
                         best_width = w;
+                        best_stage = stage;
                     }
                     continue;
                 }
@@ -1492,16 +1500,19 @@ int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const 
                     best = cost;
                     best_relax = relax;
                     best_width = w;
+                        best_stage = stage;
                 }
             }
         }
         c->opt.relax = best_relax;
         c->tree_width = best_width;
+        c->tree_stage = best_stage;
         const int rc = reanalyze(c);
         c->prof.on = prof_on;
         if (rc != HKKT_OK) return rc;
         choice[0] = best_relax;
         choice[1] = best_width;
+        choice[2] = best_stage;
         return HKKT_OK;
     })
 }

@@ -27,7 +27,7 @@ EXPORTS = [
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune", "hkkt_symbolic_cb_offsets",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
-              "cg_scalar", "residual", "other", "tri_wide", "tri_tree"]
+              "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged"]
 
 i64p = C.POINTER(C.c_int64)
 i32p = C.POINTER(C.c_int32)
@@ -363,11 +363,12 @@ class Solver(_SymbolicView):
         return rc, st, fc
 
     def autotune(self, H_val, D_x, J_val, delta, gamma, r1=None, r2=None):
-        """Pick relax and the tree-kernel width for the analysed pattern by
-        timing candidates on these values, with trial solves of r1, r2 when
-        given (see hkkt_autotune). Returns {"relax", "tree_width", "cost_ms":
-        [[relax, width, ms], ...]}; the context is re-analysed and must be
-        factored next."""
+        """Pick relax and the triangular-solve schedule (tree-kernel width,
+        staged or global tree kernel) for the analysed pattern by timing
+        candidates on these values, with trial solves of r1, r2 when given
+        (see hkkt_autotune). Returns {"relax", "tree_width", "tree_staged",
+        "cost_ms": [[relax, width, staged, ms], ...]}; the context is
+        re-analysed and must be factored next."""
         delta = np.atleast_1d(np.asarray(delta, np.float64)).reshape(-1)
         gamma = np.atleast_1d(np.asarray(gamma, np.float64)).reshape(-1)
         nb = int(delta.shape[0]) // self.G
@@ -378,14 +379,16 @@ class Solver(_SymbolicView):
             Jv = None
         R1 = self._arr(r1, nb, self.n) if r1 is not None else None
         R2 = self._arr(r2, nb, self.m) if (r1 is not None and self.m > 0) else None
-        choice = np.zeros(2, np.int32)
-        cost = np.full(12, np.nan)
+        choice = np.zeros(3, np.int32)
+        cost = np.full(21, np.nan)
         _check(lib().hkkt_autotune(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv), delta.ctypes.data,
-                                   gamma.ctypes.data, _ptr(R1), _ptr(R2), choice.ctypes.data, cost.ctypes.data, 12),
+                                   gamma.ctypes.data, _ptr(R1), _ptr(R2), choice.ctypes.data, cost.ctypes.data, 21),
                self._ctx)
         self.nb = 0   # re-analysed: factor next
-        table = [[r, w, float(cost[i * 4 + j])] for i, r in enumerate((0, 1, 2)) for j, w in enumerate((0, 8, 32, 128))]
-        return {"relax": int(choice[0]), "tree_width": int(choice[1]), "cost_ms": table}
+        sched = [(0, 1)] + [(w, st) for w in (8, 32, 128) for st in (1, 0)]
+        table = [[r, w, st, float(cost[i * 7 + j])] for i, r in enumerate((0, 1, 2)) for j, (w, st) in enumerate(sched)]
+        return {"relax": int(choice[0]), "tree_width": int(choice[1]), "tree_staged": int(choice[2]),
+                "cost_ms": table}
 
     def factor_batch(self, batch):
         return self.factor(batch.H_val, batch.D_x, batch.J_val, batch.delta, batch.gamma)

@@ -304,17 +304,20 @@ def test_deterministic_and_atomic_forward_agree():
 
 
 def test_autotune_picks_min_cost_and_solves():
-    """The autotuner times all twelve candidates, keeps the cheapest, leaves
-    the context analysed with that relax, and the solve that follows meets
-    the oracle's residual bar."""
+    """The autotuner times all 21 candidates (3 relax x 7 solve schedules),
+    keeps the cheapest, leaves the context analysed with that relax, and the
+    solve that follows meets the oracle's residual bar."""
     b = synth.grid_like(3000, nb=4, seed=39, gammas=(1e4,), dx_exp=6.0)
     s = _solver(b, precision="mixed")
     r0 = s.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma)      # proxy objective
-    assert min(r0["cost_ms"], key=lambda c: c[2])[:2] == [r0["relax"], r0["tree_width"]]
+    best0 = min(r0["cost_ms"], key=lambda c: c[3])
+    assert best0[0] == r0["relax"] and best0[1] == r0["tree_width"]
+    assert best0[1] == 0 or best0[2] == r0["tree_staged"]
     r = s.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma, b.r1, b.r2)   # trial solves
-    assert len(r["cost_ms"]) == 12 and all(np.isfinite(c[2]) and c[2] > 0 for c in r["cost_ms"])
-    best = min(r["cost_ms"], key=lambda c: c[2])
+    assert len(r["cost_ms"]) == 21 and all(np.isfinite(c[3]) and c[3] > 0 for c in r["cost_ms"])
+    best = min(r["cost_ms"], key=lambda c: c[3])
     assert (best[0], best[1]) == (r["relax"], r["tree_width"])
+    assert best[1] == 0 or best[2] == r["tree_staged"]
     ref = hkkt.Symbolic.from_pattern(b.pattern, relax=r["relax"]).stats()
     assert s.stats()["supernodes"] == ref["supernodes"]
     with pytest.raises(hkkt.HKKTError):        # re-analysed: not factored
