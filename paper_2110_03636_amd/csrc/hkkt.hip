@@ -197,7 +197,8 @@ struct DevSym {
     std::vector<int> tree_nt;                   // [nlevels + 1]
     std::vector<int> lev_desc0, lev_rs0;        // [nlevels + 1] first descriptor / row slot of a level
     std::vector<i64> lev_lptr;                  // [nlevels + 1] L storage range of a level's panels
-    DBuf lev_desc0_dev, lev_lptr_dev;
+    std::vector<i64> lev_toff;                  // [nlevels + 1] the same in the staged solves' copy layout
+    DBuf lev_desc0_dev, lev_toff_dev;
     SymView v{};
 };
 
@@ -392,10 +393,13 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
             }
             std::vector<TreeDesc> trd(td.size());
             std::vector<i32> trs;
+            i64 toff = 0;   // row-major copies, rows padded to 4 entries, in descriptor (level-major) order
             for (size_t q = 0; q < td.size(); q++) {
                 const TriDesc& a = td[q];
                 TreeDesc& e = trd[q];
                 e.lptr = a.lptr;
+                e.toff = toff;
+                toff += (i64)a.nr * tree2_ws(a.w);
                 e.f = a.f;
                 e.w = a.w;
                 e.nr = a.nr;
@@ -412,10 +416,12 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
             }
             D.lev_desc0.assign(S.nlevels + 1, (int)td.size());
             D.lev_rs0.assign(S.nlevels + 1, (int)trs.size());
+            D.lev_toff.assign(S.nlevels + 1, toff);
             for (i32 l = 0; l < S.nlevels; l++) {
                 const int q = D.tri_seg[(size_t)l * kTriClasses].first;
                 D.lev_desc0[l] = q;
                 D.lev_rs0[l] = q < (int)trd.size() ? trd[q].rs : (int)trs.size();
+                D.lev_toff[l] = q < (int)trd.size() ? trd[q].toff : toff;
             }
             D.lev_lptr.assign(S.nlevels + 1, S.Lsize);
             for (i32 l = 0; l < S.nlevels; l++) {
@@ -429,7 +435,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
             upload(D.tree_cols, tcols, st);
             upload(D.tree_rs, trs, st);
             upload(D.lev_desc0_dev, D.lev_desc0, st);
-            upload(D.lev_lptr_dev, D.lev_lptr, st);
+            upload(D.lev_toff_dev, D.lev_toff, st);
             HIPCHK(hipStreamSynchronize(st));
         }
         std::vector<i32> sg(2 * D.tri_seg.size());
@@ -505,6 +511,12 @@ struct Batch {
     DBuf rsq, rowred, knorm, active;
     DBuf ids_pass, ids_a, ids_b, ids_all;   // batch-entry lists of the solve phase
     DBuf cact;                 // per (entry, member): member takes part in the current pass (groups)
+    // solve copy of the top levels' panels for the staged tree kernel:
+    // levels [lt_lo, nlevels), lt_size entries per instance from L storage
+    // offset lt_base; lt_lo = -1 when stale (rebuilt after a factorization)
+    DBuf Lt;
+    int lt_lo = -1;
+    i64 lt_base = 0, lt_size = 0;
     std::vector<int> h_fail;   // per (entry, member) min failing permuted column (INT_MAX ok)
 
     ValView vals() const {
@@ -765,7 +777,7 @@ static int tree2_lo(const hkkt_ctx* c, int lo, int* pmax_out) {
     int best = S.nlevels;
     i64 pmax = 0;
     for (int l = S.nlevels - 1; l >= lo; l--) {
-        const i64 ps = D.lev_lptr[l + 1] - D.lev_lptr[l];
+        const i64 ps = D.lev_toff[l + 1] - D.lev_toff[l];
         if (ps > cap) break;
         pmax = std::max(pmax, ps);
         const int nd = D.lev_desc0[S.nlevels] - D.lev_desc0[l];
@@ -787,15 +799,25 @@ static void launch_tree2(hkkt_ctx* c, Batch& B, int l0, int pmax, const int* ids
     const int nd = D.lev_desc0[l1] - D.lev_desc0[l0];
     const int rs0 = D.lev_rs0[l0], nrs = D.lev_rs0[l1] - rs0;
     const size_t lds = tree2_layout(D.tree_nt[l0], (int)sizeof(T), nd, nrs, l1 - l0, S.G, pmax).total;
+    if (B.lt_lo != l0) {   // solve copy of levels [l0, nlevels) after this factorization
+        B.lt_base = D.lev_toff[l0];
+        B.lt_size = D.lev_toff[S.nlevels] - B.lt_base;
+        B.Lt.ensure((size_t)B.nb * std::max<i64>(1, B.lt_size) * sizeof(T));
+        const int d0 = D.lev_desc0[l0];
+        LAUNCH(10, k_solve_copy<T>, dim3(nd, B.nb), dim3(kBlock), 0, B.stream, D.tree_desc.as<TreeDesc>() + d0,
+               (const T*)B.L.as<T>(), (i64)S.Lsize, (const T*)B.Dinv.as<T>(), (i64)S.n, B.Lt.as<T>(), B.lt_size,
+               B.lt_base);
+        B.lt_lo = l0;
+    }
     static std::once_flag attr;   // allow dynamic LDS up to the device's limit, once per instantiation
     std::call_once(attr, [&] {
         HIPCHK(hipFuncSetAttribute((const void*)k_tri_tree2<T, kTreeNT, PR>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_max));
     });
     LAUNCH(13 + 16 * (l0 + 1), (k_tri_tree2<T, kTreeNT, PR>), dim3(nids), dim3(kTreeNT), lds, B.stream, D.v,
-           D.tree_desc.as<TreeDesc>(), D.lev_desc0_dev.as<i32>(), D.lev_lptr_dev.as<i64>(), l0, l1,
-           D.tree_cols.as<i32>(), D.tree_nt[l0], D.tree_rs.as<i32>(), rs0, nrs, pmax, B.L.as<T>(), B.Dinv.as<T>(),
-           B.X.as<T>(), ids, st_);
+           D.tree_desc.as<TreeDesc>(), D.lev_desc0_dev.as<i32>(), D.lev_toff_dev.as<i64>(), l0, l1,
+           D.tree_cols.as<i32>(), D.tree_nt[l0], D.tree_rs.as<i32>(), rs0, nrs, pmax, (const T*)B.Lt.as<T>(),
+           B.lt_size, B.lt_base, B.Dinv.as<T>(), B.X.as<T>(), ids, st_);
 }
 
 template <typename T>
@@ -902,6 +924,7 @@ static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h
     HIPCHK(hipMemcpyAsync(B.active.p, active_h.data(), B.nb * 4, hipMemcpyHostToDevice, st));
     if (B.prec == HKKT_MIXED) launch_factor<float>(c, B, B.active.as<int>());
     else launch_factor<double>(c, B, B.active.as<int>());
+    B.lt_lo = -1;   // the staged solves' panel copy is rebuilt from the new factor
     B.h_fail.assign((size_t)B.nb * c->sym.S.G, INT_MAX);
     HIPCHK(hipMemcpyAsync(B.h_fail.data(), B.fail.p, B.h_fail.size() * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

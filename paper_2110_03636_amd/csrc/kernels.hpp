@@ -90,6 +90,7 @@ struct TriDesc {
 // offset of its below-diagonal rows' LDS indices in the row-slot table.
 struct TreeDesc {
     i64 lptr;    // panel offset in L storage
+    i64 toff;    // offset of its row-major copy in the staged solves' layout
     i32 f;       // first column (for the reciprocal diagonal)
     i32 w;       // width
     i32 nr;      // rows

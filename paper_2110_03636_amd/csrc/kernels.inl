@@ -975,117 +975,129 @@ __host__ __device__ constexpr int tree2_chunk() {
     return (64 / (R * (int)(sizeof(T) / 4))) < 32 ? 64 / (R * (int)(sizeof(T) / 4)) : 32;
 }
 
-template <typename T, int NT, int PR>
-__device__ __forceinline__ void tree2_load(T (&pr)[PR], const T* __restrict__ src, int ne) {
+// staging of a level's ne panel entries by nl threads (thread t holds
+// entries t, t + nl, ...)
+template <typename T, int PR>
+__device__ __forceinline__ void tree2_load(T (&pr)[PR], const T* __restrict__ src, int ne, int t, int nl) {
 #pragma unroll
     for (int k = 0; k < PR; k++)
-        if (k * NT < ne) pr[k] = src[min(k * NT + (int)threadIdx.x, ne - 1)];
+        if (k * nl < ne) pr[k] = src[min(k * nl + t, ne - 1)];
 }
 
-template <typename T, int NT, int PR>
-__device__ __forceinline__ void tree2_store(const T (&pr)[PR], T* P, int ne) {
-    T* p = P + threadIdx.x;
+template <typename T, int PR>
+__device__ __forceinline__ void tree2_store(const T (&pr)[PR], T* P, int ne, int t, int nl) {
 #pragma unroll
     for (int k = 0; k < PR; k++) {
-        if ((k + 1) * NT <= ne) p[k * NT] = pr[k];
-        else if (k * NT < ne && k * NT + (int)threadIdx.x < ne) p[k * NT] = pr[k];
+        const int e = k * nl + t;
+        if (k * nl < ne && e < ne) P[e] = pr[k];
     }
 }
 
-// forward solve of one supernode (w columns, nr rows, panel at staged offset
-// p0, first column at LDS slot `slot`, below-diagonal row slots at rsl[rs..]).
-// A column step: y_c = v_c / L_cc formed in lane c and broadcast, then one
-// FMA per row held; loads and masks of a chunk of columns come first.
+// The staged kernel solves with the unit lower triangular factor of
+// L = Lt D (Lt(r, c) = L(r, c) / L(c, c), D = diag(L)): forward Lt z = b
+// (then y = D^-1 z), backward Lt^T x = D^-1 y = D^-2 z. A solve copy of the
+// top levels' panels holds Lt row-major, each row padded to ws = w rounded
+// up to 4 columns, with zeros on and above the diagonal of each diagonal
+// block (k_solve_copy, once per factorization): a column step of either
+// sweep is one lane broadcast and one FMA per entry held (no masks, no
+// scaling on the chain); the forward sweep reads four columns of its row
+// per LDS access, the backward sweep's column-per-lane reads are
+// consecutive across lanes.
+__host__ __device__ inline int tree2_ws(int w) { return (w + 3) & ~3; }
+
+// four consecutive entries from a 16-byte aligned LDS address (FP32: one
+// 128-bit read; FP64: two)
+__device__ __forceinline__ void load4(float (&a)[4], const float* p) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    a[0] = t.x; a[1] = t.y; a[2] = t.z; a[3] = t.w;
+}
+__device__ __forceinline__ void load4(double (&a)[4], const double* p) {
+    const double2 t0 = *reinterpret_cast<const double2*>(p);
+    const double2 t1 = *reinterpret_cast<const double2*>(p + 2);
+    a[0] = t0.x; a[1] = t0.y; a[2] = t1.x; a[3] = t1.y;
+}
+
+// forward sweep of one supernode (w columns, nr rows, staged panel at p0,
+// first column at LDS slot `slot`, below-diagonal row slots at rsl[rs..]);
+// leaves D^-2 z on the supernode's columns and adds the updates into the
+// ancestors' entries
 template <typename T, int R>
 __device__ __forceinline__ void fwd2(int w, int nr, int slot, int rs, int p0, const T* P, T* xs, const T* dv,
                                      const i32* rsl) {
     constexpr int CH = tree2_chunk<T, R>();
     const int lane = threadIdx.x & (kWave - 1);
-    T v[R], di[R];
-    const T* Pr[R];
+    const int ws = tree2_ws(w);
+    T v[R];
+    const T* Pr[R];   // row of the panel (lanes past nr: row nr - 1, never read back)
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int row = lane + kWave * r, rc = min(row, w - 1);
-        const T a = xs[slot + rc], e = dv[slot + rc];
+        const int row = lane + kWave * r;
+        const T a = xs[slot + min(row, w - 1)];
         v[r] = row < w ? a : T(0);
-        di[r] = e;
-        Pr[r] = P + p0 + min(row, nr - 1);
+        Pr[r] = P + p0 + min(row, nr - 1) * ws;
     }
-    // column step on prescaled entries L(row, c) / L(c, c): broadcast the
-    // final v_c from lane c, one FMA per row held; the next chunk's entries
-    // are read from LDS while the current one is applied
 #pragma unroll
     for (int rb = 0; rb < R; rb++) {
         const int cend = min(w, kWave * (rb + 1));
-        T cur[CH][R], nxt[CH][R];
-#pragma unroll
-        for (int r = 0; r < R; r++)
-#pragma unroll
-            for (int cc = 0; cc < CH; cc++)
-                if (r >= rb) cur[cc][r] = Pr[r][min(kWave * rb + cc, w - 1) * nr];
         for (int c0 = kWave * rb; c0 < cend; c0 += CH) {
-            if (c0 + CH < cend) {
-#pragma unroll
-                for (int r = 0; r < R; r++)
-#pragma unroll
-                    for (int cc = 0; cc < CH; cc++)
-                        if (r >= rb) nxt[cc][r] = Pr[r][min(c0 + CH + cc, w - 1) * nr];
-            }
-#pragma unroll
-            for (int cc = 0; cc < CH; cc++) {
-                const T sc = lane_read(di[rb], (c0 + cc) & (kWave - 1));   // 1 / L(c, c)
-                const T vc = lane_read(v[rb], (c0 + cc) & (kWave - 1));    // final v_c
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    if (r < rb) continue;   // rows above column block rb take no update
-                    // entry (row, c) is used iff it is below the diagonal and
-                    // the column is in the block
-                    const int row = lane + kWave * r;
-                    const T l = (row > c0 + cc && c0 + cc < cend) ? cur[cc][r] * sc : T(0);
-                    v[r] -= l * vc;
-                }
-            }
+            // four columns per read; columns past w read as zero (padding
+            // up to ws, masked beyond), so the column steps carry no guard
+            T lc[CH][R];
 #pragma unroll
             for (int r = 0; r < R; r++)
 #pragma unroll
-                for (int cc = 0; cc < CH; cc++)
-                    if (r >= rb) cur[cc][r] = nxt[cc][r];
+                for (int cc = 0; cc < CH; cc += 4)
+                    if (r >= rb) {
+                        const int cq = min(c0 + cc, ws - 4);
+                        T a[4];
+                        load4(a, Pr[r] + cq);
+#pragma unroll
+                        for (int u = 0; u < 4; u++) lc[cc + u][r] = c0 + cc < ws ? a[u] : T(0);
+                    }
+#pragma unroll
+            for (int cc = 0; cc < CH; cc++) {
+                const T zc = lane_read(v[rb], (c0 + cc) & (kWave - 1));   // final z_c
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    if (r >= rb) v[r] -= lc[cc][r] * zc;   // rows above block rb take no update
+            }
         }
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int row = lane + kWave * r;
-        if (row < w) xs[slot + row] = v[r] * di[r];
-        else if (row < nr) atomicAdd(&xs[rsl[rs + row - w]], v[r]);
+        if (row < w) {
+            const T e = dv[slot + row];
+            xs[slot + row] = v[r] * e * e;
+        } else if (row < nr) {
+            atomicAdd(&xs[rsl[rs + row - w]], v[r]);
+        }
     }
 }
 
-// backward solve of one supernode; lane i holds diagonal-block column i
-// (and i + 64, ... for wider supernodes). The rows below (ancestors, solved)
-// are folded in by per-lane dot products, then the triangle is swept from
-// the last column down, x_j = acc_j / L_jj broadcast from lane j.
+// backward sweep of one supernode; lane i holds diagonal-block column i
+// (and i + 64, ... for wider supernodes): the solved rows below are folded
+// in by per-lane dot products, then the triangle is swept from the last
+// column down
 template <typename T, int R>
-__device__ __forceinline__ void bwd2(int w, int nr, int slot, int rs, int p0, const T* P, T* xs, const T* dv,
-                                     const i32* rsl) {
+__device__ __forceinline__ void bwd2(int w, int nr, int slot, int rs, int p0, const T* P, T* xs, const i32* rsl) {
     constexpr int CH = tree2_chunk<T, R>();
     const int lane = threadIdx.x & (kWave - 1);
-    const int nb = nr - w;
-    T acc[R], acc2[R], xb[R], di[R];
-    const T* Pc[R];   // column i of the panel (lanes past w: column w - 1, never read back)
+    const int nb = nr - w, ws = tree2_ws(w);
+    T acc[R], acc2[R], xb[R];
+    const T* Pc[R];   // column i of the panel, stride ws (lanes past w: column w - 1, never read back)
 #pragma unroll
     for (int q = 0; q < R; q++) {
         const int i = lane + kWave * q, ic = min(i, w - 1);
-        const T a = xs[slot + ic], e = dv[slot + ic];
+        const T a = xs[slot + ic];
         acc[q] = i < w ? a : T(0);
-        di[q] = e;
         acc2[q] = T(0);
-        Pc[q] = P + p0 + ic * nr;
-        // solution on the rows below, one per lane
+        Pc[q] = P + p0 + ic;
         T xv = T(0);
         if (nb > 0) xv = xs[rsl[rs + min(i, nb - 1)]];
         xb[q] = i < nb ? xv : T(0);
     }
-    // acc_i -= sum_k L(w + k, i) x(w + k), CH rows at a time
+    // acc_i -= sum_k Lt(w + k, i) x(w + k), CH rows at a time
 #pragma unroll
     for (int kb = 0; kb < R; kb++) {
         const int kend = min(nb - kWave * kb, kWave);
@@ -1095,7 +1107,7 @@ __device__ __forceinline__ void bwd2(int w, int nr, int slot, int rs, int p0, co
             for (int kk = 0; kk < CH; kk++) {
                 const int row = w + kWave * kb + min(k0 + kk, kend - 1);
 #pragma unroll
-                for (int q = 0; q < R; q++) pa[kk][q] = Pc[q][row];
+                for (int q = 0; q < R; q++) pa[kk][q] = Pc[q][row * ws];
             }
 #pragma unroll
             for (int kk = 0; kk < CH; kk++) {
@@ -1115,62 +1127,68 @@ __device__ __forceinline__ void bwd2(int w, int nr, int slot, int rs, int p0, co
 #pragma unroll
     for (int qb = R - 1; qb >= 0; qb--) {
         if (kWave * qb >= w) continue;
-        const int jlo = kWave * qb, jtop = min(w, kWave * (qb + 1)) - 1;
-        T cur[CH][R], nxt[CH][R];
-#pragma unroll
-        for (int q = 0; q < R; q++)
-#pragma unroll
-            for (int jj = 0; jj < CH; jj++)
-                if (q <= qb) cur[jj][q] = Pc[q][max(jtop - jj, jlo)];
-        for (int j1 = jtop; j1 >= jlo; j1 -= CH) {
-            if (j1 - CH >= jlo) {
-#pragma unroll
-                for (int q = 0; q < R; q++)
-#pragma unroll
-                    for (int jj = 0; jj < CH; jj++)
-                        if (q <= qb) nxt[jj][q] = Pc[q][max(j1 - CH - jj, jlo)];
-            }
-#pragma unroll
-            for (int jj = 0; jj < CH; jj++) {
-                const int j = j1 - jj;
-                const T sc = lane_read(di[qb], j & (kWave - 1));    // 1 / L(j, j)
-                const T aj = lane_read(acc[qb], j & (kWave - 1));   // final acc_j
-#pragma unroll
-                for (int q = 0; q < R; q++) {
-                    if (q > qb) continue;   // columns right of block qb are final
-                    // entry (j, i) is used iff it is below the diagonal and the
-                    // row is in block qb
-                    const int i = lane + kWave * q;
-                    const T l = (i < j && j >= jlo) ? cur[jj][q] * sc : T(0);
-                    acc[q] -= l * aj;
-                }
-            }
+        const int jlo = kWave * qb;
+        for (int j1 = min(w, kWave * (qb + 1)) - 1; j1 >= jlo; j1 -= CH) {
+            // Lt(j, i), zero for j <= i; rows below jlo (the last chunk's
+            // tail) read as zero, so the steps carry no guard
+            T t[CH][R];
 #pragma unroll
             for (int q = 0; q < R; q++)
 #pragma unroll
                 for (int jj = 0; jj < CH; jj++)
-                    if (q <= qb) cur[jj][q] = nxt[jj][q];
+                    if (q <= qb) {
+                        const T a = Pc[q][max(j1 - jj, jlo) * ws];
+                        t[jj][q] = j1 - jj >= jlo ? a : T(0);
+                    }
+#pragma unroll
+            for (int jj = 0; jj < CH; jj++) {
+                const T xj = lane_read(acc[qb], (j1 - jj) & (kWave - 1));   // final x_j
+#pragma unroll
+                for (int q = 0; q < R; q++)
+                    if (q <= qb) acc[q] -= t[jj][q] * xj;   // columns right of block qb are final
+            }
         }
     }
 #pragma unroll
     for (int q = 0; q < R; q++) {
         const int i = lane + kWave * q;
-        if (i < w) xs[slot + i] = acc[q] * di[q];
+        if (i < w) xs[slot + i] = acc[q];
+    }
+}
+
+// Solve copy of the panels of supernodes desc[0, gridDim.x): row-major,
+// rows of ws = tree2_ws(w) entries, Lt(r, c) = L(r, c) / L(c, c) below the
+// diagonal, zero on and above it and in the padding, at offset toff - base
+// of instance b's copy (ltsize entries per instance).
+template <typename T>
+__global__ void k_solve_copy(const TreeDesc* __restrict__ desc, const T* __restrict__ L, i64 Lsize,
+                             const T* __restrict__ Dinv, i64 n, T* __restrict__ Lt, i64 ltsize, i64 base) {
+    const TreeDesc d = desc[blockIdx.x];
+    const int b = blockIdx.y;
+    const int ws = tree2_ws(d.w);
+    const T* src = L + (i64)b * Lsize + d.lptr;
+    T* dst = Lt + (i64)b * ltsize + (d.toff - base);
+    const T* di = Dinv + (i64)b * n + d.f;
+    const int tot = d.nr * ws;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int row = e / ws, c = e - row * ws;
+        dst[e] = (c < d.w && row > c) ? src[(i64)c * d.nr + row] * di[c] : T(0);
     }
 }
 
 // forward over levels [l0, l1), then backward. tcols[0..nt) are the columns
 // of those levels (slot i holds x[tcols[i]]); desc[lev_desc0[l0] ..
 // lev_desc0[l1]) their supernodes, trs[rs0, rs0 + nrs) their row slots;
-// level l's panels are L storage [lev_lptr[l], lev_lptr[l + 1]) of at most
-// pmax <= NT * PR entries.
+// level l's panels are the solve copy's [lev_off[l] - base, lev_off[l + 1]
+// - base) (ltsize entries per instance), at most pmax <= NT * PR entries.
 template <typename T, int NT, int PR>
 __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __restrict__ desc,
-                                                  const i32* __restrict__ lev_desc0, const i64* __restrict__ lev_lptr,
+                                                  const i32* __restrict__ lev_desc0, const i64* __restrict__ lev_off,
                                                   int l0, int l1, const i32* __restrict__ tcols, int nt,
                                                   const i32* __restrict__ trs, int rs0, int nrs, int pmax,
-                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
-                                                  T* __restrict__ X, const int* ids, const CGState* st) {
+                                                  const T* __restrict__ Lt, i64 ltsize, i64 base,
+                                                  const T* __restrict__ Dinv, T* __restrict__ X, const int* ids,
+                                                  const CGState* st) {
     extern __shared__ double smem_d[];
     const int nlev = l1 - l0;
     const int d0 = lev_desc0[l0], nd = lev_desc0[l1] - d0;
@@ -1186,7 +1204,7 @@ __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __r
     T* P = reinterpret_cast<T*>(sm + o.pan);
     const int b = inst_of(ids, blockIdx.x);
     T* x = X + (i64)b * S.n;
-    const T* Lb = L + (i64)b * S.Lsize;
+    const T* Lb = Lt + (i64)b * ltsize;
     const T* Db = Dinv + (i64)b * S.n;
     for (int i = threadIdx.x; i < nt; i += NT) {
         const int col = tcols[i];
@@ -1201,12 +1219,13 @@ __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __r
     for (int i = threadIdx.x; i < nrs; i += NT) rsl[i] = trs[rs0 + i];
     for (int i = threadIdx.x; i <= nlev; i += NT) {
         lvd[i] = lev_desc0[l0 + i] - d0;
-        lvp[i] = lev_lptr[l0 + i];
+        lvp[i] = lev_off[l0 + i] - base;
     }
     for (int k = threadIdx.x; k < S.G; k += NT) done[k] = st ? st[(i64)b * S.G + k].done : 0;
     T pr[PR];
-    tree2_load<T, NT, PR>(pr, Lb + lev_lptr[l0], (int)(lev_lptr[l0 + 1] - lev_lptr[l0]));
+    tree2_load<T, PR>(pr, Lb + (lev_off[l0] - base), (int)(lev_off[l0 + 1] - lev_off[l0]), threadIdx.x, NT);
     const int wv = threadIdx.x / kWave, nw = NT / kWave;
+    int lw = 0;   // first wavefront of the threads holding the next visit's panels
     // visits: levels l0 .. l1-1 forward, then l1-1 .. l0 backward; the top
     // level's staged panels serve both of its visits
     for (int v = 0; v < 2 * nlev; v++) {
@@ -1214,13 +1233,20 @@ __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __r
         const int li = fwd ? v : 2 * nlev - 1 - v;
         __syncthreads();   // previous visit done with P and xs
         if (v != nlev) {
-            tree2_store<T, NT, PR>(pr, P, (int)(lvp[li + 1] - lvp[li]));
+            if (wv >= lw)
+                tree2_store<T, PR>(pr, P, (int)(lvp[li + 1] - lvp[li]), threadIdx.x - lw * kWave, NT - lw * kWave);
             __syncthreads();
         }
+        // the next visit's panels are loaded by the wavefronts without a
+        // supernode in this visit when they can hold them, so the loads do
+        // not hold up the ones that solve
         const int vn = v + 1;
         if (vn < 2 * nlev && vn != nlev) {
             const int ln = vn < nlev ? vn : 2 * nlev - 1 - vn;
-            tree2_load<T, NT, PR>(pr, Lb + lvp[ln], (int)(lvp[ln + 1] - lvp[ln]));
+            const int ne = (int)(lvp[ln + 1] - lvp[ln]);
+            lw = min(lvd[li + 1] - lvd[li], nw);
+            if (lw >= nw || (nw - lw) * kWave * PR < ne) lw = 0;
+            if (wv >= lw) tree2_load<T, PR>(pr, Lb + lvp[ln], ne, threadIdx.x - lw * kWave, NT - lw * kWave);
         }
         const i64 pbase = lvp[li];
         for (int q = lvd[li] + wv; q < lvd[li + 1]; q += nw) {
@@ -1229,16 +1255,16 @@ __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __r
             const int nr = __builtin_amdgcn_readfirstlane(e.nr);
             const int slot = __builtin_amdgcn_readfirstlane(e.slot);
             const int rs = __builtin_amdgcn_readfirstlane(e.rs);
-            const int p0 = __builtin_amdgcn_readfirstlane((int)(e.lptr - pbase));
+            const int p0 = __builtin_amdgcn_readfirstlane((int)(e.toff - base - pbase));
             if (__builtin_amdgcn_readfirstlane(done[e.mem])) continue;
             if (fwd) {
                 if (nr <= kWave) fwd2<T, 1>(w, nr, slot, rs, p0, P, xs, dv, rsl);
                 else if (nr <= 2 * kWave) fwd2<T, 2>(w, nr, slot, rs, p0, P, xs, dv, rsl);
                 else fwd2<T, 4>(w, nr, slot, rs, p0, P, xs, dv, rsl);
             } else {
-                if (nr <= kWave) bwd2<T, 1>(w, nr, slot, rs, p0, P, xs, dv, rsl);
-                else if (nr <= 2 * kWave) bwd2<T, 2>(w, nr, slot, rs, p0, P, xs, dv, rsl);
-                else bwd2<T, 4>(w, nr, slot, rs, p0, P, xs, dv, rsl);
+                if (nr <= kWave) bwd2<T, 1>(w, nr, slot, rs, p0, P, xs, rsl);
+                else if (nr <= 2 * kWave) bwd2<T, 2>(w, nr, slot, rs, p0, P, xs, rsl);
+                else bwd2<T, 4>(w, nr, slot, rs, p0, P, xs, rsl);
             }
         }
     }
