@@ -966,7 +966,7 @@ __host__ __device__ inline Tree2Lds tree2_layout(int nt, int esz, int nd, int nr
 // panel staging registers per thread (a level of at most NT * PR entries)
 template <typename T>
 __host__ __device__ constexpr int tree2_pr() {
-    return sizeof(T) == 4 ? 32 : 16;
+    return 32;
 }
 
 // columns per chunk of the column loops (register budget of 64 words)
