@@ -93,6 +93,30 @@ def test_hsolve_backward_error(case):
     assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_staged_tree_kernel_runs_and_solves(precision):
+    """The top levels of a grid-like pattern fit the staged tree kernel (its
+    launches are counted in their own profile class): H_gamma^{-1} b from it
+    has backward error 1e-14 on the dense H_gamma in FP64 (and matches the
+    oracle's solve), 1e-5 with the FP32 factor."""
+    b = H.tiny_grid_like(2500, 31, dx_exp=4.0)
+    s = _solver(b, precision=precision)
+    assert s.factor_batch(b)[0] == 0
+    rhs = np.random.default_rng(1).standard_normal((1, b.pattern.n_x))
+    s.profile_begin()
+    x = s.hsolve(rhs)[0]
+    prof = s.profile_end()
+    assert prof["tri_tree_staged"][1] >= 1 and prof["tri_tree"][1] == 0, prof
+    A = H.dense_Hgamma(b)
+    be = np.linalg.norm(A @ x - rhs[0]) / (np.linalg.norm(A, np.inf) * np.linalg.norm(x) + np.linalg.norm(rhs))
+    assert be < (1e-14 if precision == "fp64" else 1e-5), be
+    if precision == "fp64":   # same solution as the oracle's up to the conditioning of H_gamma
+        o = oracle.System.from_batch(b)
+        o.factor(o.order_mindeg())
+        xo = o.hsolve(rhs[0])
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
+
+
 def _check_solution(b, x, y, infos, kkt_tol=1e-10, ref_iters=None):
     for i in range(b.nb):
         o = oracle.System.from_batch(b, i)
