@@ -158,7 +158,7 @@ int hkkt_analyze_group(hkkt_ctx *ctx, int G, const int64_t *x_off, const int64_t
  * Cost per candidate (milliseconds, host clock around synchronised work):
  * with right-hand sides r1, r2 (as for hkkt_solve_batch; r2 may be NULL when
  * m = 0), one hkkt_factor_batch plus one hkkt_solve_batch of the nb
- * instances; with r1 = NULL a proxy: one factorization + one application of
+ * instances, the faster of two such runs; with r1 = NULL a proxy: one factorization + one application of
  * H_gamma^{-1} to all instances + four applications to a list of min(nb, 8)
  * instances (the late CG iterations run on few instances). The chosen relax
  * is written to the context's options and the pattern is re-analysed with
