@@ -1346,21 +1346,47 @@ __global__ void k_inv_diag(const i64* __restrict__ diag_off, i64 n, i64 Lsize, c
 // with g = gamma of the row's member if use_gamma else 1; a may be null.
 // Rows of members whose CG is done (st) are left alone.
 // ---------------------------------------------------------------------------
+// Dot product of CSR row entries [k0, k1) with a gathered vector, in entry
+// order (the same sum as a plain loop), with the index and value loads of
+// eight entries and then their eight gathers in flight at once instead of
+// one dependent gather per entry.
+template <typename TV>
+__device__ __forceinline__ double row_dot(i64 k0, i64 k1, const double* __restrict__ val,
+                                          const i32* __restrict__ col, const TV* __restrict__ x) {
+    double sum = 0.0;
+    for (i64 k = k0; k < k1; k += 8) {
+        double vv[8];
+        i32 cc[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const i64 kk = k + u < k1 ? k + u : k1 - 1;
+            vv[u] = val[kk];
+            cc[u] = col[kk];
+        }
+        TV xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) xv[u] = x[cc[u]];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (k + u < k1) sum += vv[u] * (double)xv[u];
+    }
+    return sum;
+}
+
 template <typename TO>
 __global__ void k_jt(SymView S, ValView V, const double* __restrict__ a, double scale, int use_gamma,
                      const double* __restrict__ v, TO* __restrict__ out, const int* ids, const CGState* st) {
     const int b = inst_of(ids, blockIdx.y);
-    if (S.G == 1 && st && st[b].done) return;
     const double* JT = V.JT + (i64)b * S.nnzJ;
     const double* vb = v + (i64)b * S.m;
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += (i64)gridDim.x * blockDim.x) {
+        // the convergence flag only gates the store: its load overlaps the others
         const i64 c = (i64)b * S.G + mem_x(S, i);
-        if (S.G > 1 && st && st[c].done) continue;
+        const bool done = st && st[c].done;
         const double sc = scale * (use_gamma ? V.gamma[c] : 1.0);
-        double sum = 0.0;
-        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) sum += JT[k] * vb[S.JT_col[k]];
+        const double sum = row_dot(S.JT_rowptr[i], S.JT_rowptr[i + 1], JT, S.JT_col, vb);
         const double base = a ? a[(i64)b * S.n + i] : 0.0;
-        out[(i64)b * S.n + i] = (TO)(base + sc * sum);
+        if (!done) out[(i64)b * S.n + i] = (TO)(base + sc * sum);
     }
 }
 
@@ -1388,14 +1414,15 @@ __global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __
     const int b = inst_of(ids, blockIdx.y);
     const Blk bk = blk_of(S.mblk, blockIdx.x);
     const i64 c = (i64)b * S.G + bk.k;
-    if (mode == 1 && st[c].done) return;
+    // the convergence flag (uniform in the block) only gates the stores: its
+    // load overlaps the row's loads
+    const bool done = mode == 1 && st[c].done;
     const double* J = V.J + (i64)b * S.nnzJ;
     const TI* ub = u + (i64)b * S.n;
     const i64 i = bk.lo + threadIdx.x;
     double a1 = 0.0, a2 = 0.0;
     if (i < bk.hi) {
-        double sum = 0.0;
-        for (i64 k = S.J_rowptr[i]; k < S.J_rowptr[i + 1]; k++) sum += J[k] * (double)ub[S.J_colp[k]];
+        double sum = row_dot(S.J_rowptr[i], S.J_rowptr[i + 1], J, S.J_colp, ub);
         if (mode == 0) {
             sum -= sub[(i64)b * S.m + i];
             a1 = sum * sum;
@@ -1405,8 +1432,9 @@ __global__ __launch_bounds__(kBlock) void k_j(SymView S, ValView V, const TI* __
             a1 = pi * sum;
             a2 = pi * pi;
         }
-        q[(i64)b * S.m + i] = sum;
+        if (!done) q[(i64)b * S.m + i] = sum;
     }
+    if (done) return;   // uniform in the block
     a1 = block_sum(a1, sh);
     if (mode == 1) a2 = block_sum(a2, sh);
     if (threadIdx.x == 0) {
