@@ -1493,9 +1493,12 @@ __global__ void k_cg_alpha(SymView S, CGState* st, const double* part1, const do
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
     const i64 ci = (i64)b * S.G + k;
-    if (st[ci].done) return;
+    // the flag (uniform in the block) is tested after the reductions' loads
+    // are out, not before them
+    const int done = st[ci].done;
     const double pq = reduce_member(part1, S.nbm, S.mblk_off, b, k, sh);
     const double pp = reduce_member(part2, S.nbm, S.mblk_off, b, k, sh);
+    if (done) return;
     if (threadIdx.x == 0) {
         CGState c = st[ci];
         if (c.curv0 < 0.0) c.curv0 = pq / pp;
@@ -1527,23 +1530,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(SymView S, const double* _
     const int b = inst_of(ids, blockIdx.y);
     const Blk bk = blk_of(S.mblk, blockIdx.x);
     const CGState* cs = st + (i64)b * S.G + bk.k;
-    if (cs->done) return;
+    // the state (uniform in the block) and the vectors are loaded together
+    const int done = cs->done, pad = cs->pad;
+    const double al = cs->alpha;
     const i64 i = bk.lo + threadIdx.x;
     double a = 0.0;
     if (i < bk.hi) {
         const i64 o = (i64)b * S.m + i;
-        double r;
-        if (cs->pad) {
-            y[o] = 0.0;
-            r = bvec[o];
-        } else {
-            const double al = cs->alpha;
-            y[o] += al * p[o];
-            r = res[o] - al * q[o];
+        const double pv = p[o], qv = q[o], yv = y[o], rv = res[o], bv = bvec[o];
+        const double r = pad ? bv : rv - al * qv;
+        if (!done) {
+            y[o] = pad ? 0.0 : yv + al * pv;
+            res[o] = r;
         }
-        res[o] = r;
         a = r * r;
     }
+    if (done) return;   // uniform in the block
     a = block_sum(a, sh);
     if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
 }
@@ -1552,8 +1554,9 @@ __global__ void k_cg_beta(SymView S, CGState* st, const double* part, double tol
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
     const i64 ci = (i64)b * S.G + k;
-    if (st[ci].done) return;
+    const int done = st[ci].done;
     const double r1 = reduce_member(part, S.nbm, S.mblk_off, b, k, sh);
+    if (done) return;   // uniform in the block
     if (threadIdx.x == 0) {
         CGState c = st[ci];
         if (c.pad) {
@@ -1577,11 +1580,13 @@ __global__ void k_cg_p(SymView S, double* __restrict__ p, const double* __restri
     const int b = inst_of(ids, blockIdx.y);
     const Blk bk = blk_of(S.mblk, blockIdx.x);
     const CGState* cs = st + (i64)b * S.G + bk.k;
-    if (cs->done) return;
+    const int done = cs->done;
+    const double be = cs->beta;
     const i64 i = bk.lo + threadIdx.x;
     if (i < bk.hi) {
         const i64 o = (i64)b * S.m + i;
-        p[o] = res[o] + cs->beta * p[o];
+        const double v = res[o] + be * p[o];
+        if (!done) p[o] = v;
     }
 }
 
