@@ -636,11 +636,25 @@ __device__ __forceinline__ T seg_allsum(T v) {
 
 // Value of lane jl of the segment in every lane of it. A 64-lane segment is
 // the whole wavefront, whose column loop runs in lockstep, so jl is uniform
-// and v_readlane serves; narrower segments use a lane permute (segments of a
-// tree-kernel wavefront may sit at different columns).
-template <typename T, int SEG>
+// and v_readlane serves. When every segment of the wavefront is at the same
+// column (U: the per-level kernels, whose segments share a supernode), lane
+// jl of each segment is read with v_readlane and each lane keeps its own
+// segment's value (a readlane is several times cheaper than a lane permute
+// through LDS); otherwise (segments of a tree-kernel wavefront may sit at
+// different columns) a lane permute.
+template <typename T, int SEG, bool U>
 __device__ __forceinline__ T seg_bcast(T v, int jl) {
     if (SEG == kWave) return lane_read(v, jl);
+    if (U) {
+        const int sg = (int)(threadIdx.x & (kWave - 1)) / SEG;
+        T r = lane_read(v, jl);
+#pragma unroll
+        for (int k = 1; k < kWave / SEG; k++) {
+            const T a = lane_read(v, jl + k * SEG);
+            r = sg == k ? a : r;
+        }
+        return r;
+    }
     return __shfl(v, jl, SEG);
 }
 
@@ -675,7 +689,7 @@ __device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ 
 // v enters as the right-hand side (rows of the diagonal block) or zero
 // (rows below) and leaves as the solution or the update for the rows below.
 // lc holds the first chunk of columns on entry.
-template <typename T, int SEG, int R, int CH, typename DT>
+template <typename T, int SEG, int R, int CH, bool U, typename DT>
 __device__ __forceinline__ void fwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di)[R], const T* __restrict__ Lb,
                                          const DT& d, int sl) {
     for (int j0 = 0; j0 < d.w; j0 += CH) {
@@ -689,7 +703,7 @@ __device__ __forceinline__ void fwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di
 #pragma unroll
                 for (int r = 1; r < R; r++)
                     if (r == jr) { vs = v[r]; es = di[r]; }
-                const T yj = seg_bcast<T, SEG>(vs * es, jl);      // y_j = v_j / L_jj, formed in lane jl
+                const T yj = seg_bcast<T, SEG, U>(vs * es, jl);      // y_j = v_j / L_jj, formed in lane jl
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const int row = sl + SEG * r;
@@ -705,7 +719,7 @@ __device__ __forceinline__ void fwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di
 // right-hand side on the diagonal rows and the known solution on the rows
 // below, and leaves with the solution on the diagonal rows. lc holds the
 // chunk [w - CH, w) on entry.
-template <typename T, int SEG, int R, int CH, typename DT>
+template <typename T, int SEG, int R, int CH, bool U, typename DT>
 __device__ __forceinline__ void bwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di)[R], const T* __restrict__ Lb,
                                          const DT& d, int sl) {
     for (int jhi = d.w; jhi > 0; jhi -= CH) {
@@ -724,7 +738,7 @@ __device__ __forceinline__ void bwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di
 #pragma unroll
                 for (int r = 1; r < R; r++)
                     if (r == jr) { vs = v[r]; es = di[r]; }
-                const T xj = seg_bcast<T, SEG>((vs - part) * es, jl);   // formed in lane jl
+                const T xj = seg_bcast<T, SEG, U>((vs - part) * es, jl);   // formed in lane jl
 #pragma unroll
                 for (int r = 0; r < R; r++)
                     if (sl + SEG * r == j) v[r] = xj;
@@ -733,7 +747,7 @@ __device__ __forceinline__ void bwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di
     }
 }
 
-template <typename T, int SEG, int R, bool PUSH>
+template <typename T, int SEG, int R, bool PUSH, bool U>
 __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
                                          const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X,
                                          T* __restrict__ UV) {
@@ -761,7 +775,7 @@ __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int
         v[r] = a;
         di[r] = e;
     }
-    fwd_cols<T, SEG, R, CH>(lc, v, di, Lb, d, sl);
+    fwd_cols<T, SEG, R, CH, U>(lc, v, di, Lb, d, sl);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -774,7 +788,7 @@ __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int
     }
 }
 
-template <typename T, int SEG, int R>
+template <typename T, int SEG, int R, bool U>
 __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
                                          const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X) {
     constexpr int CH = chunk_cols<T, SEG, R>();
@@ -796,7 +810,7 @@ __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int
         v[r] = a;
         di[r] = e;
     }
-    bwd_cols<T, SEG, R, CH>(lc, v, di, Lb, d, sl);
+    bwd_cols<T, SEG, R, CH, U>(lc, v, di, Lb, d, sl);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -824,7 +838,7 @@ __device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __rest
     const int b = valid ? inst_of(ids, k) : 0;
     const TriDesc d = desc[q];
     if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-    fwd_body<T, SEG, R, PUSH>(S, d, b, valid, L, Dinv, X, UV);
+    fwd_body<T, SEG, R, PUSH, true>(S, d, b, valid, L, Dinv, X, UV);
 }
 
 template <typename T, int SEG, int R>
@@ -841,7 +855,7 @@ __device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __rest
     const int b = valid ? inst_of(ids, k) : 0;
     const TriDesc d = desc[q];
     if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-    bwd_body<T, SEG, R>(S, d, b, valid, L, Dinv, X);
+    bwd_body<T, SEG, R, true>(S, d, b, valid, L, Dinv, X);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,7 +886,7 @@ __device__ __forceinline__ void fwd_tree_class(const SymView& S, const TriDesc* 
         bool valid = q < cnt;
         const TriDesc d = desc[valid ? q : cnt - 1];
         if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-        fwd_body<T, SEG, R, PUSH>(S, d, b, valid, L, Dinv, X, UV);
+        fwd_body<T, SEG, R, PUSH, false>(S, d, b, valid, L, Dinv, X, UV);
     }
 }
 
@@ -888,7 +902,7 @@ __device__ __forceinline__ void bwd_tree_class(const SymView& S, const TriDesc* 
         bool valid = q < cnt;
         const TriDesc d = desc[valid ? q : cnt - 1];
         if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-        bwd_body<T, SEG, R>(S, d, b, valid, L, Dinv, X);
+        bwd_body<T, SEG, R, false>(S, d, b, valid, L, Dinv, X);
     }
 }
 
