@@ -32,6 +32,12 @@
  *    value/vector pointers are host or device (device = on the context's
  *    device, e.g. a torch tensor's data_ptr()). Pattern arrays given to
  *    hkkt_analyze are always host pointers and are copied.
+ *  - The context owns its device memory: the symbolic tables, the factor (per
+ *    instance, L storage entries in the factor's precision), the
+ *    contribution-block and solve workspaces, and, for the staged
+ *    tree-traversal solves, a solve copy of the top levels' panels built at
+ *    the first triangular solve after each factorization. It grows on demand
+ *    and is freed by hkkt_destroy.
  *  - Work is enqueued on the stream given to hkkt_create; entry points return
  *    after their outputs are written (factor: after its one status read;
  *    solve: after x and y are written).
