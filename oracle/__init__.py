@@ -23,7 +23,10 @@ f64p = C.POINTER(C.c_double)
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        # -ffp-contract=off: the compensated residual's error-free
+        # transformations need every product and sum rounded on its own
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp,
+                               _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -67,6 +70,9 @@ def lib():
         L.orc_hybrid_once.restype = C.c_int64
         L.orc_hybrid_once.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.POINTER(C.c_int)]
         L.orc_apply_K.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
+        L.orc_residual.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p, f64p, f64p, f64p, f64p]
+        L.orc_refine_dd.restype = C.c_int64
+        L.orc_refine_dd.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.c_int64, f64p]
         _lib = L
     return _lib
 
@@ -185,6 +191,29 @@ class System:
         it = lib().orc_hybrid_once(self._h, C.byref(o), _p(r1, f64p), _p(r2, f64p), _p(x, f64p),
                                    _p(y, f64p), C.byref(brk))
         return x, y, int(it), bool(brk.value)
+
+    def residual(self, r1, r2, x, y):
+        """Compensated r - K z and the per-row sums |r_i| + sum |term|."""
+        a = [_c(v, np.float64) for v in (r1, r2, x, y)]
+        g1, t1 = np.empty(self.n), np.empty(self.n)
+        g2, t2 = np.empty(self.m), np.empty(self.m)
+        lib().orc_residual(self._h, *[_p(v, f64p) for v in a], _p(g1, f64p), _p(g2, f64p), _p(t1, f64p),
+                           _p(t2, f64p))
+        return g1, g2, t1, t2
+
+    def refine_dd(self, r1, r2, x, y, max_steps=8, **kw):
+        """Refinement with a double-double iterate started at (x, y): returns
+        (x, y) = the exact solution rounded to FP64 (to the accuracy reached)
+        and the history of ||r - K z_dd|| / ||r||."""
+        r1 = _c(r1, np.float64)
+        r2 = _c(r2, np.float64)
+        x = np.array(x, np.float64)
+        y = np.array(y, np.float64)
+        hist = np.zeros(max_steps + 1)
+        o = self._opts(**kw)
+        k = lib().orc_refine_dd(self._h, C.byref(o), _p(r1, f64p), _p(r2, f64p), _p(x, f64p), _p(y, f64p),
+                                int(max_steps), _p(hist, f64p))
+        return x, y, hist[:k + 1]
 
     def apply_K(self, x, y):
         x = _c(x, np.float64)

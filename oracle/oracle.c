@@ -25,11 +25,28 @@
  * Readings where the paper is silent (each also listed in the design notes):
  *  - CG starts from y = 0 and stops when ||res||_2 <= cg_tol * ||b||_2
  *    (Sec. 5.1: relative residual tolerance 1e-12), or after max_cg steps.
- *  - "small quadratic form" (Algorithm 1): p'q <= qf_eps*||p||^2*(p0'q0/||p0||^2).
+ *  - Algorithm 1's breakdown test on the quadratic form has no threshold in
+ *    the paper: breakdown when p'q <= qf_eps*||p||^2*(p0'q0/||p0||^2).
  *  - refinement: while RR > kkt_tol and steps < max_refine: solve K e = res by
  *    the same hybrid steps, z += e, recompute res = r - K z.
  *  - inertia of K after a successful Cholesky of H_gamma and CG without
  *    breakdown: (n_x, m, 0) (Sec. 4.2, Theorem 3; congruence + Haynsworth).
+ *    After a breakdown only the n_x positive eigenvalues are determined: the
+ *    other m split between negative and at least one zero (reported as -1).
+ *  - the KKT residual r - K z that RR, BE and refinement use is evaluated
+ *    with compensated dot products (error-free TwoProduct by FMA and TwoSum,
+ *    Ogita, Rump and Oishi 2005, "Accurate sum and dot product", algorithm
+ *    Dot2), every product of a stored value with an entry of z a term of its
+ *    own (K's diagonal is H_ii + D_i + delta, three terms), so the residual
+ *    is as accurate as if computed in twice the working precision: the plain
+ *    FP64 sum has an error near u * || |K||z| + |r| || (the "floor"), which
+ *    on these inputs can exceed the 1e-10 target itself.
+ *  - the best RR any FP64 z can be expected to reach is that of the
+ *    correctly rounded exact solution; orc_refine_dd computes it by
+ *    refinement with z held as an unevaluated sum of two doubles.
+ *
+ * Build with -ffp-contract=off: the error-free transformations need every
+ * product and sum rounded on its own.
  */
 #include <math.h>
 #include <stdint.h>
@@ -240,7 +257,8 @@ void orc_order_mindeg(const orc *s, i32 *perm) {
 /* ------------------------------------------------------------------ */
 /* left-looking column Cholesky  P H_gamma P^T = L L^T                  */
 /* (Cholesky is stable without pivoting, Sec. 3; a non-positive or       */
-/*  non-finite pivot means H_gamma is not SPD: Algorithm 1's "Fail")     */
+/*  non-finite pivot means H_gamma is not SPD, the failed-factorization  */
+/*  branch of Algorithm 1)                                               */
 /* ------------------------------------------------------------------ */
 
 static int cmp_i32(const void *a, const void *b) { i32 x = *(const i32 *)a, y = *(const i32 *)b; return (x > y) - (x < y); }
@@ -393,17 +411,104 @@ static void H_mul(const orc *s, const double *v, double *out) {          /* out 
 static double dot(const double *a, const double *b, i64 n) { double s = 0.0; for (i64 i = 0; i < n; i++) s += a[i] * b[i]; return s; }
 static double nrm2(const double *a, i64 n) { return sqrt(dot(a, a, n)); }
 
-/* res = r - K z;  K = [H + D_x + delta I, J^T; J, 0] */
+/* ------------------------------------------------------------------ */
+/* compensated residual (Ogita, Rump, Oishi 2005: TwoSum, TwoProduct by  */
+/* FMA, Dot2). Each row keeps an unevaluated sum hi + lo; a term a*b is  */
+/* split exactly into fl(a*b) + err and both parts are accumulated, so   */
+/* the rounded row sum is within about u of the exact one.               */
+/* ------------------------------------------------------------------ */
+
+/* a + b = *s + *e exactly (Knuth's TwoSum, no ordering assumption) */
+static void two_sum(double a, double b, double *s, double *e) {
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+/* a * b = *p + *e exactly (FMA form of TwoProduct) */
+static void two_prod(double a, double b, double *p, double *e) {
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+typedef struct { double hi, lo; } acc2;
+
+/* acc += a * b (Dot2 step: the product's error and the sum's error both go
+ * to the low part) */
+static void acc_fma(acc2 *c, double a, double b) {
+    double p, ep, s, es;
+    two_prod(a, b, &p, &ep);
+    two_sum(c->hi, p, &s, &es);
+    c->hi = s;
+    c->lo += es + ep;
+}
+
+static void acc_add(acc2 *c, double a) {
+    double s, es;
+    two_sum(c->hi, a, &s, &es);
+    c->hi = s;
+    c->lo += es;
+}
+
+/* res = r - K (z + z_lo), K = [H + D_x + delta I, J^T; J, 0], row by row with
+ * compensated sums (z_lo = the low parts of a double-double iterate, or
+ * NULL); t (if non-NULL) gets per row |r_i| + the sum of |term| over the
+ * row's terms (|K||z| + |r| when diag(H) >= 0, which makes every diagonal
+ * term of K of one sign). */
+static void residual_comp(const orc *s, const double *r1, const double *r2, const double *x, const double *y,
+                          const double *xl, const double *yl, double *res1, double *res2, double *t1, double *t2) {
+    i64 n = s->n, m = s->m;
+    acc2 *a1 = xcalloc((size_t)(n ? n : 1), sizeof(acc2)), *a2 = xcalloc((size_t)(m ? m : 1), sizeof(acc2));
+    double *f1 = xcalloc((size_t)(n ? n : 1), sizeof(double)), *f2 = xcalloc((size_t)(m ? m : 1), sizeof(double));
+    for (i64 i = 0; i < n; i++) { a1[i].hi = r1[i]; f1[i] = fabs(r1[i]); }
+    for (i64 i = 0; i < m; i++) { a2[i].hi = r2[i]; f2[i] = fabs(r2[i]); }
+    /* H (tril stored; the upper entries are the transposes) */
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+            i64 j = s->Hi[p];
+            double h = s->Hx[p];
+            acc_fma(&a1[i], -h, x[j]); f1[i] += fabs(h * x[j]);
+            if (xl) acc_fma(&a1[i], -h, xl[j]);
+            if (j != i) {
+                acc_fma(&a1[j], -h, x[i]); f1[j] += fabs(h * x[i]);
+                if (xl) acc_fma(&a1[j], -h, xl[i]);
+            }
+        }
+    /* D_x and delta on the diagonal, each a term of its own */
+    for (i64 i = 0; i < n; i++) {
+        acc_fma(&a1[i], -s->Dx[i], x[i]); f1[i] += fabs(s->Dx[i] * x[i]);
+        acc_fma(&a1[i], -s->delta, x[i]); f1[i] += fabs(s->delta * x[i]);
+        if (xl) { acc_fma(&a1[i], -s->Dx[i], xl[i]); acc_fma(&a1[i], -s->delta, xl[i]); }
+    }
+    /* J^T y into the first block, J x into the second */
+    for (i64 k = 0; k < m; k++)
+        for (i64 p = s->Jp[k]; p < s->Jp[k + 1]; p++) {
+            i64 j = s->Ji[p];
+            double v = s->Jx[p];
+            acc_fma(&a1[j], -v, y[k]); f1[j] += fabs(v * y[k]);
+            acc_fma(&a2[k], -v, x[j]); f2[k] += fabs(v * x[j]);
+            if (yl) acc_fma(&a1[j], -v, yl[k]);
+            if (xl) acc_fma(&a2[k], -v, xl[j]);
+        }
+    for (i64 i = 0; i < n; i++) res1[i] = a1[i].hi + a1[i].lo;
+    for (i64 i = 0; i < m; i++) res2[i] = a2[i].hi + a2[i].lo;
+    if (t1) memcpy(t1, f1, sizeof(double) * (size_t)n);
+    if (t2) memcpy(t2, f2, sizeof(double) * (size_t)m);
+    free(a1); free(a2); free(f1); free(f2);
+}
+
+/* res = r - K z (compensated) */
 static void kkt_residual(const orc *s, const double *r1, const double *r2, const double *x, const double *y,
                          double *res1, double *res2) {
-    i64 n = s->n, m = s->m;
-    double *hx = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
-    double *jty = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
-    double *jx = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
-    H_mul(s, x, hx); JT_mul(s, y, jty); J_mul(s, x, jx);
-    for (i64 j = 0; j < n; j++) res1[j] = r1[j] - (hx[j] + (s->Dx[j] + s->delta) * x[j] + jty[j]);
-    for (i64 i = 0; i < m; i++) res2[i] = r2[i] - jx[i];
-    free(hx); free(jty); free(jx);
+    residual_comp(s, r1, r2, x, y, NULL, NULL, res1, res2, NULL, NULL);
+}
+
+/* exposed for the pins: the compensated residual and the per-row term sums */
+void orc_residual(const orc *s, const double *r1, const double *r2, const double *x, const double *y,
+                  double *res1, double *res2, double *t1, double *t2) {
+    residual_comp(s, r1, r2, x, y, NULL, NULL, res1, res2, t1, t2);
 }
 
 /* ||K||_inf: max row sum of |K| */
@@ -429,31 +534,18 @@ static double kkt_norm_inf(const orc *s) {
     return mx;
 }
 
-/* RR, BE (Sec. 5.1, ||K||_inf for ||K||_2) and the FP64 evaluation floor
- * u * || |K||z| + |r| ||_2 / ||r||_2 (u = 2^-53). */
+/* RR, BE (Sec. 5.1, ||K||_inf for ||K||_2) of the compensated residual, and
+ * the plain FP64 evaluation floor u * || |K||z| + |r| ||_2 / ||r||_2
+ * (u = 2^-53; |K||z| summed term by term as above). */
 void orc_metrics(orc *s, const double *r1, const double *r2, const double *x, const double *y, double *out3) {
     i64 n = s->n, m = s->m;
     double *a = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *b = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
-    kkt_residual(s, r1, r2, x, y, a, b);
+    double *f1 = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *f2 = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    residual_comp(s, r1, r2, x, y, NULL, NULL, a, b, f1, f2);
     double rn = sqrt(dot(a, a, n) + dot(b, b, m));
     double bn = sqrt(dot(r1, r1, n) + dot(r2, r2, m));
     double zn = sqrt(dot(x, x, n) + dot(y, y, m));
     double kn = kkt_norm_inf(s);
-    /* |K||z| + |r| */
-    double *f1 = xcalloc((size_t)(n ? n : 1), sizeof(double)), *f2 = xcalloc((size_t)(m ? m : 1), sizeof(double));
-    for (i64 i = 0; i < n; i++)
-        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
-            i64 j = s->Hi[p];
-            f1[i] += fabs(s->Hx[p] * x[j]);
-            if (j != i) f1[j] += fabs(s->Hx[p] * x[i]);
-        }
-    for (i64 i = 0; i < n; i++) f1[i] += fabs((s->Dx[i] + s->delta) * x[i]) + fabs(r1[i]);
-    for (i64 i = 0; i < m; i++)
-        for (i64 p = s->Jp[i]; p < s->Jp[i + 1]; p++) {
-            f1[s->Ji[p]] += fabs(s->Jx[p] * y[i]);
-            f2[i] += fabs(s->Jx[p] * x[s->Ji[p]]);
-        }
-    for (i64 i = 0; i < m; i++) f2[i] += fabs(r2[i]);
     double fl = ldexp(1.0, -53) * sqrt(dot(f1, f1, n) + dot(f2, f2, m));
     out3[0] = bn > 0 ? rn / bn : rn;
     out3[1] = rn / (kn * zn + bn);
@@ -522,7 +614,8 @@ static i64 hybrid_pass(const orc *s, const orc_opts *o, const double *r1, const 
             double pq = dot(p, q, m), pp = dot(p, p, m);
             if (curv0 < 0.0) curv0 = pq / pp;
             if (!(pq > o->qf_eps * pp * curv0)) {
-                /* small quadratic form (Algorithm 1): restart on S + delta2 I */
+                /* quadratic form below the threshold (Algorithm 1's breakdown
+                 * test): restart on S + delta2 I */
                 *breakdown = 1;
                 if (o->delta2 > 0.0 && d2 == 0.0) {
                     d2 = o->delta2;
@@ -562,7 +655,7 @@ int orc_solve(orc *s, const orc_opts *o, const double *r1, const double *r2, dou
     i64 max_ref = o->max_refine > 0 ? o->max_refine : 10;
     if (max_ref > 15) max_ref = 15;
     int brk_any = 0;
-    double rr = rn > 0 ? 1.0 : 0.0;
+    double rr = rn > 0 ? 1.0 : 0.0, rr_best = INFINITY;
     i64 pass = 0;
     while (pass <= max_ref) {
         int brk = 0;
@@ -576,15 +669,64 @@ int orc_solve(orc *s, const orc_opts *o, const double *r1, const double *r2, dou
         rep->rr_hist[pass] = rr;
         pass++;
         if (rr <= o->kkt_tol || brk) break;
+        /* a later pass that does not halve RR: z is as close to the exact
+         * solution as FP64 entries allow (the residual of the rounded
+         * solution is of the order of the floor) */
+        if (pass >= 2 && !(rr < 0.5 * rr_best)) break;
+        if (rr < rr_best) rr_best = rr;
     }
     rep->passes = pass;
     double mt[3];
     orc_metrics(s, r1, r2, x, y, mt);
     rep->rr = mt[0]; rep->be = mt[1]; rep->floor = mt[2];
-    rep->inertia[0] = n; rep->inertia[1] = brk_any ? m - 1 : m; rep->inertia[2] = brk_any ? 1 : 0;
+    /* Theorem 3 with congruence + Haynsworth: n_x positive eigenvalues from the
+     * Cholesky of H_gamma; the rest are those of -S, negative unless J is
+     * rank-deficient. A breakdown shows S singular (or nearly so) but not its
+     * nullity, so negative and zero counts are then left undetermined (-1). */
+    rep->inertia[0] = n; rep->inertia[1] = brk_any ? -1 : m; rep->inertia[2] = brk_any ? -1 : 0;
     rep->status = brk_any && o->delta2 == 0.0 ? 2 : (rr <= o->kkt_tol ? 0 : 3);
     free(ex); free(ey); free(g1); free(g2);
     return (int)rep->status;
+}
+
+/* Refinement with the iterate held as an unevaluated sum z + z_lo of two
+ * doubles (z_lo starts at 0): each step evaluates g = r - K (z + z_lo) with
+ * compensated sums, takes the correction e from one hybrid pass on g, and
+ * adds it with TwoSum per entry, renormalised so that z = fl(z + z_lo). The
+ * steps stop after max_steps or when ||g|| no longer halves. On return
+ * (x, y) = z, the exact solution rounded to FP64 up to the accuracy the
+ * steps reached; hist[k] = ||g|| / ||r|| before step k (max_steps + 1
+ * entries). Returns the number of steps taken. */
+i64 orc_refine_dd(orc *s, const orc_opts *o, const double *r1, const double *r2, double *x, double *y,
+                  i64 max_steps, double *hist) {
+    i64 n = s->n, m = s->m;
+    if (!s->factored) return -3;
+    double *xl = xcalloc((size_t)(n ? n : 1), sizeof(double)), *yl = xcalloc((size_t)(m ? m : 1), sizeof(double));
+    double *ex = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *ey = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *g1 = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *g2 = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double rn = sqrt(dot(r1, r1, n) + dot(r2, r2, m));
+    if (!(rn > 0)) rn = 1.0;
+    double prev = INFINITY;
+    i64 k = 0;
+    for (;; k++) {
+        residual_comp(s, r1, r2, x, y, xl, yl, g1, g2, NULL, NULL);
+        double g = sqrt(dot(g1, g1, n) + dot(g2, g2, m)) / rn;
+        if (hist) hist[k] = g;
+        if (k >= max_steps || !(g < 0.5 * prev) || g == 0.0) break;
+        prev = g;
+        int brk = 0;
+        hybrid_pass(s, o, g1, g2, ex, ey, &brk);
+        for (i64 j = 0; j < n + m; j++) {
+            double *hi = j < n ? &x[j] : &y[j - n], *lo = j < n ? &xl[j] : &yl[j - n];
+            double e = j < n ? ex[j] : ey[j - n];
+            double sh, sl;
+            two_sum(*hi, e, &sh, &sl);
+            sl += *lo;
+            two_sum(sh, sl, hi, lo);   /* renormalise: hi = fl(sh + sl) */
+        }
+    }
+    free(xl); free(yl); free(ex); free(ey); free(g1); free(g2);
+    return k;
 }
 
 /* single hybrid pass without refinement (for CG-count and Theorem 4 tests) */

@@ -371,7 +371,32 @@ def test_inertia_duplicate_row_reports_breakdown():
     ev = np.linalg.eigvalsh(K)
     want = _sign_counts(ev, 1e-9 * np.abs(ev).max())
     assert want == (n, m - 1, 1)
-    assert info["status"] == 2 and info["inertia"] == want
+    # the breakdown shows a zero eigenvalue but not how many: only the n_x
+    # positive ones (Cholesky of H_gamma) are reported, the rest undetermined
+    assert info["status"] == 2 and info["inertia"] == (n, -1, -1)
+    assert info["inertia"][0] == want[0] and want[2] >= 1
+
+
+def test_inertia_two_duplicate_rows_undetermined():
+    # rank(J) = m - 2: K has two zero eigenvalues; a breakdown alone cannot
+    # count them, so the oracle must not claim exactly one
+    rng = np.random.default_rng(74)
+    n, m = 18, 6
+    J = rng.standard_normal((m, n))
+    J[3] = J[1]
+    J[5] = 2.0 * J[0]
+    B = rng.standard_normal((n, n))
+    Hd = B.T @ B / n
+    Dx = 10 ** rng.uniform(-1, 1, n)
+    r1 = rng.standard_normal(n); r2 = rng.standard_normal(m)
+    b = H.batch_from_dense(Hd, Dx, J, 0.0, 1e2, r1, r2)
+    s = _sys(b)
+    assert s.factor(None)[0] == 0
+    x, y, info = s.solve(r1, r2)
+    ev = np.linalg.eigvalsh(H.dense_K(b))
+    want = _sign_counts(ev, 1e-9 * np.abs(ev).max())
+    assert want == (n, m - 2, 2)
+    assert info["status"] == 2 and info["inertia"] == (n, -1, -1)
 
 
 def test_theorem1_gamma_threshold():
@@ -418,9 +443,9 @@ def test_metrics_equal_dense_definitions():
     r = np.concatenate([b.r1[0], b.r2[0]])
     z = np.concatenate([x, y])
     res = np.linalg.norm(K @ z - r)
-    assert rr == pytest.approx(res / np.linalg.norm(r), rel=1e-12)
+    assert rr == pytest.approx(res / np.linalg.norm(r), rel=1e-12, abs=0)
     assert be == pytest.approx(res / (np.linalg.norm(K, np.inf) * np.linalg.norm(z) + np.linalg.norm(r)),
-                               rel=1e-12)
+                               rel=1e-12, abs=0)
     o1, o2 = s.apply_K(x, y)
     np.testing.assert_allclose(np.concatenate([o1, o2]), K @ z, rtol=1e-13, atol=1e-13 * np.abs(K @ z).max())
 
@@ -454,3 +479,199 @@ def test_single_pass_is_exact(gen, seed):
     assert np.linalg.norm(K @ z - r) / np.linalg.norm(r) < 1e-9
     xs, ys, info = s.solve(b.r1[0], b.r2[0])
     assert info["passes"] <= 2
+
+
+# --------------------------------------------------------------------------
+# compensated residual, evaluation floor and the rounded exact solution
+# (Sec. 5.1 RR; Ogita-Rump-Oishi Dot2 for the residual)
+# --------------------------------------------------------------------------
+
+U = 2.0 ** -53
+
+
+def _exact_residual(b, x, y):
+    """r - K z in exact rational arithmetic on the FP64 inputs, with K's
+    diagonal H_ii + D_i + delta summed exactly."""
+    from fractions import Fraction as F
+    p = b.pattern
+    n, m = p.n_x, p.m
+    X = [F(float(v)) for v in x]
+    Y = [F(float(v)) for v in y]
+    g1 = [F(float(v)) for v in b.r1[0]]
+    g2 = [F(float(v)) for v in b.r2[0]]
+    for i in range(n):
+        for k in range(p.H_rowptr[i], p.H_rowptr[i + 1]):
+            j = int(p.H_col[k])
+            h = F(float(b.H_val[0, k]))
+            g1[i] -= h * X[j]
+            if j != i:
+                g1[j] -= h * X[i]
+        g1[i] -= (F(float(b.D_x[0, i])) + F(float(b.delta[0]))) * X[i]
+    for r in range(m):
+        for k in range(p.J_rowptr[r], p.J_rowptr[r + 1]):
+            j = int(p.J_col[k])
+            v = F(float(b.J_val[0, k]))
+            g1[j] -= v * Y[r]
+            g2[r] -= v * X[j]
+    return g1, g2
+
+
+def _row_terms(b):
+    p = b.pattern
+    nt = np.full(p.n_x, 3)                       # r_i, D_i x_i, delta x_i
+    for i in range(p.n_x):
+        for k in range(p.H_rowptr[i], p.H_rowptr[i + 1]):
+            j = int(p.H_col[k])
+            nt[i] += 1
+            if j != i:
+                nt[j] += 1
+    for k in range(p.J_rowptr[-1]):
+        nt[p.J_col[k]] += 1
+    nt2 = np.diff(p.J_rowptr) + 1
+    return nt, nt2
+
+
+@pytest.mark.parametrize("gen,seed", [("grid", 101), ("dense", 102), ("grid", 103)])
+def test_compensated_residual_equals_exact(gen, seed):
+    # z = the oracle's own solution: r - K z cancels to ~1e-14 of the terms,
+    # where a plain FP64 sum is wrong in its leading digits; Dot2 keeps
+    # |res - exact| <= u |exact| + (k u)^2 sum|terms| (k terms in the row)
+    b = H.tiny_dense_like(30, seed, dx_exp=6.0) if gen == "dense" else H.tiny_grid_like(40, seed, dx_exp=8.0)
+    s = _sys(b)
+    s.factor(s.order_mindeg())
+    x, y, info = s.solve(b.r1[0], b.r2[0])
+    g1, g2, t1, t2 = s.residual(b.r1[0], b.r2[0], x, y)
+    e1, e2 = _exact_residual(b, x, y)
+    nt1, nt2 = _row_terms(b)
+    for got, ex, t, k in ((g1, e1, t1, nt1), (g2, e2, t2, nt2)):
+        for i in range(len(got)):
+            bound = 2 * U * abs(float(ex[i])) + 2 * (k[i] * U) ** 2 * t[i]
+            assert abs(got[i] - float(ex[i])) <= bound, (i, got[i], float(ex[i]), t[i])
+    # the cancellation is real: the plain FP64 residual would be off by far more
+    K = H.dense_K(b)
+    plain = np.concatenate([b.r1[0], b.r2[0]]) - K @ np.concatenate([x, y])
+    exact = np.array([float(v) for v in e1 + e2])
+    assert np.abs(plain - exact).max() > 1e3 * np.abs(np.concatenate([g1, g2]) - exact).max()
+
+
+@pytest.mark.parametrize("gen,seed,spread", [("grid", 111, 0.0), ("dense", 112, 0.0), ("grid", 113, 4.0)])
+def test_floor_equals_dense_definition(gen, seed, spread):
+    # floor = 2^-53 || |K||z| + |r| ||_2 / ||r||_2 (diag(H) >= 0 here, so the
+    # term-wise sums equal |K||z|), checked densely and in exact arithmetic;
+    # spread 0 keeps both block rows of K of the same weight, so that a
+    # dropped term of either shows
+    from fractions import Fraction as F
+    dx = 1.0 if spread == 0.0 else 8.0
+    b = H.tiny_dense_like(24, seed, dx_exp=dx) if gen == "dense" else H.tiny_grid_like(30, seed, dx_exp=dx)
+    assert np.all(np.diag(H.dense_H(b)) >= 0)
+    rng = np.random.default_rng(seed)
+    n, m = b.pattern.n_x, b.pattern.m
+    x = rng.standard_normal(n) * 10 ** rng.uniform(-spread, spread, n)
+    y = rng.standard_normal(m) * 10 ** rng.uniform(-spread, spread, m)
+    s = _sys(b)
+    rr, be, fl = s.metrics(b.r1[0], b.r2[0], x, y)
+    K = H.dense_K(b)
+    r = np.concatenate([b.r1[0], b.r2[0]])
+    z = np.concatenate([x, y])
+    t = np.abs(K) @ np.abs(z) + np.abs(r)
+    assert fl == pytest.approx(U * np.linalg.norm(t) / np.linalg.norm(r), rel=1e-13, abs=0)
+    _, _, t1, t2 = s.residual(b.r1[0], b.r2[0], x, y)
+    np.testing.assert_allclose(np.concatenate([t1, t2]), t, rtol=1e-13)
+    # exact: sum of squares in rationals, one square root in FP64 at the end
+    Kf = [[F(float(v)) for v in row] for row in np.abs(K)]
+    zf = [F(float(abs(v))) for v in z]
+    tf = [sum(Kf[i][j] * zf[j] for j in range(n + m)) + F(float(abs(r[i]))) for i in range(n + m)]
+    want = U * np.sqrt(float(sum(v * v for v in tf))) / np.sqrt(float(sum(F(float(v)) ** 2 for v in r)))
+    assert fl == pytest.approx(want, rel=1e-14, abs=0)
+
+
+def _exact_K(b):
+    """K in rationals from the FP64 inputs (diagonal H_ii + D_i + delta exact)."""
+    from fractions import Fraction as F
+    n, m = b.pattern.n_x, b.pattern.m
+    Hd, J = H.dense_H(b), H.dense_J(b)
+    K = [[F(0)] * (n + m) for _ in range(n + m)]
+    for i in range(n):
+        for j in range(n):
+            K[i][j] = F(float(Hd[i, j]))
+        K[i][i] += F(float(b.D_x[0, i])) + F(float(b.delta[0]))
+    for r in range(m):
+        for j in range(n):
+            K[n + r][j] = K[j][n + r] = F(float(J[r, j]))
+    return K
+
+
+def _exact_solve(K, r):
+    """Gauss-Jordan elimination in rationals."""
+    from fractions import Fraction as F
+    N = len(K)
+    A = [list(K[i]) + [F(float(r[i]))] for i in range(N)]
+    for c in range(N):
+        p = next(i for i in range(c, N) if A[i][c] != 0)
+        A[c], A[p] = A[p], A[c]
+        for i in range(N):
+            if i != c and A[i][c] != 0:
+                f = A[i][c] / A[c][c]
+                A[i] = [a - f * bb for a, bb in zip(A[i], A[c])]
+    return [A[i][N] / A[i][i] for i in range(N)]
+
+
+@pytest.mark.parametrize("seed", [121, 122])
+def test_refine_dd_rounds_the_exact_solution(seed):
+    # a badly scaled system (D_x over 12 decades): the double-double
+    # refinement must return the exact solution rounded to FP64, and the RR
+    # it reports must be that of the rounded solution in exact arithmetic
+    rng = np.random.default_rng(seed)
+    n, m = 9, 4
+    B = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.4)
+    Hd = B.T @ B
+    Dx = 10 ** rng.uniform(-6, 6, n)
+    J = rng.standard_normal((m, n)) * (rng.random((m, n)) < 0.5)
+    J[np.arange(m), 2 * np.arange(m)] = 1.0
+    r1 = rng.standard_normal(n); r2 = rng.standard_normal(m)
+    b = H.batch_from_dense(Hd, Dx, J, 1e-8, 1e4, r1, r2)
+    s = _sys(b)
+    s.factor(None)
+    x, y, info = s.solve(r1, r2)
+    xr, yr, hist = s.refine_dd(r1, r2, x, y)
+    zs = _exact_solve(_exact_K(b), np.concatenate([r1, r2]))
+    got = np.concatenate([xr, yr])
+    want = np.array([float(v) for v in zs])       # correctly rounded
+    ulps = np.abs(got - want) / np.spacing(np.abs(want))
+    assert ulps.max() <= 1.0, ulps
+    assert hist[-1] < 1e-25
+    e1, e2 = _exact_residual(b, xr, yr)
+    rr_exact = np.sqrt(float(sum(v * v for v in e1 + e2))) / np.linalg.norm(np.concatenate([r1, r2]))
+    rr, _, _ = s.metrics(r1, r2, xr, yr)
+    assert rr == pytest.approx(rr_exact, rel=1e-12, abs=0)
+
+
+def _mindeg_bruteforce(A):
+    """Minimum degree on the explicit elimination graph, ties to the smallest
+    index, by sets (tiny inputs)."""
+    n = A.shape[0]
+    adj = [set(np.nonzero(A[i])[0].tolist()) - {i} for i in range(n)]
+    alive = set(range(n))
+    perm = []
+    while alive:
+        v = min(alive, key=lambda u: (len(adj[u]), u))
+        nb = adj[v]
+        for u in nb:
+            adj[u] |= nb
+            adj[u] -= {u, v}
+        alive.remove(v)
+        for u in range(n):
+            adj[u].discard(v)
+        perm.append(v)
+    return perm
+
+
+@pytest.mark.parametrize("gen,seed", [("grid", 131), ("dense", 132), ("grid", 133)])
+def test_order_is_exact_minimum_degree(gen, seed):
+    b = H.tiny_dense_like(40, seed) if gen == "dense" else H.tiny_grid_like(60, seed)
+    s = _sys(b)
+    cp, ri, v = s.hgamma()
+    n = b.pattern.n_x
+    A = H.csc_to_dense_lower(cp, ri, np.ones_like(v), n) != 0
+    A = A | A.T
+    assert s.order_mindeg().tolist() == _mindeg_bruteforce(A)
