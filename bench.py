@@ -79,11 +79,15 @@ def run_gpu(args):
     H, D, J, R1, R2 = dev(b.H_val), dev(b.D_x), dev(b.J_val), dev(b.r1), dev(b.r2)
 
     tuned = {}
+    given = {"mixed": args.schedule_mixed, "fp64": args.schedule_fp64}
 
     def make(prec, tune=False):
         s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10)
         s.analyze(b.pattern)
-        if tune:   # once per pattern, outside the timed region (like the analysis)
+        if given.get(prec):   # a schedule from an earlier autotuning (profiler runs)
+            s.set_schedule(*[int(v) for v in given[prec].split(",")])
+            tuned[prec] = dict(zip(("relax", "tree_width", "tree_staged"), s.schedule()), given=True)
+        elif tune:   # once per pattern, outside the timed region (like the analysis)
             r = s.autotune(H, D, J, b.delta, b.gamma, R1, R2)
             tuned[prec] = {"relax": r["relax"], "tree_width": r["tree_width"], "tree_staged": r["tree_staged"]}
         return s
@@ -92,24 +96,35 @@ def run_gpu(args):
         rc, st, fc = s.factor(h, d, j, delta, gamma)
         rc2, x, y, infos = s.solve(r1, r2)
         s.last_infos = infos
+        s.last_xy = (x, y)
         return infos
 
     s = make("mixed", tune=not args.no_autotune)
     for _ in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
+    # the timed steps, with per-kernel HIP events recorded on the library's
+    # stream around every launch (the roofline's kernel durations); with
+    # --events-after, one extra identical step carries the events instead
+    if not args.events_after:
+        s.profile_begin()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         infos = step(s)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if args.events_after:
+        s.profile_begin()
+        infos = step(s)
+        nprof = 1
+    else:
+        nprof = args.steps
+    prof_all = s.profile_end()
+    prof = {k: (v[0] / nprof, v[1] / nprof) for k, v in prof_all.items()}   # per step
     ok = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
     value = ok * args.steps / el
-    # one profiled step (per-kernel HIP events on the library's stream)
-    s.profile_begin()
-    step(s)
-    prof = s.profile_end()
-    pinfos = s.last_infos
+    pinfos = infos
+    xs, ys = s.last_xy
     stats = s.stats()
     per = per_instance_bytes(stats, 4)
     lf, lb = level_bytes(s, 4)
@@ -131,6 +146,16 @@ def run_gpu(args):
     avg_ms = ms_tot / max(launches, 1)
     per_launch = total[best] / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    # phases: all triangular-solve launches, and both SpMV kernels
+    tri = [k for k in ("fwd", "bwd", tk) if prof[k][1]]
+    phases = {}
+    for name, keys, extra_ms in (("solve", tri, prof["tri_wide"][0]), ("spmv", ["jt_spmv", "j_spmv"], 0.0)):
+        byt = sum(total[k] for k in keys)
+        ms = sum(prof[k][0] for k in keys) + extra_ms
+        phases[name] = {"alg_GB": round(byt / 1e9, 3), "ms": round(ms, 3),
+                        "GBps": round(byt / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                        "frac": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+    phases["stream_copy_GBps"] = stream_copy_gbps()
     kname = {"fwd": "k_fwd_lvl<float,true> (forward supernodal triangular solve, one launch per level)",
              "bwd": "k_bwd_lvl<float> (backward supernodal triangular solve, one launch per level)",
              "tri_tree": "k_tri_tree<float,true,512> (both solves over the thin top levels)",
@@ -142,32 +167,40 @@ def run_gpu(args):
                 "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(per_launch),
                 "launches_per_step": launches, "per_level_launch_levels": lo}
 
-    # plain FP64 comparators: batched, and one instance at a time
-    s64 = make("fp64", tune=not args.no_autotune)
-    step(s64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos64 = step(s64)
-    torch.cuda.synchronize()
-    fp64_batched = sum(1 for i in infos64 if i["status"] == 0 and i["rr"] <= 1e-10) / (time.perf_counter() - t0)
-    s1 = make("fp64")
-    k1 = args.single
-    step(s1, H[:1], D[:1], J[:1], R1[:1], R2[:1], b.delta[:1], b.gamma[:1])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    good = 0
-    for i in range(k1):
-        sl = slice(i, i + 1)
-        inf = step(s1, H[sl], D[sl], J[sl], R1[sl], R2[sl], b.delta[sl], b.gamma[sl])
-        good += inf[0]["status"] == 0 and inf[0]["rr"] <= 1e-10
-    torch.cuda.synchronize()
-    fp64_plain = good / (time.perf_counter() - t0)
+    # plain FP64 comparators: batched (same steps as the mixed path, fewer of
+    # them), and one instance at a time
+    fp64_batched = fp64_plain = None
+    if not args.no_comparators:
+        s64 = make("fp64", tune=not args.no_autotune)
+        step(s64)
+        torch.cuda.synchronize()
+        k64 = max(1, min(3, args.steps))
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            infos64 = step(s64)
+        torch.cuda.synchronize()
+        fp64_batched = sum(1 for i in infos64 if i["status"] == 0 and i["rr"] <= 1e-10) * k64 / (
+            time.perf_counter() - t0)
+        s1 = make("fp64")
+        k1 = min(args.single, nb)
+        step(s1, H[:1], D[:1], J[:1], R1[:1], R2[:1], b.delta[:1], b.gamma[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        good = 0
+        for i in range(k1):
+            sl = slice(i, i + 1)
+            inf = step(s1, H[sl], D[sl], J[sl], R1[sl], R2[sl], b.delta[sl], b.gamma[sl])
+            good += inf[0]["status"] == 0 and inf[0]["rr"] <= 1e-10
+        torch.cuda.synchronize()
+        fp64_plain = good / (time.perf_counter() - t0)
 
     cg = [i["cg_iters"] for i in infos]
     extra = {
-        "fp64_batched_solves_per_s": round(fp64_batched, 2),
-        "fp64_plain_solves_per_s": round(fp64_plain, 2),
-        "speedup_vs_plain_fp64": round(value / fp64_plain, 2) if fp64_plain > 0 else None,
+        "fp64_batched_solves_per_s": round(fp64_batched, 2) if fp64_batched else None,
+        "fp64_plain_solves_per_s": round(fp64_plain, 2) if fp64_plain else None,
+        "fp64_plain_instances": min(args.single, nb),
+        "speedup_vs_plain_fp64": round(value / fp64_plain, 2) if fp64_plain else None,
+        "speedup_vs_fp64_batched": round(value / fp64_batched, 3) if fp64_batched else None,
         "converged": f"{ok}/{nb}",
         "not_converged": [{"rr": i["rr"], "floor": i["floor"], "fallback": i["fp64_fallback"]}
                           for i in infos if not (i["status"] == 0 and i["rr"] <= 1e-10)],
@@ -175,10 +208,12 @@ def run_gpu(args):
         "fp64_fallbacks": sum(i["fp64_fallback"] for i in infos),
         "cg_iters_mean": round(float(np.mean(cg)), 2),
         "passes_max": max(i["passes"] for i in infos),
-        "profile_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "profile_ms_per_step": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "phases": phases,
         "autotuned": tuned or None,
         "symbolic": {k: stats[k] for k in ("nnz_L", "L_storage", "supernodes", "levels", "etree_height")},
     }
+    extra["_xy"] = (xs.cpu().numpy(), ys.cpu().numpy())
     return value, el, roofline, extra, b
 
 
@@ -384,21 +419,112 @@ def load_traffic():
         return None
 
 
-def cpu_baseline(b, budget_s):
+def stream_copy_gbps():
+    """Measured device-to-device copy bandwidth (1 GiB read + 1 GiB written),
+    best of five, the practical HBM ceiling beside the 8 TB/s nominal peak."""
+    import torch
+    a = torch.empty(2**28, dtype=torch.float32, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, c
+    return round(best, 1)
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(b, budget_s, xy=None):
+    """The oracle (plain FP64 C, one instance per thread) on the host cores:
+    first a 1-thread run over the first instances for about budget_s / 3,
+    then a pool of one thread per core (at most 16, the host share of one
+    GPU) over the whole batch for up to budget_s. Ordering once per pattern,
+    not timed (as on the GPU). Also the forward error of the GPU's solution
+    against the oracle's, per instance the oracle solved."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     o0 = oracle.System.from_batch(b, 0)
-    perm = o0.order_mindeg()          # ordering once per pattern, not timed (as on the GPU)
-    done = 0
-    t_used = 0.0
-    while done < b.nb and (t_used < budget_s or done == 0):
-        t0 = time.perf_counter()
-        o = oracle.System.from_batch(b, done)
-        st, fc = o.factor(perm)
-        x, y, info = o.solve(b.r1[done], b.r2[done], kkt_tol=1e-10)
-        t_used += time.perf_counter() - t0
-        done += 1
-    return {"value": round(done / t_used, 4), "unit": "KKT solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of the {b.nb} instances, factor+solve to RR<=1e-10, ordering excluded"}
+    perm = o0.order_mindeg()
+    zs = {}
+
+    def one(i):
+        o = oracle.System.from_batch(b, i)
+        o.factor(perm)
+        x, y, info = o.solve(b.r1[i], b.r2[i], kkt_tol=1e-10)
+        zs[i] = (np.concatenate([x, y]), info)
+
+    t0 = time.perf_counter()
+    n1 = 0
+    while n1 < max(1, b.nb // 4) and (time.perf_counter() - t0 < budget_s / 3 or n1 == 0):
+        one(n1)
+        n1 += 1
+    rate1 = n1 / (time.perf_counter() - t0)
+    model, avail = host_cpu()
+    threads = max(1, min(16, avail))
+    # every thread takes instances from a shared counter until the budget is
+    # spent; the rate counts the instances finished in the pool's wall time
+    import threading
+    lock = threading.Lock()
+    nxt = [n1]
+    done = [0]
+    t1 = time.perf_counter()
+
+    def worker():
+        while True:
+            with lock:
+                i = nxt[0]
+                if i >= b.nb or time.perf_counter() - t1 > budget_s:
+                    return
+                nxt[0] += 1
+            one(i)
+            with lock:
+                done[0] += 1
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for f in [ex.submit(worker) for _ in range(threads)]:
+            f.result()
+    wall = time.perf_counter() - t1
+    rate = done[0] / wall if wall > 0 else rate1
+    out = {"value": round(rate, 3), "unit": "KKT solves/s", "cores": threads, "kind": "oracle",
+           "one_core_value": round(rate1, 4), "cpu_model": model, "cpus_available": avail,
+           "sample": f"{n1} instances on 1 thread ({rate1:.2f}/s), then {done[0]} more of the {b.nb} on "
+                     f"{threads} threads in {wall:.1f} s; factor+solve to RR<=1e-10, ordering excluded"}
+    if xy is not None:
+        x, y = xy
+        errs = {}
+        for i, (z, info) in sorted(zs.items()):
+            zg = np.concatenate([x[i], y[i]])
+            errs[i] = float(np.linalg.norm(zg - z) / np.linalg.norm(z))
+        v = np.array(list(errs.values()))
+        g = np.array([b.gamma[i] for i in errs])
+        out["fwd_err_vs_oracle"] = {
+            "what": "||z_gpu - z_oracle||_2 / ||z_oracle||_2 per instance the oracle solved (index: error)",
+            "max": float(v.max()), "median": float(np.median(v)),
+            "by_gamma": {f"{gg:g}": {"max": float(v[g == gg].max()), "median": float(np.median(v[g == gg]))}
+                         for gg in sorted(set(g.tolist()))},
+            "per_instance": {str(i): float(f"{e:.2e}") for i, e in errs.items()}}
+    return out
 
 
 def main():
@@ -408,8 +534,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--n", type=int, default=20000)
-    ap.add_argument("--single", type=int, default=4, help="instances timed on the plain FP64 path")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--single", type=int, default=32, help="instances timed on the plain FP64 path")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--schedule-mixed", default="", help="relax,tree_width,staged for the mixed solver "
+                    "(skips its autotuning; for profiler runs)")
+    ap.add_argument("--schedule-fp64", default="", help="the same for the FP64 batched solver")
+    ap.add_argument("--events-after", action="store_true",
+                    help="per-kernel events on one extra step after the timed ones instead of on the timed steps")
+    ap.add_argument("--no-comparators", action="store_true",
+                    help="skip the FP64 batched and plain FP64 runs (profiler runs of the mixed path)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule instead of the autotuner's")
     ap.add_argument("--uneven", type=int, default=0,
@@ -450,7 +583,8 @@ def main():
         # bytes of the same launches, applied to this run's launches
         roofline["traffic"] = int(ratio * roofline["bytes_per_launch"])
         roofline["traffic_over_alg"] = ratio
-    cpu = None if args.no_cpu else cpu_baseline(b, args.cpu_budget)
+    xy = extra.pop("_xy", None)
+    cpu = None if args.no_cpu else cpu_baseline(b, args.cpu_budget, xy)
     out = {
         "metric": "KKT solves/sec at 1e-10 rel. KKT residual: mixed-prec batched vs plain FP64",
         "value": round(value, 2),

@@ -59,7 +59,7 @@ extern "C" {
 enum {
     HKKT_OK = 0,
     HKKT_NOT_SPD = 1,         /* Cholesky of H_gamma met a pivot <= 0 or not finite */
-    HKKT_CG_BREAKDOWN = 2,    /* CG met a small quadratic form (rank-deficient J) */
+    HKKT_CG_BREAKDOWN = 2,    /* CG's quadratic form fell below the breakdown threshold (rank-deficient J) */
     HKKT_NOT_CONVERGED = 3,   /* CG or refinement did not reach the tolerances */
     HKKT_ERR_ARG = -1,
     HKKT_ERR_PATTERN = -2,
@@ -93,7 +93,11 @@ typedef struct {
                                only the stall test of the solve decides (measured faster on the
                                benchmark: the first FP32 pass still warms the FP64 start) */
     double mixed_check_tol; /* default 0.5 */
-    int reserved[2];
+    int autotune_cache;     /* 1 (default): hkkt_autotune reuses the choice it made earlier in
+                               this process for the same pattern (hash of the analysed pattern,
+                               group layout and given order), precision and batch size instead
+                               of timing again; 0: always time */
+    int reserved;
 } hkkt_options;
 
 typedef struct {
@@ -109,7 +113,8 @@ typedef struct {
 
 /* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
- * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5. */
+ * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5,
+ * autotune_cache 1. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream
@@ -173,14 +178,29 @@ int hkkt_analyze_group(hkkt_ctx *ctx, int G, const int64_t *x_off, const int64_t
  * costs, relax-major, in the schedule order above (21 in all). Values as for
  * hkkt_factor_batch. The context is left analysed and not factored: call
  * hkkt_factor_batch next. Returns 0 or a negative code (-3 if not
- * analysed). */
+ * analysed; a failed trial returns its code, e.g. -1 when r1 is given and
+ * r2 is NULL while m > 0). On any failure the
+ * context's schedule and profiling state are restored (the context is then
+ * analysed with its previous relax and not factored). With autotune_cache
+ * set, a choice already made for the same key is applied without timing
+ * (cost_ms entries are then NaN). */
 int hkkt_autotune(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
                   const double *J_val, const double *delta, const double *gamma,
                   const double *r1, const double *r2,
                   int32_t choice[3], double *cost_ms, int max_cost);
 
+/* The context's current schedule, choice = (relax, tree width, staged tree
+ * kernel) as hkkt_autotune reports it; -3 if not analysed. */
+int hkkt_get_schedule(const hkkt_ctx *ctx, int32_t choice[3]);
+
+/* Set the schedule (e.g. one the autotuner chose in an earlier run): relax in
+ * {0, 1, 2}, tree width >= 0 (0 = no tree kernel), staged in {0, 1}. A
+ * changed relax re-analyses the pattern and the context must be factored
+ * again. -1 on values out of range, -3 if not analysed. */
+int hkkt_set_schedule(hkkt_ctx *ctx, const int32_t choice[3]);
+
 /* Numeric factorization of nb instances that share the analysed pattern
- * (Sec. 2: once per matrix; Algorithm 1 "Try LL^T = chol(H_delta)").
+ * (Sec. 2: once per matrix; Algorithm 1's Cholesky attempt on H_gamma).
  * H_val [nb][nnz(tril H)], D_x [nb][n_x], J_val [nb][nnz(J)], delta [nb],
  * gamma [nb] (always host arrays for delta and gamma). status[b] (host, may
  * be NULL) gets 0 or HKKT_NOT_SPD; fail_col[b] (host, may be NULL) gets the
@@ -212,8 +232,12 @@ int hkkt_solve(hkkt_ctx *ctx, const double *r1, const double *r2, double *x, dou
 /* Inertia (positive, negative, zero eigenvalue counts) of K for instance b
  * after a successful factor and solve (Sec. 4.2, Theorem 3: a successful
  * Cholesky of H_gamma gives n_x positive; with full-rank J the Schur
- * complement adds m negative). A CG breakdown counts one zero eigenvalue.
- * Returns -3 if no successful factor+solve precedes it. */
+ * complement adds m negative). Returns 0 with (n_x, m, 0) when CG did not
+ * break down. After a breakdown (J rank-deficient or nearly so) K has at
+ * least one zero eigenvalue but the count is not known: returns
+ * HKKT_CG_BREAKDOWN with out = (n_x, -1, -1) (n_x positive is still exact;
+ * the other m are negative or zero). Returns -3 if no successful
+ * factor+solve precedes it. */
 int hkkt_inertia(const hkkt_ctx *ctx, int b, int64_t out[3]);
 
 /* ---- host-only symbolic analysis handle (no GPU needed) ------------------

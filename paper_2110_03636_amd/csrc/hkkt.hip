@@ -29,6 +29,8 @@
 #include <thread>
 #include <functional>
 #include <exception>
+#include <array>
+#include <map>
 #include <vector>
 
 struct hkkt_symbolic {
@@ -185,6 +187,7 @@ struct DevSym {
     DBuf tri_list, tri_desc;
     std::vector<std::pair<i32, i32>> tri_seg;   // [level * kTriClasses + class] = (offset, count)
     std::vector<int> tri_wg_maxnr;              // per level, class 7
+    std::vector<std::vector<std::pair<int, int>>> tri_wg_nrw;   // per level, class 7: (nr, w) in list order
     DBuf tri_seg_dev;                           // tri_seg on the device (int pairs)
     std::vector<int> lev_count;                 // supernodes per level
     std::vector<char> tree_fits;                // level fits the tree-traversal classes
@@ -339,6 +342,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
         std::vector<i32> tl;
         D.tri_seg.assign((size_t)S.nlevels * kTriClasses, {0, 0});
         D.tri_wg_maxnr.assign(S.nlevels, 0);
+        D.tri_wg_nrw.assign(S.nlevels, {});
         // supernodes of 33..1024 rows of a level share the level's largest
         // 64-lane class (one launch); HKKT_TRI_SPLIT keeps them apart
         const bool merge_classes = std::getenv("HKKT_TRI_SPLIT") == nullptr;
@@ -370,7 +374,10 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                     dd.mem = S.sn_mem[sn];
                     dd.pad = 0;
                     td.push_back(dd);
-                    if (cls == kTriWG) D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
+                    if (cls == kTriWG) {
+                        D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
+                        D.tri_wg_nrw[l].push_back({nr, dd.w});
+                    }
                 }
                 D.tri_seg[(size_t)l * kTriClasses + cls] = {off, (i32)tl.size() - off};
             }
@@ -656,6 +663,59 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
            (i64)S.Lsize, (const T*)L, B.Dinv.as<T>(), active);
 }
 
+// Wide supernodes of level l (class 7) by the blocked multi-work-group
+// solves: forward launches q = 0..nblk, backward the rows-below launch and
+// then q = nblk-1..0 (nblk = blocks of the widest supernode of the level).
+// HKKT_TRI_WS=0 keeps the one-work-group-per-supernode kernels instead.
+static bool ws_on() {
+    static const bool on = !(std::getenv("HKKT_TRI_WS") && std::atoi(std::getenv("HKKT_TRI_WS")) == 0);
+    return on;
+}
+
+template <typename T>
+static void launch_ws(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const TriDesc* dsc, int cnt, const int* ids, int nids,
+                      const CGState* st_) {
+    const DevSym& D = c->dev;
+    const auto& nrw = D.tri_wg_nrw[l];
+    const T* L = B.L.as<T>();
+    T* X = B.X.as<T>();
+    const int kind = 11 + 16 * (l + 1);
+    int maxw = 0, maxbelow = 0;
+    for (const auto& p : nrw) {
+        maxw = std::max(maxw, p.second);
+        maxbelow = std::max(maxbelow, p.first - p.second);
+    }
+    const int nblk = (maxw + kWsB - 1) / kWsB;
+    if (fwd) {
+        for (int q = 0; q <= nblk; q++) {
+            // update work-groups: rows [min(qB + B, w), nr) of the supernodes
+            // that apply block q-1
+            int chunks = 0;
+            for (const auto& p : nrw) {
+                if (q == 0 || (q - 1) * kWsB >= p.second) continue;
+                const int s0 = std::min(q * kWsB + kWsB, p.second);
+                chunks = std::max(chunks, (p.first - s0 + kWsR - 1) / kWsR);
+            }
+            LAUNCH(kind, k_ws_fwd<T>, dim3(1 + chunks, cnt, nids), dim3(kBlock), 0, B.stream, D.v, dsc, q, L, X,
+                   ids, st_);
+        }
+    } else {
+        if (maxbelow > 0) {
+            LAUNCH(kind, k_ws_bwd_below<T>, dim3((maxw + kWsR - 1) / kWsR, cnt, nids), dim3(kBlock), 0, B.stream,
+                   D.v, dsc, L, X, ids, st_);
+        }
+        for (int q = nblk - 1; q >= 0; q--) {
+            // update work-groups: columns [0, qB) of the supernodes that
+            // apply block q+1
+            int chunks = 0;
+            for (const auto& p : nrw)
+                if ((q + 1) * kWsB < p.second) chunks = std::max(chunks, (q * kWsB + kWsR - 1) / kWsR);
+            LAUNCH(kind, k_ws_bwd<T>, dim3(1 + chunks, cnt, nids), dim3(kBlock), 0, B.stream, D.v, dsc, q, L, X,
+                   ids, st_);
+        }
+    }
+}
+
 // X <- H_gamma^{-1} X (in place) for the nids instances listed in ids;
 // instances whose CG is done (st) are skipped
 template <typename T>
@@ -713,6 +773,10 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
             case 5: HKKT_TRI_S(64, 8) break;
             case 6: HKKT_TRI_S(64, 16) break;
             default: {
+                if (push && ws_on()) {
+                    launch_ws<T>(c, B, l, fwd, dsc, cnt, ids, nids, st_);
+                    break;
+                }
                 // the working vector in LDS when it fits, else in the solve and update vectors
                 size_t lds = (size_t)(kTri * kTri + D.tri_wg_maxnr[l]) * sizeof(T);
                 if (lds <= kMaxLds) {
@@ -1269,6 +1333,54 @@ static int reanalyze(hkkt_ctx* c) {
                        P.Hp.data(), P.Hi.data(), P.Jp.data(), P.Ji.data(), P.perm.empty() ? nullptr : P.perm.data());
 }
 
+// Autotuner choices made in this process, keyed by a hash of the analysed
+// pattern (with the group layout, the given order and the ordering option),
+// the precision, the batch size and whether trial solves were timed.
+static std::mutex g_tune_mu;
+static std::map<uint64_t, std::array<int, 3>> g_tune_cache;
+
+static uint64_t fnv1a(uint64_t h, const void* p, size_t bytes) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < bytes; i++) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+template <typename T>
+static uint64_t fnv1a_vec(uint64_t h, const std::vector<T>& v) {
+    const uint64_t n = v.size();
+    h = fnv1a(h, &n, sizeof(n));
+    return v.empty() ? h : fnv1a(h, v.data(), v.size() * sizeof(T));
+}
+
+static uint64_t tune_key(const hkkt_ctx* c, int nb, bool trial) {
+    const auto& P = c->pat;
+    uint64_t h = 1469598103934665603ull;
+    const int64_t head[7] = {P.G, P.n, P.m, c->opt.precision, c->opt.ordering, nb, trial ? 1 : 0};
+    h = fnv1a(h, head, sizeof(head));
+    h = fnv1a_vec(h, P.xo);
+    h = fnv1a_vec(h, P.yo);
+    h = fnv1a_vec(h, P.Hp);
+    h = fnv1a_vec(h, P.Hi);
+    h = fnv1a_vec(h, P.Jp);
+    h = fnv1a_vec(h, P.Ji);
+    return fnv1a_vec(h, P.perm);
+}
+
+// schedule = (relax, tree width, staged tree kernel): applied to the context;
+// a changed relax re-analyses the stored pattern (the context is then not
+// factored)
+static int apply_schedule(hkkt_ctx* c, int relax, int width, int stage) {
+    c->tree_width = width;
+    c->tree_stage = stage;
+    if (relax != c->opt.relax || !c->analysed) {
+        c->opt.relax = relax;
+        return reanalyze(c);
+    }
+    c->dev.tree_width = width;
+    c->dev.tree_stage = stage;
+    return HKKT_OK;
+}
+
 extern "C" {
 
 void hkkt_default_options(hkkt_options* o) {
@@ -1287,6 +1399,7 @@ void hkkt_default_options(hkkt_options* o) {
     o->deterministic = 0;
     o->mixed_check = 0;
     o->mixed_check_tol = 0.5;
+    o->autotune_cache = 1;
 }
 
 int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
@@ -1416,6 +1529,30 @@ int hkkt_analyze_group(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* 
     return analyze_ctx(c, G, x_off, y_off, n, m, Hp, Hi, Jp, Ji, nullptr);
 }
 
+int hkkt_get_schedule(const hkkt_ctx* c, int32_t choice[3]) {
+    if (!c || !choice) return HKKT_ERR_ARG;
+    if (!c->analysed) return HKKT_ERR_STATE;
+    choice[0] = c->opt.relax;
+    choice[1] = c->dev.tree_width;
+    choice[2] = c->dev.tree_stage;
+    return HKKT_OK;
+}
+
+int hkkt_set_schedule(hkkt_ctx* c, const int32_t choice[3]) {
+    if (!c || !choice) return HKKT_ERR_ARG;
+    if (!c->analysed) { c->err = "schedule before analyze"; return HKKT_ERR_STATE; }
+    if (choice[0] < 0 || choice[0] > 2 || choice[1] < 0 || (choice[2] != 0 && choice[2] != 1)) {
+        c->err = "schedule: relax in {0,1,2}, tree width >= 0, staged in {0,1}";
+        return HKKT_ERR_ARG;
+    }
+    const bool re = choice[0] != c->opt.relax;
+    ABI_GUARD(c, {
+        const int rc = apply_schedule(c, choice[0], choice[1], choice[2]);
+        if (re) c->factored = false;
+        return rc;
+    })
+}
+
 int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* delta,
                   const double* gamma, const double* r1, const double* r2, int32_t choice[3], double* cost_ms,
                   int max_cost) {
@@ -1425,6 +1562,50 @@ int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const 
         c->err = "bad autotune arguments";
         return HKKT_ERR_ARG;
     }
+    const uint64_t key = tune_key(c, nb, r1 != nullptr);
+    if (c->opt.autotune_cache) {
+        std::array<int, 3> hit{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) { hit = it->second; found = true; }
+        }
+        if (found) {
+            ABI_GUARD(c, {
+                const int rc = apply_schedule(c, hit[0], hit[1], hit[2]);
+                if (rc != HKKT_OK) return rc;
+                c->factored = false;
+                for (int i = 0; i < max_cost && cost_ms; i++) cost_ms[i] = NAN;
+                choice[0] = hit[0];
+                choice[1] = hit[1];
+                choice[2] = hit[2];
+                return HKKT_OK;
+            })
+        }
+    }
+    // the caller's schedule and profiling state come back on every exit that
+    // does not complete the tuning (a failed trial, an exception)
+    struct Restore {
+        hkkt_ctx* c;
+        int relax, width, stage, tw, ts;
+        bool prof, armed = true;
+        ~Restore() {
+            if (!armed) return;
+            c->prof.on = prof;
+            c->opt.relax = relax;
+            c->tree_width = tw;
+            c->tree_stage = ts;
+            try {
+                if (reanalyze(c) == HKKT_OK) {
+                    c->dev.tree_width = width;
+                    c->dev.tree_stage = stage;
+                }
+            } catch (...) {
+            }
+            c->factored = false;
+        }
+    } restore{c, c->opt.relax, c->dev.tree_width, c->dev.tree_stage, c->tree_width, c->tree_stage, c->prof.on};
     ABI_GUARD(c, {
         static const int relaxes[] = {0, 1, 2};
         static const int widths[] = {0, 8, 32, 128};
@@ -1535,11 +1716,17 @@ int hkkt_autotune(hkkt_ctx* c, int nb, const double* H, const double* Dx, const 
         c->tree_width = best_width;
         c->tree_stage = best_stage;
         const int rc = reanalyze(c);
-        c->prof.on = prof_on;
         if (rc != HKKT_OK) return rc;
+        c->prof.on = prof_on;
+        c->factored = false;
+        restore.armed = false;
         choice[0] = best_relax;
         choice[1] = best_width;
         choice[2] = best_stage;
+        if (c->opt.autotune_cache) {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            g_tune_cache[key] = {best_relax, best_width, best_stage};
+        }
         return HKKT_OK;
     })
 }
@@ -1918,10 +2105,19 @@ int hkkt_inertia(const hkkt_ctx* c, int i, int64_t out[3]) {
         return HKKT_ERR_STATE;
     const Symbolic& S = c->sym.S;
     const int k = i % S.G;
-    const int64_t nu = c->breakdown[i] ? 1 : 0;
+    // congruence with [I, (gamma/2) J^T; 0, I] and Haynsworth: In(K) =
+    // In(H_gamma) + In(-S); the Cholesky gives n_x positive eigenvalues and,
+    // without a breakdown, S = J H_gamma^{-1} J^T is SPD (m negative). A
+    // breakdown shows S singular or nearly so but not its nullity: the split
+    // of the other m eigenvalues is then left undetermined.
     out[0] = S.x_off[k + 1] - S.x_off[k];
-    out[1] = S.y_off[k + 1] - S.y_off[k] - nu;
-    out[2] = nu;
+    if (c->breakdown[i]) {
+        out[1] = -1;
+        out[2] = -1;
+        return HKKT_CG_BREAKDOWN;
+    }
+    out[1] = S.y_off[k + 1] - S.y_off[k];
+    out[2] = 0;
     return HKKT_OK;
 }
 

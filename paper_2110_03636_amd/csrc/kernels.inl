@@ -583,6 +583,238 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Wide supernodes (more than 1024 rows or columns): blocked triangular solves
+// spread over many work-groups, right-looking forward solve with FP atomics
+// for the rows below the supernode. The w columns of the panel are cut into
+// diagonal blocks of kWsB columns.
+// Forward, launch q: every work-group but the first applies block q-1's
+// solution (final since launch q-1) to kWsR rows below that block; the first
+// work-group owns block q's rows, applies block q-1 to them and then solves
+// block q with its diagonal triangle (look-ahead: one launch per block, the
+// rows of block q are final once block q-1 is applied).
+// Backward: one launch subtracts the rows below the supernode (ancestors'
+// x, final) from every column; then launch q (last block first) applies
+// block q+1's solution to kWsR columns left of block q per work-group, and
+// the first work-group, owning block q's columns, applies it to them and
+// solves block q with the transposed triangle.
+// Grid: x = work-group of the supernode (0 = owner), y = supernode of the
+// level's list, z = instance list index. All work of a supernode sits in
+// its panel (column-major, nr x w, leading dimension nr).
+// ---------------------------------------------------------------------------
+constexpr int kWsB = 256;   // columns per diagonal block (= threads of the owner work-group)
+constexpr int kWsR = 64;    // rows (forward) / columns (backward) per update work-group
+
+static_assert(kWsB == kBlock, "the owner work-group holds one block row per thread");
+
+// sum_{j < n} col[j * ld] * v[j], eight independent loads in flight
+template <typename T>
+__device__ __forceinline__ T strided_dot(const T* __restrict__ col, i64 ld, const T* v, int n) {
+    T sum = T(0);
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        T l[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) l[u] = col[(i64)(j + u) * ld];
+#pragma unroll
+        for (int u = 0; u < 8; u++) sum += l[u] * v[j + u];
+    }
+    for (; j < n; j++) sum += col[(i64)j * ld] * v[j];
+    return sum;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ws_fwd(SymView S, const TriDesc* __restrict__ desc, int q,
+                                                   const T* __restrict__ L, T* __restrict__ X, const int* ids,
+                                                   const CGState* st) {
+    __shared__ T ys[kWsB];                       // block q-1's solution
+    __shared__ T part[kBlock / kWave][kWave];    // partial row sums of the waves
+    __shared__ T D[kTri * kTri];                 // owner: diagonal tile
+    __shared__ T u[kWsB];                        // owner: the block's right-hand side, then solution
+    const TriDesc d = desc[blockIdx.y];
+    const int b = inst_of(ids, blockIdx.z);
+    if (st && st[(i64)b * S.G + d.mem].done) return;
+    const int w = d.w, nr = d.nr;
+    const int a = (q - 1) * kWsB;                // applied block [a, e)
+    const bool apply = q > 0 && a < w;
+    const int e = apply ? min(a + kWsB, w) : a;
+    const int qb = q * kWsB;
+    const int s0 = min(qb + kWsB, w);            // rows of the update work-groups start here
+    const bool owner = blockIdx.x == 0;
+    int r_lo, r_hi;
+    if (owner) {
+        if (qb >= w) return;
+        r_lo = qb;
+        r_hi = s0;
+    } else {
+        if (!apply) return;
+        r_lo = s0 + (int)(blockIdx.x - 1) * kWsR;
+        if (r_lo >= nr) return;
+        r_hi = min(r_lo + kWsR, nr);
+    }
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    T* x = X + (i64)b * S.n;
+    const int na = e - a;
+    for (int j = threadIdx.x; apply && j < na; j += blockDim.x) ys[j] = x[d.f + a + j];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (!owner) {
+        // kWsR = 64 rows, the waves split the applied block's columns
+        const int r = r_lo + lane;
+        const int per = (na + (kBlock / kWave) - 1) / (kBlock / kWave);
+        const int j0 = min(wid * per, na), j1 = min(j0 + per, na);
+        T sum = T(0);
+        if (r < r_hi) sum = strided_dot(Lb + (i64)(a + j0) * nr + r, nr, ys + j0, j1 - j0);
+        part[wid][lane] = sum;
+        __syncthreads();
+        if (wid == 0 && r < r_hi) {
+            T t = part[0][lane];
+#pragma unroll
+            for (int k = 1; k < kBlock / kWave; k++) t += part[k][lane];
+            if (r < w) x[d.f + r] -= t;
+            else unsafeAtomicAdd(&x[S.sn_rows[d.rp + r]], -t);
+        }
+        return;
+    }
+    // owner: rows [qb, s0) of block q, one per thread
+    const int bw = s0 - qb;
+    const int t = threadIdx.x;
+    T val = T(0);
+    if (t < bw) {
+        val = x[d.f + qb + t];
+        if (apply) val -= strided_dot(Lb + (i64)a * nr + qb + t, nr, ys, na);
+    }
+    u[t] = val;
+    __syncthreads();
+    for (int kb = 0; kb < bw; kb += kTri) {
+        const int tw = min(kTri, bw - kb);
+        for (int idx = t; idx < tw * tw; idx += blockDim.x) {
+            const int jj = idx / tw, ii = idx - jj * tw;
+            D[jj * kTri + ii] = Lb[(i64)(qb + kb + jj) * nr + qb + kb + ii];
+        }
+        __syncthreads();
+        if (wid == 0) {
+            T v = lane < tw ? u[kb + lane] : T(0);
+            for (int k = 0; k < tw; k++) {
+                if (lane == k) v = v / D[k * kTri + k];
+                const T yk = __shfl(v, k, kWave);
+                if (lane > k && lane < tw) v -= D[k * kTri + lane] * yk;
+            }
+            if (lane < tw) u[kb + lane] = v;
+        }
+        __syncthreads();
+        if (t >= kb + tw && t < bw) u[t] -= strided_dot(Lb + (i64)(qb + kb) * nr + qb + t, nr, u + kb, tw);
+        __syncthreads();
+    }
+    if (t < bw) x[d.f + qb + t] = u[t];
+}
+
+// Backward, rows below the supernode: x_j -= sum_{r >= w} L(r, j) x(row r)
+// for the kWsR columns of this work-group (one wave per column at a time).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ws_bwd_below(SymView S, const TriDesc* __restrict__ desc,
+                                                         const T* __restrict__ L, T* __restrict__ X,
+                                                         const int* ids, const CGState* st) {
+    const TriDesc d = desc[blockIdx.y];
+    const int b = inst_of(ids, blockIdx.z);
+    if (st && st[(i64)b * S.G + d.mem].done) return;
+    const int w = d.w, nr = d.nr;
+    const int c0 = (int)blockIdx.x * kWsR;
+    if (c0 >= w || nr == w) return;
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    T* x = X + (i64)b * S.n;
+    const i32* rows = S.sn_rows + d.rp;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int j = c0 + wid; j < min(c0 + kWsR, w); j += kBlock / kWave) {
+        const T* col = Lb + (i64)j * nr;
+        T sum = T(0);
+        for (int r = w + lane; r < nr; r += kWave) sum += col[r] * x[rows[r]];
+        sum = wave_sum(sum);
+        if (lane == 0) x[d.f + j] -= sum;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ws_bwd(SymView S, const TriDesc* __restrict__ desc, int q,
+                                                   const T* __restrict__ L, T* __restrict__ X, const int* ids,
+                                                   const CGState* st) {
+    __shared__ T xs[kWsB];                       // block q+1's solution
+    __shared__ T D[kTri * kTri];                 // owner: diagonal tile
+    __shared__ T u[kWsB];                        // owner: the block's right-hand side, then solution
+    const TriDesc d = desc[blockIdx.y];
+    const int b = inst_of(ids, blockIdx.z);
+    if (st && st[(i64)b * S.G + d.mem].done) return;
+    const int w = d.w, nr = d.nr;
+    const int qb = q * kWsB;
+    if (qb >= w) return;                         // this supernode has no block q
+    const int a = qb + kWsB;                     // applied block [a, e)
+    const bool apply = a < w;
+    const int e = apply ? min(a + kWsB, w) : a;
+    const bool owner = blockIdx.x == 0;
+    int c_lo, c_hi;
+    if (owner) {
+        c_lo = qb;
+        c_hi = min(qb + kWsB, w);
+    } else {
+        if (!apply) return;
+        c_lo = (int)(blockIdx.x - 1) * kWsR;
+        if (c_lo >= qb) return;
+        c_hi = min(c_lo + kWsR, qb);
+    }
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    T* x = X + (i64)b * S.n;
+    const int na = e - a;
+    for (int j = threadIdx.x; apply && j < na; j += blockDim.x) xs[j] = x[d.f + a + j];
+    if (owner)
+        for (int j = threadIdx.x; j < c_hi - c_lo; j += blockDim.x) u[j] = x[d.f + c_lo + j];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    // columns j in [c_lo, c_hi): x_j -= sum_{i in [a, e)} L(i, j) x_i (one wave per column)
+    for (int j = c_lo + wid; apply && j < c_hi; j += kBlock / kWave) {
+        const T* col = Lb + (i64)j * nr + a;
+        T sum = T(0);
+        for (int i = lane; i < na; i += kWave) sum += col[i] * xs[i];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+            if (owner) u[j - c_lo] -= sum;
+            else x[d.f + j] -= sum;
+        }
+    }
+    if (!owner) return;
+    __syncthreads();
+    // owner: transposed solve of block q, last 64-column tile first
+    const int bw = c_hi - c_lo;
+    const int ntile = (bw + kTri - 1) / kTri;
+    for (int ti = ntile - 1; ti >= 0; ti--) {
+        const int kb = ti * kTri;
+        const int tw = min(kTri, bw - kb);
+        for (int idx = threadIdx.x; idx < tw * tw; idx += blockDim.x) {
+            const int jj = idx / tw, ii = idx - jj * tw;
+            D[jj * kTri + ii] = Lb[(i64)(qb + kb + jj) * nr + qb + kb + ii];
+        }
+        __syncthreads();
+        if (wid == 0) {
+            T v = lane < tw ? u[kb + lane] : T(0);
+            for (int k = tw - 1; k >= 0; k--) {
+                if (lane == k) v = v / D[k * kTri + k];
+                const T xk = __shfl(v, k, kWave);
+                if (lane < k) v -= D[lane * kTri + k] * xk;
+            }
+            if (lane < tw) u[kb + lane] = v;
+        }
+        __syncthreads();
+        // earlier columns of the block: u_j -= sum_{i in tile} L(qb+kb+i, qb+j) u_{kb+i}
+        for (int j = wid; j < kb; j += kBlock / kWave) {
+            const T* col = Lb + (i64)(qb + j) * nr + qb + kb;
+            T sum = lane < tw ? col[lane] * u[kb + lane] : T(0);
+            sum = wave_sum(sum);
+            if (lane == 0) u[j] -= sum;
+        }
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < bw; j += blockDim.x) x[d.f + qb + j] = u[j];
+}
+
+// ---------------------------------------------------------------------------
 // wavefront triangular solves: a wavefront is split into 64/SEG segments of
 // SEG lanes; each segment solves one (supernode, instance) task, all
 // segments of a wavefront the same supernode for consecutive instances (the
@@ -1649,8 +1881,35 @@ __global__ __launch_bounds__(kBlock) void k_axpy2(SymView S, double* __restrict_
     else yz[(i64)b * S.m + (i - S.n)] += ey[(i64)b * S.m + (i - S.n)];
 }
 
+// Compensated accumulation of r_i - sum_k a_k b_k (Ogita, Rump and Oishi
+// 2005, "Accurate sum and dot product", Dot2): the running sum is the
+// unevaluated pair hi + lo; each product is split exactly into p + ep by an
+// FMA (TwoProduct) and hi - p exactly into s + es (TwoSum), and both error
+// terms go to lo. The rounded result hi + lo is as accurate as a sum in
+// twice the working precision. Contraction is off so that every product and
+// sum is rounded on its own, as the transformations require.
+struct Acc2 {
+    double hi, lo, aabs;   // aabs: sum of |a_k b_k| (the evaluation floor's terms)
+};
+
+__device__ __forceinline__ void acc2_sub_prod(Acc2& c, double a, double b) {
+#pragma clang fp contract(off)
+    const double p = a * b;
+    const double ep = __builtin_fma(a, b, -p);
+    const double s = c.hi - p;
+    const double z = s - c.hi;
+    const double es = (c.hi - (s - z)) + (-p - z);
+    c.hi = s;
+    c.lo += es - ep;
+    c.aabs += fabs(p);
+}
+
 // g = r - K z over rows [0, n) (first block row) and [n, n+m) (J rows),
-// partial ||g||^2; optional partials of || |K||z| + |r| ||^2 (floor).
+// K = [H + D_x + delta I, J^T; J, 0], every product of a stored value with
+// an entry of z a term of its own (the diagonal's H_ii, D_i and delta
+// separately), summed by the compensated accumulation above; partial
+// ||g||^2; optional partials of (|r_i| + sum of |term|)^2 (the floor:
+// plain FP64 evaluation would err by about u times that).
 __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const double* __restrict__ r1,
                                                      const double* __restrict__ r2, const double* __restrict__ xz,
                                                      const double* __restrict__ yz, double* __restrict__ g1,
@@ -1666,40 +1925,28 @@ __global__ __launch_bounds__(kBlock) void k_residual(SymView S, ValView V, const
     if (i < bk.hi && i < S.n) {
         const double* HF = V.HF + (i64)b * S.nnzHF;
         const double* JT = V.JT + (i64)b * S.nnzJ;
-        double acc = 0.0, aabs = 0.0;
-        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) {
-            const double t = HF[k] * x[S.HF_col[k]];
-            acc += t;
-            aabs += fabs(t);
-        }
-        const double dt = (V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + bk.k]) * x[i];
-        acc += dt;
-        aabs += fabs(dt);
-        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) {
-            const double t = JT[k] * y[S.JT_col[k]];
-            acc += t;
-            aabs += fabs(t);
-        }
         const double rv = r1[(i64)b * S.n + i];
-        const double g = rv - acc;
+        Acc2 c{rv, 0.0, 0.0};
+        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) acc2_sub_prod(c, HF[k], x[S.HF_col[k]]);
+        const double xi = x[i];
+        acc2_sub_prod(c, V.Dxp[(i64)b * S.n + i], xi);
+        acc2_sub_prod(c, V.delta[(i64)b * S.G + bk.k], xi);
+        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) acc2_sub_prod(c, JT[k], y[S.JT_col[k]]);
+        const double g = c.hi + c.lo;
         g1[(i64)b * S.n + i] = g;
         a = g * g;
-        fl = aabs + fabs(rv);
+        fl = c.aabs + fabs(rv);
         fl = fl * fl;
     } else if (i < bk.hi) {
         const i64 r = i - S.n;
         const double* J = V.J + (i64)b * S.nnzJ;
-        double acc = 0.0, aabs = 0.0;
-        for (i64 k = S.J_rowptr[r]; k < S.J_rowptr[r + 1]; k++) {
-            const double t = J[k] * x[S.J_colp[k]];
-            acc += t;
-            aabs += fabs(t);
-        }
         const double rv = r2[(i64)b * S.m + r];
-        const double g = rv - acc;
+        Acc2 c{rv, 0.0, 0.0};
+        for (i64 k = S.J_rowptr[r]; k < S.J_rowptr[r + 1]; k++) acc2_sub_prod(c, J[k], x[S.J_colp[k]]);
+        const double g = c.hi + c.lo;
         g2[(i64)b * S.m + r] = g;
         a = g * g;
-        fl = aabs + fabs(rv);
+        fl = c.aabs + fabs(rv);
         fl = fl * fl;
     }
     a = block_sum(a, sh);

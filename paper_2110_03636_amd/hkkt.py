@@ -24,7 +24,8 @@ EXPORTS = [
     "hkkt_factor_batch", "hkkt_factor", "hkkt_solve_batch", "hkkt_solve", "hkkt_inertia",
     "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
-    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune", "hkkt_symbolic_cb_offsets",
+    "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
+    "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged"]
@@ -39,7 +40,8 @@ class Options(C.Structure):
                 ("cg_tol_mixed", C.c_double), ("kkt_tol", C.c_double), ("quad_form_eps", C.c_double),
                 ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
                 ("ordering", C.c_int), ("relax", C.c_int), ("deterministic", C.c_int),
-                ("mixed_check", C.c_int), ("mixed_check_tol", C.c_double), ("reserved", C.c_int * 2)]
+                ("mixed_check", C.c_int), ("mixed_check_tol", C.c_double), ("autotune_cache", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class Info(C.Structure):
@@ -86,6 +88,8 @@ def lib():
         L.hkkt_analyze_group.argtypes = [V, C.c_int, V, V, C.c_int64, C.c_int64, V, V, V, V]
         L.hkkt_factor_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V]
         L.hkkt_autotune.argtypes = [V, C.c_int, V, V, V, V, V, V, V, V, V, C.c_int]
+        L.hkkt_get_schedule.argtypes = [V, V]
+        L.hkkt_set_schedule.argtypes = [V, V]
         L.hkkt_factor.argtypes = [V, V, V, V, C.c_double, C.c_double, V]
         L.hkkt_solve_batch.argtypes = [V, C.c_int, V, V, V, V, V]
         L.hkkt_solve.argtypes = [V, V, V, V, V, V]
@@ -378,7 +382,7 @@ class Solver(_SymbolicView):
         if Jv is not None and Jv.shape[1] == 0:
             Jv = None
         R1 = self._arr(r1, nb, self.n) if r1 is not None else None
-        R2 = self._arr(r2, nb, self.m) if (r1 is not None and self.m > 0) else None
+        R2 = self._arr(r2, nb, self.m) if (r1 is not None and r2 is not None and self.m > 0) else None
         choice = np.zeros(3, np.int32)
         cost = np.full(21, np.nan)
         _check(lib().hkkt_autotune(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv), delta.ctypes.data,
@@ -389,6 +393,19 @@ class Solver(_SymbolicView):
         table = [[r, w, st, float(cost[i * 7 + j])] for i, r in enumerate((0, 1, 2)) for j, (w, st) in enumerate(sched)]
         return {"relax": int(choice[0]), "tree_width": int(choice[1]), "tree_staged": int(choice[2]),
                 "cost_ms": table}
+
+    def schedule(self):
+        """(relax, tree_width, tree_staged) currently in use."""
+        ch = np.zeros(3, np.int32)
+        _check(lib().hkkt_get_schedule(self._ctx, ch.ctypes.data), self._ctx)
+        return tuple(int(v) for v in ch)
+
+    def set_schedule(self, relax, tree_width, tree_staged):
+        """Apply a schedule (e.g. an earlier autotuner choice); a changed relax
+        re-analyses the pattern, so factor next."""
+        ch = np.array([relax, tree_width, tree_staged], np.int32)
+        _check(lib().hkkt_set_schedule(self._ctx, ch.ctypes.data), self._ctx)
+        self.nb = 0
 
     def factor_batch(self, batch):
         return self.factor(batch.H_val, batch.D_x, batch.J_val, batch.delta, batch.gamma)

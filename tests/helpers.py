@@ -1,5 +1,6 @@
-"""Small shared helpers for the tests: dense views of generated systems and
-tiny hand-made systems. No solver arithmetic lives here."""
+"""Small shared helpers for the tests: dense views of generated systems,
+tiny hand-made systems, and the oracle-side acceptance check of a GPU
+solution. No solver arithmetic lives here."""
 from __future__ import annotations
 
 import json
@@ -99,3 +100,32 @@ def tiny_grid_like(n_x, seed, gamma=1e4, dx_exp=1.0, nb=1):
 def with_gamma(batch, gamma):
     import dataclasses
     return dataclasses.replace(batch, gamma=np.full_like(batch.gamma, gamma))
+
+
+def rounded_solution_rr(o, r1, r2):
+    """RR of the exact solution rounded to FP64, computed by the oracle
+    (solve, then refinement with a double-double iterate): the least RR an
+    FP64 z can be expected to reach."""
+    o.factor(o.order_mindeg())
+    xo, yo, io = o.solve(r1, r2)
+    xr, yr, hist = o.refine_dd(r1, r2, xo, yo)
+    assert hist[-1] < 1e-20, hist
+    return o.metrics(r1, r2, xr, yr)[0]
+
+
+def check_gpu_solution(o, r1, r2, x, y, info, tol):
+    """Accept a GPU solution by the oracle's compensated residual: status 0
+    and RR <= tol; or, only where the exact solution rounded to FP64 itself
+    misses tol, status NOT_CONVERGED (3) with RR within 2x of that rounded
+    solution's. The library's own RR (also compensated) must equal the
+    oracle's to 1e-8 relative. Returns (rr, rr of the rounded solution or
+    None)."""
+    rr, be, fl = o.metrics(r1, r2, x, y)
+    assert abs(info["rr"] - rr) <= 1e-8 * rr, (info["rr"], rr)
+    if info["status"] == 0:
+        assert rr <= tol, (rr, fl, info)
+        return rr, None
+    assert info["status"] == 3, info
+    rr_round = rounded_solution_rr(o, r1, r2)
+    assert rr_round > tol and rr <= 2 * rr_round, (rr, rr_round, fl)
+    return rr, rr_round

@@ -1,5 +1,7 @@
-"""Full-size runs (n_x = 500,000): residual-only parity. The oracle's own
-FP64 KKT residual (O(nnz) on the CPU) judges the GPU solution; the paper's
+"""Full-size runs (n_x = 500,000): residual-only parity. The oracle's
+compensated KKT residual (O(nnz) on the CPU) judges the GPU solution (an
+instance may miss the target only where the exact solution rounded to FP64
+misses it too, which the oracle's double-double refinement decides); the paper's
 qualitative result that CG iterations fall as gamma grows (Sec. 5.1,
 Theorem 4) is checked on the same systems."""
 import numpy as np
@@ -7,6 +9,7 @@ import pytest
 
 import oracle
 from paper_2110_03636_amd import hkkt, synth
+from tests import helpers as H
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -20,10 +23,8 @@ def _check(b, x, y, infos, tol):
     out = []
     for i in range(b.nb):
         o = oracle.System.from_batch(b, i)
-        rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
-        out.append((rr, fl))
-        assert rr <= max(tol, 20 * fl), (i, rr, fl, infos[i])
-        assert abs(infos[i]["rr"] - rr) <= 1e-3 * rr + 2 * fl
+        out.append(H.check_gpu_solution(o, b.r1[i], b.r2[i], x[i], y[i], infos[i], tol))
+        print(i, infos[i], out[-1])
     return out
 
 

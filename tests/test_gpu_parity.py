@@ -4,10 +4,15 @@ same seeded inputs. Tolerances:
     (both are backward-stable Cholesky factors of the same permuted matrix,
     summed in different orders);
   - H_gamma^{-1} b: normwise backward error <= 1e-14 (FP64);
-  - end to end: relative KKT residual RR <= kkt_tol (1e-10), evaluated by the
-    oracle's own FP64 residual on the CPU; CG iteration count within +-2 of
-    the oracle's on the first pass; inertia equal.
+  - end to end: status 0 and relative KKT residual RR <= kkt_tol (1e-10),
+    evaluated by the oracle's own compensated residual on the CPU (accurate
+    to about u, where a plain FP64 sum errs by the floor
+    u*|| |K||z| + |r| ||/||r||); the library's RR, also compensated, equal
+    to it to 1e-8 relative; CG iteration count within +-2 per pass of the
+    oracle's; inertia equal.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -121,11 +126,11 @@ def _check_solution(b, x, y, infos, kkt_tol=1e-10, ref_iters=None):
     for i in range(b.nb):
         o = oracle.System.from_batch(b, i)
         rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
-        assert rr <= max(kkt_tol, 20 * fl), (i, rr, fl)
-        assert infos[i]["status"] == 0, infos[i]
-        # both residuals are FP64 sums in different orders: they agree to
-        # within the evaluation floor u*|| |K||z| + |r| ||/||r||
-        assert abs(infos[i]["rr"] - rr) <= 1e-3 * rr + 2 * fl
+        assert infos[i]["status"] == 0, (i, infos[i], rr, fl)
+        assert rr <= kkt_tol, (i, rr, fl)
+        # both are compensated residuals: they differ by the rounding of the
+        # final norms only
+        assert abs(infos[i]["rr"] - rr) <= 1e-8 * rr, (i, infos[i]["rr"], rr)
 
 
 @pytest.mark.parametrize("kkt_tol", [1e-8, 1e-10])
@@ -259,7 +264,9 @@ def test_breakdown_on_duplicate_row():
     s.factor_batch(b)
     rc, x, y, infos = s.solve(b.r1, b.r2)
     assert infos[0]["status"] == hkkt.CG_BREAKDOWN
-    assert s.inertia(0) == (n, m - 1, 1)
+    # the breakdown shows a zero eigenvalue, not how many: n_x positive is
+    # exact, the rest is reported undetermined
+    assert s.inertia(0) == (n, -1, -1)
 
 
 @pytest.mark.parametrize("n,m", [(1, 0), (7, 0), (2, 1), (65, 32), (130, 1)])
@@ -293,20 +300,54 @@ def test_state_errors():
     assert e.value.code == hkkt.ERR_STATE
 
 
-def test_full_size_batch_sampled():
+def test_full_size_batch_all_instances():
     """256 instances of the 20k/10k grid-like workload in one batch, mixed
-    precision, as the benchmark runs it: sampled instances checked by the
-    oracle's CPU residual."""
+    precision, as the benchmark runs it: every instance checked by the
+    oracle's compensated residual. An instance may miss 1e-10 only if the
+    exact solution rounded to FP64 misses it too (then RR can be no better
+    than that of the rounded solution: the GPU's must be within 2x of it)."""
     b = synth.workload(4)
     s = _solver(b, precision="mixed")
     rc, st, fc = s.factor_batch(b)
     assert rc == 0
     rc, x, y, infos = s.solve(b.r1, b.r2)
-    for i in (0, 1, 77, 128, 255):
+    missed = []
+    for i in range(b.nb):
         o = oracle.System.from_batch(b, i)
-        rr, be, fl = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
-        assert rr <= max(1e-10, 20 * fl), (i, rr, fl, infos[i])
-        assert infos[i]["status"] == 0
+        rr, rr_round = H.check_gpu_solution(o, b.r1[i], b.r2[i], x[i], y[i], infos[i], 1e-10)
+        if rr_round is not None:
+            print(f"instance {i}: rr {rr:.3e}, rounded exact solution {rr_round:.3e}")
+            missed.append(i)
+    assert len(missed) <= 2, missed
+
+
+def test_full_size_batch_fp64_cg_counts():
+    """The same 256 instances in FP64: every instance at RR <= 1e-10 (or at
+    its rounding limit) and the CG iterations of each within +-2 per pass of
+    the oracle's (oracle solves run on the host cores in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+    b = synth.workload(4)
+    s = _solver(b, precision="fp64")
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    perm = oracle.System.from_batch(b, 0).order_mindeg()
+
+    def orc(i):
+        o = oracle.System.from_batch(b, i)
+        o.factor(perm)
+        xo, yo, io = o.solve(b.r1[i], b.r2[i])
+        rr, _, _ = o.metrics(b.r1[i], b.r2[i], x[i], y[i])
+        return io, rr
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(orc, range(b.nb)))
+    for i, (io, rr) in enumerate(res):
+        if infos[i]["status"] == 0:
+            assert rr <= 1e-10, (i, rr)
+        else:
+            H.check_gpu_solution(oracle.System.from_batch(b, i), b.r1[i], b.r2[i], x[i], y[i], infos[i], 1e-10)
+        assert abs(infos[i]["cg_iters"] - sum(io["cg_iters"])) <= 2 * max(io["passes"], infos[i]["passes"]) + 2, \
+            (i, infos[i], io["cg_iters"])
 
 
 def test_deterministic_and_atomic_forward_agree():
@@ -351,22 +392,65 @@ def test_autotune_picks_min_cost_and_solves():
     _check_solution(b, x, y, infos)
 
 
-def test_wide_supernodes_beyond_lds():
-    """FP64 supernodes of more than 4096 rows: the work-group triangular
-    solves keep the working vector in the solve and update vectors instead
-    of LDS. End-to-end residual checked by the oracle."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_wide_supernodes_beyond_lds(precision):
+    """Supernodes of more than 4096 rows: the default (push) mode runs the
+    blocked multi-work-group solves; the deterministic (pull) mode keeps the
+    one-work-group kernels with the working vector in the solve and update
+    vectors instead of LDS. End-to-end residual checked by the oracle."""
     b = synth.dense_like(10000, seed=1234)
-    s = _solver(b)
+    s = _solver(b, precision=precision)
     assert s.stats()["max_rows"] > 4096
     assert s.factor_batch(b)[0] == 0
     rc, x, y, infos = s.solve(b.r1, b.r2)
     _check_solution(b, x, y, infos)
     # the same system in deterministic (pull) mode, which keeps the rows
     # below in the update vectors
-    s2 = _solver(b, deterministic=1)
+    s2 = _solver(b, precision=precision, deterministic=1)
     assert s2.factor_batch(b)[0] == 0
     rc, x2, y2, infos2 = s2.solve(b.r1, b.r2)
     _check_solution(b, x2, y2, infos2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_wide_supernode_hsolve_equals_oracle(precision):
+    """Supernodes of more than 1024 rows (a 1500-column root) take the
+    blocked multi-work-group solves (several diagonal blocks, rows below
+    pushed with atomics): H_gamma^{-1} b against the oracle's solve, and the
+    backward error on the dense H_gamma."""
+    b = synth.dense_like(3000, seed=4242)
+    s = _solver(b, precision=precision)
+    assert s.stats()["max_rows"] > 1024 and s.stats()["max_width"] > 2 * 256
+    assert s.factor_batch(b)[0] == 0
+    rhs = np.random.default_rng(7).standard_normal((1, b.pattern.n_x))
+    s.profile_begin()
+    x = s.hsolve(rhs)[0]
+    prof = s.profile_end()
+    assert prof["tri_wide"][1] > 2 * (s.stats()["max_width"] // 256), prof   # one launch per block
+    A = H.dense_Hgamma(b)
+    be = np.linalg.norm(A @ x - rhs[0]) / (np.linalg.norm(A, np.inf) * np.linalg.norm(x) + np.linalg.norm(rhs))
+    assert be < (1e-14 if precision == "fp64" else 1e-6), be
+    if precision == "fp64":
+        o = oracle.System.from_batch(b)
+        o.factor(o.order_mindeg())
+        xo = o.hsolve(rhs[0])
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dense_like_20k_wide_supernodes(precision):
+    """The largest member size of the uneven group's lower half: a 20k
+    dense-like system whose root supernode has about 10k columns, solved end
+    to end in FP64 and in mixed precision (FP32 wide-supernode solves),
+    judged by the oracle's compensated residual."""
+    b = synth.dense_like(20000, seed=5020)
+    s = _solver(b, precision=precision)
+    assert s.stats()["max_width"] > 8000
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    print(precision, infos[0])
+    o = oracle.System.from_batch(b)
+    H.check_gpu_solution(o, b.r1[0], b.r2[0], x[0], y[0], infos[0], 1e-10)
 
 
 def test_mixed_factor_check_routes_to_fp64():
@@ -377,4 +461,41 @@ def test_mixed_factor_check_routes_to_fp64():
     assert s.factor_batch(b)[0] == 0
     rc, x, y, infos = s.solve(b.r1, b.r2)
     assert all(i["fp64_fallback"] == 1 for i in infos)
+    _check_solution(b, x, y, infos)
+
+
+def test_autotune_failed_trial_restores_context():
+    """A trial that fails (here: trial solves without r2 while m > 0) returns
+    its error and leaves the context's schedule, analysis and profiling state
+    as they were; the context still factors and solves."""
+    b = synth.grid_like(2000, nb=2, seed=41, gammas=(1e4,), dx_exp=6.0)
+    s = _solver(b, precision="mixed", relax=2, autotune_cache=0)
+    before = s.schedule()
+    stats = s.stats()
+    with pytest.raises(hkkt.HKKTError) as e:
+        s.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma, b.r1, None)
+    assert e.value.code == hkkt.ERR_ARG
+    assert s.schedule() == before and s.stats() == stats
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
+
+
+def test_schedule_set_and_autotune_cache():
+    """set_schedule applies a (relax, width, staged) triple; with the cache
+    on, a second autotune of the same pattern, precision and batch size
+    applies the first choice without timing (costs NaN)."""
+    b = synth.grid_like(2000, nb=2, seed=42, gammas=(1e4,), dx_exp=6.0)
+    s = _solver(b, precision="mixed")
+    s.set_schedule(0, 8, 0)
+    assert s.schedule() == (0, 8, 0)
+    assert s.stats()["supernodes"] == hkkt.Symbolic.from_pattern(b.pattern, relax=0).stats()["supernodes"]
+    r1 = s.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma)
+    s2 = _solver(b, precision="mixed")
+    r2 = s2.autotune(b.H_val, b.D_x, b.J_val, b.delta, b.gamma)
+    assert (r2["relax"], r2["tree_width"], r2["tree_staged"]) == (r1["relax"], r1["tree_width"], r1["tree_staged"])
+    assert all(np.isnan(c[3]) for c in r2["cost_ms"])
+    assert s2.schedule() == (r1["relax"], r1["tree_width"], r1["tree_staged"])
+    assert s2.factor_batch(b)[0] == 0
+    rc, x, y, infos = s2.solve(b.r1, b.r2)
     _check_solution(b, x, y, infos)
