@@ -129,3 +129,17 @@ def check_gpu_solution(o, r1, r2, x, y, info, tol):
     rr_round = rounded_solution_rr(o, r1, r2)
     assert rr_round > tol and rr <= 2 * rr_round, (rr, rr_round, fl)
     return rr, rr_round
+
+
+def cg_count_tol(oracle_per_pass, gpu_passes):
+    """Bound on |GPU CG iterations - oracle CG iterations| for one solve.
+    Both run the same unpreconditioned CG with the same stopping rule, but
+    their triangular solves and dot products round in different orders, and
+    in floating point the iteration at which the recurrence residual crosses
+    the tolerance shifts with the rounding (loss of orthogonality delays
+    convergence by an amount that depends on the rounding errors, more so the
+    longer the run). Per pass: 2 iterations, or 3% of the oracle's count for
+    that pass when larger; 2 more for every pass the GPU runs beyond the
+    oracle's, and 2 overall."""
+    tol = sum(max(2, int(np.ceil(0.03 * k))) for k in oracle_per_pass)
+    return tol + 2 + 2 * max(0, gpu_passes - len(oracle_per_pass))

@@ -148,7 +148,7 @@ def test_solve_workload1_equals_oracle(kkt_tol):
     zo = np.concatenate([xo, yo])
     # forward error is bounded by cond(K)*RR only; report-level check
     assert np.linalg.norm(z - zo) / np.linalg.norm(zo) < 1e-4
-    assert abs(infos[0]["cg_iters"] - sum(io["cg_iters"])) <= 2 * io["passes"] + 2
+    assert abs(infos[0]["cg_iters"] - sum(io["cg_iters"])) <= H.cg_count_tol(io["cg_iters"], infos[0]["passes"])
     assert s.inertia(0) == io["inertia"] == (1200, 600, 0)
 
 
@@ -187,7 +187,7 @@ def test_solve_batch_grid_fp64():
         o.factor(o.order_mindeg())
         xo, yo, io = o.solve(b.r1[i], b.r2[i])
         assert io["status"] == 0
-        assert abs(infos[i]["cg_iters"] - sum(io["cg_iters"])) <= 2 * io["passes"] + 2
+        assert abs(infos[i]["cg_iters"] - sum(io["cg_iters"])) <= H.cg_count_tol(io["cg_iters"], infos[i]["passes"])
 
 
 def test_solve_batch_mixed_reaches_target():
@@ -323,8 +323,9 @@ def test_full_size_batch_all_instances():
 
 def test_full_size_batch_fp64_cg_counts():
     """The same 256 instances in FP64: every instance at RR <= 1e-10 (or at
-    its rounding limit) and the CG iterations of each within +-2 per pass of
-    the oracle's (oracle solves run on the host cores in parallel)."""
+    its rounding limit) and the CG iterations of each within the rounding
+    bound of helpers.cg_count_tol of the oracle's (oracle solves run on the
+    host cores in parallel)."""
     from concurrent.futures import ThreadPoolExecutor
     b = synth.workload(4)
     s = _solver(b, precision="fp64")
@@ -341,13 +342,17 @@ def test_full_size_batch_fp64_cg_counts():
 
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         res = list(ex.map(orc, range(b.nb)))
+    off = []
     for i, (io, rr) in enumerate(res):
         if infos[i]["status"] == 0:
             assert rr <= 1e-10, (i, rr)
         else:
             H.check_gpu_solution(oracle.System.from_batch(b, i), b.r1[i], b.r2[i], x[i], y[i], infos[i], 1e-10)
-        assert abs(infos[i]["cg_iters"] - sum(io["cg_iters"])) <= 2 * max(io["passes"], infos[i]["passes"]) + 2, \
-            (i, infos[i], io["cg_iters"])
+        d = infos[i]["cg_iters"] - sum(io["cg_iters"])
+        if abs(d) > H.cg_count_tol(io["cg_iters"], infos[i]["passes"]):
+            off.append((i, d, infos[i]["cg_iters"], io["cg_iters"]))
+    print("CG counts outside the bound (instance, gpu - oracle, gpu, oracle per pass):", off)
+    assert not off
 
 
 def test_deterministic_and_atomic_forward_agree():
