@@ -296,6 +296,29 @@ int hkkt_get_factor(hkkt_ctx *ctx, int b, int64_t *colptr, int32_t *rowind, doub
  * Vectors [nb][n_x], per pointer mode. For parity tests. */
 int hkkt_hsolve(hkkt_ctx *ctx, int nb, const double *b, double *x);
 
+/* Allocation-free form of hkkt_hsolve, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same triangular-solve kernels, with their
+ * working vectors (the permuted right-hand side, the solve vector and, with
+ * deterministic = 1, the update vectors) in a fixed device array of the
+ * library (64 MiB per GPU, set up by hkkt_create and held until the process
+ * ends) instead of library-allocated buffers. Needs pointer_mode =
+ * HKKT_PTR_DEVICE: b [nb][n_x] and x [nb][n_x] are device pointers in the
+ * original order, nb equal to the last factorization's. It allocates, frees
+ * and synchronises nothing: the work is enqueued on the context's stream and
+ * x is written when the stream reaches it. The staged tree kernel's panel
+ * copy is used only if an earlier hkkt_solve/hkkt_hsolve after the last
+ * factorization built it; otherwise the levels it would cover run in the
+ * global-memory tree kernel (same solution up to rounding). Per-kernel
+ * profiling is suspended during the call. Returns -1 for host pointer mode
+ * or when 8*nb*n_x + (4 or 8)*nb*n_x (+ the update vectors) exceeds 64 MiB
+ * (each part rounded up to 256 bytes), -3 if not factored or nb differs.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other contexts or streams) race and must be serialised by the
+ * caller; the array keeps the last call's contents, and every entry a call
+ * reads is written by it first. */
+int hkkt_hsolve_noalloc(hkkt_ctx *ctx, int nb, const double *b, double *x);
+
 /* Time spent in the phases of the last calls (milliseconds, host clock
  * around stream-synchronised phases): [0] analyze, [1] assemble+factor,
  * [2] solve, [3] fp64 fallback. */

@@ -129,21 +129,30 @@ struct ProfScope {
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool owned = true;   // false: a view of memory owned elsewhere (never freed or grown here)
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
     void ensure(size_t b) {
         if (b <= bytes && p) return;
+        if (!owned) throw Error(HKKT_ERR_STATE, "a borrowed device buffer is too small (no allocation allowed)");
         release();
         if (b == 0) b = 16;
         HIPCHK(hipMalloc(&p, b));
         bytes = b;
+    }
+    void view(void* q, size_t b) {
+        release();
+        p = q;
+        bytes = b;
+        owned = false;
     }
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
@@ -891,7 +900,9 @@ static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* ids, int nids, con
     const int lo = tree_lo(c->dev, S.nlevels);
     int pmax = 0;
     const int lo2 = lo < S.nlevels ? tree2_lo<T>(c, lo, &pmax) : S.nlevels;
-    if (lo2 < S.nlevels) {
+    // a borrowed solve copy (allocation-free calls) is used only when it is
+    // current; building it would allocate
+    if (lo2 < S.nlevels && (B.Lt.owned || B.lt_lo == lo2)) {
         for (i32 l = 0; l < lo2; l++) launch_tri_level<T>(c, B, l, true, ids, nids, st_);
         launch_tree2<T>(c, B, lo2, pmax, ids, nids, st_);
         for (i32 l = lo2 - 1; l >= 0; l--) launch_tri_level<T>(c, B, l, false, ids, nids, st_);
@@ -1381,6 +1392,35 @@ static int apply_schedule(hkkt_ctx* c, int relax, int width, int stage) {
     return HKKT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free entry point: a file-scope device array, one
+// copy per GPU, alive until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): its
+// device address is looked up once per device, with that device current, in
+// hkkt_create, and kept per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;
+
+// address of `scratch` on device dev (the current device); 0 or a HIP error
+static hipError_t scratch_lookup(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_addr.count(dev)) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = ptr;
+    return hipSuccess;
+}
+
+static void* scratch_addr(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    return it == g_scratch_addr.end() ? nullptr : it->second;
+}
+
 extern "C" {
 
 void hkkt_default_options(hkkt_options* o) {
@@ -1417,6 +1457,7 @@ int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && v > 0)
             c->lds_max = v;
     }
+    if (scratch_lookup(c->device) != hipSuccess) { delete c; return HKKT_ERR_DEVICE; }
     c->main.prec = c->opt.precision;
     c->fb.prec = HKKT_FP64;
     // the fallback stream: default priority, no implicit ordering with the caller's stream
@@ -2191,6 +2232,77 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                               st));
         HIPCHK(hipStreamSynchronize(st));
+        return HKKT_OK;
+    })
+}
+
+int hkkt_hsolve_noalloc(hkkt_ctx* c, int nb, const double* bvec, double* x) {
+    if (!c || !bvec || !x) return HKKT_ERR_ARG;
+    if (c->opt.pointer_mode != HKKT_PTR_DEVICE) {
+        c->err = "hkkt_hsolve_noalloc takes device pointers only (pointer_mode = HKKT_PTR_DEVICE)";
+        return HKKT_ERR_ARG;
+    }
+    if (!c->factored || nb != c->nb) { c->err = "hkkt_hsolve_noalloc: not factored, or nb differs"; return HKKT_ERR_STATE; }
+    ABI_GUARD(c, {
+        const Symbolic& S = c->sym.S;
+        Batch& M = c->main;
+        // update vectors: read and written by the pull-mode forward solves,
+        // and by the push-mode work-group solves when the blocked ones are off
+        const bool need_uv = c->opt.deterministic != 0 || !ws_on();
+        const size_t esz = M.esz();
+        auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t vec = (size_t)nb * S.n;
+        const size_t o_x = up(vec * 8);                                   // FP64 permuted vector first
+        const size_t o_uv = o_x + up(vec * esz);                          // then the solve vector
+        const size_t need = o_uv + (need_uv ? up((size_t)nb * std::max<i64>(1, S.UVsize) * esz) : 0);
+        if (need > kScratchBytes) {
+            c->err = "hkkt_hsolve_noalloc: needs " + std::to_string(need) + " bytes of scratch, the maximum is " +
+                     std::to_string(kScratchBytes) + " (nb * n_x too large)";
+            return HKKT_ERR_ARG;
+        }
+        unsigned char* base = static_cast<unsigned char*>(scratch_addr(c->device));
+        if (!base) { c->err = "scratch not set up on this device"; return HKKT_ERR_DEVICE; }
+        // a view of the factor and of the scratch: nothing is allocated,
+        // grown or freed through it
+        Batch V;
+        V.nb = nb;
+        V.prec = M.prec;
+        V.stream = c->stream;
+        V.L.view(M.L.p, M.L.bytes);
+        V.Dinv.view(M.Dinv.p, M.Dinv.bytes);
+        V.Lt.view(M.Lt.p, M.Lt.bytes);
+        V.lt_lo = M.lt_lo;
+        V.lt_base = M.lt_base;
+        V.lt_size = M.lt_size;
+        V.rhat.view(base, o_x);
+        V.X.view(base + o_x, o_uv - o_x);
+        if (need_uv) V.UV.view(base + o_uv, need - o_uv);
+        const bool prof_on = c->prof.on;   // no event records (their pool may grow)
+        c->prof.on = false;
+        struct Restore {
+            hkkt_ctx* c;
+            bool on;
+            ~Restore() { c->prof.on = on; }
+        } restore{c, prof_on};
+        hipStream_t st = c->stream;
+        const unsigned gn = grid1(S.n, 4096);
+        LAUNCH(10, k_perm_gather, dim3(gn, nb), dim3(kBlock), 0, st, c->dev.v.perm, bvec, V.rhat.as<double>(),
+               (i64)S.n);
+        if (V.prec == HKKT_MIXED) {
+            LAUNCH(10, (k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, (const double*)V.rhat.as<double>(),
+                   V.X.as<float>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+            launch_trisolve<float>(c, V, nullptr, nb, nullptr);
+            LAUNCH(10, (k_cast<float, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const float*)V.X.as<float>(),
+                   V.rhat.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+        } else {
+            LAUNCH(10, (k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const double*)V.rhat.as<double>(),
+                   V.X.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+            launch_trisolve<double>(c, V, nullptr, nb, nullptr);
+            LAUNCH(10, (k_cast<double, double>), dim3(gn, nb), dim3(kBlock), 0, st, (const double*)V.X.as<double>(),
+                   V.rhat.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+        }
+        LAUNCH(10, k_perm_scatter, dim3(gn, nb), dim3(kBlock), 0, st, c->dev.v.perm, (const double*)V.rhat.as<double>(),
+               x, (i64)S.n);
         return HKKT_OK;
     })
 }

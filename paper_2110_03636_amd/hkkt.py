@@ -25,7 +25,7 @@ EXPORTS = [
     "hkkt_symbolic_create", "hkkt_symbolic_destroy", "hkkt_get_symbolic", "hkkt_symbolic_stats",
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
-    "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule",
+    "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule", "hkkt_hsolve_noalloc",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged"]
@@ -107,6 +107,7 @@ def lib():
         L.hkkt_symbolic_supernodes.argtypes = [V, V, V, V, V, V, V]
         L.hkkt_get_factor.argtypes = [V, C.c_int, V, V, V]
         L.hkkt_hsolve.argtypes = [V, C.c_int, V, V]
+        L.hkkt_hsolve_noalloc.argtypes = [V, C.c_int, V, V]
         L.hkkt_timings.argtypes = [V, V]
         L.hkkt_profile_begin.argtypes = [V]
         L.hkkt_profile_end.argtypes = [V, V, V]
@@ -451,6 +452,13 @@ class Solver(_SymbolicView):
         B = self._arr(bvec, self.nb, self.n)
         x = self._out(self.nb, self.n)
         _check(lib().hkkt_hsolve(self._ctx, self.nb, _ptr(B), _ptr(x)), self._ctx)
+        return x
+
+    def hsolve_noalloc(self, bvec, x):
+        """The allocation-free form of hsolve: bvec and x are caller-owned
+        float64 CUDA tensors [nb, n_x] (device=True contexts only); x is
+        written when the context's stream reaches the enqueued work."""
+        _check(lib().hkkt_hsolve_noalloc(self._ctx, self.nb, _ptr(bvec), _ptr(x)), self._ctx)
         return x
 
     def timings(self):
