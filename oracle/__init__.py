@@ -71,6 +71,11 @@ def lib():
         L.orc_hybrid_once.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.POINTER(C.c_int)]
         L.orc_apply_K.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
         L.orc_residual.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p, f64p, f64p, f64p, f64p]
+        L.orc_set_delta.argtypes = [C.c_void_p, C.c_double]
+        L.orc_factor_regularized.restype = C.c_int
+        L.orc_factor_regularized.argtypes = [C.c_void_p, i32p, f64p, C.c_double, f64p, i64p]
+        L.orc_gamma_heuristic.restype = C.c_double
+        L.orc_gamma_heuristic.argtypes = [C.c_void_p]
         L.orc_refine_dd.restype = C.c_int64
         L.orc_refine_dd.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.c_int64, f64p]
         _lib = L
@@ -137,6 +142,23 @@ class System:
             st = lib().orc_factor(self._h, _p(pa, i32p), _p(fc, i64p))
         self.perm = None if perm is None else np.asarray(perm, np.int32)
         return int(st), int(fc[0])
+
+    def factor_regularized(self, perm=None, delta_min=1e-9, delta_max=1e-6):
+        """Algorithm 1's Cholesky attempts with delta1 regularization.
+        Returns (status, delta1, delta_min after the loop, fail_col); the
+        system keeps delta + delta1."""
+        dm = np.array([delta_min], np.float64)
+        d1 = np.zeros(1)
+        fc = np.zeros(1, np.int64)
+        pa = None if perm is None else _c(perm, np.int32)
+        st = lib().orc_factor_regularized(self._h, None if pa is None else _p(pa, i32p), _p(dm, f64p),
+                                          float(delta_max), _p(d1, f64p), _p(fc, i64p))
+        self.perm = None if perm is None else np.asarray(perm, np.int32)
+        return int(st), float(d1[0]), float(dm[0]), int(fc[0])
+
+    def gamma_heuristic(self):
+        """||H + D_x + delta I||_inf / ||J||_inf^2."""
+        return float(lib().orc_gamma_heuristic(self._h))
 
     def L(self):
         nz = lib().orc_L_nnz(self._h)

@@ -745,3 +745,69 @@ void orc_apply_K(const orc *s, const double *x, const double *y, double *o1, dou
     for (i64 i = 0; i < m; i++) o2[i] = -o2[i];
     free(z1); free(z2);
 }
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1's regularization of the (1,1) block, and the gamma      */
+/* heuristic of Sec. 3                                                 */
+/* ------------------------------------------------------------------ */
+
+/* K's (1,1) block regularization becomes delta (re-assembles H_gamma; the
+ * factor is dropped). */
+void orc_set_delta(orc *s, double delta) {
+    free_factor(s);
+    free(s->Ap); free(s->Ai); free(s->Ax);
+    s->Ap = NULL; s->Ai = NULL; s->Ax = NULL;
+    s->delta = delta;
+    assemble(s);
+}
+
+/* Algorithm 1, Sec. 4.1: Cholesky of H_gamma with the system's delta; while
+ * it fails and delta1 <= delta_max / 2, the first retry takes delta1 =
+ * delta_min, every later one doubles delta_min and takes delta1 = delta_min
+ * (so delta_min carries the last value tried into the next matrix of a
+ * sequence). The system keeps delta + delta1 as its (1,1) regularization:
+ * the solve then works on the perturbed system, as Algorithm 1's solves
+ * do. Returns 0 (factored) or 1 (still not positive definite: the caller's
+ * fail-safe), with *delta1 the last value tried and *fail_col the failing
+ * pivot of the last attempt. */
+int orc_factor_regularized(orc *s, const i32 *perm, double *delta_min, double delta_max, double *delta1,
+                           i64 *fail_col) {
+    const double base = s->delta;
+    double d1 = 0.0;
+    int st = orc_factor(s, perm, fail_col);
+    while (st != 0 && d1 <= delta_max / 2) {
+        if (d1 == 0.0) d1 = *delta_min;
+        else { *delta_min = 2.0 * *delta_min; d1 = *delta_min; }
+        orc_set_delta(s, base + d1);
+        st = orc_factor(s, perm, fail_col);
+    }
+    *delta1 = d1;
+    return st;
+}
+
+/* gamma = ||Htilde|| / ||J||^2 (Sec. 3, after Golub and Greif), with the
+ * infinity norm standing in for the 2-norm as in Sec. 5.1 and Htilde the
+ * system's (1,1) block H + D_x + delta I. Returns 0 when J is empty or
+ * zero. */
+double orc_gamma_heuristic(const orc *s) {
+    i64 n = s->n, m = s->m;
+    double *rs = xcalloc((size_t)(n ? n : 1), sizeof(double));
+    for (i64 i = 0; i < n; i++) {
+        int has = 0;
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+            i64 j = s->Hi[p];
+            if (j == i) { rs[i] += fabs(s->Hx[p] + s->Dx[i] + s->delta); has = 1; }
+            else { rs[i] += fabs(s->Hx[p]); rs[j] += fabs(s->Hx[p]); }
+        }
+        if (!has) rs[i] += fabs(s->Dx[i] + s->delta);
+    }
+    double hn = 0.0, jn = 0.0;
+    for (i64 i = 0; i < n; i++) if (rs[i] > hn) hn = rs[i];
+    for (i64 i = 0; i < m; i++) {
+        double r = 0.0;
+        for (i64 p = s->Jp[i]; p < s->Jp[i + 1]; p++) r += fabs(s->Jx[p]);
+        if (r > jn) jn = r;
+    }
+    free(rs);
+    return jn > 0.0 ? hn / (jn * jn) : 0.0;
+}

@@ -675,3 +675,116 @@ def test_order_is_exact_minimum_degree(gen, seed):
     A = H.csc_to_dense_lower(cp, ri, np.ones_like(v), n) != 0
     A = A | A.T
     assert s.order_mindeg().tolist() == _mindeg_bruteforce(A)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1's regularization (Sec. 4.1) and the gamma heuristic (Sec. 3)
+# --------------------------------------------------------------------------
+
+def _system_with_hgamma_spectrum(n, m, lam, gamma, seed):
+    """A system whose assembled H_gamma = H + D_x + delta I + gamma J^T J is
+    Q diag(lam) Q^T (Q random orthogonal): H is chosen to make it so."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    target = Q @ np.diag(lam) @ Q.T
+    target = (target + target.T) / 2
+    J = rng.standard_normal((m, n)) if m else np.zeros((0, n))
+    Dx = 10 ** rng.uniform(-1, 0, n)
+    Hd = target - np.diag(Dx) - gamma * J.T @ J
+    return H.batch_from_dense(Hd, Dx, J, 0.0, gamma, rng.standard_normal(n), rng.standard_normal(m)), target
+
+
+def _first_success(target, delta_min, delta_max):
+    """Algorithm 1's delta1 sequence decided by the dense eigenvalues (and
+    LAPACK's Cholesky): (succeeded, delta1, delta_min after)."""
+    def spd(d):
+        ok_eig = np.linalg.eigvalsh(target + d * np.eye(target.shape[0])).min() > 0
+        try:
+            sla.cholesky(target + d * np.eye(target.shape[0]), lower=True)
+            ok_chol = True
+        except np.linalg.LinAlgError:
+            ok_chol = False
+        assert ok_eig == ok_chol      # the cases keep a clear margin
+        return ok_eig
+    d1 = 0.0
+    ok = spd(d1)
+    while not ok and d1 <= delta_max / 2:
+        if d1 == 0.0:
+            d1 = delta_min
+        else:
+            delta_min *= 2
+            d1 = delta_min
+        ok = spd(d1)
+    return ok, d1, delta_min
+
+
+@pytest.mark.parametrize("n,m,lam_min,dmin,expect", [
+    (9, 0, -3e-9, 1e-9, 4e-9),        # three doublings past delta_min
+    (9, 3, -3e-9, 1e-9, 4e-9),        # the same through gamma J^T J
+    (9, 3, -3e-9, 4e-9, 4e-9),        # delta_min carried from an earlier matrix: first retry succeeds
+    (9, 3, 2.0, 1e-9, 0.0),           # already SPD: delta1 = 0
+    (9, 3, -7e-7, 1e-9, 5.12e-7),     # beyond delta_max / 2: fails after 5.12e-7
+])
+def test_regularization_delta1_equals_dense_first_success(n, m, lam_min, dmin, expect):
+    lam = np.concatenate([[lam_min], np.linspace(1.0, 3.0, n - 1)])
+    b, target = _system_with_hgamma_spectrum(n, m, lam, 1e2, seed=91 + m)
+    ok, d1_ref, dmin_ref = _first_success(target, dmin, 1e-6)
+    assert d1_ref == pytest.approx(expect, rel=1e-12, abs=0)
+    s = _sys(b)
+    st, d1, dmin_out, fc = s.factor_regularized(None, delta_min=dmin, delta_max=1e-6)
+    assert (st == 0) == ok
+    assert d1 == d1_ref and dmin_out == dmin_ref
+    if ok:   # the perturbed system is solved: its residual includes delta1
+        # (S inherits H_delta's 1e-9 eigenvalue: CG needs more than m = 3
+        # iterations in floating point)
+        x, y, info = s.solve(b.r1[0], b.r2[0], max_cg=50)
+        Kd = H.dense_K(b) + np.diag(np.r_[np.full(n, d1), np.zeros(m)])
+        r = np.r_[b.r1[0], b.r2[0]]
+        z = np.r_[x, y]
+        # at most the residual the rounded exact solution can have (H_delta's
+        # 1e-9 eigenvalue makes ||z|| ~ 1e9 ||r|| when m = 0)
+        bound = max(1e-9, 10 * 2.0 ** -53 * np.linalg.norm(np.abs(Kd) @ np.abs(z)) / np.linalg.norm(r))
+        assert np.linalg.norm(Kd @ z - r) / np.linalg.norm(r) < bound
+
+
+def test_gamma_heuristic_equals_dense_norms():
+    for gen, seed in (("dense", 95), ("grid", 96)):
+        b = H.tiny_dense_like(60, seed) if gen == "dense" else H.tiny_grid_like(300, seed, dx_exp=3.0)
+        Hd = H.dense_H(b) + np.diag(b.D_x[0] + b.delta[0])
+        Jd = H.dense_J(b)
+        want = np.abs(Hd).sum(1).max() / np.abs(Jd).sum(1).max() ** 2
+        assert _sys(b).gamma_heuristic() == pytest.approx(want, rel=1e-13)
+
+
+def test_delta2_restart_equals_dense_perturbed_schur():
+    """After a breakdown (duplicate J row, inconsistent r2) CG restarts on
+    S + delta2 I (Algorithm 1): the pass returns y = (S + delta2 I)^{-1} b,
+    x = H_gamma^{-1}(rhat - J^T y), with S, b and rhat formed densely."""
+    rng = np.random.default_rng(97)
+    n, m = 16, 5
+    J = rng.standard_normal((m, n))
+    J[3] = J[1]
+    B = rng.standard_normal((n, n))
+    Hd = B.T @ B / n
+    Dx = 10 ** rng.uniform(-1, 1, n)
+    gamma, d2 = 1e2, 1e-6
+    b = H.batch_from_dense(Hd, Dx, J, 0.0, gamma, rng.standard_normal(n), rng.standard_normal(m))
+    s = _sys(b)
+    s.factor(None)
+    x, y, it, brk = s.hybrid_once(b.r1[0], b.r2[0], delta2=d2, max_cg=100)
+    assert brk
+    Hg = Hd + np.diag(Dx) + gamma * J.T @ J
+    rhat = b.r1[0] + gamma * J.T @ b.r2[0]
+    S = J @ np.linalg.solve(Hg, J.T)
+    bv = J @ np.linalg.solve(Hg, rhat) - b.r2[0]
+    ys = np.linalg.solve(S + d2 * np.eye(m), bv)
+    xs = np.linalg.solve(Hg, rhat - J.T @ ys)
+    # y is fixed up to kappa(S + delta2 I) ~ 1e6 times CG's tolerance: its
+    # residual on the perturbed Schur system is the sharp check; x depends on
+    # J^T y only, which the null direction of J^T does not move
+    assert np.linalg.norm((S + d2 * np.eye(m)) @ y - bv) / np.linalg.norm(bv) < 1e-9
+    assert np.linalg.norm(y - ys) / np.linalg.norm(ys) < 1e-4
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
+    # the full solve stops after the pass that broke down
+    x2, y2, info = s.solve(b.r1[0], b.r2[0], delta2=d2, max_cg=100)
+    assert info["passes"] == 1 and info["status"] in (0, 3) and info["inertia"] == (n, -1, -1)
