@@ -80,7 +80,9 @@ typedef struct {
     double cg_tol_mixed;    /* inner CG tolerance when the operator is FP32 (default 1e-5) */
     double kkt_tol;         /* target relative KKT residual ||r - K z||_2 / ||r||_2 */
     double quad_form_eps;   /* breakdown if p'q <= eps*||p||^2*(p0'q0/||p0||^2) (default 1e-14) */
-    double delta2;          /* 0: report CG_BREAKDOWN; > 0: restart CG on S + delta2*I (Algorithm 1) */
+    double delta2;          /* 0: report CG_BREAKDOWN; > 0: restart CG on S + delta2*I (Algorithm 1);
+                               either way a breakdown ends the solve after that pass (status 0 or 3
+                               with delta2 > 0, 2 without) */
     int max_cg;             /* <= 0: min(m, 1000) */
     int max_refine;         /* refinement passes after the first (default 10) */
     int ordering;           /* 0 = own approximate minimum degree (Sec. 5.3), 1 = natural */
@@ -97,7 +99,12 @@ typedef struct {
                                this process for the same pattern (hash of the analysed pattern,
                                group layout and given order), precision and batch size instead
                                of timing again; 0: always time */
-    int reserved;
+    int scaling;            /* reserved for equilibration of K (0 = none) */
+    double mixed_pivot_tol; /* mixed precision: an FP32 factor whose smallest ratio of pivot L_jj^2
+                               to the assembled FP64 diagonal a_jj of H_gamma is below this is
+                               replaced by an FP64 factor at factor time (the FP32 success does not
+                               show that H_gamma is positive definite, Algorithm 1's test);
+                               0 turns the test off (default 2^-16) */
 } hkkt_options;
 
 typedef struct {
@@ -114,7 +121,7 @@ typedef struct {
 /* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
  * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5,
- * autotune_cache 1. */
+ * autotune_cache 1, scaling 0, mixed_pivot_tol 2^-16. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream
@@ -211,6 +218,38 @@ int hkkt_set_schedule(hkkt_ctx *ctx, const int32_t choice[3]);
 int hkkt_factor_batch(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
                       const double *J_val, const double *delta, const double *gamma,
                       int *status, int64_t *fail_col);
+
+/* Algorithm 1's regularization of the (1,1) block around the Cholesky
+ * attempt (Sec. 4.1), per (instance, member): factor with delta; while the
+ * factorization fails and delta1 <= delta_max / 2, retry with delta + delta1,
+ * where the first retry takes delta1 = delta_min[i] and every later one
+ * doubles delta_min[i] and takes delta1 = delta_min[i]. delta_min (host,
+ * [nb*G], every entry > 0) is in/out: it carries the last value tried into
+ * the next matrix of a sequence (the listing's in-place update of
+ * delta_min). delta1 (host, [nb*G]) gets the regularization used (0 when the
+ * first attempt succeeded); status/fail_col as for hkkt_factor_batch, of the
+ * last attempt (NOT_SPD left = Algorithm 1's fail-safe branch: the caller's
+ * LDL^T or a return to the optimizer). The context then holds the factor of
+ * H_gamma + (delta + delta1) I, and hkkt_solve_batch solves the perturbed
+ * system K with delta + delta1 in its (1,1) block, as Algorithm 1 does. Each
+ * retry refactors the whole batch (instances that succeeded get the same
+ * factor again). Other arguments as for hkkt_factor_batch. Returns as
+ * hkkt_factor_batch for the last attempt; -1 if delta_min <= 0 or
+ * delta_max < 0. */
+int hkkt_factor_regularized(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
+                            const double *J_val, const double *delta, const double *gamma,
+                            double *delta_min, double delta_max, double *delta1,
+                            int *status, int64_t *fail_col);
+
+/* The gamma heuristic of Sec. 3 (Golub and Greif): gamma = ||Htilde|| /
+ * ||J||^2 per (instance, member), with Htilde = H + D_x + delta I and the
+ * infinity norm standing in for the 2-norm (as Sec. 5.1 does for ||K||);
+ * 0 when J is empty or zero. Values as for hkkt_factor_batch (no gamma);
+ * gamma_out host [nb*G]. It loads the values into the context's batch on
+ * the device, so the current factorization is dropped (factor again before
+ * solving). Returns 0, or -3 if not analysed. */
+int hkkt_gamma_heuristic(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
+                         const double *J_val, const double *delta, double *gamma_out);
 
 /* Single-instance form of hkkt_factor_batch. */
 int hkkt_factor(hkkt_ctx *ctx, const double *H_val, const double *D_x, const double *J_val,

@@ -1006,6 +1006,29 @@ static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h
 }
 
 // ---------------------------------------------------------------------------
+// min over the columns of L_jj^2 / a_jj (the pivot against the assembled FP64
+// diagonal of H_gamma) of B's factor, per (entry, member)
+// ---------------------------------------------------------------------------
+template <typename T>
+static std::vector<double> pivot_ratio(hkkt_ctx* c, Batch& B) {
+    const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
+    hipStream_t st = B.stream;
+    const int nb = B.nb, G = S.G;
+    alloc_solve(c, B);
+    const unsigned nbr = (unsigned)D.v.nbr;
+    LAUNCH(10, k_pivot_ratio<T>, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(), (const T*)B.Dinv.as<T>(),
+           B.part1.as<double>());
+    LAUNCH(10, k_reduce_max, dim3(nb, G), dim3(64), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
+           D.v.rblk_off, B.rowred.as<double>(), -INFINITY);
+    std::vector<double> r((size_t)nb * G);
+    HIPCHK(hipMemcpyAsync(r.data(), B.rowred.p, r.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (double& v : r) v = -v;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
 // relative residual ||v - H_gamma M^{-1} v|| / ||v|| of B's FP32 factor M per
 // (entry, member), for a fixed probe vector v: above about 1 the FP32 factor
 // cannot drive refinement down (an FP32 pass would stall)
@@ -1239,9 +1262,11 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
             s.passes++;
             s.cg += hst[i].it;
             s.rr = rr;
-            if (hst[i].breakdown && o.delta2 == 0.0) {
+            if (hst[i].breakdown) {
+                // Algorithm 1: a breakdown ends the solve; with delta2 > 0 the
+                // pass already restarted CG on S + delta2 I
                 s.brk = 1;
-                s.status = HKKT_CG_BREAKDOWN;
+                s.status = o.delta2 == 0.0 ? HKKT_CG_BREAKDOWN : (rr <= o.kkt_tol ? HKKT_OK : HKKT_NOT_CONVERGED);
                 act[i] = 0;
             } else if (rr <= o.kkt_tol) {
                 s.status = HKKT_OK;
@@ -1440,6 +1465,8 @@ void hkkt_default_options(hkkt_options* o) {
     o->mixed_check = 0;
     o->mixed_check_tol = 0.5;
     o->autotune_cache = 1;
+    o->scaling = 0;
+    o->mixed_pivot_tol = 0x1p-16;
 }
 
 int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
@@ -1801,8 +1828,12 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         std::vector<int> fpos(nc, INT_MAX);
         // mixed precision: entries whose FP32 factor cannot drive refinement
         // (probe residual above mixed_check_tol) go to the FP64 refactor now
-        std::vector<double> rho;
+        std::vector<double> rho, piv;
         if (c->opt.precision == HKKT_MIXED && c->opt.mixed_check) rho = fp32_factor_quality(c, c->main);
+        // an FP32 pivot that is a small fraction of its FP64 diagonal is
+        // mostly rounding: the FP32 factorization's success does not show
+        // that H_gamma is positive definite, so FP64 decides
+        if (c->opt.precision == HKKT_MIXED && c->opt.mixed_pivot_tol > 0) piv = pivot_ratio<float>(c, c->main);
         static const bool trace = std::getenv("HKKT_TRACE") != nullptr;
         for (int b = 0; b < nb; b++) {
             bool any = false, weak = false;
@@ -1812,6 +1843,10 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
                 if (!rho.empty()) {
                     weak = weak || !(rho[i] <= c->opt.mixed_check_tol);
                     if (trace) std::fprintf(stderr, "hkkt: fp32 factor check inst=%zu rho=%.3e\n", i, rho[i]);
+                }
+                if (!piv.empty() && c->main.h_fail[i] == INT_MAX) {
+                    weak = weak || !(piv[i] >= c->opt.mixed_pivot_tol);
+                    if (trace) std::fprintf(stderr, "hkkt: fp32 pivot ratio inst=%zu min=%.3e\n", i, piv[i]);
                 }
             }
             if (!any && !weak) continue;
@@ -1847,6 +1882,80 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         c->factored = true;
         c->ms[1] = now_ms() - t0;
         return rc;
+    })
+}
+
+int hkkt_factor_regularized(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J,
+                            const double* delta, const double* gamma, double* delta_min, double delta_max,
+                            double* delta1, int* status, int64_t* fail_col) {
+    if (!c) return HKKT_ERR_ARG;
+    if (!c->analysed) { c->err = "factor before analyze"; return HKKT_ERR_STATE; }
+    if (nb < 1 || !delta || !delta_min || !delta1 || !(delta_max >= 0.0)) {
+        c->err = "bad regularized factor arguments";
+        return HKKT_ERR_ARG;
+    }
+    const size_t nc = (size_t)nb * c->sym.S.G;
+    for (size_t i = 0; i < nc; i++)
+        if (!(delta_min[i] > 0.0)) { c->err = "delta_min must be positive"; return HKKT_ERR_ARG; }
+    std::vector<double> d1(nc, 0.0), deff(nc);
+    std::vector<int> st(nc, 0);
+    std::vector<int64_t> fc(nc, -1);
+    int rc = 0;
+    for (;;) {
+        for (size_t i = 0; i < nc; i++) deff[i] = delta[i] + d1[i];
+        rc = hkkt_factor_batch(c, nb, H, Dx, J, deff.data(), gamma, st.data(), fc.data());
+        if (rc < 0) return rc;
+        bool retry = false;
+        for (size_t i = 0; i < nc; i++) {
+            if (st[i] != HKKT_NOT_SPD || !(d1[i] <= delta_max / 2)) continue;
+            if (d1[i] == 0.0) d1[i] = delta_min[i];
+            else { delta_min[i] *= 2.0; d1[i] = delta_min[i]; }
+            retry = true;
+        }
+        if (!retry) break;
+    }
+    for (size_t i = 0; i < nc; i++) {
+        delta1[i] = d1[i];
+        if (status) status[i] = st[i];
+        if (fail_col) fail_col[i] = fc[i];
+    }
+    return rc;
+}
+
+int hkkt_gamma_heuristic(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J,
+                         const double* delta, double* gamma_out) {
+    if (!c || !gamma_out || !delta) return HKKT_ERR_ARG;
+    if (!c->analysed) { c->err = "gamma heuristic before analyze"; return HKKT_ERR_STATE; }
+    if (nb < 1 || !Dx || (c->sym.S.nnzH > 0 && !H) || (c->sym.S.nnzJ > 0 && !J)) {
+        c->err = "bad gamma heuristic arguments";
+        return HKKT_ERR_ARG;
+    }
+    ABI_GUARD(c, {
+        const Symbolic& S = c->sym.S;
+        const DevSym& D = c->dev;
+        const int G = S.G;
+        const size_t nc = (size_t)nb * G;
+        hipStream_t st = c->stream;
+        Batch& B = c->main;
+        c->factored = false;   // the batch's values are replaced
+        c->nb = nb;
+        std::vector<double> zero(nc, 0.0);
+        alloc_values(c, B, nb);
+        alloc_solve(c, B);
+        load_values(c, B, H, Dx, J, delta, zero.data(), nullptr, c->opt.pointer_mode == HKKT_PTR_DEVICE);
+        const unsigned nbr = (unsigned)D.v.nbr;
+        LAUNCH(10, k_gamma_rows, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(), B.part1.as<double>(),
+               B.part2.as<double>());
+        LAUNCH(10, k_reduce_max, dim3(nb, G), dim3(64), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
+               D.v.rblk_off, B.knorm.as<double>(), 0.0);
+        LAUNCH(10, k_reduce_max, dim3(nb, G), dim3(64), 0, st, (const double*)B.part2.as<double>(), (int)nbr,
+               D.v.rblk_off, B.rowred.as<double>(), 0.0);
+        std::vector<double> hn(nc), jn(nc);
+        HIPCHK(hipMemcpyAsync(hn.data(), B.knorm.p, nc * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(jn.data(), B.rowred.p, nc * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < nc; i++) gamma_out[i] = jn[i] > 0.0 ? hn[i] / (jn[i] * jn[i]) : 0.0;
+        return HKKT_OK;
     })
 }
 
@@ -2094,7 +2203,7 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         update_residual(c, B, B.ids_all.as<int>(), nall, rsq, false, fl.data());
         LAUNCH(10, k_knorm_rows, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(), B.part2.as<double>());
         LAUNCH(10, k_reduce_max, dim3(nb, G), dim3(64), 0, st, (const double*)B.part2.as<double>(), (int)nbr,
-               D.v.rblk_off, B.knorm.as<double>());
+               D.v.rblk_off, B.knorm.as<double>(), 0.0);
         LAUNCH(10, k_sumsq2, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, (const double*)B.xz.as<double>(),
                (const double*)B.yz.as<double>(), B.part1.as<double>());
         LAUNCH(10, k_reduce_rows, dim3(nb, G), dim3(kBlock), 0, st, (const double*)B.part1.as<double>(), (int)nbr,

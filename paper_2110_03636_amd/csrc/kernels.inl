@@ -2058,11 +2058,91 @@ __global__ __launch_bounds__(kBlock) void k_hgamma_check(SymView S, ValView V, c
     }
 }
 
+// Pivot certainty of a factor: per column j (permuted order) the ratio of
+// the pivot L_jj^2 to the assembled diagonal a_jj of H_gamma (FP64:
+// H_jj + D_x,j + delta + gamma * sum_i J_ij^2). Cholesky's pivot is a_jj less
+// the squares already eliminated from the row, so a small ratio means the
+// pivot is what is left after cancellation, known to fewer bits of the
+// factor's precision. Block maxima of -ratio (so that k_reduce_max gives
+// -min) into part.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pivot_ratio(SymView S, ValView V, const T* __restrict__ Dinv,
+                                                        double* __restrict__ part) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.y;
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    const i64 i = bk.lo + threadIdx.x;
+    double a = -INFINITY;
+    if (i < bk.hi && i < S.n) {
+        const double* HF = V.HF + (i64)b * S.nnzHF;
+        const double* JT = V.JT + (i64)b * S.nnzJ;
+        double d = V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + bk.k], jj = 0.0;
+        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++)
+            if (S.HF_col[k] == i) d += HF[k];
+        for (i64 k = S.JT_rowptr[i]; k < S.JT_rowptr[i + 1]; k++) jj += JT[k] * JT[k];
+        d += V.gamma[(i64)b * S.G + bk.k] * jj;
+        const double r = (double)Dinv[(i64)b * S.n + i];
+        a = -1.0 / (r * r * d);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) a = fmax(a, __shfl_down(a, o, kWave));
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = -INFINITY;
+        for (int t = 0; t < (int)(blockDim.x / kWave); t++) r = fmax(r, sh[t]);
+        part[(i64)b * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+// block maxima of the row sums of |H + D_x + delta I| (rows of x, into
+// part_h) and of |J| (rows of J, into part_j), for the gamma heuristic
+__global__ __launch_bounds__(kBlock) void k_gamma_rows(SymView S, ValView V, double* __restrict__ part_h,
+                                                       double* __restrict__ part_j) {
+    __shared__ double sh[2][kBlock / kWave];
+    const int b = blockIdx.y;
+    const Blk bk = blk_of(S.rblk, blockIdx.x);
+    const i64 i = bk.lo + threadIdx.x;
+    double a = 0.0, c = 0.0;
+    if (i < bk.hi && i < S.n) {
+        const double* HF = V.HF + (i64)b * S.nnzHF;
+        double dsum = V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + bk.k];
+        for (i64 k = S.HF_rowptr[i]; k < S.HF_rowptr[i + 1]; k++) {
+            if (S.HF_col[k] == i) dsum += HF[k];
+            else a += fabs(HF[k]);
+        }
+        a += fabs(dsum);
+    } else if (i < bk.hi) {
+        const i64 r = i - S.n;
+        const double* J = V.J + (i64)b * S.nnzJ;
+        for (i64 k = S.J_rowptr[r]; k < S.J_rowptr[r + 1]; k++) c += fabs(J[k]);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a = fmax(a, __shfl_down(a, o, kWave));
+        c = fmax(c, __shfl_down(c, o, kWave));
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        sh[0][wid] = a;
+        sh[1][wid] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ra = 0.0, rc = 0.0;
+        for (int t = 0; t < (int)(blockDim.x / kWave); t++) {
+            ra = fmax(ra, sh[0][t]);
+            rc = fmax(rc, sh[1][t]);
+        }
+        part_h[(i64)b * gridDim.x + blockIdx.x] = ra;
+        part_j[(i64)b * gridDim.x + blockIdx.x] = rc;
+    }
+}
+
 // out[b * G + k] = max of the partials of member k (grid (nb, G))
-__global__ void k_reduce_max(const double* part, int nblk, const i32* off, double* out) {
+__global__ void k_reduce_max(const double* part, int nblk, const i32* off, double* out, double init) {
     const int b = blockIdx.x, k = blockIdx.y;
     if (threadIdx.x == 0) {
-        double r = 0.0;
+        double r = init;
         for (int i = off[k]; i < off[k + 1]; i++) r = fmax(r, part[(i64)b * nblk + i]);
         out[(i64)b * gridDim.y + k] = r;
     }

@@ -26,6 +26,7 @@ EXPORTS = [
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
     "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule", "hkkt_hsolve_noalloc",
+    "hkkt_factor_regularized", "hkkt_gamma_heuristic",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged"]
@@ -41,7 +42,7 @@ class Options(C.Structure):
                 ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
                 ("ordering", C.c_int), ("relax", C.c_int), ("deterministic", C.c_int),
                 ("mixed_check", C.c_int), ("mixed_check_tol", C.c_double), ("autotune_cache", C.c_int),
-                ("reserved", C.c_int)]
+                ("scaling", C.c_int), ("mixed_pivot_tol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -108,6 +109,8 @@ def lib():
         L.hkkt_get_factor.argtypes = [V, C.c_int, V, V, V]
         L.hkkt_hsolve.argtypes = [V, C.c_int, V, V]
         L.hkkt_hsolve_noalloc.argtypes = [V, C.c_int, V, V]
+        L.hkkt_factor_regularized.argtypes = [V, C.c_int, V, V, V, V, V, V, C.c_double, V, V, V]
+        L.hkkt_gamma_heuristic.argtypes = [V, C.c_int, V, V, V, V, V]
         L.hkkt_timings.argtypes = [V, V]
         L.hkkt_profile_begin.argtypes = [V]
         L.hkkt_profile_end.argtypes = [V, V, V]
@@ -407,6 +410,45 @@ class Solver(_SymbolicView):
         ch = np.array([relax, tree_width, tree_staged], np.int32)
         _check(lib().hkkt_set_schedule(self._ctx, ch.ctypes.data), self._ctx)
         self.nb = 0
+
+    def factor_regularized(self, H_val, D_x, J_val, delta, gamma, delta_min, delta_max=1e-6):
+        """Algorithm 1's delta1 loop around the factorization. delta_min:
+        [nb*G] (or a scalar), updated as Algorithm 1 does. Returns (rc,
+        status, fail_col, delta1, delta_min_after)."""
+        delta = np.atleast_1d(np.asarray(delta, np.float64)).reshape(-1)
+        gamma = np.atleast_1d(np.asarray(gamma, np.float64)).reshape(-1)
+        nb = int(delta.shape[0]) // self.G
+        dmin = np.array(np.broadcast_to(np.asarray(delta_min, np.float64), delta.shape), np.float64)
+        d1 = np.zeros_like(delta)
+        Hv = self._arr(H_val, nb, -1)
+        Dx = self._arr(D_x, nb, self.n)
+        Jv = self._arr(J_val, nb, -1) if self.m > 0 else None
+        if Jv is not None and Jv.shape[1] == 0:
+            Jv = None
+        self._keep_vals = (Hv, Dx, Jv)
+        st = np.zeros(nb * self.G, np.int32)
+        fc = np.zeros(nb * self.G, np.int64)
+        rc = _check(lib().hkkt_factor_regularized(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv), delta.ctypes.data,
+                                                  gamma.ctypes.data, dmin.ctypes.data, float(delta_max),
+                                                  d1.ctypes.data, st.ctypes.data, fc.ctypes.data), self._ctx)
+        self.nb = nb
+        return rc, st, fc, d1, dmin
+
+    def gamma_heuristic(self, H_val, D_x, J_val, delta):
+        """||H + D_x + delta I||_inf / ||J||_inf^2 per (instance, member);
+        drops the current factorization."""
+        delta = np.atleast_1d(np.asarray(delta, np.float64)).reshape(-1)
+        nb = int(delta.shape[0]) // self.G
+        Hv = self._arr(H_val, nb, -1)
+        Dx = self._arr(D_x, nb, self.n)
+        Jv = self._arr(J_val, nb, -1) if self.m > 0 else None
+        if Jv is not None and Jv.shape[1] == 0:
+            Jv = None
+        out = np.zeros(nb * self.G)
+        _check(lib().hkkt_gamma_heuristic(self._ctx, nb, _ptr(Hv), _ptr(Dx), _ptr(Jv), delta.ctypes.data,
+                                          out.ctypes.data), self._ctx)
+        self.nb = 0
+        return out
 
     def factor_batch(self, batch):
         return self.factor(batch.H_val, batch.D_x, batch.J_val, batch.delta, batch.gamma)
