@@ -100,6 +100,13 @@ typedef struct {
                                group layout and given order), precision and batch size instead
                                of timing again; 0: always time */
     int scaling;            /* reserved for equilibration of K (0 = none) */
+    int flow_live;          /* applications of H_gamma^{-1} to at most this many instances (the CG
+                               tail) run as one dataflow launch (each supernode task waits only for
+                               its children / parent) instead of one launch per level; 0 = never.
+                               Needs deterministic = 0 and every supernode within 128 rows.
+                               Default 0: measured no faster than the level launches for one
+                               live instance and slower for more (each task's agent-scope
+                               release and acquire cost about as much as a launch) */
     double mixed_pivot_tol; /* mixed precision: an FP32 factor whose smallest ratio of pivot L_jj^2
                                to the assembled FP64 diagonal a_jj of H_gamma is below this is
                                replaced by an FP64 factor at factor time (the FP32 success does not
@@ -121,7 +128,7 @@ typedef struct {
 /* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
  * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5,
- * autotune_cache 1, scaling 0, mixed_pivot_tol 2^-16. */
+ * autotune_cache 1, scaling 0, flow_live 0, mixed_pivot_tol 2^-16. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream
@@ -374,8 +381,9 @@ int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
  * 10 other, 11 triangular solves of very wide/tall supernodes, 12 both
  * triangular solves over the thin top levels of the tree (one launch, one
  * work-group per instance), 13 the same with the top levels' working set
- * staged in LDS. */
-#define HKKT_NPROF 14
+ * staged in LDS, 14 both triangular solves over all levels as one dataflow
+ * launch. */
+#define HKKT_NPROF 15
 int hkkt_profile_begin(hkkt_ctx *ctx);
 int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);
 

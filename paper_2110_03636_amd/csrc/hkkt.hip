@@ -62,7 +62,7 @@ static double now_ms() {
 // ---------------------------------------------------------------------------
 // optional per-kernel timing with HIP events on the context's stream
 // ---------------------------------------------------------------------------
-constexpr int kNProf = 14;
+constexpr int kNProf = 15;
 struct Prof {
     bool on = false;
     std::mutex mu;                                   // launches may come from two host threads
@@ -200,6 +200,7 @@ struct DevSym {
     DBuf tri_seg_dev;                           // tri_seg on the device (int pairs)
     std::vector<int> lev_count;                 // supernodes per level
     std::vector<char> tree_fits;                // level fits the tree-traversal classes
+    bool flow_ok = false;                       // every supernode in classes 0..3 (dataflow solves)
     int tree_width = 32;                        // widest level run by the tree kernels
     int tree_stage = 1;                         // staged (LDS) tree kernel where it fits
     // tree solve with x in LDS: columns ordered by level from the root down,
@@ -381,7 +382,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                     dd.nr = nr;
                     dd.nchild = S.child_ptr[sn + 1] - S.child_ptr[sn];
                     dd.mem = S.sn_mem[sn];
-                    dd.pad = 0;
+                    dd.pq = -1;
                     td.push_back(dd);
                     if (cls == kTriWG) {
                         D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
@@ -390,6 +391,18 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
                 }
                 D.tri_seg[(size_t)l * kTriClasses + cls] = {off, (i32)tl.size() - off};
             }
+        }
+        {   // parent descriptor of every descriptor (dataflow solves)
+            std::vector<i32> qof(S.ns, -1);
+            for (size_t q = 0; q < tl.size(); q++) qof[tl[q]] = (i32)q;
+            D.flow_ok = true;
+            for (size_t q = 0; q < tl.size(); q++) {
+                const i32 par = S.sn_parent[tl[q]];
+                td[q].pq = par < 0 ? -1 : qof[par];
+                if (par >= 0 && qof[par] < 0) throw std::runtime_error("descriptor of a parent missing");
+                if (tri_class(td[q].nr, td[q].w) >= 4) D.flow_ok = false;
+            }
+            if ((i64)tl.size() != S.ns) D.flow_ok = false;
         }
         upload(D.tri_desc, td, st);
         upload(D.tri_list, tl, st);
@@ -531,6 +544,13 @@ struct Batch {
     // levels [lt_lo, nlevels), lt_size entries per instance from L storage
     // offset lt_base; lt_lo = -1 when stale (rebuilt after a factorization)
     DBuf Lt;
+    // dataflow triangular solves: per (instance, descriptor) counters and
+    // flags, the abort word, the token of the last application
+    DBuf fcnt, fflag, bflag, fabort;
+    int flow_app = 0;
+    bool flow_used = false;    // a dataflow launch since the last abort check
+    bool allow_flow = true;    // false for views that must not allocate
+    int h_abort = 0;
     int lt_lo = -1;
     i64 lt_base = 0, lt_size = 0;
     std::vector<int> h_fail;   // per (entry, member) min failing permuted column (INT_MAX ok)
@@ -561,6 +581,7 @@ struct hkkt_ctx {
     DBuf cbws;                    // contribution-block workspace, shared: the batches factor one after the other
     hipStream_t fb_stream = nullptr;  // FP64 fallback work, concurrent with the FP32 refinement
     i64 lds_max = 65536;          // dynamic LDS per work-group the device allows
+    int cu_count = 256;           // compute units of the device
     std::vector<std::unique_ptr<Batch>> fbx;   // fallback batches of a solve's stall groups
     std::vector<int> fb_idx;      // main index of each fallback instance
     int nb = 0;
@@ -893,10 +914,74 @@ static void launch_tree2(hkkt_ctx* c, Batch& B, int l0, int pmax, const int* ids
            B.lt_size, B.lt_base, B.Dinv.as<T>(), B.X.as<T>(), ids, st_);
 }
 
+// Dataflow solves (k_tri_flow): used for applications to at most flow_live
+// instances (the CG tail) when every supernode fits the wavefront classes
+// 0..3 and the forward solve is the push form.
+static int flow_live(const hkkt_ctx* c) {
+    static const int env = std::getenv("HKKT_FLOW_LIVE") ? std::atoi(std::getenv("HKKT_FLOW_LIVE")) : -1;
+    return env >= 0 ? env : c->opt.flow_live;
+}
+
+template <typename T>
+static void launch_flow(hkkt_ctx* c, Batch& B, const int* ids, int nids, const CGState* st_) {
+    const DevSym& D = c->dev;
+    const Symbolic& S = c->sym.S;
+    const i32 nd = (i32)S.ns;
+    const size_t words = (size_t)B.nb * nd * 4;
+    if (B.fcnt.bytes < words || !B.fcnt.p) {   // new (zeroed) words; tokens restart above any old one
+        for (DBuf* d : {&B.fcnt, &B.fflag, &B.bflag}) {
+            d->ensure(words);
+            HIPCHK(hipMemsetAsync(d->p, 0, words, B.stream));
+        }
+        B.fabort.ensure(4);
+        HIPCHK(hipMemsetAsync(B.fabort.p, 0, 4, B.stream));
+    }
+    FlowArgs F;
+    F.seg = D.tri_seg_dev.as<i32>();
+    F.nlevels = S.nlevels;
+    F.ndesc = nd;
+    F.ids = ids;
+    F.nids = nids;
+    F.st = st_;
+    F.fcnt = B.fcnt.as<int>();
+    F.fflag = B.fflag.as<int>();
+    F.bflag = B.bflag.as<int>();
+    F.abort = B.fabort.as<int>();
+    F.app = ++B.flow_app;
+    // wave tasks of the launch; the grid stays within a quarter of the
+    // device's resident work-groups (two batches may run it concurrently)
+    i64 tasks = 0;
+    for (i32 l = 0; l < S.nlevels; l++)
+        for (int cls = 0; cls < 4; cls++) {
+            const i64 g = flow_group(cls);
+            tasks += 2 * (i64)D.tri_seg[(size_t)l * kTriClasses + cls].second * ((nids + g - 1) / g);
+        }
+    static int occ = 0;
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void*)k_tri_flow<float>, kBlock, 0) != hipSuccess)
+            o = 1;
+        int o64 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, (const void*)k_tri_flow<double>, kBlock, 0) != hipSuccess)
+            o64 = 1;
+        occ = std::max(1, std::min(o, o64));
+    });
+    const i64 cap = std::max<i64>(1, (i64)c->cu_count * occ / 4);
+    const i64 grid = std::max<i64>(1, std::min<i64>(cap, (tasks + 3) / 4));
+    LAUNCH(14, k_tri_flow<T>, dim3((unsigned)grid), dim3(kBlock), 0, B.stream, D.v, F, D.tri_desc.as<TriDesc>(),
+           (const T*)B.L.as<T>(), (const T*)B.Dinv.as<T>(), B.X.as<T>());
+    B.flow_used = true;
+}
+
 template <typename T>
 static void launch_trisolve(hkkt_ctx* c, Batch& B, const int* ids, int nids, const CGState* st_) {
     const Symbolic& S = c->sym.S;
     if (nids <= 0) return;
+    if (nids <= flow_live(c) && c->dev.flow_ok && B.allow_flow && c->opt.deterministic == 0) {
+        launch_flow<T>(c, B, ids, nids, st_);
+        return;
+    }
     const int lo = tree_lo(c->dev, S.nlevels);
     int pmax = 0;
     const int lo2 = lo < S.nlevels ? tree2_lo<T>(c, lo, &pmax) : S.nlevels;
@@ -1075,6 +1160,21 @@ static std::vector<double> fp32_factor_quality(hkkt_ctx* c, Batch& B) {
 // in B.ids_pass (members flagged in B.cact for a group):
 // ex, y <- approx K^{-1} g (Algorithm 1, solve phase)
 // ---------------------------------------------------------------------------
+// after the stream has reached the end of the dataflow launches since the
+// last check: raise if one of their dependency waits timed out (the words
+// are then cleared for the next launch)
+static void check_flow(Batch& B) {
+    if (!B.flow_used) return;
+    B.flow_used = false;
+    HIPCHK(hipMemcpyAsync(&B.h_abort, B.fabort.p, 4, hipMemcpyDeviceToHost, B.stream));
+    HIPCHK(hipStreamSynchronize(B.stream));
+    if (B.h_abort) {
+        B.fcnt.release();   // reallocated and zeroed by the next launch
+        B.h_abort = 0;
+        throw Error(HKKT_ERR_DEVICE, "dataflow triangular solve: a dependency wait timed out");
+    }
+}
+
 template <typename T>
 static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_tol, std::vector<CGState>& hst) {
     const Symbolic& S = c->sym.S;
@@ -1252,6 +1352,7 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
         if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, nids, max_cg, cg_tol, hst);
         else hybrid_pass<double>(c, B, nids, max_cg, cg_tol, hst);
         update_residual(c, B, B.ids_pass.as<int>(), nids, rsq, true, nullptr);
+        check_flow(B);
         for (int i = 0; i < nc; i++) {
             if (!act[i]) continue;
             InstState& s = is[i];
@@ -1466,6 +1567,7 @@ void hkkt_default_options(hkkt_options* o) {
     o->mixed_check_tol = 0.5;
     o->autotune_cache = 1;
     o->scaling = 0;
+    o->flow_live = 0;
     o->mixed_pivot_tol = 0x1p-16;
 }
 
@@ -1483,6 +1585,8 @@ int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && v > 0)
             c->lds_max = v;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && v > 0)
+            c->cu_count = v;
     }
     if (scratch_lookup(c->device) != hipSuccess) { delete c; return HKKT_ERR_DEVICE; }
     c->main.prec = c->opt.precision;
@@ -2341,6 +2445,7 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                               st));
         HIPCHK(hipStreamSynchronize(st));
+        check_flow(B);
         return HKKT_OK;
     })
 }
@@ -2376,6 +2481,7 @@ int hkkt_hsolve_noalloc(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         Batch V;
         V.nb = nb;
         V.prec = M.prec;
+        V.allow_flow = false;
         V.stream = c->stream;
         V.L.view(M.L.p, M.L.bytes);
         V.Dinv.view(M.Dinv.p, M.Dinv.bytes);

@@ -82,8 +82,9 @@ struct TriDesc {
     i32 nr;      // rows
     i32 nchild;  // number of children (0: leaf, no gather)
     i32 mem;     // group member
-    i32 pad;
+    i32 pq;      // descriptor index of the parent supernode, -1 for a root
 };
+
 
 // Supernode of the tree-traversal solve with the right-hand side of the
 // tree's columns held in LDS: slot = LDS index of the first column, rs =
@@ -116,6 +117,21 @@ struct ValView {
 struct CGState {
     double rho, pq, pp, bnorm, alpha, beta, curv0, d2;
     int it, done, breakdown, pad;
+};
+
+// Dataflow triangular solves (k_tri_flow): per (instance, descriptor) words.
+struct FlowArgs {
+    const i32* seg;   // (offset, count) of the descriptors per (level, class), kTriClasses per level
+    int nlevels;
+    int ndesc;
+    const int* ids;   // instance slots, nids of them (null: slot k = instance k)
+    int nids;
+    const CGState* st;
+    int* fcnt;        // [nb][ndesc] children whose forward task is done; reset by the task itself
+    int* fflag;       // [nb][ndesc] = app when a root's forward task is done
+    int* bflag;       // [nb][ndesc] = app when the backward task is done
+    int* abort;       // set when a wait timed out: every later wait returns at once
+    int app;          // token of this application (> 0, increasing per batch)
 };
 
 }  // namespace hkkt

@@ -1575,6 +1575,190 @@ __global__ __launch_bounds__(kBlock) void k_bwd_lvl(SymView S, LevelTasks lt, co
         bwd_task<T, 64, 2>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], L, Dinv, X, ids, nids, st);
 }
 
+// ---------------------------------------------------------------------------
+// Dataflow triangular solves: the forward sweep over every level and then
+// the backward sweep, for all listed instances, in one launch. The wave
+// tasks (one supernode descriptor x a group of 64/SEG instance slots, as in
+// the per-level kernels) are numbered forward levels up, then backward
+// levels down, classes 0..3 within a level; wave w takes tasks w, w + W, ...
+// in that order. A task needs no level barrier: it issues its panel and
+// diagonal loads, waits (one lane per segment polling) until its own
+// dependencies are met, acquires, solves and releases:
+//   forward (b, s): all children of s have added their updates into x
+//     (fcnt[b][s] == nchild; the task then clears its counter), then adds
+//     its own rows below into the ancestors' entries (FP atomics) and counts
+//     itself done at its parent (or marks fflag = app at a root);
+//   backward (b, s): the parent's backward task is done (bflag[b][parent]
+//     == app; a root waits for its own forward task), then marks bflag.
+// A child is done only after its own children, so "all children done"
+// covers every descendant that updates x at the columns of s. Tasks are
+// assigned in a topological order and every wait is on an earlier task, so
+// the launch completes when its work-groups are co-resident (the grid is
+// sized to a fraction of the device); every wait is also bounded: after
+// kFlowSpin polls it sets *abort and every later wait returns, so the
+// launch always ends (the host then reports the failure).
+// ---------------------------------------------------------------------------
+constexpr int kFlowSpin = 1 << 20;
+
+__device__ __forceinline__ void flow_wait(const int* p, int target, bool need, int* abortf) {
+    bool ok = !need;
+    int spins = 0;
+    while (true) {
+        if (!ok) ok = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == target;
+        if (__all(ok)) break;
+        if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (++spins > kFlowSpin) {
+            __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T, int SEG, int R>
+__device__ __forceinline__ void flow_fwd(const SymView& S, const FlowArgs& F, const TriDesc& d, int qi, int b,
+                                         bool valid, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         T* __restrict__ X) {
+    constexpr int CH = chunk_cols<T, SEG, R>();
+    const int sl = threadIdx.x & (SEG - 1);
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    const T* dinv = Dinv + (i64)b * S.n + d.f;
+    T* x = X + (i64)b * S.n;
+    T lc[CH][R];
+    load_cols<T, SEG, R, CH>(lc, Lb, d, 0, sl);     // the factor is not written during the solve
+    T di[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = sl + SEG * r;
+        di[r] = row < d.w ? dinv[row] : T(0);
+    }
+    int* cnt = F.fcnt + (i64)b * F.ndesc + qi;
+    const bool lead = valid && sl == 0;
+    flow_wait(cnt, d.nchild, lead && d.nchild > 0, F.abort);
+    if (lead && d.nchild > 0) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = sl + SEG * r;
+        v[r] = row < d.w ? x[d.f + row] : T(0);
+    }
+    fwd_cols<T, SEG, R, CH, true>(lc, v, di, Lb, d, sl);
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int row = sl + SEG * r;
+            if (row < d.w) x[d.f + row] = v[r];
+            else if (row < d.nr) unsafeAtomicAdd(&x[S.sn_rows[d.rp + row]], v[r]);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lead) {
+        if (d.pq >= 0)
+            __hip_atomic_fetch_add(F.fcnt + (i64)b * F.ndesc + d.pq, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_store(F.fflag + (i64)b * F.ndesc + qi, F.app, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <typename T, int SEG, int R>
+__device__ __forceinline__ void flow_bwd(const SymView& S, const FlowArgs& F, const TriDesc& d, int qi, int b,
+                                         bool valid, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         T* __restrict__ X) {
+    constexpr int CH = chunk_cols<T, SEG, R>();
+    const int sl = threadIdx.x & (SEG - 1);
+    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    const T* dinv = Dinv + (i64)b * S.n + d.f;
+    T* x = X + (i64)b * S.n;
+    T lc[CH][R];
+    load_cols<T, SEG, R, CH>(lc, Lb, d, d.w - CH, sl);
+    T di[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = sl + SEG * r;
+        di[r] = row < d.w ? dinv[row] : T(0);
+    }
+    const int* dep = d.pq < 0 ? F.fflag + (i64)b * F.ndesc + qi : F.bflag + (i64)b * F.ndesc + d.pq;
+    flow_wait(dep, F.app, valid && sl == 0, F.abort);
+    T v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int row = sl + SEG * r;
+        T a = T(0);
+        if (row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
+        v[r] = a;
+    }
+    bwd_cols<T, SEG, R, CH, true>(lc, v, di, Lb, d, sl);
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int row = sl + SEG * r;
+            if (row < d.w) x[d.f + row] = v[r];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (valid && sl == 0)
+        __hip_atomic_store(F.bflag + (i64)b * F.ndesc + qi, F.app, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T, int SEG, int R>
+__device__ __forceinline__ void flow_task(const SymView& S, const FlowArgs& F, const TriDesc* __restrict__ desc,
+                                          bool fwd, int off, i64 u, const T* __restrict__ L,
+                                          const T* __restrict__ Dinv, T* __restrict__ X) {
+    constexpr int G = kWave / SEG;
+    const int ng = (F.nids + G - 1) / G;
+    const int q = (int)(u / ng);
+    const int k = (int)(u - (i64)q * ng) * G + (int)(threadIdx.x & (kWave - 1)) / SEG;
+    bool valid = k < F.nids;
+    const int b = valid ? inst_of(F.ids, k) : inst_of(F.ids, 0);
+    const int qi = off + q;
+    const TriDesc d = desc[qi];
+    if (valid && F.st && F.st[(i64)b * S.G + d.mem].done) valid = false;
+    if (fwd) flow_fwd<T, SEG, R>(S, F, d, qi, b, valid, L, Dinv, X);
+    else flow_bwd<T, SEG, R>(S, F, d, qi, b, valid, L, Dinv, X);
+}
+
+__host__ __device__ constexpr int flow_group(int cls) { return cls == 0 ? 4 : cls == 1 ? 2 : 1; }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tri_flow(SymView S, FlowArgs F, const TriDesc* __restrict__ desc,
+                                                     const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                     T* __restrict__ X) {
+    const i64 W = (i64)gridDim.x * (kBlock / kWave);
+    const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int nseg = 2 * F.nlevels * 4;
+    int si = 0;
+    i64 s0 = 0;   // first task of segment si
+    auto seg_of = [&](int i, bool* fwd, int* cls, int* off, int* cnt) {
+        const int half = F.nlevels * 4;
+        *fwd = i < half;
+        const int j = *fwd ? i : i - half;
+        const int lv = *fwd ? j / 4 : F.nlevels - 1 - j / 4;
+        *cls = j % 4;
+        *off = F.seg[2 * (lv * kTriClasses + *cls)];
+        *cnt = F.seg[2 * (lv * kTriClasses + *cls) + 1];
+    };
+    for (i64 t = wave;; t += W) {
+        bool fwd = true;
+        int cls = 0, off = 0, cnt = 0;
+        while (si < nseg) {
+            seg_of(si, &fwd, &cls, &off, &cnt);
+            const i64 len = (i64)cnt * ((F.nids + flow_group(cls) - 1) / flow_group(cls));
+            if (t < s0 + len) break;
+            s0 += len;
+            si++;
+        }
+        if (si >= nseg) return;
+        const i64 u = t - s0;
+        switch (cls) {
+            case 0: flow_task<T, 16, 1>(S, F, desc, fwd, off, u, L, Dinv, X); break;
+            case 1: flow_task<T, 32, 1>(S, F, desc, fwd, off, u, L, Dinv, X); break;
+            case 2: flow_task<T, 64, 1>(S, F, desc, fwd, off, u, L, Dinv, X); break;
+            default: flow_task<T, 64, 2>(S, F, desc, fwd, off, u, L, Dinv, X); break;
+        }
+    }
+}
+
 // reciprocals of the factor's diagonal (one per column), used by the
 // wavefront triangular solves in place of divisions
 template <typename T>

@@ -29,7 +29,8 @@ EXPORTS = [
     "hkkt_factor_regularized", "hkkt_gamma_heuristic",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
-              "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged"]
+              "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged",
+              "tri_flow"]
 
 i64p = C.POINTER(C.c_int64)
 i32p = C.POINTER(C.c_int32)
@@ -42,7 +43,7 @@ class Options(C.Structure):
                 ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
                 ("ordering", C.c_int), ("relax", C.c_int), ("deterministic", C.c_int),
                 ("mixed_check", C.c_int), ("mixed_check_tol", C.c_double), ("autotune_cache", C.c_int),
-                ("scaling", C.c_int), ("mixed_pivot_tol", C.c_double)]
+                ("scaling", C.c_int), ("flow_live", C.c_int), ("mixed_pivot_tol", C.c_double)]
 
 
 class Info(C.Structure):
