@@ -103,33 +103,19 @@ def run_gpu(args):
     for _ in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
-    # the timed steps, with per-kernel HIP events recorded on the library's
-    # stream around every launch (the roofline's kernel durations); with
-    # --events-after, one extra identical step carries the events instead
-    if not args.events_after:
-        s.profile_begin()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos = step(s)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    if args.events_after:
-        s.profile_begin()
-        infos = step(s)
-        nprof = 1
-    else:
-        nprof = args.steps
-    prof_all = s.profile_end()
-    prof = {k: (v[0] / nprof, v[1] / nprof) for k, v in prof_all.items()}   # per step
-    ok = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
-    value = ok * args.steps / el
-    pinfos = infos
-    xs, ys = s.last_xy
+    # one extra step with an event pair around every launch (an event pair
+    # costs about as much as a short kernel, so the timed steps do not carry
+    # them all): the per-class breakdown of a step and the phases
+    s.profile_select(None, 1)
+    s.profile_begin()
+    pinfos = step(s)
+    prof = s.profile_end()                      # per step
+    # timed steps, with HIP events on the library's stream around every
+    # PROF_EVERY-th launch of the step's dominant kernel class only: its
+    # average launch duration over the timed region
     stats = s.stats()
     per = per_instance_bytes(stats, 4)
     lf, lb = level_bytes(s, 4)
-    # levels below `lo` run one launch per level; the levels above in the
-    # tree-traversal kernel (one launch per application of H_gamma^{-1})
     nlev = len(lf)
     tk = tree_key(prof)
     lo = round(prof["bwd"][1] / prof[tk][1]) if prof[tk][1] else nlev
@@ -142,8 +128,21 @@ def run_gpu(args):
              tk: (sum(lf[lo:]) + sum(lb[lo:])) * apps,
              "jt_spmv": per["jt_spmv"] * spmv_apps / 2, "j_spmv": per["j_spmv"] * spmv_apps / 2}
     best = max(total, key=lambda k: prof[k][0])
-    ms_tot, launches = prof[best]
-    avg_ms = ms_tot / max(launches, 1)
+    PROF_EVERY = 4
+    s.profile_select([best], PROF_EVERY)
+    s.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = step(s)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timed = s.profile_end()
+    s.profile_select(None, 1)
+    ok = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
+    value = ok * args.steps / el
+    xs, ys = s.last_xy
+    launches = prof[best][1]                    # per step
+    avg_ms = timed[best][0] / max(timed[best][1], 1)
     per_launch = total[best] / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     # phases: all triangular-solve launches, and both SpMV kernels
@@ -165,7 +164,10 @@ def run_gpu(args):
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(per_launch),
-                "launches_per_step": launches, "per_level_launch_levels": lo}
+                "launches_per_step": launches, "per_level_launch_levels": lo,
+                "timing": f"HIP events around every {PROF_EVERY}th launch of this class over the {args.steps} "
+                          f"timed steps ({timed[best][1]} launches timed); bytes and launches per step from one "
+                          f"profiled step with events around every launch"}
 
     # plain FP64 comparators: batched (same steps as the mixed path, fewer of
     # them), and one instance at a time
@@ -209,6 +211,7 @@ def run_gpu(args):
         "cg_iters_mean": round(float(np.mean(cg)), 2),
         "passes_max": max(i["passes"] for i in infos),
         "profile_ms_per_step": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "profile_note": "per-class kernel time of one extra step with an event pair around every launch",
         "phases": phases,
         "autotuned": tuned or None,
         "symbolic": {k: stats[k] for k in ("nnz_L", "L_storage", "supernodes", "levels", "etree_height")},
@@ -367,6 +370,50 @@ def large_single(args):
                       "fp64_fallbacks": sum(i["fp64_fallback"] for i in res),
                       "cg_iters_mean": round(float(np.mean([i["cg_iters"] for i in res])), 1),
                       "symbolic": {k: st[k] for k in ("nnz_L", "L_storage", "levels", "max_width")}}))
+
+
+def solve_only(args):
+    """Factor reuse across adjacent Newton steps (Sec. 2 reuse list): the
+    256-instance batch is factored once, then solved for args.solve_only
+    fresh right-hand sides in a row (the next Newton steps' residuals),
+    each to RR <= 1e-10; solves/s beside the factor+solve rate of the same
+    batch."""
+    import numpy as np
+    import torch
+    from paper_2110_03636_amd import hkkt, synth
+    b = synth.grid_like(args.n, nb=args.nb, seed=4000, gammas=(1e4, 1e6), dx_exp=8.0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    H, D, J = dev(b.H_val), dev(b.D_x), dev(b.J_val)
+    rng = np.random.default_rng(4100)
+    rhs = [(dev(rng.standard_normal((args.nb, args.n))), dev(rng.standard_normal((args.nb, args.n // 2))))
+           for _ in range(args.solve_only)]
+    s = hkkt.Solver(precision="mixed", device=True, kkt_tol=1e-10)
+    s.analyze(b.pattern)
+    if args.schedule_mixed:
+        s.set_schedule(*[int(v) for v in args.schedule_mixed.split(",")])
+    elif not args.no_autotune:
+        s.autotune(H, D, J, b.delta, b.gamma, rhs[0][0], rhs[0][1])
+    s.factor(H, D, J, b.delta, b.gamma)
+    s.solve(*rhs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.factor(H, D, J, b.delta, b.gamma)
+    rc, x, y, infos = s.solve(*rhs[0])
+    torch.cuda.synchronize()
+    t_fs = time.perf_counter() - t0
+    ok_fs = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
+    t0 = time.perf_counter()
+    ok = 0
+    for r1, r2 in rhs:
+        rc, x, y, infos = s.solve(r1, r2)
+        ok += sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"workload": f"batch of {args.nb} grid-like KKT systems, n_x={args.n}, one factorization, "
+                                  f"{args.solve_only} right-hand sides in a row, mixed precision, target RR<=1e-10",
+                      "solve_only_solves_per_s": round(ok / el, 2), "ms_per_solve_batch": round(el / args.solve_only * 1e3, 3),
+                      "factor_plus_solve_solves_per_s": round(ok_fs / t_fs, 2),
+                      "converged": f"{ok}/{args.nb * args.solve_only}"}))
 
 
 def profile_hsolve(args):
@@ -539,8 +586,6 @@ def main():
     ap.add_argument("--schedule-mixed", default="", help="relax,tree_width,staged for the mixed solver "
                     "(skips its autotuning; for profiler runs)")
     ap.add_argument("--schedule-fp64", default="", help="the same for the FP64 batched solver")
-    ap.add_argument("--events-after", action="store_true",
-                    help="per-kernel events on one extra step after the timed ones instead of on the timed steps")
     ap.add_argument("--no-comparators", action="store_true",
                     help="skip the FP64 batched and plain FP64 runs (profiler runs of the mixed path)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -552,6 +597,8 @@ def main():
     ap.add_argument("--cycles", type=int, default=20, help="factor + solve cycles of --large")
     ap.add_argument("--factor-mfma", type=int, default=0,
                     help="factorization of one dense-like system of this n_x (MFMA large-front measurement)")
+    ap.add_argument("--solve-only", type=int, default=0,
+                    help="factor once, then solve this many right-hand sides in a row (factor reuse)")
     ap.add_argument("--profile-hsolve", type=int, default=0,
                     help="counter-collection mode: calibration copy + this many H_gamma^{-1} applications")
     args = ap.parse_args()
@@ -562,6 +609,9 @@ def main():
         sys.exit(2)
     if args.profile_hsolve:
         profile_hsolve(args)
+        return
+    if args.solve_only:
+        solve_only(args)
         return
     if args.factor_mfma:
         factor_mfma(args)

@@ -85,7 +85,8 @@ typedef struct {
                                with delta2 > 0, 2 without) */
     int max_cg;             /* <= 0: min(m, 1000) */
     int max_refine;         /* refinement passes after the first (default 10) */
-    int ordering;           /* 0 = own approximate minimum degree (Sec. 5.3), 1 = natural */
+    int ordering;           /* 0 = own approximate minimum degree (Sec. 5.3), 1 = natural,
+                               2 = nested dissection (level-structure bisection, AMD on small parts) */
     int relax;              /* supernode amalgamation: 0 none (fundamental), 1 default, 2 more */
     int deterministic;      /* 1: forward solves pull children's update vectors in a fixed order
                                (bitwise reproducible); 0: right-looking FP atomics (faster) */
@@ -385,6 +386,13 @@ int hkkt_timings(const hkkt_ctx *ctx, double ms[8]);
  * launch. */
 #define HKKT_NPROF 15
 int hkkt_profile_begin(hkkt_ctx *ctx);
+/* Which launches hkkt_profile_begin/end record (an event pair on the
+ * stream costs about as much as a short kernel): bit k of class_mask
+ * selects class k, and of the selected classes only every `every`-th launch
+ * of each class is recorded (the first one included); launches[] of
+ * hkkt_profile_end then counts recorded launches. Default: all classes,
+ * every launch. -1 if every < 1. */
+int hkkt_profile_select(hkkt_ctx *ctx, unsigned class_mask, int every);
 int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -14,7 +14,7 @@ using i64 = int64_t;
 using i32 = int32_t;
 
 struct AnalyzeOptions {
-    int ordering = 0;   // 0 own AMD, 1 natural
+    int ordering = 0;   // 0 own AMD, 1 natural, 2 nested dissection
     int relax = 1;      // supernode amalgamation level
     int lds_rows = 64;  // fronts with at most this many rows use the LDS kernel
 };
@@ -93,6 +93,7 @@ std::string validate_pattern(i64 n, i64 m, const i64* Hp, const i32* Hi, const i
 // Own approximate minimum degree on the symmetric graph (ptr/adj without
 // the diagonal). Returns perm[k] = node eliminated k-th.
 std::vector<i32> amd_order(i64 n, const std::vector<i64>& ptr, const std::vector<i32>& adj);
+std::vector<i32> nd_order(i64 n, const std::vector<i64>& ptr, const std::vector<i32>& adj, int leaf);
 
 // Full analysis. perm_in may be null. For an uneven group, G > 1 members
 // with variable offsets x_off[G+1] and J-row offsets y_off[G+1] (entries of

@@ -30,6 +30,7 @@
 #include <functional>
 #include <exception>
 #include <array>
+#include <atomic>
 #include <map>
 #include <vector>
 
@@ -65,6 +66,9 @@ static double now_ms() {
 constexpr int kNProf = 15;
 struct Prof {
     bool on = false;
+    unsigned mask = ~0u;                             // classes recorded (bit k: class k)
+    int every = 1;                                   // record every this many launches of a class
+    std::atomic<long long> seen[16] = {};            // launches of each class since profile begin
     std::mutex mu;                                   // launches may come from two host threads
     std::vector<hipEvent_t> pool;
     size_t used = 0;
@@ -98,7 +102,7 @@ struct ProfScope {
     size_t i0 = 0;
     bool rec = false;
     ProfScope(Prof& p_, hipStream_t s, int k) : p(p_), st(s), kind(k) {
-        if (p.on) {
+        if (p.on && ((p.mask >> (k & 15)) & 1u) && p.seen[k & 15].fetch_add(1) % p.every == 0) {
             i0 = p.take2();
             HIPCHK(hipEventRecord(p.ev(i0), st));
             rec = true;
@@ -2533,6 +2537,14 @@ int hkkt_profile_begin(hkkt_ctx* c) {
     c->prof.on = true;
     c->prof.used = 0;
     c->prof.recs.clear();
+    for (auto& v : c->prof.seen) v = 0;
+    return HKKT_OK;
+}
+
+int hkkt_profile_select(hkkt_ctx* c, unsigned class_mask, int every) {
+    if (!c || every < 1) return HKKT_ERR_ARG;
+    c->prof.mask = class_mask;
+    c->prof.every = every;
     return HKKT_OK;
 }
 

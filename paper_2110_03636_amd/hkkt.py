@@ -26,7 +26,7 @@ EXPORTS = [
     "hkkt_symbolic_perm", "hkkt_symbolic_supernodes", "hkkt_get_factor", "hkkt_hsolve", "hkkt_timings",
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
     "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule", "hkkt_hsolve_noalloc",
-    "hkkt_factor_regularized", "hkkt_gamma_heuristic",
+    "hkkt_factor_regularized", "hkkt_gamma_heuristic", "hkkt_profile_select",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged",
@@ -115,6 +115,7 @@ def lib():
         L.hkkt_timings.argtypes = [V, V]
         L.hkkt_profile_begin.argtypes = [V]
         L.hkkt_profile_end.argtypes = [V, V, V]
+        L.hkkt_profile_select.argtypes = [V, C.c_uint, C.c_int]
         _lib = L
     return _lib
 
@@ -511,6 +512,11 @@ class Solver(_SymbolicView):
 
     def profile_begin(self):
         _check(lib().hkkt_profile_begin(self._ctx), self._ctx)
+
+    def profile_select(self, classes=None, every=1):
+        """Record only the named classes (None: all), every `every`-th launch."""
+        mask = 0xFFFFFFFF if classes is None else sum(1 << PROF_NAMES.index(k) for k in classes)
+        _check(lib().hkkt_profile_select(self._ctx, mask, int(every)), self._ctx)
 
     def profile_end(self):
         """{class: (total_ms, launches)} of the launches since profile_begin."""

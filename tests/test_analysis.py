@@ -40,7 +40,7 @@ def _struct(b):
 
 def _cases():
     return [H.tiny_grid_like(120, 1), H.tiny_dense_like(80, 2), H.tiny_grid_like(200, 3),
-            H.tiny_dense_like(150, 4)]
+            H.tiny_dense_like(150, 4), H.tiny_grid_like(900, 5)]
 
 
 def test_exports_match_header():
@@ -53,12 +53,12 @@ def test_exports_match_header():
         assert hasattr(L, name), name
 
 
-@pytest.mark.parametrize("k", range(4))
-@pytest.mark.parametrize("relax", [0, 1])
-def test_supernodal_structure_equals_fill(k, relax):
+@pytest.mark.parametrize("k", range(5))
+@pytest.mark.parametrize("relax,ordering", [(0, 0), (1, 0), (0, 2), (1, 2)])
+def test_supernodal_structure_equals_fill(k, relax, ordering):
     b = _cases()[k]
     n = b.pattern.n_x
-    sym = hkkt.Symbolic.from_pattern(b.pattern, relax=relax)
+    sym = hkkt.Symbolic.from_pattern(b.pattern, relax=relax, ordering=ordering)
     perm = sym.perm()
     assert sorted(perm.tolist()) == list(range(n))
     fill = _boolean_fill(_struct(b)[np.ix_(perm, perm)])
@@ -318,3 +318,37 @@ def test_group_contribution_workspace_below_sum():
     nc = (sn["rowptr"][1:] - sn["rowptr"][:-1]) - (sn["first"][1:] - sn["first"][:-1])
     rounded = ((nc.astype(np.int64) ** 2 + 63) // 64 * 64).sum()
     assert sym.cb_offsets()[-1] < 0.9 * rounded
+
+
+def test_nested_dissection_orders_every_part():
+    """Nested dissection (ordering 2) on a grid-like pattern, a group of
+    disconnected members and a dense-like pattern: a permutation, members
+    kept apart, and on a connected pattern the last pivots form a separator
+    whose removal disconnects the graph of H_gamma."""
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as cg
+    b = H.tiny_grid_like(5000, 61, dx_exp=6.0)
+    sym = hkkt.Symbolic.from_pattern(b.pattern, ordering=2)
+    perm = sym.perm()
+    assert sorted(perm.tolist()) == list(range(b.pattern.n_x))
+    p = b.pattern
+    n = p.n_x
+    Hs = sp.csr_matrix((np.ones(p.H_col.size), p.H_col, p.H_rowptr), shape=(n, n))
+    Js = sp.csr_matrix((np.ones(p.J_col.size), p.J_col, p.J_rowptr), shape=(p.m, n))
+    A = ((Hs + Hs.T + Js.T @ Js) != 0).tocsr()
+    # the top separator: the pivots of the root supernode's columns
+    sn = sym.supernodes()
+    root_cols = perm[sn["first"][-2]:sn["first"][-1]]
+    keep = np.setdiff1d(np.arange(b.pattern.n_x), root_cols)
+    ncomp, _ = cg.connected_components(A[keep][:, keep], directed=False)
+    assert ncomp >= 2
+    mem = [H.tiny_grid_like(n, 62 + n) for n in (700, 400, 900)]
+    g = hkkt.GroupPattern([m.pattern for m in mem])
+    gs = hkkt.Symbolic.from_group(g, ordering=2)
+    p = gs.perm()
+    assert sorted(p.tolist()) == list(range(g.n_x))
+    for k in range(3):   # member k's pivots are its own variables, in its range
+        assert set(p[g.x_off[k]:g.x_off[k + 1]].tolist()) == set(range(g.x_off[k], g.x_off[k + 1]))
+    d = H.tiny_dense_like(400, 63)
+    ds = hkkt.Symbolic.from_pattern(d.pattern, ordering=2)
+    assert sorted(ds.perm().tolist()) == list(range(400))

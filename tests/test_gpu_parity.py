@@ -504,3 +504,31 @@ def test_schedule_set_and_autotune_cache():
     assert s2.factor_batch(b)[0] == 0
     rc, x, y, infos = s2.solve(b.r1, b.r2)
     _check_solution(b, x, y, infos)
+
+
+def test_factor_reuse_across_right_hand_sides():
+    """One factorization, three solves in a row (Sec. 2: a factorization can
+    serve adjacent Newton steps): each accepted by the oracle's residual,
+    and the first right-hand side solved again gives the same solution."""
+    b = synth.grid_like(3000, nb=4, seed=39, gammas=(1e4, 1e6), dx_exp=8.0)
+    rng = np.random.default_rng(40)
+    rhs = [(b.r1, b.r2), (rng.standard_normal(b.r1.shape), rng.standard_normal(b.r2.shape))]
+    for precision in ("fp64", "mixed"):
+        s = _solver(b, precision=precision)
+        assert s.factor_batch(b)[0] == 0
+        sols = []
+        for r1, r2 in rhs + rhs[:1]:
+            rc, x, y, infos = s.solve(r1, r2)
+            for i in range(b.nb):
+                H.check_gpu_solution(oracle.System.from_batch(b, i), r1[i], r2[i], x[i], y[i], infos[i], 1e-10)
+            sols.append(np.concatenate([x, y], axis=1))
+        assert np.linalg.norm(sols[2] - sols[0]) <= 1e-8 * np.linalg.norm(sols[0])
+
+
+def test_nested_dissection_ordering_solves():
+    b = synth.grid_like(3000, nb=2, seed=41, gammas=(1e4, 1e6), dx_exp=8.0)
+    s = hkkt.Solver(precision="mixed", ordering=2)
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    _check_solution(b, x, y, infos)
