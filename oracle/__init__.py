@@ -76,6 +76,10 @@ def lib():
         L.orc_factor_regularized.argtypes = [C.c_void_p, i32p, f64p, C.c_double, f64p, i64p]
         L.orc_gamma_heuristic.restype = C.c_double
         L.orc_gamma_heuristic.argtypes = [C.c_void_p]
+        L.orc_ruiz.argtypes = [C.c_void_p, C.c_int64, f64p]
+        L.orc_solve_scaled.restype = C.c_int
+        L.orc_solve_scaled.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, i32p, f64p, f64p, f64p, f64p,
+                                       C.POINTER(_Report)]
         L.orc_refine_dd.restype = C.c_int64
         L.orc_refine_dd.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.c_int64, f64p]
         _lib = L
@@ -196,6 +200,31 @@ class System:
         o = self._opts(**kw)
         lib().orc_solve(self._h, C.byref(o), _p(r1, f64p), _p(r2, f64p), _p(x, f64p), _p(y, f64p),
                         C.byref(rep))
+        info = dict(status=int(rep.status), passes=int(rep.passes),
+                    cg_iters=[int(rep.cg_iters[i]) for i in range(rep.passes)],
+                    rr_hist=[float(rep.rr_hist[i]) for i in range(rep.passes)],
+                    rr=float(rep.rr), be=float(rep.be), floor=float(rep.floor),
+                    inertia=tuple(int(v) for v in rep.inertia))
+        return x, y, info
+
+    def ruiz(self, iters=10):
+        """Symmetrized Ruiz scaling vector d (n_x + m) of K."""
+        d = np.empty(self.n + self.m)
+        lib().orc_ruiz(self._h, int(iters), _p(d, f64p))
+        return d
+
+    def solve_scaled(self, r1, r2, d, perm=None, **kw):
+        """Hybrid passes on D K D, refinement on K (orc_solve_scaled)."""
+        r1 = _c(r1, np.float64)
+        r2 = _c(r2, np.float64)
+        d = _c(d, np.float64)
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        rep = _Report()
+        o = self._opts(**kw)
+        pa = None if perm is None else _c(perm, np.int32)
+        lib().orc_solve_scaled(self._h, C.byref(o), _p(d, f64p), None if pa is None else _p(pa, i32p),
+                               _p(r1, f64p), _p(r2, f64p), _p(x, f64p), _p(y, f64p), C.byref(rep))
         info = dict(status=int(rep.status), passes=int(rep.passes),
                     cg_iters=[int(rep.cg_iters[i]) for i in range(rep.passes)],
                     rr_hist=[float(rep.rr_hist[i]) for i in range(rep.passes)],

@@ -811,3 +811,114 @@ double orc_gamma_heuristic(const orc *s) {
     free(rs);
     return jn > 0.0 ? hn / (jn * jn) : 0.0;
 }
+
+/* ------------------------------------------------------------------ */
+/* symmetrized Ruiz scaling (Sec. 4.1, after Ruiz 2001)                */
+/* ------------------------------------------------------------------ */
+
+/* d (n + m entries) such that D K D, D = diag(d), has every row's largest
+ * magnitude near 1: starting from d = 1, each of `iters` sweeps divides d_i
+ * by the square root of row i's largest |(D K D)_ij| (rows that are all
+ * zero keep their d). K = [H + D_x + delta I, J^T; J, 0] as in the solve. */
+void orc_ruiz(const orc *s, i64 iters, double *d) {
+    i64 n = s->n, m = s->m;
+    double *r = xmalloc(sizeof(double) * (size_t)(n + m ? n + m : 1));
+    for (i64 i = 0; i < n + m; i++) d[i] = 1.0;
+    for (i64 it = 0; it < iters; it++) {
+        for (i64 i = 0; i < n + m; i++) r[i] = 0.0;
+        for (i64 i = 0; i < n; i++) {
+            int has = 0;
+            for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) {
+                i64 j = s->Hi[p];
+                if (j == i) {
+                    double a = fabs(s->Hx[p] + s->Dx[i] + s->delta) * d[i] * d[i];
+                    if (a > r[i]) r[i] = a;
+                    has = 1;
+                } else {
+                    double a = fabs(s->Hx[p]) * d[i] * d[j];
+                    if (a > r[i]) r[i] = a;
+                    if (a > r[j]) r[j] = a;
+                }
+            }
+            if (!has) { double a = fabs(s->Dx[i] + s->delta) * d[i] * d[i]; if (a > r[i]) r[i] = a; }
+        }
+        for (i64 k = 0; k < m; k++)
+            for (i64 p = s->Jp[k]; p < s->Jp[k + 1]; p++) {
+                i64 j = s->Ji[p];
+                double a = fabs(s->Jx[p]) * d[n + k] * d[j];
+                if (a > r[n + k]) r[n + k] = a;
+                if (a > r[j]) r[j] = a;
+            }
+        for (i64 i = 0; i < n + m; i++) if (r[i] > 0.0) d[i] /= sqrt(r[i]);
+    }
+    free(r);
+}
+
+/* The system D K D for the scaling d: (1,1) block D1 (H + D_x + delta I) D1
+ * with delta folded into the diagonal (D_x' = d1^2 (D_x + delta), delta' =
+ * 0), J' = D2 J D1, the same gamma. */
+orc *orc_new_scaled(const orc *s, const double *d) {
+    i64 n = s->n, m = s->m;
+    double *Hs = xmalloc(sizeof(double) * (size_t)(s->Hp[n] ? s->Hp[n] : 1));
+    double *Js = xmalloc(sizeof(double) * (size_t)(s->Jp[m] ? s->Jp[m] : 1));
+    double *Ds = xmalloc(sizeof(double) * (size_t)(n ? n : 1));
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = s->Hp[i]; p < s->Hp[i + 1]; p++) Hs[p] = s->Hx[p] * d[i] * d[s->Hi[p]];
+    for (i64 k = 0; k < m; k++)
+        for (i64 p = s->Jp[k]; p < s->Jp[k + 1]; p++) Js[p] = s->Jx[p] * d[n + k] * d[s->Ji[p]];
+    for (i64 i = 0; i < n; i++) Ds[i] = d[i] * d[i] * (s->Dx[i] + s->delta);
+    orc *t = orc_new(n, m, s->Hp, s->Hi, Hs, Ds, s->Jp, s->Ji, Js, 0.0, s->gamma);
+    free(Hs); free(Js); free(Ds);
+    return t;
+}
+
+/* Solve K z = r with the hybrid passes on the scaled system (Sec. 4.1: scale,
+ * then apply the method with gamma relative to the scaled system) and the
+ * refinement on the original K: g = r - K z (compensated); one pass on
+ * D K D with right-hand side D g gives e_hat; z += D e_hat. Stop rules,
+ * report and inertia as orc_solve (D K D is congruent to K). The scaled
+ * system is factored with perm (NULL: natural). Returns the status. */
+int orc_solve_scaled(orc *s, const orc_opts *o, const double *d, const i32 *perm, const double *r1,
+                     const double *r2, double *x, double *y, orc_report *rep) {
+    i64 n = s->n, m = s->m;
+    memset(rep, 0, sizeof(*rep));
+    orc *t = orc_new_scaled(s, d);
+    i64 fc;
+    if (orc_factor(t, perm, &fc) != 0) { orc_free(t); rep->status = 1; return 1; }
+    double *ex = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *ey = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *g1 = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *g2 = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double rn = sqrt(dot(r1, r1, n) + dot(r2, r2, m));
+    for (i64 j = 0; j < n; j++) { x[j] = 0.0; g1[j] = r1[j] * d[j]; }
+    for (i64 i = 0; i < m; i++) { y[i] = 0.0; g2[i] = r2[i] * d[n + i]; }
+    i64 max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    if (max_ref > 15) max_ref = 15;
+    int brk_any = 0;
+    double rr = rn > 0 ? 1.0 : 0.0, rr_best = INFINITY;
+    i64 pass = 0;
+    while (pass <= max_ref) {
+        int brk = 0;
+        i64 it = hybrid_pass(t, o, g1, g2, ex, ey, &brk);
+        brk_any |= brk;
+        for (i64 j = 0; j < n; j++) x[j] += d[j] * ex[j];
+        for (i64 i = 0; i < m; i++) y[i] += d[n + i] * ey[i];
+        kkt_residual(s, r1, r2, x, y, g1, g2);
+        rr = rn > 0 ? sqrt(dot(g1, g1, n) + dot(g2, g2, m)) / rn : 0.0;
+        for (i64 j = 0; j < n; j++) g1[j] *= d[j];
+        for (i64 i = 0; i < m; i++) g2[i] *= d[n + i];
+        rep->cg_iters[pass] = it;
+        rep->rr_hist[pass] = rr;
+        pass++;
+        if (rr <= o->kkt_tol || brk) break;
+        if (pass >= 2 && !(rr < 0.5 * rr_best)) break;
+        if (rr < rr_best) rr_best = rr;
+    }
+    rep->passes = pass;
+    double mt[3];
+    orc_metrics(s, r1, r2, x, y, mt);
+    rep->rr = mt[0]; rep->be = mt[1]; rep->floor = mt[2];
+    rep->inertia[0] = n; rep->inertia[1] = brk_any ? -1 : m; rep->inertia[2] = brk_any ? -1 : 0;
+    rep->status = brk_any && o->delta2 == 0.0 ? 2 : (rr <= o->kkt_tol ? 0 : 3);
+    free(ex); free(ey); free(g1); free(g2);
+    orc_free(t);
+    return (int)rep->status;
+}

@@ -788,3 +788,52 @@ def test_delta2_restart_equals_dense_perturbed_schur():
     # the full solve stops after the pass that broke down
     x2, y2, info = s.solve(b.r1[0], b.r2[0], delta2=d2, max_cg=100)
     assert info["passes"] == 1 and info["status"] in (0, 3) and info["inertia"] == (n, -1, -1)
+
+
+# --------------------------------------------------------------------------
+# symmetrized Ruiz scaling (Sec. 4.1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("gen", ["grid", "dense"])
+def test_ruiz_rows_of_scaled_K_converge_to_one(gen):
+    """Every row of D K D (dense, numpy) has its largest magnitude near 1,
+    the deviation shrinking about twofold per sweep (Ruiz 2001's rate for
+    the inf-norm)."""
+    b = H.tiny_grid_like(400, 84, dx_exp=8.0) if gen == "grid" else H.tiny_dense_like(150, 85, dx_exp=6.0)
+    o = _sys(b)
+    K = H.dense_K(b)
+    devs = []
+    for it in (10, 20, 40):
+        d = o.ruiz(it)
+        assert np.all(d > 0)
+        r = np.abs(d[:, None] * K * d[None, :]).max(axis=1)
+        devs.append(np.abs(r - 1).max())
+    assert devs[0] < 2e-2 and devs[1] < 1e-4 and devs[2] < 1e-9, devs
+
+
+@pytest.mark.parametrize("seed", [86, 87])
+def test_scaled_solve_equals_dense_solution(seed):
+    """Passes on D K D and refinement on K reach the exact solution of K (the
+    scaling is a congruence: the solution and the inertia are those of K)."""
+    b = H.tiny_dense_like(50, seed, dx_exp=4.0)
+    o = _sys(b)
+    d = o.ruiz(10)
+    x, y, info = o.solve_scaled(b.r1[0], b.r2[0], d, o.order_mindeg())
+    z = np.linalg.solve(H.dense_K(b), np.r_[b.r1[0], b.r2[0]])
+    assert info["status"] == 0 and info["rr"] <= 1e-10
+    assert np.linalg.norm(np.r_[x, y] - z) / np.linalg.norm(z) < 1e-8
+    assert info["inertia"] == (b.pattern.n_x, b.pattern.m, 0)
+
+
+def test_scaled_solve_needs_fewer_cg_iterations():
+    """With gamma judged on the scaled system (Sec. 4.1) each J row's
+    effective gamma is gamma * d_y^2: on a grid-like system with D_x spread
+    over 16 decades the scaled solve needs fewer CG iterations in total."""
+    b = H.tiny_grid_like(3000, 83, gamma=1e4, dx_exp=8.0)
+    o = _sys(b)
+    p = o.order_mindeg()
+    o.factor(p)
+    x, y, info = o.solve(b.r1[0], b.r2[0])
+    xs, ys, infs = o.solve_scaled(b.r1[0], b.r2[0], o.ruiz(10), p)
+    assert info["status"] == 0 and infs["status"] == 0
+    assert sum(infs["cg_iters"]) < sum(info["cg_iters"]), (infs["cg_iters"], info["cg_iters"])
