@@ -82,7 +82,7 @@ def run_gpu(args):
     given = {"mixed": args.schedule_mixed, "fp64": args.schedule_fp64}
 
     def make(prec, tune=False):
-        s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10)
+        s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10, scaling=args.scaling)
         s.analyze(b.pattern)
         if given.get(prec):   # a schedule from an earlier autotuning (profiler runs)
             s.set_schedule(*[int(v) for v in given[prec].split(",")])
@@ -183,7 +183,7 @@ def run_gpu(args):
         torch.cuda.synchronize()
         fp64_batched = sum(1 for i in infos64 if i["status"] == 0 and i["rr"] <= 1e-10) * k64 / (
             time.perf_counter() - t0)
-        s1 = make("fp64")
+        s1 = make("fp64")   # same scaling option as the batched solvers
         k1 = min(args.single, nb)
         step(s1, H[:1], D[:1], J[:1], R1[:1], R2[:1], b.delta[:1], b.gamma[:1])
         torch.cuda.synchronize()
@@ -589,6 +589,9 @@ def main():
     ap.add_argument("--no-comparators", action="store_true",
                     help="skip the FP64 batched and plain FP64 runs (profiler runs of the mixed path)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scaling", type=int, default=1,
+                    help="1 (default): symmetrized Ruiz scaling of K before the hybrid method (Sec. 4.1), for the "
+                         "batched and the plain solvers; 0: none")
     ap.add_argument("--no-autotune", action="store_true", help="library default schedule instead of the autotuner's")
     ap.add_argument("--uneven", type=int, default=0,
                     help="this many dense-like systems of uneven sizes in one group (factor + solve once)")

@@ -100,7 +100,12 @@ typedef struct {
                                this process for the same pattern (hash of the analysed pattern,
                                group layout and given order), precision and batch size instead
                                of timing again; 0: always time */
-    int scaling;            /* reserved for equilibration of K (0 = none) */
+    int scaling;            /* 1: symmetrized Ruiz scaling of K (Sec. 4.1; ten sweeps d_i /= sqrt(max_j
+                               |(D K D)_ij|)): the factorization and the hybrid passes work on D K D
+                               (delta folded into its diagonal, gamma acting on the scaled J, i.e.
+                               gamma * d_y^2 per J row), refinement on K's own residual; the factor
+                               (hkkt_get_factor) and hkkt_hsolve are then those of the scaled
+                               system. 0 (default): none */
     int flow_live;          /* applications of H_gamma^{-1} to at most this many instances (the CG
                                tail) run as one dataflow launch (each supernode task waits only for
                                its children / parent) instead of one launch per level; 0 = never.

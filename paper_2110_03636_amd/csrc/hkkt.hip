@@ -537,6 +537,10 @@ struct Batch {
     int prec = HKKT_FP64;   // precision of L / triangular solves
     // values (FP64)
     DBuf H, J, JT, HF, Dx, Dxp, delta, gamma;
+    // scaled system D K D (scaling on): its values, delta 0, the scaling
+    // [d1 permuted ; d2] per instance and a row-max workspace
+    DBuf Hs, Js, JTs, HFs, Dxps, Dxs, dz, sc, rm;
+    bool scaled = false;
     // factor (Dinv: reciprocals of the diagonal of L, per column)
     DBuf L, fail, Dinv;
     // solve workspace
@@ -564,6 +568,16 @@ struct Batch {
         V.nb = nb;
         V.H = H.as<double>(); V.J = J.as<double>(); V.JT = JT.as<double>(); V.HF = HF.as<double>();
         V.Dxp = Dxp.as<double>(); V.Dx = Dx.as<double>(); V.delta = delta.as<double>(); V.gamma = gamma.as<double>();
+        return V;
+    }
+    // the values the factorization and the hybrid passes work on: the
+    // scaled system's when scaling is on (the KKT residual keeps vals())
+    ValView fvals() const {
+        ValView V = vals();
+        if (scaled) {
+            V.H = Hs.as<double>(); V.J = Js.as<double>(); V.JT = JTs.as<double>(); V.HF = HFs.as<double>();
+            V.Dxp = Dxps.as<double>(); V.Dx = Dxs.as<double>(); V.delta = dz.as<double>();
+        }
         return V;
     }
     size_t esz() const { return prec == HKKT_MIXED ? 4 : 8; }
@@ -623,7 +637,7 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     T* CB = c->cbws.as<T>();
     LAUNCH(10, k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
     LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb * S.G, INT_MAX);
-    LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.vals(), L, active);
+    LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.fvals(), L, active);
     for (i32 l = 0; l < S.nlevels; l++) {
         const int ns_small = D.small_ptr[l + 1] - D.small_ptr[l];
         if (ns_small > 0) {
@@ -1015,6 +1029,42 @@ static void alloc_values(hkkt_ctx* c, Batch& B, int nb) {
     B.gamma.ensure((size_t)nb * S.G * 8);
     B.fail.ensure((size_t)nb * S.G * 4);
     B.active.ensure((size_t)nb * 4);
+    B.scaled = c->opt.scaling != 0;
+    if (B.scaled) {
+        B.Hs.ensure((size_t)nb * std::max<i64>(1, S.nnzH) * 8);
+        B.Js.ensure((size_t)nb * std::max<i64>(1, S.nnzJ) * 8);
+        B.JTs.ensure((size_t)nb * std::max<i64>(1, S.nnzJ) * 8);
+        B.HFs.ensure((size_t)nb * std::max<i64>(1, (i64)S.HF_col.size()) * 8);
+        B.Dxps.ensure((size_t)nb * S.n * 8);
+        B.Dxs.ensure((size_t)nb * S.n * 8);
+        B.dz.ensure((size_t)nb * S.G * 8);
+        B.sc.ensure((size_t)nb * (S.n + S.m) * 8);
+        B.rm.ensure((size_t)nb * (S.n + S.m) * 8);
+    }
+}
+
+// symmetrized Ruiz scaling of every instance's K and the scaled system's
+// values (Sec. 4.1: the method then runs on D K D, gamma judged there)
+constexpr int kRuizSweeps = 10;
+static void scale_values(hkkt_ctx* c, Batch& B) {
+    const Symbolic& S = c->sym.S;
+    const DevSym& D = c->dev;
+    hipStream_t st = B.stream;
+    const int nb = B.nb;
+    const i64 nm = S.n + S.m;
+    LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * nm)), dim3(kBlock), 0, st, B.sc.as<double>(), (i64)nb * nm, 1.0);
+    LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.G)), dim3(kBlock), 0, st, B.dz.as<double>(), (i64)nb * S.G,
+           0.0);
+    const ValView V = B.vals();
+    for (int it = 0; it < kRuizSweeps; it++) {
+        LAUNCH(10, k_ruiz_rows, dim3(grid1(nm, 1024), nb), dim3(kBlock), 0, st, D.v, V, (const double*)B.sc.as<double>(),
+               B.rm.as<double>());
+        LAUNCH(10, k_ruiz_apply, dim3(grid1((i64)nb * nm)), dim3(kBlock), 0, st, (i64)nb * nm, B.sc.as<double>(),
+               (const double*)B.rm.as<double>());
+    }
+    LAUNCH(10, k_scale_vals, dim3(grid1(nm, 1024), nb), dim3(kBlock), 0, st, D.v, V, (const double*)B.sc.as<double>(),
+           B.Hs.as<double>(), B.Js.as<double>(), B.JTs.as<double>(), B.HFs.as<double>(), B.Dxps.as<double>(),
+           B.Dxs.as<double>());
 }
 
 static void alloc_factor(hkkt_ctx* c, Batch& B) {
@@ -1077,6 +1127,7 @@ static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx
     LAUNCH(10, k_gather_vals, dim3(grid1(std::max<i64>({S.n, S.nnzJ, (i64)S.HF_col.size()}), 1024), nb),
                        dim3(kBlock), 0, st, c->dev.v, B.H.as<double>(), B.J.as<double>(), B.Dx.as<double>(),
                        B.JT.as<double>(), B.HF.as<double>(), B.Dxp.as<double>());
+    if (B.scaled) scale_values(c, B);
     HIPCHK(hipStreamSynchronize(st));   // host staging vectors go out of scope
 }
 
@@ -1106,7 +1157,7 @@ static std::vector<double> pivot_ratio(hkkt_ctx* c, Batch& B) {
     const int nb = B.nb, G = S.G;
     alloc_solve(c, B);
     const unsigned nbr = (unsigned)D.v.nbr;
-    LAUNCH(10, k_pivot_ratio<T>, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(), (const T*)B.Dinv.as<T>(),
+    LAUNCH(10, k_pivot_ratio<T>, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.fvals(), (const T*)B.Dinv.as<T>(),
            B.part1.as<double>());
     LAUNCH(10, k_reduce_max, dim3(nb, G), dim3(64), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
            D.v.rblk_off, B.rowred.as<double>(), -INFINITY);
@@ -1136,14 +1187,14 @@ static std::vector<double> fp32_factor_quality(hkkt_ctx* c, Batch& B) {
     if (D.v.nbm > 0) {
         LAUNCH(10, k_fill<double>, dim3(grid1((i64)nb * S.m)), dim3(kBlock), 0, st, B.g2.as<double>(), (i64)nb * S.m,
                0.0);
-        LAUNCH(10, k_j<float>, dim3(D.v.nbm, nb), dim3(kBlock), 0, st, D.v, B.vals(), (const float*)B.X.as<float>(),
+        LAUNCH(10, k_j<float>, dim3(D.v.nbm, nb), dim3(kBlock), 0, st, D.v, B.fvals(), (const float*)B.X.as<float>(),
                (const double*)B.g2.as<double>(), (const double*)nullptr, (const CGState*)nullptr, 0,
                B.bvec.as<double>(), B.part2.as<double>(), (double*)nullptr, (const int*)nullptr);
     } else if (S.m > 0) {
         throw Error(HKKT_ERR_DEVICE, "internal: J rows without reduction blocks");
     }
     const unsigned nbr = (unsigned)D.v.nbr;
-    LAUNCH(10, k_hgamma_check<float>, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.vals(),
+    LAUNCH(10, k_hgamma_check<float>, dim3(nbr, nb), dim3(kBlock), 0, st, D.v, B.fvals(),
            (const double*)B.rhat.as<double>(), (const float*)B.X.as<float>(), (const double*)B.bvec.as<double>(),
            B.part1.as<double>(), B.pfloor.as<double>());
     LAUNCH(10, k_reduce_rows, dim3(nb, G), dim3(kBlock), 0, st, (const double*)B.part1.as<double>(), (int)nbr,
@@ -1187,11 +1238,15 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
     const int* ids = B.ids_pass.as<int>();
     const int G = S.G;
     const int* cact = G > 1 ? B.cact.as<int>() : nullptr;
-    const ValView V = B.vals();
+    const ValView V = B.fvals();
     CGState* cst = B.st.as<CGState>();
     const unsigned gn = grid1(S.n, 4096), gm = grid1(S.m);
     const unsigned nbm = (unsigned)D.v.nbm;
     T* X = B.X.as<T>();
+    // scaling: the pass works on D K D, its right-hand side D g
+    if (B.scaled)
+        LAUNCH(10, k_scale_pair, dim3(grid1(S.n + S.m, 4096), nids), dim3(kBlock), 0, st,
+               (const double*)B.sc.as<double>(), (i64)S.n, (i64)S.m, B.g1.as<double>(), B.g2.as<double>(), ids);
     // rhat = g1 + gamma J^T g2; w = H_gamma^{-1} rhat
     LAUNCH(5, k_jt<double>, dim3(gn, nids), dim3(kBlock), 0, st, D.v, V, B.g1.as<double>(), 1.0, 1,
            B.g2.as<double>(), B.rhat.as<double>(), ids, (const CGState*)nullptr);
@@ -1247,6 +1302,10 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
     launch_trisolve<T>(c, B, ids, nids, nullptr);
     LAUNCH(10, (k_cast<T, double>), dim3(gn, nids), dim3(kBlock), 0, st, (const T*)X, B.ex.as<double>(), (i64)S.n,
            ids, (const CGState*)nullptr);
+    // back from the scaled system: e = D e_hat
+    if (B.scaled)
+        LAUNCH(10, k_scale_pair, dim3(grid1(S.n + S.m, 4096), nids), dim3(kBlock), 0, st,
+               (const double*)B.sc.as<double>(), (i64)S.n, (i64)S.m, B.ex.as<double>(), B.y.as<double>(), ids);
     hst.resize((size_t)B.nb * G);
     HIPCHK(hipMemcpyAsync(hst.data(), cst, hst.size() * sizeof(CGState), hipMemcpyDeviceToHost, st));
 }
@@ -2150,6 +2209,11 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                     cp(F.H, B.H, S.nnzH, i, e); cp(F.J, B.J, S.nnzJ, i, e); cp(F.JT, B.JT, S.nnzJ, i, e);
                     cp(F.HF, B.HF, (i64)S.HF_col.size(), i, e); cp(F.Dx, B.Dx, S.n, i, e);
                     cp(F.Dxp, B.Dxp, S.n, i, e); cp(F.delta, B.delta, G, i, e); cp(F.gamma, B.gamma, G, i, e);
+                    if (F.scaled) {
+                        cp(F.Hs, B.Hs, S.nnzH, i, e); cp(F.Js, B.Js, S.nnzJ, i, e); cp(F.JTs, B.JTs, S.nnzJ, i, e);
+                        cp(F.HFs, B.HFs, (i64)S.HF_col.size(), i, e); cp(F.Dxps, B.Dxps, S.n, i, e);
+                        cp(F.Dxs, B.Dxs, S.n, i, e); cp(F.dz, B.dz, G, i, e); cp(F.sc, B.sc, S.n + S.m, i, e);
+                    }
                 }
                 std::vector<int> act(ne, 1);
                 factor_batch(c, F, act);

@@ -99,6 +99,95 @@ __global__ void k_gather_vals(SymView S, const double* __restrict__ H, const dou
 }
 
 // ---------------------------------------------------------------------------
+// symmetrized Ruiz scaling of K = [H + D_x + delta I, J^T; J, 0] (Sec. 4.1):
+// sc per instance holds d over [x rows in the permuted order ; J rows]. One
+// sweep: rm_i = max_j |(D K D)_ij| (k_ruiz_rows), then d_i /= sqrt(rm_i)
+// (k_ruiz_apply, rows that are all zero keep their d).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_ruiz_rows(SymView S, ValView V, const double* __restrict__ sc,
+                                                      double* __restrict__ rm) {
+    const int b = blockIdx.y;
+    const i64 nm = S.n + S.m;
+    const double* d = sc + (i64)b * nm;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nm; i += (i64)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        if (i < S.n) {
+            const double* HF = V.HF + (i64)b * S.nnzHF;
+            const double* JT = V.JT + (i64)b * S.nnzJ;
+            const int k = S.G > 1 ? S.xp_mem[i] : 0;
+            double dg = V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k];
+            const double di = d[i];
+            for (i64 q = S.HF_rowptr[i]; q < S.HF_rowptr[i + 1]; q++) {
+                if (S.HF_col[q] == i) dg += HF[q];
+                else a = fmax(a, fabs(HF[q]) * di * d[S.HF_col[q]]);
+            }
+            a = fmax(a, fabs(dg) * di * di);
+            for (i64 q = S.JT_rowptr[i]; q < S.JT_rowptr[i + 1]; q++)
+                a = fmax(a, fabs(JT[q]) * di * d[S.n + S.JT_col[q]]);
+        } else {
+            const double* J = V.J + (i64)b * S.nnzJ;
+            const i64 r = i - S.n;
+            const double dr = d[i];
+            for (i64 q = S.J_rowptr[r]; q < S.J_rowptr[r + 1]; q++) a = fmax(a, fabs(J[q]) * dr * d[S.J_colp[q]]);
+        }
+        rm[(i64)b * nm + i] = a;
+    }
+}
+
+__global__ void k_ruiz_apply(i64 len, double* __restrict__ sc, const double* __restrict__ rm) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (i64)gridDim.x * blockDim.x)
+        if (rm[i] > 0.0) sc[i] /= sqrt(rm[i]);
+}
+
+// Values of the scaled system D K D: H' = D1 H D1 (full permuted HF', and
+// tril H' in the caller's order by scattering HF' through HF_src: both
+// triangle entries of a pair carry the same value), J' = D2 J D1, J'^T, and
+// the diagonal D_x' = d1^2 (D_x + delta) (delta folded in; the scaled
+// system's delta is 0), permuted and in the caller's order.
+__global__ __launch_bounds__(kBlock) void k_scale_vals(SymView S, ValView V, const double* __restrict__ sc,
+                                                       double* __restrict__ Hs, double* __restrict__ Js,
+                                                       double* __restrict__ JTs, double* __restrict__ HFs,
+                                                       double* __restrict__ Dxps, double* __restrict__ Dxs) {
+    const int b = blockIdx.y;
+    const i64 nm = S.n + S.m;
+    const double* d = sc + (i64)b * nm;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nm; i += (i64)gridDim.x * blockDim.x) {
+        if (i < S.n) {
+            const double di = d[i];
+            for (i64 q = S.HF_rowptr[i]; q < S.HF_rowptr[i + 1]; q++) {
+                const double v = V.HF[(i64)b * S.nnzHF + q] * di * d[S.HF_col[q]];
+                HFs[(i64)b * S.nnzHF + q] = v;
+                Hs[(i64)b * S.nnzH + S.HF_src[q]] = v;
+            }
+            for (i64 q = S.JT_rowptr[i]; q < S.JT_rowptr[i + 1]; q++)
+                JTs[(i64)b * S.nnzJ + q] = V.JT[(i64)b * S.nnzJ + q] * di * d[S.n + S.JT_col[q]];
+            const int k = S.G > 1 ? S.xp_mem[i] : 0;
+            const double v = di * di * (V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k]);
+            Dxps[(i64)b * S.n + i] = v;
+            Dxs[(i64)b * S.n + S.perm[i]] = v;
+        } else {
+            const i64 r = i - S.n;
+            const double dr = d[i];
+            for (i64 q = S.J_rowptr[r]; q < S.J_rowptr[r + 1]; q++)
+                Js[(i64)b * S.nnzJ + q] = V.J[(i64)b * S.nnzJ + q] * dr * d[S.J_colp[q]];
+        }
+    }
+}
+
+// x[b][i] *= d[b][i] (i < n, permuted order) and y[b][r] *= d[b][n + r] for
+// the instances listed in ids (all when null): a vector pair into or out of
+// the scaled system
+__global__ void k_scale_pair(const double* __restrict__ sc, i64 n, i64 m, double* __restrict__ x,
+                             double* __restrict__ y, const int* ids) {
+    const int b = inst_of(ids, blockIdx.y);
+    const double* d = sc + (i64)b * (n + m);
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += (i64)gridDim.x * blockDim.x) {
+        if (i < n) x[(i64)b * n + i] *= d[i];
+        else y[(i64)b * m + (i - n)] *= d[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // assembly: H_gamma = tril(H) + diag(D_x + delta) + gamma * tril(J^T J)
 // (Sec. 3 and eq. eq:gamma), one thread per entry of tril(P H_gamma P^T),
 // summed in FP64 in a fixed order and written into the supernodal panels.
