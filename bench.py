@@ -82,7 +82,9 @@ def run_gpu(args):
     given = {"mixed": args.schedule_mixed, "fp64": args.schedule_fp64}
 
     def make(prec, tune=False):
-        s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10, scaling=args.scaling)
+        extra = {} if args.mixed_pivot_tol is None else {"mixed_pivot_tol": args.mixed_pivot_tol}
+        s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10, scaling=args.scaling,
+                        refine_inexact=args.refine_inexact, mixed_check=args.mixed_check, **extra)
         s.analyze(b.pattern)
         if given.get(prec):   # a schedule from an earlier autotuning (profiler runs)
             s.set_schedule(*[int(v) for v in given[prec].split(",")])
@@ -589,6 +591,14 @@ def main():
     ap.add_argument("--no-comparators", action="store_true",
                     help="skip the FP64 batched and plain FP64 runs (profiler runs of the mixed path)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mixed-check", type=int, default=0,
+                    help="1: probe each FP32 factor at factor time and refactor in FP64 where it cannot drive "
+                         "refinement")
+    ap.add_argument("--mixed-pivot-tol", type=float, default=None,
+                    help="FP32 pivot test threshold (library default 2^-16)")
+    ap.add_argument("--refine-inexact", type=int, default=1,
+                    help="1 (default): refinement passes after the first stop CG at the accuracy the correction "
+                         "needs; 0: every pass at the CG tolerance")
     ap.add_argument("--scaling", type=int, default=1,
                     help="1 (default): symmetrized Ruiz scaling of K before the hybrid method (Sec. 4.1), for the "
                          "batched and the plain solvers; 0: none")

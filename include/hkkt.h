@@ -113,6 +113,11 @@ typedef struct {
                                Default 0: measured no faster than the level launches for one
                                live instance and slower for more (each task's agent-scope
                                release and acquire cost about as much as a launch) */
+    int refine_inexact;     /* 1: refinement passes after the first stop CG at the relative residual
+                               max(cg tolerance, min(1e-2, 0.1 * kkt_tol / RR)) of their instance
+                               (the accuracy the correction needs to take RR below kkt_tol with a
+                               tenfold margin); the first pass keeps the CG tolerance. 0 (default):
+                               every pass at the CG tolerance */
     double mixed_pivot_tol; /* mixed precision: an FP32 factor whose smallest ratio of pivot L_jj^2
                                to the assembled FP64 diagonal a_jj of H_gamma is below this is
                                replaced by an FP64 factor at factor time (the FP32 success does not
@@ -134,7 +139,7 @@ typedef struct {
 /* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
  * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5,
- * autotune_cache 1, scaling 0, flow_live 0, mixed_pivot_tol 2^-16. */
+ * autotune_cache 1, scaling 0, flow_live 0, refine_inexact 0, mixed_pivot_tol 2^-16. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream

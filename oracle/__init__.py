@@ -33,7 +33,8 @@ def build(force: bool = True) -> str:
 
 class _Opts(C.Structure):
     _fields_ = [("cg_tol", C.c_double), ("kkt_tol", C.c_double), ("qf_eps", C.c_double),
-                ("delta2", C.c_double), ("max_cg", C.c_int64), ("max_refine", C.c_int64)]
+                ("delta2", C.c_double), ("max_cg", C.c_int64), ("max_refine", C.c_int64),
+                ("inexact", C.c_int64)]
 
 
 class _Report(C.Structure):
@@ -188,8 +189,8 @@ class System:
         return float(out[0]), float(out[1]), float(out[2])
 
     @staticmethod
-    def _opts(cg_tol=1e-12, kkt_tol=1e-10, qf_eps=1e-14, delta2=0.0, max_cg=0, max_refine=10):
-        return _Opts(cg_tol, kkt_tol, qf_eps, delta2, max_cg, max_refine)
+    def _opts(cg_tol=1e-12, kkt_tol=1e-10, qf_eps=1e-14, delta2=0.0, max_cg=0, max_refine=10, inexact=0):
+        return _Opts(cg_tol, kkt_tol, qf_eps, delta2, max_cg, max_refine, inexact)
 
     def solve(self, r1, r2, **kw):
         r1 = _c(r1, np.float64)

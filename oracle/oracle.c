@@ -564,7 +564,23 @@ typedef struct {
     double delta2;        /* used only after a breakdown; 0 = report breakdown */
     i64 max_cg;           /* <= 0: min(m, 1000) */
     i64 max_refine;       /* 10 */
+    i64 inexact;          /* 1: passes after the first at the CG tolerance pass_tol() gives */
 } orc_opts;
+
+/* Inexact refinement (a reading: the paper has no refinement): a pass after
+ * the first needs its correction only as accurately as it takes RR below
+ * kkt_tol with a tenfold margin, so its CG stops at the relative residual
+ * max(cg_tol, min(1e-2, 0.1 * kkt_tol / RR)) with RR that of the current
+ * iterate. */
+static orc_opts pass_opts(const orc_opts *o, i64 pass, double rr) {
+    orc_opts q = *o;
+    if (o->inexact && pass > 0 && rr > 0.0) {
+        double t = 0.1 * o->kkt_tol / rr;
+        if (t > 1e-2) t = 1e-2;
+        if (t > q.cg_tol) q.cg_tol = t;
+    }
+    return q;
+}
 
 typedef struct {
     i64 status;           /* 0 ok, 2 CG breakdown, 3 not converged, -3 no factor */
@@ -659,7 +675,8 @@ int orc_solve(orc *s, const orc_opts *o, const double *r1, const double *r2, dou
     i64 pass = 0;
     while (pass <= max_ref) {
         int brk = 0;
-        i64 it = hybrid_pass(s, o, g1, g2, ex, ey, &brk);
+        const orc_opts po = pass_opts(o, pass, rr);
+        i64 it = hybrid_pass(s, &po, g1, g2, ex, ey, &brk);
         brk_any |= brk;
         for (i64 j = 0; j < n; j++) x[j] += ex[j];
         for (i64 i = 0; i < m; i++) y[i] += ey[i];
@@ -897,7 +914,8 @@ int orc_solve_scaled(orc *s, const orc_opts *o, const double *d, const i32 *perm
     i64 pass = 0;
     while (pass <= max_ref) {
         int brk = 0;
-        i64 it = hybrid_pass(t, o, g1, g2, ex, ey, &brk);
+        const orc_opts po = pass_opts(o, pass, rr);
+        i64 it = hybrid_pass(t, &po, g1, g2, ex, ey, &brk);
         brk_any |= brk;
         for (i64 j = 0; j < n; j++) x[j] += d[j] * ex[j];
         for (i64 i = 0; i < m; i++) y[i] += d[n + i] * ey[i];

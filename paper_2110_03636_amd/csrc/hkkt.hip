@@ -548,6 +548,7 @@ struct Batch {
     DBuf rsq, rowred, knorm, active;
     DBuf ids_pass, ids_a, ids_b, ids_all;   // batch-entry lists of the solve phase
     DBuf cact;                 // per (entry, member): member takes part in the current pass (groups)
+    DBuf ptol;                 // per (entry, member) CG tolerance of the current pass (inexact refinement)
     // solve copy of the top levels' panels for the staged tree kernel:
     // levels [lt_lo, nlevels), lt_size entries per instance from L storage
     // offset lt_base; lt_lo = -1 when stale (rebuilt after a factorization)
@@ -1231,7 +1232,8 @@ static void check_flow(Batch& B) {
 }
 
 template <typename T>
-static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_tol, std::vector<CGState>& hst) {
+static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_tol, const double* ptol,
+                        std::vector<CGState>& hst) {
     const Symbolic& S = c->sym.S;
     const DevSym& D = c->dev;
     hipStream_t st = B.stream;
@@ -1283,7 +1285,7 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
                (const double*)B.q.as<double>(), (const double*)B.bvec.as<double>(), B.y.as<double>(),
                B.res.as<double>(), (const CGState*)cst, B.part1.as<double>(), (const int*)cur);
         LAUNCH(8, k_cg_beta, dim3(ncur, G), dim3(kBlock), 0, st, D.v, cst, (const double*)B.part1.as<double>(),
-               cg_tol, max_cg, (const int*)cur);
+               cg_tol, ptol, max_cg, (const int*)cur);
         LAUNCH(7, k_cg_p, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, B.p.as<double>(),
                (const double*)B.res.as<double>(), (const CGState*)cst, (const int*)cur);
         if ((it + 1) % check_every == 0) {
@@ -1412,8 +1414,21 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
     for (int pass = 0; pass <= max_ref; pass++) {
         nids = upload_ids(c, B, B.ids_pass, act);
         if (nids == 0) break;
-        if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, nids, max_cg, cg_tol, hst);
-        else hybrid_pass<double>(c, B, nids, max_cg, cg_tol, hst);
+        // inexact refinement: after the first pass of a cold start (the
+        // paper's CG tolerance) a pass needs its correction only to the
+        // accuracy that takes RR below kkt_tol with a tenfold margin
+        const double* ptol = nullptr;
+        if ((pass > 0 || warm) && o.refine_inexact) {
+            std::vector<double> tl(nc, cg_tol);
+            for (int i = 0; i < nc; i++)
+                if (act[i] && is[i].rr > 0.0) tl[i] = std::max(cg_tol, std::min(1e-2, 0.1 * o.kkt_tol / is[i].rr));
+            B.ptol.ensure((size_t)nc * 8);
+            HIPCHK(hipMemcpyAsync(B.ptol.p, tl.data(), (size_t)nc * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));   // tl goes out of scope
+            ptol = B.ptol.as<double>();
+        }
+        if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, nids, max_cg, cg_tol, ptol, hst);
+        else hybrid_pass<double>(c, B, nids, max_cg, cg_tol, ptol, hst);
         update_residual(c, B, B.ids_pass.as<int>(), nids, rsq, true, nullptr);
         check_flow(B);
         for (int i = 0; i < nc; i++) {
@@ -1631,6 +1646,7 @@ void hkkt_default_options(hkkt_options* o) {
     o->autotune_cache = 1;
     o->scaling = 0;
     o->flow_live = 0;
+    o->refine_inexact = 0;
     o->mixed_pivot_tol = 0x1p-16;
 }
 

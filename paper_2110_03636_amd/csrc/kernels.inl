@@ -2069,7 +2069,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(SymView S, const double* _
     if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
 }
 
-__global__ void k_cg_beta(SymView S, CGState* st, const double* part, double tol, int max_it, const int* ids) {
+__global__ void k_cg_beta(SymView S, CGState* st, const double* part, double tol, const double* ptol, int max_it,
+                          const int* ids) {
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
     const i64 ci = (i64)b * S.G + k;
@@ -2085,7 +2086,8 @@ __global__ void k_cg_beta(SymView S, CGState* st, const double* part, double tol
             c.curv0 = -1.0;
         } else {
             c.it++;
-            if (sqrt(r1) <= tol * c.bnorm || c.it >= max_it) c.done = 1;
+            const double t = ptol ? ptol[ci] : tol;   // per (instance, member) when given
+            if (sqrt(r1) <= t * c.bnorm || c.it >= max_it) c.done = 1;
             c.beta = r1 / c.rho;
             c.rho = r1;
         }

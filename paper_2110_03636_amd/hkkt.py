@@ -43,7 +43,8 @@ class Options(C.Structure):
                 ("delta2", C.c_double), ("max_cg", C.c_int), ("max_refine", C.c_int),
                 ("ordering", C.c_int), ("relax", C.c_int), ("deterministic", C.c_int),
                 ("mixed_check", C.c_int), ("mixed_check_tol", C.c_double), ("autotune_cache", C.c_int),
-                ("scaling", C.c_int), ("flow_live", C.c_int), ("mixed_pivot_tol", C.c_double)]
+                ("scaling", C.c_int), ("flow_live", C.c_int), ("refine_inexact", C.c_int),
+                ("mixed_pivot_tol", C.c_double)]
 
 
 class Info(C.Structure):

@@ -49,3 +49,27 @@ def test_scaled_solve_dense_like_and_group():
     xs, ys = g.split_x(x), g.split_y(y)
     for k, m in enumerate(mem):
         H.check_gpu_solution(oracle.System.from_batch(m, 0), m.r1[0], m.r2[0], xs[k][0], ys[k][0], infos[k], 1e-10)
+
+
+@pytest.mark.parametrize("precision,scaling", [("fp64", 0), ("fp64", 1), ("mixed", 1)])
+def test_inexact_refinement_equals_oracle(precision, scaling):
+    """refine_inexact = 1: passes after the first at max(tol, min(1e-2, 0.1
+    kkt_tol / RR)); every instance accepted by the oracle at 1e-10 and, in
+    FP64, CG counts within the rounding bound of the oracle's inexact
+    refinement (the same rule on its own RR)."""
+    b = synth.grid_like(3000, nb=6, seed=520 + scaling, gammas=(1e4, 1e6), dx_exp=8.0)
+    s = hkkt.Solver(precision=precision, scaling=scaling, refine_inexact=1)
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    for i in range(b.nb):
+        o = oracle.System.from_batch(b, i)
+        H.check_gpu_solution(o, b.r1[i], b.r2[i], x[i], y[i], infos[i], 1e-10)
+        if precision == "fp64":
+            if scaling:
+                xo, yo, io = o.solve_scaled(b.r1[i], b.r2[i], o.ruiz(10), s.perm(), inexact=1)
+            else:
+                o.factor(s.perm())
+                xo, yo, io = o.solve(b.r1[i], b.r2[i], inexact=1)
+            assert io["status"] == 0
+            assert abs(infos[i]["cg_iters"] - sum(io["cg_iters"])) <= H.cg_count_tol(io["cg_iters"], infos[i]["passes"])

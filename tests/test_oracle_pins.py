@@ -837,3 +837,34 @@ def test_scaled_solve_needs_fewer_cg_iterations():
     xs, ys, infs = o.solve_scaled(b.r1[0], b.r2[0], o.ruiz(10), p)
     assert info["status"] == 0 and infs["status"] == 0
     assert sum(infs["cg_iters"]) < sum(info["cg_iters"]), (infs["cg_iters"], info["cg_iters"])
+
+
+@pytest.mark.parametrize("scaled", [False, True])
+def test_inexact_refinement_reaches_the_solution_with_fewer_iterations(scaled):
+    """Refinement passes after the first stop CG at max(cg_tol, min(1e-2,
+    0.1 kkt_tol / RR)): the iterate still reaches RR <= 1e-10 and, on a tiny
+    system, numpy's solution of K; the later passes take fewer CG
+    iterations than at the full tolerance."""
+    b = H.tiny_dense_like(50, 88, dx_exp=4.0)
+    o = _sys(b)
+    z = np.linalg.solve(H.dense_K(b), np.r_[b.r1[0], b.r2[0]])
+    if scaled:
+        x, y, info = o.solve_scaled(b.r1[0], b.r2[0], o.ruiz(10), o.order_mindeg(), inexact=1)
+    else:
+        o.factor(o.order_mindeg())
+        x, y, info = o.solve(b.r1[0], b.r2[0], inexact=1)
+    assert info["status"] == 0 and info["rr"] <= 1e-10
+    assert np.linalg.norm(np.r_[x, y] - z) / np.linalg.norm(z) < 1e-8
+    g = H.tiny_grid_like(3000, 89, gamma=1e4, dx_exp=8.0)
+    og = _sys(g)
+    p = og.order_mindeg()
+    og.factor(p)
+    d = og.ruiz(10)
+    run = (lambda **kw: og.solve_scaled(g.r1[0], g.r2[0], d, p, **kw)) if scaled else \
+        (lambda **kw: og.solve(g.r1[0], g.r2[0], **kw))
+    _, _, full = run(inexact=0)
+    _, _, inex = run(inexact=1)
+    assert inex["status"] == 0 and inex["rr"] <= 1e-10
+    assert inex["cg_iters"][0] == full["cg_iters"][0]          # the first pass is the paper's
+    if full["passes"] > 1:
+        assert sum(inex["cg_iters"][1:]) < sum(full["cg_iters"][1:]), (inex["cg_iters"], full["cg_iters"])
