@@ -81,6 +81,14 @@ def lib():
         L.orc_solve_scaled.restype = C.c_int
         L.orc_solve_scaled.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, i32p, f64p, f64p, f64p, f64p,
                                        C.POINTER(_Report)]
+        L.orc4_new.restype = C.c_void_p
+        L.orc4_new.argtypes = [C.c_int64, C.c_int64, C.c_int64, i64p, i32p, f64p, f64p, i64p, i32p, f64p,
+                               i64p, i32p, f64p, f64p, C.c_double, C.c_double]
+        L.orc4_free.argtypes = [C.c_void_p]
+        L.orc4_two.restype = C.c_void_p
+        L.orc4_two.argtypes = [C.c_void_p]
+        L.orc4_solve.argtypes = [C.c_void_p, C.POINTER(_Opts)] + [f64p] * 9
+        L.orc4_metrics.argtypes = [C.c_void_p] + [f64p] * 9
         L.orc_refine_dd.restype = C.c_int64
         L.orc_refine_dd.argtypes = [C.c_void_p, C.POINTER(_Opts), f64p, f64p, f64p, f64p, C.c_int64, f64p]
         _lib = L
@@ -274,3 +282,56 @@ class System:
         o2 = np.empty(self.m)
         lib().orc_apply_K(self._h, _p(x, f64p), _p(y, f64p), _p(o1, f64p), _p(o2, f64p))
         return o1, o2
+
+
+class System4:
+    """The 4x4 system of Sec. 3: K4 = [H + D_x + delta I, 0, J^T, J_d^T; 0, D_s,
+    0, -I; J, 0, 0, 0; J_d, -I, 0, 0], solved through the 2x2 reduction."""
+
+    def __init__(self, n_x, m, m_d, H_rowptr, H_col, H_val, D_x, J_rowptr, J_col, J_val, Jd_rowptr, Jd_col,
+                 Jd_val, D_s, delta, gamma):
+        self.n, self.m, self.md = int(n_x), int(m), int(m_d)
+        k = self._keep = [_c(H_rowptr, np.int64), _c(H_col, np.int32), _c(H_val, np.float64), _c(D_x, np.float64),
+                          _c(J_rowptr, np.int64), _c(J_col, np.int32), _c(J_val, np.float64),
+                          _c(Jd_rowptr, np.int64), _c(Jd_col, np.int32), _c(Jd_val, np.float64),
+                          _c(D_s, np.float64)]
+        t = [i64p, i32p, f64p, f64p, i64p, i32p, f64p, i64p, i32p, f64p, f64p]
+        self._h = lib().orc4_new(self.n, self.m, self.md, *[_p(a, tt) for a, tt in zip(k, t)],
+                                 float(delta), float(gamma))
+        self.two = System.__new__(System)        # view of the 2x2 system (owned here)
+        self.two.n, self.two.m, self.two._h, self.two.perm = self.n, self.m, lib().orc4_two(self._h), None
+
+    @classmethod
+    def from_batch(cls, batch, ineq, b=0):
+        p = batch.pattern
+        return cls(p.n_x, p.m, ineq.m_d, p.H_rowptr, p.H_col, batch.H_val[b], batch.D_x[b], p.J_rowptr, p.J_col,
+                   batch.J_val[b], ineq.Jd_rowptr, ineq.Jd_col, ineq.Jd_val[b], ineq.D_s[b], batch.delta[b],
+                   batch.gamma[b])
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self.two._h = None
+                lib().orc4_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def factor(self, perm=None):
+        return self.two.factor(perm)
+
+    def solve(self, rx, rs, ry, ryd, **kw):
+        a = [_c(v, np.float64) for v in (rx, rs, ry, ryd)]
+        x, sv, y, yd = np.empty(self.n), np.empty(self.md), np.empty(self.m), np.empty(self.md)
+        out = np.empty(5)
+        o = System._opts(**kw)
+        lib().orc4_solve(self._h, C.byref(o), *[_p(v, f64p) for v in a], *[_p(v, f64p) for v in (x, sv, y, yd)],
+                         _p(out, f64p))
+        return x, sv, y, yd, dict(rr=float(out[0]), be=float(out[1]), steps=int(out[2]), cg_iters=int(out[3]),
+                                  status=int(out[4]))
+
+    def metrics(self, rx, rs, ry, ryd, x, sv, y, yd):
+        a = [_c(v, np.float64) for v in (rx, rs, ry, ryd, x, sv, y, yd)]
+        out = np.empty(2)
+        lib().orc4_metrics(self._h, *[_p(v, f64p) for v in a], _p(out, f64p))
+        return float(out[0]), float(out[1])

@@ -940,3 +940,204 @@ int orc_solve_scaled(orc *s, const orc_opts *o, const double *d, const i32 *perm
     orc_free(t);
     return (int)rep->status;
 }
+
+/* ------------------------------------------------------------------ */
+/* the full 4x4 system of Sec. 3 (eq. linsys4x4)                       */
+/* ------------------------------------------------------------------ */
+/* K4 = [H + D_x + delta I, 0, J^T, J_d^T; 0, D_s, 0, -I; J, 0, 0, 0;
+ *       J_d, -I, 0, 0], unknowns (dx, ds, dy, dyd), right-hand side
+ * (rx~, rs, ry, ryd). Eliminating ds = J_d dx - ryd and dyd = D_s ds - rs
+ * gives the 2x2 system (eq. linsys2x2) with Htilde = H + D_x + J_d^T D_s J_d
+ * and r_x = rx~ + J_d^T (D_s ryd + rs), which the hybrid method solves. */
+typedef struct {
+    orc *two;                 /* the 2x2 system with Htilde's H part H + J_d^T D_s J_d */
+    i64 n, m, md;
+    i64 *Hp; i32 *Hi; double *Hx;        /* tril(H) as given */
+    i64 *Dp; i32 *Di; double *Dv;        /* J_d CSR */
+    double *Ds;
+} orc4;
+
+orc4 *orc4_new(i64 n, i64 m, i64 md, const i64 *Hp, const i32 *Hi, const double *Hx, const double *Dx,
+               const i64 *Jp, const i32 *Ji, const double *Jx, const i64 *Dp, const i32 *Di, const double *Dv,
+               const double *Ds, double delta, double gamma) {
+    orc4 *q = xcalloc(1, sizeof(orc4));
+    q->n = n; q->m = m; q->md = md;
+    q->Hp = xmalloc(sizeof(i64) * (size_t)(n + 1)); memcpy(q->Hp, Hp, sizeof(i64) * (size_t)(n + 1));
+    q->Hi = xmalloc(sizeof(i32) * (size_t)(Hp[n] ? Hp[n] : 1)); memcpy(q->Hi, Hi, sizeof(i32) * (size_t)Hp[n]);
+    q->Hx = xmalloc(sizeof(double) * (size_t)(Hp[n] ? Hp[n] : 1)); memcpy(q->Hx, Hx, sizeof(double) * (size_t)Hp[n]);
+    q->Dp = xmalloc(sizeof(i64) * (size_t)(md + 1)); memcpy(q->Dp, Dp, sizeof(i64) * (size_t)(md + 1));
+    q->Di = xmalloc(sizeof(i32) * (size_t)(Dp[md] ? Dp[md] : 1)); memcpy(q->Di, Di, sizeof(i32) * (size_t)Dp[md]);
+    q->Dv = xmalloc(sizeof(double) * (size_t)(Dp[md] ? Dp[md] : 1)); memcpy(q->Dv, Dv, sizeof(double) * (size_t)Dp[md]);
+    q->Ds = xmalloc(sizeof(double) * (size_t)(md ? md : 1)); memcpy(q->Ds, Ds, sizeof(double) * (size_t)md);
+    /* tril(H + J_d^T D_s J_d) by triplets (row >= col), duplicates summed in
+     * a fixed order, rows sorted */
+    i64 cnt = Hp[n];
+    for (i64 i = 0; i < md; i++) { i64 k = Dp[i + 1] - Dp[i]; cnt += k * (k + 1) / 2; }
+    trip *t = xmalloc(sizeof(trip) * (size_t)(cnt ? cnt : 1));
+    i64 z = 0;
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = Hp[i]; p < Hp[i + 1]; p++) { t[z].row = Hi[p]; t[z].col = i; t[z].v = Hx[p]; t[z].seq = z; z++; }
+    for (i64 i = 0; i < md; i++)
+        for (i64 a = Dp[i]; a < Dp[i + 1]; a++)
+            for (i64 b = Dp[i]; b < Dp[i + 1]; b++) {
+                if (Di[a] < Di[b]) continue;
+                /* stored as (row = larger index, col = smaller): tril by rows below */
+                t[z].row = Di[b]; t[z].col = Di[a]; t[z].v = Ds[i] * Dv[a] * Dv[b]; t[z].seq = z; z++;
+            }
+    /* trip_cmp sorts by col then row: here col holds the CSR row (larger
+     * index) and row the CSR column */
+    qsort(t, (size_t)z, sizeof(trip), trip_cmp);
+    i64 *Tp = xcalloc((size_t)n + 1, sizeof(i64));
+    i32 *Ti = xmalloc(sizeof(i32) * (size_t)(z ? z : 1));
+    double *Tx = xmalloc(sizeof(double) * (size_t)(z ? z : 1));
+    i64 nz = 0;
+    for (i64 k = 0; k < z; k++) {
+        if (nz > 0 && k > 0 && t[k - 1].col == t[k].col && Ti[nz - 1] == t[k].row) Tx[nz - 1] += t[k].v;
+        else { Ti[nz] = (i32)t[k].row; Tx[nz] = t[k].v; Tp[t[k].col + 1]++; nz++; }
+    }
+    for (i64 i = 0; i < n; i++) Tp[i + 1] += Tp[i];
+    free(t);
+    q->two = orc_new(n, m, Tp, Ti, Tx, Dx, Jp, Ji, Jx, delta, gamma);
+    free(Tp); free(Ti); free(Tx);
+    return q;
+}
+
+void orc4_free(orc4 *q) {
+    if (!q) return;
+    orc_free(q->two);
+    free(q->Hp); free(q->Hi); free(q->Hx); free(q->Dp); free(q->Di); free(q->Dv); free(q->Ds);
+    free(q);
+}
+
+orc *orc4_two(orc4 *q) { return q->two; }
+
+/* g = r - K4 z, plain FP64, row by row */
+static void res4(const orc4 *q, const double *rx, const double *rs, const double *ry, const double *ryd,
+                 const double *x, const double *sv, const double *y, const double *yd,
+                 double *gx, double *gs, double *gy, double *gyd) {
+    const orc *s = q->two;
+    i64 n = q->n, m = q->m, md = q->md;
+    for (i64 i = 0; i < n; i++) gx[i] = rx[i] - (s->Dx[i] + s->delta) * x[i];
+    for (i64 i = 0; i < n; i++)
+        for (i64 p = q->Hp[i]; p < q->Hp[i + 1]; p++) {
+            i64 j = q->Hi[p];
+            gx[i] -= q->Hx[p] * x[j];
+            if (j != i) gx[j] -= q->Hx[p] * x[i];
+        }
+    for (i64 k = 0; k < m; k++) {
+        double jx = 0.0;
+        for (i64 p = s->Jp[k]; p < s->Jp[k + 1]; p++) { jx += s->Jx[p] * x[s->Ji[p]]; gx[s->Ji[p]] -= s->Jx[p] * y[k]; }
+        gy[k] = ry[k] - jx;
+    }
+    for (i64 k = 0; k < md; k++) {
+        double dxk = 0.0;
+        for (i64 p = q->Dp[k]; p < q->Dp[k + 1]; p++) { dxk += q->Dv[p] * x[q->Di[p]]; gx[q->Di[p]] -= q->Dv[p] * yd[k]; }
+        gyd[k] = ryd[k] - (dxk - sv[k]);
+        gs[k] = rs[k] - (q->Ds[k] * sv[k] - yd[k]);
+    }
+}
+
+/* ||K4||_inf */
+static double norm4(const orc4 *q) {
+    const orc *s = q->two;
+    i64 n = q->n, m = q->m, md = q->md;
+    double *r = xcalloc((size_t)(n + md + m + md ? n + md + m + md : 1), sizeof(double));
+    for (i64 i = 0; i < n; i++) {
+        int has = 0;
+        for (i64 p = q->Hp[i]; p < q->Hp[i + 1]; p++) {
+            i64 j = q->Hi[p];
+            if (j == i) { r[i] += fabs(q->Hx[p] + s->Dx[i] + s->delta); has = 1; }
+            else { r[i] += fabs(q->Hx[p]); r[j] += fabs(q->Hx[p]); }
+        }
+        if (!has) r[i] += fabs(s->Dx[i] + s->delta);
+    }
+    for (i64 k = 0; k < m; k++)
+        for (i64 p = s->Jp[k]; p < s->Jp[k + 1]; p++) { r[s->Ji[p]] += fabs(s->Jx[p]); r[n + md + k] += fabs(s->Jx[p]); }
+    for (i64 k = 0; k < md; k++) {
+        for (i64 p = q->Dp[k]; p < q->Dp[k + 1]; p++) { r[q->Di[p]] += fabs(q->Dv[p]); r[n + md + m + k] += fabs(q->Dv[p]); }
+        r[n + k] += fabs(q->Ds[k]) + 1.0;
+        r[n + md + m + k] += 1.0;
+    }
+    double mx = 0.0;
+    for (i64 i = 0; i < n + md + m + md; i++) if (r[i] > mx) mx = r[i];
+    free(r);
+    return mx;
+}
+
+/* Solve K4 z = r: each step forms g = r - K4 z, reduces it to the 2x2
+ * right-hand side r_x = g_x + J_d^T (D_s g_yd + g_s), r_y = g_y, solves the
+ * 2x2 system by the hybrid method (with its own refinement to kkt_tol on the
+ * 2x2 residual), recovers e_s = J_d e_x - g_yd, e_yd = D_s e_s - g_s and adds
+ * e to z, while RR4 = ||g|| / ||r|| > kkt_tol and RR4 halves (at most
+ * max_refine + 1 steps). The 2x2 system must be factored. out: [0] RR4,
+ * [1] BE4 (||K4||_inf for ||K4||_2, Sec. 5.1), [2] steps, [3] total CG
+ * iterations, [4] status (0 ok, 2 breakdown, 3 not converged). */
+void orc4_solve(orc4 *q, const orc_opts *o, const double *rx, const double *rs, const double *ry, const double *ryd,
+                double *x, double *sv, double *y, double *yd, double *out) {
+    i64 n = q->n, m = q->m, md = q->md;
+    double *gx = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *gs = xmalloc(sizeof(double) * (size_t)(md ? md : 1));
+    double *gy = xmalloc(sizeof(double) * (size_t)(m ? m : 1)), *gyd = xmalloc(sizeof(double) * (size_t)(md ? md : 1));
+    double *ex = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *ey = xmalloc(sizeof(double) * (size_t)(m ? m : 1));
+    double *r2x = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *t = xmalloc(sizeof(double) * (size_t)(md ? md : 1));
+    for (i64 i = 0; i < n; i++) x[i] = 0.0;
+    for (i64 i = 0; i < m; i++) y[i] = 0.0;
+    for (i64 i = 0; i < md; i++) { sv[i] = 0.0; yd[i] = 0.0; }
+    double rn = sqrt(dot(rx, rx, n) + dot(rs, rs, md) + dot(ry, ry, m) + dot(ryd, ryd, md));
+    i64 max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    double rr = rn > 0 ? 1.0 : 0.0, best = INFINITY;
+    i64 steps = 0, cg = 0;
+    int status = 3;
+    orc_report rep;
+    for (;;) {
+        res4(q, rx, rs, ry, ryd, x, sv, y, yd, gx, gs, gy, gyd);
+        rr = rn > 0 ? sqrt(dot(gx, gx, n) + dot(gs, gs, md) + dot(gy, gy, m) + dot(gyd, gyd, md)) / rn : 0.0;
+        if (rr <= o->kkt_tol) { status = 0; break; }
+        if (steps > max_ref || (steps >= 2 && !(rr < 0.5 * best))) break;
+        if (rr < best) best = rr;
+        for (i64 k = 0; k < md; k++) t[k] = q->Ds[k] * gyd[k] + gs[k];
+        for (i64 i = 0; i < n; i++) r2x[i] = gx[i];
+        for (i64 k = 0; k < md; k++)
+            for (i64 p = q->Dp[k]; p < q->Dp[k + 1]; p++) r2x[q->Di[p]] += q->Dv[p] * t[k];
+        orc_solve(q->two, o, r2x, gy, ex, ey, &rep);
+        for (i64 c = 0; c < rep.passes; c++) cg += rep.cg_iters[c];
+        steps++;
+        if (rep.status == 2) { status = 2; }
+        for (i64 i = 0; i < n; i++) x[i] += ex[i];
+        for (i64 i = 0; i < m; i++) y[i] += ey[i];
+        for (i64 k = 0; k < md; k++) {
+            double jx = 0.0;
+            for (i64 p = q->Dp[k]; p < q->Dp[k + 1]; p++) jx += q->Dv[p] * ex[q->Di[p]];
+            double es = jx - gyd[k];
+            sv[k] += es;
+            yd[k] += q->Ds[k] * es - gs[k];
+        }
+        if (status == 2) {
+            res4(q, rx, rs, ry, ryd, x, sv, y, yd, gx, gs, gy, gyd);
+            rr = rn > 0 ? sqrt(dot(gx, gx, n) + dot(gs, gs, md) + dot(gy, gy, m) + dot(gyd, gyd, md)) / rn : 0.0;
+            break;
+        }
+    }
+    double zn = sqrt(dot(x, x, n) + dot(sv, sv, md) + dot(y, y, m) + dot(yd, yd, md));
+    double gn = rr * (rn > 0 ? rn : 1.0);
+    out[0] = rr;
+    out[1] = gn / (norm4(q) * zn + rn);
+    out[2] = (double)steps;
+    out[3] = (double)cg;
+    out[4] = (double)status;
+    free(gx); free(gs); free(gy); free(gyd); free(ex); free(ey); free(r2x); free(t);
+}
+
+/* RR4, BE4 of a given z (plain FP64 residual) */
+void orc4_metrics(const orc4 *q, const double *rx, const double *rs, const double *ry, const double *ryd,
+                  const double *x, const double *sv, const double *y, const double *yd, double *out2) {
+    i64 n = q->n, m = q->m, md = q->md;
+    double *gx = xmalloc(sizeof(double) * (size_t)(n ? n : 1)), *gs = xmalloc(sizeof(double) * (size_t)(md ? md : 1));
+    double *gy = xmalloc(sizeof(double) * (size_t)(m ? m : 1)), *gyd = xmalloc(sizeof(double) * (size_t)(md ? md : 1));
+    res4(q, rx, rs, ry, ryd, x, sv, y, yd, gx, gs, gy, gyd);
+    double rn = sqrt(dot(rx, rx, n) + dot(rs, rs, md) + dot(ry, ry, m) + dot(ryd, ryd, md));
+    double gn = sqrt(dot(gx, gx, n) + dot(gs, gs, md) + dot(gy, gy, m) + dot(gyd, gyd, md));
+    double zn = sqrt(dot(x, x, n) + dot(sv, sv, md) + dot(y, y, m) + dot(yd, yd, md));
+    out2[0] = rn > 0 ? gn / rn : gn;
+    out2[1] = gn / (norm4(q) * zn + rn);
+    free(gx); free(gs); free(gy); free(gyd);
+}

@@ -354,3 +354,32 @@ def uneven_dense_like(nb: int = 64, lo: int = 2000, hi: int = 50_000, seed: int 
     sizes = np.round(10.0 ** _rng(seed).uniform(np.log10(lo), np.log10(hi), nb)).astype(int)
     sizes -= sizes % 2
     return [dense_like(int(n), seed=seed + 1 + b, gamma=gamma) for b, n in enumerate(sizes)]
+
+
+@dataclasses.dataclass
+class Inequalities:
+    """Inequality block of the 4x4 system (Sec. 3): J_d (m_d x n_x, shared
+    pattern), per instance J_d values, D_s = S^-1 Z_s (positive diagonal) and
+    the right-hand side parts r_s, r_yd."""
+    m_d: int
+    Jd_rowptr: np.ndarray   # int64 [m_d+1]
+    Jd_col: np.ndarray      # int32, sorted per row
+    Jd_val: np.ndarray      # [nb, nnz]
+    D_s: np.ndarray         # [nb, m_d]
+    r_s: np.ndarray         # [nb, m_d]
+    r_yd: np.ndarray        # [nb, m_d]
+
+
+def inequalities(pattern, nb=1, seed=0, frac=0.25, per_row=3, ds_exp=6.0) -> Inequalities:
+    """m_d = frac * n_x inequality rows, each with per_row N(0,1) entries at
+    distinct random columns; D_s = 10^U(-ds_exp, ds_exp); r_s, r_yd ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    n = pattern.n_x
+    md = max(1, int(frac * n))
+    k = min(per_row, n)
+    cols = np.sort(np.stack([rng.choice(n, size=k, replace=False) for _ in range(md)]), axis=1)
+    rowptr = np.arange(md + 1, dtype=np.int64) * k
+    colv = cols.reshape(-1).astype(np.int32)
+    return Inequalities(md, rowptr, colv, rng.standard_normal((nb, md * k)),
+                        10.0 ** rng.uniform(-ds_exp, ds_exp, (nb, md)), rng.standard_normal((nb, md)),
+                        rng.standard_normal((nb, md)))

@@ -143,3 +143,31 @@ def cg_count_tol(oracle_per_pass, gpu_passes):
     oracle's, and 2 overall."""
     tol = sum(max(2, int(np.ceil(0.03 * k))) for k in oracle_per_pass)
     return tol + 2 + 2 * max(0, gpu_passes - len(oracle_per_pass))
+
+
+def dense_Jd(ineq, n, b=0):
+    Jd = np.zeros((ineq.m_d, n))
+    rows = np.repeat(np.arange(ineq.m_d), np.diff(ineq.Jd_rowptr))
+    Jd[rows, ineq.Jd_col] = ineq.Jd_val[b]
+    return Jd
+
+
+def dense_K4(batch, ineq, b=0):
+    """K4 = [H + D_x + delta I, 0, J^T, J_d^T; 0, D_s, 0, -I; J, 0, 0, 0;
+    J_d, -I, 0, 0] (Sec. 3, eq. linsys4x4 with delta in the (1,1) block)."""
+    n, m, md = batch.pattern.n_x, batch.pattern.m, ineq.m_d
+    Hd = dense_H(batch, b) + np.diag(batch.D_x[b] + batch.delta[b])
+    J = dense_J(batch, b)
+    Jd = dense_Jd(ineq, n, b)
+    N = n + md + m + md
+    K = np.zeros((N, N))
+    o1, o2, o3 = n, n + md, n + md + m
+    K[:n, :n] = Hd
+    K[:n, o2:o3] = J.T
+    K[:n, o3:] = Jd.T
+    K[o1:o2, o1:o2] = np.diag(ineq.D_s[b])
+    K[o1:o2, o3:] = -np.eye(md)
+    K[o2:o3, :n] = J
+    K[o3:, :n] = Jd
+    K[o3:, o1:o2] = -np.eye(md)
+    return K

@@ -868,3 +868,57 @@ def test_inexact_refinement_reaches_the_solution_with_fewer_iterations(scaled):
     assert inex["cg_iters"][0] == full["cg_iters"][0]          # the first pass is the paper's
     if full["passes"] > 1:
         assert sum(inex["cg_iters"][1:]) < sum(full["cg_iters"][1:]), (inex["cg_iters"], full["cg_iters"])
+
+
+# --------------------------------------------------------------------------
+# the 4x4 system (Sec. 3, eqs. linsys4x4 / linsys2x2) through the reduction
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,ds_exp", [(93, 2.0), (94, 6.0)])
+def test_4x4_solve_equals_dense_solution(seed, ds_exp):
+    b = H.tiny_dense_like(40, seed, dx_exp=2.0)
+    q = synth.inequalities(b.pattern, 1, seed=seed + 1, frac=0.3, ds_exp=ds_exp)
+    o4 = oracle.System4.from_batch(b, q)
+    assert o4.factor(o4.two.order_mindeg())[0] == 0
+    r = [b.r1[0], q.r_s[0], b.r2[0], q.r_yd[0]]
+    x, sv, y, yd, info = o4.solve(*r)
+    K4 = H.dense_K4(b, q)
+    z = np.linalg.solve(K4, np.concatenate(r))
+    got = np.concatenate([x, sv, y, yd])
+    assert info["status"] == 0 and info["rr"] <= 1e-10
+    assert np.linalg.norm(got - z) / np.linalg.norm(z) < 1e-8
+    # RR and BE as defined in Sec. 5.1, on K4, at a point away from the
+    # solution (so that the residual is not just rounding)
+    zp = got + 1e-3 * np.random.default_rng(seed).standard_normal(got.size) * np.abs(got).max()
+    n, md, m = b.pattern.n_x, q.m_d, b.pattern.m
+    parts = np.split(zp, [n, n + md, n + md + m])
+    res = np.linalg.norm(K4 @ zp - np.concatenate(r))
+    rr, be = o4.metrics(*r, *parts)
+    assert rr == pytest.approx(res / np.linalg.norm(np.concatenate(r)), rel=1e-10)
+    kinf = np.abs(K4).sum(axis=1).max()
+    assert be == pytest.approx(res / (kinf * np.linalg.norm(zp) + np.linalg.norm(np.concatenate(r))), rel=1e-10)
+
+
+def test_4x4_reduced_matrix_and_no_inequalities():
+    """The 2x2 system the reduction builds has Htilde = H + D_x + delta I +
+    J_d^T D_s J_d (dense check of its H_gamma); with every D_s = 0 the
+    reduction is still exact (dense solve)."""
+    b = H.tiny_dense_like(30, 95, dx_exp=1.0)
+    q = synth.inequalities(b.pattern, 1, seed=96, frac=0.3)
+    o4 = oracle.System4.from_batch(b, q)
+    cp, ri, v = o4.two.hgamma()
+    got = np.zeros((30, 30))
+    cols = np.repeat(np.arange(30), np.diff(cp))
+    got[ri, cols] = v
+    Jd = H.dense_Jd(q, 30)
+    want = np.tril(H.dense_H(b) + np.diag(b.D_x[0] + b.delta[0]) + Jd.T @ np.diag(q.D_s[0]) @ Jd +
+                   b.gamma[0] * H.dense_J(b).T @ H.dense_J(b))
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    import dataclasses
+    q0 = dataclasses.replace(q, D_s=np.zeros_like(q.D_s))
+    o0 = oracle.System4.from_batch(b, q0)
+    o0.factor(None)
+    r = [b.r1[0], q0.r_s[0], b.r2[0], q0.r_yd[0]]
+    x, sv, y, yd, info = o0.solve(*r)
+    z = np.linalg.solve(H.dense_K4(b, q0), np.concatenate(r))
+    assert np.linalg.norm(np.concatenate([x, sv, y, yd]) - z) / np.linalg.norm(z) < 1e-8
