@@ -269,6 +269,48 @@ int hkkt_factor_regularized(hkkt_ctx *ctx, int nb, const double *H_val, const do
 int hkkt_gamma_heuristic(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
                          const double *J_val, const double *delta, double *gamma_out);
 
+/* ---- the full 4x4 system of Sec. 3 (eq. linsys4x4) ------------------------
+ *   K4 = [ H + D_x + delta I   0     J^T   J_d^T ]   z = (dx, ds, dy, dyd)
+ *        [ 0                   D_s   0     -I    ]   r = (rx~, rs, ry, ryd)
+ *        [ J                   0     0     0     ]
+ *        [ J_d                 -I    0     0     ]
+ * solved through the reduction of Sec. 3: ds = J_d dx - ryd, dyd = D_s ds - rs
+ * leave the 2x2 system (eq. linsys2x2) with Htilde = H + D_x +
+ * J_d^T D_s J_d and r_x = rx~ + J_d^T (D_s ryd + rs), which the hybrid
+ * method solves (all the 2x2 options apply: precision, scaling, ...).
+ *
+ * hkkt_analyze4: patterns as for hkkt_analyze plus J_d (m_d x n_x CSR, host,
+ * copied); the context is analysed for the 2x2 system on the pattern
+ * tril(H) U tril(J_d^T J_d) (single system, no group). Errors as for
+ * hkkt_analyze. A later hkkt_analyze / hkkt_analyze_group drops the 4x4
+ * layer. */
+int hkkt_analyze4(hkkt_ctx *ctx, int64_t n_x, int64_t m, int64_t m_d,
+                  const int64_t *H_rowptr, const int32_t *H_col,
+                  const int64_t *J_rowptr, const int32_t *J_col,
+                  const int64_t *Jd_rowptr, const int32_t *Jd_col, const int32_t *perm);
+
+/* Factor nb instances: H_val, D_x, J_val as for hkkt_factor_batch, Jd_val
+ * [nb][nnz(J_d)], D_s [nb][m_d] (pointer mode), delta, gamma [nb] host.
+ * Htilde's H part H + J_d^T D_s J_d is formed on the device on the combined
+ * pattern (fixed summation order), then factored as hkkt_factor_batch does.
+ * Returns as hkkt_factor_batch; -3 without hkkt_analyze4. */
+int hkkt_factor4_batch(hkkt_ctx *ctx, int nb, const double *H_val, const double *D_x,
+                       const double *J_val, const double *Jd_val, const double *D_s,
+                       const double *delta, const double *gamma, int *status, int64_t *fail_col);
+
+/* Solve K4 z = r for the factored instances: rx [nb][n_x], rs [nb][m_d],
+ * ry [nb][m], ryd [nb][m_d] in, dx, ds, dy, dyd out (pointer mode). Each
+ * step forms the 4x4 residual g = r - K4 z (plain FP64), reduces it to the
+ * 2x2 right-hand side, solves the 2x2 system (with its own refinement),
+ * recovers e_s = J_d e_x - g_yd, e_yd = D_s e_s - g_s and adds e to z, while
+ * RR4 = ||g||/||r|| > kkt_tol and halves (at most max_refine + 1 steps). info
+ * per instance: status, cg_iters (total), passes (4x4 steps), fp64_fallback,
+ * rr and be on K4 (Sec. 5.1, ||K4||_inf), floor NaN (not computed for K4).
+ * Returns the largest status or a negative code (-3 without factor4). */
+int hkkt_solve4_batch(hkkt_ctx *ctx, int nb, const double *rx, const double *rs, const double *ry,
+                      const double *ryd, double *dx, double *ds, double *dy, double *dyd,
+                      hkkt_info *info);
+
 /* Single-instance form of hkkt_factor_batch. */
 int hkkt_factor(hkkt_ctx *ctx, const double *H_val, const double *D_x, const double *J_val,
                 double delta, double gamma, int64_t *fail_col);

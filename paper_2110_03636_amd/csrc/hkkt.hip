@@ -584,6 +584,23 @@ struct Batch {
     size_t esz() const { return prec == HKKT_MIXED ? 4 : 8; }
 };
 
+// the 4x4 system of Sec. 3 around the 2x2 solver: the assembly map of
+// Htilde's H part (H + J_d^T D_s J_d on the combined pattern), the operators
+// of the 4x4 residual in the caller's order, staged values and vectors
+struct K4Data {
+    i64 n = 0, m = 0, md = 0, nnzH = 0, nnzJ = 0, nnzJd = 0, nnzHt = 0;
+    DBuf h_src, pptr, prow, pa, pb;     // Htilde assembly: per combined entry its H entry and J_d pairs
+    DBuf d_ptr, d_col;                  // J_d CSR
+    DBuf dt_ptr, dt_col, dt_src;        // J_d^T (rows = variables), values through src
+    DBuf hf_ptr, hf_col, hf_src;        // full symmetric H (rows = variables), values of tril(H)
+    DBuf jt_ptr, jt_col, jt_src;        // J^T
+    DBuf j_ptr, j_col;                  // J CSR
+    DBuf H, Dx, J, Jd, Ds, delta, gamma, Ht;   // staged values [nb][...] (delta, gamma [nb])
+    DBuf rx, rs, ry, ryd, x, s, y, yd, gx, gs, gy, gyd, t, tx, jx, dx, r2x, ex, ey, jde, act, sq, kn;
+    int nb = 0;
+    bool factored = false;
+};
+
 }  // namespace hkkt
 
 using namespace hkkt;
@@ -621,6 +638,7 @@ struct hkkt_ctx {
     } pat;
     int tree_width = -1;          // autotuned tree-kernel width (-1: library default)
     int tree_stage = -1;          // autotuned staged-kernel choice (-1: library default)
+    std::unique_ptr<hkkt::K4Data> k4;   // the 4x4 layer (hkkt_analyze4), null otherwise
 };
 
 namespace hkkt {
@@ -1772,11 +1790,13 @@ int hkkt_symbolic_supernodes(const hkkt_symbolic* sym, int32_t* sn_first, int64_
 
 int hkkt_analyze(hkkt_ctx* c, int64_t n, int64_t m, const int64_t* Hp, const int32_t* Hi, const int64_t* Jp,
                  const int32_t* Ji, const int32_t* perm) {
+    if (c) c->k4.reset();
     return analyze_ctx(c, 1, nullptr, nullptr, n, m, Hp, Hi, Jp, Ji, perm);
 }
 
 int hkkt_analyze_group(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* y_off, int64_t n, int64_t m,
                        const int64_t* Hp, const int32_t* Hi, const int64_t* Jp, const int32_t* Ji) {
+    if (c) c->k4.reset();
     return analyze_ctx(c, G, x_off, y_off, n, m, Hp, Hi, Jp, Ji, nullptr);
 }
 
@@ -2603,6 +2623,339 @@ int hkkt_hsolve_noalloc(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         LAUNCH(10, k_perm_scatter, dim3(gn, nb), dim3(kBlock), 0, st, c->dev.v.perm, (const double*)V.rhat.as<double>(),
                x, (i64)S.n);
         return HKKT_OK;
+    })
+}
+
+// ---------------------------------------------------------------------------
+// the 4x4 system of Sec. 3
+// ---------------------------------------------------------------------------
+int hkkt_analyze4(hkkt_ctx* c, int64_t n, int64_t m, int64_t md, const int64_t* Hp, const int32_t* Hi,
+                  const int64_t* Jp, const int32_t* Ji, const int64_t* Dp, const int32_t* Di, const int32_t* perm) {
+    if (!c) return HKKT_ERR_ARG;
+    if (n < 1 || m < 0 || md < 0 || !Hp || !Hi || !Jp || (md > 0 && (!Dp || !Di))) {
+        c->err = "bad 4x4 analysis arguments";
+        return HKKT_ERR_ARG;
+    }
+    {
+        std::vector<i64> dp0(1, 0);
+        const std::string e = validate_pattern(n, md, Hp, Hi, md > 0 ? Dp : dp0.data(), Di);
+        if (!e.empty()) { c->err = "J_d: " + e; return HKKT_ERR_PATTERN; }
+        const std::string e2 = validate_pattern(n, m, Hp, Hi, Jp, Ji);
+        if (!e2.empty()) { c->err = e2; return HKKT_ERR_PATTERN; }
+    }
+    ABI_GUARD(c, {
+        auto K = std::make_unique<K4Data>();
+        K->n = n; K->m = m; K->md = md;
+        K->nnzH = Hp[n]; K->nnzJ = Jp[m]; K->nnzJd = md > 0 ? Dp[md] : 0;
+        // combined lower pattern: tril(H) U tril(J_d^T J_d), rows sorted
+        std::vector<std::vector<i32>> rows(n);
+        for (i64 i = 0; i < n; i++) rows[i].assign(Hi + Hp[i], Hi + Hp[i + 1]);
+        for (i64 k = 0; k < md; k++)
+            for (i64 a = Dp[k]; a < Dp[k + 1]; a++)
+                for (i64 b = Dp[k]; b <= a; b++) rows[Di[a]].push_back(Di[b]);   // columns sorted within J_d rows
+        std::vector<i64> cp(n + 1, 0);
+        std::vector<i32> ci;
+        for (i64 i = 0; i < n; i++) {
+            auto& r = rows[i];
+            std::sort(r.begin(), r.end());
+            r.erase(std::unique(r.begin(), r.end()), r.end());
+            ci.insert(ci.end(), r.begin(), r.end());
+            cp[i + 1] = (i64)ci.size();
+        }
+        K->nnzHt = cp[n];
+        auto find = [&](i64 i, i32 j) -> i64 {
+            auto b = ci.begin() + cp[i], e = ci.begin() + cp[i + 1];
+            auto it = std::lower_bound(b, e, j);
+            return (it != e && *it == j) ? (i64)(it - ci.begin()) : -1;
+        };
+        std::vector<i64> hsrc(K->nnzHt, -1);
+        for (i64 i = 0; i < n; i++)
+            for (i64 p = Hp[i]; p < Hp[i + 1]; p++) hsrc[find(i, Hi[p])] = p;
+        // J_d pairs per combined entry, in the order (row k, a, b)
+        std::vector<i64> pcount(K->nnzHt + 1, 0);
+        for (i64 k = 0; k < md; k++)
+            for (i64 a = Dp[k]; a < Dp[k + 1]; a++)
+                for (i64 b = Dp[k]; b <= a; b++) pcount[find(Di[a], Di[b]) + 1]++;
+        for (i64 e = 0; e < K->nnzHt; e++) pcount[e + 1] += pcount[e];
+        std::vector<i64> fillp(pcount.begin(), pcount.end() - 1), pa(pcount[K->nnzHt]), pb(pcount[K->nnzHt]);
+        std::vector<i32> prow(pcount[K->nnzHt]);
+        for (i64 k = 0; k < md; k++)
+            for (i64 a = Dp[k]; a < Dp[k + 1]; a++)
+                for (i64 b = Dp[k]; b <= a; b++) {
+                    const i64 q = fillp[find(Di[a], Di[b])]++;
+                    prow[q] = (i32)k; pa[q] = a; pb[q] = b;
+                }
+        // transposes and the full symmetric H (rows = variables), values by src
+        auto transpose = [&](i64 rowsN, const int64_t* P, const int32_t* I, std::vector<i64>& tp, std::vector<i32>& tc,
+                             std::vector<i64>& ts) {
+            tp.assign(n + 1, 0);
+            for (i64 r = 0; r < rowsN; r++)
+                for (i64 q = P[r]; q < P[r + 1]; q++) tp[I[q] + 1]++;
+            for (i64 i = 0; i < n; i++) tp[i + 1] += tp[i];
+            std::vector<i64> f(tp.begin(), tp.end() - 1);
+            tc.assign(tp[n], 0);
+            ts.assign(tp[n], 0);
+            for (i64 r = 0; r < rowsN; r++)
+                for (i64 q = P[r]; q < P[r + 1]; q++) { const i64 z = f[I[q]]++; tc[z] = (i32)r; ts[z] = q; }
+        };
+        std::vector<i64> jtp, jts, dtp, dts, hfp(n + 1, 0), hfs;
+        std::vector<i32> jtc, dtc, hfc;
+        transpose(m, Jp, Ji, jtp, jtc, jts);
+        std::vector<i64> dp1(1, 0);
+        transpose(md, md > 0 ? Dp : dp1.data(), Di, dtp, dtc, dts);
+        {
+            std::vector<std::vector<std::pair<i32, i64>>> hr(n);
+            for (i64 i = 0; i < n; i++)
+                for (i64 p = Hp[i]; p < Hp[i + 1]; p++) {
+                    hr[i].push_back({Hi[p], p});
+                    if (Hi[p] != i) hr[Hi[p]].push_back({(i32)i, p});
+                }
+            for (i64 i = 0; i < n; i++) {
+                std::sort(hr[i].begin(), hr[i].end());
+                for (auto& q : hr[i]) { hfc.push_back(q.first); hfs.push_back(q.second); }
+                hfp[i + 1] = (i64)hfc.size();
+            }
+        }
+        hipStream_t st = c->stream;
+        upload(K->h_src, hsrc, st); upload(K->pptr, pcount, st); upload(K->prow, prow, st);
+        upload(K->pa, pa, st); upload(K->pb, pb, st);
+        std::vector<i64> dpv(md > 0 ? Dp : dp1.data(), (md > 0 ? Dp : dp1.data()) + md + 1);
+        std::vector<i32> dcv(Di ? Di : nullptr, Di ? Di + K->nnzJd : nullptr);
+        upload(K->d_ptr, dpv, st); upload(K->d_col, dcv, st);
+        upload(K->dt_ptr, dtp, st); upload(K->dt_col, dtc, st); upload(K->dt_src, dts, st);
+        upload(K->hf_ptr, hfp, st); upload(K->hf_col, hfc, st); upload(K->hf_src, hfs, st);
+        upload(K->jt_ptr, jtp, st); upload(K->jt_col, jtc, st); upload(K->jt_src, jts, st);
+        std::vector<i64> jpv(Jp, Jp + m + 1);
+        std::vector<i32> jcv(Ji, Ji + K->nnzJ);
+        upload(K->j_ptr, jpv, st); upload(K->j_col, jcv, st);
+        HIPCHK(hipStreamSynchronize(st));
+        const int rc = analyze_ctx(c, 1, nullptr, nullptr, n, m, cp.data(), ci.data(), Jp, Ji, perm);
+        if (rc != HKKT_OK) return rc;
+        c->k4 = std::move(K);
+        return HKKT_OK;
+    })
+}
+
+// stage a [nb][len] argument (host or device per pointer mode) into d
+static void stage(hkkt_ctx* c, DBuf& d, const double* src, size_t count) {
+    d.ensure(std::max<size_t>(1, count) * 8);
+    if (count == 0) return;
+    const hipMemcpyKind k = c->opt.pointer_mode == HKKT_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(d.p, src, count * 8, k, c->stream));
+}
+
+// the 2x2 entry points on device buffers, whatever the caller's pointer mode
+struct DevicePointers {
+    hkkt_ctx* c;
+    int saved;
+    explicit DevicePointers(hkkt_ctx* c_) : c(c_), saved(c_->opt.pointer_mode) { c->opt.pointer_mode = HKKT_PTR_DEVICE; }
+    ~DevicePointers() { c->opt.pointer_mode = saved; }
+};
+
+int hkkt_factor4_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, const double* J, const double* Jd,
+                       const double* Ds, const double* delta, const double* gamma, int* status, int64_t* fail_col) {
+    if (!c) return HKKT_ERR_ARG;
+    if (!c->k4) { c->err = "factor4 before analyze4"; return HKKT_ERR_STATE; }
+    K4Data& K = *c->k4;
+    if (nb < 1 || !Dx || !delta || !gamma || (K.nnzH > 0 && !H) || (K.nnzJ > 0 && !J) ||
+        (K.md > 0 && (!Ds || (K.nnzJd > 0 && !Jd)))) {
+        c->err = "bad 4x4 factor arguments";
+        return HKKT_ERR_ARG;
+    }
+    int rc = HKKT_OK;
+    ABI_GUARD(c, {
+        hipStream_t st = c->stream;
+        K.factored = false;
+        stage(c, K.H, H, (size_t)nb * K.nnzH);
+        stage(c, K.Dx, Dx, (size_t)nb * K.n);
+        stage(c, K.J, J, (size_t)nb * K.nnzJ);
+        stage(c, K.Jd, Jd, (size_t)nb * K.nnzJd);
+        stage(c, K.Ds, Ds, (size_t)nb * K.md);
+        K.delta.ensure((size_t)nb * 8);
+        K.gamma.ensure((size_t)nb * 8);
+        HIPCHK(hipMemcpyAsync(K.delta.p, delta, (size_t)nb * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(K.gamma.p, gamma, (size_t)nb * 8, hipMemcpyHostToDevice, st));
+        K.Ht.ensure((size_t)nb * std::max<i64>(1, K.nnzHt) * 8);
+        LAUNCH(10, k_htilde, dim3(grid1(K.nnzHt, 4096), nb), dim3(kBlock), 0, st, K.nnzHt,
+               (const i64*)K.h_src.as<i64>(), (const i64*)K.pptr.as<i64>(), (const i32*)K.prow.as<i32>(),
+               (const i64*)K.pa.as<i64>(), (const i64*)K.pb.as<i64>(), (const double*)K.H.as<double>(), K.nnzH,
+               (const double*)K.Jd.as<double>(), K.nnzJd, (const double*)K.Ds.as<double>(), K.md,
+               K.Ht.as<double>());
+        HIPCHK(hipStreamSynchronize(st));   // delta/gamma host copies, then the 2x2 factor
+        K.nb = nb;
+        {
+            DevicePointers dp(c);
+            rc = hkkt_factor_batch(c, nb, K.Ht.as<double>(), K.Dx.as<double>(), K.J.as<double>(), delta, gamma,
+                                   status, fail_col);
+        }
+        if (rc >= 0) K.factored = true;
+        return rc;
+    })
+}
+
+int hkkt_solve4_batch(hkkt_ctx* c, int nb, const double* rx, const double* rs, const double* ry, const double* ryd,
+                      double* x, double* sv, double* y, double* yd, hkkt_info* info) {
+    if (!c) return HKKT_ERR_ARG;
+    if (!c->k4 || !c->k4->factored || !c->factored) { c->err = "solve4 before factor4"; return HKKT_ERR_STATE; }
+    K4Data& K = *c->k4;
+    if (nb != K.nb || !rx || !x || (K.m > 0 && (!ry || !y)) || (K.md > 0 && (!rs || !ryd || !sv || !yd))) {
+        c->err = "bad 4x4 solve arguments";
+        return HKKT_ERR_ARG;
+    }
+    ABI_GUARD(c, {
+        const double t0 = now_ms();
+        hipStream_t st = c->stream;
+        const i64 n = K.n, m = K.m, md = K.md;
+        const size_t vn = (size_t)nb * n, vm = (size_t)nb * m, vd = (size_t)nb * md;
+        stage(c, K.rx, rx, vn); stage(c, K.ry, ry, vm); stage(c, K.rs, rs, vd); stage(c, K.ryd, ryd, vd);
+        for (DBuf* d : {&K.x, &K.gx, &K.tx, &K.r2x, &K.ex}) d->ensure(std::max<size_t>(1, vn) * 8);
+        for (DBuf* d : {&K.y, &K.gy, &K.jx, &K.ey}) d->ensure(std::max<size_t>(1, vm) * 8);
+        for (DBuf* d : {&K.s, &K.yd, &K.gs, &K.gyd, &K.t, &K.dx, &K.jde}) d->ensure(std::max<size_t>(1, vd) * 8);
+        K.act.ensure((size_t)nb * 4);
+        K.sq.ensure((size_t)nb * 8);
+        K.kn.ensure((size_t)nb * 8);
+        for (auto q : {std::make_pair(&K.x, vn), std::make_pair(&K.y, vm), std::make_pair(&K.s, vd),
+                       std::make_pair(&K.yd, vd)})
+            if (q.second)
+                LAUNCH(10, k_fill<double>, dim3(grid1((i64)q.second)), dim3(kBlock), 0, st, q.first->as<double>(),
+                       (i64)q.second, 0.0);
+        const unsigned gn = grid1(n, 4096);
+        auto spmv = [&](i64 nrow, const DBuf& ptr, const DBuf& col, const i64* src, const DBuf& vals, i64 nnz,
+                        const DBuf& xin, i64 ncol, DBuf& out, double alpha, int acc) {
+            if (nrow == 0) return;
+            LAUNCH(10, k_spmv_src, dim3(grid1(nrow, 4096), nb), dim3(kBlock), 0, st, nrow, (const i64*)ptr.as<i64>(),
+                   (const i32*)col.as<i32>(), src, (const double*)vals.as<double>(), nnz, (const double*)xin.as<double>(),
+                   ncol, out.as<double>(), alpha, acc);
+        };
+        // g = r - K4 z; sq[b] = ||g||^2
+        auto residual = [&]() {
+            spmv(n, K.hf_ptr, K.hf_col, K.hf_src.as<i64>(), K.H, K.nnzH, K.x, n, K.tx, 1.0, 0);
+            if (m > 0) {
+                spmv(n, K.jt_ptr, K.jt_col, K.jt_src.as<i64>(), K.J, K.nnzJ, K.y, m, K.tx, 1.0, 1);
+                spmv(m, K.j_ptr, K.j_col, nullptr, K.J, K.nnzJ, K.x, n, K.jx, 1.0, 0);
+            }
+            if (md > 0) {
+                spmv(n, K.dt_ptr, K.dt_col, K.dt_src.as<i64>(), K.Jd, K.nnzJd, K.yd, md, K.tx, 1.0, 1);
+                spmv(md, K.d_ptr, K.d_col, nullptr, K.Jd, K.nnzJd, K.x, n, K.dx, 1.0, 0);
+            }
+            LAUNCH(10, k_res4, dim3(grid1(n + m + md, 4096), nb), dim3(kBlock), 0, st, n, m, md,
+                   (const double*)K.Dx.as<double>(), (const double*)K.delta.as<double>(), (const double*)K.Ds.as<double>(),
+                   (const double*)K.rx.as<double>(), (const double*)K.rs.as<double>(), (const double*)K.ry.as<double>(),
+                   (const double*)K.ryd.as<double>(), (const double*)K.x.as<double>(), (const double*)K.s.as<double>(),
+                   (const double*)K.yd.as<double>(), (const double*)K.tx.as<double>(), (const double*)K.jx.as<double>(),
+                   (const double*)K.dx.as<double>(), K.gx.as<double>(), K.gs.as<double>(), K.gy.as<double>(),
+                   K.gyd.as<double>(), K.t.as<double>());
+            LAUNCH(10, k_sumsq4, dim3(nb), dim3(kBlock), 0, st, n, md, m, (const double*)K.gx.as<double>(),
+                   (const double*)K.gs.as<double>(), (const double*)K.gy.as<double>(), (const double*)K.gyd.as<double>(),
+                   K.sq.as<double>());
+            std::vector<double> g2(nb);
+            HIPCHK(hipMemcpyAsync(g2.data(), K.sq.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return g2;
+        };
+        // ||r|| per instance
+        LAUNCH(10, k_sumsq4, dim3(nb), dim3(kBlock), 0, st, n, md, m, (const double*)K.rx.as<double>(),
+               (const double*)K.rs.as<double>(), (const double*)K.ry.as<double>(), (const double*)K.ryd.as<double>(),
+               K.sq.as<double>());
+        std::vector<double> rn(nb);
+        HIPCHK(hipMemcpyAsync(rn.data(), K.sq.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (double& v : rn) v = std::sqrt(v);
+        std::vector<double> rr(nb, 0.0), best(nb, INFINITY);
+        std::vector<int> act(nb, 1), steps(nb, 0), cg(nb, 0), brk(nb, 0), fb(nb, 0), st2(nb, HKKT_OK);
+        const int max_ref = c->opt.max_refine >= 0 ? c->opt.max_refine : 10;
+        std::vector<hkkt_info> in2((size_t)nb);
+        for (int step = 0;; step++) {
+            const std::vector<double> g2 = residual();
+            int any = 0;
+            for (int b = 0; b < nb; b++) {
+                rr[b] = rn[b] > 0 ? std::sqrt(g2[b]) / rn[b] : 0.0;
+                if (!act[b]) continue;
+                if (rr[b] <= c->opt.kkt_tol || brk[b] || st2[b] == HKKT_NOT_SPD || step > max_ref ||
+                    (step >= 2 && !(rr[b] < 0.5 * best[b])))
+                    act[b] = 0;
+                else
+                    best[b] = std::min(best[b], rr[b]);
+                any += act[b];
+            }
+            if (!any) break;
+            // reduced right-hand side: r_x = g_x + J_d^T (D_s g_yd + g_s), r_y = g_y
+            HIPCHK(hipMemcpyAsync(K.r2x.p, K.gx.p, vn * 8, hipMemcpyDeviceToDevice, st));
+            if (md > 0) spmv(n, K.dt_ptr, K.dt_col, K.dt_src.as<i64>(), K.Jd, K.nnzJd, K.t, md, K.r2x, 1.0, 1);
+            // instances already done get a zero right-hand side (no CG work)
+            for (int b = 0; b < nb; b++)
+                if (!act[b]) {
+                    LAUNCH(10, k_fill<double>, dim3(gn), dim3(kBlock), 0, st, K.r2x.as<double>() + (i64)b * n, n, 0.0);
+                    if (m > 0)
+                        LAUNCH(10, k_fill<double>, dim3(grid1(m)), dim3(kBlock), 0, st, K.gy.as<double>() + (i64)b * m,
+                               m, 0.0);
+                }
+            int rc2;
+            {
+                DevicePointers dp(c);
+                rc2 = hkkt_solve_batch(c, nb, K.r2x.as<double>(), m > 0 ? K.gy.as<double>() : nullptr,
+                                       K.ex.as<double>(), m > 0 ? K.ey.as<double>() : nullptr, in2.data());
+            }
+            if (rc2 < 0) return rc2;
+            for (int b = 0; b < nb; b++) {
+                if (!act[b]) continue;
+                steps[b]++;
+                cg[b] += in2[b].cg_iters;
+                fb[b] |= in2[b].fp64_fallback;
+                if (in2[b].status == HKKT_CG_BREAKDOWN) brk[b] = 1;
+                if (in2[b].status == HKKT_NOT_SPD) st2[b] = HKKT_NOT_SPD;
+            }
+            HIPCHK(hipMemcpyAsync(K.act.p, act.data(), (size_t)nb * 4, hipMemcpyHostToDevice, st));
+            if (md > 0) spmv(md, K.d_ptr, K.d_col, nullptr, K.Jd, K.nnzJd, K.ex, n, K.jde, 1.0, 0);
+            LAUNCH(10, k_recover4, dim3(grid1(n + m + md, 4096), nb), dim3(kBlock), 0, st, n, m, md,
+                   (const int*)K.act.as<int>(), (const double*)K.Ds.as<double>(), (const double*)K.ex.as<double>(),
+                   (const double*)K.ey.as<double>(), (const double*)K.jde.as<double>(), (const double*)K.gs.as<double>(),
+                   (const double*)K.gyd.as<double>(), K.x.as<double>(), K.y.as<double>(), K.s.as<double>(),
+                   K.yd.as<double>());
+            HIPCHK(hipStreamSynchronize(st));   // act goes out of date next step
+        }
+        // ||K4||_inf and ||z|| for BE
+        LAUNCH(10, k_norm4, dim3(nb), dim3(kBlock), 0, st, n, m, md, (const i64*)K.hf_ptr.as<i64>(),
+               (const i32*)K.hf_col.as<i32>(), (const i64*)K.hf_src.as<i64>(), (const double*)K.H.as<double>(), K.nnzH,
+               (const double*)K.Dx.as<double>(), (const double*)K.delta.as<double>(), (const i64*)K.jt_ptr.as<i64>(),
+               (const i64*)K.jt_src.as<i64>(), (const double*)K.J.as<double>(), K.nnzJ, (const i64*)K.dt_ptr.as<i64>(),
+               (const i64*)K.dt_src.as<i64>(), (const double*)K.Jd.as<double>(), K.nnzJd, (const i64*)K.j_ptr.as<i64>(),
+               (const i64*)K.d_ptr.as<i64>(), (const double*)K.Ds.as<double>(), K.kn.as<double>());
+        std::vector<double> kn(nb), zn(nb);
+        HIPCHK(hipMemcpyAsync(kn.data(), K.kn.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+        LAUNCH(10, k_sumsq4, dim3(nb), dim3(kBlock), 0, st, n, md, m, (const double*)K.x.as<double>(),
+               (const double*)K.s.as<double>(), (const double*)K.y.as<double>(), (const double*)K.yd.as<double>(),
+               K.sq.as<double>());
+        HIPCHK(hipMemcpyAsync(zn.data(), K.sq.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+        const hipMemcpyKind ok = c->opt.pointer_mode == HKKT_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIPCHK(hipMemcpyAsync(x, K.x.p, vn * 8, ok, st));
+        if (m > 0) HIPCHK(hipMemcpyAsync(y, K.y.p, vm * 8, ok, st));
+        if (md > 0) {
+            HIPCHK(hipMemcpyAsync(sv, K.s.p, vd * 8, ok, st));
+            HIPCHK(hipMemcpyAsync(yd, K.yd.p, vd * 8, ok, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        int rc = HKKT_OK;
+        for (int b = 0; b < nb; b++) {
+            int s_ = st2[b] == HKKT_NOT_SPD ? HKKT_NOT_SPD
+                     : brk[b] && c->opt.delta2 == 0.0 ? HKKT_CG_BREAKDOWN
+                     : rr[b] <= c->opt.kkt_tol ? HKKT_OK : HKKT_NOT_CONVERGED;
+            if (c->fstatus[b] != HKKT_OK) s_ = c->fstatus[b];
+            rc = std::max(rc, s_);
+            if (info) {
+                hkkt_info& I = info[b];
+                I.status = s_;
+                I.cg_iters = cg[b];
+                I.passes = steps[b];
+                I.fp64_fallback = fb[b];
+                I.rr = rr[b];
+                I.be = rr[b] * rn[b] / (kn[b] * std::sqrt(zn[b]) + rn[b]);
+                I.floor = NAN;
+                I.fail_col = c->ffail[b];
+            }
+        }
+        c->ms[2] = now_ms() - t0;
+        return rc;
     })
 }
 

@@ -188,6 +188,165 @@ __global__ void k_scale_pair(const double* __restrict__ sc, i64 n, i64 m, double
 }
 
 // ---------------------------------------------------------------------------
+// the 4x4 system of Sec. 3 (eq. linsys4x4) around the 2x2 solver, in the
+// caller's variable order, plain FP64
+// ---------------------------------------------------------------------------
+// out[b][i] = (acc ? out[b][i] : 0) + alpha * sum_k vals[b][src[k]] x[b][col[k]]
+// over row i of a CSR pattern whose values are gathered through src (null:
+// the k-th value)
+__global__ void k_spmv_src(i64 nrow, const i64* __restrict__ rowptr, const i32* __restrict__ col,
+                           const i64* __restrict__ src, const double* __restrict__ vals, i64 nnz,
+                           const double* __restrict__ x, i64 ncol, double* __restrict__ out, double alpha, int acc) {
+    const int b = blockIdx.y;
+    const double* v = vals + (i64)b * nnz;
+    const double* xb = x + (i64)b * ncol;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += (i64)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (i64 k = rowptr[i]; k < rowptr[i + 1]; k++) a += v[src ? src[k] : k] * xb[col[k]];
+        out[(i64)b * nrow + i] = (acc ? out[(i64)b * nrow + i] : 0.0) + alpha * a;
+    }
+}
+
+// Htilde's H part, H + J_d^T D_s J_d, on the combined pattern: entry e takes
+// H[h_src[e]] (if any) plus D_s[k] J_d[a] J_d[b] for its pairs, in a fixed
+// order
+__global__ void k_htilde(i64 nnz, const i64* __restrict__ h_src, const i64* __restrict__ pptr,
+                         const i32* __restrict__ prow, const i64* __restrict__ pa, const i64* __restrict__ pb,
+                         const double* __restrict__ H, i64 nnzH, const double* __restrict__ Jd, i64 nnzJd,
+                         const double* __restrict__ Ds, i64 md, double* __restrict__ Ht) {
+    const int b = blockIdx.y;
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (i64)gridDim.x * blockDim.x) {
+        double v = h_src[e] >= 0 ? H[(i64)b * nnzH + h_src[e]] : 0.0;
+        for (i64 p = pptr[e]; p < pptr[e + 1]; p++)
+            v += Ds[(i64)b * md + prow[p]] * Jd[(i64)b * nnzJd + pa[p]] * Jd[(i64)b * nnzJd + pb[p]];
+        Ht[(i64)b * nnz + e] = v;
+    }
+}
+
+// the 4x4 residual from the products: tx = H x + J^T y + J_d^T y_d, jx = J x,
+// dx = J_d x (all already formed):
+//   g_x = r_x - tx - (D_x + delta) x,  g_y = r_y - jx,
+//   g_yd = r_yd - (dx - s),             g_s = r_s - (D_s s - y_d)
+// and the reduced right-hand side parts t = D_s g_yd + g_s
+__global__ void k_res4(i64 n, i64 m, i64 md, const double* __restrict__ Dx, const double* __restrict__ delta,
+                       const double* __restrict__ Ds, const double* __restrict__ rx, const double* __restrict__ rs,
+                       const double* __restrict__ ry, const double* __restrict__ ryd, const double* __restrict__ x,
+                       const double* __restrict__ s, const double* __restrict__ yd, const double* __restrict__ tx,
+                       const double* __restrict__ jx, const double* __restrict__ dx, double* __restrict__ gx,
+                       double* __restrict__ gs, double* __restrict__ gy, double* __restrict__ gyd,
+                       double* __restrict__ t) {
+    const int b = blockIdx.y;
+    const i64 tot = n + m + md;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (i64)gridDim.x * blockDim.x) {
+        if (i < n) {
+            const i64 q = (i64)b * n + i;
+            gx[q] = rx[q] - tx[q] - (Dx[q] + delta[b]) * x[q];
+        } else if (i < n + m) {
+            const i64 q = (i64)b * m + (i - n);
+            gy[q] = ry[q] - jx[q];
+        } else {
+            const i64 q = (i64)b * md + (i - n - m);
+            const double a = ryd[q] - (dx[q] - s[q]);
+            const double c = rs[q] - (Ds[q] * s[q] - yd[q]);
+            gyd[q] = a;
+            gs[q] = c;
+            t[q] = Ds[q] * a + c;
+        }
+    }
+}
+
+// after the 2x2 correction (e_x, e_y) of the active instances: x += e_x,
+// y += e_y, e_s = J_d e_x - g_yd (jde = J_d e_x formed), s += e_s,
+// y_d += D_s e_s - g_s
+__global__ void k_recover4(i64 n, i64 m, i64 md, const int* __restrict__ active, const double* __restrict__ Ds,
+                           const double* __restrict__ ex, const double* __restrict__ ey,
+                           const double* __restrict__ jde, const double* __restrict__ gs,
+                           const double* __restrict__ gyd, double* __restrict__ x, double* __restrict__ y,
+                           double* __restrict__ s, double* __restrict__ yd) {
+    const int b = blockIdx.y;
+    if (!active[b]) return;
+    const i64 tot = n + m + md;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (i64)gridDim.x * blockDim.x) {
+        if (i < n) x[(i64)b * n + i] += ex[(i64)b * n + i];
+        else if (i < n + m) y[(i64)b * m + (i - n)] += ey[(i64)b * m + (i - n)];
+        else {
+            const i64 q = (i64)b * md + (i - n - m);
+            const double es = jde[q] - gyd[q];
+            s[q] += es;
+            yd[q] += Ds[q] * es - gs[q];
+        }
+    }
+}
+
+// per instance (one block): out[b] = sum of squares of the four vectors
+// (lengths n, md, m, md; a null vector counts as zero)
+__global__ __launch_bounds__(kBlock) void k_sumsq4(i64 n, i64 md, i64 m, const double* __restrict__ a,
+                                                   const double* __restrict__ c, const double* __restrict__ d,
+                                                   const double* __restrict__ e, double* __restrict__ out) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (i64 i = threadIdx.x; i < n; i += blockDim.x) { const double v = a[(i64)b * n + i]; acc += v * v; }
+    for (i64 i = threadIdx.x; i < md; i += blockDim.x) {
+        const double v = c[(i64)b * md + i], w = e[(i64)b * md + i];
+        acc += v * v + w * w;
+    }
+    for (i64 i = threadIdx.x; i < m; i += blockDim.x) { const double v = d[(i64)b * m + i]; acc += v * v; }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[b] = acc;
+}
+
+// per instance (one block): ||K4||_inf from the row sums: x rows |H| (full
+// pattern) + |D_x + delta| + |J^T| + |J_d^T|; s rows |D_s| + 1; y rows |J|;
+// y_d rows |J_d| + 1
+__global__ __launch_bounds__(kBlock) void k_norm4(i64 n, i64 m, i64 md, const i64* __restrict__ hf_ptr,
+                                                  const i32* __restrict__ hf_col, const i64* __restrict__ hf_src,
+                                                  const double* __restrict__ H, i64 nnzH,
+                                                  const double* __restrict__ Dx, const double* __restrict__ delta,
+                                                  const i64* __restrict__ jt_ptr, const i64* __restrict__ jt_src,
+                                                  const double* __restrict__ J, i64 nnzJ,
+                                                  const i64* __restrict__ dt_ptr, const i64* __restrict__ dt_src,
+                                                  const double* __restrict__ Jd, i64 nnzJd,
+                                                  const i64* __restrict__ j_ptr, const i64* __restrict__ d_ptr,
+                                                  const double* __restrict__ Ds, double* __restrict__ out) {
+    __shared__ double sh[kBlock / kWave];
+    const int b = blockIdx.x;
+    double mx = 0.0;
+    for (i64 i = threadIdx.x; i < n; i += blockDim.x) {
+        double r = 0.0, dg = Dx[(i64)b * n + i] + delta[b];
+        for (i64 k = hf_ptr[i]; k < hf_ptr[i + 1]; k++) {
+            const double v = H[(i64)b * nnzH + hf_src[k]];
+            if (hf_col[k] == i) dg += v;
+            else r += fabs(v);
+        }
+        r += fabs(dg);
+        for (i64 k = jt_ptr[i]; k < jt_ptr[i + 1]; k++) r += fabs(J[(i64)b * nnzJ + jt_src[k]]);
+        for (i64 k = dt_ptr[i]; k < dt_ptr[i + 1]; k++) r += fabs(Jd[(i64)b * nnzJd + dt_src[k]]);
+        mx = fmax(mx, r);
+    }
+    for (i64 i = threadIdx.x; i < md; i += blockDim.x) {
+        mx = fmax(mx, fabs(Ds[(i64)b * md + i]) + 1.0);
+        double r = 1.0;
+        for (i64 k = d_ptr[i]; k < d_ptr[i + 1]; k++) r += fabs(Jd[(i64)b * nnzJd + k]);
+        mx = fmax(mx, r);
+    }
+    for (i64 i = threadIdx.x; i < m; i += blockDim.x) {
+        double r = 0.0;
+        for (i64 k = j_ptr[i]; k < j_ptr[i + 1]; k++) r += fabs(J[(i64)b * nnzJ + k]);
+        mx = fmax(mx, r);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, kWave));
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int t = 0; t < (int)(blockDim.x / kWave); t++) r = fmax(r, sh[t]);
+        out[b] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // assembly: H_gamma = tril(H) + diag(D_x + delta) + gamma * tril(J^T J)
 // (Sec. 3 and eq. eq:gamma), one thread per entry of tril(P H_gamma P^T),
 // summed in FP64 in a fixed order and written into the supernodal panels.

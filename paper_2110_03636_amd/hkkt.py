@@ -27,6 +27,7 @@ EXPORTS = [
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
     "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule", "hkkt_hsolve_noalloc",
     "hkkt_factor_regularized", "hkkt_gamma_heuristic", "hkkt_profile_select",
+    "hkkt_analyze4", "hkkt_factor4_batch", "hkkt_solve4_batch",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged",
@@ -117,6 +118,9 @@ def lib():
         L.hkkt_profile_begin.argtypes = [V]
         L.hkkt_profile_end.argtypes = [V, V, V]
         L.hkkt_profile_select.argtypes = [V, C.c_uint, C.c_int]
+        L.hkkt_analyze4.argtypes = [V, C.c_int64, C.c_int64, C.c_int64, V, V, V, V, V, V, V]
+        L.hkkt_factor4_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V, V, V]
+        L.hkkt_solve4_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V, V, V]
         _lib = L
     return _lib
 
@@ -452,6 +456,47 @@ class Solver(_SymbolicView):
                                           out.ctypes.data), self._ctx)
         self.nb = 0
         return out
+
+    # -- the 4x4 system of Sec. 3 ---------------------------------------------
+    def analyze4(self, pattern, ineq, perm=None):
+        p = pattern
+        keep = [_np(p.H_rowptr, np.int64), _np(p.H_col, np.int32), _np(p.J_rowptr, np.int64),
+                _np(p.J_col, np.int32), _np(ineq.Jd_rowptr, np.int64), _np(ineq.Jd_col, np.int32)]
+        pp = None if perm is None else _np(perm, np.int32)
+        _check(lib().hkkt_analyze4(self._ctx, int(p.n_x), int(p.m), int(ineq.m_d), *[_ptr(a) for a in keep],
+                                   _ptr(pp)), self._ctx)
+        self.n, self.m, self.md, self.G = int(p.n_x), int(p.m), int(ineq.m_d), 1
+        return self
+
+    def factor4(self, batch, ineq):
+        nb = batch.nb
+        delta = np.ascontiguousarray(batch.delta, np.float64)
+        gamma = np.ascontiguousarray(batch.gamma, np.float64)
+        vals = (self._arr(batch.H_val, nb, -1), self._arr(batch.D_x, nb, self.n),
+                self._arr(batch.J_val, nb, -1) if self.m > 0 else None,
+                self._arr(ineq.Jd_val, nb, -1) if self.md > 0 else None,
+                self._arr(ineq.D_s, nb, self.md) if self.md > 0 else None)
+        self._keep_vals = vals
+        st = np.zeros(nb, np.int32)
+        fc = np.zeros(nb, np.int64)
+        rc = _check(lib().hkkt_factor4_batch(self._ctx, nb, *[_ptr(v) for v in vals], delta.ctypes.data,
+                                             gamma.ctypes.data, st.ctypes.data, fc.ctypes.data), self._ctx)
+        self.nb = nb
+        return rc, st, fc
+
+    def solve4(self, rx, rs, ry, ryd):
+        """Returns (rc, dx, ds, dy, dyd, infos)."""
+        nb = self.nb
+        ins = [self._arr(rx, nb, self.n), self._arr(rs, nb, self.md) if self.md else None,
+               self._arr(ry, nb, self.m) if self.m else None, self._arr(ryd, nb, self.md) if self.md else None]
+        outs = [self._out(nb, self.n), self._out(nb, max(self.md, 0)), self._out(nb, max(self.m, 0)),
+                self._out(nb, max(self.md, 0))]
+        info = (Info * nb)()
+        rc = _check(lib().hkkt_solve4_batch(self._ctx, nb, *[_ptr(a) for a in ins],
+                                            _ptr(outs[0]), _ptr(outs[1]) if self.md else None,
+                                            _ptr(outs[2]) if self.m else None, _ptr(outs[3]) if self.md else None,
+                                            info), self._ctx)
+        return (rc, *outs, [info[i].as_dict() for i in range(nb)])
 
     def factor_batch(self, batch):
         return self.factor(batch.H_val, batch.D_x, batch.J_val, batch.delta, batch.gamma)

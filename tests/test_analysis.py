@@ -45,7 +45,7 @@ def _cases():
 
 def test_exports_match_header():
     hdr = open(os.path.join(ROOT, "include", "hkkt.h")).read()
-    declared = set(re.findall(r"\b(hkkt_[a-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(hkkt_[a-z0-9_]+)\s*\(", hdr))
     declared = {d for d in declared if not d.endswith("_t")}
     assert declared == set(hkkt.EXPORTS), declared ^ set(hkkt.EXPORTS)
     L = ctypes.CDLL(hkkt.LIB_PATH)
