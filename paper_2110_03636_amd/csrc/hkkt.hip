@@ -549,6 +549,7 @@ struct Batch {
     DBuf ids_pass, ids_a, ids_b, ids_all;   // batch-entry lists of the solve phase
     DBuf cact;                 // per (entry, member): member takes part in the current pass (groups)
     DBuf ptol;                 // per (entry, member) CG tolerance of the current pass (inexact refinement)
+    DBuf gidx;                 // entries of a source batch gathered into this one
     // solve copy of the top levels' panels for the staged tree kernel:
     // levels [lt_lo, nlevels), lt_size entries per instance from L storage
     // offset lt_base; lt_lo = -1 when stale (rebuilt after a factorization)
@@ -1108,6 +1109,41 @@ static void alloc_solve(hkkt_ctx* c, Batch& B) {
     for (DBuf* d : {&B.ids_pass, &B.ids_a, &B.ids_b, &B.ids_all}) d->ensure(nb * 4);
     for (DBuf* d : {&B.rsq, &B.rowred, &B.knorm}) d->ensure(nc * 8);
     B.cact.ensure(nc * 4);
+}
+
+// F's entries i <- B's entries idx[i] (idx host, uploaded into F.gidx), on
+// F's stream: one gather launch per array
+static void gather_rows(hkkt_ctx* c, Batch& F, const std::vector<std::pair<DBuf*, const DBuf*>>& arrays, i64 len) {
+    if (len <= 0) return;
+    for (const auto& a : arrays)
+        LAUNCH(10, k_gather_inst, dim3(grid1(len, 1024), F.nb), dim3(kBlock), 0, F.stream,
+               (const double*)a.second->as<double>(), a.first->as<double>(), len, (const int*)F.gidx.as<int>());
+    (void)c;
+}
+
+static void upload_gidx(Batch& F, const std::vector<int>& idx) {
+    F.gidx.ensure(std::max<size_t>(1, idx.size()) * 4);
+    HIPCHK(hipMemcpyAsync(F.gidx.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, F.stream));
+    HIPCHK(hipStreamSynchronize(F.stream));   // idx may go out of scope
+}
+
+// every value array (and the scaled system's) of F from B's entries in F.gidx
+static void gather_values(hkkt_ctx* c, Batch& F, const Batch& B) {
+    const Symbolic& S = c->sym.S;
+    const i64 nHF = (i64)S.HF_col.size();
+    gather_rows(c, F, {{&F.H, &B.H}}, S.nnzH);
+    gather_rows(c, F, {{&F.J, &B.J}, {&F.JT, &B.JT}}, S.nnzJ);
+    gather_rows(c, F, {{&F.HF, &B.HF}}, nHF);
+    gather_rows(c, F, {{&F.Dx, &B.Dx}, {&F.Dxp, &B.Dxp}}, S.n);
+    gather_rows(c, F, {{&F.delta, &B.delta}, {&F.gamma, &B.gamma}}, S.G);
+    if (F.scaled) {
+        gather_rows(c, F, {{&F.Hs, &B.Hs}}, S.nnzH);
+        gather_rows(c, F, {{&F.Js, &B.Js}, {&F.JTs, &B.JTs}}, S.nnzJ);
+        gather_rows(c, F, {{&F.HFs, &B.HFs}}, nHF);
+        gather_rows(c, F, {{&F.Dxps, &B.Dxps}, {&F.Dxs, &B.Dxs}}, S.n);
+        gather_rows(c, F, {{&F.dz, &B.dz}}, S.G);
+        gather_rows(c, F, {{&F.sc, &B.sc}}, S.n + S.m);
+    }
 }
 
 // copy values of the given (host or device) buffers into B, entry i of B
@@ -2061,7 +2097,8 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         if (!c->fb_idx.empty()) {
             const double t1 = now_ms();
             alloc_values(c, c->fb, (int)c->fb_idx.size());
-            load_values(c, c->fb, H, Dx, J, delta, gamma, &c->fb_idx, dev);
+            upload_gidx(c->fb, c->fb_idx);          // the main batch's values, already gathered and scaled
+            gather_values(c, c->fb, c->main);
             std::vector<int> act(c->fb_idx.size(), 1);
             factor_batch(c, c->fb, act);
             for (size_t i = 0; i < c->fb_idx.size(); i++)
@@ -2233,37 +2270,21 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
             Batch& F = *g.F;
             const int ne = (int)g.entries.size();
             hipStream_t fst = F.stream;
-            auto cp = [&](DBuf& d, const DBuf& src, i64 len, int i, int e) {
-                if (len > 0)
-                    HIPCHK(hipMemcpyAsync(d.as<double>() + (i64)i * len, src.as<double>() + (i64)e * len,
-                                          (size_t)len * 8, hipMemcpyDeviceToDevice, fst));
-            };
             if (!g.prefactored) {
                 alloc_values(c, F, ne);
-                for (int i = 0; i < ne; i++) {
-                    const int e = g.entries[i];
-                    cp(F.H, B.H, S.nnzH, i, e); cp(F.J, B.J, S.nnzJ, i, e); cp(F.JT, B.JT, S.nnzJ, i, e);
-                    cp(F.HF, B.HF, (i64)S.HF_col.size(), i, e); cp(F.Dx, B.Dx, S.n, i, e);
-                    cp(F.Dxp, B.Dxp, S.n, i, e); cp(F.delta, B.delta, G, i, e); cp(F.gamma, B.gamma, G, i, e);
-                    if (F.scaled) {
-                        cp(F.Hs, B.Hs, S.nnzH, i, e); cp(F.Js, B.Js, S.nnzJ, i, e); cp(F.JTs, B.JTs, S.nnzJ, i, e);
-                        cp(F.HFs, B.HFs, (i64)S.HF_col.size(), i, e); cp(F.Dxps, B.Dxps, S.n, i, e);
-                        cp(F.Dxs, B.Dxs, S.n, i, e); cp(F.dz, B.dz, G, i, e); cp(F.sc, B.sc, S.n + S.m, i, e);
-                    }
-                }
+                upload_gidx(F, g.entries);
+                gather_values(c, F, B);
                 std::vector<int> act(ne, 1);
                 factor_batch(c, F, act);
             }
             g.ffail = F.h_fail;
             alloc_solve(c, F);
-            for (int i = 0; i < ne; i++) {
-                const int e = g.entries[i];
-                cp(F.r1p, B.r1p, S.n, i, e);
-                cp(F.r2, B.r2, S.m, i, e);
-                if (!g.prefactored) {   // start from the FP32 iterate (stable: its members no longer run there)
-                    cp(F.xz, B.xz, S.n, i, e);
-                    cp(F.yz, B.yz, S.m, i, e);
-                }
+            if (g.prefactored) upload_gidx(F, g.entries);
+            gather_rows(c, F, {{&F.r1p, &B.r1p}}, S.n);
+            gather_rows(c, F, {{&F.r2, &B.r2}}, S.m);
+            if (!g.prefactored) {   // start from the FP32 iterate (stable: its members no longer run there)
+                gather_rows(c, F, {{&F.xz, &B.xz}}, S.n);
+                gather_rows(c, F, {{&F.yz, &B.yz}}, S.m);
             }
             std::vector<int> frun(g.run);
             for (size_t q = 0; q < frun.size(); q++)
@@ -2372,9 +2393,12 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         close_join();
         if (werr) std::rethrow_exception(werr);
         double fb_ms = 0.0;
+        std::vector<int> src_rows, dst_rows;   // single systems: whole rows, one copy launch per vector
         for (auto& gp : groups) {
             Group& g = *gp;
             fb_ms += g.ms;
+            src_rows.clear();
+            dst_rows.clear();
             for (size_t i = 0; i < g.entries.size(); i++)
                 for (int k = 0; k < G; k++) {
                     const size_t fi = i * G + k, ci = (size_t)g.entries[i] * G + k;
@@ -2385,15 +2409,20 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                         continue;
                     }
                     // the member's slices of the iterate back into the main batch
-                    const i64 x0 = S.x_off[k], nx = S.x_off[k + 1] - S.x_off[k];
-                    const i64 y0 = S.y_off[k], ny = S.y_off[k + 1] - S.y_off[k];
-                    HIPCHK(hipMemcpyAsync(B.xz.as<double>() + (i64)g.entries[i] * S.n + x0,
-                                          g.F->xz.as<double>() + (i64)i * S.n + x0, (size_t)nx * 8,
-                                          hipMemcpyDeviceToDevice, st));
-                    if (ny > 0)
-                        HIPCHK(hipMemcpyAsync(B.yz.as<double>() + (i64)g.entries[i] * S.m + y0,
-                                              g.F->yz.as<double>() + (i64)i * S.m + y0, (size_t)ny * 8,
+                    if (G == 1) {
+                        src_rows.push_back((int)i);
+                        dst_rows.push_back(g.entries[i]);
+                    } else {
+                        const i64 x0 = S.x_off[k], nx = S.x_off[k + 1] - S.x_off[k];
+                        const i64 y0 = S.y_off[k], ny = S.y_off[k + 1] - S.y_off[k];
+                        HIPCHK(hipMemcpyAsync(B.xz.as<double>() + (i64)g.entries[i] * S.n + x0,
+                                              g.F->xz.as<double>() + (i64)i * S.n + x0, (size_t)nx * 8,
                                               hipMemcpyDeviceToDevice, st));
+                        if (ny > 0)
+                            HIPCHK(hipMemcpyAsync(B.yz.as<double>() + (i64)g.entries[i] * S.m + y0,
+                                                  g.F->yz.as<double>() + (i64)i * S.m + y0, (size_t)ny * 8,
+                                                  hipMemcpyDeviceToDevice, st));
+                    }
                     const InstState& f = g.fs[fi];
                     is[ci].status = f.status;
                     is[ci].rr = f.rr;
@@ -2401,6 +2430,20 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                     is[ci].cg = f.cg;
                     is[ci].passes = f.passes;
                 }
+            if (!src_rows.empty()) {
+                const int cnt = (int)src_rows.size();
+                std::vector<int> both(src_rows);
+                both.insert(both.end(), dst_rows.begin(), dst_rows.end());
+                g.F->gidx.ensure(both.size() * 4);
+                HIPCHK(hipMemcpyAsync(g.F->gidx.p, both.data(), both.size() * 4, hipMemcpyHostToDevice, st));
+                const int* sidx = g.F->gidx.as<int>();
+                LAUNCH(10, k_copy_rows, dim3(grid1(S.n, 1024), cnt), dim3(kBlock), 0, st,
+                       (const double*)g.F->xz.as<double>(), B.xz.as<double>(), (i64)S.n, sidx, sidx + cnt);
+                if (S.m > 0)
+                    LAUNCH(10, k_copy_rows, dim3(grid1(S.m, 1024), cnt), dim3(kBlock), 0, st,
+                           (const double*)g.F->yz.as<double>(), B.yz.as<double>(), (i64)S.m, sidx, sidx + cnt);
+                HIPCHK(hipStreamSynchronize(st));   // both goes out of scope
+            }
         }
         c->ms[3] = fb_ms;
         // final metrics: RR, BE, floor on the full KKT residual, per member

@@ -346,6 +346,22 @@ __global__ __launch_bounds__(kBlock) void k_norm4(i64 n, i64 m, i64 md, const i6
     }
 }
 
+// dst[i][0:len) = src[idx[i]][0:len) (gather of batch entries; grid.y = entry)
+__global__ void k_gather_inst(const double* __restrict__ src, double* __restrict__ dst, i64 len,
+                              const int* __restrict__ idx) {
+    const i64 so = (i64)idx[blockIdx.y] * len, d0 = (i64)blockIdx.y * len;
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += (i64)gridDim.x * blockDim.x)
+        dst[d0 + k] = src[so + k];
+}
+
+// dst[didx[i]][0:len) = src[sidx[i]][0:len) (rows of batch entries)
+__global__ void k_copy_rows(const double* __restrict__ src, double* __restrict__ dst, i64 len,
+                            const int* __restrict__ sidx, const int* __restrict__ didx) {
+    const i64 s0 = (i64)sidx[blockIdx.y] * len, d0 = (i64)didx[blockIdx.y] * len;
+    for (i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x; k < len; k += (i64)gridDim.x * blockDim.x)
+        dst[d0 + k] = src[s0 + k];
+}
+
 // ---------------------------------------------------------------------------
 // assembly: H_gamma = tril(H) + diag(D_x + delta) + gamma * tril(J^T J)
 // (Sec. 3 and eq. eq:gamma), one thread per entry of tril(P H_gamma P^T),
