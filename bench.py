@@ -82,9 +82,7 @@ def run_gpu(args):
     given = {"mixed": args.schedule_mixed, "fp64": args.schedule_fp64}
 
     def make(prec, tune=False):
-        extra = {} if args.mixed_pivot_tol is None else {"mixed_pivot_tol": args.mixed_pivot_tol}
-        s = hkkt.Solver(precision=prec, device=True, kkt_tol=1e-10, scaling=args.scaling,
-                        refine_inexact=args.refine_inexact, mixed_check=args.mixed_check, **extra)
+        s = hkkt.Solver(precision=prec, device=True, **solver_options(args))
         s.analyze(b.pattern)
         if given.get(prec):   # a schedule from an earlier autotuning (profiler runs)
             s.set_schedule(*[int(v) for v in given[prec].split(",")])
@@ -107,31 +105,55 @@ def run_gpu(args):
     torch.cuda.synchronize()
     # one extra step with an event pair around every launch (an event pair
     # costs about as much as a short kernel, so the timed steps do not carry
-    # them all): the per-class breakdown of a step and the phases
+    # them all): the per-class breakdown of a step; then one such step per
+    # factor precision (the FP32 batch and the FP64 fallback batches run
+    # kernels of the same classes with 4- and 8-byte elements)
     s.profile_select(None, 1)
     s.profile_begin()
     pinfos = step(s)
     prof = s.profile_end()                      # per step
-    # timed steps, with HIP events on the library's stream around every
-    # PROF_EVERY-th launch of the step's dominant kernel class only: its
-    # average launch duration over the timed region
+    byprec = {}
+    for prec, esz in (("mixed", 4), ("fp64", 8)):
+        s.profile_precision(prec)
+        s.profile_begin()
+        pi = step(s)
+        byprec[prec] = {"prof": s.profile_end(), "esz": esz, "infos": pi}
+    s.profile_precision(None)
     stats = s.stats()
-    per = per_instance_bytes(stats, 4)
-    lf, lb = level_bytes(s, 4)
-    nlev = len(lf)
-    tk = tree_key(prof)
-    lo = round(prof["bwd"][1] / prof[tk][1]) if prof[tk][1] else nlev
-    # applications per instance over the profiled step: each pass applies
-    # H_gamma^{-1} once per CG iteration plus twice (w and the primal
-    # recovery); J^T and J are applied once per CG iteration plus twice / once
-    apps = sum(i["cg_iters"] + 2 * i["passes"] for i in pinfos)
-    spmv_apps = sum(2 * i["cg_iters"] + 3 * i["passes"] for i in pinfos)
-    total = {"fwd": sum(lf[:lo]) * apps, "bwd": sum(lb[:lo]) * apps,
-             tk: (sum(lf[lo:]) + sum(lb[lo:])) * apps,
-             "jt_spmv": per["jt_spmv"] * spmv_apps / 2, "j_spmv": per["j_spmv"] * spmv_apps / 2}
-    best = max(total, key=lambda k: prof[k][0])
+    nlev = len(level_bytes(s, 4)[0])
+    # algorithmic bytes per (class, precision) over a profiled step:
+    # per-instance bytes of one application of H_gamma^{-1} (J^T, J) times
+    # the instance-applications run on factors of that precision. Each pass
+    # applies H_gamma^{-1} once per CG iteration plus twice (w and the
+    # primal recovery); J^T and J once per CG iteration plus twice / once.
+    total, pprof, meta = {}, {}, {}
+    for prec, d in byprec.items():
+        pr, esz, pi = d["prof"], d["esz"], d["infos"]
+        if prec == "fp64":
+            cgk = [i["cg_iters_fp64"] for i in pi]; psk = [i["passes_fp64"] for i in pi]
+        else:
+            cgk = [i["cg_iters"] - i["cg_iters_fp64"] for i in pi]
+            psk = [i["passes"] - i["passes_fp64"] for i in pi]
+        apps = sum(cgk) + 2 * sum(psk)
+        spmv_apps = 2 * sum(cgk) + 3 * sum(psk)
+        lf, lb = level_bytes(s, esz)
+        tk = tree_key(pr)
+        lo = round(pr["bwd"][1] / pr[tk][1]) if pr[tk][1] else nlev
+        per = per_instance_bytes(stats, esz)
+        for cls, byt in (("fwd", sum(lf[:lo]) * apps), ("bwd", sum(lb[:lo]) * apps),
+                         (tk, (sum(lf[lo:]) + sum(lb[lo:])) * apps),
+                         ("jt_spmv", per["jt_spmv"] * spmv_apps / 2), ("j_spmv", per["j_spmv"] * spmv_apps / 2)):
+            total[(cls, prec)] = byt
+            pprof[(cls, prec)] = pr[cls]
+        meta[prec] = {"lo": lo, "tk": tk, "apps": apps}
+    best = max(total, key=lambda k: pprof[k][0])
+    bcls, bprec = best
+    # timed steps, with HIP events on the library's streams around every
+    # PROF_EVERY-th launch of the dominant (class, precision) only: its
+    # average launch duration over the timed region
     PROF_EVERY = 4
-    s.profile_select([best], PROF_EVERY)
+    s.profile_select([bcls], PROF_EVERY)
+    s.profile_precision(bprec)
     s.profile_begin()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -140,36 +162,39 @@ def run_gpu(args):
     el = time.perf_counter() - t0
     timed = s.profile_end()
     s.profile_select(None, 1)
+    s.profile_precision(None)
     ok = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
     value = ok * args.steps / el
     xs, ys = s.last_xy
-    launches = prof[best][1]                    # per step
-    avg_ms = timed[best][0] / max(timed[best][1], 1)
+    launches = pprof[best][1]                   # per step
+    avg_ms = timed[bcls][0] / max(timed[bcls][1], 1)
     per_launch = total[best] / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    # phases: all triangular-solve launches, and both SpMV kernels
-    tri = [k for k in ("fwd", "bwd", tk) if prof[k][1]]
+    # phases: all triangular-solve launches, and both SpMV kernels, both precisions
     phases = {}
-    for name, keys, extra_ms in (("solve", tri, prof["tri_wide"][0]), ("spmv", ["jt_spmv", "j_spmv"], 0.0)):
-        byt = sum(total[k] for k in keys)
-        ms = sum(prof[k][0] for k in keys) + extra_ms
+    for name, classes in (("solve", ("fwd", "bwd", "tri_tree", "tri_tree_staged", "tri_wide")),
+                          ("spmv", ("jt_spmv", "j_spmv"))):
+        byt = sum(v for (c_, p_), v in total.items() if c_ in classes and pprof[(c_, p_)][1])
+        ms = sum(byprec[p_]["prof"][c_][0] for p_ in byprec for c_ in classes)
         phases[name] = {"alg_GB": round(byt / 1e9, 3), "ms": round(ms, 3),
                         "GBps": round(byt / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                         "frac": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
     phases["stream_copy_GBps"] = stream_copy_gbps()
-    kname = {"fwd": "k_fwd_lvl<float,true> (forward supernodal triangular solve, one launch per level)",
-             "bwd": "k_bwd_lvl<float> (backward supernodal triangular solve, one launch per level)",
-             "tri_tree": "k_tri_tree<float,true,512> (both solves over the thin top levels)",
-             "tri_tree_staged": "k_tri_tree2<float,512,32> (both solves over the thin top levels, "
+    T = {"mixed": "float", "fp64": "double"}[bprec]
+    kname = {"fwd": f"k_fwd_lvl<{T},true> (forward supernodal triangular solve, one launch per level)",
+             "bwd": f"k_bwd_lvl<{T}> (backward supernodal triangular solve, one launch per level)",
+             "tri_tree": f"k_tri_tree<{T},true,512> (one sweep over the thin top levels)",
+             "tri_tree_staged": f"k_tri_tree2<{T},512,32> (one sweep over the thin top levels, "
                                 "working set staged in LDS)",
-             "jt_spmv": "k_jt<float>", "j_spmv": "k_j<float>"}[best]
+             "jt_spmv": "k_jt", "j_spmv": "k_j"}[bcls]
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": int(per_launch),
-                "launches_per_step": launches, "per_level_launch_levels": lo,
-                "timing": f"HIP events around every {PROF_EVERY}th launch of this class over the {args.steps} "
-                          f"timed steps ({timed[best][1]} launches timed); bytes and launches per step from one "
-                          f"profiled step with events around every launch"}
+                "launches_per_step": launches, "factor_precision": bprec,
+                "per_level_launch_levels": meta[bprec]["lo"],
+                "timing": f"HIP events around every {PROF_EVERY}th launch of this kernel on {bprec} factors "
+                          f"over the {args.steps} timed steps ({timed[bcls][1]} launches timed); bytes and "
+                          f"launches per step from one profiled step with events around every launch"}
 
     # plain FP64 comparators: batched (same steps as the mixed path, fewer of
     # them), and one instance at a time
@@ -213,6 +238,8 @@ def run_gpu(args):
         "cg_iters_mean": round(float(np.mean(cg)), 2),
         "passes_max": max(i["passes"] for i in infos),
         "profile_ms_per_step": {k: round(v[0], 3) for k, v in prof.items() if v[1]},
+        "profile_ms_per_step_by_factor_precision": {
+            p_: {k: round(v[0], 3) for k, v in d["prof"].items() if v[1]} for p_, d in byprec.items()},
         "profile_note": "per-class kernel time of one extra step with an event pair around every launch",
         "phases": phases,
         "autotuned": tuned or None,
@@ -249,6 +276,13 @@ def big_front_flops(sym, lds_rows):
     return upd, float(sym.stats()["flops_proxy"]) * 2
 
 
+def solver_options(args):
+    """Options every benchmark mode passes to its solvers (the headline's)."""
+    extra = {} if args.mixed_pivot_tol is None else {"mixed_pivot_tol": args.mixed_pivot_tol}
+    return dict(kkt_tol=1e-10, scaling=args.scaling, refine_inexact=args.refine_inexact,
+                mixed_check=args.mixed_check, **extra)
+
+
 def factor_mfma(args):
     """Numeric factorization of one dense-like system (the generator of the
     1200-variable configuration at a larger size), whose top supernodes are
@@ -261,7 +295,8 @@ def factor_mfma(args):
     H, D, J = dev(b.H_val), dev(b.D_x), dev(b.J_val)
     out = {}
     for prec in ("mixed", "fp64"):
-        s = hkkt.Solver(precision=prec, device=True)
+        # the FP32 factor alone: no pivot test routing instances to an FP64 refactor
+        s = hkkt.Solver(precision=prec, device=True, mixed_pivot_tol=0.0)
         s.analyze(b.pattern)
         s.factor(H, D, J, b.delta, b.gamma)
         torch.cuda.synchronize()
@@ -301,7 +336,7 @@ def uneven_group(args):
     R1, R2 = dev(cat([b.r1 for b in mem])), dev(cat([b.r2 for b in mem]))
     delta = np.stack([b.delta for b in mem], axis=1)
     gamma = np.stack([b.gamma for b in mem], axis=1)
-    s = hkkt.Solver(precision="mixed", device=True, kkt_tol=1e-10)
+    s = hkkt.Solver(precision="mixed", device=True, **solver_options(args))
     t0 = time.perf_counter()
     s.analyze_group(g)
     t_an = time.perf_counter() - t0
@@ -342,7 +377,7 @@ def large_single(args):
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
     H, J, R1, R2 = dev(b.H_val), dev(b.J_val), dev(b.r1), dev(b.r2)
     dxs = [dev(synth.fresh_dx(n, 5200 + k)[None]) for k in range(args.cycles)]
-    s = hkkt.Solver(precision="mixed", device=True, kkt_tol=1e-10)
+    s = hkkt.Solver(precision="mixed", device=True, **solver_options(args))
     t0 = time.perf_counter()
     s.analyze(b.pattern)
     t_an = time.perf_counter() - t0
@@ -389,7 +424,7 @@ def solve_only(args):
     rng = np.random.default_rng(4100)
     rhs = [(dev(rng.standard_normal((args.nb, args.n))), dev(rng.standard_normal((args.nb, args.n // 2))))
            for _ in range(args.solve_only)]
-    s = hkkt.Solver(precision="mixed", device=True, kkt_tol=1e-10)
+    s = hkkt.Solver(precision="mixed", device=True, **solver_options(args))
     s.analyze(b.pattern)
     if args.schedule_mixed:
         s.set_schedule(*[int(v) for v in args.schedule_mixed.split(",")])
@@ -421,27 +456,34 @@ def solve_only(args):
 def profile_hsolve(args):
     """Counter-collection driver: a 1 GiB device copy (calibration of the
     byte counters) followed by args.profile_hsolve applications of
-    H_gamma^{-1} to all instances of the workload (mixed precision)."""
+    H_gamma^{-1} to all instances of the workload, on factors of precision
+    args.profile_precision, with the schedule given for that precision (else
+    the library default)."""
     import numpy as np
     import torch
     from paper_2110_03636_amd import hkkt, synth
     a = torch.empty(2**28, dtype=torch.float32, device="cuda").fill_(1.0)
     torch.empty_like(a).copy_(a)
     torch.cuda.synchronize()
+    prec = args.profile_precision
     b = synth.grid_like(args.n, nb=args.nb, seed=4000, gammas=(1e4, 1e6), dx_exp=8.0)
     dev = lambda x: torch.as_tensor(x, device="cuda")
-    s = hkkt.Solver(precision="mixed", device=True)
+    s = hkkt.Solver(precision=prec, device=True)
     s.analyze(b.pattern)
+    sched = {"mixed": args.schedule_mixed, "fp64": args.schedule_fp64}[prec]
+    if sched:
+        s.set_schedule(*[int(v) for v in sched.split(",")])
     s.factor(dev(b.H_val), dev(b.D_x), dev(b.J_val), b.delta, b.gamma)
     rhs = dev(np.random.default_rng(0).standard_normal((args.nb, args.n)))
     s.profile_begin()
     for _ in range(args.profile_hsolve):
         s.hsolve(rhs)
     prof = s.profile_end()
-    lf, lb = level_bytes(s, 4)
+    lf, lb = level_bytes(s, 4 if prec == "mixed" else 8)
     tk = tree_key(prof)
     lo = round(prof["bwd"][1] / prof[tk][1]) if prof[tk][1] else len(lf)
-    print(json.dumps({"levels": len(lf), "per_level_launch_levels": lo, "tree_kernel": tk,
+    print(json.dumps({"precision": prec, "schedule": list(s.schedule()), "levels": len(lf),
+                      "per_level_launch_levels": lo, "tree_kernel": tk,
                       "alg_bytes_per_launch": {"fwd": sum(lf[:lo]) * args.nb / max(lo, 1),
                                                "bwd": sum(lb[:lo]) * args.nb / max(lo, 1),
                                                tk: (sum(lf[lo:]) + sum(lb[lo:])) * args.nb}}))
@@ -612,6 +654,8 @@ def main():
                     help="factorization of one dense-like system of this n_x (MFMA large-front measurement)")
     ap.add_argument("--solve-only", type=int, default=0,
                     help="factor once, then solve this many right-hand sides in a row (factor reuse)")
+    ap.add_argument("--profile-precision", default="mixed", choices=("mixed", "fp64"),
+                    help="factor precision of --profile-hsolve")
     ap.add_argument("--profile-hsolve", type=int, default=0,
                     help="counter-collection mode: calibration copy + this many H_gamma^{-1} applications")
     args = ap.parse_args()

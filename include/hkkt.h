@@ -130,6 +130,9 @@ typedef struct {
     int cg_iters;           /* total CG iterations over all passes */
     int passes;             /* hybrid passes (1 + refinement steps) */
     int fp64_fallback;      /* 1 if the instance was refactored in FP64 */
+    int cg_iters_fp64;      /* of cg_iters, those run on an FP64 factor (all of them in FP64
+                               precision; a mixed solve's after its fallback) */
+    int passes_fp64;        /* of passes, those run on an FP64 factor */
     double rr;              /* ||r - K z||_2 / ||r||_2, FP64 on the device */
     double be;              /* ||r - K z||_2 / (||K||_inf ||z||_2 + ||r||_2), Sec. 5.1 */
     double floor;           /* 2^-53 * || |K||z| + |r| ||_2 / ||r||_2 */
@@ -445,6 +448,13 @@ int hkkt_profile_begin(hkkt_ctx *ctx);
  * hkkt_profile_end then counts recorded launches. Default: all classes,
  * every launch. -1 if every < 1. */
 int hkkt_profile_select(hkkt_ctx *ctx, unsigned class_mask, int every);
+/* Which batches' launches hkkt_profile_begin/end record: -1 (default) all;
+ * HKKT_FP64 or HKKT_MIXED only the work on factors of that precision (a
+ * mixed-precision solver's FP64 fallback batches count as HKKT_FP64; the
+ * FP64 completion of its factor-time fallbacks too). Kernels of one class
+ * differ in element size between the two, so per-launch bytes do too.
+ * -1 on any other value. */
+int hkkt_profile_precision(hkkt_ctx *ctx, int precision);
 int hkkt_profile_end(hkkt_ctx *ctx, double *ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -64,10 +64,22 @@ static double now_ms() {
 // optional per-kernel timing with HIP events on the context's stream
 // ---------------------------------------------------------------------------
 constexpr int kNProf = 15;
+// precision of the batch whose work the calling host thread is launching
+// (HKKT_FP64 or HKKT_MIXED; -1 outside any batch), set by PrecScope: the
+// profile can record one precision's launches only (a mixed solver's FP64
+// fallback batches run in a worker thread of their own)
+static thread_local int tl_batch_prec = -1;
+struct PrecScope {
+    int old;
+    explicit PrecScope(int p) : old(tl_batch_prec) { tl_batch_prec = p; }
+    ~PrecScope() { tl_batch_prec = old; }
+};
+
 struct Prof {
     bool on = false;
     unsigned mask = ~0u;                             // classes recorded (bit k: class k)
     int every = 1;                                   // record every this many launches of a class
+    int prec = -1;                                   // record launches of this batch precision only (-1: all)
     std::atomic<long long> seen[16] = {};            // launches of each class since profile begin
     std::mutex mu;                                   // launches may come from two host threads
     std::vector<hipEvent_t> pool;
@@ -102,7 +114,8 @@ struct ProfScope {
     size_t i0 = 0;
     bool rec = false;
     ProfScope(Prof& p_, hipStream_t s, int k) : p(p_), st(s), kind(k) {
-        if (p.on && ((p.mask >> (k & 15)) & 1u) && p.seen[k & 15].fetch_add(1) % p.every == 0) {
+        if (p.on && ((p.mask >> (k & 15)) & 1u) && (p.prec < 0 || p.prec == tl_batch_prec) &&
+            p.seen[k & 15].fetch_add(1) % p.every == 0) {
             i0 = p.take2();
             HIPCHK(hipEventRecord(p.ev(i0), st));
             rec = true;
@@ -1189,6 +1202,7 @@ static void load_values(hkkt_ctx* c, Batch& B, const double* H, const double* Dx
 // factor all entries of B whose active flag is set; returns per (entry,
 // member) the min failing permuted column (INT_MAX = ok) in B.h_fail
 static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h) {
+    PrecScope ps(B.prec);
     hipStream_t st = B.stream;
     alloc_factor(c, B);
     HIPCHK(hipMemcpyAsync(B.active.p, active_h.data(), B.nb * 4, hipMemcpyHostToDevice, st));
@@ -1419,6 +1433,7 @@ static int upload_ids(hkkt_ctx* c, Batch& B, DBuf& dst, const std::vector<int>& 
 struct InstState {
     int status = HKKT_NOT_CONVERGED;
     int cg = 0, passes = 0, brk = 0;
+    int cg64 = 0, passes64 = 0;   // of cg and passes, those run on an FP64 factor
     double rr = INFINITY, rr_prev = INFINITY, rnorm = 0.0;
     bool fallback = false;
 };
@@ -1494,6 +1509,10 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
                              hst[i].it, rr, hst[i].breakdown);
             s.passes++;
             s.cg += hst[i].it;
+            if (B.prec != HKKT_MIXED) {
+                s.passes64++;
+                s.cg64 += hst[i].it;
+            }
             s.rr = rr;
             if (hst[i].breakdown) {
                 // Algorithm 1: a breakdown ends the solve; with delta2 > 0 the
@@ -2054,6 +2073,7 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
         c->factored = false;
         c->nb = nb;
+        PrecScope ps(c->main.prec);
         alloc_values(c, c->main, nb);
         load_values(c, c->main, H, Dx, J, delta, gamma, nullptr, dev);
         std::vector<int> all(nb, 1);
@@ -2221,6 +2241,7 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         const hipMemcpyKind in_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         const hipMemcpyKind out_kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         Batch& B = c->main;
+        PrecScope ps(B.prec);
         alloc_solve(c, B);
         // right-hand side into the permuted order (staged through ex / g2)
         HIPCHK(hipMemcpyAsync(B.ex.p, r1, (size_t)nb * S.n * 8, in_kind, st));
@@ -2268,6 +2289,7 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
         auto run_group = [&](Group& g) {
             const double t1 = now_ms();
             Batch& F = *g.F;
+            PrecScope ps(F.prec);
             const int ne = (int)g.entries.size();
             hipStream_t fst = F.stream;
             if (!g.prefactored) {
@@ -2353,6 +2375,8 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                     f.rnorm = is[cis[q]].rnorm;
                     f.cg = is[cis[q]].cg;
                     f.passes = is[cis[q]].passes;
+                    f.cg64 = is[cis[q]].cg64;
+                    f.passes64 = is[cis[q]].passes64;
                 }
             return g;
         };
@@ -2429,6 +2453,8 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                     is[ci].brk = f.brk;
                     is[ci].cg = f.cg;
                     is[ci].passes = f.passes;
+                    is[ci].cg64 = f.cg64;
+                    is[ci].passes64 = f.passes64;
                 }
             if (!src_rows.empty()) {
                 const int cnt = (int)src_rows.size();
@@ -2484,6 +2510,8 @@ int hkkt_solve_batch(hkkt_ctx* c, int nb, const double* r1, const double* r2, do
                 I.cg_iters = s.cg;
                 I.passes = s.passes;
                 I.fp64_fallback = s.fallback ? 1 : 0;
+                I.cg_iters_fp64 = s.cg64;
+                I.passes_fp64 = s.passes64;
                 I.rr = rr;
                 I.be = std::sqrt(rsq[i]) / (kn[i] * std::sqrt(zn2[i]) + rnorm);
                 I.floor = std::ldexp(1.0, -53) * std::sqrt(fl[i]) / (rnorm > 0 ? rnorm : 1.0);
@@ -2566,6 +2594,7 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         const Symbolic& S = c->sym.S;
         hipStream_t st = c->stream;
         Batch& B = c->main;
+        PrecScope ps(B.prec);
         alloc_solve(c, B);
         const bool dev = c->opt.pointer_mode == HKKT_PTR_DEVICE;
         HIPCHK(hipMemcpyAsync(B.ex.p, bvec, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -2905,7 +2934,7 @@ int hkkt_solve4_batch(hkkt_ctx* c, int nb, const double* rx, const double* rs, c
         HIPCHK(hipStreamSynchronize(st));
         for (double& v : rn) v = std::sqrt(v);
         std::vector<double> rr(nb, 0.0), best(nb, INFINITY);
-        std::vector<int> act(nb, 1), steps(nb, 0), cg(nb, 0), brk(nb, 0), fb(nb, 0), st2(nb, HKKT_OK);
+        std::vector<int> act(nb, 1), steps(nb, 0), cg(nb, 0), cg64(nb, 0), ps64(nb, 0), brk(nb, 0), fb(nb, 0), st2(nb, HKKT_OK);
         const int max_ref = c->opt.max_refine >= 0 ? c->opt.max_refine : 10;
         std::vector<hkkt_info> in2((size_t)nb);
         for (int step = 0;; step++) {
@@ -2944,6 +2973,8 @@ int hkkt_solve4_batch(hkkt_ctx* c, int nb, const double* rx, const double* rs, c
                 if (!act[b]) continue;
                 steps[b]++;
                 cg[b] += in2[b].cg_iters;
+                cg64[b] += in2[b].cg_iters_fp64;
+                ps64[b] += in2[b].passes_fp64;
                 fb[b] |= in2[b].fp64_fallback;
                 if (in2[b].status == HKKT_CG_BREAKDOWN) brk[b] = 1;
                 if (in2[b].status == HKKT_NOT_SPD) st2[b] = HKKT_NOT_SPD;
@@ -2991,6 +3022,8 @@ int hkkt_solve4_batch(hkkt_ctx* c, int nb, const double* rx, const double* rs, c
                 I.cg_iters = cg[b];
                 I.passes = steps[b];
                 I.fp64_fallback = fb[b];
+                I.cg_iters_fp64 = cg64[b];
+                I.passes_fp64 = ps64[b];
                 I.rr = rr[b];
                 I.be = rr[b] * rn[b] / (kn[b] * std::sqrt(zn[b]) + rn[b]);
                 I.floor = NAN;
@@ -3021,6 +3054,12 @@ int hkkt_profile_select(hkkt_ctx* c, unsigned class_mask, int every) {
     if (!c || every < 1) return HKKT_ERR_ARG;
     c->prof.mask = class_mask;
     c->prof.every = every;
+    return HKKT_OK;
+}
+
+int hkkt_profile_precision(hkkt_ctx* c, int precision) {
+    if (!c || (precision != -1 && precision != HKKT_FP64 && precision != HKKT_MIXED)) return HKKT_ERR_ARG;
+    c->prof.prec = precision;
     return HKKT_OK;
 }
 

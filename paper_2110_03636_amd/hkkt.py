@@ -27,7 +27,7 @@ EXPORTS = [
     "hkkt_profile_begin", "hkkt_profile_end", "hkkt_analyze_group", "hkkt_symbolic_create_group", "hkkt_autotune",
     "hkkt_symbolic_cb_offsets", "hkkt_get_schedule", "hkkt_set_schedule", "hkkt_hsolve_noalloc",
     "hkkt_factor_regularized", "hkkt_gamma_heuristic", "hkkt_profile_select",
-    "hkkt_analyze4", "hkkt_factor4_batch", "hkkt_solve4_batch",
+    "hkkt_analyze4", "hkkt_factor4_batch", "hkkt_solve4_batch", "hkkt_profile_precision",
 ]
 PROF_NAMES = ["assemble", "front_lds", "front_big", "fwd", "bwd", "jt_spmv", "j_spmv", "cg_vec",
               "cg_scalar", "residual", "other", "tri_wide", "tri_tree", "tri_tree_staged",
@@ -50,7 +50,8 @@ class Options(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int), ("cg_iters", C.c_int), ("passes", C.c_int),
-                ("fp64_fallback", C.c_int), ("rr", C.c_double), ("be", C.c_double),
+                ("fp64_fallback", C.c_int), ("cg_iters_fp64", C.c_int), ("passes_fp64", C.c_int),
+                ("rr", C.c_double), ("be", C.c_double),
                 ("floor", C.c_double), ("fail_col", C.c_int64)]
 
     def as_dict(self):
@@ -118,6 +119,7 @@ def lib():
         L.hkkt_profile_begin.argtypes = [V]
         L.hkkt_profile_end.argtypes = [V, V, V]
         L.hkkt_profile_select.argtypes = [V, C.c_uint, C.c_int]
+        L.hkkt_profile_precision.argtypes = [V, C.c_int]
         L.hkkt_analyze4.argtypes = [V, C.c_int64, C.c_int64, C.c_int64, V, V, V, V, V, V, V]
         L.hkkt_factor4_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V, V, V]
         L.hkkt_solve4_batch.argtypes = [V, C.c_int, V, V, V, V, V, V, V, V, V]
@@ -563,6 +565,14 @@ class Solver(_SymbolicView):
         """Record only the named classes (None: all), every `every`-th launch."""
         mask = 0xFFFFFFFF if classes is None else sum(1 << PROF_NAMES.index(k) for k in classes)
         _check(lib().hkkt_profile_select(self._ctx, mask, int(every)), self._ctx)
+
+    def profile_precision(self, precision=None):
+        """Record only launches on factors of this precision ("fp64" or
+        "mixed"; None: all)."""
+        if precision not in (None, "fp64", "mixed"):
+            raise ValueError(f"precision must be None, 'fp64' or 'mixed', not {precision!r}")
+        p = -1 if precision is None else {"fp64": FP64, "mixed": MIXED}[precision]
+        _check(lib().hkkt_profile_precision(self._ctx, p), self._ctx)
 
     def profile_end(self):
         """{class: (total_ms, launches)} of the launches since profile_begin."""

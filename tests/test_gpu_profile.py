@@ -1,0 +1,85 @@
+"""The library's own accounting, through the C ABI: per-instance counts of
+the CG iterations and passes that ran on FP64 factors, and per-class launch
+profiles restricted to one factor precision and one class subset. These
+numbers drive the benchmark's roofline (bytes per launch depend on the
+factor's element size), so they are checked against what the solve did."""
+import numpy as np
+import pytest
+
+from paper_2110_03636_amd import hkkt, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch():
+    # gamma 1e4 and 1e6 with D_x spread over 16 decades (unscaled): the FP32
+    # pivot test routes the gamma = 1e6 instances to FP64 at factor time
+    return synth.grid_like(3000, nb=8, seed=610, gammas=(1e4, 1e6), dx_exp=8.0)
+
+
+def test_fp64_counts_cover_every_iteration_on_fp64_solver():
+    b = _batch()
+    s = hkkt.Solver(precision="fp64")
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    for i in infos:
+        assert i["cg_iters_fp64"] == i["cg_iters"] and i["passes_fp64"] == i["passes"], i
+
+
+def test_mixed_counts_split_by_fallback():
+    b = _batch()
+    s = hkkt.Solver(precision="mixed")
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    rc, x, y, infos = s.solve(b.r1, b.r2)
+    assert any(i["fp64_fallback"] for i in infos), "workload meant to route some instances to FP64"
+    for i in infos:
+        assert 0 <= i["cg_iters_fp64"] <= i["cg_iters"] and 0 <= i["passes_fp64"] <= i["passes"], i
+        if not i["fp64_fallback"]:
+            assert i["cg_iters_fp64"] == 0 and i["passes_fp64"] == 0, i
+        else:
+            assert i["passes_fp64"] >= 1, i
+
+
+def test_profile_precision_partitions_launches():
+    """Launches recorded with the FP32 filter plus those with the FP64 filter
+    equal those recorded unfiltered, class by class (the same solve three
+    times; deterministic forward solves, so the three runs take the same
+    iterations and launch the same kernels)."""
+    b = _batch()
+    s = hkkt.Solver(precision="mixed", deterministic=1)
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    s.solve(b.r1, b.r2)
+    counts = {}
+    for p in (None, "mixed", "fp64"):
+        s.profile_precision(p)
+        s.profile_begin()
+        s.solve(b.r1, b.r2)
+        counts[p] = {k: v[1] for k, v in s.profile_end().items()}
+    s.profile_precision(None)
+    solves = ("fwd", "bwd", "tri_tree", "tri_tree_staged", "tri_wide")
+    assert sum(counts["fp64"][k] for k in solves) > 0 and sum(counts["mixed"][k] for k in solves) > 0, counts
+    for k in counts[None]:
+        assert counts["mixed"][k] + counts["fp64"][k] == counts[None][k], (k, counts)
+
+
+def test_profile_select_samples_one_class():
+    b = _batch()
+    s = hkkt.Solver(precision="fp64", deterministic=1)
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    s.profile_begin()
+    s.solve(b.r1, b.r2)
+    full = s.profile_end()
+    s.profile_select(["j_spmv"], 4)
+    s.profile_begin()
+    s.solve(b.r1, b.r2)
+    part = s.profile_end()
+    s.profile_select(None, 1)
+    assert part["j_spmv"][1] == (full["j_spmv"][1] + 3) // 4
+    assert all(v[1] == 0 for k, v in part.items() if k != "j_spmv")
+    with pytest.raises(ValueError):
+        s.profile_precision("fp16")
+    assert hkkt.lib().hkkt_profile_precision(s._ctx, 7) == hkkt.ERR_ARG
