@@ -637,7 +637,7 @@ def main():
                     help="1: probe each FP32 factor at factor time and refactor in FP64 where it cannot drive "
                          "refinement")
     ap.add_argument("--mixed-pivot-tol", type=float, default=None,
-                    help="FP32 pivot test threshold (library default 2^-16)")
+                    help="FP32 pivot test threshold (library default 2^-12)")
     ap.add_argument("--refine-inexact", type=int, default=1,
                     help="1 (default): refinement passes after the first stop CG at the accuracy the correction "
                          "needs; 0: every pass at the CG tolerance")

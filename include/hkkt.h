@@ -120,9 +120,11 @@ typedef struct {
                                every pass at the CG tolerance */
     double mixed_pivot_tol; /* mixed precision: an FP32 factor whose smallest ratio of pivot L_jj^2
                                to the assembled FP64 diagonal a_jj of H_gamma is below this is
-                               replaced by an FP64 factor at factor time (the FP32 success does not
-                               show that H_gamma is positive definite, Algorithm 1's test);
-                               0 turns the test off (default 2^-16) */
+                               replaced by an FP64 factor at factor time: the FP32 success does not
+                               show that H_gamma is positive definite (Algorithm 1's test), and a
+                               pivot that kept fewer than about 12 of its 24 bits cannot drive
+                               refinement to 1e-10 in fewer passes than an FP64 factor needs.
+                               0 turns the test off (default 2^-12) */
 } hkkt_options;
 
 typedef struct {
@@ -142,7 +144,7 @@ typedef struct {
 /* Defaults: FP64, host pointers, cg_tol 1e-12, cg_tol_mixed 1e-5,
  * kkt_tol 1e-10, quad_form_eps 1e-14, delta2 0, max_cg 0, max_refine 10,
  * ordering 0, relax 1, deterministic 0, mixed_check 0, mixed_check_tol 0.5,
- * autotune_cache 1, scaling 0, flow_live 0, refine_inexact 0, mixed_pivot_tol 2^-16. */
+ * autotune_cache 1, scaling 0, flow_live 0, refine_inexact 0, mixed_pivot_tol 2^-12. */
 void hkkt_default_options(hkkt_options *opt);
 
 /* Create a context bound to the current HIP device and the given stream

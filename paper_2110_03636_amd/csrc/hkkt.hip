@@ -195,17 +195,23 @@ struct DevSym {
     DBuf sn_first, sn_rowptr, sn_rows, sn_lptr, sn_cbptr, sn_uvptr, child_ptr, child_list, relmap, perm;
     DBuf a_dst, a_h, a_d, a_pptr, a_pa, a_pb;
     DBuf J_rowptr, J_colp, JT_rowptr, JT_col, JT_src, HF_rowptr, HF_col, HF_src;
-    DBuf lev_all, lev_small, lev_big;   // supernode lists, level-major
-    std::vector<i32> all_ptr, small_ptr, big_ptr;
-    std::vector<int> all_maxnr, small_maxnr;
+    DBuf lev_all;   // supernode lists, level-major
+    std::vector<i32> all_ptr;
+    std::vector<int> all_maxnr;
     DBuf ga_row, ga_idx, diag_off;
     DBuf xp_mem, a_mem, sn_mem, mblk, mblk_off, rblk, rblk_off;   // group members
-    // large fronts: per level sorted by width (descending) in lev_big, child
-    // rank pair lists (front, child) and per-front (nr, w) on the host
-    DBuf big_pairs;
-    std::vector<std::vector<std::pair<i32, i32>>> big_pair_seg;   // [level][rank] = (offset, count) in pairs
-    std::vector<std::vector<int>> big_pair_maxnc;                // [level][rank] = widest child CB (columns)
-    std::vector<std::pair<int, int>> big_nrw;                     // parallel to lev_big
+    // fronts split by size per element size (fs[0]: FP32 factors, fs[1]:
+    // FP64; a mixed-precision context factors both): LDS fronts, and large
+    // fronts per level sorted by width (descending) in lev_big, child rank
+    // pair lists (front, child) and per-front (nr, w) on the host
+    struct FrontSplit {
+        DBuf lev_small, lev_big, big_pairs;
+        std::vector<i32> small_ptr, big_ptr;
+        std::vector<int> small_maxnr;
+        std::vector<std::vector<std::pair<i32, i32>>> big_pair_seg;   // [level][rank] = (offset, count) in pairs
+        std::vector<std::vector<int>> big_pair_maxnc;                // [level][rank] = widest child CB (columns)
+        std::vector<std::pair<int, int>> big_nrw;                     // parallel to lev_big
+    } fs[2];
     // triangular-solve lists per (level, size class): classes 0..6 are the
     // segmented wavefront kernels (SEG, R) = (16,1) (32,1) (64,1) (64,2)
     // (64,4) (64,8) (64,16), class 7 the work-group kernel for supernodes with
@@ -257,7 +263,65 @@ static int lds_rows_limit(int elem_bytes) {
     return elem_bytes == 8 ? 90 : 128;
 }
 
-static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_rows) {
+// level lists of the LDS fronts (nr <= lds_rows) and of the large fronts
+static void build_split(DevSym::FrontSplit& F, const Symbolic& S, hipStream_t st, int lds_rows) {
+    std::vector<i32> small, big;
+    F.small_ptr.assign(1, 0);
+    F.big_ptr.assign(1, 0);
+    F.small_maxnr.clear();
+    for (i32 l = 0; l < S.nlevels; l++) {
+        int mxs = 0;
+        const size_t big0 = big.size();
+        for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
+            const i32 s = S.level_sn[q];
+            const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
+            if (nr <= lds_rows) { small.push_back(s); mxs = std::max(mxs, nr); }
+            else big.push_back(s);
+        }
+        std::sort(big.begin() + big0, big.end(), [&](i32 a, i32 b2) {
+            const int wa = S.sn_first[a + 1] - S.sn_first[a], wb = S.sn_first[b2 + 1] - S.sn_first[b2];
+            return wa != wb ? wa > wb : a < b2;
+        });
+        F.small_ptr.push_back((i32)small.size());
+        F.big_ptr.push_back((i32)big.size());
+        F.small_maxnr.push_back(mxs);
+    }
+    upload(F.lev_small, small, st);
+    upload(F.lev_big, big, st);
+    std::vector<i32> pairs;
+    F.big_pair_seg.assign(S.nlevels, {});
+    F.big_pair_maxnc.assign(S.nlevels, {});
+    F.big_nrw.clear();
+    for (i32 s2 : big)
+        F.big_nrw.push_back({(int)(S.sn_rowptr[s2 + 1] - S.sn_rowptr[s2]), S.sn_first[s2 + 1] - S.sn_first[s2]});
+    for (i32 l = 0; l < S.nlevels; l++) {
+        int maxc = 0;
+        for (i32 q = F.big_ptr[l]; q < F.big_ptr[l + 1]; q++) {
+            const i32 s2 = big[q];
+            maxc = std::max(maxc, S.child_ptr[s2 + 1] - S.child_ptr[s2]);
+        }
+        for (int r = 0; r < maxc; r++) {
+            const i32 off = (i32)(pairs.size() / 2);
+            int maxnc = 0;
+            for (i32 q = F.big_ptr[l]; q < F.big_ptr[l + 1]; q++) {
+                const i32 s2 = big[q];
+                if (S.child_ptr[s2 + 1] - S.child_ptr[s2] > r) {
+                    const i32 ch = S.child_list[S.child_ptr[s2] + r];
+                    pairs.push_back(s2);
+                    pairs.push_back(ch);
+                    maxnc = std::max(maxnc, (int)(S.sn_rowptr[ch + 1] - S.sn_rowptr[ch]) -
+                                                (S.sn_first[ch + 1] - S.sn_first[ch]));
+                }
+            }
+            F.big_pair_seg[l].push_back({off, (i32)(pairs.size() / 2) - off});
+            F.big_pair_maxnc[l].push_back(maxnc);
+        }
+    }
+    upload(F.big_pairs, pairs, st);
+}
+
+// mixed: the FP32 main batch and FP64 fallback batches both factor here
+static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, bool mixed) {
     upload(D.sn_first, S.sn_first, st);
     upload(D.sn_rowptr, S.sn_rowptr, st);
     upload(D.sn_rows, S.sn_rows, st);
@@ -289,69 +353,23 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, int lds_r
     upload(D.mblk_off, S.mblk_off, st);
     upload(D.rblk, S.rblk, st);
     upload(D.rblk_off, S.rblk_off, st);
-    // level lists: all supernodes of a level; split by front size
-    std::vector<i32> all, small, big;
+    // level lists: all supernodes of a level
+    std::vector<i32> all;
     D.all_ptr.assign(1, 0);
-    D.small_ptr.assign(1, 0);
-    D.big_ptr.assign(1, 0);
     D.all_maxnr.clear();
-    D.small_maxnr.clear();
     for (i32 l = 0; l < S.nlevels; l++) {
-        int mx = 0, mxs = 0;
-        const size_t big0 = big.size();
+        int mx = 0;
         for (i32 q = S.level_ptr[l]; q < S.level_ptr[l + 1]; q++) {
             const i32 s = S.level_sn[q];
-            const int nr = (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]);
             all.push_back(s);
-            mx = std::max(mx, nr);
-            if (nr <= lds_rows) { small.push_back(s); mxs = std::max(mxs, nr); }
-            else big.push_back(s);
+            mx = std::max(mx, (int)(S.sn_rowptr[s + 1] - S.sn_rowptr[s]));
         }
-        std::sort(big.begin() + big0, big.end(), [&](i32 a, i32 b2) {
-            const int wa = S.sn_first[a + 1] - S.sn_first[a], wb = S.sn_first[b2 + 1] - S.sn_first[b2];
-            return wa != wb ? wa > wb : a < b2;
-        });
         D.all_ptr.push_back((i32)all.size());
-        D.small_ptr.push_back((i32)small.size());
-        D.big_ptr.push_back((i32)big.size());
         D.all_maxnr.push_back(mx);
-        D.small_maxnr.push_back(mxs);
     }
     upload(D.lev_all, all, st);
-    upload(D.lev_small, small, st);
-    upload(D.lev_big, big, st);
-    {
-        std::vector<i32> pairs;
-        D.big_pair_seg.assign(S.nlevels, {});
-        D.big_pair_maxnc.assign(S.nlevels, {});
-        D.big_nrw.clear();
-        for (i32 s2 : big)
-            D.big_nrw.push_back({(int)(S.sn_rowptr[s2 + 1] - S.sn_rowptr[s2]), S.sn_first[s2 + 1] - S.sn_first[s2]});
-        for (i32 l = 0; l < S.nlevels; l++) {
-            int maxc = 0;
-            for (i32 q = D.big_ptr[l]; q < D.big_ptr[l + 1]; q++) {
-                const i32 s2 = big[q];
-                maxc = std::max(maxc, S.child_ptr[s2 + 1] - S.child_ptr[s2]);
-            }
-            for (int r = 0; r < maxc; r++) {
-                const i32 off = (i32)(pairs.size() / 2);
-                int maxnc = 0;
-                for (i32 q = D.big_ptr[l]; q < D.big_ptr[l + 1]; q++) {
-                    const i32 s2 = big[q];
-                    if (S.child_ptr[s2 + 1] - S.child_ptr[s2] > r) {
-                        const i32 ch = S.child_list[S.child_ptr[s2] + r];
-                        pairs.push_back(s2);
-                        pairs.push_back(ch);
-                        maxnc = std::max(maxnc, (int)(S.sn_rowptr[ch + 1] - S.sn_rowptr[ch]) -
-                                                    (S.sn_first[ch + 1] - S.sn_first[ch]));
-                    }
-                }
-                D.big_pair_seg[l].push_back({off, (i32)(pairs.size() / 2) - off});
-                D.big_pair_maxnc[l].push_back(maxnc);
-            }
-        }
-        upload(D.big_pairs, pairs, st);
-    }
+    for (int e = 0; e < 2; e++)
+        if (e == 1 || mixed) build_split(D.fs[e], S, st, lds_rows_limit(e == 0 ? 4 : 8));
     upload(D.ga_row, S.ga_row, st);
     upload(D.ga_idx, S.ga_idx, st);
     {
@@ -664,6 +682,7 @@ template <typename T>
 static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     const Symbolic& S = c->sym.S;
     const DevSym& D = c->dev;
+    const DevSym::FrontSplit& F = D.fs[sizeof(T) == 8 ? 1 : 0];
     hipStream_t st = B.stream;
     const int nb = B.nb;
     T* L = B.L.as<T>();
@@ -672,17 +691,17 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb * S.G, INT_MAX);
     LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.fvals(), L, active);
     for (i32 l = 0; l < S.nlevels; l++) {
-        const int ns_small = D.small_ptr[l + 1] - D.small_ptr[l];
+        const int ns_small = F.small_ptr[l + 1] - F.small_ptr[l];
         if (ns_small > 0) {
-            const int nr = D.small_maxnr[l];
+            const int nr = F.small_maxnr[l];
             const size_t lds = (size_t)nr * nr * sizeof(T);
             LAUNCH(1, k_front_lds<T>, dim3(ns_small, nb), dim3(kBlock), lds, st, D.v,
-                               D.lev_small.as<i32>() + D.small_ptr[l], L, CB, B.fail.as<int>(), active);
+                               F.lev_small.as<i32>() + F.small_ptr[l], L, CB, B.fail.as<int>(), active);
         }
-        const int ns_big = D.big_ptr[l + 1] - D.big_ptr[l];
+        const int ns_big = F.big_ptr[l + 1] - F.big_ptr[l];
         if (ns_big > 0) {
-            const i32* fr = D.lev_big.as<i32>() + D.big_ptr[l];
-            const auto* nrw = D.big_nrw.data() + D.big_ptr[l];
+            const i32* fr = F.lev_big.as<i32>() + F.big_ptr[l];
+            const auto* nrw = F.big_nrw.data() + F.big_ptr[l];
             i64 maxcb = 0;
             int maxw = 0;
             for (int q = 0; q < ns_big; q++) {
@@ -690,13 +709,13 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                 maxw = std::max(maxw, nrw[q].second);
             }
             LAUNCH(2, k_big_zero<T>, dim3(grid1(maxcb, 8192), ns_big, nb), dim3(kBlock), 0, st, D.v, fr, CB, active);
-            for (size_t r = 0; r < D.big_pair_seg[l].size(); r++) {
-                const auto& seg = D.big_pair_seg[l][r];
+            for (size_t r = 0; r < F.big_pair_seg[l].size(); r++) {
+                const auto& seg = F.big_pair_seg[l][r];
                 // columns of the widest child contribution block of this rank
-                const int ncc = D.big_pair_maxnc[l][r];
+                const int ncc = F.big_pair_maxnc[l][r];
                 if (ncc <= 0) continue;
                 LAUNCH(2, k_big_extend<T>, dim3((ncc + kExtCols - 1) / kExtCols, seg.second, nb), dim3(kBlock), 0, st,
-                       D.v, D.big_pairs.as<i32>() + 2 * seg.first, L, CB, active);
+                       D.v, F.big_pairs.as<i32>() + 2 * seg.first, L, CB, active);
             }
             // 128-column blocks: per 32-column panel a left-looking strip
             // update from the block's earlier panels, POTRF, TRSM; then one
@@ -1590,7 +1609,7 @@ static int analyze_ctx(hkkt_ctx* c, int G, const int64_t* x_off, const int64_t* 
             return (n < 1 || m < 0) ? HKKT_ERR_ARG : HKKT_ERR_PATTERN;
         }
         HIPCHK(hipSetDevice(c->device));
-        build_devsym(c->dev, c->sym.S, c->stream, lds_rows_limit(c->opt.precision == HKKT_MIXED ? 4 : 8));
+        build_devsym(c->dev, c->sym.S, c->stream, c->opt.precision == HKKT_MIXED);
         HIPCHK(hipStreamSynchronize(c->stream));
         if (c->pat.Hp.data() != Hp) {   // keep a copy for re-analysis (not when re-analysing from it)
             c->tree_width = -1;         // a new pattern drops the tuned choice
@@ -1720,7 +1739,7 @@ void hkkt_default_options(hkkt_options* o) {
     o->scaling = 0;
     o->flow_live = 0;
     o->refine_inexact = 0;
-    o->mixed_pivot_tol = 0x1p-16;
+    o->mixed_pivot_tol = 0x1p-12;
 }
 
 int hkkt_create(hkkt_ctx** out, const hkkt_options* opt, void* stream) {

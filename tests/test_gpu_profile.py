@@ -12,9 +12,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _batch():
-    # gamma 1e4 and 1e6 with D_x spread over 16 decades (unscaled): the FP32
-    # pivot test routes the gamma = 1e6 instances to FP64 at factor time
-    return synth.grid_like(3000, nb=8, seed=610, gammas=(1e4, 1e6), dx_exp=8.0)
+    # gamma 10 and 1e6 with D_x over four decades (unscaled): the FP32 pivot
+    # test routes the gamma = 1e6 instances to FP64 at factor time and keeps
+    # the gamma = 10 ones in FP32
+    return synth.grid_like(3000, nb=8, seed=610, gammas=(10.0, 1e6), dx_exp=2.0)
 
 
 def test_fp64_counts_cover_every_iteration_on_fp64_solver():
@@ -34,6 +35,7 @@ def test_mixed_counts_split_by_fallback():
     assert s.factor_batch(b)[0] == 0
     rc, x, y, infos = s.solve(b.r1, b.r2)
     assert any(i["fp64_fallback"] for i in infos), "workload meant to route some instances to FP64"
+    assert not all(i["fp64_fallback"] for i in infos), "workload meant to keep some instances in FP32"
     for i in infos:
         assert 0 <= i["cg_iters_fp64"] <= i["cg_iters"] and 0 <= i["passes_fp64"] <= i["passes"], i
         if not i["fp64_fallback"]:
