@@ -279,6 +279,8 @@ def big_front_flops(sym, lds_rows):
 def solver_options(args):
     """Options every benchmark mode passes to its solvers (the headline's)."""
     extra = {} if args.mixed_pivot_tol is None else {"mixed_pivot_tol": args.mixed_pivot_tol}
+    if args.cg_tol is not None:
+        extra["cg_tol"] = args.cg_tol
     return dict(kkt_tol=1e-10, scaling=args.scaling, refine_inexact=args.refine_inexact,
                 mixed_check=args.mixed_check, **extra)
 
@@ -638,6 +640,8 @@ def main():
                          "refinement")
     ap.add_argument("--mixed-pivot-tol", type=float, default=None,
                     help="FP32 pivot test threshold (library default 2^-12)")
+    ap.add_argument("--cg-tol", type=float, default=None,
+                    help="CG tolerance of the first hybrid pass (library default 1e-12)")
     ap.add_argument("--refine-inexact", type=int, default=1,
                     help="1 (default): refinement passes after the first stop CG at the accuracy the correction "
                          "needs; 0: every pass at the CG tolerance")
