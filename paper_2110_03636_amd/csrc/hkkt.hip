@@ -738,6 +738,12 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                     cols = std::max(cols, c1 - c0);
                 }
                 if (rows <= 0 || cols <= 0) return;
+                if (!strip) {   // the trailing matrix: 128 x 128 tiles
+                    const int nt = (rows + kUpdTile - 1) / kUpdTile;
+                    LAUNCH(2, k_big_update2<T>, dim3(nt * nt, cnt, nb), dim3(kUpdThreads), 0, st, D.v, fr, ka, R, nt,
+                           L, CB, active);
+                    return;
+                }
                 const int nti = (rows + kTile - 1) / kTile, ntj = (cols + kTile - 1) / kTile;
                 LAUNCH(2, k_big_update<T>, dim3(nti * ntj, cnt, nb), dim3(kBlock), 0, st, D.v, fr, ka, R, strip, nti,
                        L, CB, active);
@@ -749,11 +755,8 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                     int maxrows = 0;
                     for (int q = 0; q < cnt; q++)
                         maxrows = std::max(maxrows, nrw[q].first - kb - std::min(kNB, nrw[q].second - kb));
-                    LAUNCH(2, k_big_potrf<T>, dim3(1, cnt, nb), dim3(kWave), 0, st, D.v, fr, kb, L, CB,
-                           B.fail.as<int>(), active);
-                    if (maxrows <= 0) continue;
-                    LAUNCH(2, k_big_trsm<T>, dim3((maxrows + kBlock - 1) / kBlock, cnt, nb), dim3(kBlock), 0, st, D.v,
-                           fr, kb, L, CB, active);
+                    LAUNCH(2, k_big_ptrsm<T>, dim3(std::max(1, (maxrows + kBlock - 1) / kBlock), cnt, nb),
+                           dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(), active);
                 }
                 update(K, kUpdBlock, 0);
             }

@@ -485,12 +485,13 @@ struct FrontRef {
 //   k_big_zero    clear the fronts' contribution blocks
 //   k_big_extend  add the children's contribution blocks (one child rank per
 //                 launch, so two children never write one front at once)
-//   k_big_potrf   Cholesky of the NB x NB diagonal block (one wavefront)
-//   k_big_trsm    L21 = A21 L11^{-T}, one thread per row
+//   k_big_ptrsm   Cholesky of the NB x NB diagonal block (one wavefront)
+//                 and L21 = A21 L11^{-T}, one thread per row
 //   k_big_update  SYRK/GEMM C -= L21 L21^T on 64 x 64 lower tiles, rank up to
 //                 128: inside a 128-column block each panel first takes the
 //                 block's earlier panels (left-looking strip), then one
-//                 trailing update per block (right-looking)
+//                 trailing update per block (right-looking, k_big_update2 on
+//                 128 x 128 tiles)
 //                 with MFMA (v_mfma_*_16x16x4: A[i][k] in lane i+16k,
 //                 B[k][j] in lane j+16k; D[i][j] in lane j+16q, register r
 //                 with i = 4q+r for f32 and i = q+4r for f64, as measured)
@@ -547,62 +548,61 @@ __global__ __launch_bounds__(kBlock) void k_big_extend(SymView S, const i32* __r
     }
 }
 
-// Cholesky of the NB x NB diagonal block by one wavefront: lane i holds row
-// i in registers; column k is scaled and its values broadcast with
-// v_readlane (uniform lane index), no LDS and no barriers.
+// POTRF and TRSM of one 32-column panel in one launch. Every work-group
+// factors the NB x NB diagonal block in its first wavefront: lane i holds
+// row i in registers, column k is scaled and its values broadcast with
+// v_readlane (uniform lane index), no LDS and no barriers. It shares the
+// factored block through LDS and solves L21 = A21 L11^{-T} for its rows
+// below, one thread per row; work-group 0 also stores the factored block
+// and reports a failed pivot. The block is factored redundantly per
+// work-group (a few microseconds of one wavefront) instead of by a launch
+// of its own, identically in each (the same operations on the same values).
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_big_potrf(SymView S, const i32* __restrict__ fronts, int kb,
-                                                     T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
-                                                     const int* active) {
-    const int b = blockIdx.z;
-    if (active && !active[b]) return;
-    const i32 s = fronts[blockIdx.y];
-    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
-    const int bw = min(kNB, F.w - kb);
-    const int i = threadIdx.x;
-    T r[kNB];
-#pragma unroll
-    for (int j = 0; j < kNB; j++) r[j] = (i < bw && j <= i) ? F.P[(i64)(kb + j) * F.nr + kb + i] : T(0);
-    const i32 f = S.sn_first[s];
-#pragma unroll
-    for (int k = 0; k < kNB; k++) {
-        if (k < bw) {
-            const T d = lane_read(r[k], k);
-            if (i == 0 && !pivot_ok(d)) atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + kb + k);
-            const T sq = sqrt(d), inv = T(1) / sq;
-            r[k] = i == k ? sq : (i > k ? r[k] * inv : r[k]);
-#pragma unroll
-            for (int j = k + 1; j < kNB; j++) {
-                if (j < bw) {
-                    const T ljk = lane_read(r[k], j);
-                    if (i >= j) r[j] -= r[k] * ljk;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kNB; j++)
-        if (i < bw && j <= i) F.P[(i64)(kb + j) * F.nr + kb + i] = r[j];
-}
-
-// rows below the diagonal block: x L11^T = a  (one thread per row)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_big_trsm(SymView S, const i32* __restrict__ fronts, int kb,
-                                                     T* __restrict__ L, T* __restrict__ CB, const int* active) {
+__global__ __launch_bounds__(kBlock) void k_big_ptrsm(SymView S, const i32* __restrict__ fronts, int kb,
+                                                      T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
+                                                      const int* active) {
     __shared__ T D[kNB][kNB + 1];
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     const i32 s = fronts[blockIdx.y];
     const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
     const int bw = min(kNB, F.w - kb);
-    const int row = kb + bw + blockIdx.x * blockDim.x + threadIdx.x;
-    if (kb + bw + (int)(blockIdx.x * blockDim.x) >= F.nr) return;   // whole block past the front
-    for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
-        const int j = idx / bw, i = idx - j * bw;
-        D[j][i] = F.P[(i64)(kb + j) * F.nr + kb + i];
+    if (bw <= 0) return;
+    const bool rows_here = kb + bw + (int)(blockIdx.x * blockDim.x) < F.nr;
+    if (blockIdx.x > 0 && !rows_here) return;   // whole block past the front
+    if (threadIdx.x < kWave) {
+        const int i = threadIdx.x;
+        T r[kNB];
+#pragma unroll
+        for (int j = 0; j < kNB; j++) r[j] = (i < bw && j <= i) ? F.P[(i64)(kb + j) * F.nr + kb + i] : T(0);
+        const i32 f = S.sn_first[s];
+#pragma unroll
+        for (int k = 0; k < kNB; k++) {
+            if (k < bw) {
+                const T d = lane_read(r[k], k);
+                if (i == 0 && blockIdx.x == 0 && !pivot_ok(d))
+                    atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + kb + k);
+                const T sq = sqrt(d), inv = T(1) / sq;
+                r[k] = i == k ? sq : (i > k ? r[k] * inv : r[k]);
+#pragma unroll
+                for (int j = k + 1; j < kNB; j++) {
+                    if (j < bw) {
+                        const T ljk = lane_read(r[k], j);
+                        if (i >= j) r[j] -= r[k] * ljk;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kNB; j++)
+            if (i < bw && j <= i) {
+                D[j][i] = r[j];
+                if (blockIdx.x == 0) F.P[(i64)(kb + j) * F.nr + kb + i] = r[j];
+            }
     }
     __syncthreads();
-    if (row >= F.nr) return;
+    const int row = kb + bw + blockIdx.x * blockDim.x + threadIdx.x;
+    if (!rows_here || row >= F.nr) return;
     T x[kNB];
 #pragma unroll
     for (int k = 0; k < kNB; k++) x[k] = k < bw ? F.P[(i64)(kb + k) * F.nr + row] : T(0);
@@ -709,6 +709,110 @@ __global__ __launch_bounds__(kBlock) void k_big_update(SymView S, const i32* __r
                 const int i = i0 + qi + 16 * a + MfmaT<T>::row(lane, r);
                 const int j = j0 + qj + 16 * c + (lane & 15);
                 if (i < F.nr && j < c1 && i >= j) F.at(i, j) -= acc[a][c][r];
+            }
+}
+
+// The trailing update of a 128-column block (strip = 0 above) on 128 x 128
+// tiles: eight wavefronts, each a 64 x 32 part as 4 x 2 MFMA blocks (an
+// operand value read from LDS feeds two or four MFMAs), and the R columns
+// stream through two LDS buffers of KC columns: the loads of chunk c + 1 are
+// in flight while chunk c is multiplied, one barrier per chunk. Tile (ti,
+// tj) from blockIdx.x = tj * nti + ti, ti >= tj; targets rows c0..nr-1,
+// columns c0..nr-1 (lower part).
+constexpr int kUpdTile = 128;
+constexpr int kUpdThreads = 512;
+template <typename T>
+__host__ __device__ constexpr int upd2_kc() {
+    return sizeof(T) == 4 ? 16 : 8;    // 18 KiB of LDS per buffer either way (37 KiB in all)
+}
+constexpr int kUpdPad = 16;            // row stride kUpdTile + 16: the four k rows of a read hit distinct banks
+
+template <typename T>
+__global__ __launch_bounds__(kUpdThreads) void k_big_update2(SymView S, const i32* __restrict__ fronts, int ka,
+                                                             int R, int nti, T* __restrict__ L, T* __restrict__ CB,
+                                                             const int* active) {
+    constexpr int KC = upd2_kc<T>();
+    constexpr int LD = kUpdTile + kUpdPad;
+    constexpr int NE = 2 * kUpdTile * KC / kUpdThreads;   // elements each thread stages per chunk (both operands)
+    __shared__ T buf[2][2][KC][LD];                       // [buffer][operand i / j][k][row]
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const i32 s = fronts[blockIdx.y];
+    const FrontRef<T> F = front_of<T>(S, s, b, L, CB);
+    const int rf = min(R, F.w - ka);
+    if (rf <= 0) return;
+    const int c0 = ka + rf;
+    if (F.nr <= c0) return;
+    const int tj = blockIdx.x / nti, ti = blockIdx.x - tj * nti;
+    if (ti < tj) return;
+    const int i0 = c0 + ti * kUpdTile, j0 = c0 + tj * kUpdTile;
+    if (i0 >= F.nr) return;
+    typedef typename MfmaT<T>::v4 v4;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int qi = (wv >> 2) * 64, qj = (wv & 3) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    v4 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 2; c++) acc[a][c] = v4{T(0), T(0), T(0), T(0)};
+    // staging: element e of a thread is operand (e & 1) [i / j], flat index
+    // f = (e >> 1) * kUpdThreads + threadIdx.x of the operand's KC x 128
+    // block (k = f / 128, row = f % 128): consecutive threads read
+    // consecutive rows of one column (coalesced)
+    T st[NE];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int e = 0; e < NE; e++) {
+            const int f = (e >> 1) * kUpdThreads + threadIdx.x;
+            const int k = f / kUpdTile, r = f - k * kUpdTile;
+            const int row = ((e & 1) ? j0 : i0) + r;
+            const bool ok = kc + k < rf && row < F.nr;
+            const i64 at = (i64)(ka + kc + min(k, rf - 1 - kc)) * F.nr + min(row, F.nr - 1);
+            const T v = F.P[at];
+            st[e] = ok ? v : T(0);
+        }
+    };
+    auto stage = [&](int q) {
+#pragma unroll
+        for (int e = 0; e < NE; e++) {
+            const int f = (e >> 1) * kUpdThreads + threadIdx.x;
+            const int k = f / kUpdTile, r = f - k * kUpdTile;
+            buf[q][e & 1][k][r] = st[e];
+        }
+    };
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int q = 0;
+    for (int kc = 0; kc < rf; kc += KC) {
+        const bool more = kc + KC < rf;
+        if (more) fetch(kc + KC);
+#pragma unroll
+        for (int k4 = 0; k4 < KC; k4 += 4) {
+            T av[4], bv[2];
+#pragma unroll
+            for (int a = 0; a < 4; a++) av[a] = buf[q][0][k4 + lk][qi + 16 * a + li];
+#pragma unroll
+            for (int c = 0; c < 2; c++) bv[c] = buf[q][1][k4 + lk][qj + 16 * c + li];
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) acc[a][c] = MfmaT<T>::mma(av[a], bv[c], acc[a][c]);
+        }
+        if (more) stage(q ^ 1);
+        __syncthreads();   // the other buffer is staged; this one is free again
+        q ^= 1;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = i0 + qi + 16 * a + MfmaT<T>::row(lane, r);
+                const int j = j0 + qj + 16 * c + li;
+                if (i < F.nr && i >= j) F.at(i, j) -= acc[a][c][r];
             }
 }
 
