@@ -354,13 +354,17 @@ def uneven_group(args):
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
     ok = sum(1 for i in infos if i["status"] == 0 and i["rr"] <= 1e-10)
+    statuses = {}
+    for i in infos:
+        statuses[str(i["status"])] = statuses.get(str(i["status"]), 0) + 1
     st_ = s.stats()
     print(json.dumps({"workload": f"{g.G} dense-like systems in one group, n_x log-uniform in [2000, {args.uneven_hi}] "
                                   f"(min {min(b.pattern.n_x for b in mem)}, max {max(b.pattern.n_x for b in mem)}, "
                                   f"total {g.n_x}), mixed precision, target RR<=1e-10",
                       "analyze_s": round(t_an, 2), "factor_s": round(t_f, 3), "solve_s": round(t_s, 3),
-                      "solves_per_s": round(ok / (t_f + t_s), 3), "converged": f"{ok}/{g.G}",
-                      "max_rr": max(i["rr"] for i in infos), "fp64_fallbacks": sum(i["fp64_fallback"] for i in infos),
+                      "solves_per_s": round(ok / (t_f + t_s), 3), "converged": f"{ok}/{g.G}", "status_counts": statuses,
+                      "max_rr": float(np.nanmax([i["rr"] for i in infos])) if ok else None,
+                      "fp64_fallbacks": sum(i["fp64_fallback"] for i in infos),
                       "cg_iters_max": max(i["cg_iters"] for i in infos), "passes_max": max(i["passes"] for i in infos),
                       "symbolic": {k: st_[k] for k in ("nnz_L", "L_storage", "cb_entries", "max_width", "levels")}}))
 

@@ -574,6 +574,7 @@ struct Batch {
     bool scaled = false;
     // factor (Dinv: reciprocals of the diagonal of L, per column)
     DBuf L, fail, Dinv;
+    DBuf pcnt;   // per (instance, large front of a level): panel counters of k_big_ptrsm
     // solve workspace
     DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
@@ -756,7 +757,7 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                     for (int q = 0; q < cnt; q++)
                         maxrows = std::max(maxrows, nrw[q].first - kb - std::min(kNB, nrw[q].second - kb));
                     LAUNCH(2, k_big_ptrsm<T>, dim3(std::max(1, (maxrows + kBlock - 1) / kBlock), cnt, nb),
-                           dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(), active);
+                           dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(), B.pcnt.as<int>(), active);
                 }
                 update(K, kUpdBlock, 0);
             }
@@ -1127,6 +1128,16 @@ static void alloc_factor(hkkt_ctx* c, Batch& B) {
     B.L.ensure((size_t)B.nb * std::max<i64>(1, S.Lsize) * B.esz());
     B.Dinv.ensure((size_t)B.nb * S.n * B.esz());
     c->cbws.ensure((size_t)B.nb * std::max<i64>(1, S.CBsize) * B.esz());
+    // panel counters of k_big_ptrsm, one per (instance, large front of a
+    // level); zero when allocated, and every launch leaves them at zero
+    const DevSym::FrontSplit& F = c->dev.fs[B.esz() == 8 ? 1 : 0];
+    i32 mx = 1;
+    for (size_t l = 0; l + 1 < F.big_ptr.size(); l++) mx = std::max(mx, F.big_ptr[l + 1] - F.big_ptr[l]);
+    const size_t need = (size_t)B.nb * mx * 4;
+    if (B.pcnt.bytes < need || !B.pcnt.p) {
+        B.pcnt.ensure(need);
+        HIPCHK(hipMemsetAsync(B.pcnt.p, 0, B.pcnt.bytes, B.stream));
+    }
 }
 
 static void alloc_solve(hkkt_ctx* c, Batch& B) {

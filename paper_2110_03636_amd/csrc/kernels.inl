@@ -553,15 +553,21 @@ __global__ __launch_bounds__(kBlock) void k_big_extend(SymView S, const i32* __r
 // row i in registers, column k is scaled and its values broadcast with
 // v_readlane (uniform lane index), no LDS and no barriers. It shares the
 // factored block through LDS and solves L21 = A21 L11^{-T} for its rows
-// below, one thread per row; work-group 0 also stores the factored block
-// and reports a failed pivot. The block is factored redundantly per
+// below, one thread per row. The block is factored redundantly per
 // work-group (a few microseconds of one wavefront) instead of by a launch
 // of its own, identically in each (the same operations on the same values).
+// Every work-group of a (front, instance) reads the unfactored block, so
+// the factored one is stored by the last of them to finish: each counts
+// itself in cnt[(instance, front slot)] after its reads have been consumed
+// (its own stores done and fenced), and the one that completes the count
+// stores the block and resets the counter to zero for the next panel.
+// Work-group 0 reports a failed pivot.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_big_ptrsm(SymView S, const i32* __restrict__ fronts, int kb,
                                                       T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
-                                                      const int* active) {
+                                                      int* __restrict__ cnt, const int* active) {
     __shared__ T D[kNB][kNB + 1];
+    __shared__ int last;
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     const i32 s = fronts[blockIdx.y];
@@ -570,6 +576,10 @@ __global__ __launch_bounds__(kBlock) void k_big_ptrsm(SymView S, const i32* __re
     if (bw <= 0) return;
     const bool rows_here = kb + bw + (int)(blockIdx.x * blockDim.x) < F.nr;
     if (blockIdx.x > 0 && !rows_here) return;   // whole block past the front
+    // work-groups of this (front, instance) that read the block: x = 0 and
+    // every x with rows below
+    const int below = F.nr - kb - bw;
+    const int nwg = below > 0 ? (below + (int)blockDim.x - 1) / (int)blockDim.x : 1;
     if (threadIdx.x < kWave) {
         const int i = threadIdx.x;
         T r[kNB];
@@ -595,30 +605,45 @@ __global__ __launch_bounds__(kBlock) void k_big_ptrsm(SymView S, const i32* __re
         }
 #pragma unroll
         for (int j = 0; j < kNB; j++)
-            if (i < bw && j <= i) {
-                D[j][i] = r[j];
-                if (blockIdx.x == 0) F.P[(i64)(kb + j) * F.nr + kb + i] = r[j];
-            }
+            if (i < bw && j <= i) D[j][i] = r[j];
     }
     __syncthreads();
     const int row = kb + bw + blockIdx.x * blockDim.x + threadIdx.x;
-    if (!rows_here || row >= F.nr) return;
-    T x[kNB];
+    if (rows_here && row < F.nr) {
+        T x[kNB];
 #pragma unroll
-    for (int k = 0; k < kNB; k++) x[k] = k < bw ? F.P[(i64)(kb + k) * F.nr + row] : T(0);
+        for (int k = 0; k < kNB; k++) x[k] = k < bw ? F.P[(i64)(kb + k) * F.nr + row] : T(0);
 #pragma unroll
-    for (int k = 0; k < kNB; k++) {
-        if (k < bw) {
-            T a = x[k];
+        for (int k = 0; k < kNB; k++) {
+            if (k < bw) {
+                T a = x[k];
 #pragma unroll
-            for (int m = 0; m < kNB; m++)
-                if (m < k) a -= x[m] * D[m][k];
-            x[k] = a / D[k][k];
+                for (int m = 0; m < kNB; m++)
+                    if (m < k) a -= x[m] * D[m][k];
+                x[k] = a / D[k][k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kNB; k++)
+            if (k < bw) F.P[(i64)(kb + k) * F.nr + row] = x[k];
+    }
+    // the last work-group of this (front, instance) stores the factored block
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int* c = cnt + (i64)blockIdx.z * gridDim.y + blockIdx.y;
+        const int done = atomicAdd(c, 1) + 1;
+        last = done == nwg;
+        if (last) atomicExch(c, 0);
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
+            const int j = idx / bw, i = idx - j * bw;
+            if (j <= i) F.P[(i64)(kb + j) * F.nr + kb + i] = D[j][i];
         }
     }
-#pragma unroll
-    for (int k = 0; k < kNB; k++)
-        if (k < bw) F.P[(i64)(kb + k) * F.nr + row] = x[k];
 }
 
 template <typename T>

@@ -145,3 +145,20 @@ def test_group_hsolve_per_member():
         sl = slice(g.x_off[k], g.x_off[k + 1])
         xo = o.hsolve(rhs[0, sl])
         assert np.linalg.norm(x[0, sl] - xo) <= 1e-6 * np.linalg.norm(xo), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_group_of_large_fronts_each_member_equals_oracle(precision):
+    """Members of 2.5k–6k dense-like variables: each has fronts of thousands
+    of rows (the blocked path: panel factorization launches with many
+    work-groups per front, several fronts per level and launch, 128 x 128
+    trailing updates). Every member's factor must succeed and its solution
+    meet the oracle's bar; in particular each panel's factored diagonal
+    block is stored only after every work-group of its front has read the
+    unfactored one."""
+    mem = synth.uneven_dense_like(nb=6, lo=2500, hi=6000, seed=5300)
+    assert max(b.pattern.n_x for b in mem) > 4000
+    g, s, (rc, st, fc), (rc2, x, y, infos) = _run(mem, precision)
+    assert rc == 0 and list(st) == [0] * g.G, (rc, list(st), list(fc))
+    assert s.stats()["max_width"] > 900
+    _check_members(mem, g, x, y, infos)
