@@ -245,8 +245,12 @@ constexpr int kTriWG = 7;
 // size class of a supernode for the triangular solves: rows decide the
 // wavefront class; supernodes wider than HKKT_TRI_WIDE columns (default
 // 1024) or taller than 1024 rows go to the work-group kernel
+// supernodes wider than 512 columns take the blocked multi-work-group
+// solves (class 7): one wavefront walking more columns than that is slower
+// (measured on dense-like systems up to 50k variables); HKKT_TRI_WIDE
+// overrides the width
 static int tri_class(int nr, int w) {
-    static const int wide = std::getenv("HKKT_TRI_WIDE") ? std::atoi(std::getenv("HKKT_TRI_WIDE")) : 1024;
+    static const int wide = std::getenv("HKKT_TRI_WIDE") ? std::atoi(std::getenv("HKKT_TRI_WIDE")) : 512;
     if (w > wide) return 7;
     if (nr <= 16) return 0;
     if (nr <= 32) return 1;

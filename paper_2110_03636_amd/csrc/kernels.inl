@@ -841,6 +841,29 @@ __global__ __launch_bounds__(kUpdThreads) void k_big_update2(SymView S, const i3
             }
 }
 
+// the bw x bw diagonal tile whose first entry is panel entry (r0, r0) into
+// D (leading dimension kTri), by a kBlock-thread work-group with every load
+// in flight before the LDS stores (bw <= kTri)
+template <typename T>
+__device__ __forceinline__ void load_tile(T* D, const T* __restrict__ Lb, i64 nr, int r0, int bw) {
+    constexpr int K = kTri * kTri / kBlock;
+    T v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int idx = min((int)threadIdx.x + k * kBlock, bw * bw - 1);
+        const int jj = idx / bw, ii = idx - jj * bw;
+        v[k] = Lb[(i64)(r0 + jj) * nr + r0 + ii];
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int idx = (int)threadIdx.x + k * kBlock;
+        if (idx < bw * bw) {
+            const int jj = idx / bw, ii = idx - jj * bw;
+            D[jj * kTri + ii] = v[k];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // supernodal triangular solves, one work-group per (supernode, instance) of a
 // level. Forward (L y = b), multifrontal form: each supernode gathers its
@@ -889,10 +912,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(SymView S, const i32* __restrict
     }
     for (int kb = 0; kb < w; kb += kTri) {
         const int bw = min(kTri, w - kb);
-        for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
-            const int jj = idx / bw, ii = idx - jj * bw;
-            D[jj * kTri + ii] = Lb[(i64)(kb + jj) * nr + kb + ii];
-        }
+        load_tile(D, Lb, nr, kb, bw);
         __syncthreads();
         if (threadIdx.x < kWave) {
             const int lane = threadIdx.x;
@@ -955,10 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd(SymView S, const i32* __restrict
             sum = wave_sum(sum);
             if (lane == 0) U(j) -= sum;
         }
-        for (int idx = threadIdx.x; idx < bw * bw; idx += blockDim.x) {
-            const int jj = idx / bw, ii = idx - jj * bw;
-            D[jj * kTri + ii] = Lb[(i64)(kb + jj) * nr + kb + ii];
-        }
+        load_tile(D, Lb, nr, kb, bw);
         __syncthreads();
         if (threadIdx.x < kWave) {
             T val = lane < bw ? U(kb + lane) : T(0);
@@ -999,17 +1016,17 @@ constexpr int kWsR = 64;    // rows (forward) / columns (backward) per update wo
 
 static_assert(kWsB == kBlock, "the owner work-group holds one block row per thread");
 
-// sum_{j < n} col[j * ld] * v[j], eight independent loads in flight
+// sum_{j < n} col[j * ld] * v[j], sixteen independent loads in flight
 template <typename T>
 __device__ __forceinline__ T strided_dot(const T* __restrict__ col, i64 ld, const T* v, int n) {
     T sum = T(0);
     int j = 0;
-    for (; j + 8 <= n; j += 8) {
-        T l[8];
+    for (; j + 16 <= n; j += 16) {
+        T l[16];
 #pragma unroll
-        for (int u = 0; u < 8; u++) l[u] = col[(i64)(j + u) * ld];
+        for (int u = 0; u < 16; u++) l[u] = col[(i64)(j + u) * ld];
 #pragma unroll
-        for (int u = 0; u < 8; u++) sum += l[u] * v[j + u];
+        for (int u = 0; u < 16; u++) sum += l[u] * v[j + u];
     }
     for (; j < n; j++) sum += col[(i64)j * ld] * v[j];
     return sum;
@@ -1080,10 +1097,7 @@ __global__ __launch_bounds__(kBlock) void k_ws_fwd(SymView S, const TriDesc* __r
     __syncthreads();
     for (int kb = 0; kb < bw; kb += kTri) {
         const int tw = min(kTri, bw - kb);
-        for (int idx = t; idx < tw * tw; idx += blockDim.x) {
-            const int jj = idx / tw, ii = idx - jj * tw;
-            D[jj * kTri + ii] = Lb[(i64)(qb + kb + jj) * nr + qb + kb + ii];
-        }
+        load_tile(D, Lb, nr, qb + kb, tw);
         __syncthreads();
         if (wid == 0) {
             T v = lane < tw ? u[kb + lane] : T(0);
@@ -1117,10 +1131,25 @@ __global__ __launch_bounds__(kBlock) void k_ws_bwd_below(SymView S, const TriDes
     T* x = X + (i64)b * S.n;
     const i32* rows = S.sn_rows + d.rp;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    // eight row chunks of the wave in flight: their row indices, then the
+    // panel entries and the gathered x together
     for (int j = c0 + wid; j < min(c0 + kWsR, w); j += kBlock / kWave) {
         const T* col = Lb + (i64)j * nr;
         T sum = T(0);
-        for (int r = w + lane; r < nr; r += kWave) sum += col[r] * x[rows[r]];
+        for (int r0 = w + lane; r0 < nr; r0 += 8 * kWave) {
+            i32 ri[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) ri[k] = rows[min(r0 + k * kWave, nr - 1)];
+            T lv[8], xv[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                lv[k] = col[min(r0 + k * kWave, nr - 1)];
+                xv[k] = x[ri[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (r0 + k * kWave < nr) sum += lv[k] * xv[k];
+        }
         sum = wave_sum(sum);
         if (lane == 0) x[d.f + j] -= sum;
     }
@@ -1161,18 +1190,55 @@ __global__ __launch_bounds__(kBlock) void k_ws_bwd(SymView S, const TriDesc* __r
         for (int j = threadIdx.x; j < c_hi - c_lo; j += blockDim.x) u[j] = x[d.f + c_lo + j];
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    // columns j in [c_lo, c_hi): x_j -= sum_{i in [a, e)} L(i, j) x_i (one wave per column)
-    for (int j = c_lo + wid; apply && j < c_hi; j += kBlock / kWave) {
-        const T* col = Lb + (i64)j * nr + a;
-        T sum = T(0);
-        for (int i = lane; i < na; i += kWave) sum += col[i] * xs[i];
-        sum = wave_sum(sum);
-        if (lane == 0) {
-            if (owner) u[j - c_lo] -= sum;
-            else x[d.f + j] -= sum;
+    // columns j in [c_lo, c_hi): x_j -= sum_{i in [a, e)} L(i, j) x_i: the
+    // applied rows of a column are a contiguous run, loaded 16 at a time.
+    // The owner takes one thread per column (kWsB = threads); an update
+    // work-group (kWsR = 64 columns) one lane per column with the applied
+    // rows split in four quarters over the waves, the four partial sums
+    // added in LDS
+    if (owner) {
+        const int j = c_lo + (int)threadIdx.x;
+        if (apply && j < c_hi) {
+            const T* col = Lb + (i64)j * nr + a;
+            T sum = T(0);
+            for (int i0 = 0; i0 < na; i0 += 16) {
+                T l[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) l[k] = col[min(i0 + k, na - 1)];
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (i0 + k < na) sum += l[k] * xs[i0 + k];
+            }
+            u[j - c_lo] -= sum;
         }
+    } else {
+        __shared__ T part[kBlock / kWave][kWave];
+        static_assert(kWsR == kWave, "an update work-group holds one column per lane");
+        const int j = c_lo + lane;
+        const int per = (na + (kBlock / kWave) - 1) / (kBlock / kWave);
+        const int i_lo = min(wid * per, na), i_hi = min(i_lo + per, na);
+        T sum = T(0);
+        if (j < c_hi) {
+            const T* col = Lb + (i64)j * nr + a;
+            for (int i0 = i_lo; i0 < i_hi; i0 += 16) {
+                T l[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) l[k] = col[min(i0 + k, i_hi - 1)];
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (i0 + k < i_hi) sum += l[k] * xs[i0 + k];
+            }
+        }
+        part[wid][lane] = sum;
+        __syncthreads();
+        if (wid == 0 && j < c_hi) {
+            T t = part[0][lane];
+#pragma unroll
+            for (int k = 1; k < kBlock / kWave; k++) t += part[k][lane];
+            x[d.f + j] -= t;
+        }
+        return;
     }
-    if (!owner) return;
     __syncthreads();
     // owner: transposed solve of block q, last 64-column tile first
     const int bw = c_hi - c_lo;
@@ -1180,10 +1246,7 @@ __global__ __launch_bounds__(kBlock) void k_ws_bwd(SymView S, const TriDesc* __r
     for (int ti = ntile - 1; ti >= 0; ti--) {
         const int kb = ti * kTri;
         const int tw = min(kTri, bw - kb);
-        for (int idx = threadIdx.x; idx < tw * tw; idx += blockDim.x) {
-            const int jj = idx / tw, ii = idx - jj * tw;
-            D[jj * kTri + ii] = Lb[(i64)(qb + kb + jj) * nr + qb + kb + ii];
-        }
+        load_tile(D, Lb, nr, qb + kb, tw);
         __syncthreads();
         if (wid == 0) {
             T v = lane < tw ? u[kb + lane] : T(0);
@@ -1195,12 +1258,21 @@ __global__ __launch_bounds__(kBlock) void k_ws_bwd(SymView S, const TriDesc* __r
             if (lane < tw) u[kb + lane] = v;
         }
         __syncthreads();
-        // earlier columns of the block: u_j -= sum_{i in tile} L(qb+kb+i, qb+j) u_{kb+i}
-        for (int j = wid; j < kb; j += kBlock / kWave) {
-            const T* col = Lb + (i64)(qb + j) * nr + qb + kb;
-            T sum = lane < tw ? col[lane] * u[kb + lane] : T(0);
-            sum = wave_sum(sum);
-            if (lane == 0) u[j] -= sum;
+        // earlier columns of the block: u_j -= sum_{i in tile} L(qb+kb+i, qb+j)
+        // u_{kb+i}, one thread per column j < kb (kb < kWsB = threads): the
+        // tile's rows of a column are contiguous, loaded 16 at a time
+        if ((int)threadIdx.x < kb) {
+            const T* col = Lb + (i64)(qb + threadIdx.x) * nr + qb + kb;
+            T sum = T(0);
+            for (int i0 = 0; i0 < tw; i0 += 16) {
+                T l[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) l[k] = col[min(i0 + k, tw - 1)];
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    if (i0 + k < tw) sum += l[k] * u[kb + i0 + k];
+            }
+            u[threadIdx.x] -= sum;
         }
         __syncthreads();
     }
