@@ -399,8 +399,8 @@ def large_single(args):
         s.factor(H, dxs[k], J, b.delta, b.gamma)
         rc, x, y, infos = s.solve(R1, R2)
         res.append(infos[0])
-        print(f"large: cycle {k} rr={infos[0]['rr']:.2e} cg={infos[0]['cg_iters']} fb={infos[0]['fp64_fallback']}",
-              file=sys.stderr, flush=True)
+        print(f"large: cycle {k} rr={infos[0]['rr']:.2e} floor={infos[0]['floor']:.2e} cg={infos[0]['cg_iters']} "
+              f"passes={infos[0]['passes']} fb={infos[0]['fp64_fallback']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ok = sum(1 for i in res if i["status"] == 0 and i["rr"] <= 1e-10)
@@ -410,6 +410,8 @@ def large_single(args):
                       "analyze_s": round(t_an, 2), "autotuned": {"relax": tune["relax"], "tree_width": tune["tree_width"], "tree_staged": tune["tree_staged"]},
                       "sustained_solves_per_s": round(ok / el, 3), "s_per_cycle": round(el / args.cycles, 3),
                       "converged": f"{ok}/{args.cycles}", "max_rr": max(i["rr"] for i in res),
+                      "not_converged": [{"cycle": k, "rr": i["rr"], "floor": i["floor"], "status": i["status"]}
+                                        for k, i in enumerate(res) if not (i["status"] == 0 and i["rr"] <= 1e-10)],
                       "fp64_fallbacks": sum(i["fp64_fallback"] for i in res),
                       "cg_iters_mean": round(float(np.mean([i["cg_iters"] for i in res])), 1),
                       "symbolic": {k: st[k] for k in ("nnz_L", "L_storage", "levels", "max_width")}}))

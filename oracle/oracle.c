@@ -571,8 +571,7 @@ typedef struct {
  * the first needs its correction only as accurately as it takes RR below
  * kkt_tol with a tenfold margin, so its CG stops at the relative residual
  * max(cg_tol, min(1e-2, 0.1 * kkt_tol / RR)) with RR that of the current
- * iterate. A loosened pass that does not halve RR does not end refinement:
- * the passes after it run at cg_tol (the solve loops). */
+ * iterate. */
 static orc_opts pass_opts(const orc_opts *o, i64 pass, double rr) {
     orc_opts q = *o;
     if (o->inexact && pass > 0 && rr > 0.0) {
@@ -674,11 +673,9 @@ int orc_solve(orc *s, const orc_opts *o, const double *r1, const double *r2, dou
     int brk_any = 0;
     double rr = rn > 0 ? 1.0 : 0.0, rr_best = INFINITY;
     i64 pass = 0;
-    int tight = 0;   /* after a loosened pass that did not halve RR: every pass at the CG tolerance */
     while (pass <= max_ref) {
         int brk = 0;
-        const orc_opts po = tight ? *o : pass_opts(o, pass, rr);
-        const int loose = po.cg_tol > o->cg_tol;
+        const orc_opts po = pass_opts(o, pass, rr);
         i64 it = hybrid_pass(s, &po, g1, g2, ex, ey, &brk);
         brk_any |= brk;
         for (i64 j = 0; j < n; j++) x[j] += ex[j];
@@ -691,13 +688,8 @@ int orc_solve(orc *s, const orc_opts *o, const double *r1, const double *r2, dou
         if (rr <= o->kkt_tol || brk) break;
         /* a later pass that does not halve RR: z is as close to the exact
          * solution as FP64 entries allow (the residual of the rounded
-         * solution is of the order of the floor), unless that pass stopped
-         * CG early (inexact refinement): then the passes go on at the CG
-         * tolerance and only such a pass can end refinement */
-        if (pass >= 2 && !(rr < 0.5 * rr_best)) {
-            if (!loose) break;
-            tight = 1;
-        }
+         * solution is of the order of the floor) */
+        if (pass >= 2 && !(rr < 0.5 * rr_best)) break;
         if (rr < rr_best) rr_best = rr;
     }
     rep->passes = pass;
@@ -920,11 +912,9 @@ int orc_solve_scaled(orc *s, const orc_opts *o, const double *d, const i32 *perm
     int brk_any = 0;
     double rr = rn > 0 ? 1.0 : 0.0, rr_best = INFINITY;
     i64 pass = 0;
-    int tight = 0;   /* as in orc_solve */
     while (pass <= max_ref) {
         int brk = 0;
-        const orc_opts po = tight ? *o : pass_opts(o, pass, rr);
-        const int loose = po.cg_tol > o->cg_tol;
+        const orc_opts po = pass_opts(o, pass, rr);
         i64 it = hybrid_pass(t, &po, g1, g2, ex, ey, &brk);
         brk_any |= brk;
         for (i64 j = 0; j < n; j++) x[j] += d[j] * ex[j];
@@ -937,10 +927,7 @@ int orc_solve_scaled(orc *s, const orc_opts *o, const double *d, const i32 *perm
         rep->rr_hist[pass] = rr;
         pass++;
         if (rr <= o->kkt_tol || brk) break;
-        if (pass >= 2 && !(rr < 0.5 * rr_best)) {
-            if (!loose) break;
-            tight = 1;
-        }
+        if (pass >= 2 && !(rr < 0.5 * rr_best)) break;
         if (rr < rr_best) rr_best = rr;
     }
     rep->passes = pass;

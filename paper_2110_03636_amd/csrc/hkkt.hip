@@ -1471,7 +1471,6 @@ struct InstState {
     int status = HKKT_NOT_CONVERGED;
     int cg = 0, passes = 0, brk = 0;
     int cg64 = 0, passes64 = 0;   // of cg and passes, those run on an FP64 factor
-    bool tight = false;           // inexact refinement: a loosened pass stalled, every pass at the CG tolerance
     double rr = INFINITY, rr_prev = INFINITY, rnorm = 0.0;
     bool fallback = false;
 };
@@ -1525,15 +1524,13 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
         // paper's CG tolerance) a pass needs its correction only to the
         // accuracy that takes RR below kkt_tol with a tenfold margin
         const double* ptol = nullptr;
-        std::vector<double> tl;
         if ((pass > 0 || warm) && o.refine_inexact) {
-            tl.assign(nc, cg_tol);
+            std::vector<double> tl(nc, cg_tol);
             for (int i = 0; i < nc; i++)
-                if (act[i] && is[i].rr > 0.0 && !is[i].tight)
-                    tl[i] = std::max(cg_tol, std::min(1e-2, 0.1 * o.kkt_tol / is[i].rr));
+                if (act[i] && is[i].rr > 0.0) tl[i] = std::max(cg_tol, std::min(1e-2, 0.1 * o.kkt_tol / is[i].rr));
             B.ptol.ensure((size_t)nc * 8);
             HIPCHK(hipMemcpyAsync(B.ptol.p, tl.data(), (size_t)nc * 8, hipMemcpyHostToDevice, st));
-            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipStreamSynchronize(st));   // tl goes out of scope
             ptol = B.ptol.as<double>();
         }
         if (B.prec == HKKT_MIXED) hybrid_pass<float>(c, B, nids, max_cg, cg_tol, ptol, hst);
@@ -1563,13 +1560,6 @@ static void refine(hkkt_ctx* c, Batch& B, std::vector<InstState>& is, const std:
             } else if (rr <= o.kkt_tol) {
                 s.status = HKKT_OK;
                 act[i] = 0;
-            } else if (!tl.empty() && tl[i] > cg_tol && !(rr < 0.5 * s.rr_prev) &&
-                       (allow_stall_exit ? s.passes < 6 : s.passes >= 2)) {
-                // a loosened pass that did not halve RR may have stopped CG
-                // too early: the passes after it run at the CG tolerance, and
-                // only such a pass can count as a stall
-                s.tight = true;
-                s.status = HKKT_NOT_CONVERGED;
             } else if (allow_stall_exit && (!(rr < 0.5 * s.rr_prev) || s.passes >= 6)) {
                 s.fallback = true;
                 s.status = HKKT_NOT_CONVERGED;
