@@ -683,6 +683,16 @@ namespace hkkt {
 // ---------------------------------------------------------------------------
 // kernel launch helpers
 // ---------------------------------------------------------------------------
+// threads of an LDS-front work-group for a level whose largest front has nr
+// rows: a rank-1 step of a front touches at most nr^2 / 2 entries, so small
+// fronts keep one or two wavefronts busy and leave the CU's other slots to
+// more work-groups (HKKT_FRONT_WIDE=1: always kBlock)
+static int front_threads(int nr) {
+    static const bool wide = std::getenv("HKKT_FRONT_WIDE") && std::atoi(std::getenv("HKKT_FRONT_WIDE")) == 1;
+    if (wide) return kBlock;
+    return nr <= 32 ? kWave : nr <= 64 ? 2 * kWave : kBlock;
+}
+
 template <typename T>
 static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     const Symbolic& S = c->sym.S;
@@ -700,7 +710,7 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
         if (ns_small > 0) {
             const int nr = F.small_maxnr[l];
             const size_t lds = (size_t)nr * nr * sizeof(T);
-            LAUNCH(1, k_front_lds<T>, dim3(ns_small, nb), dim3(kBlock), lds, st, D.v,
+            LAUNCH(1, k_front_lds<T>, dim3(ns_small, nb), dim3(front_threads(nr)), lds, st, D.v,
                                F.lev_small.as<i32>() + F.small_ptr[l], L, CB, B.fail.as<int>(), active);
         }
         const int ns_big = F.big_ptr[l + 1] - F.big_ptr[l];
