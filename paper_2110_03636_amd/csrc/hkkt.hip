@@ -1127,12 +1127,12 @@ static void scale_values(hkkt_ctx* c, Batch& B) {
            0.0);
     const ValView V = B.vals();
     for (int it = 0; it < kRuizSweeps; it++) {
-        LAUNCH(10, k_ruiz_rows, dim3(grid1(nm, 1024), nb), dim3(kBlock), 0, st, D.v, V, (const double*)B.sc.as<double>(),
-               B.rm.as<double>());
+        LAUNCH(10, k_ruiz_rows, dim3(grid1(4 * nm, 4096), nb), dim3(kBlock), 0, st, D.v, V,
+               (const double*)B.sc.as<double>(), B.rm.as<double>());
         LAUNCH(10, k_ruiz_apply, dim3(grid1((i64)nb * nm)), dim3(kBlock), 0, st, (i64)nb * nm, B.sc.as<double>(),
                (const double*)B.rm.as<double>());
     }
-    LAUNCH(10, k_scale_vals, dim3(grid1(nm, 1024), nb), dim3(kBlock), 0, st, D.v, V, (const double*)B.sc.as<double>(),
+    LAUNCH(10, k_scale_vals, dim3(grid1(4 * nm, 4096), nb), dim3(kBlock), 0, st, D.v, V, (const double*)B.sc.as<double>(),
            B.Hs.as<double>(), B.Js.as<double>(), B.JTs.as<double>(), B.HFs.as<double>(), B.Dxps.as<double>(),
            B.Dxs.as<double>());
 }

@@ -106,31 +106,42 @@ __global__ void k_gather_vals(SymView S, const double* __restrict__ H, const dou
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_ruiz_rows(SymView S, ValView V, const double* __restrict__ sc,
                                                       double* __restrict__ rm) {
+    // four lanes per row, each taking every fourth entry of the row's runs
+    // (consecutive lanes read consecutive entries), then a max over the four
+    // lanes (and a sum for the diagonal, which one lane holds): the same
+    // products as one thread per row, so the same maxima
     const int b = blockIdx.y;
     const i64 nm = S.n + S.m;
     const double* d = sc + (i64)b * nm;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nm; i += (i64)gridDim.x * blockDim.x) {
+    const int l4 = threadIdx.x & 3;
+    const i64 step = ((i64)gridDim.x * blockDim.x) >> 2;
+    for (i64 i = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 2; i < nm; i += step) {
         double a = 0.0;
         if (i < S.n) {
             const double* HF = V.HF + (i64)b * S.nnzHF;
             const double* JT = V.JT + (i64)b * S.nnzJ;
             const int k = S.G > 1 ? S.xp_mem[i] : 0;
-            double dg = V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k];
+            double dg = l4 == 0 ? V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k] : 0.0;
             const double di = d[i];
-            for (i64 q = S.HF_rowptr[i]; q < S.HF_rowptr[i + 1]; q++) {
+            for (i64 q = S.HF_rowptr[i] + l4; q < S.HF_rowptr[i + 1]; q += 4) {
                 if (S.HF_col[q] == i) dg += HF[q];
                 else a = fmax(a, fabs(HF[q]) * di * d[S.HF_col[q]]);
             }
+            dg += __shfl_xor(dg, 1, 4);
+            dg += __shfl_xor(dg, 2, 4);
             a = fmax(a, fabs(dg) * di * di);
-            for (i64 q = S.JT_rowptr[i]; q < S.JT_rowptr[i + 1]; q++)
+            for (i64 q = S.JT_rowptr[i] + l4; q < S.JT_rowptr[i + 1]; q += 4)
                 a = fmax(a, fabs(JT[q]) * di * d[S.n + S.JT_col[q]]);
         } else {
             const double* J = V.J + (i64)b * S.nnzJ;
             const i64 r = i - S.n;
             const double dr = d[i];
-            for (i64 q = S.J_rowptr[r]; q < S.J_rowptr[r + 1]; q++) a = fmax(a, fabs(J[q]) * dr * d[S.J_colp[q]]);
+            for (i64 q = S.J_rowptr[r] + l4; q < S.J_rowptr[r + 1]; q += 4)
+                a = fmax(a, fabs(J[q]) * dr * d[S.J_colp[q]]);
         }
-        rm[(i64)b * nm + i] = a;
+        a = fmax(a, __shfl_xor(a, 1, 4));
+        a = fmax(a, __shfl_xor(a, 2, 4));
+        if (l4 == 0) rm[(i64)b * nm + i] = a;
     }
 }
 
@@ -148,27 +159,32 @@ __global__ __launch_bounds__(kBlock) void k_scale_vals(SymView S, ValView V, con
                                                        double* __restrict__ Hs, double* __restrict__ Js,
                                                        double* __restrict__ JTs, double* __restrict__ HFs,
                                                        double* __restrict__ Dxps, double* __restrict__ Dxs) {
+    // four lanes per row, every fourth entry each (as in k_ruiz_rows)
     const int b = blockIdx.y;
     const i64 nm = S.n + S.m;
     const double* d = sc + (i64)b * nm;
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nm; i += (i64)gridDim.x * blockDim.x) {
+    const int l4 = threadIdx.x & 3;
+    const i64 step = ((i64)gridDim.x * blockDim.x) >> 2;
+    for (i64 i = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 2; i < nm; i += step) {
         if (i < S.n) {
             const double di = d[i];
-            for (i64 q = S.HF_rowptr[i]; q < S.HF_rowptr[i + 1]; q++) {
+            for (i64 q = S.HF_rowptr[i] + l4; q < S.HF_rowptr[i + 1]; q += 4) {
                 const double v = V.HF[(i64)b * S.nnzHF + q] * di * d[S.HF_col[q]];
                 HFs[(i64)b * S.nnzHF + q] = v;
                 Hs[(i64)b * S.nnzH + S.HF_src[q]] = v;
             }
-            for (i64 q = S.JT_rowptr[i]; q < S.JT_rowptr[i + 1]; q++)
+            for (i64 q = S.JT_rowptr[i] + l4; q < S.JT_rowptr[i + 1]; q += 4)
                 JTs[(i64)b * S.nnzJ + q] = V.JT[(i64)b * S.nnzJ + q] * di * d[S.n + S.JT_col[q]];
-            const int k = S.G > 1 ? S.xp_mem[i] : 0;
-            const double v = di * di * (V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k]);
-            Dxps[(i64)b * S.n + i] = v;
-            Dxs[(i64)b * S.n + S.perm[i]] = v;
+            if (l4 == 0) {
+                const int k = S.G > 1 ? S.xp_mem[i] : 0;
+                const double v = di * di * (V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k]);
+                Dxps[(i64)b * S.n + i] = v;
+                Dxs[(i64)b * S.n + S.perm[i]] = v;
+            }
         } else {
             const i64 r = i - S.n;
             const double dr = d[i];
-            for (i64 q = S.J_rowptr[r]; q < S.J_rowptr[r + 1]; q++)
+            for (i64 q = S.J_rowptr[r] + l4; q < S.J_rowptr[r + 1]; q += 4)
                 Js[(i64)b * S.nnzJ + q] = V.J[(i64)b * S.nnzJ + q] * dr * d[S.J_colp[q]];
         }
     }
