@@ -476,7 +476,8 @@ def profile_hsolve(args):
     prec = args.profile_precision
     b = synth.grid_like(args.n, nb=args.nb, seed=4000, gammas=(1e4, 1e6), dx_exp=8.0)
     dev = lambda x: torch.as_tensor(x, device="cuda")
-    s = hkkt.Solver(precision=prec, device=True)
+    # the FP32 factor of every instance (no pivot test sending some to FP64)
+    s = hkkt.Solver(precision=prec, device=True, mixed_pivot_tol=0.0)
     s.analyze(b.pattern)
     sched = {"mixed": args.schedule_mixed, "fp64": args.schedule_fp64}[prec]
     if sched:

@@ -397,7 +397,10 @@ int hkkt_get_factor(hkkt_ctx *ctx, int b, int64_t *colptr, int32_t *rowind, doub
 
 /* Apply H_gamma^{-1} (forward + backward supernodal triangular solves) of
  * instance set [0, nb) to b, in the original order: x = H_gamma^{-1} b.
- * Vectors [nb][n_x], per pointer mode. For parity tests. */
+ * Vectors [nb][n_x], per pointer mode. For parity tests. In mixed precision
+ * the factor applied is the one the solve uses: FP32, or FP64 for the
+ * instances the factorization sent to FP64 factors (their FP32
+ * factorization stops at the first pivot below mixed_pivot_tol). */
 int hkkt_hsolve(hkkt_ctx *ctx, int nb, const double *b, double *x);
 
 /* Allocation-free form of hkkt_hsolve, for callers that cannot allocate
@@ -416,8 +419,10 @@ int hkkt_hsolve(hkkt_ctx *ctx, int nb, const double *b, double *x);
  * global-memory tree kernel (same solution up to rounding). Per-kernel
  * profiling is suspended during the call. Returns -1 for host pointer mode
  * or when 8*nb*n_x + (4 or 8)*nb*n_x (+ the update vectors) exceeds 64 MiB
- * (each part rounded up to 256 bytes), -3 if not factored or nb differs.
- * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * (each part rounded up to 256 bytes), -3 if not factored, nb differs, or
+ * (mixed precision) the factorization sent instances to FP64 factors: this
+ * form applies the FP32 factor only. Every call on one GPU shares that
+ * GPU's array: calls that overlap in time
  * on one GPU (other contexts or streams) race and must be serialised by the
  * caller; the array keeps the last call's contents, and every entry a call
  * reads is written by it first. */

@@ -579,6 +579,14 @@ struct Batch {
     // factor (Dinv: reciprocals of the diagonal of L, per column)
     DBuf L, fail, Dinv;
     DBuf pcnt;   // per (instance, large front of a level): panel counters of k_big_ptrsm
+    // FP32 factor read by the pivot test (mixed precision): the FP64
+    // diagonal of H_gamma per (instance, pivot); an instance whose pivot
+    // ratio falls below the test's threshold stops factoring in FP32 (its
+    // entry of active is cleared on the device; h_alive holds active after
+    // the factorization) and is refactored in FP64
+    bool early = false;
+    DBuf adiag;
+    std::vector<int> h_alive;
     // solve workspace
     DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
@@ -702,6 +710,12 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     const int nb = B.nb;
     T* L = B.L.as<T>();
     T* CB = c->cbws.as<T>();
+    const bool early = B.early && sizeof(T) == 4;
+    const double* adiag = early ? B.adiag.as<double>() : nullptr;
+    int* act_w = early ? B.active.as<int>() : nullptr;   // the array passed as active
+    const double ptol = c->opt.mixed_pivot_tol;
+    if (early)
+        LAUNCH(10, k_hg_diag, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, D.v, B.fvals(), B.adiag.as<double>());
     LAUNCH(10, k_fill<T>, dim3(grid1((i64)nb * S.Lsize)), dim3(kBlock), 0, st, L, (i64)nb * S.Lsize, T(0));
     LAUNCH(10, k_fill<int>, dim3(1), dim3(kBlock), 0, st, B.fail.as<int>(), (i64)nb * S.G, INT_MAX);
     LAUNCH(0, k_assemble<T>, dim3(grid1(S.nnzA, 4096), nb), dim3(kBlock), 0, st, D.v, B.fvals(), L, active);
@@ -711,7 +725,8 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
             const int nr = F.small_maxnr[l];
             const size_t lds = (size_t)nr * nr * sizeof(T);
             LAUNCH(1, k_front_lds<T>, dim3(ns_small, nb), dim3(front_threads(nr)), lds, st, D.v,
-                               F.lev_small.as<i32>() + F.small_ptr[l], L, CB, B.fail.as<int>(), active);
+                               F.lev_small.as<i32>() + F.small_ptr[l], L, CB, B.fail.as<int>(), active, adiag, ptol,
+                               act_w);
         }
         const int ns_big = F.big_ptr[l + 1] - F.big_ptr[l];
         if (ns_big > 0) {
@@ -771,7 +786,8 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                     for (int q = 0; q < cnt; q++)
                         maxrows = std::max(maxrows, nrw[q].first - kb - std::min(kNB, nrw[q].second - kb));
                     LAUNCH(2, k_big_ptrsm<T>, dim3(std::max(1, (maxrows + kBlock - 1) / kBlock), cnt, nb),
-                           dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(), B.pcnt.as<int>(), active);
+                           dim3(kBlock), 0, st, D.v, fr, kb, L, CB, B.fail.as<int>(), B.pcnt.as<int>(), active, adiag,
+                           ptol, act_w);
                 }
                 update(K, kUpdBlock, 0);
             }
@@ -1252,12 +1268,16 @@ static void factor_batch(hkkt_ctx* c, Batch& B, const std::vector<int>& active_h
     PrecScope ps(B.prec);
     hipStream_t st = B.stream;
     alloc_factor(c, B);
+    if (B.early) B.adiag.ensure((size_t)B.nb * c->sym.S.n * 8);
     HIPCHK(hipMemcpyAsync(B.active.p, active_h.data(), B.nb * 4, hipMemcpyHostToDevice, st));
     if (B.prec == HKKT_MIXED) launch_factor<float>(c, B, B.active.as<int>());
     else launch_factor<double>(c, B, B.active.as<int>());
     B.lt_lo = -1;   // the staged solves' panel copy is rebuilt from the new factor
     B.h_fail.assign((size_t)B.nb * c->sym.S.G, INT_MAX);
     HIPCHK(hipMemcpyAsync(B.h_fail.data(), B.fail.p, B.h_fail.size() * 4, hipMemcpyDeviceToHost, st));
+    B.h_alive.assign(B.nb, 1);
+    if (B.early && B.prec == HKKT_MIXED)
+        HIPCHK(hipMemcpyAsync(B.h_alive.data(), B.active.p, (size_t)B.nb * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
 }
 
@@ -2124,6 +2144,9 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
         alloc_values(c, c->main, nb);
         load_values(c, c->main, H, Dx, J, delta, gamma, nullptr, dev);
         std::vector<int> all(nb, 1);
+        // with the pivot test on, an instance stops factoring in FP32 at its
+        // first pivot below the threshold: it takes the FP64 factor anyway
+        c->main.early = c->opt.precision == HKKT_MIXED && c->opt.mixed_pivot_tol > 0;
         factor_batch(c, c->main, all);
         c->fstatus.assign(nc, HKKT_OK);
         c->ffail.assign(nc, -1);
@@ -2150,6 +2173,7 @@ int hkkt_factor_batch(hkkt_ctx* c, int nb, const double* H, const double* Dx, co
                     weak = weak || !(rho[i] <= c->opt.mixed_check_tol);
                     if (trace) std::fprintf(stderr, "hkkt: fp32 factor check inst=%zu rho=%.3e\n", i, rho[i]);
                 }
+                if (!c->main.h_alive[b]) weak = true;   // stopped at a pivot below the threshold
                 if (!piv.empty() && c->main.h_fail[i] == INT_MAX) {
                     weak = weak || !(piv[i] >= c->opt.mixed_pivot_tol);
                     if (trace) std::fprintf(stderr, "hkkt: fp32 pivot ratio inst=%zu min=%.3e\n", i, piv[i]);
@@ -2649,6 +2673,22 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         LAUNCH(10, k_perm_gather, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.ex.as<double>(), B.rhat.as<double>(), (i64)S.n);
         const unsigned gn = grid1(S.n, 4096);
+        // mixed precision: entries the factorization sent to FP64 factors are
+        // solved with those (their FP32 factorization may have stopped early)
+        const bool routed = B.prec == HKKT_MIXED && !c->fb_idx.empty();
+        if (routed) {
+            Batch& F = c->fb;
+            HIPCHK(hipStreamSynchronize(st));   // the permuted right-hand sides are in place
+            alloc_solve(c, F);
+            upload_gidx(F, c->fb_idx);
+            gather_rows(c, F, {{&F.rhat, &B.rhat}}, S.n);
+            LAUNCH(10, (k_cast<double, double>), dim3(gn, F.nb), dim3(kBlock), 0, F.stream, F.rhat.as<double>(),
+                   F.X.as<double>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
+            launch_trisolve<double>(c, F, nullptr, F.nb, nullptr);
+            LAUNCH(10, (k_cast<double, double>), dim3(gn, F.nb), dim3(kBlock), 0, F.stream,
+                   (const double*)F.X.as<double>(), F.rhat.as<double>(), (i64)S.n, (const int*)nullptr,
+                   (const CGState*)nullptr);
+        }
         if (B.prec == HKKT_MIXED) {
             LAUNCH(10, (k_cast<double, float>), dim3(gn, nb), dim3(kBlock), 0, st, B.rhat.as<double>(),
                                B.X.as<float>(), (i64)S.n, (const int*)nullptr, (const CGState*)nullptr);
@@ -2663,11 +2703,24 @@ int hkkt_hsolve(hkkt_ctx* c, int nb, const double* bvec, double* x) {
                                (const double*)B.X.as<double>(), B.rhat.as<double>(), (i64)S.n, (const int*)nullptr,
                                (const CGState*)nullptr);
         }
+        std::vector<int> both;
+        if (routed) {   // the FP64 solutions into their entries' rows
+            Batch& F = c->fb;
+            HIPCHK(hipStreamSynchronize(F.stream));
+            const int cnt = (int)c->fb_idx.size();
+            for (int i = 0; i < cnt; i++) both.push_back(i);
+            both.insert(both.end(), c->fb_idx.begin(), c->fb_idx.end());
+            F.gidx.ensure(both.size() * 4);
+            HIPCHK(hipMemcpyAsync(F.gidx.p, both.data(), both.size() * 4, hipMemcpyHostToDevice, st));
+            const int* sidx = F.gidx.as<int>();
+            LAUNCH(10, k_copy_rows, dim3(grid1(S.n, 1024), cnt), dim3(kBlock), 0, st, (const double*)F.rhat.as<double>(),
+                   B.rhat.as<double>(), (i64)S.n, sidx, sidx + cnt);
+        }
         LAUNCH(10, k_perm_scatter, dim3(grid1(S.n, 4096), nb), dim3(kBlock), 0, st, c->dev.v.perm,
                            B.rhat.as<double>(), B.ex.as<double>(), (i64)S.n);
         HIPCHK(hipMemcpyAsync(x, B.ex.p, (size_t)nb * S.n * 8, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                               st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipStreamSynchronize(st));   // also: both may go out of scope
         check_flow(B);
         return HKKT_OK;
     })
@@ -2680,6 +2733,11 @@ int hkkt_hsolve_noalloc(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         return HKKT_ERR_ARG;
     }
     if (!c->factored || nb != c->nb) { c->err = "hkkt_hsolve_noalloc: not factored, or nb differs"; return HKKT_ERR_STATE; }
+    if (c->main.prec == HKKT_MIXED && !c->fb_idx.empty()) {
+        c->err = "hkkt_hsolve_noalloc: the factorization sent some instances to FP64 factors (mixed precision); "
+                 "hkkt_hsolve applies those";
+        return HKKT_ERR_STATE;
+    }
     ABI_GUARD(c, {
         const Symbolic& S = c->sym.S;
         Batch& M = c->main;

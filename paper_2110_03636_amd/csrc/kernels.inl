@@ -422,9 +422,20 @@ __device__ __forceinline__ bool pivot_ok(T d) {
     return d > T(0) && d <= (T)(sizeof(T) == 8 ? DBL_MAX : FLT_MAX);
 }
 
+// adiag (may be null): the FP64 diagonal of H_gamma per (instance, pivot);
+// a pivot below ptol times it clears the instance's entry of act_w (the
+// active array this factorization reads), so the instance's later fronts
+// are skipped (the instance is refactored in FP64)
+template <typename T>
+__device__ __forceinline__ void pivot_stop(const double* adiag, double ptol, int* act_w, const SymView& S, int b,
+                                           i64 col, T d) {
+    if (adiag && !((double)d >= ptol * adiag[(i64)b * S.n + col])) act_w[b] = 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __restrict__ list, T* __restrict__ L,
-                                                      T* __restrict__ CB, int* __restrict__ fail, const int* active) {
+                                                      T* __restrict__ CB, int* __restrict__ fail, const int* active,
+                                                      const double* adiag, double ptol, int* act_w) {
     extern __shared__ double smem_d[];
     T* F = reinterpret_cast<T*>(smem_d);
     const int b = blockIdx.y;
@@ -460,6 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __re
         }
         if (k < w) {
             if (threadIdx.x == 0 && !pivot_ok(dk)) atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + k);
+            if (threadIdx.x == 0) pivot_stop(adiag, ptol, act_w, S, b, f + k, dk);
             const T invd = T(1) / dk;
             const int len = nr - k - 1;
             for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
@@ -581,7 +593,8 @@ __global__ __launch_bounds__(kBlock) void k_big_extend(SymView S, const i32* __r
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_big_ptrsm(SymView S, const i32* __restrict__ fronts, int kb,
                                                       T* __restrict__ L, T* __restrict__ CB, int* __restrict__ fail,
-                                                      int* __restrict__ cnt, const int* active) {
+                                                      int* __restrict__ cnt, const int* active, const double* adiag,
+                                                      double ptol, int* act_w) {
     __shared__ T D[kNB][kNB + 1];
     __shared__ int last;
     const int b = blockIdx.z;
@@ -608,6 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_big_ptrsm(SymView S, const i32* __re
                 const T d = lane_read(r[k], k);
                 if (i == 0 && blockIdx.x == 0 && !pivot_ok(d))
                     atomicMin(&fail[b * S.G + (S.G > 1 ? S.sn_mem[s] : 0)], f + kb + k);
+                if (i == 0 && blockIdx.x == 0) pivot_stop(adiag, ptol, act_w, S, b, f + kb + k, d);
                 const T sq = sqrt(d), inv = T(1) / sq;
                 r[k] = i == k ? sq : (i > k ? r[k] * inv : r[k]);
 #pragma unroll
@@ -2732,6 +2746,22 @@ __global__ __launch_bounds__(kBlock) void k_hgamma_check(SymView S, ValView V, c
 // pivot is what is left after cancellation, known to fewer bits of the
 // factor's precision. Block maxima of -ratio (so that k_reduce_max gives
 // -min) into part.
+// the FP64 diagonal of H_gamma = H + D_x + delta I + gamma J^T J per
+// (instance, permuted column), the quantity k_pivot_ratio divides by
+__global__ __launch_bounds__(kBlock) void k_hg_diag(SymView S, ValView V, double* __restrict__ out) {
+    const int b = blockIdx.y;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < S.n; i += (i64)gridDim.x * blockDim.x) {
+        const int k = S.G > 1 ? S.xp_mem[i] : 0;
+        const double* HF = V.HF + (i64)b * S.nnzHF;
+        const double* JT = V.JT + (i64)b * S.nnzJ;
+        double d = V.Dxp[(i64)b * S.n + i] + V.delta[(i64)b * S.G + k], jj = 0.0;
+        for (i64 q = S.HF_rowptr[i]; q < S.HF_rowptr[i + 1]; q++)
+            if (S.HF_col[q] == i) d += HF[q];
+        for (i64 q = S.JT_rowptr[i]; q < S.JT_rowptr[i + 1]; q++) jj += JT[q] * JT[q];
+        out[(i64)b * S.n + i] = d + V.gamma[(i64)b * S.G + k] * jj;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pivot_ratio(SymView S, ValView V, const T* __restrict__ Dinv,
                                                         double* __restrict__ part) {
