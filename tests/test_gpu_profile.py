@@ -85,3 +85,39 @@ def test_profile_select_samples_one_class():
     with pytest.raises(ValueError):
         s.profile_precision("fp16")
     assert hkkt.lib().hkkt_profile_precision(s._ctx, 7) == hkkt.ERR_ARG
+
+
+def test_mixed_hsolve_uses_fp64_factor_of_routed_instances():
+    """Instances the pivot test sends to FP64 stop their FP32 factorization
+    at the first failing pivot: hkkt_hsolve applies their FP64 factor (equal
+    to an FP64 context's solve to 1e-10), and the FP32 one to the others
+    (backward error of FP32 quality); the allocation-free form, which applies
+    FP32 factors only, refuses such a context."""
+    import torch
+    b = _batch()
+    s = hkkt.Solver(precision="mixed")
+    s.analyze(b.pattern)
+    assert s.factor_batch(b)[0] == 0
+    s64 = hkkt.Solver(precision="fp64")
+    s64.analyze(b.pattern)
+    assert s64.factor_batch(b)[0] == 0
+    rhs = np.random.default_rng(11).standard_normal((b.nb, b.pattern.n_x))
+    x, x64 = s.hsolve(rhs), s64.hsolve(rhs)
+    rc, xs, ys, infos = s.solve(b.r1, b.r2)
+    routed = [i for i in range(b.nb) if infos[i]["fp64_fallback"] and infos[i]["passes_fp64"] == infos[i]["passes"]]
+    kept = [i for i in range(b.nb) if not infos[i]["fp64_fallback"]]
+    assert routed and kept, (routed, kept)
+    for i in routed:
+        assert np.linalg.norm(x[i] - x64[i]) / np.linalg.norm(x64[i]) < 1e-10, i
+    from tests import helpers as H
+    for i in kept:
+        A = H.dense_Hgamma(b, i)
+        be = np.linalg.norm(A @ x[i] - rhs[i]) / (np.linalg.norm(A, np.inf) * np.linalg.norm(x[i]) + np.linalg.norm(rhs[i]))
+        assert be < 1e-5, (i, be)
+    sd = hkkt.Solver(precision="mixed", device=True)
+    sd.analyze(b.pattern)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    assert sd.factor(dev(b.H_val), dev(b.D_x), dev(b.J_val), b.delta, b.gamma)[0] == 0
+    with pytest.raises(hkkt.HKKTError) as e:
+        sd.hsolve_noalloc(dev(rhs), torch.empty((b.nb, b.pattern.n_x), dtype=torch.float64, device="cuda"))
+    assert e.value.code == hkkt.ERR_STATE
