@@ -32,10 +32,10 @@ HBM_PEAK_GBS = 8000.0
 def level_bytes(sym, s_elem):
     """Algorithmic bytes one instance moves per level of the supernodal tree,
     forward and backward solve: the structurally non-zero panel entries
-    (s_elem each), the reciprocal diagonal and the solution entries of the
-    supernode's columns (read and written), the entries of the rows below
-    (forward: read-modify-write of the ancestors' entries; backward: read)
-    and their 4-byte row indices."""
+    strictly below the diagonal (s_elem each), the reciprocal diagonal and
+    the solution entries of the supernode's columns (read and written), the
+    entries of the rows below (forward: read-modify-write of the ancestors'
+    entries; backward: read) and their 4-byte row indices."""
     import numpy as np
     sn = sym.supernodes()
     first, rowptr, lp, lsn = sn["first"], sn["rowptr"], sn["level_ptr"], sn["level_sn"]
@@ -44,7 +44,7 @@ def level_bytes(sym, s_elem):
         ids = lsn[lp[l]:lp[l + 1]]
         w = (first[ids + 1] - first[ids]).astype(np.int64)
         nr = (rowptr[ids + 1] - rowptr[ids]).astype(np.int64)
-        nnz = nr * w - w * (w - 1) // 2
+        nnz = nr * w - w * (w + 1) // 2
         below = nr - w
         fwd.append(int((s_elem * nnz + 3 * s_elem * w + 2 * s_elem * below + 4 * below).sum()))
         bwd.append(int((s_elem * nnz + 3 * s_elem * w + s_elem * below + 4 * below).sum()))

@@ -230,6 +230,12 @@ struct DevSym {
     // so that the columns of levels [l, nlevels) are the first tree_nt[l]
     // slots for every l; per supernode (parallel to tri_desc) its slots
     DBuf tree_desc, tree_cols, tree_rs;
+    // packed solve copy of the supernodes of classes 0..6 (the wavefront
+    // solves): LPsize entries per instance, entry e copied from L storage
+    // entry pk_src[e] (int32 entries, int64 when pk_wide)
+    DBuf pk_src;
+    bool pk_wide = false;
+    i64 LPsize = 1;
     std::vector<int> tree_nt;                   // [nlevels + 1]
     std::vector<int> lev_desc0, lev_rs0;        // [nlevels + 1] first descriptor / row slot of a level
     std::vector<i64> lev_lptr;                  // [nlevels + 1] L storage range of a level's panels
@@ -422,6 +428,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, bool mixe
                     dd.nchild = S.child_ptr[sn + 1] - S.child_ptr[sn];
                     dd.mem = S.sn_mem[sn];
                     dd.pq = -1;
+                    dd.pptr = -1;
                     td.push_back(dd);
                     if (cls == kTriWG) {
                         D.tri_wg_maxnr[l] = std::max(D.tri_wg_maxnr[l], nr);
@@ -442,6 +449,31 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, bool mixe
                 if (tri_class(td[q].nr, td[q].w) >= 4) D.flow_ok = false;
             }
             if ((i64)tl.size() != S.ns) D.flow_ok = false;
+        }
+        {   // packed solve copy: strictly lower entries column by column
+            std::vector<i64> src;
+            for (i32 l = 0; l < S.nlevels; l++)
+                for (int cls = 0; cls < kTriWG; cls++) {
+                    const auto seg = D.tri_seg[(size_t)l * kTriClasses + cls];
+                    for (i32 q = seg.first; q < seg.first + seg.second; q++) {
+                        TriDesc& a = td[q];
+                        src.push_back(a.lptr);   // padding entry before the supernode's copy
+                        a.pptr = (i64)src.size();
+                        for (i32 j = 0; j < a.w; j++)
+                            for (i32 r = j + 1; r < a.nr; r++) src.push_back(a.lptr + (i64)j * a.nr + r);
+                    }
+                }
+            if (src.empty()) src.push_back(0);
+            D.LPsize = (i64)src.size();
+            D.pk_wide = S.Lsize > (i64)INT32_MAX;
+            std::vector<i32> src32;
+            if (D.pk_wide) {
+                upload(D.pk_src, src, st);
+            } else {
+                src32.assign(src.begin(), src.end());
+                upload(D.pk_src, src32, st);
+            }
+            HIPCHK(hipStreamSynchronize(st));   // the host vectors go out of scope
         }
         upload(D.tri_desc, td, st);
         upload(D.tri_list, tl, st);
@@ -535,6 +567,7 @@ static void build_devsym(DevSym& D, const Symbolic& S, hipStream_t st, bool mixe
     v.ga_idx = D.ga_idx.as<i32>();
     v.perm = D.perm.as<i32>();
     v.Lsize = S.Lsize; v.CBsize = S.CBsize; v.UVsize = S.UVsize;
+    v.LPsize = D.LPsize;
     v.nnzA = S.nnzA;
     v.a_dst = D.a_dst.as<i64>();
     v.a_h = D.a_h.as<i32>();
@@ -578,6 +611,7 @@ struct Batch {
     bool scaled = false;
     // factor (Dinv: reciprocals of the diagonal of L, per column)
     DBuf L, fail, Dinv;
+    DBuf Lp;   // packed solve copy of the wavefront solves' panels, rebuilt by every factorization
     DBuf pcnt;   // per (instance, large front of a level): panel counters of k_big_ptrsm
     // FP32 factor read by the pivot test (mixed precision): the FP64
     // diagonal of H_gamma per (instance, pivot); an instance whose pivot
@@ -795,6 +829,12 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     }
     LAUNCH(10, k_inv_diag<T>, dim3(grid1(S.n, 1024), nb), dim3(kBlock), 0, st, D.diag_off.as<i64>(), (i64)S.n,
            (i64)S.Lsize, (const T*)L, B.Dinv.as<T>(), active);
+    if (D.pk_wide)
+        LAUNCH(10, (k_pack<T, i64>), dim3(grid1(D.LPsize, 4096), nb), dim3(kBlock), 0, st, D.pk_src.as<i64>(),
+               D.LPsize, (const T*)L, (i64)S.Lsize, B.Lp.as<T>(), active);
+    else
+        LAUNCH(10, (k_pack<T, i32>), dim3(grid1(D.LPsize, 4096), nb), dim3(kBlock), 0, st, D.pk_src.as<i32>(),
+               D.LPsize, (const T*)L, (i64)S.Lsize, B.Lp.as<T>(), active);
 }
 
 // Wide supernodes of level l (class 7) by the blocked multi-work-group
@@ -856,6 +896,7 @@ template <typename T>
 static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* ids, int nids, const CGState* st_) {
     const DevSym& D = c->dev;
     const T* L = B.L.as<T>();
+    const T* Lp = B.Lp.as<T>();   // classes 0..6: the packed solve copy
     const T* Dv = B.Dinv.as<T>();
     T* X = B.X.as<T>();
     T* UV = B.UV.as<T>();
@@ -877,9 +918,9 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         }
         if (wend > 0) {
             const unsigned nblk = (unsigned)((wend + (kBlock / kWave) - 1) / (kBlock / kWave));
-            if (fwd && push) LAUNCH(kf, (k_fwd_lvl<T, true>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
-            else if (fwd) LAUNCH(kf, (k_fwd_lvl<T, false>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, L, Dv, X, UV, ids, nids, st_);
-            else LAUNCH(kb, (k_bwd_lvl<T>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, L, Dv, X, ids, nids, st_);
+            if (fwd && push) LAUNCH(kf, (k_fwd_lvl<T, true>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, Lp, Dv, X, UV, ids, nids, st_);
+            else if (fwd) LAUNCH(kf, (k_fwd_lvl<T, false>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, Lp, Dv, X, UV, ids, nids, st_);
+            else LAUNCH(kb, (k_bwd_lvl<T>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, lt, Lp, Dv, X, ids, nids, st_);
         }
     }
     for (int cls = 4; cls < kTriClasses; cls++) {
@@ -896,10 +937,10 @@ static void launch_tri_level(hkkt_ctx* c, Batch& B, i32 l, bool fwd, const int* 
         const i64 waves = (i64)cnt * npad / G;                                                                    \
         const unsigned nblk = (unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave));                      \
         if (fwd && push) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, true>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, \
-                                cnt, npad, L, Dv, X, UV, ids, nids, st_);                                         \
+                                cnt, npad, Lp, Dv, X, UV, ids, nids, st_);                                         \
         else if (fwd) LAUNCH(kf, (k_fwd_s<T, SEGW, RR, false>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, cnt, \
-                             npad, L, Dv, X, UV, ids, nids, st_);                                                 \
-        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, cnt, npad, L, Dv,  \
+                             npad, Lp, Dv, X, UV, ids, nids, st_);                                                 \
+        else LAUNCH(kb, (k_bwd_s<T, SEGW, RR>), dim3(nblk), dim3(kBlock), 0, B.stream, D.v, dsc, cnt, npad, Lp, Dv, \
                     X, ids, nids, st_);                                                                           \
     }
         switch (cls) {
@@ -944,17 +985,17 @@ template <typename T>
 static void launch_tree(hkkt_ctx* c, Batch& B, int l0, int l1, const int* ids, int nids, const CGState* st_) {
     const DevSym& D = c->dev;
     constexpr int NT = 512;
-    const T* L = B.L.as<T>();
+    const T* Lp = B.Lp.as<T>();
     const T* Dv = B.Dinv.as<T>();
     T* X = B.X.as<T>();
     const TriDesc* desc = D.tri_desc.as<TriDesc>();
     const i32* sg = D.tri_seg_dev.as<i32>();
     const int kind = 12 + 16 * (l0 + 1);
     if (c->opt.deterministic == 0)
-        LAUNCH(kind, (k_tri_tree<T, true, NT>), dim3(nids), dim3(NT), 0, B.stream, D.v, desc, sg, l0, l1, L, Dv, X,
+        LAUNCH(kind, (k_tri_tree<T, true, NT>), dim3(nids), dim3(NT), 0, B.stream, D.v, desc, sg, l0, l1, Lp, Dv, X,
                B.UV.as<T>(), ids, st_);
     else
-        LAUNCH(kind, (k_tri_tree<T, false, NT>), dim3(nids), dim3(NT), 0, B.stream, D.v, desc, sg, l0, l1, L, Dv,
+        LAUNCH(kind, (k_tri_tree<T, false, NT>), dim3(nids), dim3(NT), 0, B.stream, D.v, desc, sg, l0, l1, Lp, Dv,
                X, B.UV.as<T>(), ids, st_);
 }
 
@@ -1156,6 +1197,7 @@ static void scale_values(hkkt_ctx* c, Batch& B) {
 static void alloc_factor(hkkt_ctx* c, Batch& B) {
     const Symbolic& S = c->sym.S;
     B.L.ensure((size_t)B.nb * std::max<i64>(1, S.Lsize) * B.esz());
+    B.Lp.ensure((size_t)B.nb * c->dev.LPsize * B.esz());
     B.Dinv.ensure((size_t)B.nb * S.n * B.esz());
     c->cbws.ensure((size_t)B.nb * std::max<i64>(1, S.CBsize) * B.esz());
     // panel counters of k_big_ptrsm, one per (instance, large front of a
@@ -2765,6 +2807,7 @@ int hkkt_hsolve_noalloc(hkkt_ctx* c, int nb, const double* bvec, double* x) {
         V.allow_flow = false;
         V.stream = c->stream;
         V.L.view(M.L.p, M.L.bytes);
+        V.Lp.view(M.Lp.p, M.Lp.bytes);
         V.Dinv.view(M.Dinv.p, M.Dinv.bytes);
         V.Lt.view(M.Lt.p, M.Lt.bytes);
         V.lt_lo = M.lt_lo;

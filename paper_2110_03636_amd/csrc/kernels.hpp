@@ -6,6 +6,9 @@
 //  - contribution blocks (multifrontal update matrices): (nr-w) x (nr-w)
 //    column-major, lower triangle used.
 //  - update vectors of the forward solve: (nr-w) entries per supernode.
+//  - packed solve copy (supernodes of the wavefront solve classes): the
+//    entries strictly below the diagonal, column by column (column j holds
+//    rows j+1 .. nr-1 contiguously), after one padding entry.
 //  - vectors live in the permuted order of the symbolic analysis.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -39,6 +42,7 @@ struct SymView {
     const i32* ga_idx;
     const i32* perm;
     i64 Lsize, CBsize, UVsize;
+    i64 LPsize;   // entries per instance of the packed solve copy
     // assembly
     i64 nnzA;
     const i64* a_dst;
@@ -83,6 +87,7 @@ struct TriDesc {
     i32 nchild;  // number of children (0: leaf, no gather)
     i32 mem;     // group member
     i32 pq;      // descriptor index of the parent supernode, -1 for a root
+    i64 pptr;    // offset in the packed solve copy (wavefront classes), -1 if none
 };
 
 

@@ -1392,16 +1392,22 @@ __device__ __forceinline__ T seg_bcast(T v, int jl) {
 // Load panel columns [j0, j0 + CH) of the rows this lane holds (strictly
 // below the diagonal, zero elsewhere). Every lane loads from an address
 // clamped into the panel and selects afterwards: no branch per element.
-template <typename T, int SEG, int R, int CH, typename DT>
+// PK: Lb is the supernode's packed solve copy (strictly lower entries only,
+// column jc starting at jc (nr - 1) - jc (jc - 1) / 2, one padding entry at
+// Lb[-1]), else its panel. With jc and the row clamped, the packed entry
+// index of (row, jc) is jc (2 nr - 3 - jc) / 2 - 1 + row (an exact halving),
+// which stays in [-1, entries): no further clamp.
+template <typename T, int SEG, int R, int CH, bool PK, typename DT>
 __device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ Lb, const DT& d, int j0, int sl) {
 #pragma unroll
     for (int jj = 0; jj < CH; jj++) {
         const int j = j0 + jj;
         const int jc = min(max(j, 0), d.w - 1);
+        const int cst = PK ? ((jc * (2 * d.nr - 3 - jc)) >> 1) - 1 : jc * d.nr;
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const int row = sl + SEG * r;
-            const T val = Lb[jc * d.nr + min(row, d.nr - 1)];
+            const T val = Lb[cst + min(row, d.nr - 1)];
             lc[jj][r] = (j >= 0 && j < d.w && row > j && row < d.nr) ? val : T(0);
         }
     }
@@ -1416,11 +1422,11 @@ __device__ __forceinline__ void load_cols(T (&lc)[CH][R], const T* __restrict__ 
 // v enters as the right-hand side (rows of the diagonal block) or zero
 // (rows below) and leaves as the solution or the update for the rows below.
 // lc holds the first chunk of columns on entry.
-template <typename T, int SEG, int R, int CH, bool U, typename DT>
+template <typename T, int SEG, int R, int CH, bool U, bool PK, typename DT>
 __device__ __forceinline__ void fwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di)[R], const T* __restrict__ Lb,
                                          const DT& d, int sl) {
     for (int j0 = 0; j0 < d.w; j0 += CH) {
-        if (j0 > 0) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
+        if (j0 > 0) load_cols<T, SEG, R, CH, PK>(lc, Lb, d, j0, sl);
 #pragma unroll
         for (int jj = 0; jj < CH; jj++) {
             const int j = j0 + jj;
@@ -1446,12 +1452,12 @@ __device__ __forceinline__ void fwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di
 // right-hand side on the diagonal rows and the known solution on the rows
 // below, and leaves with the solution on the diagonal rows. lc holds the
 // chunk [w - CH, w) on entry.
-template <typename T, int SEG, int R, int CH, bool U, typename DT>
+template <typename T, int SEG, int R, int CH, bool U, bool PK, typename DT>
 __device__ __forceinline__ void bwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di)[R], const T* __restrict__ Lb,
                                          const DT& d, int sl) {
     for (int jhi = d.w; jhi > 0; jhi -= CH) {
         const int j0 = jhi - CH;
-        if (jhi < d.w) load_cols<T, SEG, R, CH>(lc, Lb, d, j0, sl);
+        if (jhi < d.w) load_cols<T, SEG, R, CH, PK>(lc, Lb, d, j0, sl);
 #pragma unroll
         for (int jj = CH - 1; jj >= 0; jj--) {
             const int j = j0 + jj;
@@ -1474,18 +1480,19 @@ __device__ __forceinline__ void bwd_cols(T (&lc)[CH][R], T (&v)[R], const T (&di
     }
 }
 
+// Lp: the packed solve copy (LPsize entries per instance)
 template <typename T, int SEG, int R, bool PUSH, bool U>
 __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
-                                         const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X,
+                                         const T* __restrict__ Lp, const T* __restrict__ Dinv, T* __restrict__ X,
                                          T* __restrict__ UV) {
     constexpr int CH = chunk_cols<T, SEG, R>();
     const int sl = threadIdx.x & (SEG - 1);
-    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    const T* Lb = Lp + (i64)b * S.LPsize + d.pptr;
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
     T* uvb = UV + (i64)b * S.UVsize;
     T lc[CH][R];
-    load_cols<T, SEG, R, CH>(lc, Lb, d, 0, sl);
+    load_cols<T, SEG, R, CH, true>(lc, Lb, d, 0, sl);
     T v[R], di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -1502,7 +1509,7 @@ __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int
         v[r] = a;
         di[r] = e;
     }
-    fwd_cols<T, SEG, R, CH, U>(lc, v, di, Lb, d, sl);
+    fwd_cols<T, SEG, R, CH, U, true>(lc, v, di, Lb, d, sl);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -1517,16 +1524,16 @@ __device__ __forceinline__ void fwd_body(const SymView& S, const TriDesc& d, int
 
 template <typename T, int SEG, int R, bool U>
 __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int b, bool valid,
-                                         const T* __restrict__ L, const T* __restrict__ Dinv, T* __restrict__ X) {
+                                         const T* __restrict__ Lp, const T* __restrict__ Dinv, T* __restrict__ X) {
     constexpr int CH = chunk_cols<T, SEG, R>();
     const int sl = threadIdx.x & (SEG - 1);
-    const T* Lb = L + (i64)b * S.Lsize + d.lptr;
+    const T* Lb = Lp + (i64)b * S.LPsize + d.pptr;
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
     // columns from the last one down in chunks [jhi - CH, jhi); the first
     // chunk goes out with the vector loads
     T lc[CH][R];
-    load_cols<T, SEG, R, CH>(lc, Lb, d, d.w - CH, sl);
+    load_cols<T, SEG, R, CH, true>(lc, Lb, d, d.w - CH, sl);
     T v[R], di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -1537,7 +1544,7 @@ __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int
         v[r] = a;
         di[r] = e;
     }
-    bwd_cols<T, SEG, R, CH, U>(lc, v, di, Lb, d, sl);
+    bwd_cols<T, SEG, R, CH, U, true>(lc, v, di, Lb, d, sl);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -1547,12 +1554,18 @@ __device__ __forceinline__ void bwd_body(const SymView& S, const TriDesc& d, int
 }
 
 
+// Index of this thread's wavefront in the work-group, as a wave-uniform
+// value (the compiler does not infer that threadIdx.x / 64 is uniform): the
+// task lookup below then runs on the scalar unit and the supernode's
+// descriptor arrives through scalar loads.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
+
 // Per-level mapping: all segments of a wavefront take the same supernode for
 // consecutive entries of the instance list (the task space of a supernode is
 // padded to a multiple of 64/SEG, so control flow is wave-uniform).
 template <typename T, int SEG, int R, bool PUSH>
 __device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
-                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         i64 wave, const T* __restrict__ Lp, const T* __restrict__ Dinv,
                                          T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
                                          const CGState* st) {
     constexpr int G = kWave / SEG;
@@ -1565,12 +1578,12 @@ __device__ __forceinline__ void fwd_task(const SymView& S, const TriDesc* __rest
     const int b = valid ? inst_of(ids, k) : 0;
     const TriDesc d = desc[q];
     if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-    fwd_body<T, SEG, R, PUSH, true>(S, d, b, valid, L, Dinv, X, UV);
+    fwd_body<T, SEG, R, PUSH, true>(S, d, b, valid, Lp, Dinv, X, UV);
 }
 
 template <typename T, int SEG, int R>
 __device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __restrict__ desc, int count, int npad,
-                                         i64 wave, const T* __restrict__ L, const T* __restrict__ Dinv,
+                                         i64 wave, const T* __restrict__ Lp, const T* __restrict__ Dinv,
                                          T* __restrict__ X, const int* ids, int nids, const CGState* st) {
     constexpr int G = kWave / SEG;
     const int seg = (threadIdx.x & (kWave - 1)) / SEG;
@@ -1582,7 +1595,7 @@ __device__ __forceinline__ void bwd_task(const SymView& S, const TriDesc* __rest
     const int b = valid ? inst_of(ids, k) : 0;
     const TriDesc d = desc[q];
     if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-    bwd_body<T, SEG, R, true>(S, d, b, valid, L, Dinv, X);
+    bwd_body<T, SEG, R, true>(S, d, b, valid, Lp, Dinv, X);
 }
 
 // ---------------------------------------------------------------------------
@@ -1603,33 +1616,33 @@ constexpr int kTreeClasses = 5;
 
 template <typename T, int SEG, int R, bool PUSH>
 __device__ __forceinline__ void fwd_tree_class(const SymView& S, const TriDesc* __restrict__ desc, int cnt, int b,
-                                               const T* __restrict__ L, const T* __restrict__ Dinv,
+                                               const T* __restrict__ Lp, const T* __restrict__ Dinv,
                                                T* __restrict__ X, T* __restrict__ UV, const CGState* st) {
     constexpr int G = kWave / SEG;
-    const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int wv = wave_in_block(), nw = blockDim.x / kWave;
     const int seg = (threadIdx.x & (kWave - 1)) / SEG;
     for (int base = wv * G; base < cnt; base += nw * G) {
         const int q = base + seg;
         bool valid = q < cnt;
         const TriDesc d = desc[valid ? q : cnt - 1];
         if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-        fwd_body<T, SEG, R, PUSH, false>(S, d, b, valid, L, Dinv, X, UV);
+        fwd_body<T, SEG, R, PUSH, false>(S, d, b, valid, Lp, Dinv, X, UV);
     }
 }
 
 template <typename T, int SEG, int R>
 __device__ __forceinline__ void bwd_tree_class(const SymView& S, const TriDesc* __restrict__ desc, int cnt, int b,
-                                               const T* __restrict__ L, const T* __restrict__ Dinv,
+                                               const T* __restrict__ Lp, const T* __restrict__ Dinv,
                                                T* __restrict__ X, const CGState* st) {
     constexpr int G = kWave / SEG;
-    const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int wv = wave_in_block(), nw = blockDim.x / kWave;
     const int seg = (threadIdx.x & (kWave - 1)) / SEG;
     for (int base = wv * G; base < cnt; base += nw * G) {
         const int q = base + seg;
         bool valid = q < cnt;
         const TriDesc d = desc[valid ? q : cnt - 1];
         if (valid && st && st[(i64)b * S.G + d.mem].done) valid = false;
-        bwd_body<T, SEG, R, false>(S, d, b, valid, L, Dinv, X);
+        bwd_body<T, SEG, R, false>(S, d, b, valid, Lp, Dinv, X);
     }
 }
 
@@ -1638,26 +1651,26 @@ __device__ __forceinline__ void bwd_tree_class(const SymView& S, const TriDesc* 
 // per listed instance
 template <typename T, bool PUSH, int NT>
 __global__ __launch_bounds__(NT) void k_tri_tree(SymView S, const TriDesc* __restrict__ desc,
-                                                 const i32* __restrict__ seg, int l0, int l1, const T* __restrict__ L,
+                                                 const i32* __restrict__ seg, int l0, int l1, const T* __restrict__ Lp,
                                                  const T* __restrict__ Dinv, T* __restrict__ X, T* __restrict__ UV,
                                                  const int* ids, const CGState* st) {
     const int b = inst_of(ids, blockIdx.x);
     for (int l = l0; l < l1; l++) {
         const i32* sg = seg + 2 * (l * kTriClasses);
-        if (sg[1]) fwd_tree_class<T, 16, 1, PUSH>(S, desc + sg[0], sg[1], b, L, Dinv, X, UV, st);
-        if (sg[3]) fwd_tree_class<T, 32, 1, PUSH>(S, desc + sg[2], sg[3], b, L, Dinv, X, UV, st);
-        if (sg[5]) fwd_tree_class<T, 64, 1, PUSH>(S, desc + sg[4], sg[5], b, L, Dinv, X, UV, st);
-        if (sg[7]) fwd_tree_class<T, 64, 2, PUSH>(S, desc + sg[6], sg[7], b, L, Dinv, X, UV, st);
-        if (sg[9]) fwd_tree_class<T, 64, 4, PUSH>(S, desc + sg[8], sg[9], b, L, Dinv, X, UV, st);
+        if (sg[1]) fwd_tree_class<T, 16, 1, PUSH>(S, desc + sg[0], sg[1], b, Lp, Dinv, X, UV, st);
+        if (sg[3]) fwd_tree_class<T, 32, 1, PUSH>(S, desc + sg[2], sg[3], b, Lp, Dinv, X, UV, st);
+        if (sg[5]) fwd_tree_class<T, 64, 1, PUSH>(S, desc + sg[4], sg[5], b, Lp, Dinv, X, UV, st);
+        if (sg[7]) fwd_tree_class<T, 64, 2, PUSH>(S, desc + sg[6], sg[7], b, Lp, Dinv, X, UV, st);
+        if (sg[9]) fwd_tree_class<T, 64, 4, PUSH>(S, desc + sg[8], sg[9], b, Lp, Dinv, X, UV, st);
         __syncthreads();
     }
     for (int l = l1 - 1; l >= l0; l--) {
         const i32* sg = seg + 2 * (l * kTriClasses);
-        if (sg[1]) bwd_tree_class<T, 16, 1>(S, desc + sg[0], sg[1], b, L, Dinv, X, st);
-        if (sg[3]) bwd_tree_class<T, 32, 1>(S, desc + sg[2], sg[3], b, L, Dinv, X, st);
-        if (sg[5]) bwd_tree_class<T, 64, 1>(S, desc + sg[4], sg[5], b, L, Dinv, X, st);
-        if (sg[7]) bwd_tree_class<T, 64, 2>(S, desc + sg[6], sg[7], b, L, Dinv, X, st);
-        if (sg[9]) bwd_tree_class<T, 64, 4>(S, desc + sg[8], sg[9], b, L, Dinv, X, st);
+        if (sg[1]) bwd_tree_class<T, 16, 1>(S, desc + sg[0], sg[1], b, Lp, Dinv, X, st);
+        if (sg[3]) bwd_tree_class<T, 32, 1>(S, desc + sg[2], sg[3], b, Lp, Dinv, X, st);
+        if (sg[5]) bwd_tree_class<T, 64, 1>(S, desc + sg[4], sg[5], b, Lp, Dinv, X, st);
+        if (sg[7]) bwd_tree_class<T, 64, 2>(S, desc + sg[6], sg[7], b, Lp, Dinv, X, st);
+        if (sg[9]) bwd_tree_class<T, 64, 4>(S, desc + sg[8], sg[9], b, Lp, Dinv, X, st);
         __syncthreads();
     }
 }
@@ -1897,6 +1910,20 @@ __device__ __forceinline__ void bwd2(int w, int nr, int slot, int rs, int p0, co
     }
 }
 
+// Packed solve copy of the wavefront solves' supernodes: entry e of an
+// instance's copy is entry src[e] of its L storage (the map is built with
+// the analysis). Instances whose active flag is clear are left as they are.
+template <typename T, typename IX>
+__global__ void k_pack(const IX* __restrict__ src, i64 np, const T* __restrict__ L, i64 Lsize, T* __restrict__ Lp,
+                       const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const T* Lb = L + (i64)b * Lsize;
+    T* Pb = Lp + (i64)b * np;
+    for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < np; e += (i64)gridDim.x * blockDim.x)
+        Pb[e] = Lb[src[e]];
+}
+
 // Solve copy of the panels of supernodes desc[0, gridDim.x): row-major,
 // rows of ws = tree2_ws(w) entries, Lt(r, c) = L(r, c) / L(c, c) below the
 // diagonal, zero on and above it and in the padding, at offset toff - base
@@ -1965,7 +1992,7 @@ __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __r
     for (int k = threadIdx.x; k < S.G; k += NT) done[k] = st ? st[(i64)b * S.G + k].done : 0;
     T pr[PR];
     tree2_load<T, PR>(pr, Lb + (lev_off[l0] - base), (int)(lev_off[l0 + 1] - lev_off[l0]), threadIdx.x, NT);
-    const int wv = threadIdx.x / kWave, nw = NT / kWave;
+    const int wv = wave_in_block(), nw = NT / kWave;
     int lw = 0;   // first wavefront of the threads holding the next visit's panels
     // visits: levels l0 .. l1-1 forward, then l1-1 .. l0 backward; the top
     // level's staged panels serve both of its visits
@@ -2016,18 +2043,18 @@ __global__ __launch_bounds__(NT) void k_tri_tree2(SymView S, const TreeDesc* __r
 // one class per launch (used for the wide classes R >= 4)
 template <typename T, int SEG, int R, bool PUSH>
 __global__ __launch_bounds__(kBlock) void k_fwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
-                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  const T* __restrict__ Lp, const T* __restrict__ Dinv,
                                                   T* __restrict__ X, T* __restrict__ UV, const int* ids, int nids,
                                                   const CGState* st) {
-    fwd_task<T, SEG, R, PUSH>(S, desc, count, npad, (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, L, Dinv,
+    fwd_task<T, SEG, R, PUSH>(S, desc, count, npad, (i64)blockIdx.x * (kBlock / kWave) + wave_in_block(), Lp, Dinv,
                               X, UV, ids, nids, st);
 }
 
 template <typename T, int SEG, int R>
 __global__ __launch_bounds__(kBlock) void k_bwd_s(SymView S, const TriDesc* __restrict__ desc, int count, int npad,
-                                                  const T* __restrict__ L, const T* __restrict__ Dinv,
+                                                  const T* __restrict__ Lp, const T* __restrict__ Dinv,
                                                   T* __restrict__ X, const int* ids, int nids, const CGState* st) {
-    bwd_task<T, SEG, R>(S, desc, count, npad, (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave, L, Dinv, X,
+    bwd_task<T, SEG, R>(S, desc, count, npad, (i64)blockIdx.x * (kBlock / kWave) + wave_in_block(), Lp, Dinv, X,
                         ids, nids, st);
 }
 
@@ -2041,33 +2068,33 @@ struct LevelTasks {
 };
 
 template <typename T, bool PUSH>
-__global__ __launch_bounds__(kBlock) void k_fwd_lvl(SymView S, LevelTasks lt, const T* __restrict__ L,
+__global__ __launch_bounds__(kBlock) void k_fwd_lvl(SymView S, LevelTasks lt, const T* __restrict__ Lp,
                                                     const T* __restrict__ Dinv, T* __restrict__ X, T* __restrict__ UV,
                                                     const int* ids, int nids, const CGState* st) {
-    const i64 wv = (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const i64 wv = (i64)blockIdx.x * (kBlock / kWave) + wave_in_block();
     if (wv < lt.wave_end[0])
-        fwd_task<T, 16, 1, PUSH>(S, lt.desc[0], lt.count[0], lt.npad[0], wv, L, Dinv, X, UV, ids, nids, st);
+        fwd_task<T, 16, 1, PUSH>(S, lt.desc[0], lt.count[0], lt.npad[0], wv, Lp, Dinv, X, UV, ids, nids, st);
     else if (wv < lt.wave_end[1])
-        fwd_task<T, 32, 1, PUSH>(S, lt.desc[1], lt.count[1], lt.npad[1], wv - lt.wave_end[0], L, Dinv, X, UV, ids, nids, st);
+        fwd_task<T, 32, 1, PUSH>(S, lt.desc[1], lt.count[1], lt.npad[1], wv - lt.wave_end[0], Lp, Dinv, X, UV, ids, nids, st);
     else if (wv < lt.wave_end[2])
-        fwd_task<T, 64, 1, PUSH>(S, lt.desc[2], lt.count[2], lt.npad[2], wv - lt.wave_end[1], L, Dinv, X, UV, ids, nids, st);
+        fwd_task<T, 64, 1, PUSH>(S, lt.desc[2], lt.count[2], lt.npad[2], wv - lt.wave_end[1], Lp, Dinv, X, UV, ids, nids, st);
     else if (wv < lt.wave_end[3])
-        fwd_task<T, 64, 2, PUSH>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], L, Dinv, X, UV, ids, nids, st);
+        fwd_task<T, 64, 2, PUSH>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], Lp, Dinv, X, UV, ids, nids, st);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bwd_lvl(SymView S, LevelTasks lt, const T* __restrict__ L,
+__global__ __launch_bounds__(kBlock) void k_bwd_lvl(SymView S, LevelTasks lt, const T* __restrict__ Lp,
                                                     const T* __restrict__ Dinv, T* __restrict__ X, const int* ids,
                                                     int nids, const CGState* st) {
-    const i64 wv = (i64)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const i64 wv = (i64)blockIdx.x * (kBlock / kWave) + wave_in_block();
     if (wv < lt.wave_end[0])
-        bwd_task<T, 16, 1>(S, lt.desc[0], lt.count[0], lt.npad[0], wv, L, Dinv, X, ids, nids, st);
+        bwd_task<T, 16, 1>(S, lt.desc[0], lt.count[0], lt.npad[0], wv, Lp, Dinv, X, ids, nids, st);
     else if (wv < lt.wave_end[1])
-        bwd_task<T, 32, 1>(S, lt.desc[1], lt.count[1], lt.npad[1], wv - lt.wave_end[0], L, Dinv, X, ids, nids, st);
+        bwd_task<T, 32, 1>(S, lt.desc[1], lt.count[1], lt.npad[1], wv - lt.wave_end[0], Lp, Dinv, X, ids, nids, st);
     else if (wv < lt.wave_end[2])
-        bwd_task<T, 64, 1>(S, lt.desc[2], lt.count[2], lt.npad[2], wv - lt.wave_end[1], L, Dinv, X, ids, nids, st);
+        bwd_task<T, 64, 1>(S, lt.desc[2], lt.count[2], lt.npad[2], wv - lt.wave_end[1], Lp, Dinv, X, ids, nids, st);
     else if (wv < lt.wave_end[3])
-        bwd_task<T, 64, 2>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], L, Dinv, X, ids, nids, st);
+        bwd_task<T, 64, 2>(S, lt.desc[3], lt.count[3], lt.npad[3], wv - lt.wave_end[2], Lp, Dinv, X, ids, nids, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -2121,7 +2148,7 @@ __device__ __forceinline__ void flow_fwd(const SymView& S, const FlowArgs& F, co
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
     T lc[CH][R];
-    load_cols<T, SEG, R, CH>(lc, Lb, d, 0, sl);     // the factor is not written during the solve
+    load_cols<T, SEG, R, CH, false>(lc, Lb, d, 0, sl);     // the factor is not written during the solve
     T di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -2138,7 +2165,7 @@ __device__ __forceinline__ void flow_fwd(const SymView& S, const FlowArgs& F, co
         const int row = sl + SEG * r;
         v[r] = row < d.w ? x[d.f + row] : T(0);
     }
-    fwd_cols<T, SEG, R, CH, true>(lc, v, di, Lb, d, sl);
+    fwd_cols<T, SEG, R, CH, true, false>(lc, v, di, Lb, d, sl);
     if (valid) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -2166,7 +2193,7 @@ __device__ __forceinline__ void flow_bwd(const SymView& S, const FlowArgs& F, co
     const T* dinv = Dinv + (i64)b * S.n + d.f;
     T* x = X + (i64)b * S.n;
     T lc[CH][R];
-    load_cols<T, SEG, R, CH>(lc, Lb, d, d.w - CH, sl);
+    load_cols<T, SEG, R, CH, false>(lc, Lb, d, d.w - CH, sl);
     T di[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -2183,7 +2210,7 @@ __device__ __forceinline__ void flow_bwd(const SymView& S, const FlowArgs& F, co
         if (row < d.nr) a = row < d.w ? x[d.f + row] : x[S.sn_rows[d.rp + row]];
         v[r] = a;
     }
-    bwd_cols<T, SEG, R, CH, true>(lc, v, di, Lb, d, sl);
+    bwd_cols<T, SEG, R, CH, true, false>(lc, v, di, Lb, d, sl);
     if (valid) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
