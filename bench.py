@@ -388,8 +388,12 @@ def large_single(args):
     s.analyze(b.pattern)
     t_an = time.perf_counter() - t0
     print(f"large: analysed in {t_an:.1f} s", file=sys.stderr, flush=True)
-    tune = s.autotune(H, dxs[0], J, b.delta, b.gamma)
-    print(f"large: autotuned {tune['relax']}/{tune['tree_width']}", file=sys.stderr, flush=True)
+    if args.schedule_mixed:   # a schedule from an earlier autotuning
+        s.set_schedule(*[int(v) for v in args.schedule_mixed.split(",")])
+        tune = dict(zip(("relax", "tree_width", "tree_staged"), s.schedule()), given=True)
+    else:
+        tune = s.autotune(H, dxs[0], J, b.delta, b.gamma)
+    print(f"large: schedule {tune['relax']}/{tune['tree_width']}/{tune['tree_staged']}", file=sys.stderr, flush=True)
     s.factor(H, dxs[0], J, b.delta, b.gamma)
     s.solve(R1, R2)
     torch.cuda.synchronize()
@@ -407,7 +411,8 @@ def large_single(args):
     st = s.stats()
     print(json.dumps({"workload": f"grid-like n_x={n}, m={n // 2}, gamma=1e6, mixed precision, "
                                   f"{args.cycles} factor+solve cycles with fresh D_x, target RR<=1e-10",
-                      "analyze_s": round(t_an, 2), "autotuned": {"relax": tune["relax"], "tree_width": tune["tree_width"], "tree_staged": tune["tree_staged"]},
+                      "analyze_s": round(t_an, 2), "autotuned" if not tune.get("given") else "schedule_given":
+                          {"relax": tune["relax"], "tree_width": tune["tree_width"], "tree_staged": tune["tree_staged"]},
                       "sustained_solves_per_s": round(ok / el, 3), "s_per_cycle": round(el / args.cycles, 3),
                       "converged": f"{ok}/{args.cycles}", "max_rr": max(i["rr"] for i in res),
                       "not_converged": [{"cycle": k, "rr": i["rr"], "floor": i["floor"], "status": i["status"]}

@@ -1325,10 +1325,13 @@ __global__ __launch_bounds__(kBlock) void k_ws_bwd(SymView S, const TriDesc* __r
 // x_j = (v_j - sum_{i>j} L_ij x_i) / L_jj with a butterfly segment sum.
 // ---------------------------------------------------------------------------
 // panel columns fetched per memory round trip: 16 for the 64-lane class with
-// one row per lane, 8 otherwise (register budget and occupancy)
+// one row per lane, 8 otherwise, but for sixteen rows per lane 4 (FP32) or 2
+// (FP64): more columns of that height do not fit the 256 vector registers
+// next to the rows, and the compiler then parks each loaded value in the
+// accumulation registers and waits for it, one load at a time
 template <typename T, int SEG, int R>
 __host__ __device__ constexpr int chunk_cols() {
-    return (SEG == 64 && R == 1) ? 16 : 8;
+    return (SEG == 64 && R == 1) ? 16 : R >= 16 ? (sizeof(T) == 8 ? 2 : 4) : 8;
 }
 
 // Lane permutations within rows of 16 lanes through DPP (a VALU operand
