@@ -432,6 +432,27 @@ __device__ __forceinline__ void pivot_stop(const double* adiag, double ptol, int
     if (adiag && !((double)d >= ptol * adiag[(i64)b * S.n + col])) act_w[b] = 0;
 }
 
+// (column, row) of the flat column-major index idx = col * len + row of a
+// len x len block, stepped by the block size without a division per step:
+// the same elements in the same order as idx / len, idx % len.
+struct SqIdx {
+    int col, row, dcol, drow, len;
+    __device__ __forceinline__ SqIdx(int idx, int step, int n) : len(n) {
+        col = idx / n;
+        row = idx - col * n;
+        dcol = step / n;
+        drow = step - dcol * n;
+    }
+    __device__ __forceinline__ void next() {
+        row += drow;
+        col += dcol;
+        if (row >= len) {
+            row -= len;
+            col++;
+        }
+    }
+};
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __restrict__ list, T* __restrict__ L,
                                                       T* __restrict__ CB, int* __restrict__ fail, const int* active,
@@ -455,9 +476,10 @@ __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __re
         const int ncc = (int)(S.sn_rowptr[c + 1] - S.sn_rowptr[c]) - wc;
         const i32* rel = S.relmap + S.sn_uvptr[c];
         const T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[c];
-        for (int idx = threadIdx.x; idx < ncc * ncc; idx += blockDim.x) {
-            const int j = idx / ncc, i = idx - j * ncc;
-            if (i >= j) F[rel[j] * nr + rel[i]] += C[idx];
+        if (ncc > 0) {
+            SqIdx t(threadIdx.x, blockDim.x, ncc);
+            for (int idx = threadIdx.x; idx < ncc * ncc; idx += blockDim.x, t.next())
+                if (t.row >= t.col) F[rel[t.col] * nr + rel[t.row]] += C[idx];
         }
         __syncthreads();
     }
@@ -474,11 +496,13 @@ __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __re
             if (threadIdx.x == 0) pivot_stop(adiag, ptol, act_w, S, b, f + k, dk);
             const T invd = T(1) / dk;
             const int len = nr - k - 1;
-            for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x) {
-                const int jj = idx / len, ii = idx - jj * len;
-                if (ii >= jj) {
-                    const int i = k + 1 + ii, j = k + 1 + jj;
-                    F[j * nr + i] -= F[k * nr + i] * F[k * nr + j] * invd;
+            if (len > 0) {
+                SqIdx t(threadIdx.x, blockDim.x, len);
+                for (int idx = threadIdx.x; idx < len * len; idx += blockDim.x, t.next()) {
+                    if (t.row >= t.col) {
+                        const int i = k + 1 + t.row, j = k + 1 + t.col;
+                        F[j * nr + i] -= F[k * nr + i] * F[k * nr + j] * invd;
+                    }
                 }
             }
         }
@@ -487,9 +511,10 @@ __global__ __launch_bounds__(kBlock) void k_front_lds(SymView S, const i32* __re
     }
     for (int idx = threadIdx.x; idx < nr * w; idx += blockDim.x) Lb[idx] = F[idx];
     T* C = CB + (i64)b * S.CBsize + S.sn_cbptr[s];
-    for (int idx = threadIdx.x; idx < nc * nc; idx += blockDim.x) {
-        const int j = idx / nc, i = idx - j * nc;
-        if (i >= j) C[idx] = F[(w + j) * nr + w + i];
+    if (nc > 0) {
+        SqIdx t(threadIdx.x, blockDim.x, nc);
+        for (int idx = threadIdx.x; idx < nc * nc; idx += blockDim.x, t.next())
+            if (t.row >= t.col) C[idx] = F[(w + t.col) * nr + w + t.row];
     }
 }
 
