@@ -33,8 +33,10 @@
  *    device, e.g. a torch tensor's data_ptr()). Pattern arrays given to
  *    hkkt_analyze are always host pointers and are copied.
  *  - The context owns its device memory: the symbolic tables, the factor (per
- *    instance, L storage entries in the factor's precision), the
- *    contribution-block and solve workspaces, and, for the staged
+ *    instance, L storage entries in the factor's precision), a packed copy of
+ *    the entries below the diagonal of the supernodes the wavefront solves
+ *    handle (written by every factorization; at most the L storage again),
+ *    the contribution-block and solve workspaces, and, for the staged
  *    tree-traversal solves, a solve copy of the top levels' panels built at
  *    the first triangular solve after each factorization. It grows on demand
  *    and is freed by hkkt_destroy.
@@ -413,7 +415,8 @@ int hkkt_hsolve(hkkt_ctx *ctx, int nb, const double *b, double *x);
  * HKKT_PTR_DEVICE: b [nb][n_x] and x [nb][n_x] are device pointers in the
  * original order, nb equal to the last factorization's. It allocates, frees
  * and synchronises nothing: the work is enqueued on the context's stream and
- * x is written when the stream reaches it. The staged tree kernel's panel
+ * x is written when the stream reaches it. It reads the factor and its packed
+ * solve copy, both written by the factorization. The staged tree kernel's panel
  * copy is used only if an earlier hkkt_solve/hkkt_hsolve after the last
  * factorization built it; otherwise the levels it would cover run in the
  * global-memory tree kernel (same solution up to rounding). Per-kernel
