@@ -622,7 +622,7 @@ struct Batch {
     DBuf adiag;
     std::vector<int> h_alive;
     // solve workspace
-    DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, pfloor, st, live;
+    DBuf r1p, r2, xz, yz, g1, g2, rhat, ex, X, UV, bvec, y, res, p, q, part1, part2, part3, pfloor, st, live;
     DBuf rsq, rowred, knorm, active;
     DBuf ids_pass, ids_a, ids_b, ids_all;   // batch-entry lists of the solve phase
     DBuf cact;                 // per (entry, member): member takes part in the current pass (groups)
@@ -1221,7 +1221,7 @@ static void alloc_solve(hkkt_ctx* c, Batch& B) {
     B.UV.ensure(nb * std::max<i64>(1, S.UVsize) * B.esz());
     const size_t nblk = std::max<size_t>(1, std::max(S.mblk.size(), S.rblk.size()) / 3);
     const size_t nc = nb * S.G;
-    for (DBuf* d : {&B.part1, &B.part2, &B.pfloor}) d->ensure(nb * nblk * 8);
+    for (DBuf* d : {&B.part1, &B.part2, &B.part3, &B.pfloor}) d->ensure(nb * nblk * 8);
     B.st.ensure(nc * sizeof(CGState));
     B.live.ensure(16);
     for (DBuf* d : {&B.ids_pass, &B.ids_a, &B.ids_b, &B.ids_all}) d->ensure(nb * 4);
@@ -1456,13 +1456,15 @@ static void hybrid_pass(hkkt_ctx* c, Batch& B, int nids, int max_cg, double cg_t
         LAUNCH(6, k_j<T>, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, V, (const T*)X, (const double*)nullptr,
                B.p.as<double>(), (const CGState*)cst, 1, B.q.as<double>(), B.part1.as<double>(), B.part2.as<double>(),
                (const int*)cur);
-        LAUNCH(8, k_cg_alpha, dim3(ncur, G), dim3(kBlock), 0, st, D.v, cst, (const double*)B.part1.as<double>(),
-               (const double*)B.part2.as<double>(), c->opt.quad_form_eps, c->opt.delta2, (const int*)cur);
+        // alpha: formed by every block of k_cg_update, stored by k_cg_beta
         LAUNCH(7, k_cg_update, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, (const double*)B.p.as<double>(),
                (const double*)B.q.as<double>(), (const double*)B.bvec.as<double>(), B.y.as<double>(),
-               B.res.as<double>(), (const CGState*)cst, B.part1.as<double>(), (const int*)cur);
+               B.res.as<double>(), (const CGState*)cst, (const double*)B.part1.as<double>(),
+               (const double*)B.part2.as<double>(), c->opt.quad_form_eps, c->opt.delta2, B.part3.as<double>(),
+               (const int*)cur);
         LAUNCH(8, k_cg_beta, dim3(ncur, G), dim3(kBlock), 0, st, D.v, cst, (const double*)B.part1.as<double>(),
-               cg_tol, ptol, max_cg, (const int*)cur);
+               (const double*)B.part2.as<double>(), c->opt.quad_form_eps, c->opt.delta2,
+               (const double*)B.part3.as<double>(), cg_tol, ptol, max_cg, (const int*)cur);
         LAUNCH(7, k_cg_p, dim3(nbm, ncur), dim3(kBlock), 0, st, D.v, B.p.as<double>(),
                (const double*)B.res.as<double>(), (const CGState*)cst, (const int*)cur);
         if ((it + 1) % check_every == 0) {

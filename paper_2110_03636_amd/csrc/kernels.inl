@@ -2468,79 +2468,94 @@ __global__ void k_cg_vecinit(const double* __restrict__ bvec, double* __restrict
 }
 
 // alpha = rho / p'q, with the small-quadratic-form test of Algorithm 1
-__global__ void k_cg_alpha(SymView S, CGState* st, const double* part1, const double* part2, double qf_eps,
-                           double delta2, const int* ids) {
-    __shared__ double sh[kBlock / kWave];
-    const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
-    const i64 ci = (i64)b * S.G + k;
-    // the flag (uniform in the block) is tested after the reductions' loads
-    // are out, not before them
-    const int done = st[ci].done;
-    const double pq = reduce_member(part1, S.nbm, S.mblk_off, b, k, sh);
-    const double pp = reduce_member(part2, S.nbm, S.mblk_off, b, k, sh);
-    if (done) return;
-    if (threadIdx.x == 0) {
-        CGState c = st[ci];
-        if (c.curv0 < 0.0) c.curv0 = pq / pp;
-        c.pq = pq;
-        c.pp = pp;
-        if (!(pq > qf_eps * pp * c.curv0)) {
-            c.breakdown = 1;
-            if (delta2 > 0.0 && c.d2 == 0.0) {
-                c.d2 = delta2;      // restart on S + delta2 I
-                c.alpha = 0.0;
-                c.pad = 1;          // restart pending
-            } else {
-                c.done = 1;
-            }
+// (on the state of a member whose CG is running)
+__device__ __forceinline__ void cg_alpha_step(CGState& c, double pq, double pp, double qf_eps, double delta2) {
+    if (c.curv0 < 0.0) c.curv0 = pq / pp;
+    c.pq = pq;
+    c.pp = pp;
+    if (!(pq > qf_eps * pp * c.curv0)) {
+        c.breakdown = 1;
+        if (delta2 > 0.0 && c.d2 == 0.0) {
+            c.d2 = delta2;      // restart on S + delta2 I
+            c.alpha = 0.0;
+            c.pad = 1;          // restart pending
         } else {
-            c.alpha = c.rho / pq;
+            c.done = 1;
         }
-        st[ci] = c;
+    } else {
+        c.alpha = c.rho / pq;
     }
 }
 
-// y += alpha p; res -= alpha q; partial res'res (member-aligned blocks of the
-// J rows). A pending restart resets y = 0, res = bvec.
+// y += alpha p; res -= alpha q; partial res'res into part (member-aligned
+// blocks of the J rows). Every block forms alpha itself from the state at the
+// start of the iteration and the p'q, p'p partials (part1, part2), by the
+// same reduction as k_cg_beta, which stores the state afterwards: the state
+// is read-only here. A pending restart resets y = 0, res = bvec.
 __global__ __launch_bounds__(kBlock) void k_cg_update(SymView S, const double* __restrict__ p,
                                                       const double* __restrict__ q, const double* __restrict__ bvec,
                                                       double* __restrict__ y, double* __restrict__ res,
-                                                      const CGState* st, double* __restrict__ part, const int* ids) {
+                                                      const CGState* st, const double* part1, const double* part2,
+                                                      double qf_eps, double delta2, double* __restrict__ part,
+                                                      const int* ids) {
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.y);
     const Blk bk = blk_of(S.mblk, blockIdx.x);
-    const CGState* cs = st + (i64)b * S.G + bk.k;
-    // the state (uniform in the block) and the vectors are loaded together
-    const int done = cs->done, pad = cs->pad;
-    const double al = cs->alpha;
+    // the state (uniform in the block) and the vectors are loaded before the
+    // reductions' barriers
+    CGState c = st[(i64)b * S.G + bk.k];
     const i64 i = bk.lo + threadIdx.x;
+    const bool in = i < bk.hi;
+    const i64 o = (i64)b * S.m + i;
+    double pv = 0.0, qv = 0.0, yv = 0.0, rv = 0.0, bv = 0.0;
+    if (in) {
+        pv = p[o];
+        qv = q[o];
+        yv = y[o];
+        rv = res[o];
+        bv = bvec[o];
+    }
+    // the block sums are complete in thread 0 only: it hands them to the others
+    __shared__ double pqpp[2];
+    const double pq0 = reduce_member(part1, S.nbm, S.mblk_off, b, bk.k, sh);
+    const double pp0 = reduce_member(part2, S.nbm, S.mblk_off, b, bk.k, sh);
+    if (threadIdx.x == 0) {
+        pqpp[0] = pq0;
+        pqpp[1] = pp0;
+    }
+    __syncthreads();
+    if (!c.done) cg_alpha_step(c, pqpp[0], pqpp[1], qf_eps, delta2);
+    if (c.done) return;   // uniform in the block
     double a = 0.0;
-    if (i < bk.hi) {
-        const i64 o = (i64)b * S.m + i;
-        const double pv = p[o], qv = q[o], yv = y[o], rv = res[o], bv = bvec[o];
-        const double r = pad ? bv : rv - al * qv;
-        if (!done) {
-            y[o] = pad ? 0.0 : yv + al * pv;
-            res[o] = r;
-        }
+    if (in) {
+        const double r = c.pad ? bv : rv - c.alpha * qv;
+        y[o] = c.pad ? 0.0 : yv + c.alpha * pv;
+        res[o] = r;
         a = r * r;
     }
-    if (done) return;   // uniform in the block
     a = block_sum(a, sh);
     if (threadIdx.x == 0) part[(i64)b * gridDim.x + blockIdx.x] = a;
 }
 
-__global__ void k_cg_beta(SymView S, CGState* st, const double* part, double tol, const double* ptol, int max_it,
+// the alpha step (as k_cg_update formed it) and then beta = r'r / rho with
+// the convergence test; stores the state of the iteration
+__global__ void k_cg_beta(SymView S, CGState* st, const double* part1, const double* part2, double qf_eps,
+                          double delta2, const double* part, double tol, const double* ptol, int max_it,
                           const int* ids) {
     __shared__ double sh[kBlock / kWave];
     const int b = inst_of(ids, blockIdx.x), k = blockIdx.y;
     const i64 ci = (i64)b * S.G + k;
     const int done = st[ci].done;
+    const double pq = reduce_member(part1, S.nbm, S.mblk_off, b, k, sh);
+    const double pp = reduce_member(part2, S.nbm, S.mblk_off, b, k, sh);
     const double r1 = reduce_member(part, S.nbm, S.mblk_off, b, k, sh);
     if (done) return;   // uniform in the block
     if (threadIdx.x == 0) {
         CGState c = st[ci];
-        if (c.pad) {
+        cg_alpha_step(c, pq, pp, qf_eps, delta2);
+        if (c.done) {
+            // breakdown without a restart: y and res were left as they were
+        } else if (c.pad) {
             c.pad = 0;
             c.rho = r1;
             c.beta = 0.0;
