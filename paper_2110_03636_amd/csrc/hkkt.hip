@@ -744,6 +744,11 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
     const int nb = B.nb;
     T* L = B.L.as<T>();
     T* CB = c->cbws.as<T>();
+    static std::once_flag upd2_attr;   // the trailing-update tiles use more than the default dynamic LDS
+    std::call_once(upd2_attr, [] {
+        HIPCHK(hipFuncSetAttribute((const void*)k_big_update2<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   upd2_lds<T>()));
+    });
     const bool early = B.early && sizeof(T) == 4;
     const double* adiag = early ? B.adiag.as<double>() : nullptr;
     int* act_w = early ? B.active.as<int>() : nullptr;   // the array passed as active
@@ -804,7 +809,7 @@ static void launch_factor(hkkt_ctx* c, Batch& B, const int* active) {
                 if (rows <= 0 || cols <= 0) return;
                 if (!strip) {   // the trailing matrix: 128 x 128 tiles
                     const int nt = (rows + kUpdTile - 1) / kUpdTile;
-                    LAUNCH(2, k_big_update2<T>, dim3(nt * nt, cnt, nb), dim3(kUpdThreads), 0, st, D.v, fr, ka, R, nt,
+                    LAUNCH(2, k_big_update2<T>, dim3(nt * nt, cnt, nb), dim3(kUpdThreads), upd2_lds<T>(), st, D.v, fr, ka, R, nt,
                            L, CB, active);
                     return;
                 }
